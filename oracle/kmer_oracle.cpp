@@ -1,0 +1,269 @@
+/*
+ * TEST INFRASTRUCTURE -- CPU oracle for HipMer k-mer analysis.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code with the GPU path: no headers,
+ * helpers, tables or constants.  It computes the plain definition of k-mer
+ * analysis with a std::unordered_map and std::sort; there is no Bloom filter,
+ * because the Bloom pass only removes singletons, which the depth filter
+ * removes anyway (k-mer analysis, section "Parallel k-mer analysis").
+ *
+ * What is computed (paper section "The Meraculous Assembly Pipeline", step
+ * 1, and section "Parallel k-mer analysis"):
+ *   - every read is chopped into its overlapping length-k windows (k-mers);
+ *   - each distinct k-mer is counted; k-mers seen fewer than min_depth times
+ *     are dropped as errors (the epsilon cutoff);
+ *   - for every k-mer, two arrays of four counters tally the bases seen
+ *     immediately to its left and right in the reads (the "extensions");
+ *     a base on a side is a high-quality extension when its tally reaches
+ *     ext_min (the t_hq threshold);
+ *   - each side is classified as unique (one high-quality base), fork (two
+ *     or more) or none (X), and k-mers unique on both sides (UU) are the
+ *     ones the de Bruijn graph is built from (section "Parallel contig
+ *     generation").
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - encoding: A=0, C=1, G=2, T=3, first base most significant, so numeric
+ *     order is lexicographic order;
+ *   - canonical form: the smaller of the k-mer and its reverse complement
+ *     (k odd, so they never tie); when the reverse complement is the key,
+ *     the two sides swap and their bases are complemented;
+ *   - an extension base is tallied only when its Phred quality is >= qcut;
+ *     qualities of the bases inside the k-mer are not used;
+ *   - a window containing a non-ACGT byte yields no k-mer; a neighbour that
+ *     is non-ACGT or beyond the read end yields no tally;
+ *   - owner map (owner-computes, section "Parallel k-mer analysis"):
+ *     own(key) = floor(H(key) * n_owners / 2^64) with
+ *     H = fmix64(fmix64(hi ^ 0x243F6A8885A308D3) ^ lo), fmix64 being the
+ *     64-bit finalizer of Austin Appleby's MurmurHash3 (public domain).
+ *
+ * Threads: thread t of T keeps the keys whose (separately seeded) partition
+ * hash is t and scans every read; the union over threads is the table by the
+ * owner-partition identity.  Output records are sorted by key.
+ */
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+typedef unsigned __int128 u128;
+
+namespace {
+
+constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ULL;  /* method-defined owner map */
+constexpr uint64_t kShardSeed = 0x13198A2E03707344ULL;  /* test sampling shards */
+constexpr uint64_t kThreadSeed = 0xA4093822299F31D0ULL; /* oracle thread partition */
+
+inline uint64_t fmix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+inline uint64_t key_hash(uint64_t hi, uint64_t lo, uint64_t seed) { return fmix64(fmix64(hi ^ seed) ^ lo); }
+
+inline uint32_t part_of(uint64_t h, uint32_t n) { return (uint32_t)(((u128)h * n) >> 64); }
+
+/* base code: A/a=0 C/c=1 G/g=2 T/t=3, anything else invalid (4) */
+inline int code_of(uint8_t b) {
+    switch (b) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    default: return 4;
+    }
+}
+
+struct Tally {
+    uint32_t cnt = 0;
+    uint32_t tl[4] = {0, 0, 0, 0};
+    uint32_t tr[4] = {0, 0, 0, 0};
+};
+
+struct KeyHash {
+    size_t operator()(u128 x) const { return (size_t)key_hash((uint64_t)(x >> 64), (uint64_t)x, 0x9E3779B97F4A7C15ULL); }
+};
+
+typedef std::unordered_map<u128, Tally, KeyHash> Map;
+
+}  // namespace
+
+extern "C" {
+
+enum { ORC_FORWARD_ONLY = 1, ORC_KEEP_ALL = 2 };
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOVERFLOW = -2 };
+
+typedef struct {
+    int32_t k;
+    int32_t qual_offset;
+    int32_t qcut;
+    uint32_t min_depth;
+    uint32_t ext_min;
+    uint32_t n_owners; /* method owner filter; 1 = keep every key */
+    uint32_t owner;
+    uint32_t n_shards; /* test sampling: keep only keys of shard `shard` */
+    uint32_t shard;
+    uint32_t flags;
+    int32_t n_threads;
+} orc_params_t;
+
+struct orc_result {
+    std::vector<u128> key;
+    std::vector<Tally> val;
+    int64_t positions = 0; /* valid k-mer windows scanned (before owner/shard filters) */
+};
+
+uint32_t orc_owner(uint64_t hi, uint64_t lo, uint32_t n_owners) { return part_of(key_hash(hi, lo, kOwnerSeed), n_owners); }
+uint32_t orc_shard(uint64_t hi, uint64_t lo, uint32_t n_shards) { return part_of(key_hash(hi, lo, kShardSeed), n_shards); }
+
+/* vector forms for filtering exported records: which = 0 owner map, 1 shard */
+void orc_part_many(const uint64_t *hi, const uint64_t *lo, int64_t n, uint32_t n_parts, int32_t which, uint32_t *out) {
+    const uint64_t seed = which == 0 ? kOwnerSeed : kShardSeed;
+    for (int64_t i = 0; i < n; ++i) out[i] = part_of(key_hash(hi[i], lo[i], seed), n_parts);
+}
+
+/* class of one side: the base if exactly one base reaches ext_min, 4 (fork)
+ * if several do, 5 (X, no neighbour) if none does */
+static uint8_t classify(const uint32_t t[4], uint32_t ext_min) {
+    int n = 0, b = -1;
+    for (int i = 0; i < 4; ++i)
+        if (t[i] >= ext_min) {
+            ++n;
+            b = i;
+        }
+    if (n == 0) return 5;
+    if (n == 1) return (uint8_t)b;
+    return 4;
+}
+
+static int scan_reads(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
+                      const orc_params_t *p, uint32_t n_parts, uint32_t part, Map &m, int64_t *positions) {
+    const int k = p->k;
+    const u128 mask = (k == 64) ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
+    int64_t npos = 0;
+    for (int64_t r = 0; r < n_reads; ++r) {
+        const int64_t b = read_off[r];
+        const int64_t L = read_off[r + 1] - b;
+        const uint8_t *s = ascii + b;
+        const uint8_t *q = qual + b;
+        /* HQ(j): 0 <= j < L, base valid, Phred >= qcut */
+        auto hq = [&](int64_t j) -> bool {
+            return j >= 0 && j < L && code_of(s[j]) < 4 && ((int)q[j] - p->qual_offset) >= p->qcut;
+        };
+        u128 fwd = 0, rc = 0;
+        int64_t run = 0; /* length of the current run of valid bases ending at j */
+        for (int64_t j = 0; j < L; ++j) {
+            const int c = code_of(s[j]);
+            if (c == 4) {
+                run = 0;
+                fwd = rc = 0;
+                continue;
+            }
+            /* enc of the window ending at j, and of its reverse complement */
+            fwd = ((fwd << 2) | (u128)c) & mask;
+            rc = (rc >> 2) | ((u128)(3 - c) << (2 * (k - 1)));
+            if (++run < k) continue;
+            ++npos;
+            const int64_t i = j - k + 1; /* window start */
+            const bool forward_only = (p->flags & ORC_FORWARD_ONLY) != 0;
+            const bool is_fwd = forward_only || fwd <= rc;
+            const u128 key = is_fwd ? fwd : rc;
+            const uint64_t hi = (uint64_t)(key >> 64), lo = (uint64_t)key;
+            if (p->n_owners > 1 && orc_owner(hi, lo, p->n_owners) != p->owner) continue;
+            if (p->n_shards > 1 && orc_shard(hi, lo, p->n_shards) != p->shard) continue;
+            if (n_parts > 1 && part_of(key_hash(hi, lo, kThreadSeed), n_parts) != part) continue;
+            int left = -1, right = -1;
+            if (is_fwd) {
+                if (hq(i - 1)) left = code_of(s[i - 1]);
+                if (hq(i + k)) right = code_of(s[i + k]);
+            } else {
+                if (hq(i + k)) left = 3 - code_of(s[i + k]);
+                if (hq(i - 1)) right = 3 - code_of(s[i - 1]);
+            }
+            Tally &t = m[key];
+            if (t.cnt == UINT32_MAX) return ORC_EOVERFLOW;
+            ++t.cnt;
+            if (left >= 0) ++t.tl[left];
+            if (right >= 0) ++t.tr[right];
+        }
+    }
+    *positions = npos;
+    return ORC_OK;
+}
+
+/* Run the oracle.  read_off has n_reads + 1 entries (base offsets).  Returns
+ * the number of output records (>= 0) or a negative error; *handle receives
+ * the result for orc_fetch / orc_free. */
+int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
+                const orc_params_t *p, void **handle) {
+    *handle = nullptr;
+    if (!p || p->k < 1 || p->k > 63) return ORC_EINVAL;
+    if (!(p->flags & ORC_FORWARD_ONLY) && (p->k % 2) == 0) return ORC_EINVAL;
+    if (p->n_owners < 1 || p->owner >= p->n_owners) return ORC_EINVAL;
+    if (p->n_shards < 1 || p->shard >= p->n_shards) return ORC_EINVAL;
+    if (n_reads < 0) return ORC_EINVAL;
+    const uint32_t T = p->n_threads > 1 ? (uint32_t)p->n_threads : 1u;
+    std::vector<Map> maps(T);
+    std::vector<int> rcs(T, 0);
+    std::vector<int64_t> npos(T, 0);
+    auto work = [&](uint32_t t) { rcs[t] = scan_reads(ascii, qual, read_off, n_reads, p, T, t, maps[t], &npos[t]); };
+    if (T == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (uint32_t t = 0; t < T; ++t) th.emplace_back(work, t);
+        for (auto &x : th) x.join();
+    }
+    for (uint32_t t = 0; t < T; ++t)
+        if (rcs[t] != ORC_OK) return rcs[t];
+    orc_result *res = new orc_result();
+    res->positions = npos[0];
+    const bool keep_all = (p->flags & ORC_KEEP_ALL) != 0;
+    std::vector<std::pair<u128, Tally>> recs;
+    for (auto &m : maps) {
+        for (auto &kv : m)
+            if (keep_all || kv.second.cnt >= p->min_depth) recs.push_back(kv);
+        Map().swap(m);
+    }
+    std::sort(recs.begin(), recs.end(), [](const std::pair<u128, Tally> &a, const std::pair<u128, Tally> &b) {
+        return a.first < b.first;
+    });
+    res->key.reserve(recs.size());
+    res->val.reserve(recs.size());
+    for (auto &kv : recs) {
+        res->key.push_back(kv.first);
+        res->val.push_back(kv.second);
+    }
+    *handle = res;
+    return (int64_t)recs.size();
+}
+
+/* Copy the sorted records out.  tl/tr are n x 4 row-major; cls_* as
+ * classify(): 0..3 = unique base A,C,G,T; 4 = fork; 5 = X. */
+void orc_fetch(void *handle, uint32_t ext_min, uint64_t *key_hi, uint64_t *key_lo, uint32_t *count, uint32_t *tl,
+               uint32_t *tr, uint8_t *cls_l, uint8_t *cls_r) {
+    const orc_result *res = (const orc_result *)handle;
+    const size_t n = res->key.size();
+    for (size_t i = 0; i < n; ++i) {
+        key_hi[i] = (uint64_t)(res->key[i] >> 64);
+        key_lo[i] = (uint64_t)res->key[i];
+        count[i] = res->val[i].cnt;
+        for (int b = 0; b < 4; ++b) {
+            tl[4 * i + b] = res->val[i].tl[b];
+            tr[4 * i + b] = res->val[i].tr[b];
+        }
+        cls_l[i] = classify(res->val[i].tl, ext_min);
+        cls_r[i] = classify(res->val[i].tr, ext_min);
+    }
+}
+
+int64_t orc_positions(void *handle) { return ((const orc_result *)handle)->positions; }
+
+void orc_free(void *handle) { delete (orc_result *)handle; }
+
+}  /* extern "C" */

@@ -1,0 +1,99 @@
+"""Brute-force k-mer analysis for tiny inputs, written from the definition
+with Python strings: every length-k substring is sliced out, its reverse
+complement is built by reversing and complementing the string, and base-4
+digits are read with int(s, 4).  It shares no code with the oracle (which
+rolls 2-bit encodings in C++) and is used only to pin the oracle.
+
+Definition followed: paper section "The Meraculous Assembly Pipeline" step 1
+(chop reads into k-mers, count, drop rare ones, keep the neighbouring bases)
+and section "Parallel k-mer analysis" (two arrays of four extension counters,
+t_hq threshold); the readings (canonical form, quality gate, X/fork classes)
+are the same as the oracle's and are listed in the design notes.
+"""
+from __future__ import annotations
+
+DIGIT = {"A": "0", "C": "1", "G": "2", "T": "3"}
+COMP = {"A": "T", "C": "G", "G": "C", "T": "A"}
+BASES = "ACGT"
+MASK64 = (1 << 64) - 1
+
+
+def enc(w: str) -> int:
+    return int("".join(DIGIT[c] for c in w.upper()), 4)
+
+
+def revcomp(w: str) -> str:
+    return "".join(COMP[c] for c in reversed(w.upper()))
+
+
+def fmix64(x: int) -> int:
+    """MurmurHash3 64-bit finalizer (Austin Appleby), in Python integers."""
+    x &= MASK64
+    x ^= x >> 33
+    x = (x * 0xFF51AFD7ED558CCD) & MASK64
+    x ^= x >> 33
+    x = (x * 0xC4CEB9FE1A85EC53) & MASK64
+    x ^= x >> 33
+    return x
+
+
+def owner(key: int, n_owners: int) -> int:
+    """own(key) = floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo)."""
+    hi, lo = key >> 64, key & MASK64
+    h = fmix64(fmix64(hi ^ 0x243F6A8885A308D3) ^ lo)
+    return (h * n_owners) >> 64
+
+
+def classify(t: list[int], ext_min: int) -> int:
+    hits = [b for b in range(4) if t[b] >= ext_min]
+    if not hits:
+        return 5
+    return hits[0] if len(hits) == 1 else 4
+
+
+def brute(reads: list[tuple[str, list[int]]], k: int, qcut: int = 20, min_depth: int = 2, ext_min: int | None = None,
+          forward_only: bool = False, keep_all: bool = False, n_owners: int = 1, own: int = 0,
+          qual_offset: int = 0) -> dict[int, tuple]:
+    """{key: (count, tl[4], tr[4], cls_l, cls_r)} for kept keys."""
+    ext_min = min_depth if ext_min is None else ext_min
+    table: dict[int, list] = {}
+    for seq, qual in reads:
+        L = len(seq)
+
+        def hq(j):
+            return 0 <= j < L and seq[j].upper() in DIGIT and qual[j] - qual_offset >= qcut
+
+        for i in range(0, L - k + 1):
+            w = seq[i:i + k]
+            if any(c.upper() not in DIGIT for c in w):
+                continue
+            f, r = enc(w), enc(revcomp(w))
+            if forward_only or f <= r:
+                key = f
+                left = seq[i - 1].upper() if hq(i - 1) else None
+                right = seq[i + k].upper() if hq(i + k) else None
+            else:
+                key = r
+                left = COMP[seq[i + k].upper()] if hq(i + k) else None
+                right = COMP[seq[i - 1].upper()] if hq(i - 1) else None
+            if n_owners > 1 and owner(key, n_owners) != own:
+                continue
+            rec = table.setdefault(key, [0, [0] * 4, [0] * 4])
+            rec[0] += 1
+            if left is not None:
+                rec[1][BASES.index(left)] += 1
+            if right is not None:
+                rec[2][BASES.index(right)] += 1
+    out = {}
+    for key, (c, tl, tr) in table.items():
+        if keep_all or c >= min_depth:
+            out[key] = (c, tuple(tl), tuple(tr), classify(tl, ext_min), classify(tr, ext_min))
+    return out
+
+
+def decode(key: int, k: int) -> str:
+    s = []
+    for _ in range(k):
+        s.append(BASES[key & 3])
+        key >>= 2
+    return "".join(reversed(s))
