@@ -1,0 +1,216 @@
+/*
+ * hm_kmer.h -- C ABI of the MI355X (gfx950) k-mer analysis library.
+ *
+ * k-mer analysis is the first stage of the Meraculous / HipMer de novo
+ * assembly pipeline (arXiv 1705.11147, section "The Meraculous Assembly
+ * Pipeline", step 1, and section "Parallel k-mer analysis"): reads are
+ * chopped into overlapping k-mers, each distinct k-mer is counted, k-mers
+ * seen fewer than a depth threshold are dropped as sequencing errors, two
+ * arrays of four counters per k-mer tally the bases seen on its left and
+ * right (its "extensions"), and k-mers with a unique high-quality extension
+ * on both sides (UU k-mers, section "Parallel contig generation") seed the
+ * de Bruijn graph.  A Bloom filter keeps most single-occurrence (erroneous)
+ * k-mers out of the count table (section "Parallel k-mer analysis").
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers named in the structs are DEVICE pointers owned by the
+ *     caller; the library never allocates or frees device memory, and keeps
+ *     no state besides a thread-local error message.
+ *   - Calls are asynchronous on `stream` (a hipStream_t, may be NULL for the
+ *     legacy default stream).  Argument checks run on the host before any
+ *     launch and return HM_EINVAL without touching the device.
+ *   - Errors found on the device (table or list full, counter overflow,
+ *     export buffer too small) are OR-ed into the caller's status word; read
+ *     it with hm_status() after the stream has finished.  A table whose
+ *     status is not HM_OK must not be used: rebuild it larger.
+ *   - Encoding: A=0, C=1, G=2, T=3; a k-mer of k bases is the 2k-bit
+ *     integer with its first base most significant, so numeric order is
+ *     lexicographic order.  The key of a k-mer is the smaller of its own and
+ *     its reverse complement's encoding (k odd, so they never tie); when the
+ *     reverse complement wins, left and right extensions swap sides and are
+ *     complemented.  Keys are exported as key_hi = bits 64..125 and
+ *     key_lo = bits 0..63.
+ *   - Extension classes (one byte per side): 0..3 = the unique base
+ *     (A, C, G, T) whose tally reaches ext_min; HM_CLS_FORK = two or more
+ *     bases do; HM_CLS_X = none does.
+ */
+#ifndef HM_KMER_H
+#define HM_KMER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HM_ABI_VERSION 1
+
+/* return codes */
+#define HM_OK 0
+#define HM_EINVAL (-1)     /* bad argument (checked on the host) */
+#define HM_ECAPACITY (-2)  /* count table full (probe bound hit) or first-occurrence list full */
+#define HM_EHIP (-3)       /* HIP runtime error (launch or copy) */
+#define HM_EOUTPUT (-4)    /* export buffer too small; *n_out holds the number needed */
+#define HM_EOVERFLOW (-5)  /* a per-k-mer counter would pass 2^32 - 1 */
+
+/* device status word bits (OR-ed by kernels; hm_status maps them to codes) */
+#define HM_ST_TABLE_FULL 1u
+#define HM_ST_LIST_FULL 2u
+#define HM_ST_OVERFLOW 4u
+#define HM_ST_OUTPUT_FULL 8u
+
+/* hm_params_t.flags */
+#define HM_FORWARD_ONLY 1u /* key = forward encoding (no canonical form); allows even k */
+#define HM_BLOOM_BYPASS 2u /* count every occurrence directly, no Bloom test */
+#define HM_CHECKED 4u      /* detect counter overflow (needed only past 2^32 positions per table) */
+
+/* hm_export_table flags */
+#define HM_EXPORT_UU_ONLY 1u /* only kept k-mers unique on both sides */
+#define HM_EXPORT_ALL 2u     /* every k-mer in the table, also below min_depth */
+
+#define HM_CLS_FORK 4
+#define HM_CLS_X 5
+
+#define HM_SLOT_BYTES 64
+
+/* Packed reads: the output of hm_pack_reads, input of the counting passes.
+ * Base i of the concatenated reads is stored
+ *   bases2: 2-bit code in word i/32, bits (63 - 2*(i%32)) .. (62 - 2*(i%32));
+ *   nmask:  bit (63 - i%64) of word i/64, 1 = not A/C/G/T (window invalid);
+ *   hqmask: same position, 1 = valid base with Phred >= qcut.
+ * bases2 holds hm_bases2_words(n_bases) words and each mask
+ * hm_mask_words(n_bases) words (tail padding included, written by
+ * hm_pack_reads). */
+typedef struct {
+    const uint64_t *bases2;
+    const uint64_t *nmask;
+    const uint64_t *hqmask;
+    const int64_t *read_off; /* n_reads + 1 base offsets, or NULL: read r is [r*read_len, (r+1)*read_len) */
+    int64_t n_reads;
+    int64_t n_bases;
+    int32_t read_len; /* used when read_off is NULL */
+} hm_reads_t;
+
+typedef struct {
+    int32_t k;          /* 1..63; odd unless HM_FORWARD_ONLY */
+    uint32_t min_depth; /* keep k-mers seen >= min_depth times (>= 1; 1 forces HM_BLOOM_BYPASS) */
+    uint32_t ext_min;   /* a side's base is a high-quality extension when tallied >= ext_min times (>= 1) */
+    uint32_t n_owners;  /* owner-computes partition: keep keys with own(key) == owner (1 = keep all) */
+    uint32_t owner;
+    uint32_t flags;
+    uint64_t seed; /* seed of the table and Bloom hashes; the output does not depend on it */
+} hm_params_t;
+
+/* Open-addressing count table of `capacity` 64-byte slots (power of two). */
+typedef struct {
+    void *slots;
+    uint64_t capacity;
+    uint32_t max_probe; /* linear-probe bound before HM_ST_TABLE_FULL; 0 = capacity */
+    int32_t k;          /* the k the table is built for (set by the caller) */
+    uint32_t *status;   /* device status word */
+} hm_table_t;
+
+/* Single-word blocked Bloom filter: n_words 64-bit words (power of two),
+ * n_hash bits per key set in one word (1..8). */
+typedef struct {
+    uint64_t *words;
+    uint64_t n_words;
+    uint32_t n_hash;
+} hm_bloom_t;
+
+/* First-occurrence list between the two counting passes: one entry per
+ * occurrence that the Bloom filter had not seen (key: 2 words, ext: 1 byte). */
+typedef struct {
+    uint64_t *keys;  /* 2 * capacity words */
+    uint8_t *ext;    /* capacity bytes */
+    uint64_t capacity;
+    uint64_t *count; /* device counter of entries (zeroed by hm_list_init) */
+} hm_list_t;
+
+/* Export destination: structure-of-arrays records. */
+typedef struct {
+    uint64_t *key_hi;
+    uint64_t *key_lo;
+    uint32_t *count;
+    uint32_t *tl; /* 4 per record */
+    uint32_t *tr; /* 4 per record */
+    uint8_t *cls_l;
+    uint8_t *cls_r;
+    uint64_t capacity;
+    uint64_t *n_out;  /* device counter: records exported (or needed, on HM_EOUTPUT) */
+    uint64_t *digest; /* optional (may be NULL): 2 words, order-free sum and xor of per-record hashes */
+} hm_export_t;
+
+/* ---- sizes and helpers ------------------------------------------------ */
+
+int hm_abi_version(void);
+const char *hm_last_error(void);
+uint64_t hm_bases2_words(int64_t n_bases);
+uint64_t hm_mask_words(int64_t n_bases);
+size_t hm_table_bytes(uint64_t capacity);
+size_t hm_bloom_bytes(uint64_t n_words);
+size_t hm_list_bytes(uint64_t capacity);
+/* Host-only argument check of a parameter block (no device access). */
+int hm_check_params(const hm_params_t *p);
+
+/* Fill a table with empty slots and clear its status word. */
+int hm_table_init(hm_table_t *t, hipStream_t stream);
+/* Clear a Bloom filter. */
+int hm_bloom_init(hm_bloom_t *b, hipStream_t stream);
+/* Clear a first-occurrence list's counter. */
+int hm_list_init(hm_list_t *l, hipStream_t stream);
+/* Synchronize `stream`, read the status word and map it to a return code. */
+int hm_status(const hm_table_t *t, hipStream_t stream);
+
+/* ---- the k-mer analysis path ------------------------------------------ */
+
+/* Pack reads: ascii[n_bases] bases (A/C/G/T in either case; anything else
+ * invalid) and qual[n_bases] Phred bytes (numeric Phred = byte - qual_offset)
+ * into the 2-bit and mask words described at hm_reads_t.  Read boundaries
+ * are not needed here (the layout is per base).  Section "Parallel k-mer
+ * analysis" (reading the reads); the quality gate implements the
+ * high-quality-extension reading (a base is tallied only at Phred >= qcut). */
+int hm_pack_reads(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases, uint8_t qual_offset, uint8_t qcut,
+                  uint64_t *bases2, uint64_t *nmask, uint64_t *hqmask, hipStream_t stream);
+
+/* Counting pass 1 (section "Parallel k-mer analysis", Bloom filter
+ * paragraph): every valid k-mer occurrence (canonical, owner-filtered) tests
+ * and sets its bits in the Bloom filter with one atomic OR on one word.  If
+ * the filter had already seen it, the k-mer is inserted into the table (if
+ * absent) and this occurrence is counted with its extensions at once;
+ * otherwise the occurrence is appended to the first-occurrence list `l`.
+ * With HM_BLOOM_BYPASS (or min_depth == 1) every occurrence is counted and
+ * `b`/`l` may be NULL.  `t` must be initialized; `l` must be initialized
+ * before the first pass-1 call of a table (several read batches may be
+ * passed through pass 1 one after another). */
+int hm_bloom_insert(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, hm_table_t *t, hm_list_t *l,
+                    hipStream_t stream);
+
+/* Counting pass 2: each first-occurrence entry of `l` whose k-mer is in the
+ * table (i.e. was seen at least twice, or is a Bloom false positive) is
+ * counted with its extensions.  After it the table holds, for every k-mer
+ * with count >= 2, exactly its count and extension tallies over all
+ * occurrences, whatever the Bloom false positives were.  `r` is unused by
+ * the current design and may be NULL. */
+int hm_kmer_count(const hm_reads_t *r, const hm_params_t *p, hm_table_t *t, hm_list_t *l, hipStream_t stream);
+
+/* Depth filter and extension classification (sections "Parallel k-mer
+ * analysis": epsilon cutoff and t_hq; "The Meraculous Assembly Pipeline":
+ * forks; "Parallel contig generation": UU only): for every occupied slot,
+ * count = total occurrences, kept = count >= min_depth, and each side gets
+ * its class byte.  Results stay in the table for hm_export_table. */
+int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
+
+/* Stream-compact the classified table into `out` (unordered; sort on the
+ * consumer side if an order is needed).  flags: HM_EXPORT_UU_ONLY,
+ * HM_EXPORT_ALL.  Zeroes out->n_out (and out->digest) first. */
+int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HM_KMER_H */

@@ -1,0 +1,131 @@
+"""ctypes binding of include/hm_kmer.h (argument marshalling only).
+
+Every entry point of the C ABI is exposed under its own name.  The library
+must have been built (``__graft_entry__.build()`` or ``_build.build()``);
+loading fails loudly otherwise -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import _build
+
+HM_OK = 0
+HM_EINVAL = -1
+HM_ECAPACITY = -2
+HM_EHIP = -3
+HM_EOUTPUT = -4
+HM_EOVERFLOW = -5
+
+HM_ST_TABLE_FULL = 1
+HM_ST_LIST_FULL = 2
+HM_ST_OVERFLOW = 4
+HM_ST_OUTPUT_FULL = 8
+
+HM_FORWARD_ONLY = 1
+HM_BLOOM_BYPASS = 2
+HM_CHECKED = 4
+
+HM_EXPORT_UU_ONLY = 1
+HM_EXPORT_ALL = 2
+
+HM_CLS_FORK = 4
+HM_CLS_X = 5
+HM_SLOT_BYTES = 64
+
+u64p = ctypes.c_void_p  # device pointers travel as plain addresses
+
+
+class Reads(ctypes.Structure):
+    _fields_ = [("bases2", u64p), ("nmask", u64p), ("hqmask", u64p), ("read_off", u64p),
+                ("n_reads", ctypes.c_int64), ("n_bases", ctypes.c_int64), ("read_len", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("min_depth", ctypes.c_uint32), ("ext_min", ctypes.c_uint32),
+                ("n_owners", ctypes.c_uint32), ("owner", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class Table(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("max_probe", ctypes.c_uint32),
+                ("k", ctypes.c_int32), ("status", ctypes.c_void_p)]
+
+
+class Bloom(ctypes.Structure):
+    _fields_ = [("words", ctypes.c_void_p), ("n_words", ctypes.c_uint64), ("n_hash", ctypes.c_uint32)]
+
+
+class List(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("ext", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("count", ctypes.c_void_p)]
+
+
+class Export(ctypes.Structure):
+    _fields_ = [("key_hi", ctypes.c_void_p), ("key_lo", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("tl", ctypes.c_void_p), ("tr", ctypes.c_void_p), ("cls_l", ctypes.c_void_p),
+                ("cls_r", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("n_out", ctypes.c_void_p),
+                ("digest", ctypes.c_void_p)]
+
+
+P = ctypes.POINTER
+vp = ctypes.c_void_p
+SIGNATURES = {
+    "hm_abi_version": ([], ctypes.c_int),
+    "hm_last_error": ([], ctypes.c_char_p),
+    "hm_bases2_words": ([ctypes.c_int64], ctypes.c_uint64),
+    "hm_mask_words": ([ctypes.c_int64], ctypes.c_uint64),
+    "hm_table_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_bloom_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_list_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_check_params": ([P(Params)], ctypes.c_int),
+    "hm_table_init": ([P(Table), vp], ctypes.c_int),
+    "hm_bloom_init": ([P(Bloom), vp], ctypes.c_int),
+    "hm_list_init": ([P(List), vp], ctypes.c_int),
+    "hm_status": ([P(Table), vp], ctypes.c_int),
+    "hm_pack_reads": ([vp, vp, ctypes.c_int64, ctypes.c_uint8, ctypes.c_uint8, vp, vp, vp, vp], ctypes.c_int),
+    "hm_bloom_insert": ([P(Reads), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
+    "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),
+    "hm_classify_ext": ([P(Params), P(Table), vp], ctypes.c_int),
+    "hm_export_table": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
+}
+
+_LIB = None
+
+
+class HmError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (what, code, msg))
+        self.code = code
+
+
+def lib(path: str | None = None):
+    """Load libhm_kmer.so (built in-tree).  Raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        so = path or _build.SO
+        if not os.path.exists(so):
+            raise RuntimeError("libhm_kmer.so is not built (%s); run __graft_entry__.build()" % so)
+        L = ctypes.CDLL(so)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = L
+    return _LIB
+
+
+def last_error() -> str:
+    return lib().hm_last_error().decode(errors="replace")
+
+
+def check(rc: int, what: str) -> int:
+    if rc != HM_OK:
+        raise HmError(rc, what, last_error())
+    return rc
+
+
+def call(name: str, *args) -> int:
+    """Call entry point `name`; raise HmError on a non-zero return."""
+    return check(getattr(lib(), name)(*args), name)

@@ -1,0 +1,257 @@
+"""k-mer analysis on the GPU through the C ABI.
+
+PyTorch owns device memory and streams; every step of the path runs in the
+HIP kernels of libhm_kmer.so (see include/hm_kmer.h).  The objects here only
+allocate buffers, fill the ABI structs and call the entry points in order:
+
+    hm_pack_reads -> hm_table_init / hm_bloom_init / hm_list_init
+    -> hm_bloom_insert (per read batch) -> hm_kmer_count
+    -> hm_classify_ext -> hm_export_table
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import abi
+
+DEFAULT_SEED = 0x5DEECE66D
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def next_pow2(x: int) -> int:
+    x = max(1, int(x))
+    return 1 << (x - 1).bit_length()
+
+
+def _empty_u64(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=torch.int64, device=device)
+
+
+@dataclass
+class Packed:
+    """Packed reads resident on the device (layout: include/hm_kmer.h, hm_reads_t)."""
+    bases2: torch.Tensor
+    nmask: torch.Tensor
+    hqmask: torch.Tensor
+    read_off: torch.Tensor | None
+    n_reads: int
+    n_bases: int
+    read_len: int
+
+    def struct(self) -> abi.Reads:
+        return abi.Reads(self.bases2.data_ptr(), self.nmask.data_ptr(), self.hqmask.data_ptr(),
+                         self.read_off.data_ptr() if self.read_off is not None else None,
+                         self.n_reads, self.n_bases, self.read_len)
+
+    def positions(self, k: int) -> int:
+        """Window count (upper bound of valid k-mer positions)."""
+        if self.read_off is None:
+            return self.n_reads * max(0, self.read_len - k + 1)
+        lens = (self.read_off[1:] - self.read_off[:-1]).clamp(min=0)
+        return int((lens - k + 1).clamp(min=0).sum().item())
+
+
+def pack_reads(ascii: torch.Tensor, qual: torch.Tensor, read_len: int | None = None,
+               read_off: torch.Tensor | None = None, qcut: int = 20, qual_offset: int = 0, stream=None,
+               out: Packed | None = None) -> Packed:
+    """hm_pack_reads on device-resident uint8 ascii/qual (same length)."""
+    if ascii.dtype != torch.uint8 or qual.dtype != torch.uint8 or not ascii.is_cuda or not qual.is_cuda:
+        raise TypeError("ascii and qual must be uint8 device tensors")
+    n_bases = ascii.numel()
+    if qual.numel() != n_bases:
+        raise ValueError("ascii and qual differ in length")
+    L = abi.lib()
+    n_b2 = int(L.hm_bases2_words(n_bases))
+    n_m = int(L.hm_mask_words(n_bases))
+    if read_off is None:
+        if not read_len:
+            raise ValueError("give read_len or read_off")
+        n_reads = n_bases // read_len
+    else:
+        read_off = read_off.to(device=ascii.device, dtype=torch.int64).contiguous()
+        n_reads = read_off.numel() - 1
+        read_len = 0
+    if out is None or out.bases2.numel() < n_b2:
+        out = Packed(_empty_u64(n_b2, ascii.device), _empty_u64(n_m, ascii.device), _empty_u64(n_m, ascii.device),
+                     read_off, n_reads, n_bases, read_len or 0)
+    else:
+        out = Packed(out.bases2, out.nmask, out.hqmask, read_off, n_reads, n_bases, read_len or 0)
+    abi.call("hm_pack_reads", ascii.data_ptr() if n_bases else None, qual.data_ptr() if n_bases else None, n_bases,
+             qual_offset, qcut, out.bases2.data_ptr(), out.nmask.data_ptr(), out.hqmask.data_ptr(), _stream(stream))
+    return out
+
+
+class Records:
+    """Device export buffer (structure of arrays)."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.capacity = int(capacity)
+        n = max(self.capacity, 1)
+        self.key_hi = torch.empty(n, dtype=torch.int64, device=device)
+        self.key_lo = torch.empty(n, dtype=torch.int64, device=device)
+        self.count = torch.empty(n, dtype=torch.int32, device=device)
+        self.tl = torch.empty(n * 4, dtype=torch.int32, device=device)
+        self.tr = torch.empty(n * 4, dtype=torch.int32, device=device)
+        self.cls_l = torch.empty(n, dtype=torch.uint8, device=device)
+        self.cls_r = torch.empty(n, dtype=torch.uint8, device=device)
+        self.n_out = torch.zeros(1, dtype=torch.int64, device=device)
+        self.digest = torch.zeros(2, dtype=torch.int64, device=device)
+
+    def struct(self, digest: bool = True) -> abi.Export:
+        return abi.Export(self.key_hi.data_ptr(), self.key_lo.data_ptr(), self.count.data_ptr(), self.tl.data_ptr(),
+                          self.tr.data_ptr(), self.cls_l.data_ptr(), self.cls_r.data_ptr(), self.capacity,
+                          self.n_out.data_ptr(), self.digest.data_ptr() if digest else None)
+
+    def to_numpy(self, n: int | None = None, sort: bool = True) -> dict:
+        """Copy the first n records to the host (sorted by key when `sort`)."""
+        n = int(self.n_out.item()) if n is None else n
+        n = min(n, self.capacity)
+        out = {
+            "key_hi": self.key_hi[:n].cpu().numpy().view(np.uint64),
+            "key_lo": self.key_lo[:n].cpu().numpy().view(np.uint64),
+            "count": self.count[:n].cpu().numpy().view(np.uint32),
+            "tl": self.tl[:4 * n].cpu().numpy().view(np.uint32).reshape(n, 4),
+            "tr": self.tr[:4 * n].cpu().numpy().view(np.uint32).reshape(n, 4),
+            "cls_l": self.cls_l[:n].cpu().numpy(),
+            "cls_r": self.cls_r[:n].cpu().numpy(),
+        }
+        if sort:
+            order = np.lexsort((out["key_lo"], out["key_hi"]))
+            out = {key: v[order] for key, v in out.items()}
+        return out
+
+    def digest_words(self) -> tuple[int, int]:
+        d = self.digest.cpu().numpy().view(np.uint64)
+        return int(d[0]), int(d[1])
+
+
+class KmerCounter:
+    """One count table with its Bloom filter and first-occurrence list.
+
+    capacity:      table slots (power of two, 64 bytes each)
+    bloom_words:   Bloom filter words (power of two, 8 bytes each); n_hash bits per key
+    list_capacity: first-occurrence list entries (17 bytes each); at most one per
+                   distinct k-mer plus repeats of none, so the number of distinct
+                   k-mers bounds it
+    """
+
+    def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,
+                 min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
+                 seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda"):
+        self.device = torch.device(device)
+        self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner, flags,
+                                 seed & (2 ** 64 - 1))
+        abi.call("hm_check_params", ctypes.byref(self.params))
+        self.bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
+        self.capacity = next_pow2(capacity)
+        self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
+        self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr())
+        self.bloom_words = next_pow2(bloom_words) if not self.bypass else 1
+        self.bloom_buf = torch.empty(self.bloom_words, dtype=torch.int64, device=self.device)
+        self.bloom = abi.Bloom(self.bloom_buf.data_ptr(), self.bloom_words, n_hash)
+        self.list_capacity = int(list_capacity) if not self.bypass else 0
+        lc = max(self.list_capacity, 1)
+        self.list_keys = torch.empty(2 * lc, dtype=torch.int64, device=self.device)
+        self.list_ext = torch.empty(lc, dtype=torch.uint8, device=self.device)
+        self.list_count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.list = abi.List(self.list_keys.data_ptr(), self.list_ext.data_ptr(), self.list_capacity,
+                             self.list_count.data_ptr())
+
+    @property
+    def k(self) -> int:
+        return self.params.k
+
+    def bytes(self) -> int:
+        return (self.slots.numel() + self.bloom_buf.numel() + self.list_keys.numel()) * 8 + self.list_ext.numel()
+
+    # ---- the steps, each one C-ABI call ----
+    def reset(self, stream=None):
+        s = _stream(stream)
+        abi.call("hm_table_init", ctypes.byref(self.table), s)
+        if not self.bypass:
+            abi.call("hm_bloom_init", ctypes.byref(self.bloom), s)
+            abi.call("hm_list_init", ctypes.byref(self.list), s)
+
+    def insert(self, packed: Packed, stream=None):
+        r = packed.struct()
+        abi.call("hm_bloom_insert", ctypes.byref(r), ctypes.byref(self.params),
+                 None if self.bypass else ctypes.byref(self.bloom), ctypes.byref(self.table),
+                 None if self.bypass else ctypes.byref(self.list), _stream(stream))
+
+    def count(self, stream=None):
+        abi.call("hm_kmer_count", None, ctypes.byref(self.params), ctypes.byref(self.table),
+                 None if self.bypass else ctypes.byref(self.list), _stream(stream))
+
+    def classify(self, stream=None):
+        abi.call("hm_classify_ext", ctypes.byref(self.params), ctypes.byref(self.table), _stream(stream))
+
+    def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
+        e = out.struct(digest)
+        abi.call("hm_export_table", ctypes.byref(self.table), flags, ctypes.byref(e), _stream(stream))
+
+    def status(self, stream=None) -> int:
+        """Synchronize and return the table's status code (HM_OK or a negative code)."""
+        return abi.lib().hm_status(ctypes.byref(self.table), _stream(stream))
+
+    def run(self, batches, out: Records, flags: int = 0, stream=None, digest: bool = True):
+        """reset -> pass 1 over every packed batch -> pass 2 -> classify -> export (all async)."""
+        self.reset(stream)
+        for p in batches:
+            self.insert(p, stream)
+        self.count(stream)
+        self.classify(stream)
+        self.export(out, flags, stream, digest)
+
+
+def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = None,
+            read_off: np.ndarray | None = None, qcut: int = 20, qual_offset: int = 0, min_depth: int = 2,
+            ext_min: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
+            bypass: bool = False, checked: bool = False, export_flags: int = 0, capacity: int | None = None,
+            bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
+            seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4) -> dict:
+    """Host arrays in, sorted host table out (the whole path on the GPU).
+
+    Sizes default to safe bounds derived from the number of windows; on a
+    capacity error the table (or list) is doubled and the run repeated from
+    scratch, which keeps the result exact."""
+    dev = torch.device(device)
+    a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
+    q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
+    off = None if read_off is None else torch.from_numpy(np.ascontiguousarray(read_off, dtype=np.int64)).to(dev)
+    packed = pack_reads(a, q, read_len=read_len, read_off=off, qcut=qcut, qual_offset=qual_offset)
+    P = packed.positions(k)
+    flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
+        (abi.HM_CHECKED if checked else 0)
+    cap = capacity or next_pow2(max(1024, 2 * P))
+    lcap = list_capacity if list_capacity is not None else max(P, 1)
+    bw = bloom_words or next_pow2(max(64, P * 10 // 64))
+    for _ in range(retries + 1):
+        kc = KmerCounter(k, cap, bw, lcap, n_hash=n_hash, min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
+                         owner=owner, flags=flags, seed=seed, max_probe=max_probe, device=dev)
+        out = Records(kc.capacity, device=dev)
+        kc.run([packed], out, flags=export_flags)
+        rc = kc.status()
+        if rc == abi.HM_OK:
+            res = out.to_numpy()
+            res["digest"] = out.digest_words()
+            res["positions"] = P
+            res["capacity"] = kc.capacity
+            return res
+        if rc == abi.HM_ECAPACITY:
+            st = int(kc.status_buf.item())
+            if st & abi.HM_ST_TABLE_FULL:
+                cap *= 2
+            if st & abi.HM_ST_LIST_FULL:
+                lcap *= 2
+            continue
+        abi.check(rc, "k-mer analysis")
+    raise abi.HmError(abi.HM_ECAPACITY, "k-mer analysis", "still full after %d retries" % retries)

@@ -1,0 +1,105 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/hm_kmer.h declares, and rejects bad arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1705_11147_amd import abi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hm_kmer.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[a-z_][a-z0-9_ \*]*?\b(hm_[a-z0-9_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(abi._build.SO):
+        pytest.skip("libhm_kmer.so not built")
+    return abi.lib()
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for n in ("hm_pack_reads", "hm_bloom_insert", "hm_kmer_count", "hm_classify_ext", "hm_export_table"):
+        assert n in names
+    assert set(names) == set(abi.SIGNATURES), set(names) ^ set(abi.SIGNATURES)
+
+
+def test_every_declared_symbol_is_exported(L):
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_sizes(L):
+    assert L.hm_abi_version() == 1
+    assert L.hm_table_bytes(1 << 20) == 64 << 20
+    assert L.hm_bloom_bytes(1024) == 8192
+    assert L.hm_mask_words(0) == 3 and L.hm_mask_words(64) == 4 and L.hm_mask_words(130) == 5
+    assert L.hm_bases2_words(130) == 10
+    assert L.hm_list_bytes(10) == 170
+
+
+def P(**kw):
+    d = dict(k=21, min_depth=2, ext_min=2, n_owners=1, owner=0, flags=0, seed=1)
+    d.update(kw)
+    return abi.Params(**d)
+
+
+@pytest.mark.parametrize("bad", [dict(k=0), dict(k=64), dict(k=20), dict(min_depth=0), dict(ext_min=0),
+                                 dict(n_owners=0), dict(n_owners=4, owner=4), dict(flags=64)])
+def test_check_params_rejects(L, bad):
+    assert L.hm_check_params(ctypes.byref(P(**bad))) == abi.HM_EINVAL
+    assert abi.last_error()
+
+
+@pytest.mark.parametrize("good", [dict(), dict(k=1), dict(k=63), dict(k=20, flags=abi.HM_FORWARD_ONLY),
+                                  dict(n_owners=16, owner=15), dict(flags=abi.HM_BLOOM_BYPASS | abi.HM_CHECKED)])
+def test_check_params_accepts(L, good):
+    assert L.hm_check_params(ctypes.byref(P(**good))) == abi.HM_OK
+
+
+def test_host_side_rejections_touch_no_device(L):
+    # each of these fails argument validation before any HIP call
+    assert L.hm_pack_reads(None, None, -1, 0, 20, None, None, None, None) == abi.HM_EINVAL
+    assert L.hm_pack_reads(None, None, 10, 0, 20, 8, 8, 8, None) == abi.HM_EINVAL
+    t = abi.Table(64, 1000, 0, 21, 64)  # capacity not a power of two
+    assert L.hm_table_init(ctypes.byref(t), None) == abi.HM_EINVAL
+    t = abi.Table(65, 1024, 0, 21, 64)  # misaligned slots
+    assert L.hm_table_init(ctypes.byref(t), None) == abi.HM_EINVAL
+    b = abi.Bloom(64, 1000, 4)
+    assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
+    b = abi.Bloom(64, 1024, 9)
+    assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
+    assert L.hm_list_init(None, None) == abi.HM_EINVAL
+    t = abi.Table(64, 1024, 0, 31, 64)
+    r = abi.Reads(8, 8, 8, None, 10, 100, 0)  # read_len 0 without offsets
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_BYPASS)), None,
+                             ctypes.byref(t), None, None) == abi.HM_EINVAL
+    r = abi.Reads(8, 8, 8, None, 10, 100, 150)  # 10 reads of 150 > 100 bases
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_BYPASS)), None,
+                             ctypes.byref(t), None, None) == abi.HM_EINVAL
+    r = abi.Reads(8, 8, 8, None, 1, 100, 100)
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=21)), None, ctypes.byref(t), None,
+                             None) == abi.HM_EINVAL  # k mismatch with the table
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31)), None, ctypes.byref(t), None,
+                             None) == abi.HM_EINVAL  # Bloom needed
+    e = abi.Export(None, None, None, None, None, None, None, 10, 64, None)
+    assert L.hm_export_table(ctypes.byref(t), 0, ctypes.byref(e), None) == abi.HM_EINVAL
+    assert L.hm_export_table(ctypes.byref(t), 99, ctypes.byref(e), None) == abi.HM_EINVAL
+
+
+def test_package_import_is_lazy_and_loud():
+    import subprocess
+    import sys
+    code = ("import paper_1705_11147_amd.abi as a; a._build.SO='/nonexistent/lib.so'; a._LIB=None\n"
+            "try:\n a.lib()\nexcept RuntimeError as e:\n print('loud', e)\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert "loud" in out.stdout

@@ -1,0 +1,272 @@
+"""GPU path (through the C ABI) against the CPU oracle, record by record.
+
+Integer output, so the bar is bit-exact equality of the sorted tables:
+keys, counts, both tally arrays and both class bytes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1705_11147_amd import abi, kmer, synth
+from tests.util import assert_tables_equal, random_read_set, read_golden, table_digest, table_to_dict, enc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.lib()
+    torch.cuda.set_device(0)
+
+
+def both(ascii, qual, off, k, read_len=None, n_threads=4, **kw):
+    okw = {x: kw[x] for x in ("qcut", "min_depth", "ext_min", "n_owners", "owner", "qual_offset", "forward_only")
+           if x in kw}
+    gkw = dict(kw)
+    keep_all = gkw.pop("keep_all", False)
+    if keep_all:
+        gkw["export_flags"] = abi.HM_EXPORT_ALL
+    got = kmer.analyze(ascii, qual, k, read_len=read_len, read_off=None if read_len else off, **gkw)
+    exp = oracle.run(ascii, qual, off, k, keep_all=keep_all, n_threads=n_threads, **okw)
+    return got, exp
+
+
+# ------------------------------------------------------------------ pack layout
+
+def numpy_pack(ascii, qual, qcut, qual_offset=0):
+    """The layout documented at hm_reads_t, in numpy."""
+    n = ascii.size
+    nm_words = n // 64 + 3
+    x = ascii | 0x20
+    code = np.select([x == ord("c"), x == ord("g"), x == ord("t")], [1, 2, 3], 0).astype(np.uint64)
+    valid = np.isin(x, np.frombuffer(b"acgt", np.uint8))
+    good = valid & (qual.astype(np.int64) - qual_offset >= qcut)
+    code[~valid] = 0
+    b2 = np.zeros(2 * nm_words, np.uint64)
+    nm = np.full(nm_words, np.uint64(2 ** 64 - 1))
+    hq = np.zeros(nm_words, np.uint64)
+    i = np.arange(n)
+    np.bitwise_or.at(b2, i // 32, code << (62 - 2 * (i % 32)).astype(np.uint64))
+    nm[: (n + 63) // 64] = 0
+    tail = (n + 63) // 64 * 64
+    if n % 64:
+        j = np.arange(n, tail)
+        np.bitwise_or.at(nm, j // 64, np.uint64(1) << (63 - j % 64).astype(np.uint64))
+    np.bitwise_or.at(nm, i // 64, (~valid).astype(np.uint64) << (63 - i % 64).astype(np.uint64))
+    np.bitwise_or.at(hq, i // 64, good.astype(np.uint64) << (63 - i % 64).astype(np.uint64))
+    return b2, nm, hq
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000 + 37, 4096])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_pack_layout(n, offset):
+    rng = np.random.default_rng(n)
+    ascii = rng.choice(np.frombuffer(b"ACGTNacgtX", np.uint8), n + offset)
+    qual = rng.integers(0, 60, n + offset).astype(np.uint8)
+    a = torch.from_numpy(ascii).cuda()[offset:]  # offset 1 exercises the unaligned load path
+    q = torch.from_numpy(qual).cuda()[offset:]
+    p = kmer.pack_reads(a, q, read_len=max(n, 1), qcut=20, qual_offset=3)
+    torch.cuda.synchronize()
+    b2, nm, hq = numpy_pack(ascii[offset:], qual[offset:], 20, 3)
+    assert np.array_equal(p.bases2.cpu().numpy().view(np.uint64), b2)
+    assert np.array_equal(p.nmask.cpu().numpy().view(np.uint64), nm)
+    assert np.array_equal(p.hqmask.cpu().numpy().view(np.uint64), hq)
+
+
+# ------------------------------------------------------------------ workloads
+
+def test_tiny_workload_full_size():
+    """The tiny workload at full size: 1 Mbp genome, 200k x 100 bp reads, k=21."""
+    w = synth.tiny()
+    r = w.reads()
+    got, exp = both(r.ascii, r.qual, r.offsets(), 21, read_len=100, n_threads=8)
+    assert_tables_equal(got, exp, "tiny")
+    assert got["digest"] == table_digest(exp)
+    assert len(exp["count"]) > 900_000
+
+
+def test_mid_workload_scaled():
+    """The mid workload's shape (repeats, end-biased errors, 150 bp, k=51) at 1/200 size."""
+    w = synth.mid(scale=0.005)
+    r = w.reads()
+    got, exp = both(r.ascii, r.qual, r.offsets(), 51, read_len=150, n_threads=8)
+    assert_tables_equal(got, exp, "mid/200")
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 15, 21, 31, 33, 47, 51, 63])
+def test_variable_length_reads_all_k(k):
+    """Ragged reads (0..220 bp) with N and lowercase bases, several tiles, every key width."""
+    ascii, qual, off = random_read_set(k, 3000, 0, 220, genome_len=30000, n_rate=0.002, lower_rate=0.01)
+    got, exp = both(ascii, qual, off, k, qcut=20)
+    assert_tables_equal(got, exp, "var k=%d" % k)
+
+
+@pytest.mark.parametrize("k,L", [(21, 100), (31, 150), (51, 150), (63, 64), (5, 16384 - 64), (9, 20000)])
+def test_fixed_length_reads(k, L):
+    """Fixed-length reads (LDS-tiled path, ragged last tile; L above the tile size takes the
+    offset path)."""
+    n = max(3, 700_000 // L)
+    rng = np.random.default_rng(L)
+    g = rng.choice(np.frombuffer(b"ACGT", np.uint8), 40000)
+    starts = rng.integers(0, g.size - L + 1, n)
+    ascii = np.concatenate([g[s:s + L] for s in starts])
+    flip = rng.random(ascii.size) < 0.01
+    ascii[flip] = rng.choice(np.frombuffer(b"ACGTN", np.uint8), int(flip.sum()))
+    qual = rng.integers(2, 42, ascii.size).astype(np.uint8)
+    off = np.arange(n + 1, dtype=np.int64) * L
+    if L <= 16384 - 64:
+        got, exp = both(ascii, qual, off, k, read_len=L, qcut=25, min_depth=2, ext_min=3)
+    else:
+        got, exp = both(ascii, qual, off, k, qcut=25, min_depth=2, ext_min=3)
+    assert_tables_equal(got, exp, "fixed k=%d L=%d" % (k, L))
+
+
+# ------------------------------------------------------------------ Bloom independence
+
+@pytest.mark.parametrize("bloom_words,n_hash", [(1, 1), (1, 8), (64, 2), (1 << 22, 4)])
+def test_output_independent_of_bloom(bloom_words, n_hash):
+    """A 1-word filter makes nearly every first occurrence a false positive; a huge one almost
+    none.  The table must not change."""
+    ascii, qual, off = random_read_set(77, 2000, 90, 150, genome_len=15000)
+    exp = oracle.run(ascii, qual, off, 31, n_threads=4)
+    got = kmer.analyze(ascii, qual, 31, read_off=off, bloom_words=bloom_words, n_hash=n_hash)
+    assert_tables_equal(got, exp, "bloom %d/%d" % (bloom_words, n_hash))
+
+
+def test_bypass_and_keep_all_sum():
+    ascii, qual, off = random_read_set(5, 1500, 0, 200, n_rate=0.01)
+    got, exp = both(ascii, qual, off, 21, bypass=True, keep_all=True, min_depth=2)
+    assert_tables_equal(got, exp, "bypass+all")
+    valid = oracle.run(ascii, qual, off, 21, keep_all=True, min_depth=1)["positions"]
+    assert int(got["count"].astype(np.int64).sum()) == valid
+    got1, exp1 = both(ascii, qual, off, 21, min_depth=1)
+    assert_tables_equal(got1, exp1, "min_depth=1")
+
+
+@pytest.mark.parametrize("seed", [1, 2, 0xDEADBEEF])
+def test_output_independent_of_hash_seed_and_probe(seed):
+    ascii, qual, off = random_read_set(9, 1500, 100, 150)
+    exp = oracle.run(ascii, qual, off, 51)
+    got = kmer.analyze(ascii, qual, 51, read_off=off, seed=seed, capacity=1 << 16)
+    assert_tables_equal(got, exp, "seed %x" % seed)
+
+
+# ------------------------------------------------------------------ paper examples, filters
+
+def test_paper_examples_forward_only():
+    g = read_golden("traversal_ctg.txt")
+    reads = g["reads"][0]
+    ascii = np.frombuffer("".join(reads).encode(), np.uint8).copy()
+    qual = np.full(ascii.size, 40, np.uint8)
+    got = kmer.analyze(ascii, qual, 3, read_len=len(reads[0]), forward_only=True, qcut=0)
+    d = table_to_dict(got)
+    uu = {key for key, v in d.items() if v[3] < 4 and v[4] < 4}
+    assert uu == {enc(x) for x in g["uu"][0]}
+    cnt, tl, tr, cl, cr = d[enc("CTG")]
+    assert (cr, cl) == (0, 3)  # right A, left T
+    f = read_golden("fork_gaa.txt")
+    ascii = np.frombuffer("".join(f["reads"][0]).encode(), np.uint8).copy()
+    got = kmer.analyze(ascii, np.full(ascii.size, 40, np.uint8), 3, read_len=4, qcut=0)
+    assert table_to_dict(got)[enc("GAA")][4] == abi.HM_CLS_FORK
+
+
+def test_owner_filter_partition():
+    ascii, qual, off = random_read_set(31, 2500, 120, 150)
+    parts = []
+    for p in range(4):
+        got, exp = both(ascii, qual, off, 51, n_owners=4, owner=p)
+        assert_tables_equal(got, exp, "owner %d" % p)
+        parts.append(got)
+    whole = oracle.run(ascii, qual, off, 51)
+    assert sum(len(p["count"]) for p in parts) == len(whole["count"])
+
+
+def test_uu_only_export():
+    ascii, qual, off = random_read_set(41, 2000, 150, 150)
+    got = kmer.analyze(ascii, qual, 31, read_off=off, export_flags=abi.HM_EXPORT_UU_ONLY)
+    exp = oracle.run(ascii, qual, off, 31)
+    m = oracle.uu_mask(exp)
+    assert_tables_equal(got, {x: v[m] for x, v in exp.items() if isinstance(v, np.ndarray)}, "uu")
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_and_degenerate_inputs():
+    # no reads
+    z = np.zeros(0, np.uint8)
+    got = kmer.analyze(z, z, 21, read_off=np.zeros(1, np.int64))
+    assert len(got["count"]) == 0
+    # every read shorter than k, and all-N reads
+    ascii, qual, off = random_read_set(3, 500, 0, 20)
+    got, exp = both(ascii, qual, off, 21, keep_all=True, min_depth=1)
+    assert len(got["count"]) == 0 == len(exp["count"])
+    ascii = np.full(3000, ord("N"), np.uint8)
+    got = kmer.analyze(ascii, np.full(3000, 40, np.uint8), 21, read_len=150, export_flags=abi.HM_EXPORT_ALL)
+    assert len(got["count"]) == 0
+
+
+def test_hot_key_contention():
+    """One k-mer a million times (poly-A reads) plus normal reads: counts and tallies exact under
+    same-address atomics from every wave."""
+    ascii, qual, off = random_read_set(8, 1000, 150, 150)
+    n_hot = 10_000
+    hot = np.full(n_hot * 150, ord("A"), np.uint8)
+    a2 = np.concatenate([ascii, hot])
+    q2 = np.concatenate([qual, np.full(hot.size, 40, np.uint8)])
+    off2 = np.concatenate([off, off[-1] + np.arange(1, n_hot + 1, dtype=np.int64) * 150])
+    for k in (21, 51):
+        got, exp = both(a2, q2, off2, k)
+        assert_tables_equal(got, exp, "hot k=%d" % k)
+        assert int(exp["count"][0]) >= n_hot * (150 - k + 1)
+
+
+def test_capacity_errors_are_reported_not_wrong():
+    ascii, qual, off = random_read_set(12, 2000, 150, 150)
+    exp = oracle.run(ascii, qual, off, 31)
+    # too small a table: the direct call reports HM_ECAPACITY
+    kc = kmer.KmerCounter(31, 256, 1 << 12, 1 << 20)
+    a = torch.from_numpy(ascii).cuda()
+    q = torch.from_numpy(qual).cuda()
+    p = kmer.pack_reads(a, q, read_off=torch.from_numpy(off).cuda())
+    out = kmer.Records(256)
+    kc.run([p], out)
+    assert kc.status() == abi.HM_ECAPACITY
+    # too small a list, likewise
+    kc = kmer.KmerCounter(31, 1 << 18, 1 << 12, 100)
+    kc.run([p], out)
+    assert kc.status() == abi.HM_ECAPACITY
+    # the retrying driver grows both and gets the exact table
+    got = kmer.analyze(ascii, qual, 31, read_off=off, capacity=1024, list_capacity=1000, max_probe=64, retries=12)
+    assert_tables_equal(got, exp, "after retries")
+
+
+def test_export_buffer_too_small():
+    ascii, qual, off = random_read_set(13, 500, 150, 150)
+    kc = kmer.KmerCounter(31, 1 << 16, 1 << 12, 1 << 18)
+    p = kmer.pack_reads(torch.from_numpy(ascii).cuda(), torch.from_numpy(qual).cuda(),
+                        read_off=torch.from_numpy(off).cuda())
+    out = kmer.Records(10)
+    kc.run([p], out)
+    assert kc.status() == abi.HM_EOUTPUT
+    need = int(out.n_out.item())
+    assert need == len(oracle.run(ascii, qual, off, 31)["count"])
+
+
+def test_batches_into_one_table():
+    """Several pass-1 batches into one table (the streamed human-scale shape) equal one pass
+    over all reads."""
+    ascii, qual, off = random_read_set(14, 3000, 150, 150)
+    exp = oracle.run(ascii, qual, off, 51)
+    kc = kmer.KmerCounter(51, 1 << 17, 1 << 14, 1 << 19)
+    cuts = [0, 700, 1900, 3000]
+    packs = []
+    for i in range(3):
+        b0, b1 = off[cuts[i]], off[cuts[i + 1]]
+        packs.append(kmer.pack_reads(torch.from_numpy(ascii[b0:b1]).cuda(), torch.from_numpy(qual[b0:b1]).cuda(),
+                                     read_len=150))
+    out = kmer.Records(1 << 17)
+    kc.run(packs, out)
+    assert kc.status() == abi.HM_OK
+    assert_tables_equal(out.to_numpy(), exp, "batched pass 1")
