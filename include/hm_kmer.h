@@ -22,7 +22,8 @@
  *   - Errors found on the device (table or list full, counter overflow,
  *     export buffer too small) are OR-ed into the caller's status word; read
  *     it with hm_status() after the stream has finished.  A table whose
- *     status is not HM_OK must not be used: rebuild it larger.
+ *     status is not HM_OK must not be used: rebuild it larger.  Once the
+ *     table or list is full, the counting passes skip their remaining work.
  *   - Encoding: A=0, C=1, G=2, T=3; a k-mer of k bases is the 2k-bit
  *     integer with its first base most significant, so numeric order is
  *     lexicographic order.  The key of a k-mer is the smaller of its own and
@@ -108,7 +109,7 @@ typedef struct {
 typedef struct {
     void *slots;
     uint64_t capacity;
-    uint32_t max_probe; /* linear-probe bound before HM_ST_TABLE_FULL; 0 = capacity */
+    uint32_t max_probe; /* linear-probe bound before HM_ST_TABLE_FULL; 0 = min(4096, capacity) */
     int32_t k;          /* the k the table is built for (set by the caller) */
     uint32_t *status;   /* device status word */
 } hm_table_t;

@@ -46,6 +46,15 @@ constexpr int kTileMaskWords = kTileBases / 64 + 4;
 constexpr int kTileB2Words = 2 * kTileMaskWords;
 constexpr int kVarReads = 256;              // reads per tile on the variable-length path
 constexpr uint32_t kMaxSpin = 1u << 22;     // bound on re-reads of a half-published slot
+constexpr uint32_t kDefaultMaxProbe = 4096; // default linear-probe bound
+constexpr uint32_t kAbortBits = HM_ST_TABLE_FULL | HM_ST_LIST_FULL;
+
+// True once a pass has failed (table or list full): the table will be rebuilt
+// by the caller, so the remaining work is skipped.  Wave-uniform.
+__device__ __forceinline__ bool aborted(const uint32_t *status) {
+    const uint32_t st = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (__builtin_amdgcn_readfirstlane(st) & kAbortBits) != 0;
+}
 
 struct Slot {
     uint64_t a;       // k <= 31: key | written;  k >= 32: key bits 63..125 | written
@@ -361,6 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
         const Words w{s_b2, s_nm, s_hq};
         const int total = (int)(r1 - r0) * W;
         for (int f0 = 0; f0 < total; f0 += kBlock) {
+            if (aborted(a.status)) break;
             const int f = f0 + threadIdx.x;
             Occ o{0, 0, 4, 4};
             bool act = false;
@@ -403,6 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
         __syncthreads();
         const int64_t total = s_pre[nr];
         for (int64_t f0 = 0; f0 < total; f0 += kBlock) {
+            if (aborted(a.status)) break;
             const int64_t f = f0 + threadIdx.x;
             Occ o{0, 0, 4, 4};
             bool act = false;
@@ -424,6 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
 // Pass 2: count the first occurrences whose k-mer is in the table.
 template <int KW, bool CHECKED>
 __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
+    if (*a.status & kAbortBits) return;  // pass 1 failed; the table is rebuilt by the caller
     const uint64_t n = min((uint64_t)*a.lcount, a.lcap);
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t hi = a.lkeys[2 * i], lo = a.lkeys[2 * i + 1];
@@ -808,8 +820,8 @@ static int make_args(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, h
     }
     a.slots = reinterpret_cast<Slot *>(t->slots);
     a.cmask = t->capacity - 1;
-    a.max_probe = (t->max_probe == 0 || t->max_probe > t->capacity) ? (uint32_t)min(t->capacity, (uint64_t)0xFFFFFFFFu)
-                                                                      : t->max_probe;
+    const uint64_t mp = t->max_probe ? (uint64_t)t->max_probe : (uint64_t)kDefaultMaxProbe;
+    a.max_probe = (uint32_t)(mp < t->capacity ? mp : t->capacity);
     a.status = t->status;
     return HM_OK;
 }

@@ -226,7 +226,7 @@ def test_capacity_errors_are_reported_not_wrong():
     ascii, qual, off = random_read_set(12, 2000, 150, 150)
     exp = oracle.run(ascii, qual, off, 31)
     # too small a table: the direct call reports HM_ECAPACITY
-    kc = kmer.KmerCounter(31, 256, 1 << 12, 1 << 20)
+    kc = kmer.KmerCounter(31, 256, 1 << 12, 1 << 20, max_probe=32)
     a = torch.from_numpy(ascii).cuda()
     q = torch.from_numpy(qual).cuda()
     p = kmer.pack_reads(a, q, read_off=torch.from_numpy(off).cuda())
