@@ -89,7 +89,16 @@ SIGNATURES = {
     "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),
     "hm_classify_ext": ([P(Params), P(Table), vp], ctypes.c_int),
     "hm_export_table": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
+    "hm_random_access": ([vp, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, vp, vp],
+                         ctypes.c_int),
 }
+
+HM_RA_LOAD = 0
+HM_RA_LOAD_COHERENT = 1
+HM_RA_ATOMIC_ADD = 2
+HM_RA_ATOMIC_OR_RET = 3
+HM_RA_LINE_RMW = 4
+HM_RA_COPY = 5
 
 _LIB = None
 

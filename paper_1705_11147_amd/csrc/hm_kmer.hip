@@ -261,19 +261,6 @@ __device__ __forceinline__ void count_occurrence(Slot *s, int left, int right, u
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Wave-aggregated append: lanes with `pred` get consecutive indices from one
-// atomic add on *counter.  Must be reached by every lane of the wave.
-__device__ __forceinline__ uint64_t wave_reserve(bool pred, unsigned long long *counter, uint64_t &base_out) {
-    const uint64_t m = __ballot(pred);
-    if (m == 0) return 0;
-    const int leader = __ffsll((long long)m) - 1;
-    uint64_t base = 0;
-    if ((int)lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-    base = __shfl(base, leader);
-    base_out = base + __popcll(m & ((1ull << lane_id()) - 1));
-    return m;
-}
-
 // ------------------------------------------------------------------ kernels
 
 struct PassArgs {
@@ -303,10 +290,22 @@ struct PassArgs {
     unsigned long long *lcount;
 };
 
+// Per-wave cursor into the first-occurrence list.  A wave reserves
+// kListChunk entries at a time with one atomic add, so the shared counter sees
+// one atomic per chunk instead of one per wave iteration.  Entries of a chunk
+// the wave leaves unused are marked as holes (ext = kHole) at kernel end.
+constexpr uint32_t kListChunk = 256;
+constexpr uint8_t kHole = 0xFF;
+
+struct ListCursor {
+    uint64_t base;  // first entry of the current chunk
+    uint32_t used;  // entries of the chunk handed out (kListChunk: no chunk yet)
+};
+
 // Per-occurrence body of pass 1.  `act` lanes carry an occurrence; every lane
-// of the wave must call it (it aggregates list appends per wave).
+// of the wave must call it (list appends are aggregated per wave).
 template <int KW, bool CHECKED>
-__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o) {
+__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur) {
     bool seen = false;
     uint64_t h = 0;
     if (act) {
@@ -330,17 +329,42 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
         }
     }
     if (!a.bypass) {
-        uint64_t idx = 0;
         const bool need = act && !seen;
-        if (wave_reserve(need, a.lcount, idx) && need) {
-            if (idx < a.lcap) {
-                a.lkeys[2 * idx] = o.hi;
-                a.lkeys[2 * idx + 1] = o.lo;
-                a.lext[idx] = (uint8_t)(o.left | (o.right << 4));
-            } else {
-                atomicOr(a.status, HM_ST_LIST_FULL);
+        const uint64_t m = __ballot(need);
+        if (m) {
+            const uint32_t n = (uint32_t)__popcll(m);
+            const uint32_t pos = cur.used + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1));
+            uint64_t fresh = 0;
+            if (cur.used + n > kListChunk) {  // wave-uniform: take a new chunk
+                const int leader = __ffsll((long long)m) - 1;
+                if ((int)lane_id() == leader) fresh = atomicAdd(a.lcount, (unsigned long long)kListChunk);
+                fresh = __shfl(fresh, leader);
+            }
+            if (need) {
+                const uint64_t idx = pos < kListChunk ? cur.base + pos : fresh + (pos - kListChunk);
+                if (idx < a.lcap) {
+                    a.lkeys[2 * idx] = o.hi;
+                    a.lkeys[2 * idx + 1] = o.lo;
+                    a.lext[idx] = (uint8_t)(o.left | (o.right << 4));
+                } else {
+                    atomicOr(a.status, HM_ST_LIST_FULL);
+                }
+            }
+            cur.used += n;
+            if (cur.used > kListChunk) {
+                cur.base = fresh;
+                cur.used -= kListChunk;
             }
         }
+    }
+}
+
+// Mark the unused tail of the wave's current chunk as holes.
+__device__ __forceinline__ void list_close(const PassArgs &a, const ListCursor &cur) {
+    if (a.bypass || cur.used >= kListChunk) return;
+    for (uint32_t i = cur.used + lane_id(); i < kListChunk; i += 64) {
+        const uint64_t idx = cur.base + i;
+        if (idx < a.lcap) a.lext[idx] = kHole;
     }
 }
 
@@ -353,6 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
     const int L = a.read_len;
     const int k = a.k;
     const int W = L - k + 1;  // windows per read (> 0, checked by the host)
+    ListCursor cur{0, kListChunk};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * reads_per_tile;
         const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
@@ -380,9 +405,10 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
                 const int64_t rb = (r0 + r) * L - org;
                 act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
             }
-            pass1_occ<KW, CHECKED>(a, act, o);
+            pass1_occ<KW, CHECKED>(a, act, o, cur);
         }
     }
+    list_close(a, cur);
 }
 
 // Pass 1 over variable-length reads (read_off given): packed words are read
@@ -394,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
     __shared__ int64_t s_pre[kVarReads + 1];
     const int k = a.k;
     const Words w{a.b2, a.nm, a.hq};
+    ListCursor cur{0, kListChunk};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * kVarReads;
         const int nr = (int)min((int64_t)kVarReads, a.n_reads - r0);
@@ -427,9 +454,10 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
                 const int64_t rb = s_off[lo], re = max(s_off[lo + 1], rb);
                 act = extract(w, rb + (f - s_pre[lo]), rb, re, k, a.forward_only, a.n_owners, a.owner, o);
             }
-            pass1_occ<KW, CHECKED>(a, act, o);
+            pass1_occ<KW, CHECKED>(a, act, o, cur);
         }
     }
+    list_close(a, cur);
 }
 
 // Pass 2: count the first occurrences whose k-mer is in the table.
@@ -440,6 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
         const uint64_t hi = a.lkeys[2 * i], lo = a.lkeys[2 * i + 1];
         const uint8_t e = a.lext[i];
+        if (e == kHole) continue;
         uint64_t A, B;
         slot_words<KW>(hi, lo, A, B);
         const int64_t s = table_find<KW, false>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
@@ -483,52 +512,74 @@ __device__ __forceinline__ uint64_t record_hash(uint64_t hi, uint64_t lo, uint32
     return fmix64(x ^ (cl | (cr << 8)));
 }
 
+constexpr int kExportPerLane = 8;
+
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
                                                    uint32_t *status) {
     uint64_t dsum = 0, dxor = 0;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    // every lane of a wave runs the same number of iterations (wave_reserve)
-    const uint64_t iters = (cap + stride - 1) / stride;
+    const uint32_t lane = lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
+    const uint64_t per_iter = 64 * kExportPerLane;  // slots per wave iteration
+    const uint64_t iters = (cap + per_iter * n_waves - 1) / (per_iter * n_waves);
     for (uint64_t it = 0; it < iters; ++it) {
-        const uint64_t i = it * stride + (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-        bool take = false;
-        uint64_t hi = 0, lo = 0;
-        uint32_t tl[4] = {0, 0, 0, 0}, tr[4] = {0, 0, 0, 0}, cnt = 0, cl = 0, cr = 0;
-        if (i < cap) {
-            const Slot *s = slots + i;
-            const uint64_t a = s->a;
-            if (a != 0) {
-                const uint32_t c = s->cls;
-                const bool kept = (c >> 16) & 1;
-                cl = c & 0xFF;
-                cr = (c >> 8) & 0xFF;
-                take = (flags & HM_EXPORT_ALL) ? true : kept;
-                if (flags & HM_EXPORT_UU_ONLY) take = take && kept && cl < 4 && cr < 4;
-                if ((c >> 17) & 1) atomicOr(status, HM_ST_OVERFLOW);
-                if (take) {
-                    if (KW == 1) {
-                        lo = a & kLow63;
-                    } else {
-                        const uint64_t A = a & kLow63, B = s->b & kLow63;
-                        lo = B | (A << 63);
-                        hi = A >> 1;
-                    }
-                    uint32_t nl = s->nl;
-                    for (int b = 0; b < 4; ++b) {
-                        tl[b] = s->tl[b];
-                        tr[b] = s->tr[b];
-                    }
-                    cnt = nl + tl[0] + tl[1] + tl[2] + tl[3];
+        const uint64_t first = (it * n_waves + wave) * per_iter;
+        // pass A: which of this lane's slots are taken (slots first + j*64 + lane, coalesced per j)
+        uint32_t take_bits = 0;
+#pragma unroll
+        for (int j = 0; j < kExportPerLane; ++j) {
+            const uint64_t i = first + (uint64_t)j * 64 + lane;
+            if (i < cap) {
+                const Slot *sl = slots + i;
+                if (sl->a != 0) {
+                    const uint32_t c = sl->cls;
+                    const bool kept = (c >> 16) & 1;
+                    bool take = (flags & HM_EXPORT_ALL) ? true : kept;
+                    if (flags & HM_EXPORT_UU_ONLY) take = take && kept && (c & 0xFF) < 4 && ((c >> 8) & 0xFF) < 4;
+                    if ((c >> 17) & 1) atomicOr(status, HM_ST_OVERFLOW);
+                    take_bits |= (take ? 1u : 0u) << j;
                 }
             }
         }
-        uint64_t idx = 0;
-        if (wave_reserve(take, reinterpret_cast<unsigned long long *>(out.n_out), idx) && take) {
+        // wave-wide exclusive prefix of the per-lane counts, one atomic per wave
+        const uint32_t cnt = (uint32_t)__popc(take_bits);
+        uint32_t incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d);
+            if ((int)lane >= d) incl += y;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        if (total == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out), (unsigned long long)total);
+        base = __shfl(base, 0);
+        uint64_t idx = base + (incl - cnt);
+        // pass B: write this lane's records
+#pragma unroll
+        for (int j = 0; j < kExportPerLane; ++j) {
+            if (!((take_bits >> j) & 1)) continue;
+            const Slot *sl = slots + first + (uint64_t)j * 64 + lane;
+            uint64_t hi = 0, lo;
+            if (KW == 1) {
+                lo = sl->a & kLow63;
+            } else {
+                const uint64_t A = sl->a & kLow63, B = sl->b & kLow63;
+                lo = B | (A << 63);
+                hi = A >> 1;
+            }
+            uint32_t tl[4], tr[4];
+            for (int b = 0; b < 4; ++b) {
+                tl[b] = sl->tl[b];
+                tr[b] = sl->tr[b];
+            }
+            const uint32_t c = sl->cls;
+            const uint32_t cl = c & 0xFF, cr = (c >> 8) & 0xFF;
+            const uint32_t count = sl->nl + tl[0] + tl[1] + tl[2] + tl[3];
             if (idx < out.capacity) {
                 out.key_hi[idx] = hi;
                 out.key_lo[idx] = lo;
-                out.count[idx] = cnt;
+                out.count[idx] = count;
                 for (int b = 0; b < 4; ++b) {
                     out.tl[4 * idx + b] = tl[b];
                     out.tr[4 * idx + b] = tr[b];
@@ -539,10 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t c
                 atomicOr(status, HM_ST_OUTPUT_FULL);
             }
             if (out.digest) {
-                const uint64_t x = record_hash(hi, lo, cnt, tl, tr, cl, cr);
+                const uint64_t x = record_hash(hi, lo, count, tl, tr, cl, cr);
                 dsum += x;
                 dxor ^= x;
             }
+            ++idx;
         }
     }
     if (out.digest) {
@@ -550,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t c
             dsum += __shfl_xor(dsum, off);
             dxor ^= __shfl_xor(dxor, off);
         }
-        if (lane_id() == 0 && (dsum | dxor)) {
+        if (lane == 0 && (dsum | dxor)) {
             atomicAdd(reinterpret_cast<unsigned long long *>(out.digest), (unsigned long long)dsum);
             atomicXor(reinterpret_cast<unsigned long long *>(out.digest + 1), (unsigned long long)dxor);
         }

@@ -8,14 +8,18 @@ import pytest
 
 from paper_1705_11147_amd import abi
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hm_kmer.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^[a-z_][a-z0-9_ \*]*?\b(hm_[a-z0-9_]+)\s*\(", src, flags=re.M)
-    return sorted(set(names))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(INCLUDE, h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names.update(re.findall(r"^[a-z_][a-z0-9_ \*]*?\b(hm_[a-z0-9_]+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -93,6 +97,12 @@ def test_host_side_rejections_touch_no_device(L):
     e = abi.Export(None, None, None, None, None, None, None, 10, 64, None)
     assert L.hm_export_table(ctypes.byref(t), 0, ctypes.byref(e), None) == abi.HM_EINVAL
     assert L.hm_export_table(ctypes.byref(t), 99, ctypes.byref(e), None) == abi.HM_EINVAL
+
+
+def test_random_access_rejects(L):
+    assert L.hm_random_access(None, 1024, 0, 10, 1, 8, None) == abi.HM_EINVAL
+    assert L.hm_random_access(8, 1000, 0, 10, 1, 8, None) == abi.HM_EINVAL
+    assert L.hm_random_access(8, 1024, 9, 10, 1, 8, None) == abi.HM_EINVAL
 
 
 def test_package_import_is_lazy_and_loud():
