@@ -52,6 +52,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full mid workload)")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this k-mer analysis build runs on a single MI355X "
@@ -156,16 +157,35 @@ def main():
     value = positions * args.steps / elapsed
     log("stage ms: " + ", ".join("%s %.2f" % kv for kv in stage_ms.items()))
 
-    # roofline of the dominant kernel (pass 1): line-granular algorithmic bytes per position
-    s_frac = 1.0 - n_first / positions  # fraction of positions the Bloom filter had seen
-    bytes_per_pos = 2 * LINE + s_frac * 2 * LINE + 0.5 * L / W + (1 - s_frac) * 17
-    pass1_bytes = bytes_per_pos * positions
+    # roofline of the dominant kernel (pass 1).  Algorithmic bytes, line granular
+    # (one 64-byte line per random access), from the pass's own event counters:
+    #   every occurrence reads its home slot line (64 B);
+    #   an occurrence counted in pass 1 (hit or insert) writes that line back (64 B);
+    #   a Bloom test-and-set reads and writes one line (128 B);
+    #   a deferred occurrence appends a 17-byte list entry;
+    #   the packed reads stream in once (0.5 B per base).
+    st = kc.stats()  # cleared by every step's table init: the last step's counts
+    occ, bloom_tests, deferred = st["occurrences"], st["bloom_tests"], st["deferred"]
+    pass1_bytes = (occ * LINE + (occ - deferred) * LINE + bloom_tests * 2 * LINE + deferred * 17
+                   + 0.5 * r.n_bases)
     achieved = pass1_bytes / (stage_ms["pass1"] / 1000) / 1e9
-    roofline = {"kernel": "k_pass1_fixed (Bloom test-and-set + table upsert/count)", "bound": "hbm",
+    roofline = {"kernel": "k_pass1_fixed (table probe, Bloom test-and-set, insert/count)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_position": round(bytes_per_pos, 2), "seen_fraction": round(s_frac, 4),
-                "kernel_ms": round(stage_ms["pass1"], 3)}
+                "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
+                "events_per_position": {x: round(v / positions, 4) for x, v in st.items() if x != "reserved"}}
+    if not args.no_probe:
+        from paper_1705_11147_amd import roofline as ra
+        m = ra.measure(kc.capacity * 64, kinds=("load", "atomic_add", "atomic_or_ret"), n_ops=1 << 28, reps=2,
+                       device=dev)
+        roofline["measured_random_access"] = {
+            "footprint_GB": round(m["footprint_bytes"] / 1e9, 2),
+            "load_Gops": round(m["load"]["ops_per_s"] / 1e9, 2),
+            "atomic_add_Gops": round(m["atomic_add"]["ops_per_s"] / 1e9, 2),
+            "atomic_or_ret_Gops": round(m["atomic_or_ret"]["ops_per_s"] / 1e9, 2),
+            "copy_GBps": round(m["copy"]["GBps"], 1)}
+        atomics = (occ - deferred) * 2 + bloom_tests  # counter atomics per counted occurrence + Bloom ORs
+        roofline["pass1_atomic_rate_Gops"] = round(atomics / (stage_ms["pass1"] / 1000) / 1e9, 2)
 
     cpu = None
     if not args.no_cpu:

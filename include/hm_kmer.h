@@ -105,6 +105,17 @@ typedef struct {
     uint64_t seed; /* seed of the table and Bloom hashes; the output does not depend on it */
 } hm_params_t;
 
+/* Event counters of the counting passes (hm_table_t.stats, HM_N_STATS
+ * 64-bit words, added to by every pass; clear them with hm_table_init). */
+#define HM_STAT_OCC 0        /* pass 1: valid, owned occurrences */
+#define HM_STAT_HIT 1        /* pass 1: k-mer found at the first table lookup */
+#define HM_STAT_BLOOM 2      /* pass 1: Bloom test-and-set operations */
+#define HM_STAT_DEFER 3      /* pass 1: occurrences sent to the first-occurrence list */
+#define HM_STAT_PROBES 4     /* pass 1: table slots inspected */
+#define HM_STAT_P2_ENTRIES 5 /* pass 2: list entries processed */
+#define HM_STAT_P2_FOUND 6   /* pass 2: entries whose k-mer was in the table */
+#define HM_N_STATS 8
+
 /* Open-addressing count table of `capacity` 64-byte slots (power of two). */
 typedef struct {
     void *slots;
@@ -112,6 +123,7 @@ typedef struct {
     uint32_t max_probe; /* linear-probe bound before HM_ST_TABLE_FULL; 0 = min(4096, capacity) */
     int32_t k;          /* the k the table is built for (set by the caller) */
     uint32_t *status;   /* device status word */
+    uint64_t *stats;    /* optional (may be NULL): HM_N_STATS event counters */
 } hm_table_t;
 
 /* Single-word blocked Bloom filter: n_words 64-bit words (power of two),
@@ -157,7 +169,7 @@ size_t hm_list_bytes(uint64_t capacity);
 /* Host-only argument check of a parameter block (no device access). */
 int hm_check_params(const hm_params_t *p);
 
-/* Fill a table with empty slots and clear its status word. */
+/* Fill a table with empty slots and clear its status word (and stats). */
 int hm_table_init(hm_table_t *t, hipStream_t stream);
 /* Clear a Bloom filter. */
 int hm_bloom_init(hm_bloom_t *b, hipStream_t stream);
@@ -178,11 +190,12 @@ int hm_pack_reads(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases, ui
                   uint64_t *bases2, uint64_t *nmask, uint64_t *hqmask, hipStream_t stream);
 
 /* Counting pass 1 (section "Parallel k-mer analysis", Bloom filter
- * paragraph): every valid k-mer occurrence (canonical, owner-filtered) tests
- * and sets its bits in the Bloom filter with one atomic OR on one word.  If
- * the filter had already seen it, the k-mer is inserted into the table (if
- * absent) and this occurrence is counted with its extensions at once;
- * otherwise the occurrence is appended to the first-occurrence list `l`.
+ * paragraph): every valid k-mer occurrence (canonical, owner-filtered) is
+ * looked up in the table; if present it is counted with its extensions.  An
+ * absent k-mer tests and sets its bits in the Bloom filter with one atomic OR
+ * on one word: if the filter had already seen it, the k-mer is inserted and
+ * this occurrence counted; otherwise the occurrence is appended to the
+ * first-occurrence list `l`.
  * With HM_BLOOM_BYPASS (or min_depth == 1) every occurrence is counted and
  * `b`/`l` may be NULL.  `t` must be initialized; `l` must be initialized
  * before the first pass-1 call of a table (several read batches may be

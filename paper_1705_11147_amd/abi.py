@@ -50,7 +50,11 @@ class Params(ctypes.Structure):
 
 class Table(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("max_probe", ctypes.c_uint32),
-                ("k", ctypes.c_int32), ("status", ctypes.c_void_p)]
+                ("k", ctypes.c_int32), ("status", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+STAT_NAMES = ["occurrences", "hit_first_lookup", "bloom_tests", "deferred", "probe_slots", "p2_entries",
+              "p2_found", "reserved"]
 
 
 class Bloom(ctypes.Structure):

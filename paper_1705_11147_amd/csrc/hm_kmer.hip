@@ -9,13 +9,15 @@
 //   * hm_pack_reads turns ASCII bases + Phred bytes into 2-bit codes and two
 //     bit masks (invalid base, high-quality base): 0.5 byte per base, read
 //     twice less than the ASCII input.
-//   * Pass 1 stages tiles of packed reads in LDS, extracts every window with
-//     funnel shifts (forward code) and a 2-bit group reversal (reverse
-//     complement), and per occurrence does one device-scope atomic OR on one
-//     64-bit Bloom word.  Occurrences the filter has seen are inserted into
-//     the open-addressing table and counted in the same step; the others
-//     (exactly one per distinct k-mer, unless a false positive) go to a
-//     first-occurrence list.
+//   * Pass 1 stages tiles of packed reads in LDS and extracts every window
+//     with funnel shifts (forward code) and a 2-bit group reversal (reverse
+//     complement).  Each occurrence first probes the open-addressing table
+//     with loads; if its k-mer is there it is counted at once.  Otherwise it
+//     does one device-scope atomic OR on one 64-bit Bloom word: a k-mer the
+//     filter has seen is inserted and counted, an unseen one (exactly one
+//     occurrence per distinct k-mer, unless a false positive) goes to a
+//     first-occurrence list.  Random atomics are the scarce resource on this
+//     path (a few 10^10 per second), so hits skip the Bloom atomic.
 //   * Pass 2 walks that list and counts the entries whose k-mer made it into
 //     the table.  Every occurrence is therefore counted exactly once, so the
 //     final table equals the plain definition whatever the false positives.
@@ -206,41 +208,52 @@ __device__ __forceinline__ void slot_words(uint64_t hi, uint64_t lo, uint64_t &A
     }
 }
 
-// Locate (A, B) by linear probing from `start`.  COHERENT: the table is being
-// written by this kernel (device-scope atomic loads); otherwise keys are
-// immutable and plain loads suffice.  With `insert`, an absent key claims the
-// first empty slot (CAS on word a, then store of word b; a reader that sees a
-// matching a but an unwritten b reloads the slot).  Returns the slot index,
-// -1 when absent (no insert) or -2 when the probe bound is reached.
+// Result of a table probe: slot >= 0 where the key is (or was inserted);
+// -1 absent, with `at` the empty slot that ended the probe; -2 probe bound
+// reached.  `used` counts the slots probed.
+struct Probe {
+    int64_t slot;
+    uint64_t at;
+    uint32_t used;
+};
+
+// Locate (A, B) by linear probing from `start` (the first `used0` slots of
+// the sequence were already probed by an earlier call).  COHERENT: the table
+// is being written by this kernel (device-scope atomic loads); otherwise keys
+// are immutable and plain loads suffice.  With `insert`, an absent key claims
+// the first empty slot: CAS on word a, then store of word b.  A reader that
+// sees a matching a and an unwritten b re-reads the slot.  Key words are
+// written once and never cleared, so a probe that stopped at an empty slot
+// can resume there.
 template <int KW, bool COHERENT>
-__device__ __forceinline__ int64_t table_find(Slot *slots, uint64_t cmask, uint64_t start, uint64_t A, uint64_t B,
-                                              uint32_t max_probe, bool insert) {
+__device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_t start, uint64_t A, uint64_t B,
+                                            uint32_t max_probe, bool insert, uint32_t used0 = 0) {
     uint64_t i = start & cmask;
-    uint32_t probes = 0, spins = 0;
+    uint32_t probes = used0, spins = 0;
     while (true) {
         Slot *s = slots + i;
         uint64_t a = COHERENT ? __hip_atomic_load(&s->a, RLX, AGT) : s->a;
         if (a == 0) {
-            if (!insert) return -1;
+            if (!insert) return Probe{-1, i, probes};
             uint64_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(&s->a, &expected, A, RLX, RLX, AGT)) {
                 if (KW == 2) __hip_atomic_store(&s->b, B, RLX, AGT);
-                return (int64_t)i;
+                return Probe{(int64_t)i, i, probes};
             }
             a = expected;
         }
         if (a == A) {
-            if (KW == 1) return (int64_t)i;
+            if (KW == 1) return Probe{(int64_t)i, i, probes};
             const uint64_t b = COHERENT ? __hip_atomic_load(&s->b, RLX, AGT) : s->b;
-            if (b == B) return (int64_t)i;
+            if (b == B) return Probe{(int64_t)i, i, probes};
             // claimed for a key with the same word a, word b not visible yet: re-read
             if (COHERENT && b == 0) {
-                if (++spins > kMaxSpin) return -2;
+                if (++spins > kMaxSpin) return Probe{-2, i, probes};
                 continue;
             }
         }
         i = (i + 1) & cmask;
-        if (++probes >= max_probe) return -2;
+        if (++probes >= max_probe) return Probe{-2, i, probes};
     }
 }
 
@@ -283,12 +296,30 @@ struct PassArgs {
     uint64_t cmask;
     uint32_t max_probe;
     uint32_t *status;
+    unsigned long long *stats;  // optional event counters (hm_table_t.stats)
     // first-occurrence list
     uint64_t *lkeys;
     uint8_t *lext;
     uint64_t lcap;
     unsigned long long *lcount;
 };
+
+// Per-lane event counts of a counting pass (see HM_STAT_* in hm_kmer.h).
+struct Stats {
+    uint32_t v[HM_N_STATS];
+};
+
+// Sum a wave's counts and add them to the table's counters (one atomic per
+// counter per wave).
+__device__ __forceinline__ void stats_flush(unsigned long long *dst, const Stats &st) {
+    if (!dst) return;
+#pragma unroll
+    for (int i = 0; i < HM_N_STATS; ++i) {
+        uint64_t x = st.v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane_id() == 0 && x) atomicAdd(dst + i, (unsigned long long)x);
+    }
+}
 
 // Per-wave cursor into the first-occurrence list.  A wave reserves
 // kListChunk entries at a time with one atomic add, so the shared counter sees
@@ -305,31 +336,36 @@ struct ListCursor {
 // Per-occurrence body of pass 1.  `act` lanes carry an occurrence; every lane
 // of the wave must call it (list appends are aggregated per wave).
 template <int KW, bool CHECKED>
-__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur) {
-    bool seen = false;
-    uint64_t h = 0;
+__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur, Stats &st) {
+    // The table is probed first: an occurrence whose k-mer is already there is
+    // counted without touching the Bloom filter.  Only absent k-mers test and
+    // set their Bloom bits; a k-mer the filter has seen is inserted and this
+    // occurrence counted, an unseen one goes to the first-occurrence list.
+    bool deferred = false;
     if (act) {
-        h = key_hash(o.hi, o.lo, a.seed);
-        if (a.bypass) {
-            seen = true;
-        } else {
+        const uint64_t h = key_hash(o.hi, o.lo, a.seed);
+        uint64_t A, B;
+        slot_words<KW>(o.hi, o.lo, A, B);
+        Probe pr = table_find<KW, true>(a.slots, a.cmask, h, A, B, a.max_probe, a.bypass != 0);
+        st.v[HM_STAT_OCC] += 1;
+        st.v[HM_STAT_HIT] += pr.slot >= 0 ? 1u : 0u;
+        if (pr.slot == -1) {
+            st.v[HM_STAT_BLOOM] += 1;
             const uint64_t g = fmix64(h + 0x9E3779B97F4A7C15ull);
             uint64_t mask = 0;
             for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
             uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
             const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
-            seen = (old & mask) == mask;
+            if ((old & mask) == mask) pr = table_find<KW, true>(a.slots, a.cmask, pr.at, A, B, a.max_probe, true, pr.used);
+            else deferred = true;
         }
-        if (seen) {
-            uint64_t A, B;
-            slot_words<KW>(o.hi, o.lo, A, B);
-            const int64_t s = table_find<KW, true>(a.slots, a.cmask, h, A, B, a.max_probe, true);
-            if (s >= 0) count_occurrence<CHECKED>(a.slots + s, o.left, o.right, a.status);
-            else atomicOr(a.status, HM_ST_TABLE_FULL);
-        }
+        st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;
+        st.v[HM_STAT_PROBES] += pr.used + 1;
+        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, o.left, o.right, a.status);
+        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
     }
     if (!a.bypass) {
-        const bool need = act && !seen;
+        const bool need = deferred;
         const uint64_t m = __ballot(need);
         if (m) {
             const uint32_t n = (uint32_t)__popcll(m);
@@ -378,6 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
     const int k = a.k;
     const int W = L - k + 1;  // windows per read (> 0, checked by the host)
     ListCursor cur{0, kListChunk};
+    Stats st = {};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * reads_per_tile;
         const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
@@ -405,10 +442,11 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
                 const int64_t rb = (r0 + r) * L - org;
                 act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
             }
-            pass1_occ<KW, CHECKED>(a, act, o, cur);
+            pass1_occ<KW, CHECKED>(a, act, o, cur, st);
         }
     }
     list_close(a, cur);
+    stats_flush(a.stats, st);
 }
 
 // Pass 1 over variable-length reads (read_off given): packed words are read
@@ -421,6 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
     const int k = a.k;
     const Words w{a.b2, a.nm, a.hq};
     ListCursor cur{0, kListChunk};
+    Stats st = {};
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * kVarReads;
         const int nr = (int)min((int64_t)kVarReads, a.n_reads - r0);
@@ -454,10 +493,11 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
                 const int64_t rb = s_off[lo], re = max(s_off[lo + 1], rb);
                 act = extract(w, rb + (f - s_pre[lo]), rb, re, k, a.forward_only, a.n_owners, a.owner, o);
             }
-            pass1_occ<KW, CHECKED>(a, act, o, cur);
+            pass1_occ<KW, CHECKED>(a, act, o, cur, st);
         }
     }
     list_close(a, cur);
+    stats_flush(a.stats, st);
 }
 
 // Pass 2: count the first occurrences whose k-mer is in the table.
@@ -465,16 +505,24 @@ template <int KW, bool CHECKED>
 __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
     if (*a.status & kAbortBits) return;  // pass 1 failed; the table is rebuilt by the caller
     const uint64_t n = min((uint64_t)*a.lcount, a.lcap);
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
+    Stats st = {};
+    // uniform trip count per wave so the counters can be summed with shuffles at the end
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock; i0 < n; i0 += stride) {
+        const uint64_t i = i0 + threadIdx.x;
+        if (i >= n) continue;
         const uint64_t hi = a.lkeys[2 * i], lo = a.lkeys[2 * i + 1];
         const uint8_t e = a.lext[i];
         if (e == kHole) continue;
         uint64_t A, B;
         slot_words<KW>(hi, lo, A, B);
-        const int64_t s = table_find<KW, false>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
-        if (s >= 0) count_occurrence<CHECKED>(a.slots + s, e & 15, e >> 4, a.status);
-        else if (s == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
+        const Probe pr = table_find<KW, false>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
+        st.v[HM_STAT_P2_ENTRIES] += 1;
+        st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
+        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, e & 15, e >> 4, a.status);
+        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
     }
+    stats_flush(a.stats, st);
 }
 
 __device__ __forceinline__ uint32_t side_class(const uint32_t t[4], uint32_t ext_min) {
@@ -786,6 +834,10 @@ int hm_table_init(hm_table_t *t, hipStream_t s) {
     if (rc) return rc;
     rc = fill<uint4>(reinterpret_cast<uint4 *>(t->slots), t->capacity * (HM_SLOT_BYTES / 16), make_uint4(0, 0, 0, 0), s);
     if (rc) return rc;
+    if (t->stats) {
+        rc = fill<uint64_t>(t->stats, HM_N_STATS, 0ull, s);
+        if (rc) return rc;
+    }
     return fill<uint32_t>(t->status, 1, 0u, s);
 }
 
@@ -875,6 +927,7 @@ static int make_args(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, h
     const uint64_t mp = t->max_probe ? (uint64_t)t->max_probe : (uint64_t)kDefaultMaxProbe;
     a.max_probe = (uint32_t)(mp < t->capacity ? mp : t->capacity);
     a.status = t->status;
+    a.stats = reinterpret_cast<unsigned long long *>(t->stats);
     return HM_OK;
 }
 

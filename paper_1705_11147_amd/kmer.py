@@ -154,7 +154,9 @@ class KmerCounter:
         self.capacity = next_pow2(capacity)
         self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
         self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr())
+        self.stats_buf = torch.zeros(8, dtype=torch.int64, device=self.device)
+        self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr(),
+                               self.stats_buf.data_ptr())
         self.bloom_words = next_pow2(bloom_words) if not self.bypass else 1
         self.bloom_buf = torch.empty(self.bloom_words, dtype=torch.int64, device=self.device)
         self.bloom = abi.Bloom(self.bloom_buf.data_ptr(), self.bloom_words, n_hash)
@@ -197,6 +199,10 @@ class KmerCounter:
     def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
         e = out.struct(digest)
         abi.call("hm_export_table", ctypes.byref(self.table), flags, ctypes.byref(e), _stream(stream))
+
+    def stats(self) -> dict:
+        """Event counters of the counting passes (synchronizes)."""
+        return dict(zip(abi.STAT_NAMES, (int(x) for x in self.stats_buf.cpu().numpy())))
 
     def status(self, stream=None) -> int:
         """Synchronize and return the table's status code (HM_OK or a negative code)."""

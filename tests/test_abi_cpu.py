@@ -73,16 +73,16 @@ def test_host_side_rejections_touch_no_device(L):
     # each of these fails argument validation before any HIP call
     assert L.hm_pack_reads(None, None, -1, 0, 20, None, None, None, None) == abi.HM_EINVAL
     assert L.hm_pack_reads(None, None, 10, 0, 20, 8, 8, 8, None) == abi.HM_EINVAL
-    t = abi.Table(64, 1000, 0, 21, 64)  # capacity not a power of two
+    t = abi.Table(64, 1000, 0, 21, 64, None)  # capacity not a power of two
     assert L.hm_table_init(ctypes.byref(t), None) == abi.HM_EINVAL
-    t = abi.Table(65, 1024, 0, 21, 64)  # misaligned slots
+    t = abi.Table(65, 1024, 0, 21, 64, None)  # misaligned slots
     assert L.hm_table_init(ctypes.byref(t), None) == abi.HM_EINVAL
     b = abi.Bloom(64, 1000, 4)
     assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
     b = abi.Bloom(64, 1024, 9)
     assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
     assert L.hm_list_init(None, None) == abi.HM_EINVAL
-    t = abi.Table(64, 1024, 0, 31, 64)
+    t = abi.Table(64, 1024, 0, 31, 64, None)
     r = abi.Reads(8, 8, 8, None, 10, 100, 0)  # read_len 0 without offsets
     assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_BYPASS)), None,
                              ctypes.byref(t), None, None) == abi.HM_EINVAL
