@@ -34,6 +34,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(profile: str, source: str):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3
+    summary, or None when the kernel source changed since it was measured."""
+    import hashlib
+    try:
+        text = open(profile).read()
+        digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha")))
+    if fields.get("source_sha256", "").strip() != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"].strip())
+
+
 def sizes_for(w, distinct_est: float, kept_est: float):
     """Table / Bloom / list sizes from estimates of distinct k-mers and of the
     k-mers seen at least twice (the workload recipe fixes both)."""
@@ -171,7 +186,10 @@ def main():
     achieved = pass1_bytes / (stage_ms["pass1"] / 1000) / 1e9
     roofline = {"kernel": "k_pass1_fixed (table probe, Bloom test-and-set, insert/count)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_pass1_fixed_mid_k51_traffic.md"),
+                                            os.path.join(ROOT, "paper_1705_11147_amd", "csrc", "hm_kmer.hip"))
+                if args.scale == 1.0 else None,
                 "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
                 "events_per_position": {x: round(v / positions, 4) for x, v in st.items() if x != "reserved"}}
     if not args.no_probe:

@@ -54,9 +54,25 @@ def measure(footprint_bytes: int, kinds=tuple(KINDS), n_ops: int = 1 << 28, reps
     return out
 
 
+def copy_only(gib: float, device="cuda") -> dict:
+    """One streaming copy of gib/2 GiB onto the other half of a gib-GiB buffer
+    (reads and writes gib/2 GiB each): the reference dispatch for scaling
+    byte counters such as FETCH_SIZE / WRITE_SIZE."""
+    words = int(gib * 2 ** 30) // 8
+    buf = torch.zeros(words, dtype=torch.int64, device=device)
+    sink = torch.zeros(1, dtype=torch.int64, device=device)
+    stream = torch.cuda.current_stream()
+    abi.call("hm_random_access", buf.data_ptr(), words, abi.HM_RA_COPY, 0, 0, sink.data_ptr(), stream.cuda_stream)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": words * 4, "copy_bytes_written": words * 4}
+
+
 def main(argv):
-    sizes = [float(x) for x in argv] or [0.0625, 1.0, 16.0]
     abi.lib()
+    if argv and argv[0] == "--copy":
+        print(json.dumps(copy_only(float(argv[1]) if len(argv) > 1 else 1.0)), flush=True)
+        return
+    sizes = [float(x) for x in argv] or [0.0625, 1.0, 16.0]
     for gb in sizes:
         print(json.dumps(measure(int(gb * 2 ** 30))), flush=True)
 
