@@ -59,6 +59,66 @@ def sizes_for(w, distinct_est: float, kept_est: float):
     return cap, bloom_words, list_cap
 
 
+def run_batched(args, dev, log):
+    """64 read sets (0.5-8 Mbp genomes, 10-60x, 150 bp, 1% errors, k=31): the
+    batched persistent form replayed from a HIP graph against the plain
+    per-set path on the same buffers; outputs compared set by set."""
+    import torch
+    from paper_1705_11147_amd import abi, synth, tune
+    from paper_1705_11147_amd.batch import Batch, SetSpec
+
+    t0 = time.time()
+    ws = synth.batched_sets(n_sets=args.batch_sets, scale=args.batch_scale)
+    specs = []
+    for w in ws:
+        r = w.reads()
+        d, kept = w.size_estimates()
+        specs.append(SetSpec(torch.from_numpy(r.ascii).to(dev), torch.from_numpy(r.qual).to(dev), r.read_len, d,
+                             kept))
+        del r
+    k = ws[0].params.k
+    log("batched: %d sets generated in %.1fs" % (len(ws), time.time() - t0))
+    t1 = time.time()
+    best, report = tune.autotune(specs, k, sample=16, reps=2, log=None)
+    tune_s = time.time() - t1
+    log("batched: tuned in %.1fs -> %s" % (tune_s, best.key()))
+    torch.cuda.empty_cache()
+    b = Batch(specs, k, tuning=best, device=dev)
+    b.launch()
+    st = b.status()
+    if any(x != abi.HM_OK for x in st):
+        raise RuntimeError("batched run failed: statuses %s" % st)
+    ref = b.digests()
+    b.capture()
+    positions = b.positions()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_b = timed(b.replay, args.steps)
+    assert b.digests() == ref, "batched output changed between replays"
+    ms_p = timed(b.run_plain, args.steps)
+    st = b.status()
+    same = st == [abi.HM_OK] * len(st) and b.digests() == ref
+    return {"workload": "batched-64-sets-0.5to8Mbp-10to60x-150bp-k31", "sets": len(ws), "positions": positions,
+            "batched_kmers_per_s": round(positions / (ms_b / 1000), 1), "batched_ms": round(ms_b, 3),
+            "plain_kmers_per_s": round(positions / (ms_p / 1000), 1), "plain_ms": round(ms_p, 3),
+            "speedup": round(ms_p / ms_b, 3), "outputs_identical": bool(same),
+            "tuning": dict(zip(["blocks_per_cu", "tile_bases", "list_per_item", "slots_per_item", "table_load",
+                                "bloom_bits", "n_hash"], best.key())),
+            "tune_s": round(tune_s, 1), "tune_trials": len(report.get("trials", [])),
+            "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 6 plain calls"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +128,9 @@ def main():
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batch-sets", type=int, default=64)
+    ap.add_argument("--batch-scale", type=float, default=1.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this k-mer analysis build runs on a single MI355X "
@@ -219,17 +282,25 @@ def main():
                "sample": "first %d reads (%d positions) of the same workload, %d threads, %.1fs; %s" % (
                    n_cpu, n_cpu * W, threads, res["seconds"], platform.processor() or platform.machine())}
 
+    table_slots, bloom_words = kc.capacity, kc.bloom_words
+    batched = None
+    if not args.no_batched:
+        del kc, out, packed, ascii, qual
+        torch.cuda.empty_cache()
+        batched = run_batched(args, dev, log)
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
                    "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
-                   "table_slots": kc.capacity, "bloom_words": kc.bloom_words, "n_hash": 4,
+                   "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": 4,
                    "step": "pack+init+pass1+pass2+classify+export, inputs resident in HBM",
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

@@ -56,12 +56,14 @@ extern "C" {
 #define HM_EHIP (-3)       /* HIP runtime error (launch or copy) */
 #define HM_EOUTPUT (-4)    /* export buffer too small; *n_out holds the number needed */
 #define HM_EOVERFLOW (-5)  /* a per-k-mer counter would pass 2^32 - 1 */
+#define HM_ETIMEOUT (-6)   /* batched form: a phase wait passed its time bound */
 
 /* device status word bits (OR-ed by kernels; hm_status maps them to codes) */
 #define HM_ST_TABLE_FULL 1u
 #define HM_ST_LIST_FULL 2u
 #define HM_ST_OVERFLOW 4u
 #define HM_ST_OUTPUT_FULL 8u
+#define HM_ST_TIMEOUT 16u
 
 /* hm_params_t.flags */
 #define HM_FORWARD_ONLY 1u /* key = forward encoding (no canonical form); allows even k */
@@ -222,6 +224,69 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
  * consumer side if an order is needed).  flags: HM_EXPORT_UU_ONLY,
  * HM_EXPORT_ALL.  Zeroes out->n_out (and out->digest) first. */
 int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
+
+
+/* ---- batched form: many read sets, one persistent launch -------------- */
+
+/* One read set of a batch: fixed-length reads (read_len <= 16320), its own
+ * packed-read buffers, count table, Bloom filter, first-occurrence list and
+ * export destination (all device memory owned by the caller, sized as for
+ * the plain path).  The table's k must equal the batch's params.k. */
+typedef struct {
+    const uint8_t *ascii;
+    const uint8_t *qual;
+    int64_t n_reads;
+    int32_t read_len;
+    uint64_t *bases2; /* hm_bases2_words(n_reads * read_len) words */
+    uint64_t *nmask;  /* hm_mask_words(n_reads * read_len) words */
+    uint64_t *hqmask;
+    hm_table_t table;
+    hm_bloom_t bloom; /* unused with HM_BLOOM_BYPASS or min_depth == 1 */
+    hm_list_t list;   /* likewise */
+    hm_export_t out;
+} hm_batch_set_t;
+
+/* Launch shape of the persistent kernel (chosen by an autotuner). */
+typedef struct {
+    int32_t blocks_per_cu;  /* persistent grid = CUs x blocks_per_cu, 1..16 */
+    int32_t tile_bases;     /* bases of reads per pass-1 work item, 1024..16384 */
+    int32_t list_per_item;  /* first-occurrence entries per pass-2 work item, >= 256 */
+    int32_t slots_per_item; /* table slots per classify+export work item, multiple of 2048 */
+} hm_batch_tuning_t;
+
+/* Host-side plan returned by hm_batch_prepare and consumed by hm_batch_launch. */
+typedef struct {
+    void *work;         /* caller's device scratch holding descriptors and counters */
+    int32_t n_sets;
+    int32_t grid;       /* persistent-kernel blocks */
+    int64_t n_items;    /* work items over all phases and sets */
+    int64_t n_regions;  /* buffers cleared at launch */
+    int64_t pack_words; /* mask words packed at launch, over all sets */
+    int32_t k;
+    int32_t reserved;
+} hm_batch_plan_t;
+
+/* Device scratch a batch of n_sets needs. */
+size_t hm_batch_work_bytes(int32_t n_sets);
+
+/* Validate the sets, lay out their descriptors and work items (pass 1, then
+ * pass 2; within a phase, larger sets first; export ranges separately)
+ * and copy them into `work` (device, >= hm_batch_work_bytes(n_sets)).
+ * Synchronizes `stream`; not capturable.  Sections as for the plain path. */
+int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params_t *p, uint8_t qual_offset,
+                     uint8_t qcut, uint32_t export_flags, const hm_batch_tuning_t *tuning, void *work,
+                     size_t work_bytes, hm_batch_plan_t *plan, hipStream_t stream);
+
+/* Run the whole path for every set of a prepared batch: clear tables,
+ * filters, lists and counters; pack all reads; one persistent kernel whose
+ * blocks take counting work items from an atomic ticket (a pass-2 item of a
+ * set waits for all pass-1 items of that set: agent-scope release/acquire on
+ * per-set counters); then classify and export every set.
+ * Results land in each set's export buffers, and per-set status words as
+ * in the plain path (plus HM_ST_TIMEOUT if a wait passed its bound).
+ * Launches kernels only (no copies, no allocation): capturable in a HIP
+ * graph and replayable.  Output equals the plain path's, set by set. */
+int hm_batch_launch(const hm_batch_plan_t *plan, hipStream_t stream);
 
 #ifdef __cplusplus
 }

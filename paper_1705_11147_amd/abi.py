@@ -17,11 +17,13 @@ HM_ECAPACITY = -2
 HM_EHIP = -3
 HM_EOUTPUT = -4
 HM_EOVERFLOW = -5
+HM_ETIMEOUT = -6
 
 HM_ST_TABLE_FULL = 1
 HM_ST_LIST_FULL = 2
 HM_ST_OVERFLOW = 4
 HM_ST_OUTPUT_FULL = 8
+HM_ST_TIMEOUT = 16
 
 HM_FORWARD_ONLY = 1
 HM_BLOOM_BYPASS = 2
@@ -73,6 +75,23 @@ class Export(ctypes.Structure):
                 ("digest", ctypes.c_void_p)]
 
 
+class BatchSet(ctypes.Structure):
+    _fields_ = [("ascii", ctypes.c_void_p), ("qual", ctypes.c_void_p), ("n_reads", ctypes.c_int64),
+                ("read_len", ctypes.c_int32), ("bases2", ctypes.c_void_p), ("nmask", ctypes.c_void_p),
+                ("hqmask", ctypes.c_void_p), ("table", Table), ("bloom", Bloom), ("list", List), ("out", Export)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("blocks_per_cu", ctypes.c_int32), ("tile_bases", ctypes.c_int32), ("list_per_item", ctypes.c_int32),
+                ("slots_per_item", ctypes.c_int32)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("work", ctypes.c_void_p), ("n_sets", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("n_items", ctypes.c_int64), ("n_regions", ctypes.c_int64), ("pack_words", ctypes.c_int64),
+                ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 P = ctypes.POINTER
 vp = ctypes.c_void_p
 SIGNATURES = {
@@ -93,6 +112,10 @@ SIGNATURES = {
     "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),
     "hm_classify_ext": ([P(Params), P(Table), vp], ctypes.c_int),
     "hm_export_table": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
+    "hm_batch_work_bytes": ([ctypes.c_int32], ctypes.c_size_t),
+    "hm_batch_prepare": ([P(BatchSet), ctypes.c_int32, P(Params), ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint32,
+                          P(BatchTuning), vp, ctypes.c_size_t, P(BatchPlan), vp], ctypes.c_int),
+    "hm_batch_launch": ([P(BatchPlan), vp], ctypes.c_int),
     "hm_random_access": ([vp, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, vp, vp],
                          ctypes.c_int),
 }

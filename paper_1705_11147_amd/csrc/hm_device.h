@@ -1,0 +1,452 @@
+// Device building blocks shared by the plain and the batched k-mer analysis
+// kernels (private to the library; the public interface is include/hm_kmer.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+
+#include "hm_kmer.h"
+
+namespace hm {
+
+
+constexpr uint64_t kWritten = 1ull << 63;   // set in every written key word
+constexpr uint64_t kLow63 = kWritten - 1;
+constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ull;  // owner map (definition constant)
+constexpr int kBlock = 256;
+constexpr int kTileBases = 16384;           // bases staged in LDS per tile
+constexpr int kTileMaskWords = kTileBases / 64 + 4;
+constexpr int kTileB2Words = 2 * kTileMaskWords;
+constexpr int kVarReads = 256;              // reads per tile on the variable-length path
+constexpr uint32_t kMaxSpin = 1u << 22;     // bound on re-reads of a half-published slot
+constexpr uint32_t kDefaultMaxProbe = 4096; // default linear-probe bound
+constexpr uint32_t kAbortBits = HM_ST_TABLE_FULL | HM_ST_LIST_FULL;
+
+// True once a pass has failed (table or list full): the table will be rebuilt
+// by the caller, so the remaining work is skipped.  Wave-uniform.
+__device__ __forceinline__ bool aborted(const uint32_t *status) {
+    const uint32_t st = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (__builtin_amdgcn_readfirstlane(st) & kAbortBits) != 0;
+}
+
+struct Slot {
+    uint64_t a;       // k <= 31: key | written;  k >= 32: key bits 63..125 | written
+    uint64_t b;       // k >= 32: key bits 0..62 | written
+    uint32_t tl[4];
+    uint32_t tr[4];
+    uint32_t nl;      // occurrences with no left extension
+    uint32_t cls;     // classify: cls_l | cls_r << 8 | kept << 16 | count >= 2^32 << 17
+    uint64_t pad;
+};
+static_assert(sizeof(Slot) == HM_SLOT_BYTES, "slot is one 64-byte line");
+
+#define RLX __ATOMIC_RELAXED
+#define AGT __HIP_MEMORY_SCOPE_AGENT
+
+// ------------------------------------------------------------------ hashing
+
+// 64-bit finalizer of MurmurHash3 (Austin Appleby, public domain).
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+// table / Bloom hash of a key (any good mixer; the output does not depend on it)
+__device__ __forceinline__ uint64_t key_hash(uint64_t hi, uint64_t lo, uint64_t seed) {
+    return fmix64(lo ^ fmix64(hi ^ seed));
+}
+
+// owner-computes map: floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo)
+__device__ __forceinline__ uint32_t owner_of(uint64_t hi, uint64_t lo, uint32_t n) {
+    uint64_t h = fmix64(fmix64(hi ^ kOwnerSeed) ^ lo);
+    return (uint32_t)__umul64hi(h, (uint64_t)n);
+}
+
+// ------------------------------------------------------------------ 2-bit code helpers
+
+// reverse the order of the 32 two-bit groups of a word
+__device__ __forceinline__ uint64_t rev2(uint64_t x) {
+    x = __builtin_bswap64(x);
+    x = ((x >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((x & 0x0F0F0F0F0F0F0F0Full) << 4);
+    x = ((x >> 2) & 0x3333333333333333ull) | ((x & 0x3333333333333333ull) << 2);
+    return x;
+}
+
+struct U128 {
+    uint64_t hi, lo;
+};
+
+// reverse complement of the 2k-bit code x
+__device__ __forceinline__ U128 revcomp(U128 x, int k) {
+    const uint64_t nh = rev2(~x.lo), nl = rev2(~x.hi);  // complement + reverse all 128 bits
+    const int sh = 128 - 2 * k;
+    U128 r;
+    if (sh >= 64) {
+        r.hi = 0;
+        r.lo = nh >> (sh - 64);
+    } else {
+        r.lo = (nl >> sh) | (nh << (64 - sh));
+        r.hi = nh >> sh;
+    }
+    return r;
+}
+
+// Packed words of a tile (LDS) or of the whole batch (global), addressed by a
+// base index relative to `org` (a multiple of 64).
+struct Words {
+    const uint64_t *b2, *nm, *hq;
+    __device__ __forceinline__ uint64_t code(int64_t j) const {
+        const uint64_t w = b2[j >> 5];
+        return (w >> (62 - 2 * (j & 31))) & 3;
+    }
+    __device__ __forceinline__ bool hqbit(int64_t j) const { return (hq[j >> 6] >> (63 - (j & 63))) & 1; }
+    // k validity bits starting at base j are all clear
+    __device__ __forceinline__ bool window_valid(int64_t j, int k) const {
+        const int64_t i = j >> 6;
+        const int s = (int)(j & 63);
+        uint64_t m = nm[i] << s;
+        if (s) m |= nm[i + 1] >> (64 - s);
+        return (m >> (64 - k)) == 0;
+    }
+    // 2k-bit forward code of the window starting at base j
+    __device__ __forceinline__ U128 window(int64_t j, int k) const {
+        const int64_t p = 2 * j;
+        const int64_t i = p >> 6;
+        const int s = (int)(p & 63);
+        const uint64_t w0 = b2[i], w1 = b2[i + 1];
+        const uint64_t x0 = s ? (w0 << s) | (w1 >> (64 - s)) : w0;
+        U128 r;
+        if (2 * k <= 64) {
+            r.hi = 0;
+            r.lo = x0 >> (64 - 2 * k);
+        } else {
+            const uint64_t w2 = b2[i + 2];
+            const uint64_t x1 = s ? (w1 << s) | (w2 >> (64 - s)) : w1;
+            const int sh = 128 - 2 * k;
+            r.lo = (x1 >> sh) | (x0 << (64 - sh));
+            r.hi = x0 >> sh;
+        }
+        return r;
+    }
+};
+
+// One k-mer occurrence after extraction.
+struct Occ {
+    uint64_t hi, lo;  // canonical key
+    int left, right;  // extension base 0..3, or 4 = none
+};
+
+// Extract the occurrence whose window starts at base j of a read spanning
+// [rb, re) (all relative to the Words origin).  Returns false when the window
+// holds a non-ACGT base or the key belongs to another owner.
+__device__ __forceinline__ bool extract(const Words &w, int64_t j, int64_t rb, int64_t re, int k, bool forward_only,
+                                        uint32_t n_owners, uint32_t owner, Occ &o) {
+    if (!w.window_valid(j, k)) return false;
+    const U128 f = w.window(j, k);
+    const bool lok = j > rb && w.hqbit(j - 1);
+    const bool rok = j + k < re && w.hqbit(j + k);
+    const int lb = lok ? (int)w.code(j - 1) : 4;
+    const int rb_ = rok ? (int)w.code(j + k) : 4;
+    bool fwd = true;
+    U128 r = f;
+    if (!forward_only) {
+        r = revcomp(f, k);
+        fwd = (f.hi < r.hi) || (f.hi == r.hi && f.lo <= r.lo);
+    }
+    o.hi = fwd ? f.hi : r.hi;
+    o.lo = fwd ? f.lo : r.lo;
+    o.left = fwd ? lb : (rb_ < 4 ? 3 - rb_ : 4);
+    o.right = fwd ? rb_ : (lb < 4 ? 3 - lb : 4);
+    if (n_owners > 1 && owner_of(o.hi, o.lo, n_owners) != owner) return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ table
+
+// slot key words of a canonical key
+template <int KW>
+__device__ __forceinline__ void slot_words(uint64_t hi, uint64_t lo, uint64_t &A, uint64_t &B) {
+    if (KW == 1) {
+        A = lo | kWritten;
+        B = 0;
+    } else {
+        A = ((hi << 1) | (lo >> 63)) | kWritten;
+        B = (lo & kLow63) | kWritten;
+    }
+}
+
+// Result of a table probe: slot >= 0 where the key is (or was inserted);
+// -1 absent, with `at` the empty slot that ended the probe; -2 probe bound
+// reached.  `used` counts the slots probed.
+struct Probe {
+    int64_t slot;
+    uint64_t at;
+    uint32_t used;
+};
+
+// Locate (A, B) by linear probing from `start` (the first `used0` slots of
+// the sequence were already probed by an earlier call).  COHERENT: the table
+// is being written by this kernel (device-scope atomic loads); otherwise keys
+// are immutable and plain loads suffice.  With `insert`, an absent key claims
+// the first empty slot: CAS on word a, then store of word b.  A reader that
+// sees a matching a and an unwritten b re-reads the slot.  Key words are
+// written once and never cleared, so a probe that stopped at an empty slot
+// can resume there.
+template <int KW, bool COHERENT>
+__device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_t start, uint64_t A, uint64_t B,
+                                            uint32_t max_probe, bool insert, uint32_t used0 = 0) {
+    uint64_t i = start & cmask;
+    uint32_t probes = used0, spins = 0;
+    while (true) {
+        Slot *s = slots + i;
+        uint64_t a = COHERENT ? __hip_atomic_load(&s->a, RLX, AGT) : s->a;
+        if (a == 0) {
+            if (!insert) return Probe{-1, i, probes};
+            uint64_t expected = 0;
+            if (__hip_atomic_compare_exchange_strong(&s->a, &expected, A, RLX, RLX, AGT)) {
+                if (KW == 2) __hip_atomic_store(&s->b, B, RLX, AGT);
+                return Probe{(int64_t)i, i, probes};
+            }
+            a = expected;
+        }
+        if (a == A) {
+            if (KW == 1) return Probe{(int64_t)i, i, probes};
+            const uint64_t b = COHERENT ? __hip_atomic_load(&s->b, RLX, AGT) : s->b;
+            if (b == B) return Probe{(int64_t)i, i, probes};
+            // claimed for a key with the same word a, word b not visible yet: re-read
+            if (COHERENT && b == 0) {
+                if (++spins > kMaxSpin) return Probe{-2, i, probes};
+                continue;
+            }
+        }
+        i = (i + 1) & cmask;
+        if (++probes >= max_probe) return Probe{-2, i, probes};
+    }
+}
+
+template <bool CHECKED>
+__device__ __forceinline__ void count_occurrence(Slot *s, int left, int right, uint32_t *status) {
+    uint32_t *lp = left < 4 ? &s->tl[left] : &s->nl;
+    if (CHECKED) {
+        uint32_t o = __hip_atomic_fetch_add(lp, 1u, RLX, AGT);
+        uint32_t o2 = right < 4 ? __hip_atomic_fetch_add(&s->tr[right], 1u, RLX, AGT) : 0u;
+        if (o == 0xFFFFFFFFu || o2 == 0xFFFFFFFFu) atomicOr(status, HM_ST_OVERFLOW);
+    } else {
+        __hip_atomic_fetch_add(lp, 1u, RLX, AGT);
+        if (right < 4) __hip_atomic_fetch_add(&s->tr[right], 1u, RLX, AGT);
+    }
+}
+
+// ------------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// ------------------------------------------------------------------ kernels
+
+struct PassArgs {
+    const uint64_t *b2, *nm, *hq;
+    const int64_t *read_off;
+    int64_t n_reads;
+    int64_t n_bases;
+    int32_t read_len;
+    int32_t k;
+    uint32_t forward_only;
+    uint32_t n_owners, owner;
+    uint64_t seed;
+    // bloom
+    uint64_t *bloom;
+    uint64_t bloom_mask;  // n_words - 1
+    uint32_t n_hash;
+    uint32_t bypass;
+    // table
+    Slot *slots;
+    uint64_t cmask;
+    uint32_t max_probe;
+    uint32_t *status;
+    unsigned long long *stats;  // optional event counters (hm_table_t.stats)
+    // first-occurrence list
+    uint64_t *lkeys;
+    uint8_t *lext;
+    uint64_t lcap;
+    unsigned long long *lcount;
+};
+
+// Per-lane event counts of a counting pass (see HM_STAT_* in hm_kmer.h).
+struct Stats {
+    uint32_t v[HM_N_STATS];
+};
+
+// Sum a wave's counts and add them to the table's counters (one atomic per
+// counter per wave).
+__device__ __forceinline__ void stats_flush(unsigned long long *dst, const Stats &st) {
+    if (!dst) return;
+#pragma unroll
+    for (int i = 0; i < HM_N_STATS; ++i) {
+        uint64_t x = st.v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane_id() == 0 && x) atomicAdd(dst + i, (unsigned long long)x);
+    }
+}
+
+// Per-wave cursor into the first-occurrence list.  A wave reserves
+// kListChunk entries at a time with one atomic add, so the shared counter sees
+// one atomic per chunk instead of one per wave iteration.  Entries of a chunk
+// the wave leaves unused are marked as holes (ext = kHole) at kernel end.
+constexpr uint32_t kListChunk = 256;
+constexpr uint8_t kHole = 0xFF;
+
+struct ListCursor {
+    uint64_t base;  // first entry of the current chunk
+    uint32_t used;  // entries of the chunk handed out (kListChunk: no chunk yet)
+};
+
+// Per-occurrence body of pass 1.  `act` lanes carry an occurrence; every lane
+// of the wave must call it (list appends are aggregated per wave).
+template <int KW, bool CHECKED, uint32_t CHUNK = kListChunk>
+__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur, Stats &st) {
+    // The table is probed first: an occurrence whose k-mer is already there is
+    // counted without touching the Bloom filter.  Only absent k-mers test and
+    // set their Bloom bits; a k-mer the filter has seen is inserted and this
+    // occurrence counted, an unseen one goes to the first-occurrence list.
+    bool deferred = false;
+    if (act) {
+        const uint64_t h = key_hash(o.hi, o.lo, a.seed);
+        uint64_t A, B;
+        slot_words<KW>(o.hi, o.lo, A, B);
+        Probe pr = table_find<KW, true>(a.slots, a.cmask, h, A, B, a.max_probe, a.bypass != 0);
+        st.v[HM_STAT_OCC] += 1;
+        st.v[HM_STAT_HIT] += pr.slot >= 0 ? 1u : 0u;
+        if (pr.slot == -1) {
+            st.v[HM_STAT_BLOOM] += 1;
+            const uint64_t g = fmix64(h + 0x9E3779B97F4A7C15ull);
+            uint64_t mask = 0;
+            for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
+            uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
+            const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
+            if ((old & mask) == mask) pr = table_find<KW, true>(a.slots, a.cmask, pr.at, A, B, a.max_probe, true, pr.used);
+            else deferred = true;
+        }
+        st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;
+        st.v[HM_STAT_PROBES] += pr.used + 1;
+        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, o.left, o.right, a.status);
+        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
+    }
+    if (!a.bypass) {
+        const bool need = deferred;
+        const uint64_t m = __ballot(need);
+        if (m) {
+            const uint32_t n = (uint32_t)__popcll(m);
+            const uint32_t pos = cur.used + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1));
+            uint64_t fresh = 0;
+            if (cur.used + n > CHUNK) {  // wave-uniform: take a new chunk
+                const int leader = __ffsll((long long)m) - 1;
+                if ((int)lane_id() == leader) fresh = atomicAdd(a.lcount, (unsigned long long)CHUNK);
+                fresh = __shfl(fresh, leader);
+            }
+            if (need) {
+                const uint64_t idx = pos < CHUNK ? cur.base + pos : fresh + (pos - CHUNK);
+                if (idx < a.lcap) {
+                    a.lkeys[2 * idx] = o.hi;
+                    a.lkeys[2 * idx + 1] = o.lo;
+                    a.lext[idx] = (uint8_t)(o.left | (o.right << 4));
+                } else {
+                    atomicOr(a.status, HM_ST_LIST_FULL);
+                }
+            }
+            cur.used += n;
+            if (cur.used > CHUNK) {
+                cur.base = fresh;
+                cur.used -= CHUNK;
+            }
+        }
+    }
+}
+
+// Mark the unused tail of the wave's current chunk as holes.
+template <uint32_t CHUNK = kListChunk>
+__device__ __forceinline__ void list_close(const PassArgs &a, const ListCursor &cur) {
+    if (a.bypass || cur.used >= CHUNK) return;
+    for (uint32_t i = cur.used + lane_id(); i < CHUNK; i += 64) {
+        const uint64_t idx = cur.base + i;
+        if (idx < a.lcap) a.lext[idx] = kHole;
+    }
+}
+
+__device__ __forceinline__ uint32_t side_class(const uint32_t t[4], uint32_t ext_min) {
+    uint32_t n = 0, b = 0;
+    for (uint32_t i = 0; i < 4; ++i)
+        if (t[i] >= ext_min) {
+            ++n;
+            b = i;
+        }
+    return n == 0 ? (uint32_t)HM_CLS_X : (n == 1 ? b : (uint32_t)HM_CLS_FORK);
+}
+
+__device__ __forceinline__ uint64_t record_hash(uint64_t hi, uint64_t lo, uint32_t cnt, const uint32_t tl[4],
+                                                const uint32_t tr[4], uint32_t cl, uint32_t cr) {
+    uint64_t x = fmix64(hi ^ 0x6A09E667F3BCC908ull);
+    x = fmix64(x ^ lo);
+    x = fmix64(x ^ cnt);
+    for (int b = 0; b < 4; ++b) x = fmix64(x ^ (((uint64_t)tl[b] << 32) | tr[b]));
+    return fmix64(x ^ (cl | (cr << 8)));
+}
+
+// 16 bases of ASCII + Phred -> 2-bit codes and the two masks.
+__device__ __forceinline__ void pack16(uint4 sa, uint4 sq, int nvalid, int qual_offset, int qcut, uint64_t &codes,
+                                       uint32_t &bad, uint32_t &good) {
+    // codes: 16 bases x 2 bits, first base most significant; bad/good: 16 bits, first base most significant
+    const uint32_t av[4] = {sa.x, sa.y, sa.z, sa.w};
+    const uint32_t qv[4] = {sq.x, sq.y, sq.z, sq.w};
+    codes = 0;
+    bad = 0;
+    good = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t x = ((av[i >> 2] >> (8 * (i & 3))) & 0xFFu) | 0x20u;  // fold case
+        const int q = (int)((qv[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+        const uint32_t code = (x == 'c') ? 1u : (x == 'g') ? 2u : (x == 't') ? 3u : 0u;
+        const bool valid = i < nvalid && ((x == 'a') | (x == 'c') | (x == 'g') | (x == 't'));
+        codes = (codes << 2) | (valid ? code : 0u);
+        bad = (bad << 1) | (valid ? 0u : 1u);
+        good = (good << 1) | ((valid && q - qual_offset >= qcut) ? 1u : 0u);
+    }
+}
+
+
+// ------------------------------------------------------------------ host helpers (defined in hm_kmer.hip)
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int device_cus();
+inline bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+uint64_t grid_for(uint64_t items, int per_cu = 8);
+
+#define HM_LAUNCH_CHECK(what)                                \
+    do {                                                     \
+        hipError_t e_ = hipGetLastError();                   \
+        if (e_ != hipSuccess) return hm::hip_fail(e_, what); \
+    } while (0)
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T *p, uint64_t n, T v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) p[i] = v;
+}
+
+template <typename T>
+int fill(T *p, uint64_t n, T v, hipStream_t s) {
+    if (n == 0) return HM_OK;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)grid_for(n, 16)), dim3(kBlock), 0, s, p, n, v);
+    HM_LAUNCH_CHECK("fill");
+    return HM_OK;
+}
+
+}  // namespace hm

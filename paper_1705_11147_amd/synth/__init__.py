@@ -170,6 +170,17 @@ class Workload:
         return sample_reads(self.genome, self.chrom_off, self.read_len, n, self.seed, self.err, self.end_bias,
                             r0=r0, keep_truth=keep_truth)
 
+    def size_estimates(self) -> tuple[float, float]:
+        """(distinct k-mers, k-mers seen at least twice) expected from this
+        recipe: every genome k-mer (all copies), plus about one new k-mer per
+        window covering a substitution, of which few repeat."""
+        k, L = self.params.k, self.read_len
+        W = max(0, L - k + 1)
+        per_err = W * min(k, W) / L if L else 0.0  # windows covering an average error position
+        errors = self.n_reads * L * self.err
+        G = float(self.meta["G"])
+        return G + errors * per_err, G * 1.05 + 0.02 * errors * per_err
+
     @property
     def positions(self) -> int:
         """Valid k-mer positions Sigma_r (L - k + 1) (the generator emits no N bases)."""
