@@ -58,11 +58,13 @@ class _SetBuffers:
         self.b2 = torch.empty(int(L.hm_bases2_words(n_bases)), dtype=torch.int64, device=device)
         self.nm = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
         self.hq = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
-        cap = next_pow2(max(1024, int(spec.kept_est / tuning.table_load)))
+        bypass = params.get("min_depth", 2) == 1 or bool(params.get("flags", 0) & abi.HM_BLOOM_BYPASS)
+        keys = spec.distinct_est if bypass else spec.kept_est  # bypass keeps every distinct k-mer
+        cap = next_pow2(max(1024, int(keys / tuning.table_load)))
         bw = next_pow2(max(64, int(spec.distinct_est * tuning.bloom_bits / 64)))
         lcap = int(spec.distinct_est * 1.2) + 4096 * 64  # + room for per-wave chunk tails
         self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, device=device, **params)
-        self.out = Records(int(min(cap, spec.kept_est * 1.3 + 1024)), device=device)
+        self.out = Records(int(min(cap, keys * 1.3 + 1024)), device=device)
 
     def packed(self) -> kmer.Packed:
         return kmer.Packed(self.b2, self.nm, self.hq, None, self.spec.n_reads, self.spec.n_reads * self.spec.read_len,

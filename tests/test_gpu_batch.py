@@ -107,12 +107,14 @@ def test_batched_bypass_and_owner_filter():
     specs, host = make_specs(ws)
     b = Batch(specs, 31, min_depth=1, tuning=Tuning(blocks_per_cu=4, tile_bases=4096))
     b.launch()
-    assert all(x == abi.HM_OK for x in b.status())
+    st = b.status()
+    assert all(x == abi.HM_OK for x in st), st
     exp = oracle.run(host[1].ascii, host[1].qual, host[1].offsets(), 31, min_depth=1)
     assert_tables_equal(b.table(1), exp, "bypass")
     b = Batch(specs, 31, n_owners=3, owner=2)
     b.launch()
-    assert all(x == abi.HM_OK for x in b.status())
+    st = b.status()
+    assert all(x == abi.HM_OK for x in st), st
     exp = oracle.run(host[2].ascii, host[2].qual, host[2].offsets(), 31, n_owners=3, owner=2)
     assert_tables_equal(b.table(2), exp, "owner")
 
