@@ -114,7 +114,7 @@ def run_batched(args, dev, log):
             "plain_kmers_per_s": round(positions / (ms_p / 1000), 1), "plain_ms": round(ms_p, 3),
             "speedup": round(ms_p / ms_b, 3), "outputs_identical": bool(same),
             "tuning": dict(zip(["blocks_per_cu", "tile_bases", "list_per_item", "slots_per_item", "table_load",
-                                "bloom_bits", "n_hash"], best.key())),
+                                "bloom_bits", "n_hash", "set_major"], best.key())),
             "tune_s": round(tune_s, 1), "tune_trials": len(report.get("trials", [])),
             "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 6 plain calls"}
 

@@ -252,6 +252,8 @@ typedef struct {
     int32_t tile_bases;     /* bases of reads per pass-1 work item, 1024..16384 */
     int32_t list_per_item;  /* first-occurrence entries per pass-2 work item, >= 256 */
     int32_t slots_per_item; /* table slots per classify+export work item, multiple of 2048 */
+    int32_t set_major;      /* 1: tickets run set by set (a set's pass 2 right after its pass 1, so few
+                               tables are live at once and stay cache-resident); 0: all pass-1 items first */
 } hm_batch_tuning_t;
 
 /* Host-side plan returned by hm_batch_prepare and consumed by hm_batch_launch. */
@@ -269,8 +271,10 @@ typedef struct {
 /* Device scratch a batch of n_sets needs. */
 size_t hm_batch_work_bytes(int32_t n_sets);
 
-/* Validate the sets, lay out their descriptors and work items (pass 1, then
- * pass 2; within a phase, larger sets first; export ranges separately)
+/* Validate the sets, lay out their descriptors and work items (larger sets
+ * first; ordered set by set or phase by phase as tuning.set_major says; a
+ * set's pass-2 items always come after its pass-1 items; export ranges
+ * separately)
  * and copy them into `work` (device, >= hm_batch_work_bytes(n_sets)).
  * Synchronizes `stream`; not capturable.  Sections as for the plain path. */
 int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params_t *p, uint8_t qual_offset,

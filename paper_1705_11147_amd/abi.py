@@ -83,7 +83,7 @@ class BatchSet(ctypes.Structure):
 
 class BatchTuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("tile_bases", ctypes.c_int32), ("list_per_item", ctypes.c_int32),
-                ("slots_per_item", ctypes.c_int32)]
+                ("slots_per_item", ctypes.c_int32), ("set_major", ctypes.c_int32)]
 
 
 class BatchPlan(ctypes.Structure):

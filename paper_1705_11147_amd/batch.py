@@ -26,13 +26,15 @@ class Tuning:
     table_load: float = 0.45     # sizing: expected kept k-mers / capacity
     bloom_bits: float = 12.0     # sizing: Bloom bits per expected distinct k-mer
     n_hash: int = 4
+    set_major: int = 1           # run the sets one after another (cache-resident tables)
 
     def struct(self) -> abi.BatchTuning:
-        return abi.BatchTuning(self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item)
+        return abi.BatchTuning(self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item,
+                               self.set_major)
 
     def key(self) -> tuple:
         return (self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item, self.table_load,
-                self.bloom_bits, self.n_hash)
+                self.bloom_bits, self.n_hash, self.set_major)
 
 
 @dataclass

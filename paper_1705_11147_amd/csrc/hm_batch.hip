@@ -6,9 +6,10 @@
 //   1. k_fill_regions clears every set's table, filter, counters;
 //   2. k_pack_batch packs every set's reads;
 //   3. k_batch, a persistent kernel.  Its blocks take work items from one
-//      atomic ticket.  Items are ordered pass 1 (read tiles) then pass 2
-//      (first-occurrence list ranges); within a phase larger sets come
-//      first.  A pass-2 item of set s waits until every pass-1 item of s has
+//      atomic ticket.  Items of a set are its pass-1 read tiles followed by
+//      its pass-2 first-occurrence list ranges; sets run larger first, either
+//      one after another (set-major: only one or two sets' tables are live
+//      at a time, so they stay in the memory-side cache) or phase by phase.  A pass-2 item of set s waits until every pass-1 item of s has
 //      finished: per-set counters, release (fence + atomic add) by the
 //      finisher, acquire (atomic load + fence) by the waiter.  A waiter only
 //      ever waits on items with smaller tickets, which running blocks already
@@ -75,9 +76,11 @@ struct BatchHeader {
     uint32_t pad[2];
 };
 
-// work blob layout: header | descs[S] | item_start[2S+1] | pack_start[S+1] | export_start[S+1] | regions[R] | done[2S]
+// work blob layout: header | descs[S] | item_start[2S+1] | group[2S] | pack_start[S+1] | export_start[S+1] |
+// regions[R] | done[2S].  Ticket group g covers items [item_start[g], item_start[g+1]) of phase
+// group[g] >> 24 of set group[g] & 0xFFFFFF.
 struct Layout {
-    size_t desc, item_start, pack_start, export_start, regions, done, total;
+    size_t desc, item_start, group, pack_start, export_start, regions, done, total;
 };
 
 constexpr int kRegionsPerSet = 7;
@@ -87,7 +90,8 @@ Layout layout(int32_t S) {
     Layout l;
     l.desc = up(sizeof(BatchHeader));
     l.item_start = up(l.desc + sizeof(BatchDesc) * S);
-    l.pack_start = up(l.item_start + sizeof(int64_t) * (kPhases * S + 1));
+    l.group = up(l.item_start + sizeof(int64_t) * (kPhases * S + 1));
+    l.pack_start = up(l.group + sizeof(int32_t) * kPhases * S);
     l.export_start = up(l.pack_start + sizeof(int64_t) * (S + 1));
     l.regions = up(l.export_start + sizeof(int64_t) * (S + 1));
     l.done = up(l.regions + sizeof(Region) * (kRegionsPerSet * S + 1));
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_export_batch(const BatchHeader *hdr,
 
 template <int KW, bool CHECKED>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
-                                                  uint32_t *done) {
+                                                  const int32_t *group, uint32_t *done) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
@@ -391,7 +395,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchHeader *hdr, const BatchD
                                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)s_item));
         if (t >= n_items) break;
         const int g = __builtin_amdgcn_readfirstlane(find_range(item_start, kPhases * S, t));
-        const int phase = g / S, s = g - phase * S;
+        const int gs = __builtin_amdgcn_readfirstlane(group[g]);
+        const int phase = gs >> 24, s = gs & 0xFFFFFF;
         const int64_t j = t - item_start[g];
         const BatchDesc &d = sets[s];
         if (phase > 0) {
@@ -449,6 +454,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     if (tu.list_per_item < 256) return fail(HM_EINVAL, "batch: list_per_item >= 256");
     if (tu.slots_per_item < 2048 || tu.slots_per_item % 2048) return fail(HM_EINVAL, "batch: slots_per_item % 2048");
     if (export_flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL)) return fail(HM_EINVAL, "batch: unknown export flags");
+    if (tu.set_major != 0 && tu.set_major != 1) return fail(HM_EINVAL, "batch: set_major must be 0 or 1");
     const bool bypass = (p->flags & HM_BLOOM_BYPASS) || p->min_depth == 1;
 
     std::vector<BatchDesc> descs(n_sets);
@@ -536,11 +542,16 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     hdr.slots_per_item = tu.slots_per_item;
     hdr.seed = p->seed;
     int64_t *item_start = reinterpret_cast<int64_t *>(blob.data() + lay.item_start);
+    int32_t *group = reinterpret_cast<int32_t *>(blob.data() + lay.group);
     int64_t acc = 0;
-    for (int ph = 0; ph < kPhases; ++ph)
-        for (int32_t i = 0; i < n_sets; ++i) {
-            item_start[ph * n_sets + i] = acc;
+    int gi = 0;
+    for (int outer = 0; outer < (tu.set_major ? n_sets : kPhases); ++outer)
+        for (int inner = 0; inner < (tu.set_major ? kPhases : n_sets); ++inner) {
+            const int ph = tu.set_major ? inner : outer, i = tu.set_major ? outer : inner;
+            item_start[gi] = acc;
+            group[gi] = (ph << 24) | i;
             acc += sorted[i].n_items[ph];
+            ++gi;
         }
     item_start[kPhases * n_sets] = acc;
     hdr.n_items = acc;
@@ -596,6 +607,7 @@ int hm_batch_launch(const hm_batch_plan_t *plan, hipStream_t s) {
     BatchHeader *hdr = reinterpret_cast<BatchHeader *>(w);
     const BatchDesc *descs = reinterpret_cast<const BatchDesc *>(w + lay.desc);
     const int64_t *item_start = reinterpret_cast<const int64_t *>(w + lay.item_start);
+    const int32_t *group = reinterpret_cast<const int32_t *>(w + lay.group);
     const int64_t *pack_start = reinterpret_cast<const int64_t *>(w + lay.pack_start);
     const Region *regions = reinterpret_cast<const Region *>(w + lay.regions);
     uint32_t *done = reinterpret_cast<uint32_t *>(w + lay.done);
@@ -615,11 +627,11 @@ int hm_batch_launch(const hm_batch_plan_t *plan, hipStream_t s) {
         const bool checked = plan->reserved != 0;
         const dim3 g((unsigned)plan->grid), b(kBlock);
         if (plan->k >= 32) {
-            if (checked) hipLaunchKernelGGL((k_batch<2, true>), g, b, 0, s, hdr, descs, item_start, done);
-            else hipLaunchKernelGGL((k_batch<2, false>), g, b, 0, s, hdr, descs, item_start, done);
+            if (checked) hipLaunchKernelGGL((k_batch<2, true>), g, b, 0, s, hdr, descs, item_start, group, done);
+            else hipLaunchKernelGGL((k_batch<2, false>), g, b, 0, s, hdr, descs, item_start, group, done);
         } else {
-            if (checked) hipLaunchKernelGGL((k_batch<1, true>), g, b, 0, s, hdr, descs, item_start, done);
-            else hipLaunchKernelGGL((k_batch<1, false>), g, b, 0, s, hdr, descs, item_start, done);
+            if (checked) hipLaunchKernelGGL((k_batch<1, true>), g, b, 0, s, hdr, descs, item_start, group, done);
+            else hipLaunchKernelGGL((k_batch<1, false>), g, b, 0, s, hdr, descs, item_start, group, done);
         }
         HM_LAUNCH_CHECK("batch: persistent kernel");
     }
