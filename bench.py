@@ -119,6 +119,43 @@ def run_batched(args, dev, log):
             "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 6 plain calls"}
 
 
+def run_serving(args, dev, log):
+    """Poisson arrivals (20 jobs/s) of hexaploid-like k-mer analysis jobs
+    (ancestor log-U[1,50] Mbp + 3 homeologs at 1.5%, 30x of 150 bp, 0.5%
+    errors, k=51), payloads in pinned host memory, served with continuous
+    batching; the same job stream one job at a time (FIFO) for comparison."""
+    import torch
+    from paper_1705_11147_amd import synth
+    from paper_1705_11147_amd.serve import GpuBackend, Scheduler, make_jobs, summarize
+
+    t0 = time.time()
+    _, builders = synth.serving_jobs(n_jobs=args.serve_pool, rate=args.serve_rate, scale=args.serve_scale)
+    pool = [b() for b in builders]
+    jobs, positions = make_jobs(pool, n_jobs=args.serve_jobs, rate=args.serve_rate)
+    del pool
+    log("serving: %d pooled jobs, %d arrivals prepared in %.1fs" % (args.serve_pool, len(jobs), time.time() - t0))
+    budget = int(args.serve_budget_gb * 2 ** 30)
+    out = {"workload": "serving-hexaploid-1to50Mbp-x3-30x-150bp-k51-poisson%gps" % args.serve_rate,
+           "scale": args.serve_scale, "pool_jobs": args.serve_pool, "budget_GiB": args.serve_budget_gb}
+    # warm-up: one small job through the backend (stream, allocator, kernels)
+    Scheduler(GpuBackend(51, device=dev), budget, 1).run([min(jobs, key=lambda j: j.n_bases)])
+    for name, slots in (("continuous", args.serve_slots), ("fifo_one_at_a_time", 1)):
+        torch.cuda.synchronize()
+        sch = Scheduler(GpuBackend(51, device=dev), budget, slots)
+        recs = sch.run(jobs)
+        res = summarize(recs, positions, sch.trace)
+        res["slots"] = slots
+        out[name] = {x: (round(v, 3) if isinstance(v, float) else v) for x, v in res.items()}
+        log("serving %s: p50 %.1f ms p99 %.1f ms, %.3g k-mers/s" % (name, res["p50_ms"], res["p99_ms"],
+                                                                     res["kmers_per_s"]))
+        if name == "continuous":
+            results = {r.job: r.result for r in recs}
+        else:
+            same = all(results[r.job] == r.result for r in recs)
+            out["identical_alone_vs_mix"] = bool(same)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +168,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-pool", type=int, default=12)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-scale", type=float, default=1.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this k-mer analysis build runs on a single MI355X "
@@ -283,11 +327,17 @@ def main():
                    n_cpu, n_cpu * W, threads, res["seconds"], platform.processor() or platform.machine())}
 
     table_slots, bloom_words = kc.capacity, kc.bloom_words
+    del kc, out, packed, ascii, qual
+    torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
-        del kc, out, packed, ascii, qual
-        torch.cuda.empty_cache()
         batched = run_batched(args, dev, log)
+    serving = None
+    if not args.no_serving:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        serving = run_serving(args, dev, log)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
@@ -301,6 +351,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

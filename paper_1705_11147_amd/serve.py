@@ -1,0 +1,251 @@
+"""Serving loop for k-mer analysis jobs: continuous batching on one GPU.
+
+Jobs arrive open-loop (e.g. Poisson).  The scheduler admits them in arrival
+order as soon as a slot is free and the job's HBM footprint fits the free
+budget.  It does not wait for the running jobs to drain: a job that arrives
+while others are on the GPU starts as soon as a slot and memory free up, and
+its work overlaps theirs on the device.  Each admitted job runs the whole
+path on its own HIP stream:
+
+    pinned host -> HBM copy -> pack -> init -> pass 1 -> pass 2 -> classify -> export
+
+Its table and export stay device-resident until the job completes.  Latency
+is completion time minus arrival time.
+
+The scheduler is independent of the device: `GpuBackend` runs jobs through
+the C ABI, and tests drive the same scheduler with a fake backend and a
+virtual clock.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Job:
+    id: int
+    arrival: float                 # seconds since the start of the run
+    n_bases: int
+    read_len: int
+    distinct_est: float            # size hints (k-mers expected distinct / kept)
+    kept_est: float
+    payload: object = None         # backend-specific (host tensors for the GPU backend)
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class Record:
+    job: int
+    arrival: float
+    admitted: float = float("nan")
+    done: float = float("nan")
+    status: int = 0
+    retries: int = 0
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class WallClock:
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep(self, dt: float):
+        if dt > 0:
+            time.sleep(dt)
+
+
+class Scheduler:
+    """FIFO admission by HBM footprint into at most `max_slots` concurrent jobs."""
+
+    def __init__(self, backend, budget_bytes: int, max_slots: int, poll_s: float = 0.0005):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.poll_s = poll_s
+        self.trace = []  # (time, queued, running, bytes in use)
+
+    def run(self, jobs: list[Job], clock=None, max_retries: int = 3) -> list[Record]:
+        clock = clock or WallClock()
+        order = sorted(range(len(jobs)), key=lambda i: jobs[i].arrival)
+        recs = {j.id: Record(j.id, j.arrival) for j in jobs}
+        for j in jobs:
+            if self.backend.footprint(j) > self.budget:
+                raise ValueError("job %d needs %d bytes, more than the whole budget %d" % (
+                    j.id, self.backend.footprint(j), self.budget))
+        nxt = 0                      # next job (in arrival order) not yet queued
+        queue: list[Job] = []
+        running = {}                 # job id -> (handle, bytes)
+        used = 0
+        while nxt < len(order) or queue or running:
+            now = clock.now()
+            while nxt < len(order) and jobs[order[nxt]].arrival <= now:
+                queue.append(jobs[order[nxt]])
+                nxt += 1
+            # completions first: they free slots and memory for admissions
+            for jid in list(running):
+                h, b = running[jid]
+                if self.backend.poll(h):
+                    status, result = self.backend.finish(h)
+                    used -= b
+                    del running[jid]
+                    r = recs[jid]
+                    if status == "retry" and r.retries < max_retries and self.backend.footprint(result) <= self.budget:
+                        r.retries += 1
+                        queue.insert(0, result)  # the backend returns the resized job
+                        continue
+                    if status == "retry":
+                        status, result = "capacity", None
+                    r.done = clock.now()
+                    r.status = 0 if status == "ok" else status
+                    r.result = result
+            # admission: FIFO, head of line waits for memory
+            while queue and len(running) < self.max_slots:
+                j = queue[0]
+                b = self.backend.footprint(j)
+                if used + b > self.budget:
+                    break
+                queue.pop(0)
+                if np.isnan(recs[j.id].admitted):
+                    recs[j.id].admitted = clock.now()
+                running[j.id] = (self.backend.start(j), b)
+                used += b
+            self.trace.append((now, len(queue), len(running), used))
+            if running or queue:
+                clock.sleep(self.poll_s)
+            elif nxt < len(order):
+                clock.sleep(max(0.0, jobs[order[nxt]].arrival - clock.now()))
+        return [recs[j.id] for j in jobs]
+
+
+def summarize(recs: list[Record], positions: dict, trace=None) -> dict:
+    """Latency percentiles, throughput over the makespan, offered load."""
+    lat = np.array([r.latency for r in recs])
+    arr = np.array([r.arrival for r in recs])
+    done = np.array([r.done for r in recs])
+    total_pos = float(sum(positions[r.job] for r in recs))
+    makespan = float(done.max() - arr.min())
+    span_arr = float(arr.max() - arr.min()) or 1e-9
+    out = {"jobs": len(recs), "p50_ms": float(np.percentile(lat, 50) * 1000),
+           "p99_ms": float(np.percentile(lat, 99) * 1000), "max_ms": float(lat.max() * 1000),
+           "mean_ms": float(lat.mean() * 1000), "kmers_per_s": total_pos / makespan, "makespan_s": makespan,
+           "offered_kmers_per_s": total_pos / span_arr, "offered_jobs_per_s": (len(recs) - 1) / span_arr,
+           "retries": int(sum(r.retries for r in recs)), "failed": int(sum(1 for r in recs if r.status != 0))}
+    if trace:
+        t = np.array(trace, dtype=np.float64)
+        if len(t) > 1:
+            w = np.diff(t[:, 0])
+            out["mean_in_flight"] = float((t[:-1, 2] * w).sum() / max(w.sum(), 1e-9))
+            out["mean_queued"] = float((t[:-1, 1] * w).sum() / max(w.sum(), 1e-9))
+            out["max_queued"] = int(t[:, 1].max())
+    return out
+
+
+class GpuBackend:
+    """Runs each job through the C ABI on its own HIP stream."""
+
+    def __init__(self, k: int, qcut: int = 20, min_depth: int = 2, table_load: float = 0.45, bloom_bits: float = 12.0,
+                 n_hash: int = 4, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.k, self.qcut, self.min_depth = k, qcut, min_depth
+        self.table_load, self.bloom_bits, self.n_hash = table_load, bloom_bits, n_hash
+        self._streams = []
+
+    def sizes(self, j: Job):
+        from .kmer import next_pow2
+        cap = next_pow2(max(1024, int(j.meta.get("kept", j.kept_est) / self.table_load)))
+        bw = next_pow2(max(64, int(j.distinct_est * self.bloom_bits / 64)))
+        lcap = int(j.meta.get("list", j.distinct_est * 1.2)) + (1 << 20)
+        ocap = int(min(cap, j.meta.get("out", j.meta.get("kept", j.kept_est) * 1.3 + 1024)))
+        return cap, bw, lcap, ocap
+
+    def footprint(self, j: Job) -> int:
+        cap, bw, lcap, ocap = self.sizes(j)
+        return 2 * j.n_bases + j.n_bases // 2 + 64 * cap + 8 * bw + 17 * lcap + 54 * ocap
+
+    def _stream(self):
+        return self._streams.pop() if self._streams else self.torch.cuda.Stream(device=self.device)
+
+    def start(self, j: Job):
+        from . import kmer
+        torch = self.torch
+        st = self._stream()
+        cap, bw, lcap, ocap = self.sizes(j)
+        ascii_h, qual_h = j.payload
+        with torch.cuda.stream(st):
+            a = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
+            q = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
+            a.copy_(ascii_h, non_blocking=True)
+            q.copy_(qual_h, non_blocking=True)
+            kc = kmer.KmerCounter(self.k, cap, bw, lcap, n_hash=self.n_hash, min_depth=self.min_depth,
+                                  device=self.device)
+            out = kmer.Records(ocap, device=self.device)
+            packed = kmer.pack_reads(a, q, read_len=j.read_len, qcut=self.qcut, stream=st)
+            kc.run([packed], out, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"job": j, "stream": st, "event": ev, "kc": kc, "out": out, "bufs": (a, q, packed)}
+
+    def poll(self, h) -> bool:
+        return h["event"].query()
+
+    def finish(self, h):
+        from . import abi
+        kc, out, st, j = h["kc"], h["out"], h["stream"], h["job"]
+        rc = kc.status(stream=st)
+        result = None
+        status = "ok"
+        if rc == abi.HM_OK:
+            result = {"n_out": int(out.n_out.item()), "digest": out.digest_words()}
+        elif rc in (abi.HM_ECAPACITY, abi.HM_EOUTPUT):
+            # too small for this job: rerun from scratch with the structure that overflowed doubled
+            s = int(kc.status_buf.item())
+            meta = dict(j.meta)
+            if s & abi.HM_ST_TABLE_FULL:
+                meta["kept"] = 2 * meta.get("kept", j.kept_est)
+            if s & abi.HM_ST_LIST_FULL:
+                meta["list"] = 2 * meta.get("list", j.distinct_est * 1.2)
+            if rc == abi.HM_EOUTPUT:
+                meta["out"] = int(out.n_out.item() * 1.1) + 1024
+            status, result = "retry", Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est,
+                                          j.payload, meta)
+        else:
+            status = rc
+        h.clear()  # drop device buffers: the caching allocator reuses them once the stream is done
+        self._streams.append(st)
+        return status, result
+
+
+def make_jobs(pool, n_jobs: int, rate: float, seed: int = 170511151, pin: bool = True):
+    """An open-loop Poisson stream of `n_jobs` jobs at `rate` jobs/s whose
+    payloads cycle through `pool` (list of synth Workloads), each read once
+    into (pinned) host tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_jobs)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    payloads = []
+    for w in pool:
+        r = w.reads()
+        a = torch.from_numpy(r.ascii)
+        q = torch.from_numpy(r.qual)
+        if pin:
+            a, q = a.pin_memory(), q.pin_memory()
+        d, kept = w.size_estimates()
+        payloads.append((a, q, r.n_bases, r.read_len, d, kept, w.positions))
+    jobs, positions = [], {}
+    for i in range(n_jobs):
+        a, q, nb, L, d, kept, pos = payloads[i % len(payloads)]
+        jobs.append(Job(i, float(arrivals[i]), nb, L, d, kept, (a, q), {"pool": i % len(payloads)}))
+        positions[i] = pos
+    return jobs, positions

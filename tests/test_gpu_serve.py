@@ -1,0 +1,57 @@
+"""Serving on the GPU: every job's result is the same alone and in the mix
+(tolerance 0: integer output), and equals the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1705_11147_amd import abi, synth
+from paper_1705_11147_amd.serve import GpuBackend, Scheduler, make_jobs, summarize
+from tests.util import table_digest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.lib()
+    torch.cuda.set_device(0)
+
+
+def test_alone_equals_in_mix_equals_oracle():
+    _, builders = synth.serving_jobs(n_jobs=5, scale=0.005)
+    pool = [b() for b in builders]
+    jobs, positions = make_jobs(pool, n_jobs=10, rate=400.0)
+    be = GpuBackend(51)
+    mix = Scheduler(be, budget_bytes=8 << 30, max_slots=4).run(jobs)
+    assert all(r.status == 0 for r in mix)
+    s = summarize(mix, positions)
+    assert s["jobs"] == 10 and s["failed"] == 0
+    # the same job twice in the stream, and alone on an idle GPU
+    for r in mix:
+        twin = [x for x in mix if x.job % 5 == r.job % 5]
+        assert all(x.result == r.result for x in twin)
+    for p in range(5):
+        alone = Scheduler(GpuBackend(51), budget_bytes=8 << 30, max_slots=1).run([jobs[p]])
+        assert alone[0].result == mix[p].result, p
+    for p in (0, 3):
+        w = pool[p]
+        rd = w.reads()
+        exp = oracle.run(rd.ascii, rd.qual, rd.offsets(), 51, n_threads=4)
+        assert mix[p].result["n_out"] == len(exp["count"])
+        assert mix[p].result["digest"] == table_digest(exp)
+
+
+def test_capacity_retry_in_serving():
+    _, builders = synth.serving_jobs(n_jobs=2, scale=0.005)
+    pool = [b() for b in builders]
+    jobs, _ = make_jobs(pool, n_jobs=2, rate=100.0)
+    for j in jobs:
+        j.kept_est = 100.0  # far too small a table: the server must resize and rerun
+    recs = Scheduler(GpuBackend(51), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
+    assert all(r.status == 0 and r.retries > 0 for r in recs)
+    rd = pool[1].reads()
+    exp = oracle.run(rd.ascii, rd.qual, rd.offsets(), 51)
+    assert recs[1].result["digest"] == table_digest(exp)

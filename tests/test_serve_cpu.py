@@ -1,0 +1,115 @@
+"""Serving scheduler on the CPU: a fake backend and a virtual clock drive the
+same admission, slot and latency logic the GPU backend uses."""
+import numpy as np
+import pytest
+
+from paper_1705_11147_amd.serve import Job, Scheduler, summarize
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-4)
+
+
+class FakeBackend:
+    """Job j occupies j.n_bases bytes and runs for j.meta['dur'] seconds; a job
+    with meta['fail_once'] asks for one retry with a doubled footprint."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.live = []
+        self.max_live = 0
+        self.max_bytes = 0
+
+    def footprint(self, j):
+        return j.n_bases * j.meta.get("grow", 1)
+
+    def start(self, j):
+        h = {"job": j, "end": self.clock.now() + j.meta["dur"]}
+        self.live.append(h)
+        self.max_live = max(self.max_live, len(self.live))
+        self.max_bytes = max(self.max_bytes, sum(self.footprint(x["job"]) for x in self.live))
+        return h
+
+    def poll(self, h):
+        return self.clock.now() >= h["end"]
+
+    def finish(self, h):
+        self.live.remove(h)
+        j = h["job"]
+        if j.meta.get("fail_once") and j.meta.get("grow", 1) == 1:
+            meta = dict(j.meta, grow=2)
+            return "retry", Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est, None, meta)
+        return "ok", {"digest": j.id * 7919}
+
+
+def jobs_poisson(n, rate, seed=0, sizes=(10, 40), dur=(0.01, 0.05)):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1 / rate, n))
+    return [Job(i, float(t[i]), int(rng.integers(*sizes)), 150, 1, 1, None, {"dur": float(rng.uniform(*dur))})
+            for i in range(n)]
+
+
+def test_slots_budget_and_latency():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    jobs = jobs_poisson(200, rate=100)
+    sch = Scheduler(be, budget_bytes=100, max_slots=4, poll_s=1e-3)
+    recs = sch.run(jobs, clock=clock)
+    assert be.max_live <= 4 and be.max_bytes <= 100
+    for r, j in zip(recs, jobs):
+        assert r.status == 0 and r.result == {"digest": j.id * 7919}
+        assert r.admitted >= j.arrival - 1e-12 and r.done >= r.admitted + j.meta["dur"] - 1e-9
+    s = summarize(recs, {j.id: 1 for j in jobs}, sch.trace)
+    lat = np.array([r.latency for r in recs])
+    assert s["p50_ms"] == pytest.approx(np.percentile(lat, 50) * 1000)
+    assert s["p99_ms"] == pytest.approx(np.percentile(lat, 99) * 1000)
+    assert 0 < s["mean_in_flight"] <= 4
+
+
+def test_fifo_admission_and_continuous_batching():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    # job 0 is long; jobs 1 and 2 arrive while it runs and must start at once (free slots)
+    jobs = [Job(0, 0.0, 10, 150, 1, 1, None, {"dur": 1.0}), Job(1, 0.2, 10, 150, 1, 1, None, {"dur": 0.1}),
+            Job(2, 0.3, 10, 150, 1, 1, None, {"dur": 0.1})]
+    recs = Scheduler(be, 100, 3, poll_s=1e-3).run(jobs, clock=clock)
+    assert recs[1].admitted < 0.21 and recs[2].admitted < 0.31
+    assert recs[1].done < recs[0].done
+    # with one slot the same stream is served strictly first-come first-served
+    clock = VirtualClock()
+    recs1 = Scheduler(FakeBackend(clock), 100, 1, poll_s=1e-3).run(jobs, clock=clock)
+    assert recs1[0].done <= recs1[1].admitted <= recs1[1].done <= recs1[2].admitted
+
+
+def test_head_of_line_waits_for_memory():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    jobs = [Job(0, 0.0, 60, 150, 1, 1, None, {"dur": 0.5}), Job(1, 0.01, 60, 150, 1, 1, None, {"dur": 0.1}),
+            Job(2, 0.02, 10, 150, 1, 1, None, {"dur": 0.1})]
+    recs = Scheduler(be, 100, 8, poll_s=1e-3).run(jobs, clock=clock)
+    assert recs[1].admitted >= recs[0].done  # 60 + 60 > 100
+    assert recs[2].admitted >= recs[1].admitted  # FIFO: no overtaking
+    assert be.max_bytes <= 100
+
+
+def test_retry_and_rejection():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    jobs = [Job(0, 0.0, 20, 150, 1, 1, None, {"dur": 0.1, "fail_once": True})]
+    recs = Scheduler(be, 100, 2, poll_s=1e-3).run(jobs, clock=clock)
+    assert recs[0].retries == 1 and recs[0].status == 0
+    with pytest.raises(ValueError):
+        Scheduler(FakeBackend(VirtualClock()), 10, 2).run([Job(0, 0.0, 20, 150, 1, 1, None, {"dur": 0.1})],
+                                                            clock=VirtualClock())
+    # a retry that no longer fits the budget ends as a capacity failure, not a hang
+    clock = VirtualClock()
+    recs = Scheduler(FakeBackend(clock), 30, 2, poll_s=1e-3).run(
+        [Job(0, 0.0, 20, 150, 1, 1, None, {"dur": 0.1, "fail_once": True})], clock=clock)
+    assert recs[0].status == "capacity"
