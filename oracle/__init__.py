@@ -22,6 +22,7 @@ _SO = os.path.join(_HERE, "libkmer_oracle.so")
 
 FORWARD_ONLY = 1
 KEEP_ALL = 2
+SPLIT_READS = 4
 
 CLS_FORK = 4
 CLS_X = 5
@@ -74,7 +75,8 @@ def lib():
 
 def run(ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray, k: int, qcut: int = 20, min_depth: int = 2,
         ext_min: int | None = None, n_owners: int = 1, owner: int = 0, n_shards: int = 1, shard: int = 0,
-        qual_offset: int = 0, forward_only: bool = False, keep_all: bool = False, n_threads: int = 1) -> dict:
+        qual_offset: int = 0, forward_only: bool = False, keep_all: bool = False, n_threads: int = 1,
+        split_reads: bool = False) -> dict:
     """Oracle table as a dict of numpy arrays sorted by (key_hi, key_lo):
     key_hi, key_lo (uint64), count (uint32), tl, tr (uint32, n x 4),
     cls_l, cls_r (uint8: 0..3 unique base, 4 fork, 5 none), plus
@@ -87,7 +89,8 @@ def run(ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray, k: int, qcut:
         raise ValueError("read offsets exceed the base arrays")
     ext_min = min_depth if ext_min is None else ext_min
     p = OrcParams(k, qual_offset, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard,
-                  (FORWARD_ONLY if forward_only else 0) | (KEEP_ALL if keep_all else 0), n_threads)
+                  (FORWARD_ONLY if forward_only else 0) | (KEEP_ALL if keep_all else 0) |
+                  (SPLIT_READS if split_reads else 0), n_threads)
     h = ctypes.c_void_p()
     L = lib()
     t0 = time.perf_counter()

@@ -36,9 +36,14 @@
  *     H = fmix64(fmix64(hi ^ 0x243F6A8885A308D3) ^ lo), fmix64 being the
  *     64-bit finalizer of Austin Appleby's MurmurHash3 (public domain).
  *
- * Threads: thread t of T keeps the keys whose (separately seeded) partition
- * hash is t and scans every read; the union over threads is the table by the
- * owner-partition identity.  Output records are sorted by key.
+ * Threads, two plain schemes (both exact, each pinned by a test):
+ *   - key-partitioned (default): thread t of T keeps the keys whose
+ *     separately seeded partition hash is t and scans every read; the union
+ *     over threads is the table by the owner-partition identity;
+ *   - read-partitioned (ORC_SPLIT_READS): thread t counts reads
+ *     [t*N/T, (t+1)*N/T) into its own map and the maps are summed key by key
+ *     before the depth filter, by additivity of unfiltered tables.
+ * Output records are sorted by key.
  */
 #include <algorithm>
 #include <cstdint>
@@ -95,7 +100,7 @@ typedef std::unordered_map<u128, Tally, KeyHash> Map;
 
 extern "C" {
 
-enum { ORC_FORWARD_ONLY = 1, ORC_KEEP_ALL = 2 };
+enum { ORC_FORWARD_ONLY = 1, ORC_KEEP_ALL = 2, ORC_SPLIT_READS = 4 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOVERFLOW = -2 };
 
 typedef struct {
@@ -208,10 +213,18 @@ int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_o
     if (p->n_shards < 1 || p->shard >= p->n_shards) return ORC_EINVAL;
     if (n_reads < 0) return ORC_EINVAL;
     const uint32_t T = p->n_threads > 1 ? (uint32_t)p->n_threads : 1u;
+    const bool split_reads = (p->flags & ORC_SPLIT_READS) != 0;
     std::vector<Map> maps(T);
     std::vector<int> rcs(T, 0);
     std::vector<int64_t> npos(T, 0);
-    auto work = [&](uint32_t t) { rcs[t] = scan_reads(ascii, qual, read_off, n_reads, p, T, t, maps[t], &npos[t]); };
+    auto work = [&](uint32_t t) {
+        if (split_reads) {  // reads [r0, r1) into this thread's own map, every key kept
+            const int64_t r0 = n_reads * t / T, r1 = n_reads * (t + 1) / T;
+            rcs[t] = scan_reads(ascii, qual, read_off + r0, r1 - r0, p, 1, 0, maps[t], &npos[t]);
+        } else {
+            rcs[t] = scan_reads(ascii, qual, read_off, n_reads, p, T, t, maps[t], &npos[t]);
+        }
+    };
     if (T == 1) {
         work(0);
     } else {
@@ -221,6 +234,23 @@ int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_o
     }
     for (uint32_t t = 0; t < T; ++t)
         if (rcs[t] != ORC_OK) return rcs[t];
+    if (split_reads && T > 1) {  // sum the per-thread tables key by key
+        for (uint32_t t = 1; t < T; ++t) {
+            for (auto &kv : maps[t]) {
+                Tally &d = maps[0][kv.first];
+                if ((uint64_t)d.cnt + kv.second.cnt > UINT32_MAX) return ORC_EOVERFLOW;
+                d.cnt += kv.second.cnt;
+                for (int b = 0; b < 4; ++b) {
+                    d.tl[b] += kv.second.tl[b];
+                    d.tr[b] += kv.second.tr[b];
+                }
+            }
+            Map().swap(maps[t]);
+        }
+        int64_t total = 0;
+        for (uint32_t t = 0; t < T; ++t) total += npos[t];
+        npos[0] = total;
+    }
     orc_result *res = new orc_result();
     res->positions = npos[0];
     const bool keep_all = (p->flags & ORC_KEEP_ALL) != 0;

@@ -110,6 +110,11 @@ def test_brute_force_larger_k_and_threads():
         exp = brute.brute(reads, k, qcut=20, min_depth=2)
         for T in (1, 3):
             assert table_to_dict(run_reads(reads, k, qcut=20, min_depth=2, n_threads=T)) == exp
+            assert table_to_dict(run_reads(reads, k, qcut=20, min_depth=2, n_threads=T, split_reads=True)) == exp
+        got = run_reads(reads, k, qcut=20, min_depth=2, n_threads=4, split_reads=True, n_shards=3, shard=1)
+        assert table_to_dict(got) == {key: v for key, v in exp.items()
+                                      if oracle.shard_of(np.array([key >> 64], np.uint64),
+                                                         np.array([key & (2 ** 64 - 1)], np.uint64), 3)[0] == 1}
 
 
 def test_owner_map_matches_independent_python():
