@@ -53,9 +53,10 @@ def sizes_for(w, distinct_est: float, kept_est: float):
     """Table / Bloom / list sizes from estimates of distinct k-mers and of the
     k-mers seen at least twice (the workload recipe fixes both)."""
     from paper_1705_11147_amd.kmer import next_pow2
+    from paper_1705_11147_amd.kmer import list_slack
     cap = next_pow2(int(kept_est / 0.45))
     bloom_words = next_pow2(int(distinct_est * 12 / 64))
-    list_cap = int(distinct_est * 1.15)
+    list_cap = int(distinct_est * 1.15) + list_slack(1)
     return cap, bloom_words, list_cap
 
 

@@ -31,6 +31,14 @@ def next_pow2(x: int) -> int:
     return 1 << (x - 1).bit_length()
 
 
+def list_slack(pass1_launches: int = 1, device=None) -> int:
+    """First-occurrence list entries a pass-1 launch can leave unused: every
+    wave reserves list space in chunks of 256 entries and may strand up to
+    255 at its end (8 blocks of 4 waves per CU)."""
+    cus = torch.cuda.get_device_properties(device or torch.cuda.current_device()).multi_processor_count
+    return int(pass1_launches) * cus * 8 * 4 * 255
+
+
 def _empty_u64(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.int64, device=device)
 
@@ -138,9 +146,8 @@ class KmerCounter:
 
     capacity:      table slots (power of two, 64 bytes each)
     bloom_words:   Bloom filter words (power of two, 8 bytes each); n_hash bits per key
-    list_capacity: first-occurrence list entries (17 bytes each); at most one per
-                   distinct k-mer plus repeats of none, so the number of distinct
-                   k-mers bounds it
+    list_capacity: first-occurrence list entries (17 bytes each): at most one per
+                   distinct k-mer, plus list_slack() per pass-1 launch
     """
 
     def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,

@@ -165,7 +165,7 @@ class GpuBackend:
         from .kmer import next_pow2
         cap = next_pow2(max(1024, int(j.meta.get("kept", j.kept_est) / self.table_load)))
         bw = next_pow2(max(64, int(j.distinct_est * self.bloom_bits / 64)))
-        lcap = int(j.meta.get("list", j.distinct_est * 1.2)) + (1 << 20)
+        lcap = int(j.meta.get("list", j.distinct_est * 1.2)) + (1 << 20) + 4 * 8192 * 255
         ocap = int(min(cap, j.meta.get("out", j.meta.get("kept", j.kept_est) * 1.3 + 1024)))
         return cap, bw, lcap, ocap
 

@@ -87,7 +87,7 @@ def test_human_share_streamed_batches():
     cuts = [0, n // 5, n // 2, (4 * n) // 5, n]
     d, kept = w.size_estimates()
     kc = kmer.KmerCounter(p.k, kmer.next_pow2(int(kept / 16 / 0.3)), kmer.next_pow2(int(d / 16 * 12 / 64)),
-                          int(d / 16 * 1.3) + (1 << 20), n_owners=p.n_owners, owner=p.owner, device=dev)
+                          int(d / 16 * 1.3) + kmer.list_slack(4), n_owners=p.n_owners, owner=p.owner, device=dev)
     kc.reset()
     host = []
     for i in range(4):
