@@ -310,8 +310,11 @@ def main():
             "atomic_add_Gops": round(m["atomic_add"]["ops_per_s"] / 1e9, 2),
             "atomic_or_ret_Gops": round(m["atomic_or_ret"]["ops_per_s"] / 1e9, 2),
             "copy_GBps": round(m["copy"]["GBps"], 1)}
-        atomics = (occ - deferred) * 2 + bloom_tests  # counter atomics per counted occurrence + Bloom ORs
-        roofline["pass1_atomic_rate_Gops"] = round(atomics / (stage_ms["pass1"] / 1000) / 1e9, 2)
+        # random memory requests of pass 1 (from the counters): a 16-byte load per probed slot,
+        # an 8-byte load of the second key word per match, Bloom ORs, counting CASes (and the
+        # wide atomics when a counter overflows its packed lane)
+        reqs = st["probe_slots"] + (occ - deferred) + bloom_tests + st["cas_attempts"] + 2 * st["wide_counts"]
+        roofline["pass1_random_requests_Gps"] = round(reqs / (stage_ms["pass1"] / 1000) / 1e9, 2)
 
     cpu = None
     if not args.no_cpu:

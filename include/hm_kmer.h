@@ -116,7 +116,9 @@ typedef struct {
 #define HM_STAT_PROBES 4     /* pass 1: table slots inspected */
 #define HM_STAT_P2_ENTRIES 5 /* pass 2: list entries processed */
 #define HM_STAT_P2_FOUND 6   /* pass 2: entries whose k-mer was in the table */
-#define HM_N_STATS 8
+#define HM_STAT_CAS 7        /* pass 1: compare-and-swap attempts on packed counters */
+#define HM_STAT_WIDE 8       /* pass 1: occurrences counted in the wide counters */
+#define HM_N_STATS 10
 
 /* Open-addressing count table of `capacity` 64-byte slots (power of two). */
 typedef struct {

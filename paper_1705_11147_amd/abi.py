@@ -56,7 +56,7 @@ class Table(ctypes.Structure):
 
 
 STAT_NAMES = ["occurrences", "hit_first_lookup", "bloom_tests", "deferred", "probe_slots", "p2_entries",
-              "p2_found", "reserved"]
+              "p2_found", "cas_attempts", "wide_counts", "reserved"]
 
 
 class Bloom(ctypes.Structure):

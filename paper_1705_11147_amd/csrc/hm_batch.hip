@@ -258,10 +258,10 @@ __device__ void item_pass2(const PassArgs &a, int64_t j, int64_t E) {
         if (x == kHole) continue;
         uint64_t A, B;
         slot_words<KW>(hi, lo, A, B);
-        const Probe pr = table_find<KW, true>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
+        const Probe pr = table_find<KW>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
         st.v[HM_STAT_P2_ENTRIES] += 1;
         st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
-        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, x & 15, x >> 4, a.status);
+        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, x & 15, x >> 4, a.status, pr.narrow);
         else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
     }
     stats_flush(a.stats, st);
@@ -285,11 +285,7 @@ __device__ void item_export(const BatchHeader *hdr, const BatchDesc &d, int64_t 
             if (i < end && d.slots[i].a != 0) {
                 const Slot *sl = d.slots + i;
                 uint32_t tl[4], tr[4];
-                for (int b = 0; b < 4; ++b) {
-                    tl[b] = sl->tl[b];
-                    tr[b] = sl->tr[b];
-                }
-                const uint64_t cnt = (uint64_t)sl->nl + tl[0] + tl[1] + tl[2] + tl[3];
+                const uint64_t cnt = slot_counts(sl, tl, tr);
                 if (cnt > 0xFFFFFFFFull) atomicOr(d.status, HM_ST_OVERFLOW);
                 const bool kept = cnt >= min_depth;
                 const uint32_t cl = side_class(tl, ext_min), cr = side_class(tr, ext_min);
@@ -323,11 +319,7 @@ __device__ void item_export(const BatchHeader *hdr, const BatchDesc &d, int64_t 
                 hi = A >> 1;
             }
             uint32_t tl[4], tr[4];
-            for (int b = 0; b < 4; ++b) {
-                tl[b] = sl->tl[b];
-                tr[b] = sl->tr[b];
-            }
-            const uint32_t count = sl->nl + tl[0] + tl[1] + tl[2] + tl[3];
+            const uint32_t count = (uint32_t)slot_counts(sl, tl, tr);
             const uint32_t cl = side_class(tl, ext_min), cr = side_class(tr, ext_min);
             if (idx < out.capacity) {
                 out.key_hi[idx] = hi;

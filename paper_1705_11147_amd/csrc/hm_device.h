@@ -17,6 +17,8 @@ namespace hm {
 
 constexpr uint64_t kWritten = 1ull << 63;   // set in every written key word
 constexpr uint64_t kLow63 = kWritten - 1;
+constexpr uint64_t kWideBit = 1ull << 63;   // narrow counters frozen, counting goes wide
+constexpr int kCasTries = 3;                // narrow CAS attempts before going wide
 constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ull;  // owner map (definition constant)
 constexpr int kBlock = 256;
 constexpr int kTileBases = 16384;           // bases staged in LDS per tile
@@ -34,14 +36,21 @@ __device__ __forceinline__ bool aborted(const uint32_t *status) {
     return (__builtin_amdgcn_readfirstlane(st) & kAbortBits) != 0;
 }
 
+// A slot's counters live in two forms.  `narrow` packs nine 7-bit counters
+// (lane 0: occurrences without a left extension, lanes 1..4: left tallies
+// A,C,G,T, lanes 5..8: right tallies) and takes one CAS per occurrence.  A
+// counter about to pass 127, or repeated CAS contention, sets kWideBit: the
+// narrow lanes freeze and later occurrences of the k-mer go to the 32-bit
+// wide counters (two atomic adds).  Every occurrence lands in exactly one of
+// the two, so the totals are narrow + wide.
 struct Slot {
     uint64_t a;       // k <= 31: key | written;  k >= 32: key bits 63..125 | written
+    uint64_t narrow;  // 9 x 7-bit counters | kWideBit (next to a: one 16-byte load reads both)
     uint64_t b;       // k >= 32: key bits 0..62 | written
-    uint32_t tl[4];
-    uint32_t tr[4];
-    uint32_t nl;      // occurrences with no left extension
+    uint32_t nl;      // wide: occurrences with no left extension
+    uint32_t tl[4];   // wide: left tallies
+    uint32_t tr[4];   // wide: right tallies
     uint32_t cls;     // classify: cls_l | cls_r << 8 | kept << 16 | count >= 2^32 << 17
-    uint64_t pad;
 };
 static_assert(sizeof(Slot) == HM_SLOT_BYTES, "slot is one 64-byte line");
 
@@ -191,50 +200,75 @@ struct Probe {
     int64_t slot;
     uint64_t at;
     uint32_t used;
+    uint64_t narrow;  // the slot's narrow counter word as loaded with the key (a hint for the CAS)
 };
 
 // Locate (A, B) by linear probing from `start` (the first `used0` slots of
-// the sequence were already probed by an earlier call).  COHERENT: the table
-// is being written by this kernel (device-scope atomic loads); otherwise keys
-// are immutable and plain loads suffice.  With `insert`, an absent key claims
-// the first empty slot: CAS on word a, then store of word b.  A reader that
-// sees a matching a and an unwritten b re-reads the slot.  Key words are
-// written once and never cleared, so a probe that stopped at an empty slot
-// can resume there.
-template <int KW, bool COHERENT>
+// the sequence were already probed by an earlier call).  With `insert`, an
+// absent key claims the first empty slot: CAS on word a, then store of word b;
+// a reader that sees a matching a and an unwritten b re-reads b with a
+// device-scope atomic load until it is published.  Key words are written once
+// and never cleared, so a probe that stopped at an empty slot can resume
+// there.
+//
+// Probes read a and the narrow counter word with one plain 16-byte load (and
+// b only when a matches).  A plain load may return an older value of the line
+// than another CU's latest atomic, and that is harmless here: a key word is
+// either 0 or final, so a stale read can only show a slot as empty.  An
+// inserting probe then learns the truth from its CAS; a non-inserting probe
+// reports the key absent, and the caller's Bloom test (an atomic) either
+// sends it to the inserting probe or defers the occurrence to pass 2, which
+// counts it if the key is in the table.  A stale narrow word only makes the
+// counting CAS fail once and retry with the value the CAS returned.
+template <int KW>
 __device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_t start, uint64_t A, uint64_t B,
                                             uint32_t max_probe, bool insert, uint32_t used0 = 0) {
     uint64_t i = start & cmask;
     uint32_t probes = used0, spins = 0;
     while (true) {
         Slot *s = slots + i;
-        uint64_t a = COHERENT ? __hip_atomic_load(&s->a, RLX, AGT) : s->a;
+        const uint4 v = *reinterpret_cast<const uint4 *>(s);  // a, narrow
+        uint64_t a = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        const uint64_t nw = (uint64_t)v.z | ((uint64_t)v.w << 32);
         if (a == 0) {
-            if (!insert) return Probe{-1, i, probes};
+            if (!insert) return Probe{-1, i, probes, 0};
             uint64_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(&s->a, &expected, A, RLX, RLX, AGT)) {
                 if (KW == 2) __hip_atomic_store(&s->b, B, RLX, AGT);
-                return Probe{(int64_t)i, i, probes};
+                return Probe{(int64_t)i, i, probes, 0};
             }
             a = expected;
         }
         if (a == A) {
-            if (KW == 1) return Probe{(int64_t)i, i, probes};
-            const uint64_t b = COHERENT ? __hip_atomic_load(&s->b, RLX, AGT) : s->b;
-            if (b == B) return Probe{(int64_t)i, i, probes};
-            // claimed for a key with the same word a, word b not visible yet: re-read
-            if (COHERENT && b == 0) {
-                if (++spins > kMaxSpin) return Probe{-2, i, probes};
-                continue;
+            if (KW == 1) return Probe{(int64_t)i, i, probes, nw};
+            uint64_t b = s->b;
+            while (b == 0) {  // claimed for a key with the same word a, word b not visible yet
+                if (++spins > kMaxSpin) return Probe{-2, i, probes, 0};
+                b = __hip_atomic_load(&s->b, RLX, AGT);
             }
+            if (b == B) return Probe{(int64_t)i, i, probes, nw};
         }
         i = (i + 1) & cmask;
-        if (++probes >= max_probe) return Probe{-2, i, probes};
+        if (++probes >= max_probe) return Probe{-2, i, probes, 0};
     }
 }
 
+// Count one occurrence with its extensions (left/right: base 0..3 or 4 = none).
+// One CAS on the narrow word in the common case; wide 32-bit counters once the
+// narrow lanes are frozen.  Returns the number of CAS attempts (for stats).
 template <bool CHECKED>
-__device__ __forceinline__ void count_occurrence(Slot *s, int left, int right, uint32_t *status) {
+__device__ __forceinline__ uint32_t count_occurrence(Slot *s, int left, int right, uint32_t *status, uint64_t hint) {
+    const int ll = left < 4 ? 1 + left : 0;
+    const int rl = 5 + right;  // only used when right < 4
+    const uint64_t inc = (1ull << (7 * ll)) + (right < 4 ? (1ull << (7 * rl)) : 0ull);
+    uint64_t old = hint;
+    uint32_t tries = 0;
+    while (!(old & kWideBit) && tries < (uint32_t)kCasTries) {
+        if (((old >> (7 * ll)) & 127) == 127 || (right < 4 && ((old >> (7 * rl)) & 127) == 127)) break;
+        ++tries;
+        if (__hip_atomic_compare_exchange_strong(&s->narrow, &old, old + inc, RLX, RLX, AGT)) return tries;
+    }
+    if (!(old & kWideBit)) __hip_atomic_fetch_or(&s->narrow, kWideBit, RLX, AGT);  // freeze the narrow lanes
     uint32_t *lp = left < 4 ? &s->tl[left] : &s->nl;
     if (CHECKED) {
         uint32_t o = __hip_atomic_fetch_add(lp, 1u, RLX, AGT);
@@ -244,6 +278,19 @@ __device__ __forceinline__ void count_occurrence(Slot *s, int left, int right, u
         __hip_atomic_fetch_add(lp, 1u, RLX, AGT);
         if (right < 4) __hip_atomic_fetch_add(&s->tr[right], 1u, RLX, AGT);
     }
+    return tries + 16;  // >= 16 marks a wide update
+}
+
+// Totals of a slot (narrow + wide), for classification and export.
+__device__ __forceinline__ uint64_t slot_counts(const Slot *s, uint32_t tl[4], uint32_t tr[4]) {
+    const uint64_t nw = s->narrow;
+    uint64_t cnt = (uint64_t)s->nl + (nw & 127);
+    for (int b = 0; b < 4; ++b) {
+        tl[b] = s->tl[b] + (uint32_t)((nw >> (7 * (1 + b))) & 127);
+        tr[b] = s->tr[b] + (uint32_t)((nw >> (7 * (5 + b))) & 127);
+        cnt += tl[b];
+    }
+    return cnt;
 }
 
 // ------------------------------------------------------------------ wave helpers
@@ -322,7 +369,7 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
         const uint64_t h = key_hash(o.hi, o.lo, a.seed);
         uint64_t A, B;
         slot_words<KW>(o.hi, o.lo, A, B);
-        Probe pr = table_find<KW, true>(a.slots, a.cmask, h, A, B, a.max_probe, a.bypass != 0);
+        Probe pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, a.bypass != 0);
         st.v[HM_STAT_OCC] += 1;
         st.v[HM_STAT_HIT] += pr.slot >= 0 ? 1u : 0u;
         if (pr.slot == -1) {
@@ -332,13 +379,18 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
             for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
             uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
             const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
-            if ((old & mask) == mask) pr = table_find<KW, true>(a.slots, a.cmask, pr.at, A, B, a.max_probe, true, pr.used);
+            if ((old & mask) == mask) pr = table_find<KW>(a.slots, a.cmask, pr.at, A, B, a.max_probe, true, pr.used);
             else deferred = true;
         }
         st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;
         st.v[HM_STAT_PROBES] += pr.used + 1;
-        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, o.left, o.right, a.status);
-        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
+        if (pr.slot >= 0) {
+            const uint32_t c = count_occurrence<CHECKED>(a.slots + pr.slot, o.left, o.right, a.status, pr.narrow);
+            st.v[HM_STAT_CAS] += c & 15;
+            st.v[HM_STAT_WIDE] += c >= 16 ? 1u : 0u;
+        } else if (pr.slot == -2) {
+            atomicOr(a.status, HM_ST_TABLE_FULL);
+        }
     }
     if (!a.bypass) {
         const bool need = deferred;

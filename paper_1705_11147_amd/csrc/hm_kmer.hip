@@ -180,10 +180,10 @@ __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
         if (e == kHole) continue;
         uint64_t A, B;
         slot_words<KW>(hi, lo, A, B);
-        const Probe pr = table_find<KW, false>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
+        const Probe pr = table_find<KW>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
         st.v[HM_STAT_P2_ENTRIES] += 1;
         st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
-        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, e & 15, e >> 4, a.status);
+        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, e & 15, e >> 4, a.status, pr.narrow);
         else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
     }
     stats_flush(a.stats, st);
@@ -194,11 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, 
         Slot *s = slots + i;
         if (s->a == 0) continue;
         uint32_t tl[4], tr[4];
-        for (int b = 0; b < 4; ++b) {
-            tl[b] = s->tl[b];
-            tr[b] = s->tr[b];
-        }
-        const uint64_t cnt = (uint64_t)s->nl + tl[0] + tl[1] + tl[2] + tl[3];
+        const uint64_t cnt = slot_counts(s, tl, tr);
         const uint32_t kept = cnt >= min_depth ? 1u : 0u;
         const uint32_t ovf = cnt > 0xFFFFFFFFull ? 1u : 0u;
         s->cls = side_class(tl, ext_min) | (side_class(tr, ext_min) << 8) | (kept << 16) | (ovf << 17);
@@ -262,13 +258,9 @@ __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t c
                 hi = A >> 1;
             }
             uint32_t tl[4], tr[4];
-            for (int b = 0; b < 4; ++b) {
-                tl[b] = sl->tl[b];
-                tr[b] = sl->tr[b];
-            }
+            const uint32_t count = (uint32_t)slot_counts(sl, tl, tr);
             const uint32_t c = sl->cls;
             const uint32_t cl = c & 0xFF, cr = (c >> 8) & 0xFF;
-            const uint32_t count = sl->nl + tl[0] + tl[1] + tl[2] + tl[3];
             if (idx < out.capacity) {
                 out.key_hi[idx] = hi;
                 out.key_lo[idx] = lo;

@@ -161,7 +161,7 @@ class KmerCounter:
         self.capacity = next_pow2(capacity)
         self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
         self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.stats_buf = torch.zeros(8, dtype=torch.int64, device=self.device)
+        self.stats_buf = torch.zeros(10, dtype=torch.int64, device=self.device)
         self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr(),
                                self.stats_buf.data_ptr())
         self.bloom_words = next_pow2(bloom_words) if not self.bypass else 1
