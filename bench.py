@@ -214,7 +214,7 @@ def main():
     while True:
         kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth, device=dev)
         out = kmer.Records(int(cap * 0.6), device=dev)
-        kc.run([packed], out)
+        kc.run([packed], out, fused=True)
         rc = kc.status()
         if rc == abi.HM_OK:
             break
@@ -230,7 +230,7 @@ def main():
         if rc == abi.HM_EOUTPUT:
             need = int(out.n_out.item())
             out = kmer.Records(int(need * 1.1), device=dev)
-            kc.run([packed], out)
+            kc.run([packed], out, fused=True)
             abi.check(kc.status(), "k-mer analysis")
             break
         abi.check(rc, "k-mer analysis")
@@ -241,7 +241,7 @@ def main():
         kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, kc.bloom_words * 8 / 1e9, list_cap * 17 / 1e9,
         n_records, n_first))
 
-    stages = ["pack", "init", "pass1", "pass2", "classify", "export"]
+    stages = ["pack", "init", "pass1", "pass2", "classify_export"]
 
     def step(ev=None):
         def mark(i):
@@ -256,15 +256,13 @@ def main():
         mark(3)
         kc.count()
         mark(4)
-        kc.classify()
+        kc.export(out, abi.HM_EXPORT_CLASSIFY)  # depth filter + classification fused into the export sweep
         mark(5)
-        kc.export(out)
-        mark(6)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
@@ -350,7 +348,7 @@ def main():
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
                    "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
                    "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": 4,
-                   "step": "pack+init+pass1+pass2+classify+export, inputs resident in HBM",
+                   "step": "pack+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,

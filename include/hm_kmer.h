@@ -71,8 +71,10 @@ extern "C" {
 #define HM_CHECKED 4u      /* detect counter overflow (needed only past 2^32 positions per table) */
 
 /* hm_export_table flags */
-#define HM_EXPORT_UU_ONLY 1u /* only kept k-mers unique on both sides */
-#define HM_EXPORT_ALL 2u     /* every k-mer in the table, also below min_depth */
+#define HM_EXPORT_UU_ONLY 1u  /* only kept k-mers unique on both sides */
+#define HM_EXPORT_ALL 2u      /* every k-mer in the table, also below min_depth */
+#define HM_EXPORT_CLASSIFY 4u /* classify while exporting (hm_classify_ext not needed first);
+                                 needs the min_depth/ext_min of hm_export_t */
 
 #define HM_CLS_FORK 4
 #define HM_CLS_X 5
@@ -139,12 +141,20 @@ typedef struct {
 } hm_bloom_t;
 
 /* First-occurrence list between the two counting passes: one entry per
- * occurrence that the Bloom filter had not seen (key: 2 words, ext: 1 byte). */
+ * occurrence that the Bloom filter had not seen (key: 2 words, ext: 1 byte).
+ * Optional presence filter: pass 1 sets present_hash bits of every k-mer it
+ * inserts into the table in one word of `present` (n_words a power of two),
+ * and pass 2 skips the table lookup of entries whose bits are not all set
+ * (those k-mers were never inserted).  Sized near the number of table keys
+ * it stays cache-resident; it never changes the output. */
 typedef struct {
     uint64_t *keys;  /* 2 * capacity words */
     uint8_t *ext;    /* capacity bytes */
     uint64_t capacity;
     uint64_t *count; /* device counter of entries (zeroed by hm_list_init) */
+    uint64_t *present;      /* optional (may be NULL) */
+    uint64_t present_words; /* power of two when present != NULL */
+    uint32_t present_hash;  /* bits per k-mer, 1..8 */
 } hm_list_t;
 
 /* Export destination: structure-of-arrays records. */
@@ -159,6 +169,8 @@ typedef struct {
     uint64_t capacity;
     uint64_t *n_out;  /* device counter: records exported (or needed, on HM_EOUTPUT) */
     uint64_t *digest; /* optional (may be NULL): 2 words, order-free sum and xor of per-record hashes */
+    uint32_t min_depth; /* used with HM_EXPORT_CLASSIFY */
+    uint32_t ext_min;   /* used with HM_EXPORT_CLASSIFY */
 } hm_export_t;
 
 /* ---- sizes and helpers ------------------------------------------------ */
@@ -177,7 +189,7 @@ int hm_check_params(const hm_params_t *p);
 int hm_table_init(hm_table_t *t, hipStream_t stream);
 /* Clear a Bloom filter. */
 int hm_bloom_init(hm_bloom_t *b, hipStream_t stream);
-/* Clear a first-occurrence list's counter. */
+/* Clear a first-occurrence list's counter (and its presence filter). */
 int hm_list_init(hm_list_t *l, hipStream_t stream);
 /* Synchronize `stream`, read the status word and map it to a return code. */
 int hm_status(const hm_table_t *t, hipStream_t stream);

@@ -31,6 +31,7 @@ HM_CHECKED = 4
 
 HM_EXPORT_UU_ONLY = 1
 HM_EXPORT_ALL = 2
+HM_EXPORT_CLASSIFY = 4
 
 HM_CLS_FORK = 4
 HM_CLS_X = 5
@@ -65,14 +66,15 @@ class Bloom(ctypes.Structure):
 
 class List(ctypes.Structure):
     _fields_ = [("keys", ctypes.c_void_p), ("ext", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
-                ("count", ctypes.c_void_p)]
+                ("count", ctypes.c_void_p), ("present", ctypes.c_void_p), ("present_words", ctypes.c_uint64),
+                ("present_hash", ctypes.c_uint32)]
 
 
 class Export(ctypes.Structure):
     _fields_ = [("key_hi", ctypes.c_void_p), ("key_lo", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("tl", ctypes.c_void_p), ("tr", ctypes.c_void_p), ("cls_l", ctypes.c_void_p),
                 ("cls_r", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("n_out", ctypes.c_void_p),
-                ("digest", ctypes.c_void_p)]
+                ("digest", ctypes.c_void_p), ("min_depth", ctypes.c_uint32), ("ext_min", ctypes.c_uint32)]
 
 
 class BatchSet(ctypes.Structure):

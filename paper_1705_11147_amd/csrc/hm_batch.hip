@@ -53,6 +53,9 @@ struct BatchDesc {
     uint8_t *lext;
     uint64_t lcap;
     unsigned long long *lcount;
+    uint64_t *present;
+    uint64_t present_words;
+    uint32_t present_hash;
     hm_export_t out;
     int64_t n_items[kPhases];
     int64_t n_export_items;
@@ -83,7 +86,7 @@ struct Layout {
     size_t desc, item_start, group, pack_start, export_start, regions, done, total;
 };
 
-constexpr int kRegionsPerSet = 7;
+constexpr int kRegionsPerSet = 8;
 
 Layout layout(int32_t S) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -202,6 +205,9 @@ __device__ __forceinline__ PassArgs pass_args(const BatchHeader *hdr, const Batc
     a.lext = d.lext;
     a.lcap = d.lcap;
     a.lcount = d.lcount;
+    a.present = d.present;
+    a.present_mask = d.present_words ? d.present_words - 1 : 0;
+    a.present_hash = d.present_hash;
     return a;
 }
 
@@ -253,105 +259,27 @@ __device__ void item_pass2(const PassArgs &a, int64_t j, int64_t E) {
     for (uint64_t i0 = b; i0 < e; i0 += kBlock) {
         const uint64_t i = i0 + threadIdx.x;
         if (i >= e) continue;
-        const uint64_t hi = a.lkeys[2 * i], lo = a.lkeys[2 * i + 1];
         const uint8_t x = a.lext[i];
         if (x == kHole) continue;
-        uint64_t A, B;
-        slot_words<KW>(hi, lo, A, B);
-        const Probe pr = table_find<KW>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
-        st.v[HM_STAT_P2_ENTRIES] += 1;
-        st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
-        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, x & 15, x >> 4, a.status, pr.narrow);
-        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
+        pass2_entry<KW, CHECKED>(a, a.lkeys[2 * i], a.lkeys[2 * i + 1], x, st);
     }
     stats_flush(a.stats, st);
 }
 
-// classify + export item: slots [j*SI, (j+1)*SI) of one set, 8 slots per lane
-// per wave iteration, one atomic per wave iteration for the output offset.
+// classify + export item: slots [j*SI, (j+1)*SI) of one set, 512-slot chunks
+// per wave, classes computed from the counters.
 template <int KW>
-__device__ void item_export(const BatchHeader *hdr, const BatchDesc &d, int64_t j, int64_t SI) {
-    const hm_export_t out = d.out;
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint64_t first_slot = (uint64_t)j * SI;
-    const uint64_t end = min(first_slot + (uint64_t)SI, d.capacity);
-    const uint32_t min_depth = hdr->min_depth, ext_min = hdr->ext_min, flags = hdr->export_flags;
+__device__ void item_export(const BatchHeader *hdr, const BatchDesc &d, int64_t j, int64_t SI, uint16_t *rank_of) {
+    hm_export_t out = d.out;
+    out.min_depth = hdr->min_depth;
+    out.ext_min = hdr->ext_min;
+    const uint32_t flags = hdr->export_flags | HM_EXPORT_CLASSIFY;
+    const uint64_t b = (uint64_t)j * SI, e = min(b + (uint64_t)SI, d.capacity);
     uint64_t dsum = 0, dxor = 0;
-    for (uint64_t base = first_slot + (uint64_t)wave * 512; base < end; base += (kBlock / 64) * 512) {
-        uint32_t take_bits = 0;
-#pragma unroll 1
-        for (int q = 0; q < 8; ++q) {
-            const uint64_t i = base + (uint64_t)q * 64 + lane;
-            if (i < end && d.slots[i].a != 0) {
-                const Slot *sl = d.slots + i;
-                uint32_t tl[4], tr[4];
-                const uint64_t cnt = slot_counts(sl, tl, tr);
-                if (cnt > 0xFFFFFFFFull) atomicOr(d.status, HM_ST_OVERFLOW);
-                const bool kept = cnt >= min_depth;
-                const uint32_t cl = side_class(tl, ext_min), cr = side_class(tr, ext_min);
-                bool take = (flags & HM_EXPORT_ALL) ? true : kept;
-                if (flags & HM_EXPORT_UU_ONLY) take = take && kept && cl < 4 && cr < 4;
-                take_bits |= (take ? 1u : 0u) << q;
-            }
-        }
-        const uint32_t cnt = (uint32_t)__popc(take_bits);
-        uint32_t incl = cnt;
-        for (int dd = 1; dd < 64; dd <<= 1) {
-            const uint32_t y = __shfl_up(incl, dd);
-            if ((int)lane >= dd) incl += y;
-        }
-        const uint32_t total = __shfl(incl, 63);
-        if (total == 0) continue;
-        unsigned long long obase = 0;
-        if (lane == 0) obase = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out), (unsigned long long)total);
-        obase = __shfl(obase, 0);
-        uint64_t idx = obase + (incl - cnt);
-#pragma unroll 1
-        for (int q = 0; q < 8; ++q) {
-            if (!((take_bits >> q) & 1)) continue;
-            const Slot *sl = d.slots + base + (uint64_t)q * 64 + lane;
-            uint64_t hi = 0, lo;
-            if (KW == 1) {
-                lo = sl->a & kLow63;
-            } else {
-                const uint64_t A = sl->a & kLow63, B = sl->b & kLow63;
-                lo = B | (A << 63);
-                hi = A >> 1;
-            }
-            uint32_t tl[4], tr[4];
-            const uint32_t count = (uint32_t)slot_counts(sl, tl, tr);
-            const uint32_t cl = side_class(tl, ext_min), cr = side_class(tr, ext_min);
-            if (idx < out.capacity) {
-                out.key_hi[idx] = hi;
-                out.key_lo[idx] = lo;
-                out.count[idx] = count;
-                for (int b = 0; b < 4; ++b) {
-                    out.tl[4 * idx + b] = tl[b];
-                    out.tr[4 * idx + b] = tr[b];
-                }
-                out.cls_l[idx] = (uint8_t)cl;
-                out.cls_r[idx] = (uint8_t)cr;
-            } else {
-                atomicOr(d.status, HM_ST_OUTPUT_FULL);
-            }
-            if (out.digest) {
-                const uint64_t x = record_hash(hi, lo, count, tl, tr, cl, cr);
-                dsum += x;
-                dxor ^= x;
-            }
-            ++idx;
-        }
-    }
-    if (out.digest) {
-        for (int off = 32; off > 0; off >>= 1) {
-            dsum += __shfl_xor(dsum, off);
-            dxor ^= __shfl_xor(dxor, off);
-        }
-        if (lane == 0 && (dsum | dxor)) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(out.digest), (unsigned long long)dsum);
-            atomicXor(reinterpret_cast<unsigned long long *>(out.digest + 1), (unsigned long long)dxor);
-        }
-    }
+    for (uint64_t first = b + (threadIdx.x >> 6) * (uint64_t)kExportChunk; first < e;
+         first += (kBlock / 64) * (uint64_t)kExportChunk)
+        export_chunk<KW>(d.slots, first, e, flags, out, d.status, rank_of, dsum, dxor);
+    digest_flush(out, dsum, dxor);
 }
 
 // Classify + export every set (after the persistent kernel): one block per
@@ -359,11 +287,12 @@ __device__ void item_export(const BatchHeader *hdr, const BatchDesc &d, int64_t 
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_export_batch(const BatchHeader *hdr, const BatchDesc *sets,
                                                          const int64_t *export_start) {
+    __shared__ uint16_t s_rank[kBlock / 64][kExportChunk];
     const int S = hdr->n_sets;
     const int64_t total = export_start[S];
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int s = __builtin_amdgcn_readfirstlane(find_range(export_start, S, t));
-        item_export<KW>(hdr, sets[s], t - export_start[s], hdr->slots_per_item);
+        item_export<KW>(hdr, sets[s], t - export_start[s], hdr->slots_per_item, s_rank[threadIdx.x >> 6]);
     }
 }
 
@@ -502,6 +431,13 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
             d.lext = x.list.ext;
             d.lcap = x.list.capacity;
             d.lcount = reinterpret_cast<unsigned long long *>(x.list.count);
+            if (x.list.present) {
+                if (!pow2(x.list.present_words) || x.list.present_hash < 1 || x.list.present_hash > 8)
+                    return fail(HM_EINVAL, "batch set %d: bad presence filter", i);
+                d.present = x.list.present;
+                d.present_words = x.list.present_words;
+                d.present_hash = x.list.present_hash;
+            }
         }
         d.out = o;
         const bool windows = x.n_reads > 0 && x.read_len >= p->k;
@@ -568,6 +504,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
         reg[nr++] = Region{d.slots, d.capacity * HM_SLOT_BYTES};
         reg[nr++] = Region{d.bloom, bypass ? 0ull : (d.bloom_mask + 1) * 8};
         reg[nr++] = Region{d.lcount, bypass ? 0ull : 8ull};
+        reg[nr++] = Region{d.present, (bypass || !d.present) ? 0ull : d.present_words * 8};
         reg[nr++] = Region{d.out.n_out, 8};
         reg[nr++] = Region{d.out.digest, d.out.digest ? 16ull : 0ull};
         reg[nr++] = Region{d.status, 4};

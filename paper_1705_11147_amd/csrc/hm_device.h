@@ -201,6 +201,7 @@ struct Probe {
     uint64_t at;
     uint32_t used;
     uint64_t narrow;  // the slot's narrow counter word as loaded with the key (a hint for the CAS)
+    bool inserted;    // this call claimed the slot for the key
 };
 
 // Locate (A, B) by linear probing from `start` (the first `used0` slots of
@@ -231,25 +232,25 @@ __device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_
         uint64_t a = (uint64_t)v.x | ((uint64_t)v.y << 32);
         const uint64_t nw = (uint64_t)v.z | ((uint64_t)v.w << 32);
         if (a == 0) {
-            if (!insert) return Probe{-1, i, probes, 0};
+            if (!insert) return Probe{-1, i, probes, 0, false};
             uint64_t expected = 0;
             if (__hip_atomic_compare_exchange_strong(&s->a, &expected, A, RLX, RLX, AGT)) {
                 if (KW == 2) __hip_atomic_store(&s->b, B, RLX, AGT);
-                return Probe{(int64_t)i, i, probes, 0};
+                return Probe{(int64_t)i, i, probes, 0, true};
             }
             a = expected;
         }
         if (a == A) {
-            if (KW == 1) return Probe{(int64_t)i, i, probes, nw};
+            if (KW == 1) return Probe{(int64_t)i, i, probes, nw, false};
             uint64_t b = s->b;
             while (b == 0) {  // claimed for a key with the same word a, word b not visible yet
-                if (++spins > kMaxSpin) return Probe{-2, i, probes, 0};
+                if (++spins > kMaxSpin) return Probe{-2, i, probes, 0, false};
                 b = __hip_atomic_load(&s->b, RLX, AGT);
             }
-            if (b == B) return Probe{(int64_t)i, i, probes, nw};
+            if (b == B) return Probe{(int64_t)i, i, probes, nw, false};
         }
         i = (i + 1) & cmask;
-        if (++probes >= max_probe) return Probe{-2, i, probes, 0};
+        if (++probes >= max_probe) return Probe{-2, i, probes, 0, false};
     }
 }
 
@@ -325,7 +326,20 @@ struct PassArgs {
     uint8_t *lext;
     uint64_t lcap;
     unsigned long long *lcount;
+    // presence filter of the keys pass 1 inserted (optional)
+    uint64_t *present;
+    uint64_t present_mask;
+    uint32_t present_hash;
 };
+
+// Word index and bit mask of a key in the presence filter (bits independent
+// of the table slot and of the Bloom word).
+__device__ __forceinline__ void present_bits(uint64_t h, uint64_t pmask, uint32_t nh, uint64_t &w, uint64_t &m) {
+    const uint64_t g = fmix64(h ^ 0xC2B2AE3D27D4EB4Full);
+    w = (g >> 40) & pmask;
+    m = 0;
+    for (uint32_t j = 0; j < nh; ++j) m |= 1ull << ((g >> (6 * j)) & 63);
+}
 
 // Per-lane event counts of a counting pass (see HM_STAT_* in hm_kmer.h).
 struct Stats {
@@ -384,6 +398,11 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
         }
         st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;
         st.v[HM_STAT_PROBES] += pr.used + 1;
+        if (pr.inserted && a.present) {
+            uint64_t pw, pm;
+            present_bits(h, a.present_mask, a.present_hash, pw, pm);
+            __hip_atomic_fetch_or(a.present + pw, pm, RLX, AGT);
+        }
         if (pr.slot >= 0) {
             const uint32_t c = count_occurrence<CHECKED>(a.slots + pr.slot, o.left, o.right, a.status, pr.narrow);
             st.v[HM_STAT_CAS] += c & 15;
@@ -421,6 +440,25 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
             }
         }
     }
+}
+
+// Pass-2 body for one first-occurrence entry: skip it when the presence filter
+// shows its k-mer was never inserted, else look it up and count it if found.
+template <int KW, bool CHECKED>
+__device__ __forceinline__ void pass2_entry(const PassArgs &a, uint64_t hi, uint64_t lo, uint8_t e, Stats &st) {
+    st.v[HM_STAT_P2_ENTRIES] += 1;
+    const uint64_t h = key_hash(hi, lo, a.seed);
+    if (a.present) {
+        uint64_t pw, pm;
+        present_bits(h, a.present_mask, a.present_hash, pw, pm);
+        if ((a.present[pw] & pm) != pm) return;  // never inserted: not in the table
+    }
+    uint64_t A, B;
+    slot_words<KW>(hi, lo, A, B);
+    const Probe pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, false);
+    st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
+    if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, e & 15, e >> 4, a.status, pr.narrow);
+    else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
 }
 
 // Mark the unused tail of the wave's current chunk as holes.
@@ -473,6 +511,123 @@ __device__ __forceinline__ void pack16(uint4 sa, uint4 sq, int nvalid, int qual_
     }
 }
 
+
+constexpr int kExportPerLane = 8;  // slots per lane per wave iteration: 512 per wave
+constexpr int kExportChunk = 64 * kExportPerLane;
+
+// Export one chunk of 512 consecutive slots [first, first+512) ∩ [0, cap) with
+// one wave: the slots are tested 8 per lane (coalesced), the taken ones
+// ranked with a wave prefix sum and their offsets staged in `rank_of` (LDS,
+// 512 entries per wave); one atomic add reserves the wave's output range and
+// lane r writes record base+r, so every record store is coalesced.  With
+// HM_EXPORT_CLASSIFY the depth filter and classes come from the counters
+// (out.min_depth, out.ext_min); otherwise from the table's classify word.
+template <int KW>
+__device__ __forceinline__ void export_chunk(const Slot *slots, uint64_t first, uint64_t cap, uint32_t flags,
+                                             const hm_export_t &out, uint32_t *status, uint16_t *rank_of,
+                                             uint64_t &dsum, uint64_t &dxor) {
+    const uint32_t lane = lane_id();
+    const bool inline_cls = (flags & HM_EXPORT_CLASSIFY) != 0;
+    uint32_t take_bits = 0;
+#pragma unroll 1
+    for (int j = 0; j < kExportPerLane; ++j) {
+        const uint64_t i = first + (uint64_t)j * 64 + lane;
+        if (i < cap) {
+            const Slot *sl = slots + i;
+            if (sl->a != 0) {
+                bool kept;
+                uint32_t cl, cr;
+                if (inline_cls) {
+                    uint32_t tl[4], tr[4];
+                    const uint64_t cnt = slot_counts(sl, tl, tr);
+                    if (cnt > 0xFFFFFFFFull) atomicOr(status, HM_ST_OVERFLOW);
+                    kept = cnt >= out.min_depth;
+                    cl = side_class(tl, out.ext_min);
+                    cr = side_class(tr, out.ext_min);
+                } else {
+                    const uint32_t c = sl->cls;
+                    kept = (c >> 16) & 1;
+                    cl = c & 0xFF;
+                    cr = (c >> 8) & 0xFF;
+                    if ((c >> 17) & 1) atomicOr(status, HM_ST_OVERFLOW);
+                }
+                bool take = (flags & HM_EXPORT_ALL) ? true : kept;
+                if (flags & HM_EXPORT_UU_ONLY) take = take && kept && cl < 4 && cr < 4;
+                take_bits |= (take ? 1u : 0u) << j;
+            }
+        }
+    }
+    const uint32_t cnt = (uint32_t)__popc(take_bits);
+    uint32_t incl = cnt;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d);
+        if ((int)lane >= d) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    if (total == 0) return;
+    uint32_t r = incl - cnt;
+    for (int j = 0; j < kExportPerLane; ++j)
+        if ((take_bits >> j) & 1) rank_of[r++] = (uint16_t)(j * 64 + lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out), (unsigned long long)total);
+    base = __shfl(base, 0);
+    for (uint32_t q = lane; q < total; q += 64) {
+        const Slot *sl = slots + first + rank_of[q];
+        uint64_t hi = 0, lo;
+        if (KW == 1) {
+            lo = sl->a & kLow63;
+        } else {
+            const uint64_t A = sl->a & kLow63, B = sl->b & kLow63;
+            lo = B | (A << 63);
+            hi = A >> 1;
+        }
+        uint32_t tl[4], tr[4];
+        const uint32_t count = (uint32_t)slot_counts(sl, tl, tr);
+        uint32_t cl, cr;
+        if (inline_cls) {
+            cl = side_class(tl, out.ext_min);
+            cr = side_class(tr, out.ext_min);
+        } else {
+            const uint32_t c = sl->cls;
+            cl = c & 0xFF;
+            cr = (c >> 8) & 0xFF;
+        }
+        const uint64_t idx = base + q;
+        if (idx < out.capacity) {
+            out.key_hi[idx] = hi;
+            out.key_lo[idx] = lo;
+            out.count[idx] = count;
+            *reinterpret_cast<uint4 *>(out.tl + 4 * idx) = make_uint4(tl[0], tl[1], tl[2], tl[3]);
+            *reinterpret_cast<uint4 *>(out.tr + 4 * idx) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+            out.cls_l[idx] = (uint8_t)cl;
+            out.cls_r[idx] = (uint8_t)cr;
+        } else {
+            atomicOr(status, HM_ST_OUTPUT_FULL);
+        }
+        if (out.digest) {
+            const uint64_t x = record_hash(hi, lo, count, tl, tr, cl, cr);
+            dsum += x;
+            dxor ^= x;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // rank_of is rewritten by the next chunk
+}
+
+// Add a wave's digest terms to the export digest.
+__device__ __forceinline__ void digest_flush(const hm_export_t &out, uint64_t dsum, uint64_t dxor) {
+    if (!out.digest) return;
+    for (int off = 32; off > 0; off >>= 1) {
+        dsum += __shfl_xor(dsum, off);
+        dxor ^= __shfl_xor(dxor, off);
+    }
+    if (lane_id() == 0 && (dsum | dxor)) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(out.digest), (unsigned long long)dsum);
+        atomicXor(reinterpret_cast<unsigned long long *>(out.digest + 1), (unsigned long long)dxor);
+    }
+}
 
 // ------------------------------------------------------------------ host helpers (defined in hm_kmer.hip)
 

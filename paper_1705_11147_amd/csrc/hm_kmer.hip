@@ -175,16 +175,9 @@ __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
     for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock; i0 < n; i0 += stride) {
         const uint64_t i = i0 + threadIdx.x;
         if (i >= n) continue;
-        const uint64_t hi = a.lkeys[2 * i], lo = a.lkeys[2 * i + 1];
         const uint8_t e = a.lext[i];
         if (e == kHole) continue;
-        uint64_t A, B;
-        slot_words<KW>(hi, lo, A, B);
-        const Probe pr = table_find<KW>(a.slots, a.cmask, key_hash(hi, lo, a.seed), A, B, a.max_probe, false);
-        st.v[HM_STAT_P2_ENTRIES] += 1;
-        st.v[HM_STAT_P2_FOUND] += pr.slot >= 0 ? 1u : 0u;
-        if (pr.slot >= 0) count_occurrence<CHECKED>(a.slots + pr.slot, e & 15, e >> 4, a.status, pr.narrow);
-        else if (pr.slot == -2) atomicOr(a.status, HM_ST_TABLE_FULL);
+        pass2_entry<KW, CHECKED>(a, a.lkeys[2 * i], a.lkeys[2 * i + 1], e, st);
     }
     stats_flush(a.stats, st);
 }
@@ -201,97 +194,16 @@ __global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, 
     }
 }
 
-constexpr int kExportPerLane = 8;
-
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
                                                    uint32_t *status) {
+    __shared__ uint16_t s_rank[kBlock / 64][kExportChunk];
     uint64_t dsum = 0, dxor = 0;
-    const uint32_t lane = lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
-    const uint64_t per_iter = 64 * kExportPerLane;  // slots per wave iteration
-    const uint64_t iters = (cap + per_iter * n_waves - 1) / (per_iter * n_waves);
-    for (uint64_t it = 0; it < iters; ++it) {
-        const uint64_t first = (it * n_waves + wave) * per_iter;
-        // pass A: which of this lane's slots are taken (slots first + j*64 + lane, coalesced per j)
-        uint32_t take_bits = 0;
-#pragma unroll
-        for (int j = 0; j < kExportPerLane; ++j) {
-            const uint64_t i = first + (uint64_t)j * 64 + lane;
-            if (i < cap) {
-                const Slot *sl = slots + i;
-                if (sl->a != 0) {
-                    const uint32_t c = sl->cls;
-                    const bool kept = (c >> 16) & 1;
-                    bool take = (flags & HM_EXPORT_ALL) ? true : kept;
-                    if (flags & HM_EXPORT_UU_ONLY) take = take && kept && (c & 0xFF) < 4 && ((c >> 8) & 0xFF) < 4;
-                    if ((c >> 17) & 1) atomicOr(status, HM_ST_OVERFLOW);
-                    take_bits |= (take ? 1u : 0u) << j;
-                }
-            }
-        }
-        // wave-wide exclusive prefix of the per-lane counts, one atomic per wave
-        const uint32_t cnt = (uint32_t)__popc(take_bits);
-        uint32_t incl = cnt;
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d);
-            if ((int)lane >= d) incl += y;
-        }
-        const uint32_t total = __shfl(incl, 63);
-        if (total == 0) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out), (unsigned long long)total);
-        base = __shfl(base, 0);
-        uint64_t idx = base + (incl - cnt);
-        // pass B: write this lane's records
-#pragma unroll
-        for (int j = 0; j < kExportPerLane; ++j) {
-            if (!((take_bits >> j) & 1)) continue;
-            const Slot *sl = slots + first + (uint64_t)j * 64 + lane;
-            uint64_t hi = 0, lo;
-            if (KW == 1) {
-                lo = sl->a & kLow63;
-            } else {
-                const uint64_t A = sl->a & kLow63, B = sl->b & kLow63;
-                lo = B | (A << 63);
-                hi = A >> 1;
-            }
-            uint32_t tl[4], tr[4];
-            const uint32_t count = (uint32_t)slot_counts(sl, tl, tr);
-            const uint32_t c = sl->cls;
-            const uint32_t cl = c & 0xFF, cr = (c >> 8) & 0xFF;
-            if (idx < out.capacity) {
-                out.key_hi[idx] = hi;
-                out.key_lo[idx] = lo;
-                out.count[idx] = count;
-                for (int b = 0; b < 4; ++b) {
-                    out.tl[4 * idx + b] = tl[b];
-                    out.tr[4 * idx + b] = tr[b];
-                }
-                out.cls_l[idx] = (uint8_t)cl;
-                out.cls_r[idx] = (uint8_t)cr;
-            } else {
-                atomicOr(status, HM_ST_OUTPUT_FULL);
-            }
-            if (out.digest) {
-                const uint64_t x = record_hash(hi, lo, count, tl, tr, cl, cr);
-                dsum += x;
-                dxor ^= x;
-            }
-            ++idx;
-        }
-    }
-    if (out.digest) {
-        for (int off = 32; off > 0; off >>= 1) {
-            dsum += __shfl_xor(dsum, off);
-            dxor ^= __shfl_xor(dxor, off);
-        }
-        if (lane == 0 && (dsum | dxor)) {
-            atomicAdd(reinterpret_cast<unsigned long long *>(out.digest), (unsigned long long)dsum);
-            atomicXor(reinterpret_cast<unsigned long long *>(out.digest + 1), (unsigned long long)dxor);
-        }
-    }
+    for (uint64_t first = wave * kExportChunk; first < cap; first += n_waves * kExportChunk)
+        export_chunk<KW>(slots, first, cap, flags, out, status, s_rank[threadIdx.x >> 6], dsum, dxor);
+    digest_flush(out, dsum, dxor);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases,
@@ -410,6 +322,11 @@ int hm_bloom_init(hm_bloom_t *b, hipStream_t s) {
 
 int hm_list_init(hm_list_t *l, hipStream_t s) {
     if (!l || !l->count) return fail(HM_EINVAL, "list or its counter is NULL");
+    if (l->present) {
+        if (!pow2(l->present_words)) return fail(HM_EINVAL, "presence filter words must be a power of two");
+        int rc = fill<uint64_t>(l->present, l->present_words, 0ull, s);
+        if (rc) return rc;
+    }
     return fill<uint64_t>(l->count, 1, 0ull, s);
 }
 
@@ -483,6 +400,13 @@ static int make_args(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, h
         a.lext = l->ext;
         a.lcap = l->capacity;
         a.lcount = reinterpret_cast<unsigned long long *>(l->count);
+        if (l->present) {
+            if (!pow2(l->present_words) || l->present_hash < 1 || l->present_hash > 8)
+                return fail(HM_EINVAL, "presence filter: power-of-two words and 1..8 bits per key");
+            a.present = l->present;
+            a.present_mask = l->present_words - 1;
+            a.present_hash = l->present_hash;
+        }
     }
     a.slots = reinterpret_cast<Slot *>(t->slots);
     a.cmask = t->capacity - 1;
@@ -561,7 +485,11 @@ int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipSt
     if (out->capacity > 0 && (!out->key_hi || !out->key_lo || !out->count || !out->tl || !out->tr || !out->cls_l ||
                               !out->cls_r))
         return fail(HM_EINVAL, "export: record arrays are NULL");
-    if (flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL)) return fail(HM_EINVAL, "export: unknown flags");
+    if (flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL | HM_EXPORT_CLASSIFY)) return fail(HM_EINVAL, "export: unknown flags");
+    if ((flags & HM_EXPORT_CLASSIFY) && (out->min_depth < 1 || out->ext_min < 1))
+        return fail(HM_EINVAL, "export: HM_EXPORT_CLASSIFY needs min_depth and ext_min >= 1");
+    if (out->capacity > 0 && (((uintptr_t)out->tl | (uintptr_t)out->tr) & 15))
+        return fail(HM_EINVAL, "export: tl and tr must be 16-byte aligned");
     if (t->k < 1 || t->k > 63) return fail(HM_EINVAL, "table k must be 1..63");
     rc = fill<uint64_t>(out->n_out, 1, 0ull, s);
     if (rc) return rc;

@@ -113,10 +113,10 @@ class Records:
         self.n_out = torch.zeros(1, dtype=torch.int64, device=device)
         self.digest = torch.zeros(2, dtype=torch.int64, device=device)
 
-    def struct(self, digest: bool = True) -> abi.Export:
+    def struct(self, digest: bool = True, min_depth: int = 0, ext_min: int = 0) -> abi.Export:
         return abi.Export(self.key_hi.data_ptr(), self.key_lo.data_ptr(), self.count.data_ptr(), self.tl.data_ptr(),
                           self.tr.data_ptr(), self.cls_l.data_ptr(), self.cls_r.data_ptr(), self.capacity,
-                          self.n_out.data_ptr(), self.digest.data_ptr() if digest else None)
+                          self.n_out.data_ptr(), self.digest.data_ptr() if digest else None, min_depth, ext_min)
 
     def to_numpy(self, n: int | None = None, sort: bool = True) -> dict:
         """Copy the first n records to the host (sorted by key when `sort`)."""
@@ -152,7 +152,7 @@ class KmerCounter:
 
     def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,
                  min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
-                 seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda"):
+                 seed: int = DEFAULT_SEED, max_probe: int = 0, present_filter: bool = True, device="cuda"):
         self.device = torch.device(device)
         self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner, flags,
                                  seed & (2 ** 64 - 1))
@@ -172,15 +172,20 @@ class KmerCounter:
         self.list_keys = torch.empty(2 * lc, dtype=torch.int64, device=self.device)
         self.list_ext = torch.empty(lc, dtype=torch.uint8, device=self.device)
         self.list_count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        # presence filter of inserted keys: about 8 bits per key at the table's design load
+        self.present_words = 0 if (self.bypass or not present_filter) else next_pow2(max(64, self.capacity // 16))
+        self.present_buf = torch.empty(max(self.present_words, 1), dtype=torch.int64, device=self.device)
         self.list = abi.List(self.list_keys.data_ptr(), self.list_ext.data_ptr(), self.list_capacity,
-                             self.list_count.data_ptr())
+                             self.list_count.data_ptr(), self.present_buf.data_ptr() if self.present_words else None,
+                             self.present_words, 3)
 
     @property
     def k(self) -> int:
         return self.params.k
 
     def bytes(self) -> int:
-        return (self.slots.numel() + self.bloom_buf.numel() + self.list_keys.numel()) * 8 + self.list_ext.numel()
+        return (self.slots.numel() + self.bloom_buf.numel() + self.list_keys.numel() + self.present_buf.numel()) * 8 \
+            + self.list_ext.numel()
 
     # ---- the steps, each one C-ABI call ----
     def reset(self, stream=None):
@@ -204,7 +209,9 @@ class KmerCounter:
         abi.call("hm_classify_ext", ctypes.byref(self.params), ctypes.byref(self.table), _stream(stream))
 
     def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
-        e = out.struct(digest)
+        """hm_export_table; with abi.HM_EXPORT_CLASSIFY in flags the export
+        classifies from the counters (no hm_classify_ext needed before)."""
+        e = out.struct(digest, self.params.min_depth, self.params.ext_min)
         abi.call("hm_export_table", ctypes.byref(self.table), flags, ctypes.byref(e), _stream(stream))
 
     def stats(self) -> dict:
@@ -215,14 +222,18 @@ class KmerCounter:
         """Synchronize and return the table's status code (HM_OK or a negative code)."""
         return abi.lib().hm_status(ctypes.byref(self.table), _stream(stream))
 
-    def run(self, batches, out: Records, flags: int = 0, stream=None, digest: bool = True):
-        """reset -> pass 1 over every packed batch -> pass 2 -> classify -> export (all async)."""
+    def run(self, batches, out: Records, flags: int = 0, stream=None, digest: bool = True, fused: bool = False):
+        """reset -> pass 1 over every packed batch -> pass 2 -> classify -> export
+        (all async).  fused: classify inside the export sweep instead."""
         self.reset(stream)
         for p in batches:
             self.insert(p, stream)
         self.count(stream)
-        self.classify(stream)
-        self.export(out, flags, stream, digest)
+        if fused:
+            self.export(out, flags | abi.HM_EXPORT_CLASSIFY, stream, digest)
+        else:
+            self.classify(stream)
+            self.export(out, flags, stream, digest)
 
 
 def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = None,
@@ -230,7 +241,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             ext_min: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
             bypass: bool = False, checked: bool = False, export_flags: int = 0, capacity: int | None = None,
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
-            seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4) -> dict:
+            seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
+            present_filter: bool = True) -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
     Sizes default to safe bounds derived from the number of windows; on a
@@ -249,9 +261,10 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     bw = bloom_words or next_pow2(max(64, P * 10 // 64))
     for _ in range(retries + 1):
         kc = KmerCounter(k, cap, bw, lcap, n_hash=n_hash, min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
-                         owner=owner, flags=flags, seed=seed, max_probe=max_probe, device=dev)
+                         owner=owner, flags=flags, seed=seed, max_probe=max_probe, present_filter=present_filter,
+                         device=dev)
         out = Records(kc.capacity, device=dev)
-        kc.run([packed], out, flags=export_flags)
+        kc.run([packed], out, flags=export_flags, fused=fused)
         rc = kc.status()
         if rc == abi.HM_OK:
             res = out.to_numpy()

@@ -270,3 +270,19 @@ def test_batches_into_one_table():
     kc.run(packs, out)
     assert kc.status() == abi.HM_OK
     assert_tables_equal(out.to_numpy(), exp, "batched pass 1")
+
+
+@pytest.mark.parametrize("k", [21, 51])
+def test_fused_classify_export_and_presence_filter(k):
+    """Classification fused into the export sweep, and the pass-2 presence filter switched off,
+    give the same table as the separate classify call and the oracle."""
+    ascii, qual, off = random_read_set(60 + k, 3000, 100, 150, genome_len=40000)
+    exp = oracle.run(ascii, qual, off, k, n_threads=4)
+    for fused in (False, True):
+        for pf in (True, False):
+            got = kmer.analyze(ascii, qual, k, read_off=off, fused=fused, present_filter=pf)
+            assert_tables_equal(got, exp, "fused=%s filter=%s" % (fused, pf))
+    for flags in (abi.HM_EXPORT_UU_ONLY, abi.HM_EXPORT_ALL):
+        a = kmer.analyze(ascii, qual, k, read_off=off, fused=True, export_flags=flags)
+        b = kmer.analyze(ascii, qual, k, read_off=off, fused=False, export_flags=flags)
+        assert_tables_equal(a, b, "flags %d" % flags)
