@@ -117,7 +117,7 @@ def run_batched(args, dev, log):
             "tuning": dict(zip(["blocks_per_cu", "tile_bases", "list_per_item", "slots_per_item", "table_load",
                                 "bloom_bits", "n_hash", "set_major"], best.key())),
             "tune_s": round(tune_s, 1), "tune_trials": len(report.get("trials", [])),
-            "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 6 plain calls"}
+            "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 5 plain calls"}
 
 
 def run_serving(args, dev, log):

@@ -129,12 +129,13 @@ class Batch:
             self.capture()
         self.graph.replay()
 
-    # ---- plain per-set form on the same buffers
+    # ---- plain per-set form on the same buffers (the same kernels' work as five ABI calls per set:
+    # pack, init, pass 1, pass 2, export with inline classification)
     def run_plain(self, stream=None):
         for sb in self.sets:
             kmer.pack_reads(sb.spec.ascii, sb.spec.qual, read_len=sb.spec.read_len, qcut=self.qcut,
                             qual_offset=self.qual_offset, stream=stream, out=sb.packed())
-            sb.kc.run([sb.packed()], sb.out, flags=self.export_flags, stream=stream)
+            sb.kc.run([sb.packed()], sb.out, flags=self.export_flags, stream=stream, fused=True)
 
     # ---- results
     def status(self) -> list[int]:

@@ -246,7 +246,7 @@ __device__ void item_pass1(const PassArgs &a, int32_t rpt, int64_t j, uint64_t *
         pass1_occ<KW, CHECKED, kBatchChunk>(a, act, o, cur, st);
     }
     list_close<kBatchChunk>(a, cur);
-    stats_flush(a.stats, st);
+    (void)st;  // per-item event counters are not collected in the batched form
 }
 
 // pass-2 item: first-occurrence entries [j*E, (j+1)*E) of one set
@@ -263,7 +263,7 @@ __device__ void item_pass2(const PassArgs &a, int64_t j, int64_t E) {
         if (x == kHole) continue;
         pass2_entry<KW, CHECKED>(a, a.lkeys[2 * i], a.lkeys[2 * i + 1], x, st);
     }
-    stats_flush(a.stats, st);
+    (void)st;  // per-item event counters are not collected in the batched form
 }
 
 // classify + export item: slots [j*SI, (j+1)*SI) of one set, 512-slot chunks
@@ -296,8 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_export_batch(const BatchHeader *hdr,
     }
 }
 
+// 6 waves per SIMD: the budget that holds every pass-1/pass-2 value in
+// registers without spilling.
 template <int KW, bool CHECKED>
-__global__ __launch_bounds__(kBlock) void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
                                                   const int32_t *group, uint32_t *done) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
