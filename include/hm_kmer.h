@@ -266,8 +266,9 @@ typedef struct {
     int32_t tile_bases;     /* bases of reads per pass-1 work item, 1024..16384 */
     int32_t list_per_item;  /* first-occurrence entries per pass-2 work item, >= 256 */
     int32_t slots_per_item; /* table slots per classify+export work item, multiple of 2048 */
-    int32_t set_major;      /* 1: tickets run set by set (a set's pass 2 right after its pass 1, so few
-                               tables are live at once and stay cache-resident); 0: all pass-1 items first */
+    int32_t set_major;      /* 0: all pass-1 items first, then all pass-2 items; n >= 1: set by set, each
+                               set's pass 2 after the pass 1 of the (n-1)-th following set (few tables live
+                               at once, and pass-2 items rarely wait for their set's pass-1 tail) */
 } hm_batch_tuning_t;
 
 /* Host-side plan returned by hm_batch_prepare and consumed by hm_batch_launch. */
@@ -288,7 +289,9 @@ size_t hm_batch_work_bytes(int32_t n_sets);
 /* Validate the sets, lay out their descriptors and work items (larger sets
  * first; ordered set by set or phase by phase as tuning.set_major says; a
  * set's pass-2 items always come after its pass-1 items; export ranges
- * separately)
+ * separately).  A wave's first-occurrence list chunk persists across work
+ * items of one set, so each set's list needs CUs x blocks_per_cu x 4 x 255
+ * entries of slack beyond its distinct k-mers.
  * and copy them into `work` (device, >= hm_batch_work_bytes(n_sets)).
  * Synchronizes `stream`; not capturable.  Sections as for the plain path. */
 int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params_t *p, uint8_t qual_offset,

@@ -26,7 +26,7 @@ class Tuning:
     table_load: float = 0.45     # sizing: expected kept k-mers / capacity
     bloom_bits: float = 12.0     # sizing: Bloom bits per expected distinct k-mer
     n_hash: int = 4
-    set_major: int = 1           # run the sets one after another (cache-resident tables)
+    set_major: int = 2           # set by set, pass 2 lagging one set (cache-resident tables, few waits)
 
     def struct(self) -> abi.BatchTuning:
         return abi.BatchTuning(self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item,
@@ -64,7 +64,9 @@ class _SetBuffers:
         keys = spec.distinct_est if bypass else spec.kept_est  # bypass keeps every distinct k-mer
         cap = next_pow2(max(1024, int(keys / tuning.table_load)))
         bw = next_pow2(max(64, int(spec.distinct_est * tuning.bloom_bits / 64)))
-        lcap = int(spec.distinct_est * 1.2) + 4096 * 64  # + room for per-wave chunk tails
+        cus = torch.cuda.get_device_properties(device).multi_processor_count
+        # + one partly used 256-entry chunk per wave of either form
+        lcap = int(spec.distinct_est * 1.2) + cus * max(8, tuning.blocks_per_cu) * 4 * 255
         self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, device=device, **params)
         self.out = Records(int(min(cap, keys * 1.3 + 1024)), device=device)
 

@@ -31,7 +31,6 @@ namespace {
 
 using namespace hm;
 
-constexpr uint32_t kBatchChunk = 64;  // first-occurrence list chunk per wave and item
 constexpr int kPhases = 2;  // persistent kernel: pass 1, pass 2
 constexpr uint64_t kWaitTicks = 100ull * 1000 * 1000 * 20;  // 20 s at the 100 MHz wall clock
 
@@ -63,7 +62,9 @@ struct BatchDesc {
 
 struct Region {
     void *p;
-    uint64_t bytes;  // multiple of 4
+    uint64_t bytes;    // multiple of 4
+    uint32_t pattern;  // 32-bit fill value
+    uint32_t pad;
 };
 
 struct BatchHeader {
@@ -86,7 +87,7 @@ struct Layout {
     size_t desc, item_start, group, pack_start, export_start, regions, done, total;
 };
 
-constexpr int kRegionsPerSet = 8;
+constexpr int kRegionsPerSet = 9;
 
 Layout layout(int32_t S) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -104,20 +105,22 @@ Layout layout(int32_t S) {
 
 // ------------------------------------------------------------------ kernels
 
-// Clear region blockIdx.y (16-byte stores for the aligned body, 4-byte tail).
+// Fill region blockIdx.y with its pattern (16-byte stores for the aligned
+// body, 4-byte tail).
 __global__ __launch_bounds__(kBlock) void k_fill_regions(const Region *regions) {
     const Region r = regions[blockIdx.y];
     if (!r.p || r.bytes == 0) return;
     uint8_t *p = reinterpret_cast<uint8_t *>(r.p);
+    const uint32_t v = r.pattern;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     if ((((uintptr_t)p) & 15) == 0) {
         const uint64_t n16 = r.bytes / 16;
         uint4 *q = reinterpret_cast<uint4 *>(p);
-        for (uint64_t i = tid; i < n16; i += stride) q[i] = make_uint4(0, 0, 0, 0);
-        for (uint64_t i = n16 * 4 + tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = 0;
+        for (uint64_t i = tid; i < n16; i += stride) q[i] = make_uint4(v, v, v, v);
+        for (uint64_t i = n16 * 4 + tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = v;
     } else {
-        for (uint64_t i = tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = 0;
+        for (uint64_t i = tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = v;
     }
 }
 
@@ -212,9 +215,12 @@ __device__ __forceinline__ PassArgs pass_args(const BatchHeader *hdr, const Batc
 }
 
 // pass-1 item: reads [j*rpt, (j+1)*rpt) of one set, staged in LDS
+// The wave's list cursor `cur` persists across the items of one set: entries
+// of a chunk it never fills keep the hole mark the launch wrote into the
+// whole extension array, so nothing has to be closed at item end.
 template <int KW, bool CHECKED>
 __device__ void item_pass1(const PassArgs &a, int32_t rpt, int64_t j, uint64_t *s_b2, uint64_t *s_nm,
-                           uint64_t *s_hq) {
+                           uint64_t *s_hq, ListCursor &cur) {
     const int L = a.read_len, k = a.k, W = L - k + 1;
     const int64_t r0 = j * rpt;
     const int64_t r1 = min(r0 + (int64_t)rpt, a.n_reads);
@@ -230,7 +236,6 @@ __device__ void item_pass1(const PassArgs &a, int32_t rpt, int64_t j, uint64_t *
     __syncthreads();
     const Words w{s_b2, s_nm, s_hq};
     const int total = (int)(r1 - r0) * W;
-    ListCursor cur{0, kBatchChunk};
     Stats st = {};
     for (int f0 = 0; f0 < total; f0 += kBlock) {
         if (aborted(a.status)) break;
@@ -243,9 +248,8 @@ __device__ void item_pass1(const PassArgs &a, int32_t rpt, int64_t j, uint64_t *
             const int64_t rb = (r0 + r) * L - org;
             act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
         }
-        pass1_occ<KW, CHECKED, kBatchChunk>(a, act, o, cur, st);
+        pass1_occ<KW, CHECKED>(a, act, o, cur, st);
     }
-    list_close<kBatchChunk>(a, cur);
     (void)st;  // per-item event counters are not collected in the batched form
 }
 
@@ -308,6 +312,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
     __shared__ int s_ok;
     const int S = hdr->n_sets;
     const int64_t n_items = hdr->n_items;
+    ListCursor cur{0, kListChunk};
+    int cur_set = -1;
     while (true) {
         __syncthreads();  // previous item fully done (LDS, s_item)
         if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(&hdr->ticket, 1ull);
@@ -344,7 +350,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
             if (s_ok) item_pass2<KW, CHECKED>(pass_args(hdr, d), j, hdr->list_per_item);
         } else {
             const PassArgs a = pass_args(hdr, d);
-            item_pass1<KW, CHECKED>(a, d.rpt, j, s_b2, s_nm, s_hq);
+            if (s != cur_set) {  // new set: start a fresh chunk (the old one's tail stays marked as holes)
+                cur = ListCursor{0, kListChunk};
+                cur_set = s;
+            }
+            item_pass1<KW, CHECKED>(a, d.rpt, j, s_b2, s_nm, s_hq, cur);
         }
         // release: this item's writes before the completion count
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -377,7 +387,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     if (tu.list_per_item < 256) return fail(HM_EINVAL, "batch: list_per_item >= 256");
     if (tu.slots_per_item < 2048 || tu.slots_per_item % 2048) return fail(HM_EINVAL, "batch: slots_per_item % 2048");
     if (export_flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL)) return fail(HM_EINVAL, "batch: unknown export flags");
-    if (tu.set_major != 0 && tu.set_major != 1) return fail(HM_EINVAL, "batch: set_major must be 0 or 1");
+    if (tu.set_major < 0 || tu.set_major > 64) return fail(HM_EINVAL, "batch: set_major must be 0..64");
     const bool bypass = (p->flags & HM_BLOOM_BYPASS) || p->min_depth == 1;
 
     std::vector<BatchDesc> descs(n_sets);
@@ -472,17 +482,27 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     hdr.slots_per_item = tu.slots_per_item;
     hdr.seed = p->seed;
     int64_t *item_start = reinterpret_cast<int64_t *>(blob.data() + lay.item_start);
+    // ticket order: phase-major (set_major == 0), or set by set with each set's
+    // pass 2 placed after the pass 1 of the set_major-th following set, so a
+    // pass-2 item rarely has to wait for the tail of its set's pass 1
     int32_t *group = reinterpret_cast<int32_t *>(blob.data() + lay.group);
-    int64_t acc = 0;
-    int gi = 0;
-    for (int outer = 0; outer < (tu.set_major ? n_sets : kPhases); ++outer)
-        for (int inner = 0; inner < (tu.set_major ? kPhases : n_sets); ++inner) {
-            const int ph = tu.set_major ? inner : outer, i = tu.set_major ? outer : inner;
-            item_start[gi] = acc;
-            group[gi] = (ph << 24) | i;
-            acc += sorted[i].n_items[ph];
-            ++gi;
+    std::vector<int32_t> seq;
+    if (tu.set_major == 0) {
+        for (int ph = 0; ph < kPhases; ++ph)
+            for (int32_t i = 0; i < n_sets; ++i) seq.push_back((ph << 24) | i);
+    } else {
+        const int lag = tu.set_major - 1;
+        for (int32_t i = 0; i < n_sets + lag; ++i) {
+            if (i < n_sets) seq.push_back(i);                         // pass 1 of set i
+            if (i - lag >= 0) seq.push_back((1 << 24) | (i - lag));  // pass 2 of set i - lag
         }
+    }
+    int64_t acc = 0;
+    for (size_t gi = 0; gi < seq.size(); ++gi) {
+        item_start[gi] = acc;
+        group[gi] = seq[gi];
+        acc += sorted[seq[gi] & 0xFFFFFF].n_items[seq[gi] >> 24];
+    }
     item_start[kPhases * n_sets] = acc;
     hdr.n_items = acc;
     int64_t *pack_start = reinterpret_cast<int64_t *>(blob.data() + lay.pack_start);
@@ -503,17 +523,18 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     int64_t nr = 0;
     for (int32_t i = 0; i < n_sets; ++i) {
         const BatchDesc &d = sorted[i];
-        reg[nr++] = Region{d.slots, d.capacity * HM_SLOT_BYTES};
-        reg[nr++] = Region{d.bloom, bypass ? 0ull : (d.bloom_mask + 1) * 8};
-        reg[nr++] = Region{d.lcount, bypass ? 0ull : 8ull};
-        reg[nr++] = Region{d.present, (bypass || !d.present) ? 0ull : d.present_words * 8};
-        reg[nr++] = Region{d.out.n_out, 8};
-        reg[nr++] = Region{d.out.digest, d.out.digest ? 16ull : 0ull};
-        reg[nr++] = Region{d.status, 4};
-        reg[nr++] = Region{d.stats, d.stats ? 8ull * HM_N_STATS : 0ull};
+        reg[nr++] = Region{d.slots, d.capacity * HM_SLOT_BYTES, 0u, 0u};
+        reg[nr++] = Region{d.bloom, bypass ? 0ull : (d.bloom_mask + 1) * 8, 0u, 0u};
+        reg[nr++] = Region{d.lcount, bypass ? 0ull : 8ull, 0u, 0u};
+        reg[nr++] = Region{d.lext, bypass ? 0ull : (d.lcap + 3) / 4 * 4, 0xFFFFFFFFu, 0u};  // all holes
+        reg[nr++] = Region{d.present, (bypass || !d.present) ? 0ull : d.present_words * 8, 0u, 0u};
+        reg[nr++] = Region{d.out.n_out, 8, 0u, 0u};
+        reg[nr++] = Region{d.out.digest, d.out.digest ? 16ull : 0ull, 0u, 0u};
+        reg[nr++] = Region{d.status, 4, 0u, 0u};
+        reg[nr++] = Region{d.stats, d.stats ? 8ull * HM_N_STATS : 0ull, 0u, 0u};
     }
     // the ticket (inside the header); the per-set phase counters are cleared by hm_batch_launch
-    reg[nr++] = Region{reinterpret_cast<uint8_t *>(work) + offsetof(BatchHeader, ticket), 16};
+    reg[nr++] = Region{reinterpret_cast<uint8_t *>(work) + offsetof(BatchHeader, ticket), 16, 0u, 0u};
     memcpy(blob.data(), &hdr, sizeof hdr);
     memcpy(blob.data() + lay.desc, sorted.data(), sizeof(BatchDesc) * n_sets);
     hipError_t e = hipMemcpyAsync(work, blob.data(), lay.total, hipMemcpyHostToDevice, stream);

@@ -22,7 +22,7 @@ import torch
 from .batch import Batch, SetSpec, Tuning
 
 LAUNCH_SPACE = {
-    "set_major": [1, 0],
+    "set_major": [2, 1, 3, 0],
     "blocks_per_cu": [4, 8, 12],
     "tile_bases": [4096, 8192, 16384],
     "list_per_item": [16384, 65536],
