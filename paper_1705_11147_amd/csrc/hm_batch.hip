@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_export_batch(const BatchHeader *hdr,
 }
 
 // 6 waves per SIMD: the budget that holds every pass-1/pass-2 value in
-// registers without spilling.
+// registers without spilling (a 7-wave budget spills and measured the same).
 template <int KW, bool CHECKED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
                                                   const int32_t *group, uint32_t *done) {
