@@ -34,13 +34,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(profile: str, source: str):
+def source_digest(paths) -> str:
+    """sha256 over the concatenated source files that define a kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+PASS1_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_kmer.hip")]
+
+
+def profiled_traffic(profile: str, sources=PASS1_SOURCES):
     """HBM bytes per launch of the dominant kernel from a committed rocprofv3
     summary, or None when the kernel source changed since it was measured."""
-    import hashlib
     try:
         text = open(profile).read()
-        digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        digest = source_digest(sources)
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("traffic_bytes", "source_sha")))
@@ -293,8 +304,7 @@ def main():
     roofline = {"kernel": "k_pass1_fixed (table probe, Bloom test-and-set, insert/count)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_pass1_fixed_mid_k51_traffic.md"),
-                                            os.path.join(ROOT, "paper_1705_11147_amd", "csrc", "hm_kmer.hip"))
+                "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_pass1_fixed_mid_k51_traffic.md"))
                 if args.scale == 1.0 else None,
                 "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
                 "events_per_position": {x: round(v / positions, 4) for x, v in st.items() if x != "reserved"}}
