@@ -71,6 +71,47 @@ def sizes_for(w, distinct_est: float, kept_est: float):
     return cap, bloom_words, list_cap
 
 
+def measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log, reps=3):
+    """Time the export with and without HM_EXPORT_SORTED on the bench table (outside the timed
+    step: the path's output is an unordered record set) and check the device's order."""
+    import torch
+    from paper_1705_11147_amd import abi
+    flags = abi.HM_EXPORT_CLASSIFY
+    kc.export(out, flags | abi.HM_EXPORT_SORTED)  # allocates the scratch once
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        kc.export(out, flags)
+        ev[2 * i + 1].record(stream)
+        kc.export(out, flags | abi.HM_EXPORT_SORTED)
+        ev[2 * i + 2].record(stream)
+    torch.cuda.synchronize()
+    abi.check(kc.status(), "sorted export")
+    plain = float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+    srt = float(np.mean([ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(reps)]))
+    n = int(out.n_out.item())
+    assert n == n_records and out.digest_words() == ref_digest, "sorted export changed the record set"
+    hi, lo = out.key_hi[:n], out.key_lo[:n] ^ (-2 ** 63)  # flip the sign bit: signed order = unsigned order
+    ordered = bool(((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all().item())
+    assert ordered, "sorted export is not in key order"
+    passes = (2 * k + 7) // 8
+    kw = 2 if 2 * k > 64 else 1
+    # algorithmic bytes per record: each pass reads the digit's key word for the tile counts, then
+    # reads and writes the keys and the 4-byte index; staging reads the 38 record bytes and writes
+    # a 48-byte line; the gather reads the index, one 64-byte line and the keys when the last pass
+    # left them in the scratch, and writes 38 record bytes (+ keys)
+    copy = (passes & 1) * 8 * kw
+    per_rec = passes * (8 + 2 * (8 * kw + 4)) + (38 + 48) + (4 + 64 + copy + 38 + copy)
+    sort_ms = srt - plain
+    res = {"records": n, "key_bits": 2 * k, "passes": passes, "export_ms": round(plain, 3),
+           "export_sorted_ms": round(srt, 3), "sort_ms": round(sort_ms, 3),
+           "sort_records_per_s": round(n / (sort_ms / 1000), 1), "bytes_per_record": per_rec,
+           "sort_algorithmic_GBps": round(n * per_rec / (sort_ms / 1000) / 1e9, 1), "order_checked": ordered}
+    log("sorted export: %s" % res)
+    return res
+
+
 def run_batched(args, dev, log):
     """64 read sets (0.5-8 Mbp genomes, 10-60x, 150 bp, 1% errors, k=31): the
     batched persistent form replayed from a HIP graph against the plain
@@ -177,6 +218,7 @@ def main():
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
+    ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
@@ -324,6 +366,10 @@ def main():
         reqs = st["probe_slots"] + (occ - deferred) + bloom_tests + st["cas_attempts"] + 2 * st["wide_counts"]
         roofline["pass1_random_requests_Gps"] = round(reqs / (stage_ms["pass1"] / 1000) / 1e9, 2)
 
+    sorted_export = None
+    if not args.no_sort:
+        sorted_export = measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -362,6 +408,7 @@ def main():
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "sorted_export": sorted_export,
         "batched": batched,
         "serving": serving,
     }

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define HM_ABI_VERSION 1
+#define HM_ABI_VERSION 2
 
 /* return codes */
 #define HM_OK 0
@@ -75,6 +75,8 @@ extern "C" {
 #define HM_EXPORT_ALL 2u      /* every k-mer in the table, also below min_depth */
 #define HM_EXPORT_CLASSIFY 4u /* classify while exporting (hm_classify_ext not needed first);
                                  needs the min_depth/ext_min of hm_export_t */
+#define HM_EXPORT_SORTED 8u   /* records in ascending key order (key_hi, then key_lo), i.e. the
+                                 lexicographic order of the k-mers; needs hm_export_t.sort_work */
 
 #define HM_CLS_FORK 4
 #define HM_CLS_X 5
@@ -171,6 +173,8 @@ typedef struct {
     uint64_t *digest; /* optional (may be NULL): 2 words, order-free sum and xor of per-record hashes */
     uint32_t min_depth; /* used with HM_EXPORT_CLASSIFY */
     uint32_t ext_min;   /* used with HM_EXPORT_CLASSIFY */
+    void *sort_work;          /* used with HM_EXPORT_SORTED: device scratch, 256-byte aligned, */
+    uint64_t sort_work_bytes; /* at least hm_export_sort_bytes(capacity) bytes; else may be NULL / 0 */
 } hm_export_t;
 
 /* ---- sizes and helpers ------------------------------------------------ */
@@ -182,6 +186,11 @@ uint64_t hm_mask_words(int64_t n_bases);
 size_t hm_table_bytes(uint64_t capacity);
 size_t hm_bloom_bytes(uint64_t n_words);
 size_t hm_list_bytes(uint64_t capacity);
+/* Scratch that hm_export_table needs with HM_EXPORT_SORTED for an export
+ * buffer of `capacity` records: 88 bytes per record plus 1 KiB per 4096
+ * records (keys, record index and the staged counters, double-buffered where
+ * a radix pass needs it). */
+size_t hm_export_sort_bytes(uint64_t capacity);
 /* Host-only argument check of a parameter block (no device access). */
 int hm_check_params(const hm_params_t *p);
 
@@ -234,9 +243,15 @@ int hm_kmer_count(const hm_reads_t *r, const hm_params_t *p, hm_table_t *t, hm_l
  * its class byte.  Results stay in the table for hm_export_table. */
 int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 
-/* Stream-compact the classified table into `out` (unordered; sort on the
- * consumer side if an order is needed).  flags: HM_EXPORT_UU_ONLY,
- * HM_EXPORT_ALL.  Zeroes out->n_out (and out->digest) first. */
+/* Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
+ * HM_EXPORT_ALL, HM_EXPORT_CLASSIFY, HM_EXPORT_SORTED.  Zeroes out->n_out (and
+ * out->digest) first.  Without HM_EXPORT_SORTED the records are in table-slot
+ * (hash) order.  With it they are in ascending key order: an LSD radix sort
+ * on the 2k key bits, 8 bits per pass, runs after the compaction on the same
+ * stream and uses out->sort_work as scratch (HM_EINVAL if it is NULL,
+ * misaligned, smaller than hm_export_sort_bytes(out->capacity), or if
+ * out->capacity >= 2^32).  The digest does not depend on the order.  After
+ * an HM_EOUTPUT failure the partial records are sorted too, and stay invalid. */
 int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
 
 

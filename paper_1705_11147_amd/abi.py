@@ -32,6 +32,7 @@ HM_CHECKED = 4
 HM_EXPORT_UU_ONLY = 1
 HM_EXPORT_ALL = 2
 HM_EXPORT_CLASSIFY = 4
+HM_EXPORT_SORTED = 8
 
 HM_CLS_FORK = 4
 HM_CLS_X = 5
@@ -74,7 +75,8 @@ class Export(ctypes.Structure):
     _fields_ = [("key_hi", ctypes.c_void_p), ("key_lo", ctypes.c_void_p), ("count", ctypes.c_void_p),
                 ("tl", ctypes.c_void_p), ("tr", ctypes.c_void_p), ("cls_l", ctypes.c_void_p),
                 ("cls_r", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("n_out", ctypes.c_void_p),
-                ("digest", ctypes.c_void_p), ("min_depth", ctypes.c_uint32), ("ext_min", ctypes.c_uint32)]
+                ("digest", ctypes.c_void_p), ("min_depth", ctypes.c_uint32), ("ext_min", ctypes.c_uint32),
+                ("sort_work", ctypes.c_void_p), ("sort_work_bytes", ctypes.c_uint64)]
 
 
 class BatchSet(ctypes.Structure):
@@ -104,6 +106,7 @@ SIGNATURES = {
     "hm_table_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "hm_bloom_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "hm_list_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_export_sort_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "hm_check_params": ([P(Params)], ctypes.c_int),
     "hm_table_init": ([P(Table), vp], ctypes.c_int),
     "hm_bloom_init": ([P(Bloom), vp], ctypes.c_int),

@@ -636,6 +636,9 @@ int hip_fail(hipError_t e, const char *what);
 int device_cus();
 inline bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 uint64_t grid_for(uint64_t items, int per_cu = 8);
+// key-order sort of an export (defined in hm_sort.hip); key_bits = 2k
+uint64_t sort_work_bytes(uint64_t capacity);
+int sort_export(const hm_export_t &out, int key_bits, hipStream_t s);
 
 #define HM_LAUNCH_CHECK(what)                                \
     do {                                                     \

@@ -485,7 +485,17 @@ int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipSt
     if (out->capacity > 0 && (!out->key_hi || !out->key_lo || !out->count || !out->tl || !out->tr || !out->cls_l ||
                               !out->cls_r))
         return fail(HM_EINVAL, "export: record arrays are NULL");
-    if (flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL | HM_EXPORT_CLASSIFY)) return fail(HM_EINVAL, "export: unknown flags");
+    if (flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL | HM_EXPORT_CLASSIFY | HM_EXPORT_SORTED))
+        return fail(HM_EINVAL, "export: unknown flags");
+    if (flags & HM_EXPORT_SORTED) {
+        if (out->capacity >= (1ull << 32)) return fail(HM_EINVAL, "export: HM_EXPORT_SORTED needs capacity < 2^32");
+        if (out->capacity > 0 && (!out->sort_work || ((uintptr_t)out->sort_work & 255)))
+            return fail(HM_EINVAL, "export: HM_EXPORT_SORTED needs a 256-byte aligned sort_work");
+        if (out->capacity > 0 && out->sort_work_bytes < sort_work_bytes(out->capacity))
+            return fail(HM_EINVAL, "export: sort_work has %llu bytes, %llu needed",
+                        (unsigned long long)out->sort_work_bytes,
+                        (unsigned long long)sort_work_bytes(out->capacity));
+    }
     if ((flags & HM_EXPORT_CLASSIFY) && (out->min_depth < 1 || out->ext_min < 1))
         return fail(HM_EINVAL, "export: HM_EXPORT_CLASSIFY needs min_depth and ext_min >= 1");
     if (out->capacity > 0 && (((uintptr_t)out->tl | (uintptr_t)out->tr) & 15))
@@ -505,6 +515,7 @@ int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipSt
         hipLaunchKernelGGL(k_export<1>, g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), t->capacity,
                            flags, *out, t->status);
     HM_LAUNCH_CHECK("hm_export_table");
+    if (flags & HM_EXPORT_SORTED) return sort_export(*out, 2 * t->k, s);
     return HM_OK;
 }
 

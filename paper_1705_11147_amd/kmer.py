@@ -112,11 +112,24 @@ class Records:
         self.cls_r = torch.empty(n, dtype=torch.uint8, device=device)
         self.n_out = torch.zeros(1, dtype=torch.int64, device=device)
         self.digest = torch.zeros(2, dtype=torch.int64, device=device)
+        self.device = device
+        self.sort_work = None
 
-    def struct(self, digest: bool = True, min_depth: int = 0, ext_min: int = 0) -> abi.Export:
+    def sort_scratch(self) -> tuple[int, int]:
+        """(pointer, bytes) of the scratch a key-ordered export needs, allocated on first use."""
+        need = int(abi.lib().hm_export_sort_bytes(self.capacity))
+        if self.sort_work is None:
+            self.sort_work = torch.empty(need // 8 + 64, dtype=torch.int64, device=self.device)
+        base = self.sort_work.data_ptr()
+        ptr = (base + 255) // 256 * 256
+        return ptr, self.sort_work.numel() * 8 - (ptr - base)
+
+    def struct(self, digest: bool = True, min_depth: int = 0, ext_min: int = 0, sort: bool = False) -> abi.Export:
+        work, work_bytes = self.sort_scratch() if sort else (None, 0)
         return abi.Export(self.key_hi.data_ptr(), self.key_lo.data_ptr(), self.count.data_ptr(), self.tl.data_ptr(),
                           self.tr.data_ptr(), self.cls_l.data_ptr(), self.cls_r.data_ptr(), self.capacity,
-                          self.n_out.data_ptr(), self.digest.data_ptr() if digest else None, min_depth, ext_min)
+                          self.n_out.data_ptr(), self.digest.data_ptr() if digest else None, min_depth, ext_min,
+                          work, work_bytes)
 
     def to_numpy(self, n: int | None = None, sort: bool = True) -> dict:
         """Copy the first n records to the host (sorted by key when `sort`)."""
@@ -211,7 +224,7 @@ class KmerCounter:
     def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
         """hm_export_table; with abi.HM_EXPORT_CLASSIFY in flags the export
         classifies from the counters (no hm_classify_ext needed before)."""
-        e = out.struct(digest, self.params.min_depth, self.params.ext_min)
+        e = out.struct(digest, self.params.min_depth, self.params.ext_min, sort=bool(flags & abi.HM_EXPORT_SORTED))
         abi.call("hm_export_table", ctypes.byref(self.table), flags, ctypes.byref(e), _stream(stream))
 
     def stats(self) -> dict:
@@ -267,7 +280,7 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
         kc.run([packed], out, flags=export_flags, fused=fused)
         rc = kc.status()
         if rc == abi.HM_OK:
-            res = out.to_numpy()
+            res = out.to_numpy(sort=not (export_flags & abi.HM_EXPORT_SORTED))
             res["digest"] = out.digest_words()
             res["positions"] = P
             res["capacity"] = kc.capacity

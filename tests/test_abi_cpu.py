@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(L):
 
 
 def test_sizes(L):
-    assert L.hm_abi_version() == 1
+    assert L.hm_abi_version() == 2
     assert L.hm_table_bytes(1 << 20) == 64 << 20
     assert L.hm_bloom_bytes(1024) == 8192
     assert L.hm_mask_words(0) == 3 and L.hm_mask_words(64) == 4 and L.hm_mask_words(130) == 5
@@ -113,3 +113,57 @@ def test_package_import_is_lazy_and_loud():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                          cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     assert "loud" in out.stdout
+
+
+# ---- the ctypes mirror against the C header, compiled by gcc
+
+C_NAMES = {"Reads": "hm_reads_t", "Params": "hm_params_t", "Table": "hm_table_t", "Bloom": "hm_bloom_t",
+           "List": "hm_list_t", "Export": "hm_export_t", "BatchSet": "hm_batch_set_t",
+           "BatchTuning": "hm_batch_tuning_t", "BatchPlan": "hm_batch_plan_t"}
+
+
+def test_struct_layout_matches_header(tmp_path):
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hm_kmer.h"', "int main(void) {"]
+    expect = []
+    for py, c in C_NAMES.items():
+        cls = getattr(abi, py)
+        lines.append('printf("%%zu\\n", sizeof(%s));' % c)
+        expect.append(("sizeof " + c, ctypes.sizeof(cls)))
+        for name, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (c, name))
+            expect.append(("%s.%s" % (c, name), getattr(cls, name).offset))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I",
+                    os.path.join(rocm, "include"), str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert len(got) == len(expect)
+    bad = [(what, c, py) for (what, py), c in zip(expect, got) if c != py]
+    assert not bad, "C vs ctypes: %r" % bad
+
+
+def test_sorted_export_scratch_and_rejections(L):
+    # scratch: keys, indices and staged counters (88 B per record), tile counts, digit totals
+    assert L.hm_export_sort_bytes(1 << 20) == (88 << 20) + 1024 * 256 + 1024
+    assert L.hm_export_sort_bytes(10) >= 88 * 10 + 2048
+    t = abi.Table(64, 1024, 0, 31, 64, None)
+    S = abi.HM_EXPORT_SORTED
+
+    def ex(cap=10, work=None, nbytes=0):
+        return abi.Export(8, 8, 8, 16, 16, 8, 8, cap, 64, None, 0, 0, work, nbytes)
+    assert L.hm_export_table(ctypes.byref(t), S, ctypes.byref(ex()), None) == abi.HM_EINVAL  # no scratch
+    need = L.hm_export_sort_bytes(10)
+    assert L.hm_export_table(ctypes.byref(t), S, ctypes.byref(ex(work=4096 + 64, nbytes=need)),
+                             None) == abi.HM_EINVAL  # misaligned
+    assert L.hm_export_table(ctypes.byref(t), S, ctypes.byref(ex(work=4096, nbytes=need - 1)),
+                             None) == abi.HM_EINVAL  # too small
+    assert L.hm_export_table(ctypes.byref(t), S, ctypes.byref(ex(cap=1 << 32, work=4096, nbytes=1 << 62)),
+                             None) == abi.HM_EINVAL  # indices are 32-bit
+    assert "SORTED" in abi.last_error()

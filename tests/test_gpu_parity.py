@@ -296,3 +296,79 @@ def test_fused_classify_export_and_presence_filter(k):
         assert_tables_equal({x: v[m] for x, v in t.items() if isinstance(v, np.ndarray)}, exp, "all, count >= 2")
         ones = set(zip(t["key_hi"][~m].tolist(), t["key_lo"][~m].tolist()))
         assert (t["count"][~m] == 1).all() and ones <= singles
+
+
+# ------------------------------------------------------------------ key-ordered export
+
+@pytest.mark.parametrize("k", [1, 5, 21, 31, 33, 51, 63])
+def test_sorted_export_order(k):
+    """HM_EXPORT_SORTED: the device's record order is the oracle's key order, record by record
+    (many tiles, a ragged last tile, 1 to 16 radix passes, one- and two-word keys)."""
+    ascii, qual, off = random_read_set(500 + k, 3000, 0, 220, genome_len=30000, n_rate=0.002, lower_rate=0.01)
+    exp = oracle.run(ascii, qual, off, k, n_threads=4)
+    for fused in (False, True):
+        got = kmer.analyze(ascii, qual, k, read_off=off, export_flags=abi.HM_EXPORT_SORTED, fused=fused)
+        assert_tables_equal(got, exp, "sorted k=%d fused=%s" % (k, fused))
+        plain = kmer.analyze(ascii, qual, k, read_off=off, fused=fused)
+        assert got["digest"] == plain["digest"]
+
+
+@pytest.mark.parametrize("k", [2, 32])
+def test_sorted_export_forward_only_even_k(k):
+    """Forward-only keys of exactly 64 bits (k=32) and a 4-bit key (k=2)."""
+    ascii, qual, off = random_read_set(700 + k, 2000, 40, 150, genome_len=20000)
+    exp = oracle.run(ascii, qual, off, k, forward_only=True, n_threads=4)
+    got = kmer.analyze(ascii, qual, k, read_off=off, forward_only=True, export_flags=abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, exp, "sorted forward k=%d" % k)
+
+
+def test_sorted_export_workload_scale():
+    """The tiny workload at full size (about a million records, 6 passes) and the mid workload's
+    shape at 1/200 (k=51, 13 passes), sorted on the device."""
+    w = synth.tiny()
+    r = w.reads()
+    exp = oracle.run(r.ascii, r.qual, r.offsets(), 21, n_threads=8)
+    got = kmer.analyze(r.ascii, r.qual, 21, read_len=100, fused=True, export_flags=abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, exp, "tiny sorted")
+    w = synth.mid(scale=0.005)
+    r = w.reads()
+    exp = oracle.run(r.ascii, r.qual, r.offsets(), 51, n_threads=8)
+    got = kmer.analyze(r.ascii, r.qual, 51, read_len=150, fused=True, export_flags=abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, exp, "mid/200 sorted")
+
+
+def test_sorted_export_with_other_flags():
+    ascii, qual, off = random_read_set(811, 3000, 100, 150, genome_len=40000)
+    exp = oracle.run(ascii, qual, off, 31, n_threads=4)
+    m = oracle.uu_mask(exp)
+    got = kmer.analyze(ascii, qual, 31, read_off=off, export_flags=abi.HM_EXPORT_UU_ONLY | abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, {x: v[m] for x, v in exp.items() if isinstance(v, np.ndarray)}, "uu sorted")
+    # every slot: keys strictly increasing, and the part that is unique (count >= 2) equal to the oracle's
+    got = kmer.analyze(ascii, qual, 31, read_off=off, export_flags=abi.HM_EXPORT_ALL | abi.HM_EXPORT_SORTED)
+    key = got["key_hi"].astype(object) * 2 ** 64 + got["key_lo"].astype(object)
+    assert all(a < b for a, b in zip(key[:-1], key[1:]))
+    keep = got["count"] >= 2
+    assert_tables_equal({x: v[keep] for x, v in got.items() if isinstance(v, np.ndarray)}, exp, "all sorted")
+
+
+def test_sorted_export_empty_and_too_small():
+    z = np.zeros(0, np.uint8)
+    got = kmer.analyze(z, z, 21, read_off=np.zeros(1, np.int64), export_flags=abi.HM_EXPORT_SORTED)
+    assert len(got["count"]) == 0
+    # an export buffer too small reports HM_EOUTPUT (the partial records are sorted but invalid);
+    # the same table then exports in full, in key order
+    ascii, qual, off = random_read_set(812, 2000, 100, 150, genome_len=30000)
+    exp = oracle.run(ascii, qual, off, 21, n_threads=4)
+    a = torch.from_numpy(ascii).cuda()
+    q = torch.from_numpy(qual).cuda()
+    packed = kmer.pack_reads(a, q, read_off=torch.from_numpy(off).cuda(), qcut=20)
+    kc = kmer.KmerCounter(21, 1 << 18, 1 << 14, 1 << 20, device="cuda")
+    small = kmer.Records(100, device="cuda")
+    kc.run([packed], small, flags=abi.HM_EXPORT_SORTED, fused=True)
+    assert kc.status() == abi.HM_EOUTPUT
+    assert int(small.n_out.item()) == len(exp["count"])
+    full = kmer.Records(len(exp["count"]) + 10, device="cuda")
+    kc.status_buf.zero_()
+    kc.export(full, abi.HM_EXPORT_SORTED | abi.HM_EXPORT_CLASSIFY)
+    assert kc.status() == abi.HM_OK
+    assert_tables_equal(full.to_numpy(sort=False), exp, "after resize")
