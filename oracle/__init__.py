@@ -35,6 +35,18 @@ class OrcParams(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("n_threads", ctypes.c_int32)]
 
 
+class OrcCardParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("flags", ctypes.c_uint32), ("n_owners", ctypes.c_uint32),
+                ("owner", ctypes.c_uint32), ("hll_p", ctypes.c_int32), ("sample_log2", ctypes.c_uint32),
+                ("heavy_log2", ctypes.c_uint32), ("min_depth", ctypes.c_uint32), ("heavy_min", ctypes.c_uint32),
+                ("n_threads", ctypes.c_int32)]
+
+
+class OrcCardResult(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("sampled_distinct", ctypes.c_uint64),
+                ("sampled_kept", ctypes.c_uint64), ("n_heavy", ctypes.c_uint64), ("positions", ctypes.c_int64)]
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with g++ (host code only)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
@@ -69,6 +81,10 @@ def lib():
         L.orc_part_many.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32,
                                     ctypes.c_int32, ctypes.c_void_p]
         L.orc_part_many.restype = None
+        L.orc_card.argtypes = [u8p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(OrcCardParams),
+                               ctypes.c_void_p, ctypes.POINTER(OrcCardResult), ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_uint64]
+        L.orc_card.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -134,3 +150,32 @@ def shard_of(key_hi: np.ndarray, key_lo: np.ndarray, n_shards: int) -> np.ndarra
 def uu_mask(t: dict) -> np.ndarray:
     """UU records: unique high-quality extension on both sides."""
     return (t["cls_l"] < 4) & (t["cls_r"] < 4)
+
+
+def card(ascii: np.ndarray, read_off: np.ndarray, k: int, hll_p: int = 14, sample_log2: int = 10,
+         heavy_log2: int = 8, min_depth: int = 2, heavy_min: int = 64, n_owners: int = 1, owner: int = 0,
+         forward_only: bool = False, n_threads: int = 1, heavy_cap: int = 1 << 16) -> dict:
+    """Cardinality pass over the reads (see orc_card in kmer_oracle.cpp): HyperLogLog registers and
+    estimate of the distinct owned k-mers, the exact distinct sample's size and kept count, and the
+    sorted heavy-hitter keys (at most heavy_cap returned; 'n_heavy' is the full number)."""
+    ascii = np.ascontiguousarray(ascii, dtype=np.uint8)
+    read_off = np.ascontiguousarray(read_off, dtype=np.int64)
+    if read_off[-1] > ascii.size:
+        raise ValueError("read offsets exceed the base array")
+    p = OrcCardParams(k, FORWARD_ONLY if forward_only else 0, n_owners, owner, hll_p, sample_log2, heavy_log2,
+                      min_depth, heavy_min, n_threads)
+    regs = np.zeros(1 << hll_p, np.uint32)
+    hh = np.zeros(heavy_cap, np.uint64)
+    hl = np.zeros(heavy_cap, np.uint64)
+    res = OrcCardResult()
+    t0 = time.perf_counter()
+    rc = lib().orc_card(ascii.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                        read_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), read_off.size - 1, ctypes.byref(p),
+                        regs.ctypes.data, ctypes.byref(res), hh.ctypes.data, hl.ctypes.data, heavy_cap)
+    secs = time.perf_counter() - t0
+    if rc != 0:
+        raise ValueError("oracle cardinality pass failed with code %d" % rc)
+    n = min(int(res.n_heavy), heavy_cap)
+    return {"registers": regs, "estimate": res.estimate, "sampled_distinct": int(res.sampled_distinct),
+            "sampled_kept": int(res.sampled_kept), "n_heavy": int(res.n_heavy), "heavy_hi": hh[:n],
+            "heavy_lo": hl[:n], "positions": int(res.positions), "seconds": secs}

@@ -46,6 +46,7 @@
  * Output records are sorted by key.
  */
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <thread>
@@ -59,6 +60,8 @@ namespace {
 constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ULL;  /* method-defined owner map */
 constexpr uint64_t kShardSeed = 0x13198A2E03707344ULL;  /* test sampling shards */
 constexpr uint64_t kThreadSeed = 0xA4093822299F31D0ULL; /* oracle thread partition */
+constexpr uint64_t kCardSeed = 0xB7E151628AED2A6AULL;   /* method-defined cardinality hash */
+constexpr uint64_t kPosSeed = 0x452821E638D01377ULL;    /* method-defined window sampling hash */
 
 inline uint64_t fmix64(uint64_t k) {
     k ^= k >> 33;
@@ -295,5 +298,146 @@ void orc_fetch(void *handle, uint32_t ext_min, uint64_t *key_hi, uint64_t *key_l
 int64_t orc_positions(void *handle) { return ((const orc_result *)handle)->positions; }
 
 void orc_free(void *handle) { delete (orc_result *)handle; }
+
+
+/* ---- cardinality pass (section "Parallel k-mer analysis": the
+ * HyperLogLog estimate that sizes the Bloom filter, and the heavy hitters
+ * found in the same pass) ----
+ *
+ * Over every valid window whose key is owned (owner filter as in orc_run):
+ *   Hc = fmix64(fmix64(hi ^ kCardSeed) ^ lo);
+ *   HyperLogLog (Flajolet, Fusy, Gandouet and Meunier, 2007) with m = 2^p
+ *   registers and 64-bit hashes: the top p bits of Hc select register j, and
+ *   M[j] is the maximum over the keys of rho = 1 + the number of leading
+ *   zeros of the remaining 64 - p bits (64 - p + 1 when they are all zero);
+ *   distinct sample: keys whose low `sample_log2` bits of Hc are all zero
+ *   are counted exactly;
+ *   heavy-hitter sample: the window starting at base index j of the read
+ *   set is sampled when the low `heavy_log2` bits of fmix64(j ^ kPosSeed) are
+ *   all zero, and sampled windows are counted per key.
+ * Results: the registers; the estimate alpha_m m^2 / sum_j 2^-M[j], replaced
+ * by m ln(m / V) when it is at most 5m/2 and V > 0 registers are zero (no
+ * large-range correction: the hash has 64 bits); the number of sampled keys
+ * and of sampled keys with count >= min_depth; the keys whose sampled-window
+ * count reaches heavy_min, sorted.
+ * Threads take disjoint read ranges; registers merge by maximum (the
+ * paper's merge of sketches) and counts by sum. */
+
+typedef struct {
+    int32_t k;
+    uint32_t flags; /* ORC_FORWARD_ONLY */
+    uint32_t n_owners;
+    uint32_t owner;
+    int32_t hll_p;        /* 4..18 */
+    uint32_t sample_log2; /* 0..63 */
+    uint32_t heavy_log2;  /* 0..63 */
+    uint32_t min_depth;
+    uint32_t heavy_min;
+    int32_t n_threads;
+} orc_card_params_t;
+
+typedef struct {
+    double estimate;
+    uint64_t sampled_distinct;
+    uint64_t sampled_kept;
+    uint64_t n_heavy;
+    int64_t positions; /* valid windows of owned keys */
+} orc_card_result_t;
+
+typedef std::unordered_map<u128, uint64_t, KeyHash> CountMap;
+
+static void card_scan(const uint8_t *ascii, const int64_t *read_off, int64_t r0, int64_t r1,
+                      const orc_card_params_t *p, std::vector<uint32_t> &regs, CountMap &sample, CountMap &heavy,
+                      int64_t *positions) {
+    const int k = p->k, P = p->hll_p;
+    const u128 mask = (((u128)1 << (2 * k)) - 1);
+    const uint64_t smask = p->sample_log2 ? (~0ULL >> (64 - p->sample_log2)) : 0;
+    const uint64_t hmask = p->heavy_log2 ? (~0ULL >> (64 - p->heavy_log2)) : 0;
+    int64_t npos = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const int64_t b = read_off[r];
+        const int64_t L = read_off[r + 1] - b;
+        u128 fwd = 0, rc = 0;
+        int64_t run = 0;
+        for (int64_t j = 0; j < L; ++j) {
+            const int c = code_of(ascii[b + j]);
+            if (c == 4) {
+                run = 0;
+                fwd = rc = 0;
+                continue;
+            }
+            fwd = ((fwd << 2) | (u128)c) & mask;
+            rc = (rc >> 2) | ((u128)(3 - c) << (2 * (k - 1)));
+            if (++run < k) continue;
+            const u128 key = ((p->flags & ORC_FORWARD_ONLY) || fwd <= rc) ? fwd : rc;
+            const uint64_t hi = (uint64_t)(key >> 64), lo = (uint64_t)key;
+            if (p->n_owners > 1 && orc_owner(hi, lo, p->n_owners) != p->owner) continue;
+            ++npos;
+            const uint64_t h = key_hash(hi, lo, kCardSeed);
+            const uint32_t reg = (uint32_t)(h >> (64 - P));
+            const uint64_t rest = h << P;
+            const uint32_t rho = rest == 0 ? (uint32_t)(64 - P + 1) : (uint32_t)__builtin_clzll(rest) + 1;
+            if (rho > regs[reg]) regs[reg] = rho;
+            if ((h & smask) == 0) ++sample[key];
+            const int64_t start = b + j - k + 1; /* base index of the window in the read set */
+            if ((fmix64((uint64_t)start ^ kPosSeed) & hmask) == 0) ++heavy[key];
+        }
+    }
+    *positions = npos;
+}
+
+int orc_card(const uint8_t *ascii, const int64_t *read_off, int64_t n_reads, const orc_card_params_t *p,
+             uint32_t *regs_out, orc_card_result_t *res, uint64_t *heavy_hi, uint64_t *heavy_lo, uint64_t heavy_cap) {
+    if (!p || p->k < 1 || p->k > 63 || p->hll_p < 4 || p->hll_p > 18 || n_reads < 0) return ORC_EINVAL;
+    if (!(p->flags & ORC_FORWARD_ONLY) && (p->k % 2) == 0) return ORC_EINVAL;
+    if (p->n_owners < 1 || p->owner >= p->n_owners || p->sample_log2 > 63 || p->heavy_log2 > 63) return ORC_EINVAL;
+    const uint32_t T = p->n_threads > 1 ? (uint32_t)p->n_threads : 1u;
+    const size_t m = (size_t)1 << p->hll_p;
+    std::vector<std::vector<uint32_t>> regs(T, std::vector<uint32_t>(m, 0));
+    std::vector<CountMap> sample(T), heavy(T);
+    std::vector<int64_t> npos(T, 0);
+    auto work = [&](uint32_t t) {
+        card_scan(ascii, read_off, n_reads * t / T, n_reads * (t + 1) / T, p, regs[t], sample[t], heavy[t], &npos[t]);
+    };
+    if (T == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (uint32_t t = 0; t < T; ++t) th.emplace_back(work, t);
+        for (auto &x : th) x.join();
+    }
+    for (uint32_t t = 1; t < T; ++t) {
+        for (size_t j = 0; j < m; ++j) regs[0][j] = std::max(regs[0][j], regs[t][j]);
+        for (auto &kv : sample[t]) sample[0][kv.first] += kv.second;
+        for (auto &kv : heavy[t]) heavy[0][kv.first] += kv.second;
+        npos[0] += npos[t];
+    }
+    double sum = 0.0;
+    uint64_t zeros = 0;
+    for (size_t j = 0; j < m; ++j) {
+        regs_out[j] = regs[0][j];
+        sum += std::ldexp(1.0, -(int)regs[0][j]);
+        zeros += regs[0][j] == 0;
+    }
+    const double md = (double)m;
+    const double alpha = m == 16 ? 0.673 : m == 32 ? 0.697 : m == 64 ? 0.709 : 0.7213 / (1.0 + 1.079 / md);
+    double e = alpha * md * md / sum;
+    if (e <= 2.5 * md && zeros > 0) e = md * std::log(md / (double)zeros);
+    res->estimate = e;
+    res->sampled_distinct = sample[0].size();
+    res->sampled_kept = 0;
+    for (auto &kv : sample[0]) res->sampled_kept += kv.second >= p->min_depth;
+    std::vector<u128> hv;
+    for (auto &kv : heavy[0])
+        if (kv.second >= p->heavy_min) hv.push_back(kv.first);
+    std::sort(hv.begin(), hv.end());
+    res->n_heavy = hv.size();
+    for (size_t i = 0; i < hv.size() && i < heavy_cap; ++i) {
+        heavy_hi[i] = (uint64_t)(hv[i] >> 64);
+        heavy_lo[i] = (uint64_t)hv[i];
+    }
+    res->positions = npos[0];
+    return ORC_OK;
+}
 
 }  /* extern "C" */

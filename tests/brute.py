@@ -97,3 +97,39 @@ def decode(key: int, k: int) -> str:
         s.append(BASES[key & 3])
         key >>= 2
     return "".join(reversed(s))
+
+
+def card(reads: list[str], k: int, hll_p: int, sample_log2: int, heavy_log2: int, min_depth: int, heavy_min: int,
+         forward_only: bool = False, n_owners: int = 1, own: int = 0) -> dict:
+    """Cardinality pass from its definition, over Python strings: HyperLogLog registers (Flajolet et
+    al. 2007: the top p bits of the key's 64-bit hash pick a register, which keeps the largest
+    1 + leading-zero count of the remaining bits), the exact counts of the keys whose hash has
+    `sample_log2` low zero bits, and per-key counts of the windows whose start index (in the
+    concatenated reads) hashes to `heavy_log2` low zero bits."""
+    regs = [0] * (1 << hll_p)
+    sample: dict[int, int] = {}
+    heavy: dict[int, int] = {}
+    base, positions = 0, 0
+    for seq in reads:
+        for i in range(len(seq) - k + 1):
+            w = seq[i:i + k]
+            if any(c.upper() not in DIGIT for c in w):
+                continue
+            f, r = enc(w), enc(revcomp(w))
+            key = f if forward_only or f <= r else r
+            if n_owners > 1 and owner(key, n_owners) != own:
+                continue
+            positions += 1
+            h = fmix64(fmix64((key >> 64) ^ 0xB7E151628AED2A6A) ^ (key & MASK64))
+            j = h >> (64 - hll_p)
+            rest = (h << hll_p) & MASK64
+            rho = 64 - hll_p + 1 if rest == 0 else 64 - rest.bit_length() + 1
+            regs[j] = max(regs[j], rho)
+            if h % (1 << sample_log2) == 0:
+                sample[key] = sample.get(key, 0) + 1
+            if fmix64((base + i) ^ 0x452821E638D01377) % (1 << heavy_log2) == 0:
+                heavy[key] = heavy.get(key, 0) + 1
+        base += len(seq)
+    return {"registers": regs, "sampled_distinct": len(sample),
+            "sampled_kept": sum(1 for c in sample.values() if c >= min_depth),
+            "heavy": sorted(x for x, c in heavy.items() if c >= heavy_min), "positions": positions}
