@@ -60,17 +60,6 @@ def profiled_traffic(profile: str, sources=PASS1_SOURCES):
     return int(fields["traffic_bytes_per_launch"].strip())
 
 
-def sizes_for(w, distinct_est: float, kept_est: float):
-    """Table / Bloom / list sizes from estimates of distinct k-mers and of the
-    k-mers seen at least twice (the workload recipe fixes both)."""
-    from paper_1705_11147_amd.kmer import next_pow2
-    from paper_1705_11147_amd.kmer import list_slack
-    cap = next_pow2(int(kept_est / 0.45))
-    bloom_words = next_pow2(int(distinct_est * 12 / 64))
-    list_cap = int(distinct_est * 1.15) + list_slack(1)
-    return cap, bloom_words, list_cap
-
-
 def measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log, reps=3):
     """Time the export with and without HM_EXPORT_SORTED on the bench table (outside the timed
     step: the path's output is an unordered record set) and check the device's order."""
@@ -256,14 +245,18 @@ def main():
     qual = torch.from_numpy(r.qual).to(dev)
     torch.cuda.synchronize()
 
-    # distinct k-mers ~ genome k-mers + ~30 erroneous windows per substitution
-    n_err = r.n_bases * w.err
-    distinct_est = w.meta["G"] + 30 * n_err
-    kept_est = w.meta["G"] * 1.02 + 0.03 * distinct_est
-    cap, bloom_words, list_cap = sizes_for(w, distinct_est, kept_est)
-
     stream = torch.cuda.current_stream()
     packed = kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut)
+    # sizes from the cardinality pass (HyperLogLog estimate + distinct sample), as the paper sizes
+    # its Bloom filter before counting
+    sketch = kmer.CardSketch(k, positions, device=dev)
+    card = sketch.run([packed], min_depth=p.min_depth)
+    abi.check(card.status, "cardinality pass")
+    cap, bloom_words, list_cap = kmer.plan_sizes(card, n_hash=4, device=dev)
+    log("cardinality pass: %.4g distinct (HLL), %d of %d sampled keys kept (1/2^%d), %d heavy hitters "
+        "-> table 2^%d, bloom 2^%d words, list %d" % (card.estimate, card.sampled_kept, card.sampled_distinct,
+                                                      card.sample_log2, card.n_heavy, cap.bit_length() - 1,
+                                                      bloom_words.bit_length() - 1, list_cap))
     while True:
         kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth, device=dev)
         out = kmer.Records(int(cap * 0.6), device=dev)
@@ -294,7 +287,7 @@ def main():
         kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, kc.bloom_words * 8 / 1e9, list_cap * 17 / 1e9,
         n_records, n_first))
 
-    stages = ["pack", "init", "pass1", "pass2", "classify_export"]
+    stages = ["pack", "card", "init", "pass1", "pass2", "classify_export"]
 
     def step(ev=None):
         def mark(i):
@@ -303,14 +296,18 @@ def main():
         mark(0)
         kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut, out=packed)
         mark(1)
-        kc.reset()
+        sketch.reset()  # the cardinality pass (its summary sized the structures once, before the loop)
+        sketch.update(packed)
+        sketch.summarize(min_depth=p.min_depth)
         mark(2)
-        kc.insert(packed)
+        kc.reset()
         mark(3)
-        kc.count()
+        kc.insert(packed)
         mark(4)
-        kc.export(out, abi.HM_EXPORT_CLASSIFY)  # depth filter + classification fused into the export sweep
+        kc.count()
         mark(5)
+        kc.export(out, abi.HM_EXPORT_CLASSIFY)  # depth filter + classification fused into the export sweep
+        mark(6)
 
     for _ in range(args.warmup):
         step()
@@ -324,6 +321,9 @@ def main():
     elapsed = time.perf_counter() - t_start
     abi.check(kc.status(), "k-mer analysis (timed steps)")
     assert out.digest_words() == ref_digest and int(out.n_out.item()) == n_records, "output changed between steps"
+    again = sketch.result()
+    assert (again.estimate, again.sampled_kept, again.n_heavy) == (card.estimate, card.sampled_kept, card.n_heavy), \
+        "cardinality pass changed between steps"
 
     stage_ms = {name: float(np.mean([events[s][i].elapsed_time(events[s][i + 1]) for s in range(args.steps)]))
                 for i, name in enumerate(stages)}
@@ -404,7 +404,11 @@ def main():
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
                    "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
                    "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": 4,
-                   "step": "pack+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
+                   "step": "pack+cardinality+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
+                   "cardinality": {"hll_estimate": round(card.estimate, 1), "hll_p": card.hll_p,
+                                   "sampled_kept": card.sampled_kept, "sample_log2": card.sample_log2,
+                                   "kept_estimate": card.sampled_kept << card.sample_log2,
+                                   "heavy_hitters": card.n_heavy},
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,

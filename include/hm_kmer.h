@@ -255,6 +255,67 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
 
 
+/* ---- cardinality pass: sizing and heavy hitters, before pass 1 -------- */
+
+/* Section "Parallel k-mer analysis": a first pass over the reads estimates
+ * the number of distinct k-mers with HyperLogLog (64-bit hashes; sketches
+ * merge by keeping the larger register) so that the Bloom filter can be sized,
+ * and finds the very frequent k-mers (heavy hitters) in the same pass.  Over
+ * every valid window whose key is owned (hm_params_t owner filter):
+ *   Hc = fmix64(fmix64(key_hi ^ 0xB7E151628AED2A6A) ^ key_lo)  (fmix64: the
+ *        64-bit finalizer of MurmurHash3);
+ *   HyperLogLog (Flajolet, Fusy, Gandouet, Meunier 2007), m = 2^hll_p
+ *        registers: the top hll_p bits of Hc pick register j, which keeps the
+ *        maximum of 1 + the leading-zero count of the other 64 - hll_p bits
+ *        (64 - hll_p + 1 when they are all zero);
+ *   distinct sample: a key whose Hc has `sample_log2` low zero bits is
+ *        counted in `sample` (every occurrence), so the sample's keys with
+ *        count >= min_depth, times 2^sample_log2, estimate the kept k-mers;
+ *   window sample: the window starting at base index j of the read set is
+ *        counted in `heavy` when fmix64(j ^ 0x452821E638D01377) has
+ *        `heavy_log2` low zero bits; a key with many sampled windows is a
+ *        heavy hitter.
+ * The result depends only on the reads, not on the order of work. */
+typedef struct {
+    uint32_t *registers;  /* 2^hll_p registers, device */
+    int32_t hll_p;        /* 4..16 */
+    uint32_t sample_log2; /* 0..63 */
+    uint32_t heavy_log2;  /* 0..63 */
+    uint32_t reserved;
+    uint64_t *positions;  /* device counter: valid windows of owned keys */
+    hm_table_t sample;    /* count table of the distinct sample (k as in the params) */
+    hm_table_t heavy;     /* count table of the window sample */
+} hm_card_t;
+
+/* Summary of a cardinality pass (written to device memory by hm_card_summary). */
+typedef struct {
+    double estimate;           /* HyperLogLog estimate of distinct owned k-mers: alpha_m m^2 / sum 2^-M[j],
+                                  or m ln(m / V) when that is <= 5m/2 and V > 0 registers are zero */
+    uint64_t sampled_distinct; /* keys in the distinct sample */
+    uint64_t sampled_kept;     /* of those, keys with count >= min_depth */
+    uint64_t n_heavy;          /* keys whose window-sample count >= heavy_min (all, also past heavy_cap) */
+    uint64_t positions;        /* valid windows of owned keys */
+} hm_card_summary_t;
+
+/* Zero the registers and the position counter, and initialize both tables. */
+int hm_card_init(hm_card_t *c, hipStream_t stream);
+
+/* Add one batch of packed reads to the sketch (call once per batch, after
+ * hm_card_init).  A table that fills up sets HM_ST_TABLE_FULL in its status
+ * word (hm_status then reports HM_ECAPACITY); the registers and the position
+ * count stay exact. */
+int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipStream_t stream);
+
+/* Reduce the sketch to `out` (device memory): the estimate, the distinct
+ * sample's size and its keys with count >= min_depth, and the heavy hitters,
+ * i.e. keys whose window-sample count >= heavy_min; the first heavy_cap of
+ * them (in no particular order) are written to heavy_keys as (key_hi,
+ * key_lo) pairs, 2 * heavy_cap words of device memory (may be NULL when
+ * heavy_cap is 0). */
+int hm_card_summary(const hm_card_t *c, uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,
+                    uint64_t heavy_cap, hm_card_summary_t *out, hipStream_t stream);
+
+
 /* ---- batched form: many read sets, one persistent launch -------------- */
 
 /* One read set of a batch: fixed-length reads (read_len <= 16320), its own

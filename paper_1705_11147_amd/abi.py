@@ -79,6 +79,17 @@ class Export(ctypes.Structure):
                 ("sort_work", ctypes.c_void_p), ("sort_work_bytes", ctypes.c_uint64)]
 
 
+class Card(ctypes.Structure):
+    _fields_ = [("registers", ctypes.c_void_p), ("hll_p", ctypes.c_int32), ("sample_log2", ctypes.c_uint32),
+                ("heavy_log2", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("positions", ctypes.c_void_p),
+                ("sample", Table), ("heavy", Table)]
+
+
+class CardSummary(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("sampled_distinct", ctypes.c_uint64),
+                ("sampled_kept", ctypes.c_uint64), ("n_heavy", ctypes.c_uint64), ("positions", ctypes.c_uint64)]
+
+
 class BatchSet(ctypes.Structure):
     _fields_ = [("ascii", ctypes.c_void_p), ("qual", ctypes.c_void_p), ("n_reads", ctypes.c_int64),
                 ("read_len", ctypes.c_int32), ("bases2", ctypes.c_void_p), ("nmask", ctypes.c_void_p),
@@ -117,6 +128,9 @@ SIGNATURES = {
     "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),
     "hm_classify_ext": ([P(Params), P(Table), vp], ctypes.c_int),
     "hm_export_table": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
+    "hm_card_init": ([P(Card), vp], ctypes.c_int),
+    "hm_cardinality": ([P(Reads), P(Params), P(Card), vp], ctypes.c_int),
+    "hm_card_summary": ([P(Card), ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
     "hm_batch_work_bytes": ([ctypes.c_int32], ctypes.c_size_t),
     "hm_batch_prepare": ([P(BatchSet), ctypes.c_int32, P(Params), ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint32,
                           P(BatchTuning), vp, ctypes.c_size_t, P(BatchPlan), vp], ctypes.c_int),

@@ -1,0 +1,320 @@
+// hm_card.hip -- the cardinality pass that precedes counting (section
+// "Parallel k-mer analysis"): a HyperLogLog estimate of the distinct k-mers,
+// which sizes the Bloom filter; an exact count of a hash-sampled subset of
+// the keys, which estimates how many k-mers survive the depth filter and so
+// sizes the count table; and a sample of windows, whose most frequent keys
+// are the heavy hitters.
+//
+// One kernel visits every window with the same tiling as pass 1.  Each
+// workgroup keeps its own copy of the registers in LDS, one byte each.  A
+// window raises its register only when its rank is larger than the byte: a
+// plain LDS read first, and since registers only grow, almost every window
+// stops there once the sketch has warmed up; the rare raise is a
+// compare-and-swap on the enclosing 32-bit LDS word.  When the workgroup is
+// done it raises the device registers with atomicMax wherever its bytes are
+// larger: the register-wise maximum is the merge of two sketches.  The two
+// samples are rare events (1 in 2^sample_log2 keys, 1 in 2^heavy_log2
+// windows) counted in small open-addressing tables with the pass-1 probe and
+// counter code.
+#include "hm_device.h"
+
+namespace hm {
+namespace {
+
+constexpr uint64_t kCardSeed = 0xB7E151628AED2A6Aull;  // cardinality hash (definition constant)
+constexpr uint64_t kPosSeed = 0x452821E638D01377ull;   // window sampling hash (definition constant)
+constexpr int kCardBlocksPerCu = 4;
+constexpr int kCardMaxP = 16;
+
+struct CardArgs {
+    uint32_t *regs;
+    int p;
+    uint64_t smask, hmask;
+    Slot *s_slots;
+    uint64_t s_cmask;
+    uint32_t s_probe;
+    uint32_t *s_status;
+    Slot *h_slots;
+    uint64_t h_cmask;
+    uint32_t h_probe;
+    uint32_t *h_status;
+    unsigned long long *positions;
+    uint64_t seed;
+};
+
+// Raise byte i of the LDS registers to v (no-op when it is already >= v).
+__device__ __forceinline__ void lds_raise(uint8_t *regs, uint32_t i, uint32_t v) {
+    if (regs[i] >= v) return;
+    uint32_t *w = reinterpret_cast<uint32_t *>(regs + (i & ~3u));
+    const uint32_t sh = (i & 3u) * 8;
+    uint32_t old = *w;
+    while (((old >> sh) & 255u) < v) {
+        const uint32_t prev = atomicCAS(w, old, (old & ~(255u << sh)) | (v << sh));
+        if (prev == old) break;
+        old = prev;
+    }
+}
+
+// Count one occurrence (no extensions) of a key in a sample table.  Once the
+// table is reported full its counts are void, so later samples skip the probe.
+template <int KW>
+__device__ __forceinline__ void sample_count(Slot *slots, uint64_t cmask, uint32_t max_probe, uint32_t *status,
+                                             uint64_t seed, const Occ &o) {
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & HM_ST_TABLE_FULL) return;
+    uint64_t A, B;
+    slot_words<KW>(o.hi, o.lo, A, B);
+    const Probe pr = table_find<KW>(slots, cmask, key_hash(o.hi, o.lo, seed), A, B, max_probe, true);
+    if (pr.slot >= 0) count_occurrence<false>(slots + pr.slot, 4, 4, status, pr.narrow);
+    else atomicOr(status, HM_ST_TABLE_FULL);
+}
+
+template <int KW>
+__device__ __forceinline__ void card_window(const CardArgs &c, uint8_t *s_reg, bool act, const Occ &o, int64_t j,
+                                            uint32_t &npos) {
+    if (!act) return;
+    ++npos;
+    const uint64_t h = fmix64(fmix64(o.hi ^ kCardSeed) ^ o.lo);
+    const uint32_t reg = (uint32_t)(h >> (64 - c.p));
+    const uint64_t rest = h << c.p;
+    const uint32_t rho = rest ? (uint32_t)__clzll((long long)rest) + 1u : (uint32_t)(65 - c.p);
+    lds_raise(s_reg, reg, rho);
+    if ((h & c.smask) == 0) sample_count<KW>(c.s_slots, c.s_cmask, c.s_probe, c.s_status, c.seed, o);
+    if ((fmix64((uint64_t)j ^ kPosSeed) & c.hmask) == 0)
+        sample_count<KW>(c.h_slots, c.h_cmask, c.h_probe, c.h_status, c.seed, o);
+}
+
+__device__ __forceinline__ void card_begin(const CardArgs &c, uint32_t *s_reg32) {
+    for (int i = threadIdx.x; i < (1 << c.p) / 4; i += kBlock) s_reg32[i] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void card_end(const CardArgs &c, const uint8_t *s_reg, uint32_t npos) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < (1 << c.p); i += kBlock) {
+        const uint32_t v = s_reg[i];
+        if (v > c.regs[i]) atomicMax(c.regs + i, v);  // the plain read only skips needless atomics
+    }
+    uint64_t x = npos;
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (lane_id() == 0 && x) atomicAdd(c.positions, (unsigned long long)x);
+}
+
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile,
+                                                       int64_t n_tiles) {
+    __shared__ uint64_t s_b2[kTileB2Words];
+    __shared__ uint64_t s_nm[kTileMaskWords];
+    __shared__ uint64_t s_hq[kTileMaskWords];
+    extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers
+    uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
+    card_begin(c, s_reg32);
+    uint32_t npos = 0;
+    fixed_windows<false>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq,
+                         [&](bool act, const Occ &o, int64_t j) { card_window<KW>(c, s_reg, act, o, j, npos); });
+    card_end(c, s_reg, npos);
+}
+
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_card_var(PassArgs a, CardArgs c, int64_t n_tiles) {
+    __shared__ int64_t s_off[kVarReads + 1];
+    __shared__ int64_t s_pre[kVarReads + 1];
+    extern __shared__ uint32_t s_reg32[];
+    uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
+    card_begin(c, s_reg32);
+    uint32_t npos = 0;
+    var_windows<false>(a, n_tiles, s_off, s_pre,
+                       [&](bool act, const Occ &o, int64_t j) { card_window<KW>(c, s_reg, act, o, j, npos); });
+    card_end(c, s_reg, npos);
+}
+
+// Distinct-sample size and kept count; heavy hitters of the window sample.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_card_tables(const Slot *ss, uint64_t scap, const Slot *hs, uint64_t hcap,
+                                                        uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,
+                                                        uint64_t heavy_cap, hm_card_summary_t *out) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint32_t nd = 0, nk = 0;
+    uint32_t tl[4], tr[4];
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < scap; i += stride) {
+        const Slot *s = ss + i;
+        if (s->a == 0) continue;
+        const uint64_t cnt = slot_counts(s, tl, tr);
+        ++nd;
+        nk += cnt >= min_depth ? 1u : 0u;
+    }
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < hcap; i += stride) {
+        const Slot *s = hs + i;
+        if (s->a == 0) continue;
+        if (slot_counts(s, tl, tr) < heavy_min) continue;
+        const unsigned long long idx = atomicAdd(reinterpret_cast<unsigned long long *>(&out->n_heavy), 1ull);
+        if (idx < heavy_cap) {
+            uint64_t hi = 0, lo;
+            if (KW == 1) {
+                lo = s->a & kLow63;
+            } else {
+                const uint64_t A = s->a & kLow63, B = s->b & kLow63;
+                lo = B | (A << 63);
+                hi = A >> 1;
+            }
+            heavy_keys[2 * idx] = hi;
+            heavy_keys[2 * idx + 1] = lo;
+        }
+    }
+    uint64_t d = nd, kk = nk;
+    for (int off = 32; off > 0; off >>= 1) {
+        d += __shfl_xor(d, off);
+        kk += __shfl_xor(kk, off);
+    }
+    if (lane_id() == 0) {
+        if (d) atomicAdd(reinterpret_cast<unsigned long long *>(&out->sampled_distinct), (unsigned long long)d);
+        if (kk) atomicAdd(reinterpret_cast<unsigned long long *>(&out->sampled_kept), (unsigned long long)kk);
+    }
+}
+
+// HyperLogLog estimate from the registers (one workgroup): a histogram of
+// register values, then alpha_m m^2 / sum 2^-M[j] with the small-range
+// (linear counting) correction of Flajolet et al.
+__global__ __launch_bounds__(kBlock) void k_card_estimate(const uint32_t *regs, int p,
+                                                          const unsigned long long *positions,
+                                                          hm_card_summary_t *out) {
+    __shared__ uint32_t hist[66];
+    for (int i = threadIdx.x; i < 66; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    const uint32_t m = 1u << p;
+    for (uint32_t i = threadIdx.x; i < m; i += kBlock) atomicAdd(&hist[min(regs[i], 65u)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int r = 0; r <= 65; ++r) sum += (double)hist[r] * ldexp(1.0, -r);
+        const double md = (double)m;
+        const double alpha = m == 16 ? 0.673 : m == 32 ? 0.697 : m == 64 ? 0.709 : 0.7213 / (1.0 + 1.079 / md);
+        double e = alpha * md * md / sum;
+        if (e <= 2.5 * md && hist[0] > 0) e = md * log(md / (double)hist[0]);
+        out->estimate = e;
+        out->positions = *positions;
+    }
+}
+
+int check_card(const hm_card_t *c) {
+    if (!c || !c->registers || !c->positions) return fail(HM_EINVAL, "cardinality: sketch or its buffers are NULL");
+    if (c->hll_p < 4 || c->hll_p > kCardMaxP) return fail(HM_EINVAL, "cardinality: hll_p must be 4..%d", kCardMaxP);
+    if (c->sample_log2 > 63 || c->heavy_log2 > 63) return fail(HM_EINVAL, "cardinality: sample bits must be 0..63");
+    int rc = check_table(&c->sample);
+    if (rc) return rc;
+    return check_table(&c->heavy);
+}
+
+uint32_t probe_bound(const hm_table_t &t) {
+    const uint64_t mp = t.max_probe ? (uint64_t)t.max_probe : (uint64_t)kDefaultMaxProbe;
+    return (uint32_t)(mp < t.capacity ? mp : t.capacity);
+}
+
+}  // namespace
+}  // namespace hm
+
+using namespace hm;
+
+extern "C" {
+
+int hm_card_init(hm_card_t *c, hipStream_t s) {
+    int rc = check_card(c);
+    if (rc) return rc;
+    rc = fill<uint32_t>(c->registers, 1ull << c->hll_p, 0u, s);
+    if (rc) return rc;
+    rc = fill<uint64_t>(c->positions, 1, 0ull, s);
+    if (rc) return rc;
+    rc = hm_table_init(&c->sample, s);
+    if (rc) return rc;
+    return hm_table_init(&c->heavy, s);
+}
+
+int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipStream_t s) {
+    int rc = hm_check_params(p);
+    if (rc) return rc;
+    rc = check_card(c);
+    if (rc) return rc;
+    if (c->sample.k != p->k || c->heavy.k != p->k)
+        return fail(HM_EINVAL, "cardinality: sample tables built for k=%d/%d, params have k=%d", c->sample.k,
+                    c->heavy.k, p->k);
+    rc = check_reads(r, p->k);
+    if (rc) return rc;
+    if (r->n_reads == 0) return HM_OK;
+    PassArgs a;
+    memset(&a, 0, sizeof a);
+    a.b2 = r->bases2;
+    a.nm = r->nmask;
+    a.hq = r->hqmask;
+    a.read_off = r->read_off;
+    a.n_reads = r->n_reads;
+    a.n_bases = r->n_bases;
+    a.read_len = r->read_len;
+    a.k = p->k;
+    a.forward_only = (p->flags & HM_FORWARD_ONLY) ? 1 : 0;
+    a.n_owners = p->n_owners;
+    a.owner = p->owner;
+    a.status = c->sample.status;
+    CardArgs ca;
+    ca.regs = c->registers;
+    ca.p = c->hll_p;
+    ca.smask = c->sample_log2 ? (~0ull >> (64 - c->sample_log2)) : 0ull;
+    ca.hmask = c->heavy_log2 ? (~0ull >> (64 - c->heavy_log2)) : 0ull;
+    ca.s_slots = reinterpret_cast<Slot *>(c->sample.slots);
+    ca.s_cmask = c->sample.capacity - 1;
+    ca.s_probe = probe_bound(c->sample);
+    ca.s_status = c->sample.status;
+    ca.h_slots = reinterpret_cast<Slot *>(c->heavy.slots);
+    ca.h_cmask = c->heavy.capacity - 1;
+    ca.h_probe = probe_bound(c->heavy);
+    ca.h_status = c->heavy.status;
+    ca.positions = reinterpret_cast<unsigned long long *>(c->positions);
+    ca.seed = p->seed;
+    const bool two = p->k >= 32;
+    const size_t lds = (size_t)1 << c->hll_p;
+    const int grid_cap = device_cus() * kCardBlocksPerCu;
+    if (!r->read_off && r->read_len <= kTileBases - 64) {
+        if (r->read_len < p->k) return HM_OK;
+        const int32_t rpt = kTileBases / r->read_len;
+        const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
+        const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
+        if (two) hipLaunchKernelGGL(k_card_fixed<2>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+        else hipLaunchKernelGGL(k_card_fixed<1>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+    } else {
+        if (!r->read_off) return fail(HM_EINVAL, "reads longer than %d bases need read_off", kTileBases - 64);
+        const int64_t n_tiles = (r->n_reads + kVarReads - 1) / kVarReads;
+        const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
+        if (two) hipLaunchKernelGGL(k_card_var<2>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
+        else hipLaunchKernelGGL(k_card_var<1>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
+    }
+    HM_LAUNCH_CHECK("hm_cardinality");
+    return HM_OK;
+}
+
+int hm_card_summary(const hm_card_t *c, uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,
+                    uint64_t heavy_cap, hm_card_summary_t *out, hipStream_t s) {
+    int rc = check_card(c);
+    if (rc) return rc;
+    if (!out) return fail(HM_EINVAL, "cardinality summary: out is NULL");
+    if (heavy_cap > 0 && !heavy_keys) return fail(HM_EINVAL, "cardinality summary: heavy_keys is NULL");
+    if (c->sample.k != c->heavy.k || c->sample.k < 1 || c->sample.k > 63)
+        return fail(HM_EINVAL, "cardinality summary: sample tables disagree on k");
+    static_assert(sizeof(hm_card_summary_t) == 40, "summary layout");
+    rc = fill<uint64_t>(reinterpret_cast<uint64_t *>(out), sizeof(hm_card_summary_t) / 8, 0ull, s);
+    if (rc) return rc;
+    const uint64_t cap = c->sample.capacity > c->heavy.capacity ? c->sample.capacity : c->heavy.capacity;
+    const dim3 g((unsigned)grid_for(cap, 16));
+    const Slot *ss = reinterpret_cast<const Slot *>(c->sample.slots);
+    const Slot *hs = reinterpret_cast<const Slot *>(c->heavy.slots);
+    if (c->sample.k >= 32)
+        hipLaunchKernelGGL(k_card_tables<2>, g, dim3(kBlock), 0, s, ss, c->sample.capacity, hs, c->heavy.capacity,
+                           min_depth, heavy_min, heavy_keys, heavy_cap, out);
+    else
+        hipLaunchKernelGGL(k_card_tables<1>, g, dim3(kBlock), 0, s, ss, c->sample.capacity, hs, c->heavy.capacity,
+                           min_depth, heavy_min, heavy_keys, heavy_cap, out);
+    HM_LAUNCH_CHECK("hm_card_summary (tables)");
+    hipLaunchKernelGGL(k_card_estimate, dim3(1), dim3(kBlock), 0, s, c->registers, c->hll_p,
+                       reinterpret_cast<const unsigned long long *>(c->positions), out);
+    HM_LAUNCH_CHECK("hm_card_summary (estimate)");
+    return HM_OK;
+}
+
+}  // extern "C"

@@ -442,6 +442,103 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
     }
 }
 
+// ------------------------------------------------------------------ window loops
+
+// Visit every window of fixed-length reads, tile by tile: each tile's packed
+// words are staged in the caller's LDS arrays (kTileB2Words / kTileMaskWords
+// words).  op(act, occ, j) runs for every lane of the workgroup the same
+// number of times per tile (act = the lane holds a valid, owned window;
+// j = that window's base index in the read set).  With ABORT, a wave stops
+// its tile once the table status says a pass failed.
+template <bool ABORT, class Op>
+__device__ __forceinline__ void fixed_windows(const PassArgs &a, int32_t reads_per_tile, int64_t n_tiles,
+                                              uint64_t *s_b2, uint64_t *s_nm, uint64_t *s_hq, Op &&op) {
+    const int L = a.read_len;
+    const int k = a.k;
+    const int W = L - k + 1;  // windows per read (> 0, checked by the host)
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * reads_per_tile;
+        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
+        const int64_t base0 = r0 * L, base1 = r1 * L;
+        const int64_t org = base0 & ~(int64_t)63;              // origin: multiple of 64 bases
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)(((base1 + 63) >> 6) - mw0) + 2;  // mask words incl. 2 guard words
+        __syncthreads();  // previous tile's readers are done
+        for (int i = threadIdx.x; i < nmw; i += kBlock) {
+            s_nm[i] = a.nm[mw0 + i];
+            s_hq[i] = a.hq[mw0 + i];
+        }
+        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        const Words w{s_b2, s_nm, s_hq};
+        const int total = (int)(r1 - r0) * W;
+        for (int f0 = 0; f0 < total; f0 += kBlock) {
+            if (ABORT && aborted(a.status)) break;
+            const int f = f0 + threadIdx.x;
+            Occ o{0, 0, 4, 4};
+            bool act = false;
+            int64_t j = 0;
+            if (f < total) {
+                const int r = f / W;
+                const int pos = f - r * W;
+                const int64_t rb = (r0 + r) * L - org;
+                act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
+                j = (r0 + r) * L + pos;
+            }
+            op(act, o, j);
+        }
+    }
+}
+
+// Visit every window of variable-length reads (read_off given): packed words
+// are read from global memory; a per-tile prefix sum in LDS (the caller's
+// s_off / s_pre, kVarReads + 1 entries each) maps flat window indices to
+// reads.  op as for fixed_windows.
+template <bool ABORT, class Op>
+__device__ __forceinline__ void var_windows(const PassArgs &a, int64_t n_tiles, int64_t *s_off, int64_t *s_pre,
+                                            Op &&op) {
+    const int k = a.k;
+    const Words w{a.b2, a.nm, a.hq};
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kVarReads;
+        const int nr = (int)min((int64_t)kVarReads, a.n_reads - r0);
+        __syncthreads();
+        // offsets clamped to [0, n_bases]; a decreasing offset makes an empty read
+        for (int i = threadIdx.x; i <= nr; i += kBlock) s_off[i] = min(max(a.read_off[r0 + i], (int64_t)0), a.n_bases);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t acc = 0;
+            for (int i = 0; i < nr; ++i) {
+                s_pre[i] = acc;
+                const int64_t len = s_off[i + 1] - s_off[i];
+                acc += len >= k ? len - k + 1 : 0;
+            }
+            s_pre[nr] = acc;
+        }
+        __syncthreads();
+        const int64_t total = s_pre[nr];
+        for (int64_t f0 = 0; f0 < total; f0 += kBlock) {
+            if (ABORT && aborted(a.status)) break;
+            const int64_t f = f0 + threadIdx.x;
+            Occ o{0, 0, 4, 4};
+            bool act = false;
+            int64_t j = 0;
+            if (f < total) {
+                int lo = 0, hi = nr;  // last read r with s_pre[r] <= f
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_pre[mid] <= f) lo = mid;
+                    else hi = mid;
+                }
+                const int64_t rb = s_off[lo], re = max(s_off[lo + 1], rb);
+                j = rb + (f - s_pre[lo]);
+                act = extract(w, j, rb, re, k, a.forward_only, a.n_owners, a.owner, o);
+            }
+            op(act, o, j);
+        }
+    }
+}
+
 // Pass-2 body for one first-occurrence entry: skip it when the presence filter
 // shows its k-mer was never inserted, else look it up and count it if found.
 template <int KW, bool CHECKED>
@@ -636,6 +733,9 @@ int hip_fail(hipError_t e, const char *what);
 int device_cus();
 inline bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 uint64_t grid_for(uint64_t items, int per_cu = 8);
+// argument checks shared by the entry points (defined in hm_kmer.hip)
+int check_reads(const hm_reads_t *r, int k);
+int check_table(const hm_table_t *t);
 // key-order sort of an export (defined in hm_sort.hip); key_bits = 2k
 uint64_t sort_work_bytes(uint64_t capacity);
 int sort_export(const hm_export_t &out, int key_bits, hipStream_t s);

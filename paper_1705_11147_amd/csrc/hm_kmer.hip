@@ -74,92 +74,23 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
-    const int L = a.read_len;
-    const int k = a.k;
-    const int W = L - k + 1;  // windows per read (> 0, checked by the host)
     ListCursor cur{0, kListChunk};
     Stats st = {};
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t r0 = tile * reads_per_tile;
-        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
-        const int64_t base0 = r0 * L, base1 = r1 * L;
-        const int64_t org = base0 & ~(int64_t)63;          // origin: multiple of 64 bases
-        const int64_t mw0 = org >> 6;
-        const int nmw = (int)(((base1 + 63) >> 6) - mw0) + 2;  // mask words incl. 2 guard words
-        __syncthreads();  // previous tile's readers are done
-        for (int i = threadIdx.x; i < nmw; i += kBlock) {
-            s_nm[i] = a.nm[mw0 + i];
-            s_hq[i] = a.hq[mw0 + i];
-        }
-        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
-        __syncthreads();
-        const Words w{s_b2, s_nm, s_hq};
-        const int total = (int)(r1 - r0) * W;
-        for (int f0 = 0; f0 < total; f0 += kBlock) {
-            if (aborted(a.status)) break;
-            const int f = f0 + threadIdx.x;
-            Occ o{0, 0, 4, 4};
-            bool act = false;
-            if (f < total) {
-                const int r = f / W;
-                const int pos = f - r * W;
-                const int64_t rb = (r0 + r) * L - org;
-                act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
-            }
-            pass1_occ<KW, CHECKED>(a, act, o, cur, st);
-        }
-    }
+    fixed_windows<true>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq,
+                        [&](bool act, const Occ &o, int64_t) { pass1_occ<KW, CHECKED>(a, act, o, cur, st); });
     list_close(a, cur);
     stats_flush(a.stats, st);
 }
 
-// Pass 1 over variable-length reads (read_off given): packed words are read
-// from global memory; a per-tile prefix sum in LDS maps flat window indices
-// to reads.
+// Pass 1 over variable-length reads (read_off given).
 template <int KW, bool CHECKED>
 __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tiles) {
     __shared__ int64_t s_off[kVarReads + 1];
     __shared__ int64_t s_pre[kVarReads + 1];
-    const int k = a.k;
-    const Words w{a.b2, a.nm, a.hq};
     ListCursor cur{0, kListChunk};
     Stats st = {};
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t r0 = tile * kVarReads;
-        const int nr = (int)min((int64_t)kVarReads, a.n_reads - r0);
-        __syncthreads();
-        // offsets clamped to [0, n_bases]; a decreasing offset makes an empty read
-        for (int i = threadIdx.x; i <= nr; i += kBlock) s_off[i] = min(max(a.read_off[r0 + i], (int64_t)0), a.n_bases);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t acc = 0;
-            for (int i = 0; i < nr; ++i) {
-                s_pre[i] = acc;
-                const int64_t len = s_off[i + 1] - s_off[i];
-                acc += len >= k ? len - k + 1 : 0;
-            }
-            s_pre[nr] = acc;
-        }
-        __syncthreads();
-        const int64_t total = s_pre[nr];
-        for (int64_t f0 = 0; f0 < total; f0 += kBlock) {
-            if (aborted(a.status)) break;
-            const int64_t f = f0 + threadIdx.x;
-            Occ o{0, 0, 4, 4};
-            bool act = false;
-            if (f < total) {
-                int lo = 0, hi = nr;  // last read r with s_pre[r] <= f
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_pre[mid] <= f) lo = mid;
-                    else hi = mid;
-                }
-                const int64_t rb = s_off[lo], re = max(s_off[lo + 1], rb);
-                act = extract(w, rb + (f - s_pre[lo]), rb, re, k, a.forward_only, a.n_owners, a.owner, o);
-            }
-            pass1_occ<KW, CHECKED>(a, act, o, cur, st);
-        }
-    }
+    var_windows<true>(a, n_tiles, s_off, s_pre,
+                      [&](bool act, const Occ &o, int64_t) { pass1_occ<KW, CHECKED>(a, act, o, cur, st); });
     list_close(a, cur);
     stats_flush(a.stats, st);
 }
@@ -249,6 +180,9 @@ __global__ __launch_bounds__(kBlock) void k_pack(const uint8_t *ascii, const uin
     }
 }
 
+}  // namespace
+
+namespace hm {
 
 int check_reads(const hm_reads_t *r, int k) {
     if (!r) return fail(HM_EINVAL, "reads is NULL");
@@ -270,7 +204,7 @@ int check_table(const hm_table_t *t) {
     return HM_OK;
 }
 
-}  // namespace
+}  // namespace hm
 
 // ====================================================================== C ABI
 

@@ -249,17 +249,143 @@ class KmerCounter:
             self.export(out, flags, stream, digest)
 
 
+@dataclass
+class CardResult:
+    """Summary of a cardinality pass (hm_card_summary), copied to the host."""
+    estimate: float          # HyperLogLog estimate of distinct owned k-mers
+    sampled_distinct: int    # keys in the distinct sample (1 in 2^sample_log2 keys)
+    sampled_kept: int        # of those, keys with count >= min_depth
+    n_heavy: int             # keys whose window-sample count reached heavy_min
+    positions: int           # valid windows of owned keys
+    hll_p: int
+    sample_log2: int
+    heavy_log2: int
+    heavy_hi: np.ndarray
+    heavy_lo: np.ndarray
+    status: int              # HM_OK, or HM_ECAPACITY when a sample table filled up
+
+    def distinct_hi(self, z: float = 4.0) -> float:
+        """Upper bound on the distinct k-mers: z standard errors (1.04/sqrt(m)) above the estimate."""
+        return self.estimate * (1.0 + z * 1.04 / (1 << self.hll_p) ** 0.5) + z
+
+    def kept_hi(self, z: float = 4.0) -> float:
+        """Upper bound on the k-mers that pass the depth filter: the sampled count plus z Poisson
+        standard deviations, scaled by the sampling rate."""
+        s = float(1 << self.sample_log2)
+        return min((self.sampled_kept + z * self.sampled_kept ** 0.5 + z) * s, self.distinct_hi(z))
+
+
+class CardSketch:
+    """State of the cardinality pass (C ABI hm_card_*): HyperLogLog registers, the distinct-sample
+    table and the window-sample table.  Sample rates default to about 2^18 sampled keys and
+    windows for `positions_hint` windows, so a heavy hitter (heavy_min = 16 sampled windows) is
+    a k-mer holding at least 2^-14 of all windows."""
+
+    def __init__(self, k: int, positions_hint: int, hll_p: int = 14, sample_log2: int | None = None,
+                 heavy_log2: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
+                 seed: int = DEFAULT_SEED, device="cuda"):
+        self.device = torch.device(device)
+        self.params = abi.Params(k, 2, 2, n_owners, owner, abi.HM_FORWARD_ONLY if forward_only else 0,
+                                 seed & (2 ** 64 - 1))
+        abi.call("hm_check_params", ctypes.byref(self.params))
+        hint = max(int(positions_hint), 1)
+        auto = max(0, hint.bit_length() - 18)
+        self.hll_p = hll_p
+        self.sample_log2 = auto if sample_log2 is None else sample_log2
+        self.heavy_log2 = auto if heavy_log2 is None else heavy_log2
+        self.registers = torch.zeros(1 << hll_p, dtype=torch.int32, device=self.device)
+        self.positions = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self._tabs = []
+        tables = []
+        for log2 in (self.sample_log2, self.heavy_log2):
+            cap = next_pow2(max(1024, 2 * (hint >> log2) + 256))
+            slots = torch.empty(cap * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
+            status = torch.zeros(1, dtype=torch.int32, device=self.device)
+            self._tabs.append((slots, status))
+            tables.append(abi.Table(slots.data_ptr(), cap, 0, k, status.data_ptr(), None))
+        self.card = abi.Card(self.registers.data_ptr(), hll_p, self.sample_log2, self.heavy_log2, 0,
+                             self.positions.data_ptr(), tables[0], tables[1])
+        self.summary_buf = torch.zeros(5, dtype=torch.int64, device=self.device)
+
+    def reset(self, stream=None):
+        abi.call("hm_card_init", ctypes.byref(self.card), _stream(stream))
+
+    def update(self, packed: Packed, stream=None):
+        r = packed.struct()
+        abi.call("hm_cardinality", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
+                 _stream(stream))
+
+    def summarize(self, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int = 4096, stream=None):
+        """Launch hm_card_summary (asynchronous); result() reads it."""
+        self.heavy_keys = torch.zeros(2 * max(heavy_cap, 1), dtype=torch.int64, device=self.device)
+        self.heavy_cap = heavy_cap
+        abi.call("hm_card_summary", ctypes.byref(self.card), min_depth, heavy_min, self.heavy_keys.data_ptr(),
+                 heavy_cap, self.summary_buf.data_ptr(), _stream(stream))
+
+    def result(self, stream=None) -> CardResult:
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        raw = self.summary_buf.cpu().numpy()
+        est = float(raw[:1].view(np.float64)[0])
+        u = raw.view(np.uint64)
+        n_heavy = int(u[3])
+        hk = self.heavy_keys[: 2 * min(n_heavy, self.heavy_cap)].cpu().numpy().view(np.uint64).reshape(-1, 2)
+        order = np.lexsort((hk[:, 1], hk[:, 0])) if len(hk) else np.zeros(0, np.int64)
+        rc = abi.HM_OK
+        for _, status in self._tabs:
+            if int(status.item()) & abi.HM_ST_TABLE_FULL:
+                rc = abi.HM_ECAPACITY
+        return CardResult(est, int(u[1]), int(u[2]), n_heavy, int(u[4]), self.hll_p, self.sample_log2,
+                          self.heavy_log2, hk[order, 0].copy(), hk[order, 1].copy(), rc)
+
+    def run(self, batches, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int = 4096, stream=None) -> CardResult:
+        self.reset(stream)
+        for p in batches:
+            self.update(p, stream)
+        self.summarize(min_depth, heavy_min, heavy_cap, stream)
+        return self.result(stream)
+
+
+def bloom_fp_rate(bits_per_key: float, n_hash: int) -> float:
+    """False-positive rate of the single-word blocked Bloom filter (every key's n_hash bits in one
+    64-bit word) at its final load: keys per word ~ Poisson(64 / bits_per_key)."""
+    lam = 64.0 / max(bits_per_key, 1e-9)
+    fp, pj = 0.0, np.exp(-lam)
+    for j in range(0, int(lam * 8 + 64)):
+        if j:
+            pj *= lam / j
+        fp += pj * (1.0 - (1.0 - 1.0 / 64) ** (n_hash * j)) ** n_hash
+    return fp
+
+
+def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, table_load: float = 0.5,
+               pass1_launches: int = 1, device=None) -> tuple[int, int, int]:
+    """(table capacity, Bloom words, list capacity) from a cardinality pass, the way the paper
+    sizes its Bloom filter from the HyperLogLog estimate: the filter gets `bloom_bits` bits per
+    distinct k-mer; the table holds the kept k-mers plus the singletons the filter lets through;
+    the first-occurrence list holds at most one entry per distinct k-mer plus the per-launch
+    chunk slack."""
+    d_hi = card.distinct_hi()
+    kept_hi = card.kept_hi()
+    bloom_words = next_pow2(max(64, int(d_hi * bloom_bits / 64)))
+    fp = bloom_fp_rate(bloom_words * 64 / max(d_hi, 1.0), n_hash)
+    capacity = next_pow2(max(1024, int((kept_hi + fp * max(d_hi - kept_hi, 0.0)) / table_load)))
+    lcap = int(d_hi) + list_slack(pass1_launches, device)
+    return capacity, bloom_words, lcap
+
+
 def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = None,
             read_off: np.ndarray | None = None, qcut: int = 20, qual_offset: int = 0, min_depth: int = 2,
             ext_min: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
             bypass: bool = False, checked: bool = False, export_flags: int = 0, capacity: int | None = None,
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
             seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
-            present_filter: bool = True) -> dict:
+            present_filter: bool = True, sizing: str = "card") -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
-    Sizes default to safe bounds derived from the number of windows; on a
-    capacity error the table (or list) is doubled and the run repeated from
+    Sizes not given are planned from a cardinality pass over the reads
+    (sizing="card": HyperLogLog estimate and distinct sample, plan_sizes) or
+    set to worst-case bounds from the number of windows (sizing="bound").  On
+    a capacity error the table (or list) is doubled and the run repeated from
     scratch, which keeps the result exact."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
@@ -269,9 +395,20 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     P = packed.positions(k)
     flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
         (abi.HM_CHECKED if checked else 0)
-    cap = capacity or next_pow2(max(1024, 2 * P))
-    lcap = list_capacity if list_capacity is not None else max(P, 1)
-    bw = bloom_words or next_pow2(max(64, P * 10 // 64))
+    if sizing == "card" and not (capacity and bloom_words and list_capacity is not None):
+        sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
+        card = sk.run([packed], min_depth=min_depth)
+        c_cap, c_bw, c_lcap = plan_sizes(card, n_hash=n_hash, device=dev)
+        del sk
+        if bypass or min_depth == 1:  # every distinct k-mer goes into the table
+            c_cap = next_pow2(max(1024, int(card.distinct_hi() / 0.5)))
+    elif sizing in ("card", "bound"):
+        c_cap, c_lcap, c_bw = next_pow2(max(1024, 2 * P)), max(P, 1), next_pow2(max(64, P * 10 // 64))
+    else:
+        raise ValueError("sizing must be 'card' or 'bound'")
+    cap = capacity or c_cap
+    lcap = list_capacity if list_capacity is not None else c_lcap
+    bw = bloom_words or c_bw
     for _ in range(retries + 1):
         kc = KmerCounter(k, cap, bw, lcap, n_hash=n_hash, min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
                          owner=owner, flags=flags, seed=seed, max_probe=max_probe, present_filter=present_filter,

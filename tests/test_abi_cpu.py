@@ -118,7 +118,8 @@ def test_package_import_is_lazy_and_loud():
 # ---- the ctypes mirror against the C header, compiled by gcc
 
 C_NAMES = {"Reads": "hm_reads_t", "Params": "hm_params_t", "Table": "hm_table_t", "Bloom": "hm_bloom_t",
-           "List": "hm_list_t", "Export": "hm_export_t", "BatchSet": "hm_batch_set_t",
+           "List": "hm_list_t", "Export": "hm_export_t", "Card": "hm_card_t", "CardSummary": "hm_card_summary_t",
+           "BatchSet": "hm_batch_set_t",
            "BatchTuning": "hm_batch_tuning_t", "BatchPlan": "hm_batch_plan_t"}
 
 
