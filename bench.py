@@ -204,10 +204,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full mid workload)")
+    ap.add_argument("--workload", choices=["mid", "mid-heavy"], default="mid",
+                    help="mid: the headline workload; mid-heavy: mid with 2%% satellite arrays (heavy hitters)")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
+    ap.add_argument("--no-heavy", action="store_true",
+                    help="count heavy hitters through the table instead of workgroup-local counters")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
@@ -233,7 +237,7 @@ def main():
     abi.lib()
 
     t0 = time.time()
-    w = synth.mid(scale=args.scale)
+    w = synth.mid(scale=args.scale) if args.workload == "mid" else synth.mid_heavy(scale=args.scale)
     r = w.reads()
     p = w.params
     L, k = r.read_len, p.k
@@ -258,7 +262,8 @@ def main():
                                                       card.sample_log2, card.n_heavy, cap.bit_length() - 1,
                                                       bloom_words.bit_length() - 1, list_cap))
     while True:
-        kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth, device=dev)
+        kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth,
+                              heavy=None if args.no_heavy else card, device=dev)
         out = kmer.Records(int(cap * 0.6), device=dev)
         kc.run([packed], out, fused=True)
         rc = kc.status()
@@ -333,13 +338,14 @@ def main():
 
     # roofline of the dominant kernel (pass 1).  Algorithmic bytes, line granular
     # (one 64-byte line per random access), from the pass's own event counters:
-    #   every occurrence reads its home slot line (64 B);
+    #   every occurrence counted through the table reads its home slot line (64 B) (heavy
+    #   hitters counted in workgroup-local memory touch no table line);
     #   an occurrence counted in pass 1 (hit or insert) writes that line back (64 B);
     #   a Bloom test-and-set reads and writes one line (128 B);
     #   a deferred occurrence appends a 17-byte list entry;
     #   the packed reads stream in once (0.5 B per base).
     st = kc.stats()  # cleared by every step's table init: the last step's counts
-    occ, bloom_tests, deferred = st["occurrences"], st["bloom_tests"], st["deferred"]
+    occ, bloom_tests, deferred = st["occurrences"] - st["heavy_local"], st["bloom_tests"], st["deferred"]
     pass1_bytes = (occ * LINE + (occ - deferred) * LINE + bloom_tests * 2 * LINE + deferred * 17
                    + 0.5 * r.n_bases)
     achieved = pass1_bytes / (stage_ms["pass1"] / 1000) / 1e9
@@ -347,9 +353,9 @@ def main():
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_pass1_fixed_mid_k51_traffic.md"))
-                if args.scale == 1.0 else None,
+                if args.scale == 1.0 and args.workload == "mid" else None,
                 "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
-                "events_per_position": {x: round(v / positions, 4) for x, v in st.items() if x != "reserved"}}
+                "events_per_position": {x: round(v / positions, 4) for x, v in st.items() }}
     if not args.no_probe:
         from paper_1705_11147_amd import roofline as ra
         m = ra.measure(kc.capacity * 64, kinds=("load", "atomic_add", "atomic_or_ret"), n_ops=1 << 28, reps=2,

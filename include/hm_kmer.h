@@ -122,7 +122,10 @@ typedef struct {
 #define HM_STAT_P2_FOUND 6   /* pass 2: entries whose k-mer was in the table */
 #define HM_STAT_CAS 7        /* pass 1: compare-and-swap attempts on packed counters */
 #define HM_STAT_WIDE 8       /* pass 1: occurrences counted in the wide counters */
+#define HM_STAT_HEAVY 9      /* pass 1: occurrences of heavy keys counted in workgroup-local memory */
 #define HM_N_STATS 10
+
+#define HM_MAX_HEAVY 256     /* longest heavy-key list of a table */
 
 /* Open-addressing count table of `capacity` 64-byte slots (power of two). */
 typedef struct {
@@ -132,6 +135,16 @@ typedef struct {
     int32_t k;          /* the k the table is built for (set by the caller) */
     uint32_t *status;   /* device status word */
     uint64_t *stats;    /* optional (may be NULL): HM_N_STATS event counters */
+    /* Optional heavy hitters (section "Parallel k-mer analysis": very frequent
+     * k-mers are accumulated locally, then reduced globally): n_heavy keys as
+     * (key_hi, key_lo) pairs in device memory, e.g. from hm_card_summary.  Pass 1
+     * counts their occurrences in workgroup-local memory and adds each
+     * workgroup's totals to the table once, instead of one atomic per
+     * occurrence on the same slot.  Any keys may be listed (a key that never
+     * occurs is never inserted); the counts are the same either way. */
+    const uint64_t *heavy;
+    uint32_t n_heavy;   /* 0..HM_MAX_HEAVY */
+    uint32_t reserved;
 } hm_table_t;
 
 /* Single-word blocked Bloom filter: n_words 64-bit words (power of two),

@@ -33,6 +33,7 @@ HM_EXPORT_UU_ONLY = 1
 HM_EXPORT_ALL = 2
 HM_EXPORT_CLASSIFY = 4
 HM_EXPORT_SORTED = 8
+HM_MAX_HEAVY = 256
 
 HM_CLS_FORK = 4
 HM_CLS_X = 5
@@ -54,11 +55,12 @@ class Params(ctypes.Structure):
 
 class Table(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_void_p), ("capacity", ctypes.c_uint64), ("max_probe", ctypes.c_uint32),
-                ("k", ctypes.c_int32), ("status", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+                ("k", ctypes.c_int32), ("status", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("heavy", ctypes.c_void_p), ("n_heavy", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 STAT_NAMES = ["occurrences", "hit_first_lookup", "bloom_tests", "deferred", "probe_slots", "p2_entries",
-              "p2_found", "cas_attempts", "wide_counts", "reserved"]
+              "p2_found", "cas_attempts", "wide_counts", "heavy_local"]
 
 
 class Bloom(ctypes.Structure):

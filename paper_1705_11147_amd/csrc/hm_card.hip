@@ -99,18 +99,73 @@ __device__ __forceinline__ void card_end(const CardArgs &c, const uint8_t *s_reg
     if (lane_id() == 0 && x) atomicAdd(c.positions, (unsigned long long)x);
 }
 
+// Fixed-length reads, tiles staged in LDS as in pass 1, but each lane takes a
+// run of kCardRun consecutive windows of one read: the first window's code
+// and reverse complement are extracted from the packed words, and each next
+// window is rolled in from one more base (shift the forward code left and
+// append the base, shift the reverse complement right and insert the
+// complemented base on top).  The extensions are not needed here.
+constexpr int kCardRun = 8;
+
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile,
                                                        int64_t n_tiles) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
-    __shared__ uint64_t s_hq[kTileMaskWords];
     extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers
     uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
     card_begin(c, s_reg32);
     uint32_t npos = 0;
-    fixed_windows<false>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq,
-                         [&](bool act, const Occ &o, int64_t j) { card_window<KW>(c, s_reg, act, o, j, npos); });
+    const int L = a.read_len, k = a.k;
+    const int W = L - k + 1;  // > 0, checked by the host
+    const int runs = (W + kCardRun - 1) / kCardRun;
+    const int kb = 2 * k;
+    const uint64_t mlo = kb >= 64 ? ~0ull : ((1ull << kb) - 1);
+    const uint64_t mhi = kb > 64 ? ((1ull << (kb - 64)) - 1) : 0ull;
+    const int top = kb - 2;  // bit of the newest base in the reverse-complement code
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * reads_per_tile;
+        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
+        const int64_t org = (r0 * L) & ~(int64_t)63;
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)((((r1 * L) + 63) >> 6) - mw0) + 2;
+        __syncthreads();
+        for (int i = threadIdx.x; i < nmw; i += kBlock) s_nm[i] = a.nm[mw0 + i];
+        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        const Words w{s_b2, s_nm, nullptr};
+        const int total = (int)(r1 - r0) * runs;
+        for (int g = threadIdx.x; g < total; g += kBlock) {
+            const int r = g / runs;
+            const int p0 = (g - r * runs) * kCardRun;
+            const int cnt = min(kCardRun, W - p0);
+            const int64_t j0 = (r0 + r) * L - org + p0;  // first window, relative to the tile origin
+            const int64_t jg = (r0 + r) * L + p0;        // and in the read set
+            U128 f = w.window(j0, k);
+            U128 rc = revcomp(f, k);
+            for (int i = 0; i < cnt; ++i) {
+                if (i > 0) {
+                    const uint64_t b = w.code(j0 + i + k - 1);
+                    if (KW == 1) {
+                        f.lo = ((f.lo << 2) | b) & mlo;
+                        rc.lo = (rc.lo >> 2) | ((3 - b) << top);
+                    } else {
+                        f.hi = ((f.hi << 2) | (f.lo >> 62)) & mhi;
+                        f.lo = ((f.lo << 2) | b) & mlo;
+                        rc.lo = (rc.lo >> 2) | (rc.hi << 62);
+                        rc.hi >>= 2;
+                        if (top >= 64) rc.hi |= (3 - b) << (top - 64);
+                        else rc.lo |= (3 - b) << top;
+                    }
+                }
+                if (!w.window_valid(j0 + i, k)) continue;
+                const bool fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
+                Occ o{fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, 4, 4};
+                if (a.n_owners > 1 && owner_of(o.hi, o.lo, a.n_owners) != a.owner) continue;
+                card_window<KW>(c, s_reg, true, o, jg + i, npos);
+            }
+        }
+    }
     card_end(c, s_reg, npos);
 }
 

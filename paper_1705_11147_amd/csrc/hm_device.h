@@ -330,6 +330,9 @@ struct PassArgs {
     uint64_t *present;
     uint64_t present_mask;
     uint32_t present_hash;
+    // heavy hitters of the table (hm_table_t.heavy), counted per workgroup
+    const uint64_t *heavy;
+    uint32_t n_heavy;
 };
 
 // Word index and bit mask of a key in the presence filter (bits independent
@@ -370,17 +373,121 @@ struct ListCursor {
     uint32_t used;  // entries of the chunk handed out (kListChunk: no chunk yet)
 };
 
+// ------------------------------------------------------------------ heavy hitters
+
+// Workgroup-local counters of the table's heavy keys, in dynamic LDS: the
+// keys (2 words each), nine counters per key (no left extension, left A..T,
+// right A..T) and an open-addressing index of key positions at most half full.
+struct HeavyLds {
+    uint64_t *keys;
+    uint32_t *cnt;
+    uint32_t *index;
+    uint32_t imask;
+    uint32_t n;
+};
+constexpr uint32_t kNoHeavy = 0xFFFFFFFFu;
+
+__host__ __device__ inline uint32_t heavy_index_size(uint32_t n) {
+    uint32_t s = 4;
+    while (s < 2 * n) s <<= 1;
+    return s;
+}
+
+// Dynamic LDS bytes of a pass-1 workgroup for n heavy keys.
+__host__ __device__ inline size_t heavy_lds_bytes(uint32_t n) {
+    return n ? (size_t)n * (16 + 36) + 4 * (size_t)heavy_index_size(n) : 0;
+}
+
+// Load the heavy keys into LDS, clear their counters and build the index.
+// Called by every thread of the workgroup (contains barriers).
+__device__ __forceinline__ HeavyLds heavy_setup(const PassArgs &a, uint64_t *smem) {
+    HeavyLds hv;
+    hv.n = a.n_heavy;
+    hv.keys = smem;
+    hv.cnt = reinterpret_cast<uint32_t *>(smem + 2 * hv.n);
+    hv.index = hv.cnt + 9 * hv.n;
+    const uint32_t isz = heavy_index_size(hv.n);
+    hv.imask = isz - 1;
+    for (uint32_t i = threadIdx.x; i < 2 * hv.n; i += kBlock) hv.keys[i] = a.heavy[i];
+    for (uint32_t i = threadIdx.x; i < 9 * hv.n; i += kBlock) hv.cnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < isz; i += kBlock) hv.index[i] = kNoHeavy;
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < hv.n; e += kBlock) {
+        uint32_t i = (uint32_t)(key_hash(hv.keys[2 * e], hv.keys[2 * e + 1], a.seed) >> 32) & hv.imask;
+        while (atomicCAS(&hv.index[i], kNoHeavy, e) != kNoHeavy) i = (i + 1) & hv.imask;
+    }
+    __syncthreads();
+    return hv;
+}
+
+// Count the occurrence locally if its key is a heavy key (h = its table hash).
+__device__ __forceinline__ bool heavy_count(const HeavyLds &hv, uint64_t h, const Occ &o) {
+    uint32_t i = (uint32_t)(h >> 32) & hv.imask;
+    while (true) {
+        const uint32_t e = hv.index[i];
+        if (e == kNoHeavy) return false;
+        if (hv.keys[2 * e] == o.hi && hv.keys[2 * e + 1] == o.lo) {
+            atomicAdd(&hv.cnt[9 * e + (o.left < 4 ? 1 + o.left : 0)], 1u);
+            if (o.right < 4) atomicAdd(&hv.cnt[9 * e + 5 + o.right], 1u);
+            return true;
+        }
+        i = (i + 1) & hv.imask;
+    }
+}
+
+// Add the workgroup's heavy-key counts to the table: find (or insert) each
+// key's slot once and add every non-zero counter to its wide counters.
+// Called by every thread of the workgroup (contains a barrier).
+template <int KW, bool CHECKED>
+__device__ __forceinline__ void heavy_flush(const PassArgs &a, const HeavyLds &hv) {
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < hv.n; e += kBlock) {
+        const uint32_t *c = hv.cnt + 9 * e;
+        uint32_t any = 0;
+        for (int q = 0; q < 9; ++q) any |= c[q];
+        if (!any) continue;
+        const uint64_t hi = hv.keys[2 * e], lo = hv.keys[2 * e + 1];
+        const uint64_t h = key_hash(hi, lo, a.seed);
+        uint64_t A, B;
+        slot_words<KW>(hi, lo, A, B);
+        const Probe pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, true);
+        if (pr.slot < 0) {
+            atomicOr(a.status, HM_ST_TABLE_FULL);
+            continue;
+        }
+        if (pr.inserted && a.present) {
+            uint64_t pw, pm;
+            present_bits(h, a.present_mask, a.present_hash, pw, pm);
+            __hip_atomic_fetch_or(a.present + pw, pm, RLX, AGT);
+        }
+        Slot *s = a.slots + pr.slot;
+        for (int q = 0; q < 9; ++q) {
+            if (!c[q]) continue;
+            uint32_t *dst = q == 0 ? &s->nl : (q < 5 ? &s->tl[q - 1] : &s->tr[q - 5]);
+            const uint32_t old = __hip_atomic_fetch_add(dst, c[q], RLX, AGT);
+            if (CHECKED && old + c[q] < old) atomicOr(a.status, HM_ST_OVERFLOW);
+        }
+    }
+}
+
 // Per-occurrence body of pass 1.  `act` lanes carry an occurrence; every lane
-// of the wave must call it (list appends are aggregated per wave).
-template <int KW, bool CHECKED, uint32_t CHUNK = kListChunk>
-__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur, Stats &st) {
+// of the wave must call it (list appends are aggregated per wave).  With
+// HEAVY, occurrences of the table's heavy keys are counted in `hv` instead.
+template <int KW, bool CHECKED, uint32_t CHUNK = kListChunk, bool HEAVY = false>
+__device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur, Stats &st,
+                                          const HeavyLds *hv = nullptr) {
     // The table is probed first: an occurrence whose k-mer is already there is
     // counted without touching the Bloom filter.  Only absent k-mers test and
     // set their Bloom bits; a k-mer the filter has seen is inserted and this
     // occurrence counted, an unseen one goes to the first-occurrence list.
     bool deferred = false;
+    const uint64_t h = act ? key_hash(o.hi, o.lo, a.seed) : 0;
+    if (HEAVY && act && heavy_count(*hv, h, o)) {
+        st.v[HM_STAT_OCC] += 1;
+        st.v[HM_STAT_HEAVY] += 1;
+        act = false;
+    }
     if (act) {
-        const uint64_t h = key_hash(o.hi, o.lo, a.seed);
         uint64_t A, B;
         slot_words<KW>(o.hi, o.lo, A, B);
         Probe pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, a.bypass != 0);

@@ -68,30 +68,41 @@ namespace {
 
 using namespace hm;
 
-// Pass 1 over fixed-length reads: tiles of whole reads staged in LDS.
-template <int KW, bool CHECKED>
+// Pass 1 over fixed-length reads: tiles of whole reads staged in LDS.  HEAVY:
+// the table's heavy keys are counted in dynamic LDS and flushed at the end.
+template <int KW, bool CHECKED, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t reads_per_tile, int64_t n_tiles) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
+    extern __shared__ uint64_t s_heavy[];
+    HeavyLds hv{};
+    if (HEAVY) hv = heavy_setup(a, s_heavy);
     ListCursor cur{0, kListChunk};
     Stats st = {};
-    fixed_windows<true>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq,
-                        [&](bool act, const Occ &o, int64_t) { pass1_occ<KW, CHECKED>(a, act, o, cur, st); });
+    fixed_windows<true>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv);
+    });
     list_close(a, cur);
+    if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
     stats_flush(a.stats, st);
 }
 
 // Pass 1 over variable-length reads (read_off given).
-template <int KW, bool CHECKED>
+template <int KW, bool CHECKED, bool HEAVY>
 __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tiles) {
     __shared__ int64_t s_off[kVarReads + 1];
     __shared__ int64_t s_pre[kVarReads + 1];
+    extern __shared__ uint64_t s_heavy[];
+    HeavyLds hv{};
+    if (HEAVY) hv = heavy_setup(a, s_heavy);
     ListCursor cur{0, kListChunk};
     Stats st = {};
-    var_windows<true>(a, n_tiles, s_off, s_pre,
-                      [&](bool act, const Occ &o, int64_t) { pass1_occ<KW, CHECKED>(a, act, o, cur, st); });
+    var_windows<true>(a, n_tiles, s_off, s_pre, [&](bool act, const Occ &o, int64_t) {
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv);
+    });
     list_close(a, cur);
+    if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
     stats_flush(a.stats, st);
 }
 
@@ -348,6 +359,10 @@ static int make_args(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, h
     a.max_probe = (uint32_t)(mp < t->capacity ? mp : t->capacity);
     a.status = t->status;
     a.stats = reinterpret_cast<unsigned long long *>(t->stats);
+    if (t->n_heavy > HM_MAX_HEAVY) return fail(HM_EINVAL, "table: n_heavy must be <= %d", HM_MAX_HEAVY);
+    if (t->n_heavy && !t->heavy) return fail(HM_EINVAL, "table: heavy keys are NULL");
+    a.heavy = t->heavy;
+    a.n_heavy = t->n_heavy;
     return HM_OK;
 }
 
@@ -359,23 +374,31 @@ int hm_bloom_insert(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, hm
     if (r->n_reads == 0) return HM_OK;
     const bool two = p->k >= 32;
     const bool checked = (p->flags & HM_CHECKED) != 0;
+    const bool heavy = a.n_heavy > 0;
+    const size_t lds = heavy_lds_bytes(a.n_heavy);
     const int grid_cap = device_cus() * 8;
     if (!r->read_off && r->read_len <= kTileBases - 64) {
         if (r->read_len < p->k) return HM_OK;  // no windows
         const int32_t rpt = kTileBases / r->read_len;
         const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
         const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
-#define LAUNCH_FIXED(KW, CH) hipLaunchKernelGGL((k_pass1_fixed<KW, CH>), g, dim3(kBlock), 0, s, a, rpt, n_tiles)
-        if (two) { if (checked) LAUNCH_FIXED(2, true); else LAUNCH_FIXED(2, false); }
-        else { if (checked) LAUNCH_FIXED(1, true); else LAUNCH_FIXED(1, false); }
+#define LAUNCH_FIXED(KW, CH, HV) \
+    hipLaunchKernelGGL((k_pass1_fixed<KW, CH, HV>), g, dim3(kBlock), lds, s, a, rpt, n_tiles)
+#define LAUNCH_FIXED2(KW, CH) \
+    do { if (heavy) LAUNCH_FIXED(KW, CH, true); else LAUNCH_FIXED(KW, CH, false); } while (0)
+        if (two) { if (checked) LAUNCH_FIXED2(2, true); else LAUNCH_FIXED2(2, false); }
+        else { if (checked) LAUNCH_FIXED2(1, true); else LAUNCH_FIXED2(1, false); }
+#undef LAUNCH_FIXED2
 #undef LAUNCH_FIXED
     } else {
         if (!r->read_off) return fail(HM_EINVAL, "reads longer than %d bases need read_off", kTileBases - 64);
         const int64_t n_tiles = (r->n_reads + kVarReads - 1) / kVarReads;
         const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
-#define LAUNCH_VAR(KW, CH) hipLaunchKernelGGL((k_pass1_var<KW, CH>), g, dim3(kBlock), 0, s, a, n_tiles)
-        if (two) { if (checked) LAUNCH_VAR(2, true); else LAUNCH_VAR(2, false); }
-        else { if (checked) LAUNCH_VAR(1, true); else LAUNCH_VAR(1, false); }
+#define LAUNCH_VAR(KW, CH, HV) hipLaunchKernelGGL((k_pass1_var<KW, CH, HV>), g, dim3(kBlock), lds, s, a, n_tiles)
+#define LAUNCH_VAR2(KW, CH) do { if (heavy) LAUNCH_VAR(KW, CH, true); else LAUNCH_VAR(KW, CH, false); } while (0)
+        if (two) { if (checked) LAUNCH_VAR2(2, true); else LAUNCH_VAR2(2, false); }
+        else { if (checked) LAUNCH_VAR2(1, true); else LAUNCH_VAR2(1, false); }
+#undef LAUNCH_VAR2
 #undef LAUNCH_VAR
     }
     HM_LAUNCH_CHECK("hm_bloom_insert");

@@ -165,7 +165,10 @@ class KmerCounter:
 
     def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,
                  min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
-                 seed: int = DEFAULT_SEED, max_probe: int = 0, present_filter: bool = True, device="cuda"):
+                 seed: int = DEFAULT_SEED, max_probe: int = 0, present_filter: bool = True, heavy=None,
+                 device="cuda"):
+        """heavy: optional heavy-hitter keys, an (n, 2) array of (key_hi, key_lo) or a CardResult;
+        pass 1 counts them in workgroup-local memory (at most abi.HM_MAX_HEAVY)."""
         self.device = torch.device(device)
         self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner, flags,
                                  seed & (2 ** 64 - 1))
@@ -175,8 +178,16 @@ class KmerCounter:
         self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
         self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.stats_buf = torch.zeros(10, dtype=torch.int64, device=self.device)
+        if isinstance(heavy, CardResult):  # any subset of the heavy hitters gives the same counts
+            n = min(len(heavy.heavy_hi), abi.HM_MAX_HEAVY)
+            heavy = np.stack([heavy.heavy_hi[:n], heavy.heavy_lo[:n]], axis=1) if n else None
+        hk = np.zeros((0, 2), np.uint64) if heavy is None else np.asarray(heavy, dtype=np.uint64).reshape(-1, 2)
+        if len(hk) > abi.HM_MAX_HEAVY:
+            raise ValueError("at most %d heavy keys" % abi.HM_MAX_HEAVY)
+        self.heavy_keys = torch.from_numpy(hk.view(np.int64).reshape(-1).copy()).to(self.device) if len(hk) else None
         self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr(),
-                               self.stats_buf.data_ptr())
+                               self.stats_buf.data_ptr(),
+                               self.heavy_keys.data_ptr() if self.heavy_keys is not None else None, len(hk), 0)
         self.bloom_words = next_pow2(bloom_words) if not self.bypass else 1
         self.bloom_buf = torch.empty(self.bloom_words, dtype=torch.int64, device=self.device)
         self.bloom = abi.Bloom(self.bloom_buf.data_ptr(), self.bloom_words, n_hash)
@@ -379,14 +390,15 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             bypass: bool = False, checked: bool = False, export_flags: int = 0, capacity: int | None = None,
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
             seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
-            present_filter: bool = True, sizing: str = "card") -> dict:
+            present_filter: bool = True, sizing: str = "card", heavy: bool = True) -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
     Sizes not given are planned from a cardinality pass over the reads
     (sizing="card": HyperLogLog estimate and distinct sample, plan_sizes) or
     set to worst-case bounds from the number of windows (sizing="bound").  On
     a capacity error the table (or list) is doubled and the run repeated from
-    scratch, which keeps the result exact."""
+    scratch, which keeps the result exact.  heavy: count the heavy hitters the
+    cardinality pass finds in workgroup-local memory (sizing="card" only)."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
     q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
@@ -395,7 +407,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     P = packed.positions(k)
     flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
         (abi.HM_CHECKED if checked else 0)
-    if sizing == "card" and not (capacity and bloom_words and list_capacity is not None):
+    card = None
+    if sizing == "card" and (heavy or not (capacity and bloom_words and list_capacity is not None)):
         sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
         card = sk.run([packed], min_depth=min_depth)
         c_cap, c_bw, c_lcap = plan_sizes(card, n_hash=n_hash, device=dev)
@@ -412,6 +425,7 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     for _ in range(retries + 1):
         kc = KmerCounter(k, cap, bw, lcap, n_hash=n_hash, min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
                          owner=owner, flags=flags, seed=seed, max_probe=max_probe, present_filter=present_filter,
+                         heavy=card if heavy else None,
                          device=dev)
         out = Records(kc.capacity, device=dev)
         kc.run([packed], out, flags=export_flags, fused=fused)
@@ -421,6 +435,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             res["digest"] = out.digest_words()
             res["positions"] = P
             res["capacity"] = kc.capacity
+            res["stats"] = kc.stats()
+            res["n_heavy"] = kc.table.n_heavy
             return res
         if rc == abi.HM_ECAPACITY:
             st = int(kc.status_buf.item())

@@ -12,6 +12,14 @@ path on its own HIP stream:
 Its table and export stay device-resident until the job completes.  Latency
 is completion time minus arrival time.
 
+A backend with `plans` set (and `plan`, `planned`, `finish_plan`, `discard`,
+`plan_footprint`)
+sizes each job the way the paper sizes its Bloom filter: before admission the
+job at the head of the queue is copied to the device, packed and run through
+the cardinality pass (HyperLogLog estimate and distinct sample) on its own
+stream, holding only those buffers; its exact footprint then decides when it
+is admitted.  One job plans at a time, and planned jobs keep FIFO order.
+
 The scheduler is independent of the device: `GpuBackend` runs jobs through
 the C ABI, and tests drive the same scheduler with a fake backend and a
 virtual clock.
@@ -75,17 +83,22 @@ class Scheduler:
 
     def run(self, jobs: list[Job], clock=None, max_retries: int = 3) -> list[Record]:
         clock = clock or WallClock()
+        be = self.backend
+        planner = bool(getattr(be, "plans", False))
+        first_need = be.plan_footprint if planner else be.footprint
         order = sorted(range(len(jobs)), key=lambda i: jobs[i].arrival)
         recs = {j.id: Record(j.id, j.arrival) for j in jobs}
         for j in jobs:
-            if self.backend.footprint(j) > self.budget:
+            if first_need(j) > self.budget:
                 raise ValueError("job %d needs %d bytes, more than the whole budget %d" % (
-                    j.id, self.backend.footprint(j), self.budget))
+                    j.id, first_need(j), self.budget))
         nxt = 0                      # next job (in arrival order) not yet queued
         queue: list[Job] = []
         running = {}                 # job id -> (handle, bytes)
         used = 0
-        while nxt < len(order) or queue or running:
+        planning = None              # (job, plan handle, bytes held) of the job being planned
+        ready = None                 # (job, plan handle, bytes held): planned, waiting for admission
+        while nxt < len(order) or queue or running or planning or ready:
             now = clock.now()
             while nxt < len(order) and jobs[order[nxt]].arrival <= now:
                 queue.append(jobs[order[nxt]])
@@ -93,12 +106,12 @@ class Scheduler:
             # completions first: they free slots and memory for admissions
             for jid in list(running):
                 h, b = running[jid]
-                if self.backend.poll(h):
-                    status, result = self.backend.finish(h)
+                if be.poll(h):
+                    status, result = be.finish(h)
                     used -= b
                     del running[jid]
                     r = recs[jid]
-                    if status == "retry" and r.retries < max_retries and self.backend.footprint(result) <= self.budget:
+                    if status == "retry" and r.retries < max_retries and first_need(result) <= self.budget:
                         r.retries += 1
                         queue.insert(0, result)  # the backend returns the resized job
                         continue
@@ -107,19 +120,53 @@ class Scheduler:
                     r.done = clock.now()
                     r.status = 0 if status == "ok" else status
                     r.result = result
+            if planning is not None and be.planned(planning[1]):
+                j, h, pb = planning
+                ready = (be.finish_plan(h), h, pb)
+                planning = None
             # admission: FIFO, head of line waits for memory
-            while queue and len(running) < self.max_slots:
+            while len(running) < self.max_slots:
+                if planner:
+                    if ready is None:
+                        if planning is None and queue:  # plan the head of the queue
+                            j = queue[0]
+                            pb = be.plan_footprint(j)
+                            if used + pb > self.budget:
+                                break
+                            queue.pop(0)
+                            if np.isnan(recs[j.id].admitted):
+                                recs[j.id].admitted = clock.now()
+                            planning = (j, be.plan(j), pb)
+                            used += pb
+                        break
+                    j, h, pb = ready
+                    b = be.footprint(j)
+                    if b > self.budget:  # the planned job cannot fit at all
+                        be.discard(h)
+                        used -= pb
+                        ready = None
+                        recs[j.id].done = clock.now()
+                        recs[j.id].status = "capacity"
+                        continue
+                    if used - pb + b > self.budget:
+                        break
+                    ready = None
+                    running[j.id] = (be.start(j, h), b)
+                    used += b - pb
+                    continue
+                if not queue:
+                    break
                 j = queue[0]
-                b = self.backend.footprint(j)
+                b = be.footprint(j)
                 if used + b > self.budget:
                     break
                 queue.pop(0)
                 if np.isnan(recs[j.id].admitted):
                     recs[j.id].admitted = clock.now()
-                running[j.id] = (self.backend.start(j), b)
+                running[j.id] = (be.start(j), b)
                 used += b
             self.trace.append((now, len(queue), len(running), used))
-            if running or queue:
+            if running or queue or planning or ready:
                 clock.sleep(self.poll_s)
             elif nxt < len(order):
                 clock.sleep(max(0.0, jobs[order[nxt]].arrival - clock.now()))
@@ -150,18 +197,22 @@ def summarize(recs: list[Record], positions: dict, trace=None) -> dict:
 
 
 class GpuBackend:
-    """Runs each job through the C ABI on its own HIP stream."""
+    """Runs each job through the C ABI on its own HIP stream.  With plan=True
+    (default) each job is sized by a cardinality pass before admission; with
+    plan=False by the job's own size hints (distinct_est, kept_est)."""
 
     def __init__(self, k: int, qcut: int = 20, min_depth: int = 2, table_load: float = 0.45, bloom_bits: float = 12.0,
-                 n_hash: int = 4, device="cuda"):
+                 n_hash: int = 4, device="cuda", plan: bool = True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.k, self.qcut, self.min_depth = k, qcut, min_depth
         self.table_load, self.bloom_bits, self.n_hash = table_load, bloom_bits, n_hash
         self._streams = []
+        self.plans = plan  # the scheduler plans jobs (cardinality pass) before admission
 
-    def sizes(self, j: Job):
+    # ---- sizes
+    def _hint_sizes(self, j: Job):
         from .kmer import next_pow2
         cap = next_pow2(max(1024, int(j.meta.get("kept", j.kept_est) / self.table_load)))
         bw = next_pow2(max(64, int(j.distinct_est * self.bloom_bits / 64)))
@@ -169,28 +220,91 @@ class GpuBackend:
         ocap = int(min(cap, j.meta.get("out", j.meta.get("kept", j.kept_est) * 1.3 + 1024)))
         return cap, bw, lcap, ocap
 
+    def sizes(self, j: Job):
+        return j.meta["plan"] if "plan" in j.meta else self._hint_sizes(j)
+
+    @staticmethod
+    def _reads_bytes(j: Job) -> int:
+        return 2 * j.n_bases + j.n_bases // 2 + 64  # ASCII + Phred, packed reads
+
+    def _sketch_bytes(self, j: Job) -> int:
+        from .kmer import next_pow2
+        hint = max(j.n_bases, 1)
+        cap = next_pow2(max(1024, 2 * (hint >> max(0, hint.bit_length() - 18)) + 256))
+        return 2 * 64 * cap + 4 * (1 << 14)
+
+    def plan_footprint(self, j: Job) -> int:
+        return self._reads_bytes(j) + self._sketch_bytes(j)
+
     def footprint(self, j: Job) -> int:
         cap, bw, lcap, ocap = self.sizes(j)
-        return 2 * j.n_bases + j.n_bases // 2 + 64 * cap + 8 * bw + 17 * lcap + 54 * ocap
+        return self._reads_bytes(j) + 64 * cap + cap // 2 + 8 * bw + 17 * lcap + 54 * ocap
 
     def _stream(self):
         return self._streams.pop() if self._streams else self.torch.cuda.Stream(device=self.device)
 
-    def start(self, j: Job):
+    # ---- planning: reads to the device, pack, cardinality pass
+    def _upload(self, j: Job, st):
         from . import kmer
         torch = self.torch
-        st = self._stream()
-        cap, bw, lcap, ocap = self.sizes(j)
         ascii_h, qual_h = j.payload
         with torch.cuda.stream(st):
             a = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
             q = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
             a.copy_(ascii_h, non_blocking=True)
             q.copy_(qual_h, non_blocking=True)
-            kc = kmer.KmerCounter(self.k, cap, bw, lcap, n_hash=self.n_hash, min_depth=self.min_depth,
-                                  device=self.device)
-            out = kmer.Records(ocap, device=self.device)
             packed = kmer.pack_reads(a, q, read_len=j.read_len, qcut=self.qcut, stream=st)
+        return a, q, packed
+
+    def plan(self, j: Job):
+        from . import kmer
+        torch = self.torch
+        st = self._stream()
+        bufs = self._upload(j, st)
+        with torch.cuda.stream(st):
+            sk = kmer.CardSketch(self.k, j.n_bases, device=self.device)
+            sk.reset(st)
+            sk.update(bufs[2], st)
+            sk.summarize(min_depth=self.min_depth, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"job": j, "stream": st, "event": ev, "sketch": sk, "bufs": bufs}
+
+    def planned(self, h) -> bool:
+        return h["event"].query()
+
+    def finish_plan(self, h) -> Job:
+        """The planned job, with table / filter / list / output sizes from its cardinality pass
+        (doubled per earlier capacity retry)."""
+        from . import kmer
+        j = h["job"]
+        card = h.pop("sketch").result(h["stream"])
+        cap, bw, lcap = kmer.plan_sizes(card, n_hash=self.n_hash, bloom_bits=self.bloom_bits,
+                                        table_load=self.table_load, device=self.device)
+        cap *= j.meta.get("grow_table", 1)
+        lcap *= j.meta.get("grow_list", 1)
+        ocap = int(min(cap, card.kept_hi() * 1.3 + 1024) * j.meta.get("grow_out", 1))
+        meta = dict(j.meta, plan=(cap, bw, lcap, ocap), card=card)
+        return Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est, j.payload, meta)
+
+    def discard(self, h):
+        self._streams.append(h["stream"])
+        h.clear()
+
+    # ---- the counting passes
+    def start(self, j: Job, plan_handle=None):
+        from . import kmer
+        torch = self.torch
+        cap, bw, lcap, ocap = self.sizes(j)
+        if plan_handle is not None:
+            st, (a, q, packed) = plan_handle["stream"], plan_handle["bufs"]
+        else:
+            st = self._stream()
+            a, q, packed = self._upload(j, st)
+        with torch.cuda.stream(st):
+            kc = kmer.KmerCounter(self.k, cap, bw, lcap, n_hash=self.n_hash, min_depth=self.min_depth,
+                                  heavy=j.meta.get("card"), device=self.device)
+            out = kmer.Records(ocap, device=self.device)
             kc.run([packed], out, stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
@@ -210,13 +324,16 @@ class GpuBackend:
         elif rc in (abi.HM_ECAPACITY, abi.HM_EOUTPUT):
             # too small for this job: rerun from scratch with the structure that overflowed doubled
             s = int(kc.status_buf.item())
-            meta = dict(j.meta)
+            meta = {x: v for x, v in j.meta.items() if x not in ("plan", "card")}
             if s & abi.HM_ST_TABLE_FULL:
                 meta["kept"] = 2 * meta.get("kept", j.kept_est)
+                meta["grow_table"] = 2 * meta.get("grow_table", 1)
             if s & abi.HM_ST_LIST_FULL:
                 meta["list"] = 2 * meta.get("list", j.distinct_est * 1.2)
+                meta["grow_list"] = 2 * meta.get("grow_list", 1)
             if rc == abi.HM_EOUTPUT:
                 meta["out"] = int(out.n_out.item() * 1.1) + 1024
+                meta["grow_out"] = 2 * meta.get("grow_out", 1)
             status, result = "retry", Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est,
                                           j.payload, meta)
         else:

@@ -101,6 +101,28 @@ def add_interspersed_repeats(g: np.ndarray, n_fam: int, min_len: int, max_len: i
                                               int(target), seed))
 
 
+def add_satellites(g: np.ndarray, arrays: list[tuple[bytes, float, float]], seed: int) -> int:
+    """Overwrite stretches of the genome with tandem satellite arrays: for each
+    (motif, fraction of the genome, per-base divergence) one array of that
+    length tiles the motif from a random start, with independent substitutions
+    at the given rate.  Returns the bases written."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(77,)))
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    done = 0
+    for motif, frac, div in arrays:
+        n = int(frac * g.size)
+        if n <= 0:
+            continue
+        m = np.frombuffer(motif, np.uint8)
+        arr = np.resize(m, n).copy()
+        hit = rng.random(n) < div
+        arr[hit] = acgt[(np.searchsorted(acgt, arr[hit]) + rng.integers(1, 4, int(hit.sum()))) % 4]
+        s = int(rng.integers(0, g.size - n))
+        g[s:s + n] = arr
+        done += n
+    return done
+
+
 @dataclass
 class Reads:
     """Fixed-length reads, row-major: ascii[n_reads * read_len], qual likewise
@@ -211,6 +233,22 @@ def mid(scale: float = 1.0) -> Workload:
     n = int(round(30 * G / 150))
     return Workload("mid-100Mbp-30x-k51", Params(k=51), g, np.array([0, G]), 150, n, 0.005, True, seed,
                     {"G": G, "coverage": 30})
+
+
+def mid_heavy(scale: float = 1.0) -> Workload:
+    """The mid workload with 2% of the genome replaced by tandem satellite
+    arrays, so that a few k-mers hold millions of windows (the heavy hitters
+    of section "Parallel k-mer analysis"): a telomere-like (TTAGGG)n and an
+    (AATGG)n array at 0.5% each, a poly-A and a (CA)n microsatellite at 0.25%
+    each (all 0.2% diverged), and a 171 bp monomer array at 0.5% diverged 1%.
+    Same read count, length, errors and k as mid."""
+    w = mid(scale)
+    rng = np.random.default_rng(np.random.SeedSequence(seed_for(1), spawn_key=(171,)))
+    monomer = rng.choice(np.frombuffer(b"ACGT", np.uint8), 171).tobytes()
+    add_satellites(w.genome, [(b"TTAGGG", 0.005, 0.002), (b"AATGG", 0.005, 0.002), (b"A", 0.0025, 0.002),
+                              (b"CA", 0.0025, 0.002), (monomer, 0.005, 0.01)], seed_for(1))
+    w.name = "mid-heavy-100Mbp-30x-k51-2pct-satellite"
+    return w
 
 
 def human_share(scale: float = 1.0, batch_reads: int = 64_000_000) -> Workload:

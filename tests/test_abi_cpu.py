@@ -168,3 +168,13 @@ def test_sorted_export_scratch_and_rejections(L):
     assert L.hm_export_table(ctypes.byref(t), S, ctypes.byref(ex(cap=1 << 32, work=4096, nbytes=1 << 62)),
                              None) == abi.HM_EINVAL  # indices are 32-bit
     assert "SORTED" in abi.last_error()
+
+
+def test_heavy_list_rejections(L):
+    t = abi.Table(64, 1024, 0, 31, 64, None, None, abi.HM_MAX_HEAVY + 1, 0)
+    r = abi.Reads(8, 8, 8, None, 1, 100, 100)
+    p = P(k=31, flags=abi.HM_BLOOM_BYPASS)
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(p), None, ctypes.byref(t), None, None) == abi.HM_EINVAL
+    t = abi.Table(64, 1024, 0, 31, 64, None, None, 3, 0)  # keys NULL
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(p), None, ctypes.byref(t), None, None) == abi.HM_EINVAL
+    assert "heavy" in abi.last_error()

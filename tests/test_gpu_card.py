@@ -142,3 +142,24 @@ def test_card_sizing_in_analyze():
     assert_tables_equal(got, exp, "card-sized mid/200")
     # the plan is not the worst-case bound: the table is at most 1/4 of 2 slots per window
     assert got["capacity"] <= kmer.next_pow2(2 * got["positions"]) // 4
+
+
+@pytest.mark.parametrize("k,L,fwd", [(1, 40, False), (21, 100, False), (31, 150, False), (33, 150, False),
+                                     (51, 150, False), (63, 64, False), (63, 300, False), (32, 100, True),
+                                     (2, 30, True)])
+def test_card_fixed_length_all_widths(k, L, fwd):
+    """Fixed-length reads (the LDS-tiled path that rolls consecutive windows) with N bases, every
+    key width, forward-only even k; read lengths with W a multiple of the run and not."""
+    rng = np.random.default_rng(k * 1000 + L)
+    n = max(50, 400_000 // L)
+    g = rng.choice(np.frombuffer(b"ACGT", np.uint8), 50_000)
+    st = rng.integers(0, g.size - L, n)
+    ascii = np.concatenate([g[s:s + L] for s in st])
+    ascii[rng.random(ascii.size) < 0.003] = ord("N")
+    e = rng.random(ascii.size) < 0.01
+    ascii[e] = rng.choice(np.frombuffer(b"ACGT", np.uint8), int(e.sum()))
+    off = np.arange(n + 1, dtype=np.int64) * L
+    sk, got = gpu_card(ascii, off, k, read_len=L, hll_p=12, sample_log2=3, heavy_log2=4, heavy_min=4,
+                       forward_only=fwd)
+    exp = oracle_card(ascii, off, k, sk, heavy_min=4, forward_only=fwd)
+    assert_card_equal(sk, got, exp, "fixed k=%d L=%d" % (k, L))

@@ -113,3 +113,74 @@ def test_retry_and_rejection():
     recs = Scheduler(FakeBackend(clock), 30, 2, poll_s=1e-3).run(
         [Job(0, 0.0, 20, 150, 1, 1, None, {"dur": 0.1, "fail_once": True})], clock=clock)
     assert recs[0].status == "capacity"
+
+
+class PlanningBackend(FakeBackend):
+    """Planning takes meta['plan_dur'] seconds and holds n_bases bytes; the planned job then
+    needs meta['phase2'] times n_bases in all (a retry doubles it)."""
+    plans = True
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.planning_now = 0
+        self.max_planning = 0
+        self.events = []
+
+    def plan_footprint(self, j):
+        return j.n_bases
+
+    def plan(self, j):
+        self.planning_now += 1
+        self.max_planning = max(self.max_planning, self.planning_now)
+        self.events.append(("plan", j.id, self.clock.now()))
+        return {"job": j, "end": self.clock.now() + j.meta.get("plan_dur", 0.01)}
+
+    def planned(self, h):
+        return self.clock.now() >= h["end"]
+
+    def finish_plan(self, h):
+        self.planning_now -= 1
+        j = h["job"]
+        return Job(j.id, j.arrival, j.n_bases, j.read_len, 1, 1, None, dict(j.meta, planned=True))
+
+    def discard(self, h):
+        pass
+
+    def footprint(self, j):
+        assert j.meta.get("planned"), "admitted before planning"
+        return j.n_bases * j.meta.get("phase2", 2) * j.meta.get("grow", 1)
+
+    def start(self, j, h=None):
+        self.events.append(("start", j.id, self.clock.now()))
+        return super().start(j)
+
+
+def test_planning_before_admission():
+    clock = VirtualClock()
+    be = PlanningBackend(clock)
+    jobs = [Job(i, 0.01 * i, 10 + (i % 3) * 5, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.005, "phase2": 3})
+            for i in range(40)]
+    jobs[7].meta["fail_once"] = True
+    sch = Scheduler(be, budget_bytes=120, max_slots=4, poll_s=1e-3)
+    recs = sch.run(jobs, clock=clock)
+    assert all(r.status == 0 for r in recs) and recs[7].retries == 1
+    assert be.max_planning == 1                      # one job plans at a time
+    assert max(t[3] for t in sch.trace) <= 120        # planning buffers count against the budget
+    first_start = {}
+    for e in be.events:
+        if e[0] == "start":
+            first_start.setdefault(e[1], e[2])
+    times = [first_start[i] for i in range(len(jobs))]
+    assert times == sorted(times)                     # first admissions in arrival order
+    for e in be.events:                               # every start comes after that job's planning
+        if e[0] == "start":
+            assert any(p[0] == "plan" and p[1] == e[1] and p[2] <= e[2] for p in be.events)
+
+
+def test_planned_job_too_large_is_rejected():
+    clock = VirtualClock()
+    be = PlanningBackend(clock)
+    jobs = [Job(0, 0.0, 40, 150, 1, 1, None, {"dur": 0.05, "phase2": 4}),  # 160 > 100 after planning
+            Job(1, 0.0, 10, 150, 1, 1, None, {"dur": 0.05, "phase2": 2})]
+    recs = Scheduler(be, budget_bytes=100, max_slots=2, poll_s=1e-3).run(jobs, clock=clock)
+    assert recs[0].status == "capacity" and recs[1].status == 0
