@@ -53,7 +53,8 @@ class SetSpec:
 
 
 class _SetBuffers:
-    def __init__(self, spec: SetSpec, k: int, params: dict, tuning: Tuning, device):
+    def __init__(self, spec: SetSpec, k: int, params: dict, tuning: Tuning, device, plan: bool = True, qcut: int = 20,
+                 qual_offset: int = 0):
         self.spec = spec
         n_bases = spec.n_reads * spec.read_len
         L = abi.lib()
@@ -61,12 +62,26 @@ class _SetBuffers:
         self.nm = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
         self.hq = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
         bypass = params.get("min_depth", 2) == 1 or bool(params.get("flags", 0) & abi.HM_BLOOM_BYPASS)
-        keys = spec.distinct_est if bypass else spec.kept_est  # bypass keeps every distinct k-mer
+        if plan:  # sizes from a cardinality pass over the set's own reads
+            kmer.pack_reads(spec.ascii, spec.qual, read_len=spec.read_len, qcut=qcut, qual_offset=qual_offset,
+                            out=self.packed())
+            sk = kmer.CardSketch(k, spec.n_reads * max(spec.read_len - k + 1, 0),
+                                 n_owners=params.get("n_owners", 1), owner=params.get("owner", 0),
+                                 forward_only=bool(params.get("flags", 0) & abi.HM_FORWARD_ONLY),
+                                 seed=params.get("seed", kmer.DEFAULT_SEED), device=device)
+            card = sk.run([self.packed()], min_depth=params.get("min_depth", 2))
+            del sk
+            distinct, kept = card.distinct_hi(), card.kept_hi()
+            fp = kmer.bloom_fp_rate(tuning.bloom_bits, tuning.n_hash)
+            kept = kept + fp * max(distinct - kept, 0.0)
+        else:  # the caller's size hints
+            distinct, kept = spec.distinct_est, spec.kept_est
+        keys = distinct if bypass else kept  # bypass keeps every distinct k-mer
         cap = next_pow2(max(1024, int(keys / tuning.table_load)))
-        bw = next_pow2(max(64, int(spec.distinct_est * tuning.bloom_bits / 64)))
+        bw = next_pow2(max(64, int(distinct * tuning.bloom_bits / 64)))
         cus = torch.cuda.get_device_properties(device).multi_processor_count
         # + one partly used 256-entry chunk per wave of either form
-        lcap = int(spec.distinct_est * 1.2) + cus * max(8, tuning.blocks_per_cu) * 4 * 255
+        lcap = int(distinct * (1.0 if plan else 1.2)) + cus * max(8, tuning.blocks_per_cu) * 4 * 255
         self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, device=device, **params)
         self.out = Records(int(min(cap, keys * 1.3 + 1024)), device=device)
 
@@ -86,12 +101,15 @@ class Batch:
 
     def __init__(self, specs: list[SetSpec], k: int, qcut: int = 20, min_depth: int = 2, ext_min: int | None = None,
                  qual_offset: int = 0, export_flags: int = 0, tuning: Tuning | None = None, device="cuda",
-                 **params):
+                 plan: bool = True, **params):
+        """plan: size every set's structures from a cardinality pass over its reads (else from the
+        SetSpec size hints)."""
         self.device = torch.device(device)
         self.k, self.qcut, self.qual_offset, self.export_flags = k, qcut, qual_offset, export_flags
         self.tuning = tuning or Tuning()
         self.params = dict(min_depth=min_depth, ext_min=ext_min, **params)
-        self.sets = [_SetBuffers(s, k, self.params, self.tuning, self.device) for s in specs]
+        self.sets = [_SetBuffers(s, k, self.params, self.tuning, self.device, plan=plan, qcut=qcut,
+                                 qual_offset=qual_offset) for s in specs]
         n = len(self.sets)
         wb = int(abi.lib().hm_batch_work_bytes(n))
         self.work = torch.empty(wb // 8 + 32, dtype=torch.int64, device=self.device)

@@ -317,6 +317,8 @@ class CardSketch:
         self.card = abi.Card(self.registers.data_ptr(), hll_p, self.sample_log2, self.heavy_log2, 0,
                              self.positions.data_ptr(), tables[0], tables[1])
         self.summary_buf = torch.zeros(5, dtype=torch.int64, device=self.device)
+        self.heavy_cap = 4096
+        self.heavy_keys = torch.zeros(2 * self.heavy_cap, dtype=torch.int64, device=self.device)
 
     def reset(self, stream=None):
         abi.call("hm_card_init", ctypes.byref(self.card), _stream(stream))
@@ -326,12 +328,14 @@ class CardSketch:
         abi.call("hm_cardinality", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
                  _stream(stream))
 
-    def summarize(self, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int = 4096, stream=None):
-        """Launch hm_card_summary (asynchronous); result() reads it."""
-        self.heavy_keys = torch.zeros(2 * max(heavy_cap, 1), dtype=torch.int64, device=self.device)
-        self.heavy_cap = heavy_cap
+    def summarize(self, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int | None = None, stream=None):
+        """Launch hm_card_summary (asynchronous); result() reads it.  Up to heavy_cap heavy keys
+        are kept (default 4096; a larger cap reallocates the key buffer)."""
+        if heavy_cap is not None and heavy_cap != self.heavy_cap:
+            self.heavy_cap = heavy_cap
+            self.heavy_keys = torch.zeros(2 * max(heavy_cap, 1), dtype=torch.int64, device=self.device)
         abi.call("hm_card_summary", ctypes.byref(self.card), min_depth, heavy_min, self.heavy_keys.data_ptr(),
-                 heavy_cap, self.summary_buf.data_ptr(), _stream(stream))
+                 self.heavy_cap, self.summary_buf.data_ptr(), _stream(stream))
 
     def result(self, stream=None) -> CardResult:
         torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
@@ -348,7 +352,8 @@ class CardSketch:
         return CardResult(est, int(u[1]), int(u[2]), n_heavy, int(u[4]), self.hll_p, self.sample_log2,
                           self.heavy_log2, hk[order, 0].copy(), hk[order, 1].copy(), rc)
 
-    def run(self, batches, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int = 4096, stream=None) -> CardResult:
+    def run(self, batches, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int | None = None,
+            stream=None) -> CardResult:
         self.reset(stream)
         for p in batches:
             self.update(p, stream)

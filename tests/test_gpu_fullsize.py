@@ -12,7 +12,6 @@ import numpy as np
 import pytest
 import torch
 
-import bench
 import oracle
 from paper_1705_11147_amd import abi, kmer, synth
 from tests.util import assert_tables_equal, table_digest
@@ -40,41 +39,52 @@ def test_mid_workload_full_size_sampled():
     r = w.reads()
     p = w.params
     L, k = r.read_len, p.k
+    positions = r.n_reads * (L - k + 1)
     print("mid workload full size: %d reads x %d, k=%d" % (r.n_reads, L, k), flush=True)
     dev = torch.device("cuda:0")
     a = torch.from_numpy(r.ascii).to(dev)
     q = torch.from_numpy(r.qual).to(dev)
-    distinct = w.meta["G"] + 30 * r.n_bases * w.err
-    kept = w.meta["G"] * 1.02 + 0.03 * distinct
-    cap, bloom_words, list_cap = bench.sizes_for(w, distinct, kept)
     packed = kmer.pack_reads(a, q, read_len=L, qcut=p.qcut)
-    kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth, device=dev)
+    # sizes from the cardinality pass, as bench.py does; the pass itself is checked against the
+    # oracle's below
+    sk = kmer.CardSketch(k, positions, device=dev)
+    card = sk.run([packed], min_depth=p.min_depth)
+    assert card.status == abi.HM_OK and card.positions == positions
+    regs = sk.registers.cpu().numpy().view(np.uint32).copy()
+    cap, bloom_words, list_cap = kmer.plan_sizes(card, n_hash=4, device=dev)
+    kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth, heavy=card, device=dev)
     out = kmer.Records(int(cap * 0.6), device=dev)
     digests = []
-    for _ in range(2):
-        kc.run([packed], out)
+    for flags in (0, 0, abi.HM_EXPORT_SORTED):
+        kc.run([packed], out, flags=flags)
         assert kc.status() == abi.HM_OK
         digests.append(out.digest_words())
-    assert digests[0] == digests[1]
+    assert digests[0] == digests[1] == digests[2]
     st = kc.stats()
-    positions = r.n_reads * (L - k + 1)
     assert st["occurrences"] == positions  # no N bases in the synthetic reads
-    assert st["hit_first_lookup"] + st["bloom_tests"] == positions
+    assert st["hit_first_lookup"] + st["bloom_tests"] + st["heavy_local"] == positions
     assert st["p2_entries"] == st["deferred"]
-    got = out.to_numpy(sort=False)
+    got = out.to_numpy(sort=False)  # in key order: HM_EXPORT_SORTED
     del a, q, packed, kc, out
     torch.cuda.empty_cache()
+    hi, lo = got["key_hi"], got["key_lo"]
+    assert ((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all()
     assert (got["count"] >= 2).all()
     assert (got["tl"].sum(1) <= got["count"]).all() and (got["tr"].sum(1) <= got["count"]).all()
     n_shards, s = 64, 5
-    g = shard(got, n_shards, s)
-    order = np.lexsort((g["key_lo"], g["key_hi"]))
-    g = {x: v[order] for x, v in g.items()}
+    g = shard(got, n_shards, s)  # a filter keeps the key order
     exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_shards=n_shards,
                      shard=s, n_threads=THREADS, split_reads=True)
     assert exp["positions"] == positions
     assert len(exp["count"]) > 1_000_000
     assert_tables_equal(g, exp, "mid full size, shard %d/%d" % (s, n_shards))
+    # the cardinality pass at full size, bit for bit
+    ec = oracle.card(r.ascii, r.offsets(), k, hll_p=card.hll_p, sample_log2=card.sample_log2,
+                     heavy_log2=card.heavy_log2, min_depth=p.min_depth, heavy_min=16, n_threads=THREADS)
+    assert np.array_equal(regs, ec["registers"])
+    assert (card.positions, card.sampled_distinct, card.sampled_kept, card.n_heavy) == (
+        ec["positions"], ec["sampled_distinct"], ec["sampled_kept"], ec["n_heavy"])
+    assert abs(card.estimate - ec["estimate"]) <= 1e-12 * ec["estimate"]
 
 
 def test_human_share_streamed_batches():
@@ -85,19 +95,23 @@ def test_human_share_streamed_batches():
     dev = torch.device("cuda:0")
     n = w.n_reads
     cuts = [0, n // 5, n // 2, (4 * n) // 5, n]
-    d, kept = w.size_estimates()
-    kc = kmer.KmerCounter(p.k, kmer.next_pow2(int(kept / 16 / 0.3)), kmer.next_pow2(int(d / 16 * 12 / 64)),
-                          int(d / 16 * 1.3) + kmer.list_slack(4), n_owners=p.n_owners, owner=p.owner, device=dev)
-    kc.reset()
-    host = []
+    host, packs = [], []
     for i in range(4):
         r = w.reads(r0=cuts[i], n=cuts[i + 1] - cuts[i])
         host.append(r)
-        pk = kmer.pack_reads(torch.from_numpy(r.ascii).to(dev), torch.from_numpy(r.qual).to(dev),
-                             read_len=r.read_len, qcut=p.qcut)
+        packs.append(kmer.pack_reads(torch.from_numpy(r.ascii).to(dev), torch.from_numpy(r.qual).to(dev),
+                                     read_len=r.read_len, qcut=p.qcut))
+    # one cardinality sketch over the four batches sizes the owner's table
+    sk = kmer.CardSketch(p.k, w.positions, n_owners=p.n_owners, owner=p.owner, device=dev)
+    card = sk.run(packs, min_depth=p.min_depth)
+    assert card.status == abi.HM_OK
+    cap, bw, lcap = kmer.plan_sizes(card, pass1_launches=4, device=dev)
+    kc = kmer.KmerCounter(p.k, cap, bw, lcap, n_owners=p.n_owners, owner=p.owner, device=dev)
+    kc.reset()
+    for pk in packs:
         kc.insert(pk)
-        torch.cuda.synchronize()
-        del pk
+    torch.cuda.synchronize()
+    del packs
     kc.count()
     kc.classify()
     out = kmer.Records(kc.capacity)

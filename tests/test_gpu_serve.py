@@ -27,6 +27,7 @@ def test_alone_equals_in_mix_equals_oracle():
     be = GpuBackend(51)
     mix = Scheduler(be, budget_bytes=8 << 30, max_slots=4).run(jobs)
     assert all(r.status == 0 for r in mix)
+    assert all(r.retries == 0 for r in mix)  # planned from a cardinality pass: no job had to grow
     s = summarize(mix, positions)
     assert s["jobs"] == 10 and s["failed"] == 0
     # the same job twice in the stream, and alone on an idle GPU
@@ -50,8 +51,21 @@ def test_capacity_retry_in_serving():
     jobs, _ = make_jobs(pool, n_jobs=2, rate=100.0)
     for j in jobs:
         j.kept_est = 100.0  # far too small a table: the server must resize and rerun
-    recs = Scheduler(GpuBackend(51), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
+    # sized from the (wrong) hints instead of a cardinality pass
+    recs = Scheduler(GpuBackend(51, plan=False), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
     assert all(r.status == 0 and r.retries > 0 for r in recs)
     rd = pool[1].reads()
     exp = oracle.run(rd.ascii, rd.qual, rd.offsets(), 51)
     assert recs[1].result["digest"] == table_digest(exp)
+
+
+def test_planned_and_hinted_sizing_agree():
+    """A job planned from its cardinality pass and the same job sized from hints give the same
+    result; the planned job's structures are not larger than needed by more than the plan's margins."""
+    _, builders = synth.serving_jobs(n_jobs=3, scale=0.005)
+    pool = [b() for b in builders]
+    jobs, _ = make_jobs(pool, n_jobs=3, rate=100.0)
+    planned = Scheduler(GpuBackend(51), budget_bytes=8 << 30, max_slots=2).run(jobs)
+    hinted = Scheduler(GpuBackend(51, plan=False), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
+    assert [r.result for r in planned] == [r.result for r in hinted]
+    assert all(r.status == 0 for r in planned)
