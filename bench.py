@@ -358,14 +358,25 @@ def main():
                 "events_per_position": {x: round(v / positions, 4) for x, v in st.items() }}
     if not args.no_probe:
         from paper_1705_11147_amd import roofline as ra
-        m = ra.measure(kc.capacity * 64, kinds=("load", "atomic_add", "atomic_or_ret"), n_ops=1 << 28, reps=2,
-                       device=dev)
+        m = ra.measure(kc.capacity * 64, kinds=("load", "atomic_add", "atomic_or_ret", "probe_cas"), n_ops=1 << 28,
+                       reps=2, device=dev)
         roofline["measured_random_access"] = {
             "footprint_GB": round(m["footprint_bytes"] / 1e9, 2),
             "load_Gops": round(m["load"]["ops_per_s"] / 1e9, 2),
             "atomic_add_Gops": round(m["atomic_add"]["ops_per_s"] / 1e9, 2),
             "atomic_or_ret_Gops": round(m["atomic_or_ret"]["ops_per_s"] / 1e9, 2),
+            "probe_cas_Gops": round(m["probe_cas"]["ops_per_s"] / 1e9, 2),
             "copy_GBps": round(m["copy"]["GBps"], 1)}
+        # the same pass priced at the measured rates of its own access kinds, one after another: a hit
+        # is a probe + CAS on its line, a Bloom test a probe that misses + an OR with return, every
+        # further probed slot a load, an insertion two atomics (key claim, count)
+        rate = {x: m[x]["ops_per_s"] for x in ("load", "atomic_add", "atomic_or_ret", "probe_cas")}
+        hits = st["hit_first_lookup"]
+        inserts = max(occ - hits - deferred, 0)
+        model_s = (hits / rate["probe_cas"] + bloom_tests / rate["load"] + bloom_tests / rate["atomic_or_ret"]
+                   + max(st["probe_slots"] - occ, 0) / rate["load"] + 2 * inserts / rate["atomic_add"])
+        roofline["measured_ceiling_ms"] = round(model_s * 1000, 2)
+        roofline["frac_of_measured_ceiling"] = round(model_s * 1000 / stage_ms["pass1"], 4)
         # random memory requests of pass 1 (from the counters): a 16-byte load per probed slot,
         # an 8-byte load of the second key word per match, Bloom ORs, counting CASes (and the
         # wide atomics when a counter overflows its packed lane)

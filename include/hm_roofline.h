@@ -18,6 +18,9 @@
  * events.  Returns 0 or a negative HM_E* code (hm_kmer.h).
  *   HM_RA_COPY: streaming copy of the first n_words/2 words onto the second
  *   half (n_ops ignored), the reference kernel for byte-counter scaling.
+ *   Each thread keeps four independent accesses in flight, or one with
+ *   HM_RA_SERIAL, so the probe also shows how much the rate depends on
+ *   memory-level parallelism.
  */
 #ifndef HM_ROOFLINE_H
 #define HM_ROOFLINE_H
@@ -36,6 +39,9 @@ extern "C" {
 #define HM_RA_ATOMIC_OR_RET 3 /* device-scope atomic OR, result used (Bloom test-and-set) */
 #define HM_RA_LINE_RMW 4      /* coherent load + two atomic adds on one 64-byte line (a table hit) */
 #define HM_RA_COPY 5          /* streaming copy, for counter calibration */
+#define HM_RA_PROBE_CAS 6     /* 16-byte load of a random 64-byte line, then a CAS of its second word with the
+                                 loaded value (the counting pass's table hit) */
+#define HM_RA_SERIAL 0x100    /* flag OR-ed into kind: one access in flight per thread instead of four */
 
 int hm_random_access(uint64_t *buf, uint64_t n_words, int32_t kind, uint64_t n_ops, uint64_t seed, uint64_t *sink,
                      hipStream_t stream);

@@ -147,6 +147,8 @@ HM_RA_ATOMIC_ADD = 2
 HM_RA_ATOMIC_OR_RET = 3
 HM_RA_LINE_RMW = 4
 HM_RA_COPY = 5
+HM_RA_PROBE_CAS = 6
+HM_RA_SERIAL = 0x100
 
 _LIB = None
 

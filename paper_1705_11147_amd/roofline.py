@@ -16,7 +16,11 @@ import torch
 from . import abi
 
 KINDS = {"load": abi.HM_RA_LOAD, "load_coherent": abi.HM_RA_LOAD_COHERENT, "atomic_add": abi.HM_RA_ATOMIC_ADD,
-         "atomic_or_ret": abi.HM_RA_ATOMIC_OR_RET, "line_rmw": abi.HM_RA_LINE_RMW}
+         "atomic_or_ret": abi.HM_RA_ATOMIC_OR_RET, "line_rmw": abi.HM_RA_LINE_RMW,
+         "probe_cas": abi.HM_RA_PROBE_CAS,
+         # one access in flight per thread (the others keep four)
+         "load_serial": abi.HM_RA_LOAD | abi.HM_RA_SERIAL, "atomic_add_serial": abi.HM_RA_ATOMIC_ADD | abi.HM_RA_SERIAL,
+         "probe_cas_serial": abi.HM_RA_PROBE_CAS | abi.HM_RA_SERIAL}
 
 
 def measure(footprint_bytes: int, kinds=tuple(KINDS), n_ops: int = 1 << 28, reps: int = 3, device="cuda") -> dict:

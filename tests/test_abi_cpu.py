@@ -103,6 +103,7 @@ def test_random_access_rejects(L):
     assert L.hm_random_access(None, 1024, 0, 10, 1, 8, None) == abi.HM_EINVAL
     assert L.hm_random_access(8, 1000, 0, 10, 1, 8, None) == abi.HM_EINVAL
     assert L.hm_random_access(8, 1024, 9, 10, 1, 8, None) == abi.HM_EINVAL
+    assert L.hm_random_access(8, 1024, abi.HM_RA_COPY | abi.HM_RA_SERIAL, 10, 1, 8, None) == abi.HM_EINVAL
 
 
 def test_package_import_is_lazy_and_loud():
