@@ -84,16 +84,21 @@ def measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log, reps=3
     hi, lo = out.key_hi[:n], out.key_lo[:n] ^ (-2 ** 63)  # flip the sign bit: signed order = unsigned order
     ordered = bool(((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all().item())
     assert ordered, "sorted export is not in key order"
-    passes = (2 * k + 7) // 8
     kw = 2 if 2 * k > 64 else 1
-    # algorithmic bytes per record: each pass reads the digit's key word for the tile counts, then
-    # reads and writes the keys and the 4-byte index; staging reads the 38 record bytes and writes
-    # a 48-byte line; the gather reads the index, one 64-byte line and the keys when the last pass
-    # left them in the scratch, and writes 38 record bytes (+ keys)
-    copy = (passes & 1) * 8 * kw
-    per_rec = passes * (8 + 2 * (8 * kw + 4)) + (38 + 48) + (4 + 64 + copy + 38 + copy)
+    rec = 8 * kw + 4  # key words + 4-byte index
+    # algorithmic bytes per record: staging reads the 38 record bytes and writes a 48-byte line; a
+    # counting pass reads the digit's key word for the tile counts, then reads and writes the keys
+    # and index; the gather reads the index and one 64-byte line, writes 38 record bytes (and the
+    # keys when the last pass left them in the scratch)
+    if 2 * k >= 32:  # two grouping passes, the group starts (one key word), each group read and written once
+        passes = 2
+        per_rec = (38 + 48) + passes * (8 + 2 * rec) + 8 + 2 * rec + (4 + 64 + 38)
+    else:
+        passes = (2 * k + 7) // 8
+        copy = (passes & 1) * 8 * kw
+        per_rec = (38 + 48) + passes * (8 + 2 * rec) + (4 + 64 + copy + 38 + copy)
     sort_ms = srt - plain
-    res = {"records": n, "key_bits": 2 * k, "passes": passes, "export_ms": round(plain, 3),
+    res = {"records": n, "key_bits": 2 * k, "counting_passes": passes, "export_ms": round(plain, 3),
            "export_sorted_ms": round(srt, 3), "sort_ms": round(sort_ms, 3),
            "sort_records_per_s": round(n / (sort_ms / 1000), 1), "bytes_per_record": per_rec,
            "sort_algorithmic_GBps": round(n * per_rec / (sort_ms / 1000) / 1e9, 1), "order_checked": ordered}

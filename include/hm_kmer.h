@@ -200,9 +200,9 @@ size_t hm_table_bytes(uint64_t capacity);
 size_t hm_bloom_bytes(uint64_t n_words);
 size_t hm_list_bytes(uint64_t capacity);
 /* Scratch that hm_export_table needs with HM_EXPORT_SORTED for an export
- * buffer of `capacity` records: 88 bytes per record plus 1 KiB per 4096
- * records (keys, record index and the staged counters, double-buffered where
- * a radix pass needs it). */
+ * buffer of `capacity` records: 88 bytes per record (keys, record index and
+ * the staged counters, double-buffered where a counting pass needs it), plus
+ * 1 KiB per 4096 records and about 257 KiB of digit and group tables. */
 size_t hm_export_sort_bytes(uint64_t capacity);
 /* Host-only argument check of a parameter block (no device access). */
 int hm_check_params(const hm_params_t *p);
@@ -259,12 +259,15 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 /* Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
  * HM_EXPORT_ALL, HM_EXPORT_CLASSIFY, HM_EXPORT_SORTED.  Zeroes out->n_out (and
  * out->digest) first.  Without HM_EXPORT_SORTED the records are in table-slot
- * (hash) order.  With it they are in ascending key order: an LSD radix sort
- * on the 2k key bits, 8 bits per pass, runs after the compaction on the same
+ * (hash) order.  With it they are in ascending key order: a radix sort of
+ * the 2k key bits runs after the compaction on the same
  * stream and uses out->sort_work as scratch (HM_EINVAL if it is NULL,
  * misaligned, smaller than hm_export_sort_bytes(out->capacity), or if
  * out->capacity >= 2^32).  The digest does not depend on the order.  After
- * an HM_EOUTPUT failure the partial records are sorted too, and stay invalid. */
+ * an HM_EOUTPUT failure the partial records are sorted too, and stay invalid.
+ * The sort groups records by their top 16 key bits with two stable counting
+ * passes and then orders each group in one workgroup (keys of 32 bits or
+ * more), or takes a counting pass per 8 key bits (shorter keys). */
 int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
 
 

@@ -4,14 +4,26 @@
 // The records of an export are unordered: compaction writes them in table-slot
 // order, which is hash order.  A consumer that merges or binary-searches k-mer
 // sets needs them in key order, i.e. lexicographic order of the k-mers (the
-// encoding puts the first base in the most significant bits).  The sort is a
-// least-significant-digit radix sort over the 2k key bits, 8 bits per pass.
-// Keys travel with a 32-bit record index; the rest of each record (count,
-// tallies, classes) is staged once as one 64-byte line per record and gathered
-// into place after the last pass, so a pass moves 20 bytes per record (12 for
-// k <= 32, whose keys fit one word) instead of 54.
+// encoding puts the first base in the most significant bits).  Keys travel
+// with a 32-bit record index; the rest of each record (count, tallies,
+// classes) is staged once as one 64-byte line per record and gathered into
+// place at the end.
 //
-// Each pass is three kernels:
+// Keys of 32 bits or more (k >= 16) are sorted most-significant bits first:
+//   1. two stable counting passes on the top 16 key bits (8 bits each, least
+//      significant of the two first) group the records by 16-bit prefix, in
+//      prefix order;
+//   2. k_sort_bounds finds where each of the 65536 prefix groups starts;
+//   3. k_sort_groups sorts every group on its own: one workgroup per group,
+//      the whole group in LDS and a bitonic network on the full key when it
+//      holds at most 4096 records (about 1500 on average at 10^8 records),
+//      else an in-workgroup least-significant-digit sort through global
+//      memory (a rare group: many distinct k-mers sharing their first 8 bases).
+// Shorter keys (k < 16, at most 4 digits) take stable counting passes over
+// all their digits.  Either way each record crosses memory a few times
+// instead of once per 8 key bits.
+//
+// A counting pass is three kernels:
 //   k_sort_hist     one workgroup per 4096-record tile counts the tile's digits
 //                   into row `digit` of a digit x tile matrix;
 //   k_sort_scan     one workgroup per digit turns its row into exclusive
@@ -21,8 +33,7 @@
 //                   rounds and waves orders the rest), places them in digit
 //                   order in LDS, and writes every digit's run to its global
 //                   offset, so consecutive lanes store to consecutive addresses.
-// Stability of every pass is what makes the LSD order correct; keys in a
-// table are distinct, so the final order is unique.
+// Keys in a table are distinct, so the final order is unique.
 #include "hm_device.h"
 
 namespace hm {
@@ -31,6 +42,9 @@ namespace {
 constexpr int kSortIpt = 16;                  // records per thread per tile
 constexpr int kSortTile = kBlock * kSortIpt;  // 4096 records
 constexpr int kSortWaves = kBlock / 64;
+constexpr int kPrefixBits = 16;               // bits of the grouping prefix
+constexpr uint32_t kGroups = 1u << kPrefixBits;
+constexpr int kGroupMax = 4096;               // records a group sorts in LDS
 
 struct SortLayout {
     uint64_t *hi, *lo;      // key partners of out.key_hi / out.key_lo
@@ -38,6 +52,7 @@ struct SortLayout {
     uint4 *pay;             // 4 uint4 per record: tl, tr, {count, cls_l | cls_r << 8}, unused
     uint32_t *hist;         // 256 rows of nblk tile counts
     uint32_t *tot;          // 256 digit totals
+    uint32_t *starts;       // kGroups + 1 group starts
     uint32_t nblk;
     uint64_t bytes;
 };
@@ -61,6 +76,7 @@ SortLayout sort_layout(void *work, uint64_t cap) {
     L.pay = reinterpret_cast<uint4 *>(take(64 * cap));
     L.hist = reinterpret_cast<uint32_t *>(take(4ull * 256 * nblk));
     L.tot = reinterpret_cast<uint32_t *>(take(4ull * 256));
+    L.starts = reinterpret_cast<uint32_t *>(take(4ull * (kGroups + 1)));
     L.bytes = off;
     return L;
 }
@@ -70,6 +86,16 @@ SortLayout sort_layout(void *work, uint64_t cap) {
 __device__ __forceinline__ uint32_t records_in(const uint64_t *n_out, uint64_t cap) {
     const uint64_t n = *n_out;
     return (uint32_t)(n < cap ? n : cap);
+}
+
+// Bits [s, s + 64) of the 128-bit key hi:lo, low-aligned.
+__device__ __forceinline__ uint64_t key_bits_at(uint64_t hi, uint64_t lo, uint32_t s) {
+    if (s >= 64) return hi >> (s - 64);
+    return s ? (lo >> s) | (hi << (64 - s)) : lo;
+}
+
+__device__ __forceinline__ uint32_t digit_at(uint64_t hi, uint64_t lo, uint32_t s) {
+    return (uint32_t)key_bits_at(hi, lo, s) & 255u;
 }
 
 // Exclusive prefix sum over the kBlock threads of a workgroup; every thread
@@ -96,6 +122,58 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *wsum, 
     return before + x - v;
 }
 
+// Stable rank of a tile of up to kSortTile records in tile order (item round
+// j, then wave, then lane).  dig[j] is the digit of this thread's item j (any
+// value when the item is past tile_n).  On return pos[j] is the item's place
+// in the tile's digit-sorted order (0xFFFF past tile_n) and tstart[d] the
+// first place of digit d, tstart[256] = tile_n.  `cnt` is kSortIpt x waves x
+// 256 LDS counters (32 KB), free again on return.  Contains barriers.
+__device__ __forceinline__ void tile_rank(const uint32_t (&dig)[kSortIpt], uint32_t tile_n,
+                                          uint16_t (*cnt)[kSortWaves][256], uint32_t *tstart, uint32_t *wsum,
+                                          uint32_t (&pos)[kSortIpt]) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    uint4 *z = reinterpret_cast<uint4 *>(&cnt[0][0][0]);
+    for (int i = t; i < kSortIpt * kSortWaves * 256 * 2 / 16; i += kBlock) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    const uint64_t below_mask = (1ull << lane) - 1;
+    uint32_t below[kSortIpt];
+#pragma unroll
+    for (int j = 0; j < kSortIpt; ++j) {
+        const bool valid = (uint32_t)j * kBlock + t < tile_n;
+        const uint32_t d = dig[j] & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        below[j] = (uint32_t)__popcll(m & below_mask);
+        if (valid && below[j] == 0) cnt[j][w][d] = (uint16_t)__popcll(m);
+    }
+    __syncthreads();
+    // thread t owns digit t: running count over (round, wave) in tile order
+    uint32_t run = 0;
+    for (int j = 0; j < kSortIpt; ++j)
+#pragma unroll
+        for (int q = 0; q < kSortWaves; ++q) {
+            const uint32_t c = cnt[j][q][t];
+            cnt[j][q][t] = (uint16_t)run;
+            run += c;
+        }
+    uint32_t tile_total;
+    tstart[t] = block_exclusive(run, wsum, tile_total);
+    if (t == 0) tstart[256] = tile_total;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortIpt; ++j) {
+        const bool valid = (uint32_t)j * kBlock + t < tile_n;
+        const uint32_t d = dig[j] & 255u;
+        pos[j] = valid ? tstart[d] + cnt[j][w][d] + below[j] : 0xFFFFu;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_sort_prep(hm_export_t out, uint4 *pay) {
     const uint32_t n = records_in(out.n_out, out.capacity);
     const uint4 *tl = reinterpret_cast<const uint4 *>(out.tl);
@@ -107,26 +185,32 @@ __global__ __launch_bounds__(kBlock) void k_sort_prep(hm_export_t out, uint4 *pa
     }
 }
 
-// Digit counts of one tile: `word` is the key word holding the digit, `shift`
-// its position in that word.
-__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *word, uint32_t shift, const uint64_t *n_out,
-                                                      uint64_t cap, uint32_t *hist, uint32_t nblk) {
+// Digit counts of one tile (digit = key bits [shift, shift + 8)); only the
+// key words that hold the digit are read.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t *hi, const uint64_t *lo, uint32_t shift,
+                                                      const uint64_t *n_out, uint64_t cap, uint32_t *hist,
+                                                      uint32_t nblk) {
     __shared__ uint32_t h[kSortWaves][256];
     for (int i = threadIdx.x; i < kSortWaves * 256; i += kBlock) (&h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = records_in(n_out, cap);
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     const int w = threadIdx.x >> 6;
-    uint64_t v[kSortIpt];
+    const bool need_lo = KW == 1 || shift < 64;
+    const bool need_hi = KW == 2 && shift + 8 > 64;
+    uint32_t d[kSortIpt];
 #pragma unroll
     for (int j = 0; j < kSortIpt; ++j) {
         const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-        v[j] = i < n ? word[i] : 0;
+        const bool ok = i < n;
+        const uint64_t l = ok && need_lo ? lo[i] : 0, u = ok && need_hi ? hi[i] : 0;
+        d[j] = digit_at(u, l, shift);
     }
 #pragma unroll
     for (int j = 0; j < kSortIpt; ++j) {
         const uint64_t i = base + (uint64_t)j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[w][(v[j] >> shift) & 255], 1u);
+        if (i < n) atomicAdd(&h[w][d[j]], 1u);
     }
     __syncthreads();
     uint32_t s = 0;
@@ -154,20 +238,19 @@ __global__ __launch_bounds__(kBlock) void k_sort_scan(uint32_t *hist, uint32_t n
     if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
-// One stable counting-sort step of a tile on the digit at bit `shift` of the
-// 128-bit key (hi:lo).  KW = key words moved (1 when every key fits key_lo).
-// FIRST: the record index is the input position (no index array yet).
+// One stable counting-sort step of a tile on the digit at key bits [shift,
+// shift + 8).  KW = key words moved (1 when every key fits key_lo).  FIRST: the
+// record index is the input position (no index array yet).
 template <int KW, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *shi, const uint64_t *slo, const uint32_t *sidx,
                                                          uint64_t *dhi, uint64_t *dlo, uint32_t *didx, uint32_t shift,
                                                          const uint64_t *n_out, uint64_t cap, const uint32_t *hist,
                                                          const uint32_t *tot, uint32_t nblk) {
-    // cnt[j][w][d] (records of digit d among item round j of wave w) and the
-    // digit-ordered staging area share the same 32 KB: the counts are dead
-    // once every record knows its tile position.
+    // the ranking counters and the digit-ordered staging area share 32 KB: the
+    // counters are free once every record knows its place in the tile
     __shared__ uint64_t smem[kSortTile];
     __shared__ uint8_t sdig[kSortTile];
-    __shared__ uint32_t gbase[256], tstart[256], wsum[kSortWaves];
+    __shared__ uint32_t gbase[256], tstart[257], wsum[kSortWaves];
     static_assert(sizeof(uint16_t) * kSortIpt * kSortWaves * 256 == sizeof(uint64_t) * kSortTile, "LDS overlay");
     uint16_t(*cnt)[kSortWaves][256] = reinterpret_cast<uint16_t(*)[kSortWaves][256]>(smem);
 
@@ -175,76 +258,34 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *shi, co
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     if (base >= n) return;  // whole workgroup: past the last record
     const uint32_t tile_n = (uint32_t)min<uint64_t>(kSortTile, n - base);
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int t = threadIdx.x;
 
-    uint4 *z = reinterpret_cast<uint4 *>(smem);
-    for (int i = t; i < kSortTile * 8 / 16; i += kBlock) z[i] = make_uint4(0u, 0u, 0u, 0u);
     // global start of digit t for this tile: records of smaller digits, plus
-    // digit-t records of earlier tiles (block_exclusive's barrier also orders
-    // the zeroing above before the counts below)
+    // digit-t records of earlier tiles
     uint32_t total;
     const uint32_t dstart = block_exclusive(tot[t], wsum, total);
     gbase[t] = dstart + hist[(uint64_t)t * nblk + blockIdx.x];
 
-    const bool dig_hi = shift >= 64;
-    const uint32_t sh = shift & 63;
-    const uint64_t below_mask = (1ull << lane) - 1;
     uint64_t klo[kSortIpt], khi[KW == 2 ? kSortIpt : 1];
-    uint32_t kid[kSortIpt], meta[kSortIpt];
+    uint32_t kid[kSortIpt], dig[kSortIpt], pos[kSortIpt];
 #pragma unroll
     for (int j = 0; j < kSortIpt; ++j) {
         const uint32_t r = (uint32_t)j * kBlock + t;  // tile order: round, then wave, then lane
         const bool valid = r < tile_n;
         const uint64_t i = base + r;
         klo[j] = valid ? slo[i] : 0;
-        if constexpr (KW == 2) khi[j] = valid ? shi[i] : 0;
+        uint64_t u = 0;
+        if constexpr (KW == 2) u = khi[j] = valid ? shi[i] : 0;
         kid[j] = FIRST ? (uint32_t)i : (valid ? sidx[i] : 0u);
+        dig[j] = digit_at(u, klo[j], shift);
     }
-#pragma unroll
-    for (int j = 0; j < kSortIpt; ++j) {
-        const bool valid = (uint32_t)j * kBlock + t < tile_n;
-        uint64_t dw = klo[j];
-        if constexpr (KW == 2) dw = dig_hi ? khi[j] : dw;
-        const uint32_t d = (uint32_t)(dw >> sh) & 255;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        const uint32_t below = (uint32_t)__popcll(m & below_mask);
-        if (valid && below == 0) cnt[j][w][d] = (uint16_t)__popcll(m);
-        meta[j] = d | below << 8;
-    }
-    __syncthreads();
-    // thread t owns digit t: running count over (round, wave) in tile order
-    uint32_t run = 0;
-    for (int j = 0; j < kSortIpt; ++j)
-#pragma unroll
-        for (int q = 0; q < kSortWaves; ++q) {
-            const uint32_t c = cnt[j][q][t];
-            cnt[j][q][t] = (uint16_t)run;
-            run += c;
-        }
-    uint32_t tile_total;
-    tstart[t] = block_exclusive(run, wsum, tile_total);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kSortIpt; ++j) {
-        const bool valid = (uint32_t)j * kBlock + t < tile_n;
-        const uint32_t d = meta[j] & 255;
-        const uint32_t pos = valid ? tstart[d] + cnt[j][w][d] + (meta[j] >> 8) : 0xFFFFu;
-        meta[j] = d | pos << 8;
-    }
-    __syncthreads();  // counts dead from here on: smem becomes the staging area
+    tile_rank(dig, tile_n, cnt, tstart, wsum, pos);  // its barriers also publish gbase
 
 #pragma unroll
     for (int j = 0; j < kSortIpt; ++j) {
-        const uint32_t pos = meta[j] >> 8;
-        if (pos < (uint32_t)kSortTile) {
-            sdig[pos] = (uint8_t)(meta[j] & 255);
-            smem[pos] = klo[j];
+        if (pos[j] < (uint32_t)kSortTile) {
+            sdig[pos[j]] = (uint8_t)dig[j];
+            smem[pos[j]] = klo[j];
         }
     }
     __syncthreads();
@@ -257,10 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *shi, co
     if constexpr (KW == 2) {
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kSortIpt; ++j) {
-            const uint32_t pos = meta[j] >> 8;
-            if (pos < (uint32_t)kSortTile) smem[pos] = khi[j];
-        }
+        for (int j = 0; j < kSortIpt; ++j)
+            if (pos[j] < (uint32_t)kSortTile) smem[pos[j]] = khi[j];
         __syncthreads();
         for (uint32_t r = t; r < tile_n; r += kBlock) {
             const uint32_t d = sdig[r], g = gbase[d] + (r - tstart[d]);
@@ -270,14 +309,171 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint64_t *shi, co
     __syncthreads();
     uint32_t *s32 = reinterpret_cast<uint32_t *>(smem);
 #pragma unroll
-    for (int j = 0; j < kSortIpt; ++j) {
-        const uint32_t pos = meta[j] >> 8;
-        if (pos < (uint32_t)kSortTile) s32[pos] = kid[j];
-    }
+    for (int j = 0; j < kSortIpt; ++j)
+        if (pos[j] < (uint32_t)kSortTile) s32[pos[j]] = kid[j];
     __syncthreads();
     for (uint32_t r = t; r < tile_n; r += kBlock) {
         const uint32_t d = sdig[r], g = gbase[d] + (r - tstart[d]);
         if (g < n) didx[g] = s32[r];
+    }
+}
+
+// Start of every prefix group in records grouped by their top kPrefixBits key
+// bits (bits [pshift, pshift + 16)): starts[P] = first record with prefix >= P,
+// starts[kGroups] = n.  Each start is written by the one record where the
+// prefix steps past it.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_sort_bounds(const uint64_t *hi, const uint64_t *lo, const uint64_t *n_out,
+                                                        uint64_t cap, uint32_t pshift, uint32_t *starts) {
+    const uint32_t n = records_in(n_out, cap);
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (n == 0) {
+        for (uint64_t p = tid; p <= kGroups; p += (uint64_t)gridDim.x * kBlock) starts[p] = 0;
+        return;
+    }
+    for (uint64_t i = tid; i < n; i += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t p = (uint32_t)key_bits_at(KW == 2 ? hi[i] : 0, lo[i], pshift) & (kGroups - 1);
+        const int64_t q = i ? (int64_t)((uint32_t)key_bits_at(KW == 2 ? hi[i - 1] : 0, lo[i - 1], pshift) &
+                                        (kGroups - 1))
+                            : -1;
+        for (int64_t g = q + 1; g <= (int64_t)p; ++g) starts[g] = (uint32_t)i;
+        if (i == n - 1)
+            for (uint32_t g = p + 1; g <= kGroups; ++g) starts[g] = n;
+    }
+}
+
+constexpr uint32_t kPad = 0xFFFFFFFFu;  // index of a padding entry (record indices are < 2^32 - 1)
+
+// a < b, with padding entries above every record (and never below another)
+template <int KW>
+__device__ __forceinline__ bool key_less(uint64_t ahi, uint64_t alo, uint32_t aid, uint64_t bhi, uint64_t blo,
+                                         uint32_t bid) {
+    if (aid == kPad) return false;
+    if (bid == kPad) return true;
+    if constexpr (KW == 2) return ahi < bhi || (ahi == bhi && alo < blo);
+    return alo < blo;
+}
+
+// Sort every prefix group in place (keys x*, index xid); y* / yid are
+// scratch of the same size.  One workgroup per group.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t *xlo, uint32_t *xid, uint64_t *yhi,
+                                                        uint64_t *ylo, uint32_t *yid, const uint32_t *starts,
+                                                        uint32_t pshift, const uint64_t *n_out, uint64_t cap) {
+    // 80 KB: a group of kGroupMax records (hi, lo, index), or the fallback's
+    // ranking counters (32 KB) and digit tables
+    __shared__ uint64_t smem[kGroupMax * 5 / 2];
+    const uint32_t n = records_in(n_out, cap);
+    const uint32_t b = starts[blockIdx.x], e = min(starts[blockIdx.x + 1], n);  // the clamp only guards the arrays
+    if (e <= b + 1) return;  // empty or a single record: nothing to order
+    const uint32_t s = e - b;
+    const int t = threadIdx.x;
+    if (s <= (uint32_t)kGroupMax) {
+        uint64_t *shi = smem, *slo = smem + kGroupMax;
+        uint32_t *sid = reinterpret_cast<uint32_t *>(smem + 2 * kGroupMax);
+        uint32_t m = 2;
+        while (m < s) m <<= 1;
+        for (uint32_t i = t; i < m; i += kBlock) {  // pad to a power of two with entries above every record
+            const bool ok = i < s;
+            if constexpr (KW == 2) shi[i] = ok ? xhi[b + i] : 0ull;
+            slo[i] = ok ? xlo[b + i] : 0ull;
+            sid[i] = ok ? xid[b + i] : kPad;
+        }
+        __syncthreads();
+        for (uint32_t size = 2; size <= m; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t q = t; q < m / 2; q += kBlock) {
+                    const uint32_t i = 2 * q - (q & (stride - 1)), j = i + stride;
+                    const bool up = (i & size) == 0;
+                    const uint64_t ih = KW == 2 ? shi[i] : 0, jh = KW == 2 ? shi[j] : 0;
+                    const uint64_t il = slo[i], jl = slo[j];
+                    const uint32_t id = sid[i], jd = sid[j];
+                    // ascending half: swap when j < i; descending half: when i < j
+                    if (up ? key_less<KW>(jh, jl, jd, ih, il, id) : key_less<KW>(ih, il, id, jh, jl, jd)) {
+                        if constexpr (KW == 2) {
+                            shi[i] = jh;
+                            shi[j] = ih;
+                        }
+                        slo[i] = jl;
+                        slo[j] = il;
+                        sid[i] = jd;
+                        sid[j] = id;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = t; i < s; i += kBlock) {
+            if constexpr (KW == 2) xhi[b + i] = shi[i];
+            xlo[b + i] = slo[i];
+            xid[b + i] = sid[i];
+        }
+        return;
+    }
+    // A group too large for LDS: stable counting passes over the bits below the
+    // prefix, the workgroup walking the group tile by tile in order, between
+    // the group's range of x and of y.
+    uint16_t(*cnt)[kSortWaves][256] = reinterpret_cast<uint16_t(*)[kSortWaves][256]>(smem);
+    uint32_t *h = reinterpret_cast<uint32_t *>(smem + kSortTile);  // after the ranking counters
+    uint32_t *tstart = h + 256;                                    // 257 entries
+    uint32_t *dbase = tstart + 260;                                // 256 entries
+    uint32_t *wsum = dbase + 256;                                  // kSortWaves entries
+    uint64_t *sh_ = xhi, *sl = xlo, *dh = yhi, *dl = ylo;
+    uint32_t *si = xid, *di = yid;
+    int passes = 0;
+    for (uint32_t shift = 0; shift < pshift; shift += 8, ++passes) {
+        h[t] = 0;
+        __syncthreads();
+        for (uint32_t i = b + t; i < e; i += kBlock) atomicAdd(&h[digit_at(KW == 2 ? sh_[i] : 0, sl[i], shift)], 1u);
+        __syncthreads();
+        uint32_t total;
+        dbase[t] = b + block_exclusive(h[t], wsum, total);
+        __syncthreads();
+        for (uint32_t t0 = b; t0 < e; t0 += kSortTile) {
+            const uint32_t tile_n = min((uint32_t)kSortTile, e - t0);
+            uint64_t khi[KW == 2 ? kSortIpt : 1], klo[kSortIpt];
+            uint32_t kid[kSortIpt], dig[kSortIpt], pos[kSortIpt];
+#pragma unroll
+            for (int j = 0; j < kSortIpt; ++j) {
+                const uint32_t r = (uint32_t)j * kBlock + t;
+                const bool ok = r < tile_n;
+                uint64_t u = 0;
+                if constexpr (KW == 2) u = khi[j] = ok ? sh_[t0 + r] : 0;
+                klo[j] = ok ? sl[t0 + r] : 0;
+                kid[j] = ok ? si[t0 + r] : 0u;
+                dig[j] = digit_at(u, klo[j], shift);
+            }
+            tile_rank(dig, tile_n, cnt, tstart, wsum, pos);
+#pragma unroll
+            for (int j = 0; j < kSortIpt; ++j) {
+                if (pos[j] >= (uint32_t)kSortTile) continue;
+                const uint32_t d = dig[j] & 255u;
+                const uint32_t g = dbase[d] + (pos[j] - tstart[d]);
+                if (g >= e) continue;  // never, when the counts agree
+                if constexpr (KW == 2) dh[g] = khi[j];
+                dl[g] = klo[j];
+                di[g] = kid[j];
+            }
+            __syncthreads();
+            dbase[t] += tstart[t + 1] - tstart[t];  // this tile's records of digit t
+            __syncthreads();
+        }
+        uint64_t *x = sh_;
+        sh_ = dh;
+        dh = x;
+        x = sl;
+        sl = dl;
+        dl = x;
+        uint32_t *xi = si;
+        si = di;
+        di = xi;
+    }
+    if (passes & 1) {  // the result is in y: bring it back
+        for (uint32_t i = b + t; i < e; i += kBlock) {
+            if constexpr (KW == 2) xhi[i] = yhi[i];
+            xlo[i] = ylo[i];
+            xid[i] = yid[i];
+        }
     }
 }
 
@@ -305,29 +501,56 @@ __global__ __launch_bounds__(kBlock) void k_sort_final(const uint64_t *khi, cons
     }
 }
 
+// One stable counting pass (hist, scan, scatter) from (shi, slo, sidx) to
+// (dhi, dlo, didx) on key bits [shift, shift + 8); sidx NULL: first pass.
 template <int KW>
-int sort_passes(const hm_export_t &out, const SortLayout &L, int passes, hipStream_t s) {
+int counting_pass(const hm_export_t &out, const SortLayout &L, const uint64_t *shi, const uint64_t *slo,
+                  const uint32_t *sidx, uint64_t *dhi, uint64_t *dlo, uint32_t *didx, uint32_t shift, hipStream_t s) {
     const dim3 tiles(L.nblk), blk(kBlock);
+    hipLaunchKernelGGL(k_sort_hist<KW>, tiles, blk, 0, s, shi, slo, shift, out.n_out, out.capacity, L.hist, L.nblk);
+    hipLaunchKernelGGL(k_sort_scan, dim3(256), blk, 0, s, L.hist, L.nblk, L.tot);
+    if (!sidx)
+        hipLaunchKernelGGL((k_sort_scatter<KW, true>), tiles, blk, 0, s, shi, slo, nullptr, dhi, dlo, didx, shift,
+                           out.n_out, out.capacity, L.hist, L.tot, L.nblk);
+    else
+        hipLaunchKernelGGL((k_sort_scatter<KW, false>), tiles, blk, 0, s, shi, slo, sidx, dhi, dlo, didx, shift,
+                           out.n_out, out.capacity, L.hist, L.tot, L.nblk);
+    HM_LAUNCH_CHECK("sort pass");
+    return HM_OK;
+}
+
+template <int KW>
+int sort_keys(const hm_export_t &out, const SortLayout &L, int key_bits, hipStream_t s) {
+    const dim3 blk(kBlock);
     uint64_t *kh[2] = {out.key_hi, L.hi};
     uint64_t *kl[2] = {out.key_lo, L.lo};
     uint32_t *ix[2] = {L.idx0, L.idx1};
-    for (int p = 0; p < passes; ++p) {
-        const uint32_t shift = 8u * (uint32_t)p;
-        const int src = p & 1, dst = src ^ 1;
-        const uint64_t *word = shift >= 64 ? kh[src] : kl[src];
-        hipLaunchKernelGGL(k_sort_hist, tiles, blk, 0, s, word, shift & 63u, out.n_out, out.capacity, L.hist, L.nblk);
-        hipLaunchKernelGGL(k_sort_scan, dim3(256), blk, 0, s, L.hist, L.nblk, L.tot);
-        if (p == 0)
-            hipLaunchKernelGGL((k_sort_scatter<KW, true>), tiles, blk, 0, s, kh[src], kl[src], nullptr, kh[dst],
-                               kl[dst], ix[0], shift, out.n_out, out.capacity, L.hist, L.tot, L.nblk);
-        else
-            hipLaunchKernelGGL((k_sort_scatter<KW, false>), tiles, blk, 0, s, kh[src], kl[src], ix[(p - 1) & 1],
-                               kh[dst], kl[dst], ix[p & 1], shift, out.n_out, out.capacity, L.hist, L.tot, L.nblk);
-        HM_LAUNCH_CHECK("sort pass");
+    const dim3 sweep((unsigned)grid_for(out.capacity, 16));
+    int rc;
+    if (key_bits < 2 * kPrefixBits) {  // short keys: a counting pass per digit
+        const int passes = (key_bits + 7) / 8;
+        for (int p = 0; p < passes; ++p) {
+            const int src = p & 1, dst = src ^ 1;
+            rc = counting_pass<KW>(out, L, kh[src], kl[src], p ? ix[(p - 1) & 1] : nullptr, kh[dst], kl[dst],
+                                   ix[p & 1], 8u * (uint32_t)p, s);
+            if (rc) return rc;
+        }
+        const int res = passes & 1;  // 1: the sorted keys are in the work area
+        hipLaunchKernelGGL(k_sort_final<KW>, sweep, blk, 0, s, kh[res], kl[res], ix[(passes - 1) & 1], L.pay, out, res);
+        HM_LAUNCH_CHECK("sort gather");
+        return HM_OK;
     }
-    const int res = passes & 1;  // 1: the sorted keys are in the work area
-    hipLaunchKernelGGL(k_sort_final<KW>, dim3((unsigned)grid_for(out.capacity, 16)), blk, 0, s, kh[res], kl[res],
-                       ix[(passes - 1) & 1], L.pay, out, res);
+    // group by the top 16 bits (two passes, the lower byte first), then sort each group
+    const uint32_t pshift = (uint32_t)key_bits - kPrefixBits;
+    rc = counting_pass<KW>(out, L, kh[0], kl[0], nullptr, kh[1], kl[1], ix[0], pshift, s);
+    if (rc) return rc;
+    rc = counting_pass<KW>(out, L, kh[1], kl[1], ix[0], kh[0], kl[0], ix[1], pshift + 8, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sort_bounds<KW>, sweep, blk, 0, s, kh[0], kl[0], out.n_out, out.capacity, pshift, L.starts);
+    hipLaunchKernelGGL(k_sort_groups<KW>, dim3(kGroups), blk, 0, s, kh[0], kl[0], ix[1], kh[1], kl[1], ix[0],
+                       L.starts, pshift, out.n_out, out.capacity);
+    HM_LAUNCH_CHECK("sort groups");
+    hipLaunchKernelGGL(k_sort_final<KW>, sweep, blk, 0, s, kh[0], kl[0], ix[1], L.pay, out, 0);
     HM_LAUNCH_CHECK("sort gather");
     return HM_OK;
 }
@@ -341,8 +564,7 @@ int sort_export(const hm_export_t &out, int key_bits, hipStream_t s) {
     const SortLayout L = sort_layout(out.sort_work, out.capacity);
     hipLaunchKernelGGL(k_sort_prep, dim3((unsigned)grid_for(out.capacity, 16)), dim3(kBlock), 0, s, out, L.pay);
     HM_LAUNCH_CHECK("sort prep");
-    const int passes = (key_bits + 7) / 8;
-    return key_bits > 64 ? sort_passes<2>(out, L, passes, s) : sort_passes<1>(out, L, passes, s);
+    return key_bits > 64 ? sort_keys<2>(out, L, key_bits, s) : sort_keys<1>(out, L, key_bits, s);
 }
 
 }  // namespace hm

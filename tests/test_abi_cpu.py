@@ -153,7 +153,7 @@ def test_struct_layout_matches_header(tmp_path):
 
 def test_sorted_export_scratch_and_rejections(L):
     # scratch: keys, indices and staged counters (88 B per record), tile counts, digit totals
-    assert L.hm_export_sort_bytes(1 << 20) == (88 << 20) + 1024 * 256 + 1024
+    assert L.hm_export_sort_bytes(1 << 20) == (88 << 20) + 1024 * 256 + 1024 + 4 * 65537 + 252
     assert L.hm_export_sort_bytes(10) >= 88 * 10 + 2048
     t = abi.Table(64, 1024, 0, 31, 64, None)
     S = abi.HM_EXPORT_SORTED

@@ -300,7 +300,7 @@ def test_fused_classify_export_and_presence_filter(k):
 
 # ------------------------------------------------------------------ key-ordered export
 
-@pytest.mark.parametrize("k", [1, 5, 21, 31, 33, 51, 63])
+@pytest.mark.parametrize("k", [1, 5, 15, 17, 21, 31, 33, 37, 51, 63])
 def test_sorted_export_order(k):
     """HM_EXPORT_SORTED: the device's record order is the oracle's key order, record by record
     (many tiles, a ragged last tile, 1 to 16 radix passes, one- and two-word keys)."""
@@ -313,7 +313,7 @@ def test_sorted_export_order(k):
         assert got["digest"] == plain["digest"]
 
 
-@pytest.mark.parametrize("k", [2, 32])
+@pytest.mark.parametrize("k", [2, 16, 32])
 def test_sorted_export_forward_only_even_k(k):
     """Forward-only keys of exactly 64 bits (k=32) and a 4-bit key (k=2)."""
     ascii, qual, off = random_read_set(700 + k, 2000, 40, 150, genome_len=20000)
@@ -372,3 +372,25 @@ def test_sorted_export_empty_and_too_small():
     kc.export(full, abi.HM_EXPORT_SORTED | abi.HM_EXPORT_CLASSIFY)
     assert kc.status() == abi.HM_OK
     assert_tables_equal(full.to_numpy(sort=False), exp, "after resize")
+
+
+@pytest.mark.parametrize("k", [21, 37, 51])
+def test_sorted_export_large_prefix_group(k):
+    """More than 4096 distinct k-mers sharing their first 8 bases (one 16-bit prefix group larger
+    than a workgroup sorts in LDS) among ordinary reads: the fallback path keeps the exact order."""
+    rng = np.random.default_rng(3000 + k)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    special = [np.concatenate([np.full(8, ord("A"), np.uint8), rng.choice(acgt, k - 8)]) for _ in range(6000)]
+    g = rng.choice(acgt, 40000)
+    st = rng.integers(0, g.size - 120, 4000)
+    reads = special + special + [g[s:s + 120] for s in st]  # every special k-mer twice: count 2, kept
+    ascii = np.concatenate(reads)
+    lens = np.array([len(r) for r in reads])
+    off = np.zeros(len(reads) + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    qual = np.full(ascii.size, 40, np.uint8)
+    exp = oracle.run(ascii, qual, off, k, n_threads=4)
+    got = kmer.analyze(ascii, qual, k, read_off=off, export_flags=abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, exp, "large group k=%d" % k)
+    pref = (exp["key_hi"].astype(object) * 2 ** 64 + exp["key_lo"].astype(object)) >> (2 * k - 16)
+    assert (pref == 0).sum() > 4096
