@@ -86,17 +86,17 @@ def measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log, reps=3
     assert ordered, "sorted export is not in key order"
     kw = 2 if 2 * k > 64 else 1
     rec = 8 * kw + 4  # key words + 4-byte index
-    # algorithmic bytes per record: staging reads the 38 record bytes and writes a 48-byte line; a
-    # counting pass reads the digit's key word for the tile counts, then reads and writes the keys
-    # and index; the gather reads the index and one 64-byte line, writes 38 record bytes (and the
-    # keys when the last pass left them in the scratch)
+    # algorithmic bytes per record on top of the plain export: the export writes a 48-byte staging
+    # line instead of 38 record bytes (+10); a counting pass reads the digit's key word for the tile
+    # counts, then reads and writes the keys and index; the gather reads the index and one 64-byte
+    # line and writes 38 record bytes, and moves the keys when they end in the scratch
     if 2 * k >= 32:  # two grouping passes, the group starts (one key word), each group read and written once
         passes = 2
-        per_rec = (38 + 48) + passes * (8 + 2 * rec) + 8 + 2 * rec + (4 + 64 + 38)
+        per_rec = 10 + passes * (8 + 2 * rec) + 8 + 2 * rec + (4 + 64 + 38 + 2 * 8 * kw)
     else:
         passes = (2 * k + 7) // 8
         copy = (passes & 1) * 8 * kw
-        per_rec = (38 + 48) + passes * (8 + 2 * rec) + (4 + 64 + copy + 38 + copy)
+        per_rec = 10 + passes * (8 + 2 * rec) + (4 + 64 + 38 + 2 * copy)
     sort_ms = srt - plain
     res = {"records": n, "key_bits": 2 * k, "counting_passes": passes, "export_ms": round(plain, 3),
            "export_sorted_ms": round(srt, 3), "sort_ms": round(sort_ms, 3),

@@ -729,7 +729,7 @@ constexpr int kExportChunk = 64 * kExportPerLane;
 template <int KW>
 __device__ __forceinline__ void export_chunk(const Slot *slots, uint64_t first, uint64_t cap, uint32_t flags,
                                              const hm_export_t &out, uint32_t *status, uint16_t *rank_of,
-                                             uint64_t &dsum, uint64_t &dxor) {
+                                             uint64_t &dsum, uint64_t &dxor, uint4 *staged = nullptr) {
     const uint32_t lane = lane_id();
     const bool inline_cls = (flags & HM_EXPORT_CLASSIFY) != 0;
     uint32_t take_bits = 0;
@@ -803,11 +803,17 @@ __device__ __forceinline__ void export_chunk(const Slot *slots, uint64_t first, 
         if (idx < out.capacity) {
             out.key_hi[idx] = hi;
             out.key_lo[idx] = lo;
-            out.count[idx] = count;
-            *reinterpret_cast<uint4 *>(out.tl + 4 * idx) = make_uint4(tl[0], tl[1], tl[2], tl[3]);
-            *reinterpret_cast<uint4 *>(out.tr + 4 * idx) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
-            out.cls_l[idx] = (uint8_t)cl;
-            out.cls_r[idx] = (uint8_t)cr;
+            if (staged) {  // a key-ordered export: the sort gathers these into place
+                staged[4 * idx] = make_uint4(tl[0], tl[1], tl[2], tl[3]);
+                staged[4 * idx + 1] = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+                staged[4 * idx + 2] = make_uint4(count, cl | (cr << 8), 0u, 0u);
+            } else {
+                out.count[idx] = count;
+                *reinterpret_cast<uint4 *>(out.tl + 4 * idx) = make_uint4(tl[0], tl[1], tl[2], tl[3]);
+                *reinterpret_cast<uint4 *>(out.tr + 4 * idx) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+                out.cls_l[idx] = (uint8_t)cl;
+                out.cls_r[idx] = (uint8_t)cr;
+            }
         } else {
             atomicOr(status, HM_ST_OUTPUT_FULL);
         }
@@ -843,8 +849,11 @@ uint64_t grid_for(uint64_t items, int per_cu = 8);
 // argument checks shared by the entry points (defined in hm_kmer.hip)
 int check_reads(const hm_reads_t *r, int k);
 int check_table(const hm_table_t *t);
-// key-order sort of an export (defined in hm_sort.hip); key_bits = 2k
+// key-order sort of an export (defined in hm_sort.hip); key_bits = 2k.  The
+// export writes each record's counters and classes into sort_staging(out)
+// (one 64-byte line per record), from where the sort gathers them.
 uint64_t sort_work_bytes(uint64_t capacity);
+uint4 *sort_staging(const hm_export_t &out);
 int sort_export(const hm_export_t &out, int key_bits, hipStream_t s);
 
 #define HM_LAUNCH_CHECK(what)                                \

@@ -138,13 +138,13 @@ __global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, 
 
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
-                                                   uint32_t *status) {
+                                                   uint32_t *status, uint4 *staged) {
     __shared__ uint16_t s_rank[kBlock / 64][kExportChunk];
     uint64_t dsum = 0, dxor = 0;
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
     for (uint64_t first = wave * kExportChunk; first < cap; first += n_waves * kExportChunk)
-        export_chunk<KW>(slots, first, cap, flags, out, status, s_rank[threadIdx.x >> 6], dsum, dxor);
+        export_chunk<KW>(slots, first, cap, flags, out, status, s_rank[threadIdx.x >> 6], dsum, dxor, staged);
     digest_flush(out, dsum, dxor);
 }
 
@@ -465,12 +465,13 @@ int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipSt
         if (rc) return rc;
     }
     const dim3 g((unsigned)grid_for(t->capacity, 16));
+    uint4 *staged = (flags & HM_EXPORT_SORTED) && out->capacity ? sort_staging(*out) : nullptr;
     if (t->k >= 32)
         hipLaunchKernelGGL(k_export<2>, g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), t->capacity,
-                           flags, *out, t->status);
+                           flags, *out, t->status, staged);
     else
         hipLaunchKernelGGL(k_export<1>, g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), t->capacity,
-                           flags, *out, t->status);
+                           flags, *out, t->status, staged);
     HM_LAUNCH_CHECK("hm_export_table");
     if (flags & HM_EXPORT_SORTED) return sort_export(*out, 2 * t->k, s);
     return HM_OK;

@@ -6,19 +6,20 @@
 // sets needs them in key order, i.e. lexicographic order of the k-mers (the
 // encoding puts the first base in the most significant bits).  Keys travel
 // with a 32-bit record index; the rest of each record (count, tallies,
-// classes) is staged once as one 64-byte line per record and gathered into
-// place at the end.
+// classes) is written by the export as one 64-byte line per record and
+// gathered into place at the end.
 //
 // Keys of 32 bits or more (k >= 16) are sorted most-significant bits first:
 //   1. two stable counting passes on the top 16 key bits (8 bits each, least
 //      significant of the two first) group the records by 16-bit prefix, in
 //      prefix order;
 //   2. k_sort_bounds finds where each of the 65536 prefix groups starts;
-//   3. k_sort_groups sorts every group on its own: one workgroup per group,
-//      the whole group in LDS and a bitonic network on the full key when it
-//      holds at most 4096 records (about 1500 on average at 10^8 records),
-//      else an in-workgroup least-significant-digit sort through global
-//      memory (a rare group: many distinct k-mers sharing their first 8 bases).
+//   3. k_sort_groups sorts every group on its own, one workgroup per group:
+//      a group of at most 4096 records (about 1500 on average at 10^8
+//      records) is ordered in LDS by three counting passes on the next 24 key
+//      bits plus an insertion step for the rare ties; a larger group (many
+//      distinct k-mers sharing their first 8 bases) takes in-workgroup
+//      counting passes through global memory.
 // Shorter keys (k < 16, at most 4 digits) take stable counting passes over
 // all their digits.  Either way each record crosses memory a few times
 // instead of once per 8 key bits.
@@ -172,17 +173,6 @@ __device__ __forceinline__ void tile_rank(const uint32_t (&dig)[kSortIpt], uint3
         pos[j] = valid ? tstart[d] + cnt[j][w][d] + below[j] : 0xFFFFu;
     }
     __syncthreads();
-}
-
-__global__ __launch_bounds__(kBlock) void k_sort_prep(hm_export_t out, uint4 *pay) {
-    const uint32_t n = records_in(out.n_out, out.capacity);
-    const uint4 *tl = reinterpret_cast<const uint4 *>(out.tl);
-    const uint4 *tr = reinterpret_cast<const uint4 *>(out.tr);
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
-        pay[4 * i] = tl[i];
-        pay[4 * i + 1] = tr[i];
-        pay[4 * i + 2] = make_uint4(out.count[i], out.cls_l[i] | (uint32_t)out.cls_r[i] << 8, 0u, 0u);
-    }
 }
 
 // Digit counts of one tile (digit = key bits [shift, shift + 8)); only the
@@ -342,86 +332,43 @@ __global__ __launch_bounds__(kBlock) void k_sort_bounds(const uint64_t *hi, cons
     }
 }
 
-constexpr uint32_t kPad = 0xFFFFFFFFu;  // index of a padding entry (record indices are < 2^32 - 1)
-
-// a < b, with padding entries above every record (and never below another)
 template <int KW>
-__device__ __forceinline__ bool key_less(uint64_t ahi, uint64_t alo, uint32_t aid, uint64_t bhi, uint64_t blo,
-                                         uint32_t bid) {
-    if (aid == kPad) return false;
-    if (bid == kPad) return true;
+__device__ __forceinline__ bool key_less(uint64_t ahi, uint64_t alo, uint64_t bhi, uint64_t blo) {
     if constexpr (KW == 2) return ahi < bhi || (ahi == bhi && alo < blo);
     return alo < blo;
 }
 
-// Sort every prefix group in place (keys x*, index xid); y* / yid are
-// scratch of the same size.  One workgroup per group.
+constexpr int kLowBits = 24;   // key bits below the prefix that the LDS passes sort on
+constexpr uint32_t kRunMax = 64;  // longest run of equal top bits ordered by insertion
+
+// Records of a group too large for LDS (or with long runs of equal top bits):
+// stable counting passes over all key bits below the prefix, the workgroup
+// walking the group tile by tile in order, between the group's ranges of x and
+// y; the result ends in y.  `smem` provides the ranking counters and tables.
 template <int KW>
-__global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t *xlo, uint32_t *xid, uint64_t *yhi,
-                                                        uint64_t *ylo, uint32_t *yid, const uint32_t *starts,
-                                                        uint32_t pshift, const uint64_t *n_out, uint64_t cap) {
-    // 80 KB: a group of kGroupMax records (hi, lo, index), or the fallback's
-    // ranking counters (32 KB) and digit tables
-    __shared__ uint64_t smem[kGroupMax * 5 / 2];
-    const uint32_t n = records_in(n_out, cap);
-    const uint32_t b = starts[blockIdx.x], e = min(starts[blockIdx.x + 1], n);  // the clamp only guards the arrays
-    if (e <= b + 1) return;  // empty or a single record: nothing to order
-    const uint32_t s = e - b;
+__device__ void group_sort_global(uint64_t *xhi, uint64_t *xlo, uint32_t *xid, uint64_t *yhi, uint64_t *ylo,
+                                  uint32_t *yid, uint32_t b, uint32_t e, uint32_t pshift, uint64_t *smem) {
     const int t = threadIdx.x;
-    if (s <= (uint32_t)kGroupMax) {
-        uint64_t *shi = smem, *slo = smem + kGroupMax;
-        uint32_t *sid = reinterpret_cast<uint32_t *>(smem + 2 * kGroupMax);
-        uint32_t m = 2;
-        while (m < s) m <<= 1;
-        for (uint32_t i = t; i < m; i += kBlock) {  // pad to a power of two with entries above every record
-            const bool ok = i < s;
-            if constexpr (KW == 2) shi[i] = ok ? xhi[b + i] : 0ull;
-            slo[i] = ok ? xlo[b + i] : 0ull;
-            sid[i] = ok ? xid[b + i] : kPad;
-        }
-        __syncthreads();
-        for (uint32_t size = 2; size <= m; size <<= 1) {
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t q = t; q < m / 2; q += kBlock) {
-                    const uint32_t i = 2 * q - (q & (stride - 1)), j = i + stride;
-                    const bool up = (i & size) == 0;
-                    const uint64_t ih = KW == 2 ? shi[i] : 0, jh = KW == 2 ? shi[j] : 0;
-                    const uint64_t il = slo[i], jl = slo[j];
-                    const uint32_t id = sid[i], jd = sid[j];
-                    // ascending half: swap when j < i; descending half: when i < j
-                    if (up ? key_less<KW>(jh, jl, jd, ih, il, id) : key_less<KW>(ih, il, id, jh, jl, jd)) {
-                        if constexpr (KW == 2) {
-                            shi[i] = jh;
-                            shi[j] = ih;
-                        }
-                        slo[i] = jl;
-                        slo[j] = il;
-                        sid[i] = jd;
-                        sid[j] = id;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        for (uint32_t i = t; i < s; i += kBlock) {
-            if constexpr (KW == 2) xhi[b + i] = shi[i];
-            xlo[b + i] = slo[i];
-            xid[b + i] = sid[i];
-        }
-        return;
-    }
-    // A group too large for LDS: stable counting passes over the bits below the
-    // prefix, the workgroup walking the group tile by tile in order, between
-    // the group's range of x and of y.
     uint16_t(*cnt)[kSortWaves][256] = reinterpret_cast<uint16_t(*)[kSortWaves][256]>(smem);
     uint32_t *h = reinterpret_cast<uint32_t *>(smem + kSortTile);  // after the ranking counters
     uint32_t *tstart = h + 256;                                    // 257 entries
     uint32_t *dbase = tstart + 260;                                // 256 entries
     uint32_t *wsum = dbase + 256;                                  // kSortWaves entries
+    const int passes = (int)((pshift + 7) / 8);
+    // start so that the last pass writes y
     uint64_t *sh_ = xhi, *sl = xlo, *dh = yhi, *dl = ylo;
     uint32_t *si = xid, *di = yid;
-    int passes = 0;
-    for (uint32_t shift = 0; shift < pshift; shift += 8, ++passes) {
+    if (!(passes & 1)) {  // an even number of passes: copy to y first, sort y -> x -> ... -> y
+        for (uint32_t i = b + t; i < e; i += kBlock) {
+            if constexpr (KW == 2) yhi[i] = xhi[i];
+            ylo[i] = xlo[i];
+            yid[i] = xid[i];
+        }
+        __syncthreads();
+        sh_ = yhi, sl = ylo, dh = xhi, dl = xlo, si = yid, di = xid;
+    }
+    if (passes == 0) return;  // no bits below the prefix (never for keys of 32 bits or more)
+    for (uint32_t shift = 0; shift < pshift; shift += 8) {
         h[t] = 0;
         __syncthreads();
         for (uint32_t i = b + t; i < e; i += kBlock) atomicAdd(&h[digit_at(KW == 2 ? sh_[i] : 0, sl[i], shift)], 1u);
@@ -431,17 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t 
         __syncthreads();
         for (uint32_t t0 = b; t0 < e; t0 += kSortTile) {
             const uint32_t tile_n = min((uint32_t)kSortTile, e - t0);
-            uint64_t khi[KW == 2 ? kSortIpt : 1], klo[kSortIpt];
-            uint32_t kid[kSortIpt], dig[kSortIpt], pos[kSortIpt];
+            uint32_t dig[kSortIpt], pos[kSortIpt];
 #pragma unroll
             for (int j = 0; j < kSortIpt; ++j) {
                 const uint32_t r = (uint32_t)j * kBlock + t;
                 const bool ok = r < tile_n;
-                uint64_t u = 0;
-                if constexpr (KW == 2) u = khi[j] = ok ? sh_[t0 + r] : 0;
-                klo[j] = ok ? sl[t0 + r] : 0;
-                kid[j] = ok ? si[t0 + r] : 0u;
-                dig[j] = digit_at(u, klo[j], shift);
+                dig[j] = ok ? digit_at(KW == 2 ? sh_[t0 + r] : 0, sl[t0 + r], shift) : 0u;
             }
             tile_rank(dig, tile_n, cnt, tstart, wsum, pos);
 #pragma unroll
@@ -450,9 +392,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t 
                 const uint32_t d = dig[j] & 255u;
                 const uint32_t g = dbase[d] + (pos[j] - tstart[d]);
                 if (g >= e) continue;  // never, when the counts agree
-                if constexpr (KW == 2) dh[g] = khi[j];
-                dl[g] = klo[j];
-                di[g] = kid[j];
+                const uint32_t from = t0 + (uint32_t)j * kBlock + t;  // read again: the tile is cache-resident
+                if constexpr (KW == 2) dh[g] = sh_[from];
+                dl[g] = sl[from];
+                di[g] = si[from];
             }
             __syncthreads();
             dbase[t] += tstart[t + 1] - tstart[t];  // this tile's records of digit t
@@ -468,12 +411,103 @@ __global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t 
         si = di;
         di = xi;
     }
-    if (passes & 1) {  // the result is in y: bring it back
-        for (uint32_t i = b + t; i < e; i += kBlock) {
-            if constexpr (KW == 2) xhi[i] = yhi[i];
-            xlo[i] = ylo[i];
-            xid[i] = yid[i];
+}
+
+// Sort every prefix group of x (keys, index) into the same range of y.  One
+// workgroup per group.  A group of at most kSortTile records is ordered in LDS
+// by permuting 16-bit positions: three stable counting passes on the kLowBits
+// key bits below the prefix (the records stay where they are), then runs of
+// records whose top bits are all equal, rare for distinct keys, are ordered by
+// insertion on the full key; finally the records are gathered from x into y
+// in order.  Larger groups, and groups with a run longer than kRunMax, take
+// the counting passes through global memory.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_sort_groups(uint64_t *xhi, uint64_t *xlo, uint32_t *xid, uint64_t *yhi,
+                                                        uint64_t *ylo, uint32_t *yid, const uint32_t *starts,
+                                                        uint32_t pshift, const uint64_t *n_out, uint64_t cap) {
+    // 32 KB ranking counters + 16 KB low bits + 2 x 8 KB positions + tables
+    constexpr int kWords = kSortTile + kSortTile / 2 + kSortTile / 2 + 320;
+    __shared__ uint64_t smem[kWords];
+    static_assert(sizeof(uint64_t) * kSortTile + 4 * kSortTile + 2 * 2 * kSortTile + 4 * 264 <= sizeof(uint64_t) * kWords,
+                  "group-sort LDS layout");
+    static_assert(sizeof(uint64_t) * kSortTile + 4 * 780 <= sizeof(uint64_t) * kWords, "fallback LDS layout");
+    __shared__ uint32_t flag;
+    const uint32_t n = records_in(n_out, cap);
+    const uint32_t b = starts[blockIdx.x], e = min(starts[blockIdx.x + 1], n);  // the clamp only guards the arrays
+    if (e <= b) return;
+    const uint32_t s = e - b;
+    const int t = threadIdx.x;
+    if (s > (uint32_t)kSortTile) {
+        group_sort_global<KW>(xhi, xlo, xid, yhi, ylo, yid, b, e, pshift, smem);
+        return;
+    }
+    uint16_t(*cnt)[kSortWaves][256] = reinterpret_cast<uint16_t(*)[kSortWaves][256]>(smem);
+    uint32_t *low = reinterpret_cast<uint32_t *>(smem + kSortTile);         // kSortTile entries
+    uint16_t *perm = reinterpret_cast<uint16_t *>(low + kSortTile);         // 2 x kSortTile entries
+    uint32_t *tstart = reinterpret_cast<uint32_t *>(perm + 2 * kSortTile);  // 257 entries
+    uint32_t *wsum = tstart + 260;
+    const uint32_t lbits = pshift < (uint32_t)kLowBits ? pshift : (uint32_t)kLowBits;
+    const uint32_t lshift = pshift - lbits;
+    const uint32_t lmask = (1u << lbits) - 1;
+    if (t == 0) flag = 0;
+    for (uint32_t q = t; q < s; q += kBlock) {
+        low[q] = (uint32_t)key_bits_at(KW == 2 ? xhi[b + q] : 0, xlo[b + q], lshift) & lmask;
+        perm[q] = (uint16_t)q;
+    }
+    __syncthreads();
+    uint16_t *cur = perm, *nxt = perm + kSortTile;
+    for (uint32_t shift = 0; shift < lbits; shift += 8) {
+        uint32_t dig[kSortIpt], pos[kSortIpt], src[kSortIpt];
+#pragma unroll
+        for (int j = 0; j < kSortIpt; ++j) {
+            const uint32_t q = (uint32_t)j * kBlock + t;
+            src[j] = q < s ? cur[q] : 0u;
+            dig[j] = (low[src[j]] >> shift) & 255u;
         }
+        tile_rank(dig, s, cnt, tstart, wsum, pos);
+#pragma unroll
+        for (int j = 0; j < kSortIpt; ++j)
+            if (pos[j] < s) nxt[pos[j]] = (uint16_t)src[j];
+        __syncthreads();
+        uint16_t *x = cur;
+        cur = nxt;
+        nxt = x;
+    }
+    // runs of equal low bits: order them by the full key (they share all the top bits)
+    if (lshift > 0) {
+        for (uint32_t q = t; q + 1 < s; q += kBlock) {
+            const uint32_t v = low[cur[q]];
+            if ((q > 0 && low[cur[q - 1]] == v) || low[cur[q + 1]] != v) continue;  // not the start of a run
+            uint32_t r = q + 1;
+            while (r < s && low[cur[r]] == v) ++r;
+            if (r - q > kRunMax) {
+                atomicOr(&flag, 1u);
+                continue;
+            }
+            for (uint32_t i = q + 1; i < r; ++i) {  // insertion sort of cur[q..r) by key
+                const uint16_t pi = cur[i];
+                const uint64_t ih = KW == 2 ? xhi[b + pi] : 0, il = xlo[b + pi];
+                uint32_t j = i;
+                while (j > q) {
+                    const uint16_t pj = cur[j - 1];
+                    if (!key_less<KW>(ih, il, KW == 2 ? xhi[b + pj] : 0, xlo[b + pj])) break;
+                    cur[j] = pj;
+                    --j;
+                }
+                cur[j] = pi;
+            }
+        }
+        __syncthreads();
+        if (flag) {  // a long run of equal top bits: take the general path
+            group_sort_global<KW>(xhi, xlo, xid, yhi, ylo, yid, b, e, pshift, smem);
+            return;
+        }
+    }
+    for (uint32_t q = t; q < s; q += kBlock) {
+        const uint32_t from = b + cur[q];
+        if constexpr (KW == 2) yhi[b + q] = xhi[from];
+        ylo[b + q] = xlo[from];
+        yid[b + q] = xid[from];
     }
 }
 
@@ -550,7 +584,7 @@ int sort_keys(const hm_export_t &out, const SortLayout &L, int key_bits, hipStre
     hipLaunchKernelGGL(k_sort_groups<KW>, dim3(kGroups), blk, 0, s, kh[0], kl[0], ix[1], kh[1], kl[1], ix[0],
                        L.starts, pshift, out.n_out, out.capacity);
     HM_LAUNCH_CHECK("sort groups");
-    hipLaunchKernelGGL(k_sort_final<KW>, sweep, blk, 0, s, kh[0], kl[0], ix[1], L.pay, out, 0);
+    hipLaunchKernelGGL(k_sort_final<KW>, sweep, blk, 0, s, kh[1], kl[1], ix[0], L.pay, out, 1);
     HM_LAUNCH_CHECK("sort gather");
     return HM_OK;
 }
@@ -559,11 +593,13 @@ int sort_keys(const hm_export_t &out, const SortLayout &L, int key_bits, hipStre
 
 uint64_t sort_work_bytes(uint64_t capacity) { return sort_layout(nullptr, capacity).bytes; }
 
+uint4 *sort_staging(const hm_export_t &out) { return sort_layout(out.sort_work, out.capacity).pay; }
+
+// The export has written keys to out.key_* and the rest of every record to
+// sort_staging(out).
 int sort_export(const hm_export_t &out, int key_bits, hipStream_t s) {
     if (out.capacity == 0) return HM_OK;
     const SortLayout L = sort_layout(out.sort_work, out.capacity);
-    hipLaunchKernelGGL(k_sort_prep, dim3((unsigned)grid_for(out.capacity, 16)), dim3(kBlock), 0, s, out, L.pay);
-    HM_LAUNCH_CHECK("sort prep");
     return key_bits > 64 ? sort_keys<2>(out, L, key_bits, s) : sort_keys<1>(out, L, key_bits, s);
 }
 

@@ -394,3 +394,25 @@ def test_sorted_export_large_prefix_group(k):
     assert_tables_equal(got, exp, "large group k=%d" % k)
     pref = (exp["key_hi"].astype(object) * 2 ** 64 + exp["key_lo"].astype(object)) >> (2 * k - 16)
     assert (pref == 0).sum() > 4096
+
+
+@pytest.mark.parametrize("k", [31, 51])
+def test_sorted_export_tie_runs(k):
+    """Keys sharing their first 20 bases (the 16-bit prefix and the next 24 bits): a run of 40 is
+    ordered by the insertion step, a run of 100 sends its group through the general path."""
+    rng = np.random.default_rng(4000 + k)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    p1 = np.frombuffer(b"AAAACCCCGGGGTTTTACGT", np.uint8)
+    p2 = np.frombuffer(b"CCCCAAAATTTTGGGGTGCA", np.uint8)
+    special = [np.concatenate([p1, rng.choice(acgt, k - 20)]) for _ in range(40)]
+    special += [np.concatenate([p2, rng.choice(acgt, k - 20)]) for _ in range(100)]
+    g = rng.choice(acgt, 30000)
+    st = rng.integers(0, g.size - 100, 3000)
+    reads = special + special + [g[s:s + 100] for s in st]
+    ascii = np.concatenate(reads)
+    off = np.zeros(len(reads) + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in reads])
+    qual = np.full(ascii.size, 40, np.uint8)
+    exp = oracle.run(ascii, qual, off, k, forward_only=True, n_threads=4)
+    got = kmer.analyze(ascii, qual, k, read_off=off, forward_only=True, export_flags=abi.HM_EXPORT_SORTED)
+    assert_tables_equal(got, exp, "tie runs k=%d" % k)
