@@ -163,3 +163,27 @@ def test_card_fixed_length_all_widths(k, L, fwd):
                        forward_only=fwd)
     exp = oracle_card(ascii, off, k, sk, heavy_min=4, forward_only=fwd)
     assert_card_equal(sk, got, exp, "fixed k=%d L=%d" % (k, L))
+
+
+@pytest.mark.parametrize("hll_p", [4, 16])
+def test_card_register_count_extremes(hll_p):
+    """16 registers (the smallest sketch, alpha_16) and 65536 (64 KB of registers per workgroup)."""
+    ascii, qual, off = random_read_set(970 + hll_p, 3000, 100, 150, genome_len=50000)
+    sk, got = gpu_card(ascii, off, 31, hll_p=hll_p, sample_log2=2, heavy_log2=3, heavy_min=3)
+    exp = oracle_card(ascii, off, 31, sk, heavy_min=3)
+    assert_card_equal(sk, got, exp, "p=%d" % hll_p)
+
+
+def test_card_heavy_list_longer_than_buffer():
+    """More heavy hitters than the key buffer holds: the count is complete, the buffer holds a
+    subset of the true heavy keys."""
+    ascii, qual, off = random_read_set(980, 3000, 100, 150, genome_len=5000)  # deep coverage
+    a = torch.from_numpy(ascii).cuda()
+    p = kmer.pack_reads(a, torch.full_like(a, 40), read_off=torch.from_numpy(off).cuda())
+    sk = kmer.CardSketch(21, int(off[-1]), hll_p=10, sample_log2=0, heavy_log2=0)
+    got = sk.run([p], heavy_min=40, heavy_cap=16)
+    exp = oracle.card(ascii, off, 21, hll_p=10, sample_log2=0, heavy_log2=0, heavy_min=40)
+    assert got.n_heavy == exp["n_heavy"] > 16
+    assert len(got.heavy_hi) == 16
+    allk = set(zip(exp["heavy_hi"].tolist(), exp["heavy_lo"].tolist()))
+    assert set(zip(got.heavy_hi.tolist(), got.heavy_lo.tolist())) <= allk
