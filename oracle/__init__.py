@@ -85,6 +85,15 @@ def lib():
                                ctypes.c_void_p, ctypes.POINTER(OrcCardResult), ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_uint64]
         L.orc_card.restype = ctypes.c_int
+        L.orc_contigs.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                                          ctypes.POINTER(ctypes.c_int64)]
+        L.orc_contigs.restype = ctypes.c_void_p
+        L.orc_contigs_bases.argtypes = [ctypes.c_void_p]
+        L.orc_contigs_bases.restype = ctypes.c_int64
+        L.orc_contigs_fetch.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_contigs_fetch.restype = None
+        L.orc_contigs_free.argtypes = [ctypes.c_void_p]
+        L.orc_contigs_free.restype = None
         _LIB = L
     return _LIB
 
@@ -179,3 +188,28 @@ def card(ascii: np.ndarray, read_off: np.ndarray, k: int, hll_p: int = 14, sampl
     return {"registers": regs, "estimate": res.estimate, "sampled_distinct": int(res.sampled_distinct),
             "sampled_kept": int(res.sampled_kept), "n_heavy": int(res.n_heavy), "heavy_hi": hh[:n],
             "heavy_lo": hl[:n], "positions": int(res.positions), "seconds": secs}
+
+
+def contigs(table: dict, k: int, forward_only: bool = False) -> list[str]:
+    """Contigs of the UU k-mers of a table (as returned by run(); non-UU records are ignored),
+    sorted (see orc_contigs in kmer_oracle.cpp for what a contig is)."""
+    m = uu_mask(table)
+    hi = np.ascontiguousarray(table["key_hi"][m], dtype=np.uint64)
+    lo = np.ascontiguousarray(table["key_lo"][m], dtype=np.uint64)
+    cl = np.ascontiguousarray(table["cls_l"][m], dtype=np.uint8)
+    cr = np.ascontiguousarray(table["cls_r"][m], dtype=np.uint8)
+    n = ctypes.c_int64()
+    L = lib()
+    h = L.orc_contigs(hi.ctypes.data, lo.ctypes.data, cl.ctypes.data, cr.ctypes.data, hi.size, k,
+                      1 if forward_only else 0, ctypes.byref(n))
+    if not h:
+        raise ValueError("oracle contig generation failed")
+    try:
+        total = L.orc_contigs_bases(h)
+        seq = np.zeros(max(total, 1), np.uint8)
+        off = np.zeros(n.value + 1, np.int64)
+        L.orc_contigs_fetch(h, seq.ctypes.data, off.ctypes.data)
+    finally:
+        L.orc_contigs_free(h)
+    b = seq.tobytes()
+    return [b[off[i]:off[i + 1]].decode() for i in range(n.value)]

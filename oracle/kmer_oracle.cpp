@@ -49,6 +49,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -439,5 +440,205 @@ int orc_card(const uint8_t *ascii, const int64_t *read_off, int64_t n_reads, con
     res->positions = npos[0];
     return ORC_OK;
 }
+
+
+/* ---- contig generation (section "Parallel contig generation") ----
+ *
+ * Input: the UU k-mers (keys with their unique left and right extension
+ * bases, as exported).  What is computed:
+ *   - a k-mer is read in its key orientation (fwd) or reverse-complemented
+ *     (rc); read rc, its right extension is the complement of its stored left
+ *     one and vice versa;
+ *   - stepping right from an oriented k-mer s with right extension b gives
+ *     s' = (s without its first base) + b; s' is looked up by its key; the
+ *     step exists when the k-mer is there and its left extension, read in the
+ *     orientation of s', is the first base of s (the link agrees from both
+ *     ends); stepping left mirrors this;
+ *   - every side of a k-mer then has at most one link, so the k-mers form
+ *     simple paths and cycles; a step that would leave a k-mer's side and
+ *     arrive back at the same side of the same k-mer (a hairpin) is not a link;
+ *   - a path is spelled from one end: the first oriented k-mer, then the right
+ *     extension of each k-mer before the next; the contig is the smaller of
+ *     that string and its reverse complement;
+ *   - a cycle of n k-mers is spelled from its smallest key, in fwd
+ *     orientation, stepping right: that k-mer and the next n - 1 bases.
+ * Contigs are returned sorted.  (Readings listed in the design notes.) */
+
+struct ContigResult {
+    std::vector<std::string> seq;
+};
+
+namespace {
+
+struct DbgNode {
+    u128 key;
+    int cl, cr;
+};
+
+struct Dbg {
+    int k;
+    bool fwd_only;
+    u128 mask;
+    std::vector<DbgNode> nodes;
+    std::unordered_map<u128, int64_t, KeyHash> index;
+
+    u128 rc(u128 x) const {
+        u128 r = 0;
+        for (int i = 0; i < k; ++i) {
+            r = (r << 2) | (u128)(3 - (int)(x & 3));
+            x >>= 2;
+        }
+        return r;
+    }
+    u128 seq(int64_t i, int o) const { return o ? rc(nodes[i].key) : nodes[i].key; }
+    int right_ext(int64_t i, int o) const { return o ? nodes[i].cl : nodes[i].cr; }
+    int left_ext(int64_t i, int o) const { return o ? 3 - nodes[i].cr : nodes[i].cl; }
+    /* oriented k-mer -> (node, orientation) of its key, or node -1 */
+    std::pair<int64_t, int> locate(u128 s) const {
+        u128 key = s;
+        int o = 0;
+        if (!fwd_only) {
+            const u128 r = rc(s);
+            if (r < s) {
+                key = r;
+                o = 1;
+            }
+        }
+        auto it = index.find(key);
+        return it == index.end() ? std::make_pair((int64_t)-1, 0) : std::make_pair(it->second, o);
+    }
+    /* step right (dir 0) or left (dir 1) from (i, o) */
+    bool step(int64_t i, int o, int dir, int64_t &j, int &o2) const {
+        const u128 s = seq(i, o);
+        u128 t;
+        int back_base;
+        if (dir == 0) {
+            t = ((s << 2) | (u128)right_ext(i, o)) & mask;
+            back_base = (int)(s >> (2 * (k - 1))) & 3;
+        } else {
+            t = (s >> 2) | ((u128)left_ext(i, o) << (2 * (k - 1)));
+            back_base = (int)(s & 3);
+        }
+        auto f = locate(t);
+        if (f.first < 0) return false;
+        j = f.first;
+        o2 = f.second;
+        const int back = dir == 0 ? left_ext(j, o2) : right_ext(j, o2);
+        if (back != back_base) return false;
+        /* the side left: right side of the key when (dir 0, o 0) or (dir 1, o 1);
+           the side reached: left side of the key when (dir 0, o2 0) or (dir 1, o2 1) */
+        if (j == i) {
+            const int left_side = (dir == 0) == (o == 0) ? 1 : 0;     /* 1: we left through the key's right side */
+            const int arrive_right = (dir == 0) == (o2 == 0) ? 0 : 1; /* 1: we arrive at the key's right side */
+            if (left_side == arrive_right) return false;             /* hairpin: same side */
+        }
+        return true;
+    }
+    std::string spell(u128 s) const {
+        std::string out(k, 'A');
+        for (int i = k - 1; i >= 0; --i) {
+            out[i] = "ACGT"[(int)(s & 3)];
+            s >>= 2;
+        }
+        return out;
+    }
+};
+
+std::string revcomp_str(const std::string &x) {
+    std::string r(x.rbegin(), x.rend());
+    for (char &c : r) c = c == 'A' ? 'T' : c == 'C' ? 'G' : c == 'G' ? 'C' : 'A';
+    return r;
+}
+
+}  // namespace
+
+void *orc_contigs(const uint64_t *key_hi, const uint64_t *key_lo, const uint8_t *cls_l, const uint8_t *cls_r,
+                  int64_t n, int32_t k, int32_t forward_only, int64_t *n_contigs) {
+    *n_contigs = -1;
+    if (k < 1 || k > 63 || n < 0) return nullptr;
+    Dbg g;
+    g.k = k;
+    g.fwd_only = forward_only != 0;
+    g.mask = (k == 64) ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
+    g.nodes.resize(n);
+    g.index.reserve((size_t)n * 2);
+    for (int64_t i = 0; i < n; ++i) {
+        if (cls_l[i] > 3 || cls_r[i] > 3) return nullptr; /* not a UU k-mer */
+        g.nodes[i] = DbgNode{((u128)key_hi[i] << 64) | key_lo[i], cls_l[i], cls_r[i]};
+        g.index[g.nodes[i].key] = i;
+    }
+    ContigResult *res = new ContigResult();
+    std::vector<char> visited(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        if (visited[i]) continue;
+        /* walk left from (i, fwd) to the end of the path, or back to i on a cycle */
+        int64_t cur = i, j;
+        int o = 0, o2;
+        bool cycle = false;
+        while (g.step(cur, o, 1, j, o2)) {
+            if (j == i) {
+                cycle = true;
+                break;
+            }
+            cur = j;
+            o = o2;
+        }
+        if (cycle) {
+            /* the cycle's nodes, its smallest key, then spell from there in fwd orientation */
+            int64_t m = i, c = i;
+            int oc = 0;
+            while (g.step(c, oc, 0, j, o2) && j != i) {
+                c = j;
+                oc = o2;
+                if (g.nodes[c].key < g.nodes[m].key) m = c;
+            }
+            std::string sq = g.spell(g.seq(m, 0));
+            visited[m] = 1;
+            c = m;
+            oc = 0;
+            while (g.step(c, oc, 0, j, o2) && j != m) {
+                sq.push_back("ACGT"[g.right_ext(c, oc)]);
+                c = j;
+                oc = o2;
+                visited[c] = 1;
+            }
+            res->seq.push_back(sq);
+            continue;
+        }
+        std::string sq = g.spell(g.seq(cur, o));
+        visited[cur] = 1;
+        while (g.step(cur, o, 0, j, o2)) {
+            sq.push_back("ACGT"[g.right_ext(cur, o)]);
+            cur = j;
+            o = o2;
+            visited[cur] = 1;
+        }
+        const std::string r = revcomp_str(sq);
+        res->seq.push_back(g.fwd_only || sq <= r ? sq : r);
+    }
+    std::sort(res->seq.begin(), res->seq.end());
+    *n_contigs = (int64_t)res->seq.size();
+    return res;
+}
+
+int64_t orc_contigs_bases(void *handle) {
+    int64_t t = 0;
+    for (auto &x : ((ContigResult *)handle)->seq) t += (int64_t)x.size();
+    return t;
+}
+
+/* concatenated contigs (ASCII) and n + 1 offsets */
+void orc_contigs_fetch(void *handle, char *seq, int64_t *off) {
+    const ContigResult *r = (const ContigResult *)handle;
+    int64_t p = 0;
+    off[0] = 0;
+    for (size_t i = 0; i < r->seq.size(); ++i) {
+        memcpy(seq + p, r->seq[i].data(), r->seq[i].size());
+        p += (int64_t)r->seq[i].size();
+        off[i + 1] = p;
+    }
+}
+
+void orc_contigs_free(void *handle) { delete (ContigResult *)handle; }
 
 }  /* extern "C" */

@@ -133,3 +133,83 @@ def card(reads: list[str], k: int, hll_p: int, sample_log2: int, heavy_log2: int
     return {"registers": regs, "sampled_distinct": len(sample),
             "sampled_kept": sum(1 for c in sample.values() if c >= min_depth),
             "heavy": sorted(x for x, c in heavy.items() if c >= heavy_min), "positions": positions}
+
+
+def contigs(table: dict[int, tuple], k: int, forward_only: bool = False) -> list[str]:
+    """Contigs of the UU k-mers of a brute-force table, with Python strings: two UU k-mers are
+    linked when the extension of one spells the other and the other's extension spells the first
+    back (a link from a side of a k-mer to the same side is not one); paths are spelled from an
+    end and given as min(S, revcomp(S)), cycles from their smallest k-mer read forward."""
+    uu = {key: (v[3], v[4]) for key, v in table.items() if v[3] < 4 and v[4] < 4}
+
+    def spell(key):
+        return "".join(BASES[(key >> (2 * (k - 1 - i))) & 3] for i in range(k))
+
+    def canon(s):
+        return s if forward_only else min(s, revcomp(s))
+
+    def ext(s, side):
+        c = canon(s)
+        cl, cr = uu[enc(c)]
+        if c == s:
+            return BASES[cr] if side == "R" else BASES[cl]
+        return COMP[BASES[cl]] if side == "R" else COMP[BASES[cr]]
+
+    def step(s, d):
+        t = s[1:] + ext(s, "R") if d == "R" else ext(s, "L") + s[:-1]
+        if enc(canon(t)) not in uu:
+            return None
+        if (ext(t, "L") if d == "R" else ext(t, "R")) != (s[0] if d == "R" else s[-1]):
+            return None
+        if canon(t) == canon(s):
+            leaves = "R" if (d == "R") == (s == canon(s)) else "L"
+            arrives = "L" if (d == "R") == (t == canon(t)) else "R"
+            if leaves == arrives:
+                return None
+        return t
+
+    done, out = set(), []
+    for key in sorted(uu):
+        if key in done:
+            continue
+        start = spell(key)
+        s, cycle = start, False
+        while True:
+            t = step(s, "L")
+            if t is None:
+                break
+            if canon(t) == start:
+                cycle = True
+                break
+            s = t
+        if cycle:
+            ring, s = [start], start
+            while True:
+                t = step(s, "R")
+                if t is None or canon(t) == start:
+                    break
+                ring.append(canon(t))
+                s = t
+            m = min(ring)
+            seq, s = m, m
+            done.add(enc(m))
+            while True:
+                t = step(s, "R")
+                if t is None or canon(t) == m:
+                    break
+                seq += t[-1]
+                done.add(enc(canon(t)))
+                s = t
+            out.append(seq)
+            continue
+        seq = s
+        done.add(enc(canon(s)))
+        while True:
+            t = step(s, "R")
+            if t is None:
+                break
+            seq += t[-1]
+            done.add(enc(canon(t)))
+            s = t
+        out.append(seq if forward_only else min(seq, revcomp(seq)))
+    return sorted(out)
