@@ -491,7 +491,7 @@ struct Dbg {
         return r;
     }
     u128 seq(int64_t i, int o) const { return o ? rc(nodes[i].key) : nodes[i].key; }
-    int right_ext(int64_t i, int o) const { return o ? nodes[i].cl : nodes[i].cr; }
+    int right_ext(int64_t i, int o) const { return o ? 3 - nodes[i].cl : nodes[i].cr; }
     int left_ext(int64_t i, int o) const { return o ? 3 - nodes[i].cr : nodes[i].cl; }
     /* oriented k-mer -> (node, orientation) of its key, or node -1 */
     std::pair<int64_t, int> locate(u128 s) const {
