@@ -64,6 +64,7 @@ extern "C" {
 #define HM_ST_OVERFLOW 4u
 #define HM_ST_OUTPUT_FULL 8u
 #define HM_ST_TIMEOUT 16u
+#define HM_ST_DUPLICATE 32u /* hm_contigs: a key appears twice in the input */
 
 /* hm_params_t.flags */
 #define HM_FORWARD_ONLY 1u /* key = forward encoding (no canonical form); allows even k */
@@ -330,6 +331,56 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
  * heavy_cap is 0). */
 int hm_card_summary(const hm_card_t *c, uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,
                     uint64_t heavy_cap, hm_card_summary_t *out, hipStream_t stream);
+
+
+/* ---- contig generation (section "Parallel contig generation") ---------- */
+
+/* The UU k-mers form the de Bruijn graph: a k-mer's two-letter value names
+ * the base before and after it, so a contig grows by looking up the k-mer
+ * spelled by its last k-1 bases and its extension, until a lookup fails.
+ * Two UU k-mers are linked when the extension of each spells the other
+ * (keys are canonical: a k-mer read reverse-complemented has the complement
+ * of its stored left extension on its right, and vice versa; a link from a
+ * side of a k-mer back to the same side is not one).  Every side then has at
+ * most one link, so the k-mers form simple paths and cycles, and the contigs
+ * are unique: a path is spelled from one end (its first k-mer, then one base
+ * per further k-mer) and given as the smaller of that string and its
+ * reverse complement; a cycle of n k-mers is spelled from its smallest key,
+ * read in key orientation, stepping right: k + n - 1 bases.  With
+ * HM_FORWARD_ONLY keys are forward k-mers and no reverse complement is taken.
+ *
+ * The paper grows subcontigs from random seeds with remote atomics to settle
+ * two walkers meeting; here every k-mer finds its successor at once and the
+ * paths are ranked by pointer jumping (log-depth, no seeds), which gives the
+ * same contigs. */
+typedef struct {
+    uint8_t *seq;          /* contig bases (ASCII A, C, G, T), concatenated */
+    uint64_t seq_capacity; /* bytes of seq */
+    uint64_t *off;         /* contig c is seq[off[c], off[c + 1]); off_capacity + 1 entries */
+    uint64_t off_capacity; /* most contigs */
+    uint64_t *counts;      /* device, 2 words: contigs and bases (the numbers needed, on overflow) */
+    uint32_t *status;      /* device status word: HM_ST_OUTPUT_FULL, HM_ST_DUPLICATE, HM_ST_TABLE_FULL */
+    void *work;            /* device scratch, 256-byte aligned, at least hm_contigs_work_bytes(uu capacity) */
+    uint64_t work_bytes;
+} hm_contigs_t;
+
+/* Scratch of hm_contigs for an input of up to `capacity` records: about 120
+ * bytes per record. */
+size_t hm_contigs_work_bytes(uint64_t capacity);
+
+/* Contigs of the UU k-mers among the records of `uu` (an export: key_hi,
+ * key_lo, cls_l, cls_r of min(*uu->n_out, uu->capacity) records, in any
+ * order, keys distinct; records whose class on either side is not a base
+ * (0..3) are not part of the graph; other fields unused; capacity < 2^29).
+ * k and flags (HM_FORWARD_ONLY) as for the counting passes.  Clears
+ * out->counts and out->status first.  Contig c occupies seq[off[c],
+ * off[c + 1]); contigs come in no particular order, and off[counts[0]] =
+ * counts[1].  Asynchronous on `stream`, no host synchronization: the pointer
+ * jumping stops on the device.  Returns HM_EINVAL on bad arguments (nothing
+ * launched).  After the stream, out->status reports HM_ST_OUTPUT_FULL (more
+ * contigs or bases than the capacities: counts hold the numbers needed, the
+ * output is invalid) or HM_ST_DUPLICATE (a key appears twice: no output). */
+int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *out, hipStream_t stream);
 
 
 /* ---- batched form: many read sets, one persistent launch -------------- */

@@ -24,6 +24,7 @@ HM_ST_LIST_FULL = 2
 HM_ST_OVERFLOW = 4
 HM_ST_OUTPUT_FULL = 8
 HM_ST_TIMEOUT = 16
+HM_ST_DUPLICATE = 32
 
 HM_FORWARD_ONLY = 1
 HM_BLOOM_BYPASS = 2
@@ -92,6 +93,12 @@ class CardSummary(ctypes.Structure):
                 ("sampled_kept", ctypes.c_uint64), ("n_heavy", ctypes.c_uint64), ("positions", ctypes.c_uint64)]
 
 
+class Contigs(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_void_p), ("seq_capacity", ctypes.c_uint64), ("off", ctypes.c_void_p),
+                ("off_capacity", ctypes.c_uint64), ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_uint64)]
+
+
 class BatchSet(ctypes.Structure):
     _fields_ = [("ascii", ctypes.c_void_p), ("qual", ctypes.c_void_p), ("n_reads", ctypes.c_int64),
                 ("read_len", ctypes.c_int32), ("bases2", ctypes.c_void_p), ("nmask", ctypes.c_void_p),
@@ -133,6 +140,8 @@ SIGNATURES = {
     "hm_card_init": ([P(Card), vp], ctypes.c_int),
     "hm_cardinality": ([P(Reads), P(Params), P(Card), vp], ctypes.c_int),
     "hm_card_summary": ([P(Card), ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
+    "hm_contigs_work_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_contigs": ([P(Export), ctypes.c_int32, ctypes.c_uint32, P(Contigs), vp], ctypes.c_int),
     "hm_batch_work_bytes": ([ctypes.c_int32], ctypes.c_size_t),
     "hm_batch_prepare": ([P(BatchSet), ctypes.c_int32, P(Params), ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint32,
                           P(BatchTuning), vp, ctypes.c_size_t, P(BatchPlan), vp], ctypes.c_int),

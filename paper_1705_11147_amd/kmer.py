@@ -153,6 +153,92 @@ class Records:
         d = self.digest.cpu().numpy().view(np.uint64)
         return int(d[0]), int(d[1])
 
+    @classmethod
+    def from_numpy(cls, t: dict, device="cuda") -> "Records":
+        """A device buffer holding host records (keys and classes; counters zero)."""
+        n = len(t["key_hi"])
+        r = cls(n, device=device)
+        if n:
+            r.key_hi[:n] = torch.from_numpy(np.ascontiguousarray(t["key_hi"], np.uint64).view(np.int64)).to(device)
+            r.key_lo[:n] = torch.from_numpy(np.ascontiguousarray(t["key_lo"], np.uint64).view(np.int64)).to(device)
+            r.cls_l[:n] = torch.from_numpy(np.ascontiguousarray(t["cls_l"], np.uint8)).to(device)
+            r.cls_r[:n] = torch.from_numpy(np.ascontiguousarray(t["cls_r"], np.uint8)).to(device)
+        r.count.zero_()
+        r.tl.zero_()
+        r.tr.zero_()
+        r.n_out.fill_(n)
+        return r
+
+
+class ContigSet:
+    """Contigs of the UU records of an export buffer (hm_contigs).
+
+    capacity: records of the input buffers it serves; seq_capacity and
+    off_capacity bound the bases and contigs (defaults: two bases per record
+    plus one k-mer per 64 records, and one contig per 16 records); run()
+    grows them when the device reports they were too small."""
+
+    def __init__(self, capacity: int, k: int, seq_capacity: int | None = None, off_capacity: int | None = None,
+                 device="cuda"):
+        self.capacity, self.k, self.device = int(capacity), int(k), device
+        need = int(abi.lib().hm_contigs_work_bytes(self.capacity))
+        if need == 0:
+            raise ValueError("contig generation takes fewer than 2^29 records")
+        self.work = torch.empty(need // 8 + 64, dtype=torch.int64, device=device)
+        self.counts = torch.zeros(2, dtype=torch.int64, device=device)
+        self.status_buf = torch.zeros(1, dtype=torch.int32, device=device)
+        self._alloc(seq_capacity if seq_capacity is not None else 2 * self.capacity + self.k * (self.capacity // 64 + 16),
+                    off_capacity if off_capacity is not None else self.capacity // 16 + 1024)
+
+    def _alloc(self, seq_capacity: int, off_capacity: int):
+        self.seq_capacity, self.off_capacity = int(seq_capacity), int(off_capacity)
+        self.seq = torch.empty(max(self.seq_capacity, 1), dtype=torch.uint8, device=self.device)
+        self.off = torch.empty(self.off_capacity + 1, dtype=torch.int64, device=self.device)
+
+    def struct(self) -> abi.Contigs:
+        base = self.work.data_ptr()
+        ptr = (base + 255) // 256 * 256
+        return abi.Contigs(self.seq.data_ptr(), self.seq_capacity, self.off.data_ptr(), self.off_capacity,
+                           self.counts.data_ptr(), self.status_buf.data_ptr(), ptr,
+                           self.work.numel() * 8 - (ptr - base))
+
+    def launch(self, records: Records, forward_only: bool = False, stream=None):
+        """Queue the generation on the stream (no synchronization)."""
+        if records.capacity > self.capacity:
+            raise ValueError("input buffer holds %d records, set sized for %d" % (records.capacity, self.capacity))
+        ex = records.struct(digest=False)
+        cs = self.struct()
+        abi.call("hm_contigs", ctypes.byref(ex), self.k, abi.HM_FORWARD_ONLY if forward_only else 0,
+                 ctypes.byref(cs), _stream(stream))
+
+    def run(self, records: Records, forward_only: bool = False, stream=None, retries: int = 2) -> int:
+        """Generate, growing the outputs if they were too small; returns the status word."""
+        for _ in range(retries + 1):
+            self.launch(records, forward_only, stream)
+            st = int(self.status_buf.item())
+            if not st & abi.HM_ST_OUTPUT_FULL:
+                return st
+            nc, nb = (int(x) for x in self.counts.cpu().numpy())
+            self._alloc(max(nb, self.seq_capacity), max(nc, self.off_capacity))
+        return st
+
+    def to_list(self, sort: bool = True) -> list[str]:
+        nc, nb = (int(x) for x in self.counts.cpu().numpy())
+        off = self.off[:nc + 1].cpu().numpy()
+        b = self.seq[:nb].cpu().numpy().tobytes()
+        out = [b[off[i]:off[i + 1]].decode() for i in range(nc)]
+        return sorted(out) if sort else out
+
+
+def contigs(records: Records, k: int, forward_only: bool = False, device=None) -> list[str]:
+    """Sorted contigs of the UU records in an export buffer."""
+    cs = ContigSet(records.capacity, k, device=device or records.device)
+    st = cs.run(records, forward_only)
+    if st:
+        raise abi.HmError(abi.HM_EOUTPUT if st & abi.HM_ST_OUTPUT_FULL else abi.HM_EINVAL, "hm_contigs",
+                          "status 0x%x" % st)
+    return cs.to_list()
+
 
 class KmerCounter:
     """One count table with its Bloom filter and first-occurrence list.

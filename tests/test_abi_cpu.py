@@ -120,7 +120,7 @@ def test_package_import_is_lazy_and_loud():
 
 C_NAMES = {"Reads": "hm_reads_t", "Params": "hm_params_t", "Table": "hm_table_t", "Bloom": "hm_bloom_t",
            "List": "hm_list_t", "Export": "hm_export_t", "Card": "hm_card_t", "CardSummary": "hm_card_summary_t",
-           "BatchSet": "hm_batch_set_t",
+           "Contigs": "hm_contigs_t", "BatchSet": "hm_batch_set_t",
            "BatchTuning": "hm_batch_tuning_t", "BatchPlan": "hm_batch_plan_t"}
 
 
@@ -179,3 +179,28 @@ def test_heavy_list_rejections(L):
     t = abi.Table(64, 1024, 0, 31, 64, None, None, 3, 0)  # keys NULL
     assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(p), None, ctypes.byref(t), None, None) == abi.HM_EINVAL
     assert "heavy" in abi.last_error()
+
+
+def test_contigs_scratch_and_rejections(L):
+    """hm_contigs_work_bytes and the host-side checks of hm_contigs (no device call)."""
+    assert L.hm_contigs_work_bytes(0) > 0
+    w = L.hm_contigs_work_bytes(1 << 20)
+    assert 96 << 20 <= w <= 120 << 20  # about 100 bytes per record
+    assert L.hm_contigs_work_bytes(1 << 29) == 0  # too many records
+    e = abi.Export(8, 8, None, None, None, 8, 8, 1000, 8, None)
+    c = abi.Contigs(8, 100, 8, 10, 8, 8, 256, w)
+    assert L.hm_contigs(ctypes.byref(e), 20, 0, ctypes.byref(c), None) == abi.HM_EINVAL  # even k, canonical
+    assert L.hm_contigs(ctypes.byref(e), 0, abi.HM_FORWARD_ONLY, ctypes.byref(c), None) == abi.HM_EINVAL
+    assert L.hm_contigs(ctypes.byref(e), 21, 4, ctypes.byref(c), None) == abi.HM_EINVAL  # unknown flag
+    assert L.hm_contigs(None, 21, 0, ctypes.byref(c), None) == abi.HM_EINVAL
+    e2 = abi.Export(8, 8, None, None, None, 8, 8, 1 << 29, 8, None)
+    assert L.hm_contigs(ctypes.byref(e2), 21, 0, ctypes.byref(c), None) == abi.HM_EINVAL  # too many records
+    e3 = abi.Export(None, 8, None, None, None, 8, 8, 1000, 8, None)
+    assert L.hm_contigs(ctypes.byref(e3), 21, 0, ctypes.byref(c), None) == abi.HM_EINVAL  # no keys
+    c2 = abi.Contigs(8, 100, 8, 10, 8, 8, 264, w)
+    assert L.hm_contigs(ctypes.byref(e), 21, 0, ctypes.byref(c2), None) == abi.HM_EINVAL  # misaligned work
+    c3 = abi.Contigs(8, 100, 8, 10, 8, 8, 256, L.hm_contigs_work_bytes(1000) - 1)
+    assert L.hm_contigs(ctypes.byref(e), 21, 0, ctypes.byref(c3), None) == abi.HM_EINVAL  # work too small
+    c4 = abi.Contigs(None, 100, 8, 10, 8, 8, 256, w)
+    assert L.hm_contigs(ctypes.byref(e), 21, 0, ctypes.byref(c4), None) == abi.HM_EINVAL  # no seq
+    assert abi.last_error()
