@@ -203,6 +203,42 @@ def run_serving(args, dev, log):
     return out
 
 
+def measure_contigs(kc, k, n_records, stream, log, reps=3):
+    """Time contig generation (hm_contigs) over the UU records of the bench table, outside the timed
+    step, and check that the contigs hold every UU k-mer once."""
+    import torch
+    from paper_1705_11147_amd import abi, kmer
+    uu = kmer.Records(n_records, device=kc.device)
+    kc.export(uu, abi.HM_EXPORT_CLASSIFY | abi.HM_EXPORT_UU_ONLY, digest=False)
+    abi.check(kc.status(), "UU export")
+    n_uu = int(uu.n_out.item())
+    cs = kmer.ContigSet(uu.capacity, k, device=kc.device)
+    st = cs.run(uu)  # sizes the outputs
+    assert st == 0, "contig generation status 0x%x" % st
+    ref = tuple(int(x) for x in cs.counts.cpu().numpy())
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        cs.launch(uu, stream=stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+    assert int(cs.status_buf.item()) == 0 and tuple(int(x) for x in cs.counts.cpu().numpy()) == ref
+    nc, nb = ref
+    assert nb - nc * (k - 1) == n_uu, "contigs do not hold every UU k-mer once"
+    lens = (cs.off[1:nc + 1] - cs.off[:nc]).sort(descending=True).values
+    csum = lens.cumsum(0)
+    n50 = int(lens[int((csum >= (nb + 1) // 2).nonzero()[0].item())].item()) if nc else 0
+    t = float(np.median(ms))
+    res = {"uu_kmers": n_uu, "contigs": nc, "bases": nb, "n50": n50, "longest": int(lens[0].item()) if nc else 0,
+           "ms": round(t, 3), "uu_kmers_per_s": round(n_uu / (t / 1000), 1),
+           "work_bytes": int(cs.work.numel() * 8)}
+    log("contig generation: %s" % res)
+    del cs, uu
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +251,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
+    ap.add_argument("--no-contigs", action="store_true", help="skip the contig generation measurement")
     ap.add_argument("--no-heavy", action="store_true",
                     help="count heavy hitters through the table instead of workgroup-local counters")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
@@ -391,6 +428,9 @@ def main():
     sorted_export = None
     if not args.no_sort:
         sorted_export = measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log)
+    contigs = None
+    if not args.no_contigs:
+        contigs = measure_contigs(kc, k, n_records, stream, log)
 
     cpu = None
     if not args.no_cpu:
@@ -435,6 +475,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sorted_export": sorted_export,
+        "contigs": contigs,
         "batched": batched,
         "serving": serving,
     }

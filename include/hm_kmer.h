@@ -364,8 +364,9 @@ typedef struct {
     uint64_t work_bytes;
 } hm_contigs_t;
 
-/* Scratch of hm_contigs for an input of up to `capacity` records: about 120
- * bytes per record. */
+/* Scratch of hm_contigs for an input of up to `capacity` records: 136 bytes
+ * per record (a 32-byte index slot per record at half load, and per reading
+ * of a k-mer its links, ranks and list entries), plus 512 bytes. */
 size_t hm_contigs_work_bytes(uint64_t capacity);
 
 /* Contigs of the UU k-mers among the records of `uu` (an export: key_hi,
@@ -379,7 +380,8 @@ size_t hm_contigs_work_bytes(uint64_t capacity);
  * jumping stops on the device.  Returns HM_EINVAL on bad arguments (nothing
  * launched).  After the stream, out->status reports HM_ST_OUTPUT_FULL (more
  * contigs or bases than the capacities: counts hold the numbers needed, the
- * output is invalid) or HM_ST_DUPLICATE (a key appears twice: no output). */
+ * output is invalid) or HM_ST_DUPLICATE (a key appears twice: no output);
+ * HM_ST_TIMEOUT would mean a ranking bound was not enough (not expected). */
 int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *out, hipStream_t stream);
 
 

@@ -5,18 +5,22 @@
 // The paper walks the graph from seeds, one walker per seed, and settles two
 // walkers that meet with remote atomics.  This is the data-parallel form of
 // the same result:
-//   1. index: an open-addressing table maps a key to its record;
-//   2. link: every UU k-mer looks up its right and left neighbours (two
-//      lookups) and keeps a link only where it agrees from both ends and is
-//      not a hairpin.  A half-node is a k-mer read in one orientation
-//      (2i: key orientation, 2i+1: reverse complement); each half-node gets
-//      its successor and predecessor, so each path or cycle of k-mers appears
-//      twice, once per reading direction (once with HM_FORWARD_ONLY);
-//   3. rank: pointer jumping over predecessors (in place, a packed (ancestor,
-//      distance) word per half-node) gives every half-node its chain head and
-//      its rank; a half-node whose distance passes the number of k-mers sits
-//      on a cycle;
-//   4. cycles: a second pointer jumping gives every cycle half-node the
+//   1. index: an open-addressing table of 32-byte slots (tag and record
+//      number, key, classes) maps a key to its record in one random read;
+//   2. link: every UU k-mer looks up its right and left neighbours and keeps
+//      a link only where it agrees from both ends and is not a hairpin.  A
+//      half-node is a k-mer read in one orientation (2i: key orientation,
+//      2i+1: reverse complement); each half-node gets its successor and
+//      predecessor, so each path or cycle of k-mers appears twice, once per
+//      reading direction (once with HM_FORWARD_ONLY);
+//   3. rank (sparse ruling set): chain heads and one k-mer in 32 (picked by a
+//      hash of its record number) are rulers; each ruler walks its segment up
+//      to the next ruler, giving every half-node its ruler and offset; pointer
+//      jumping over the rulers alone gives each ruler its head and rank, and
+//      then every half-node its head and rank.  A ruler whose distance passes
+//      the number of k-mers sits on a cycle, and so does a half-node no walker
+//      reached;
+//   4. cycles: pointer jumping over the cycle half-nodes gives each the
 //      cycle's smallest key; the cycle is cut before it (the reading that
 //      holds that k-mer in key orientation becomes a chain, the mirror one a
 //      chain that is dropped) and ranked again;
@@ -27,20 +31,26 @@
 //   6. spell: each kept chain takes its contig number and base offset from
 //      one packed counter (so offsets rise with the contig number), and every
 //      half-node writes its base at its rank.
-// The round kernels read their work counts from device memory, so the whole
-// call is a fixed sequence of launches with no host synchronization.
+// Counters shared by the whole grid are updated once per workgroup, not per
+// wave, on the paths every k-mer takes.  The round kernels read their work
+// counts from device memory, so the whole call is a fixed sequence of
+// launches with no host synchronization.
 #include "hm_device.h"
 
 namespace hm {
 namespace {
 
-constexpr uint32_t kNone = 0xFFFFFFFFu;      // no link / chain end
-constexpr uint32_t kInactive = 0xFFFFFFFEu;  // pred of a half-node outside the graph
-constexpr uint32_t kCut = 0xFFFFFFFDu;       // pred of a cycle cut's head
-constexpr uint64_t kEmpty = ~0ull;           // empty index slot
-constexpr uint64_t kNoOff = ~0ull;           // chain not written
+constexpr uint32_t kNone = 0xFFFFFFFFu;       // no link / chain end / no ruler yet
+constexpr uint32_t kInactive = 0xFFFFFFFEu;   // pred of a half-node outside the graph
+constexpr uint32_t kCut = 0xFFFFFFFDu;        // pred of a cycle cut's head
+constexpr unsigned long long kEmpty = ~0ull;  // empty index slot
+constexpr uint64_t kNoOff = ~0ull;            // chain not written
 constexpr uint64_t kIndexSeed = 0x13198A2E03707344ull;
 constexpr int kRounds = 32;                   // bound on pointer-jumping rounds per phase
+constexpr uint32_t kDone = 0x80000000u;       // ruler distance word: rank final
+constexpr uint32_t kCycW = 0x7FFFFFFFu;       // ruler distance word: on a cycle
+constexpr uint32_t kListDone = 0x80000000u;   // ruler list entry: settled
+constexpr int kRulerShift = 27;               // 1 ruler in 2^(32 - 27) = 32 k-mers
 constexpr int kCntBits = 29;                  // contig counter: number in the high 29 bits,
 constexpr int kOffBits = 35;                  // bases in the low 35
 constexpr uint64_t kOffMask = (1ull << kOffBits) - 1;
@@ -48,40 +58,51 @@ constexpr uint64_t kMaxRecords = 1ull << 29;
 // fewer than 2^29 contigs, and at most 2^29 k-mers plus 62 bases per contig
 static_assert(kCntBits + kOffBits == 64 && (1ull << kCntBits) >= kMaxRecords, "contig counter fields");
 constexpr uint32_t kStop = HM_ST_DUPLICATE | HM_ST_TABLE_FULL;
+constexpr int kRulerBuf = 4096;               // workgroup-local ruler buffer (entries)
+constexpr int kAllocPer = 16;                 // half-nodes per thread in the offset pass
 
 struct Ctl {
-    unsigned long long alloc;      // (contigs << 35) | bases
-    unsigned int n_uu;             // UU records
-    unsigned int n_cyc;            // half-nodes found on cycles
-    unsigned int cnt_main[kRounds + 1];
+    unsigned long long alloc;  // (contigs << 35) | bases
+    unsigned int n_uu;         // UU records
+    unsigned int n_cyc;        // half-nodes found on cycles
+    unsigned int n_rulers;
+    unsigned int pad;
     unsigned int cnt_re[kRounds + 1];
 };
 constexpr size_t kCtlBytes = 512;
 static_assert(sizeof(Ctl) <= kCtlBytes, "control block");
 
+struct IndexSlot {
+    unsigned long long tagj;  // (hash tag << 32) | record, or kEmpty
+    uint64_t hi, lo;          // key
+    uint64_t cls;             // cls_l | cls_r << 8
+};
+static_assert(sizeof(IndexSlot) == 32, "index slot");
+
 struct Layout {
     uint64_t slots, half;
-    size_t ctl, table, S, succ, pred, hlen, hoff, listA, listB, cyc, total;
+    size_t ctl, table, S, RS, succ, pred, hlen, listA, cyc, total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// work buffer: control block, index, and per half-node arrays.  The ruler
+// ranks (RS) become the chain offsets once every half-node is ranked, and the
+// second list of the cycle re-ranking lives in hlen until the chains are
+// chosen.
 Layout layout(uint64_t cap) {
     Layout L;
-    uint64_t t = 64;
-    while (t < 2 * cap) t <<= 1;
-    L.slots = t;
+    L.slots = 2 * cap < 64 ? 64 : 2 * cap;
     L.half = 2 * cap;
     size_t o = 0;
     L.ctl = o;   o += up256(kCtlBytes);
-    L.table = o; o += up256(t * 8);
+    L.table = o; o += up256(L.slots * sizeof(IndexSlot));
     L.S = o;     o += up256(L.half * 8);
-    L.hoff = o;  o += up256(L.half * 8);
+    L.RS = o;    o += up256(L.half * 8);
     L.succ = o;  o += up256(L.half * 4);
     L.pred = o;  o += up256(L.half * 4);
     L.hlen = o;  o += up256(L.half * 4);
     L.listA = o; o += up256(L.half * 4);
-    L.listB = o; o += up256(L.half * 4);
     L.cyc = o;   o += up256(L.half * 4);
     L.total = o;
     return L;
@@ -92,10 +113,10 @@ struct Graph {
     const uint8_t *cl, *cr;
     const uint64_t *n_out;
     uint64_t cap;
-    uint64_t *table;
-    uint64_t tmask;
-    unsigned long long *S;  // (distance << 32) | ancestor; in the cycle phase (min node << 32) | ancestor
-    uint64_t *hoff;
+    IndexSlot *table;
+    uint64_t slots;
+    unsigned long long *S;   // per half-node (distance << 32) | ancestor; (min node << 32) | ancestor on cycles
+    unsigned long long *RS;  // per ruler (distance << 32) | ancestor ruler; later per head: chain offset
     uint32_t *succ, *pred, *hlen, *listA, *listB, *cyc;
     Ctl *ctl;
     uint32_t *status;
@@ -133,7 +154,13 @@ __device__ __forceinline__ u128 seq_of(const Graph &g, uint32_t h) {
     return (h & 1) ? rc128(x, g.k) : x;
 }
 
-// wave-wide append: every lane of the wave calls it; lanes with `take` get consecutive slots
+// both readings of a sampled k-mer are rulers
+__device__ __forceinline__ bool sampled(uint32_t h) { return ((h >> 1) * 0x9E3779B1u) >> kRulerShift == 0; }
+
+__device__ __forceinline__ uint64_t home_slot(uint64_t h, uint64_t slots) { return __umul64hi(h, slots); }
+
+// wave-wide append for rare events: every lane of the wave calls it; lanes
+// with `take` get consecutive slots (one atomic per wave that has any)
 __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, unsigned int *cnt) {
     const uint64_t m = __ballot(take);
     if (!m) return;
@@ -145,67 +172,82 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
     if (take) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
 }
 
-// slot of a key in the index, or kNone
-__device__ __forceinline__ uint32_t find(const Graph &g, u128 key) {
+// record of a key (with its classes), or kNone
+__device__ __forceinline__ uint32_t find(const Graph &g, u128 key, int &cl, int &cr) {
     const uint64_t khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
     const uint64_t h = key_hash(khi, klo, kIndexSeed);
     const uint32_t tag = (uint32_t)(h >> 32);
-    uint64_t s = h & g.tmask;
-    for (uint64_t p = 0; p <= g.tmask; ++p) {
-        const uint64_t e = g.table[s];
-        if (e == kEmpty) return kNone;
-        if ((uint32_t)(e >> 32) == tag) {
-            const uint32_t j = (uint32_t)e;
-            if (g.hi[j] == khi && g.lo[j] == klo) return j;
+    uint64_t s = home_slot(h, g.slots);
+    for (uint64_t p = 0; p < g.slots; ++p) {
+        const uint4 *q = reinterpret_cast<const uint4 *>(g.table + s);
+        const uint4 a = q[0], b = q[1];
+        const uint64_t tagj = ((uint64_t)a.y << 32) | a.x;
+        if (tagj == kEmpty) return kNone;
+        if ((uint32_t)(tagj >> 32) == tag && (((uint64_t)a.w << 32) | a.z) == khi &&
+            (((uint64_t)b.y << 32) | b.x) == klo) {
+            cl = (int)(b.z & 0xFF);
+            cr = (int)((b.z >> 8) & 0xFF);
+            return (uint32_t)tagj;
         }
-        s = (s + 1) & g.tmask;
+        s = s + 1 == g.slots ? 0 : s + 1;
     }
     return kNone;
 }
 
 __device__ __forceinline__ bool is_uu(const Graph &g, uint64_t i) { return g.cl[i] < 4 && g.cr[i] < 4; }
 
+// sum of v over the workgroup (every thread calls it; thread 0 gets the sum)
+__device__ __forceinline__ unsigned int block_sum(unsigned int v, unsigned int *s_tmp) {
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+    if ((threadIdx.x & 63) == 0) s_tmp[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned int t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) t += s_tmp[w];
+    return t;
+}
+
 // ------------------------------------------------------------------ 1. index
 
 __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
+    __shared__ unsigned int s_tmp[kBlock / 64];
     const uint64_t n = n_records(g);
-    const int lane = __lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < n; wb += stride) {
-        const uint64_t i = wb + lane;
-        const bool uu = i < n && is_uu(g, i);
-        if (uu) {
-            const uint64_t khi = g.hi[i], klo = g.lo[i];
-            const uint64_t h = key_hash(khi, klo, kIndexSeed);
-            const uint32_t tag = (uint32_t)(h >> 32);
-            const uint64_t mine = ((uint64_t)tag << 32) | (uint32_t)i;
-            uint64_t s = h & g.tmask;
-            bool placed = false;
-            for (uint64_t p = 0; p <= g.tmask && !placed; ++p) {
-                uint64_t e = g.table[s];
+    unsigned int n_uu = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock) {
+        if (!is_uu(g, i)) continue;
+        ++n_uu;
+        const uint64_t khi = g.hi[i], klo = g.lo[i];
+        const uint64_t h = key_hash(khi, klo, kIndexSeed);
+        const uint32_t tag = (uint32_t)(h >> 32);
+        const unsigned long long mine = ((unsigned long long)tag << 32) | (uint32_t)i;
+        uint64_t s = home_slot(h, g.slots);
+        bool placed = false;
+        for (uint64_t p = 0; p < g.slots; ++p) {
+            unsigned long long e = g.table[s].tagj;
+            if (e == kEmpty) {
+                e = atomicCAS(&g.table[s].tagj, kEmpty, mine);
                 if (e == kEmpty) {
-                    e = atomicCAS(reinterpret_cast<unsigned long long *>(g.table + s), (unsigned long long)kEmpty,
-                                  (unsigned long long)mine);
-                    if (e == kEmpty) {
-                        placed = true;
-                        break;
-                    }
+                    g.table[s].hi = khi;
+                    g.table[s].lo = klo;
+                    g.table[s].cls = (uint64_t)g.cl[i] | ((uint64_t)g.cr[i] << 8);
+                    placed = true;
+                    break;
                 }
-                if ((uint32_t)(e >> 32) == tag) {
-                    const uint32_t j = (uint32_t)e;
-                    if (g.hi[j] == khi && g.lo[j] == klo) {
-                        atomicOr(g.status, HM_ST_DUPLICATE);
-                        placed = true;
-                        break;
-                    }
-                }
-                s = (s + 1) & g.tmask;
             }
-            if (!placed) atomicOr(g.status, HM_ST_TABLE_FULL);
+            if ((uint32_t)(e >> 32) == tag) {
+                const uint32_t j = (uint32_t)e;  // compared through the input records (the slot may be half-written)
+                if (g.hi[j] == khi && g.lo[j] == klo) {
+                    atomicOr(g.status, HM_ST_DUPLICATE);
+                    placed = true;
+                    break;
+                }
+            }
+            s = s + 1 == g.slots ? 0 : s + 1;
         }
-        const uint64_t m = __ballot(uu);
-        if (lane == 0 && m) atomicAdd(&g.ctl->n_uu, (unsigned int)__popcll(m));
+        if (!placed) atomicOr(g.status, HM_ST_TABLE_FULL);
     }
+    const unsigned int t = block_sum(n_uu, s_tmp);
+    if (threadIdx.x == 0 && t) atomicAdd(&g.ctl->n_uu, t);
 }
 
 // ------------------------------------------------------------------ 2. link
@@ -235,29 +277,30 @@ __device__ __forceinline__ uint32_t step(const Graph &g, uint32_t i, u128 s, int
             o = 1;
         }
     }
-    const uint32_t j = find(g, key);
+    int jl = 0, jr = 0;
+    const uint32_t j = find(g, key, jl, jr);
     if (j == kNone) return kNone;
     // the neighbour's extension facing back, read in its orientation
-    int back;
-    if (dir == 0) back = o ? 3 - (int)g.cr[j] : (int)g.cl[j];
-    else back = o ? 3 - (int)g.cl[j] : (int)g.cr[j];
+    const int back = dir == 0 ? (o ? 3 - jr : jl) : (o ? 3 - jl : jr);
     if (back != drop) return kNone;
     if (j == i && o == 1) return kNone;  // hairpin: back onto the side it left
     return 2 * j + (uint32_t)o;
 }
 
+// Links of every record; collects the rulers (heads and sampled half-nodes)
+// into listA through a workgroup-local buffer flushed with one atomic.
 __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
+    __shared__ uint32_t s_buf[kRulerBuf];
+    __shared__ unsigned int s_cnt, s_base;
     if (stopped(g)) return;
     const uint64_t n = n_records(g);
-    const int lane = __lane_id();
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < n; wb += stride) {
-        const uint64_t i = wb + lane;
-        bool in0 = false, in1 = false;
-        uint32_t h0 = 0, h1 = 0;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kBlock; b0 < n; b0 += stride) {  // uniform per workgroup
+        const uint64_t i = b0 + threadIdx.x;
         if (i < n) {
-            h0 = (uint32_t)(2 * i);
-            h1 = h0 + 1;
+            const uint32_t h0 = (uint32_t)(2 * i), h1 = h0 + 1;
             if (!is_uu(g, i)) {
                 g.succ[h0] = g.succ[h1] = kNone;
                 g.pred[h0] = g.pred[h1] = kInactive;
@@ -270,38 +313,144 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
                 const uint32_t Lf = step(g, (uint32_t)i, s, cl, cr, 1);
                 g.succ[h0] = R;
                 g.pred[h0] = Lf;
-                st(g.S + h0, Lf == kNone ? pack(0, h0) : pack(1, Lf));
-                in0 = Lf != kNone;
+                st(g.S + h0, pack(0, kNone));
+                const bool samp = sampled(h0);
+                if (Lf == kNone || samp) s_buf[atomicAdd(&s_cnt, 1u)] = h0;
                 if (g.fwd) {
                     g.succ[h1] = kNone;
                     g.pred[h1] = kInactive;
                     st(g.S + h1, pack(0, h1));
                 } else {
                     // the reverse-complement reading runs the same links backwards
-                    const uint32_t s1 = Lf == kNone ? kNone : (Lf ^ 1u);
                     const uint32_t p1 = R == kNone ? kNone : (R ^ 1u);
-                    g.succ[h1] = s1;
+                    g.succ[h1] = Lf == kNone ? kNone : (Lf ^ 1u);
                     g.pred[h1] = p1;
-                    st(g.S + h1, p1 == kNone ? pack(0, h1) : pack(1, p1));
-                    in1 = p1 != kNone;
+                    st(g.S + h1, pack(0, kNone));
+                    if (p1 == kNone || samp) s_buf[atomicAdd(&s_cnt, 1u)] = h1;
                 }
             }
         }
-        wave_append(in0, h0, g.listA, &g.ctl->cnt_main[0]);
-        wave_append(in1, h1, g.listA, &g.ctl->cnt_main[0]);
+        __syncthreads();
+        const unsigned int c = s_cnt;
+        if (c > kRulerBuf - 2 * kBlock || b0 + stride >= n) {  // at most 2 more per thread fit before the next flush
+            if (threadIdx.x == 0) s_base = c ? atomicAdd(&g.ctl->n_rulers, c) : 0u;
+            __syncthreads();
+            for (unsigned int x = threadIdx.x; x < c; x += kBlock) g.listA[s_base + x] = s_buf[x];
+            __syncthreads();
+            if (threadIdx.x == 0) s_cnt = 0;
+        }
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------ 3. rank
 
-// One round of pointer jumping over the half-nodes in `in`: a half-node whose
-// ancestor is a chain head is done; the others take their ancestor's ancestor
-// and move to `out`, or to the cycle list once the distance passes the number
-// of UU k-mers (no path is that long).  Rounds past the last non-empty one
-// find a zero count and return.
-__global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int phase, int r) {
+// Each ruler walks its segment: every half-node up to the next ruler (or the
+// chain's end) gets (offset, ruler); the next ruler gets (segment length,
+// this ruler) as its ruler-level predecessor.  A head is its own ruler-level
+// head at distance 0.
+__global__ __launch_bounds__(kBlock) void k_ctg_walk(Graph g) {
     if (stopped(g)) return;
-    unsigned int *cnt = phase == 0 ? g.ctl->cnt_main : g.ctl->cnt_re;
+    const uint32_t n = g.ctl->n_rulers;
+    const uint32_t bound = (uint32_t)(2 * g.cap);
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+        const uint32_t R = g.listA[x];
+        st(g.S + R, pack(0, R));
+        if (g.pred[R] == kNone) st(g.RS + R, pack(0, R));
+        uint32_t cur = R, t = 0, nx;
+        for (;;) {
+            nx = g.succ[cur];
+            if (nx == kNone || sampled(nx)) break;
+            if (++t >= bound) {  // longer than the graph: cannot happen
+                atomicOr(g.status, HM_ST_TIMEOUT);
+                break;
+            }
+            st(g.S + nx, pack(t, R));
+            cur = nx;
+        }
+        if (nx != kNone && t < bound) st(g.RS + nx, pack(t + 1, R));
+    }
+}
+
+// One round of pointer jumping over the rulers: a ruler whose ancestor is a
+// head (or already ranked) is ranked; the others take their ancestor's
+// ancestor; a distance past the number of UU k-mers marks a cycle.  Enough
+// rounds for both run: ceil(log2(UU k-mers + 1)) + 2.
+__global__ __launch_bounds__(kBlock) void k_ctg_rjump(Graph g, int r) {
+    if (stopped(g)) return;
+    const uint32_t n = g.ctl->n_rulers;
+    const uint32_t limit = g.ctl->n_uu + 1u;
+    const int rounds = (32 - __clz(limit - 1u)) + 2;
+    if (n == 0 || r >= rounds) return;
+    const uint32_t half = (uint32_t)(2 * g.cap);
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+        const uint32_t e = g.listA[x];
+        if (e & kListDone) continue;
+        const unsigned long long v = ld(g.RS + e);
+        const uint32_t J = (uint32_t)v, W = (uint32_t)(v >> 32);
+        if (J >= half) {  // a ruler no walker reached: cannot happen
+            atomicOr(g.status, HM_ST_TIMEOUT);
+            g.listA[x] = e | kListDone;
+            continue;
+        }
+        const unsigned long long v2 = ld(g.RS + J);
+        const uint32_t J2 = (uint32_t)v2, W2r = (uint32_t)(v2 >> 32), W2 = W2r & ~kDone;
+        bool settled = true;
+        if (W2r == kCycW) {
+            st(g.RS + e, pack(kCycW, J2));
+        } else if (J2 == J && W2 == 0) {
+            st(g.RS + e, pack(W | kDone, J));  // J is the head
+        } else {
+            const uint32_t w = W + W2;
+            if (W2r & kDone) {
+                st(g.RS + e, pack(w | kDone, J2));  // J2 is the head
+            } else if (w >= limit) {
+                st(g.RS + e, pack(kCycW, J2));
+            } else {
+                st(g.RS + e, pack(w, J2));
+                settled = false;
+            }
+        }
+        if (settled) g.listA[x] = e | kListDone;
+    }
+}
+
+// Every half-node's head and rank from its ruler's; half-nodes on cycles
+// (their ruler's, or no ruler at all) go to the cycle list.
+__global__ __launch_bounds__(kBlock) void k_ctg_settle(Graph g) {
+    if (stopped(g)) return;
+    const uint64_t nh = 2 * n_records(g);
+    const int lane = __lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < nh; wb += stride) {
+        const uint64_t h = wb + lane;
+        bool cyc = false;
+        if (h < nh && g.pred[h] != kInactive) {
+            const unsigned long long v = ld(g.S + h);
+            const uint32_t R = (uint32_t)v, t = (uint32_t)(v >> 32);
+            if (R == kNone) {
+                cyc = true;  // no walker came by: a cycle without a ruler
+            } else if (R >= nh) {
+                atomicOr(g.status, HM_ST_TIMEOUT);  // cannot happen
+            } else {
+                const unsigned long long r = ld(g.RS + R);
+                const uint32_t W = (uint32_t)(r >> 32);
+                if (W == kCycW) cyc = true;
+                else if (!(W & kDone)) atomicOr(g.status, HM_ST_TIMEOUT);  // cannot happen
+                else st(g.S + h, pack((W & ~kDone) + t, (uint32_t)r));
+            }
+        }
+        wave_append(cyc, (uint32_t)h, g.cyc, &g.ctl->n_cyc);
+    }
+}
+
+// One round of pointer jumping over the half-nodes of the cut cycles (listA
+// and listB alternate): a half-node whose ancestor is a head is done, the
+// others take their ancestor's ancestor.  Rounds past the last non-empty one
+// find a zero count and return.
+__global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int r) {
+    if (stopped(g)) return;
+    unsigned int *cnt = g.ctl->cnt_re;
     const uint32_t n = __hip_atomic_load(cnt + r, RLX, AGT);
     if (n == 0) return;
     const uint32_t *in = (r & 1) ? g.listB : g.listA;
@@ -311,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int phase, int r) 
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t wb = blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < n; wb += stride) {
         const uint32_t idx = wb + lane;
-        bool more = false, cyc = false;
+        bool more = false;
         uint32_t h = 0;
         if (idx < n) {
             h = in[idx];
@@ -322,16 +471,11 @@ __global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int phase, int r) 
             if (!(J2 == J && W2 == 0)) {
                 const uint32_t w = W + W2;
                 st(g.S + h, pack(w, J2));
-                cyc = w >= limit;
-                more = !cyc;
-                if (cyc && phase != 0) {  // no cycle is left after the cuts: cannot happen
-                    atomicOr(g.status, HM_ST_TIMEOUT);
-                    cyc = false;
-                }
+                more = w < limit;
+                if (!more) atomicOr(g.status, HM_ST_TIMEOUT);  // no cycle is left after the cuts: cannot happen
             }
         }
         wave_append(more, h, out, cnt + r + 1);
-        wave_append(cyc, h, g.cyc, &g.ctl->n_cyc);
     }
 }
 
@@ -342,7 +486,12 @@ __global__ __launch_bounds__(kBlock) void k_ctg_cyc_init(Graph g) {
     const uint32_t n = g.ctl->n_cyc;
     for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
         const uint32_t h = g.cyc[x];
-        st(g.S + h, pack(h >> 1, g.pred[h]));  // window (pred, h]: its smallest node is h's
+        uint32_t p = g.pred[h];
+        if (p >= 2 * g.cap) {  // a cycle half-node has a predecessor: cannot happen
+            atomicOr(g.status, HM_ST_TIMEOUT);
+            p = h;
+        }
+        st(g.S + h, pack(h >> 1, p));  // window (pred, h]: its smallest node is h's
     }
 }
 
@@ -407,6 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_choose(Graph g) {
         if (g.pred[t] == kInactive || g.succ[t] != kNone) continue;
         const unsigned long long v = ld(g.S + t);
         const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+        if (H >= nh) continue;  // not ranked (reported): cannot happen
         bool keep;
         if (g.pred[H] == kCut) keep = (H & 1) == 0;  // the cycle read from its smallest key, key orientation
         else keep = g.fwd || seq_of(g, H) < seq_of(g, (uint32_t)t ^ 1u);
@@ -416,52 +566,62 @@ __global__ __launch_bounds__(kBlock) void k_ctg_choose(Graph g) {
 
 // ------------------------------------------------------------------ 6. spell
 
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x) {
-    const int lane = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const unsigned long long y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
-
+// Contig numbers and offsets: a workgroup sums its chains' (1, bases) pairs
+// (packed in one word) over kAllocPer consecutive half-nodes per thread,
+// takes its range with one atomic, and hands the range out in order.
 __global__ __launch_bounds__(kBlock) void k_ctg_alloc(Graph g, uint64_t *off, uint64_t off_cap, uint64_t seq_cap) {
+    __shared__ unsigned long long s_w[kBlock / 64];
+    __shared__ unsigned long long s_base;
     if (stopped(g)) return;
     const uint64_t nh = 2 * n_records(g);
-    const int lane = __lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < nh; wb += stride) {
-        const uint64_t h = wb + lane;
-        uint64_t bases = 0;
-        bool head = false;
-        if (h < nh) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const uint64_t chunk = (uint64_t)kBlock * kAllocPer;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < nh; c0 += (uint64_t)gridDim.x * chunk) {  // uniform
+        const uint64_t h0 = c0 + (uint64_t)threadIdx.x * kAllocPer;
+        unsigned long long mine = 0;
+        for (int j = 0; j < kAllocPer; ++j) {
+            const uint64_t h = h0 + j;
+            if (h >= nh) break;
             const uint32_t p = g.pred[h];
-            head = p == kNone || p == kCut;
-            if (head) {
+            if (p == kNone || p == kCut) {
                 const uint32_t len = g.hlen[h];
-                if (len) bases = (uint64_t)g.k + len - 1;
+                if (len) mine += (1ull << kOffBits) | ((uint64_t)g.k + len - 1);
             }
         }
-        const unsigned long long mine = bases ? ((1ull << kOffBits) | bases) : 0ull;
-        const unsigned long long incl = wave_incl_scan(mine);
-        const unsigned long long tot = __shfl(incl, 63, 64);
-        unsigned long long base = 0;
-        if (tot) {
-            if (lane == 0) base = atomicAdd(&g.ctl->alloc, tot);
-            base = __shfl(base, 0, 64);
+        unsigned long long x = mine;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const unsigned long long y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
         }
-        if (head) {
-            uint64_t o = kNoOff;
-            if (bases) {
-                const unsigned long long at = base + incl - mine;
-                const uint64_t c = at >> kOffBits, b = at & kOffMask;
-                if (c < off_cap) off[c] = b;
-                if (c < off_cap && b + bases <= seq_cap) o = b;
-                else atomicOr(g.status, HM_ST_OUTPUT_FULL);
+        if (lane == 63) s_w[wave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const unsigned long long v = s_w[w];
+                s_w[w] = t;
+                t += v;
             }
-            g.hoff[h] = o;
+            s_base = t ? atomicAdd(&g.ctl->alloc, t) : 0ull;
         }
+        __syncthreads();
+        unsigned long long at = s_base + s_w[wave] + x - mine;
+        for (int j = 0; j < kAllocPer; ++j) {
+            const uint64_t h = h0 + j;
+            if (h >= nh) break;
+            const uint32_t p = g.pred[h];
+            if (p != kNone && p != kCut) continue;
+            const uint32_t len = g.hlen[h];
+            if (!len) continue;  // offsets stay kNoOff
+            const uint64_t bases = (uint64_t)g.k + len - 1;
+            const uint64_t c = at >> kOffBits, b = at & kOffMask;
+            if (c < off_cap) off[c] = b;
+            if (c < off_cap && b + bases <= seq_cap) g.RS[h] = b;
+            else atomicOr(g.status, HM_ST_OUTPUT_FULL);
+            at += (1ull << kOffBits) | bases;
+        }
+        __syncthreads();
     }
 }
 
@@ -473,11 +633,8 @@ __global__ __launch_bounds__(kBlock) void k_ctg_write(Graph g, uint8_t *seq, uin
         if (g.pred[h] == kInactive) continue;
         const unsigned long long v = ld(g.S + h);
         const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
-        // only a head has an offset (a half-node that did not reach one is
-        // reported by k_ctg_final and writes nothing)
-        const uint32_t hp = g.pred[H];
-        if ((hp != kNone && hp != kCut) || ld(g.S + H) != pack(0, H)) continue;
-        const uint64_t o = g.hoff[H];
+        if (H >= nh) continue;  // not ranked (reported): cannot happen
+        const uint64_t o = g.RS[H];  // offset of a kept head, kNoOff elsewhere
         if (o == kNoOff || o + k + W > seq_cap) continue;
         u128 s = seq_of(g, (uint32_t)h);
         if (W == 0) {
@@ -497,7 +654,7 @@ __global__ void k_ctg_final(Graph g, uint64_t *counts, uint64_t *off, uint64_t o
     const uint64_t nc = a >> kOffBits, nb = a & kOffMask;
     counts[0] = nc;
     counts[1] = nb;
-    if (g.ctl->cnt_main[kRounds] || g.ctl->cnt_re[kRounds]) atomicOr(g.status, HM_ST_TIMEOUT);
+    if (g.ctl->cnt_re[kRounds]) atomicOr(g.status, HM_ST_TIMEOUT);
     if (nc <= off_cap) off[nc] = nb;
     if (nc > off_cap || nb > seq_cap) atomicOr(g.status, HM_ST_OUTPUT_FULL);
 }
@@ -546,15 +703,15 @@ int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *o
     g.cr = uu->cls_r;
     g.n_out = uu->n_out;
     g.cap = uu->capacity;
-    g.table = reinterpret_cast<uint64_t *>(w + L.table);
-    g.tmask = L.slots - 1;
+    g.table = reinterpret_cast<IndexSlot *>(w + L.table);
+    g.slots = L.slots;
     g.S = reinterpret_cast<unsigned long long *>(w + L.S);
-    g.hoff = reinterpret_cast<uint64_t *>(w + L.hoff);
+    g.RS = reinterpret_cast<unsigned long long *>(w + L.RS);
     g.succ = reinterpret_cast<uint32_t *>(w + L.succ);
     g.pred = reinterpret_cast<uint32_t *>(w + L.pred);
     g.hlen = reinterpret_cast<uint32_t *>(w + L.hlen);
     g.listA = reinterpret_cast<uint32_t *>(w + L.listA);
-    g.listB = reinterpret_cast<uint32_t *>(w + L.listB);
+    g.listB = g.hlen;  // second re-ranking list, free until the chains are chosen
     g.cyc = reinterpret_cast<uint32_t *>(w + L.cyc);
     g.ctl = reinterpret_cast<Ctl *>(w + L.ctl);
     g.status = out->status;
@@ -564,22 +721,29 @@ int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *o
     if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(w + L.ctl), kCtlBytes / 4, 0u, s))) return rc;
     if ((rc = fill<uint32_t>(out->status, 1, 0u, s))) return rc;
     if ((rc = fill<uint64_t>(out->counts, 2, 0ull, s))) return rc;
-    if ((rc = fill<uint64_t>(g.table, L.slots, kEmpty, s))) return rc;
+    // empty index: all ones (the tag word marks a slot empty)
+    if ((rc = fill<uint4>(reinterpret_cast<uint4 *>(g.table), 2 * L.slots, make_uint4(~0u, ~0u, ~0u, ~0u), s)))
+        return rc;
     const uint64_t cap = uu->capacity ? uu->capacity : 1;
     const dim3 blk(kBlock);
     const dim3 g_rec((unsigned)grid_for(cap, 16));
     const dim3 g_half((unsigned)grid_for(2 * cap, 16));
+    const dim3 g_rul((unsigned)grid_for(2 * cap / 16 + 1, 16));
     hipLaunchKernelGGL(k_ctg_index, g_rec, blk, 0, s, g);
     HM_LAUNCH_CHECK("hm_contigs (index)");
     hipLaunchKernelGGL(k_ctg_link, g_rec, blk, 0, s, g);
     HM_LAUNCH_CHECK("hm_contigs (link)");
-    for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_jump, g_half, blk, 0, s, g, 0, r);
+    hipLaunchKernelGGL(k_ctg_walk, g_rul, blk, 0, s, g);
+    for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_rjump, g_rul, blk, 0, s, g, r);
+    hipLaunchKernelGGL(k_ctg_settle, g_half, blk, 0, s, g);
     HM_LAUNCH_CHECK("hm_contigs (rank)");
     hipLaunchKernelGGL(k_ctg_cyc_init, g_half, blk, 0, s, g);
     for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_cyc_jump, g_half, blk, 0, s, g, r);
     hipLaunchKernelGGL(k_ctg_cut, g_half, blk, 0, s, g);
-    for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_jump, g_half, blk, 0, s, g, 1, r);
+    for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_jump, g_half, blk, 0, s, g, r);
     HM_LAUNCH_CHECK("hm_contigs (cycles)");
+    // the ruler ranks are spent: the same words now hold the chain offsets (kNoOff unless a kept head)
+    if ((rc = fill<uint64_t>(reinterpret_cast<uint64_t *>(g.RS), L.half, kNoOff, s))) return rc;
     hipLaunchKernelGGL(k_ctg_choose, g_half, blk, 0, s, g);
     hipLaunchKernelGGL(k_ctg_alloc, g_half, blk, 0, s, g, out->off, out->off_capacity, out->seq_capacity);
     hipLaunchKernelGGL(k_ctg_write, g_half, blk, 0, s, g, out->seq, out->seq_capacity);
