@@ -172,24 +172,53 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
     if (take) list[base + __popcll(m & ((1ull << lane) - 1))] = v;
 }
 
-// record of a key (with its classes), or kNone
-__device__ __forceinline__ uint32_t find(const Graph &g, u128 key, int &cl, int &cr) {
-    const uint64_t khi = (uint64_t)(key >> 64), klo = (uint64_t)key;
-    const uint64_t h = key_hash(khi, klo, kIndexSeed);
-    const uint32_t tag = (uint32_t)(h >> 32);
-    uint64_t s = home_slot(h, g.slots);
-    for (uint64_t p = 0; p < g.slots; ++p) {
-        const uint4 *q = reinterpret_cast<const uint4 *>(g.table + s);
-        const uint4 a = q[0], b = q[1];
-        const uint64_t tagj = ((uint64_t)a.y << 32) | a.x;
-        if (tagj == kEmpty) return kNone;
-        if ((uint32_t)(tagj >> 32) == tag && (((uint64_t)a.w << 32) | a.z) == khi &&
-            (((uint64_t)b.y << 32) | b.x) == klo) {
-            cl = (int)(b.z & 0xFF);
-            cr = (int)((b.z >> 8) & 0xFF);
-            return (uint32_t)tagj;
-        }
-        s = s + 1 == g.slots ? 0 : s + 1;
+// A key lookup in the index: the first slot is loaded by the caller (so two
+// lookups can be in flight at once), further slots here.
+struct Lookup {
+    uint64_t khi, klo, s;
+    uint32_t tag;
+};
+
+__device__ __forceinline__ Lookup lookup_start(const Graph &g, u128 key) {
+    Lookup L;
+    L.khi = (uint64_t)(key >> 64);
+    L.klo = (uint64_t)key;
+    const uint64_t h = key_hash(L.khi, L.klo, kIndexSeed);
+    L.tag = (uint32_t)(h >> 32);
+    L.s = home_slot(h, g.slots);
+    return L;
+}
+
+__device__ __forceinline__ void load_slot(const Graph &g, uint64_t s, uint4 &a, uint4 &b) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(g.table + s);
+    a = q[0];
+    b = q[1];
+}
+
+// 1: found (record, classes), 0: absent, -1: another key, probe on
+__device__ __forceinline__ int slot_match(const Lookup &L, const uint4 &a, const uint4 &b, uint32_t &j, int &cl,
+                                          int &cr) {
+    const uint64_t tagj = ((uint64_t)a.y << 32) | a.x;
+    if (tagj == kEmpty) return 0;
+    if ((uint32_t)(tagj >> 32) == L.tag && (((uint64_t)a.w << 32) | a.z) == L.khi &&
+        (((uint64_t)b.y << 32) | b.x) == L.klo) {
+        j = (uint32_t)tagj;
+        cl = (int)(b.z & 0xFF);
+        cr = (int)((b.z >> 8) & 0xFF);
+        return 1;
+    }
+    return -1;
+}
+
+// record of a key whose first slot (a, b) did not settle it, or kNone
+__device__ __forceinline__ uint32_t lookup_rest(const Graph &g, Lookup L, int &cl, int &cr) {
+    for (uint64_t p = 1; p < g.slots; ++p) {
+        L.s = L.s + 1 == g.slots ? 0 : L.s + 1;
+        uint4 a, b;
+        load_slot(g, L.s, a, b);
+        uint32_t j;
+        const int m = slot_match(L, a, b, j, cl, cr);
+        if (m >= 0) return m ? j : kNone;
     }
     return kNone;
 }
@@ -223,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
         uint64_t s = home_slot(h, g.slots);
         bool placed = false;
         for (uint64_t p = 0; p < g.slots; ++p) {
-            unsigned long long e = g.table[s].tagj;
+            unsigned long long e = g.table[s].tagj;  // a load first: a CAS on a taken slot costs more
             if (e == kEmpty) {
                 e = atomicCAS(&g.table[s].tagj, kEmpty, mine);
                 if (e == kEmpty) {
@@ -252,55 +281,69 @@ __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
 
 // ------------------------------------------------------------------ 2. link
 
-// Half-node reached by a step from (i, key orientation) to the right (dir 0)
-// or to the left (dir 1), or kNone: the neighbour must be a UU k-mer whose
-// extension on the facing side spells the base this k-mer drops, and a step
-// back onto the side it left (only possible onto i itself) is no link.
-__device__ __forceinline__ uint32_t step(const Graph &g, uint32_t i, u128 s, int cl, int cr, int dir) {
+// The k-mer a step from (i, key orientation) to the right (dir 0) or to the
+// left (dir 1) reaches, as the key to look up, its orientation, and the base
+// the step drops.
+struct Step {
+    u128 key;
+    int o, drop;
+};
+
+__device__ __forceinline__ Step step_target(const Graph &g, u128 s, int cl, int cr, int dir) {
     const int k = g.k;
     const u128 mask = ((u128)1 << (2 * k)) - 1;
     u128 t;
-    int drop;
+    Step r;
     if (dir == 0) {
         t = ((s << 2) | (u128)cr) & mask;
-        drop = (int)(s >> (2 * (k - 1))) & 3;
+        r.drop = (int)(s >> (2 * (k - 1))) & 3;
     } else {
         t = (s >> 2) | ((u128)cl << (2 * (k - 1)));
-        drop = (int)(s & 3);
+        r.drop = (int)(s & 3);
     }
-    int o = 0;
-    u128 key = t;
+    r.o = 0;
+    r.key = t;
     if (!g.fwd) {
-        const u128 r = rc128(t, k);
-        if (r < t) {
-            key = r;
-            o = 1;
+        const u128 rc = rc128(t, k);
+        if (rc < t) {
+            r.key = rc;
+            r.o = 1;
         }
     }
-    int jl = 0, jr = 0;
-    const uint32_t j = find(g, key, jl, jr);
+    return r;
+}
+
+// The half-node the step reaches, or kNone: the neighbour must be a UU k-mer
+// whose extension on the facing side spells the base this k-mer drops, and a
+// step back onto the side it left (only possible onto i itself) is no link.
+__device__ __forceinline__ uint32_t step_link(uint32_t i, const Step &st_, int dir, uint32_t j, int jl, int jr) {
     if (j == kNone) return kNone;
     // the neighbour's extension facing back, read in its orientation
-    const int back = dir == 0 ? (o ? 3 - jr : jl) : (o ? 3 - jl : jr);
-    if (back != drop) return kNone;
-    if (j == i && o == 1) return kNone;  // hairpin: back onto the side it left
-    return 2 * j + (uint32_t)o;
+    const int back = dir == 0 ? (st_.o ? 3 - jr : jl) : (st_.o ? 3 - jl : jr);
+    if (back != st_.drop) return kNone;
+    if (j == i && st_.o == 1) return kNone;  // hairpin: back onto the side it left
+    return 2 * j + (uint32_t)st_.o;
 }
 
 // Links of every record; collects the rulers (heads and sampled half-nodes)
-// into listA through a workgroup-local buffer flushed with one atomic.
+// into listA through a wave-local buffer in LDS, flushed with one atomic per
+// kRulerBuf / 4 - 128 entries (no workgroup barrier in the loop).
 __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
+    constexpr int kWaveBuf = kRulerBuf / (kBlock / 64);
     __shared__ uint32_t s_buf[kRulerBuf];
-    __shared__ unsigned int s_cnt, s_base;
     if (stopped(g)) return;
     const uint64_t n = n_records(g);
-    if (threadIdx.x == 0) s_cnt = 0;
-    __syncthreads();
+    const int lane = __lane_id();
+    uint32_t *wbuf = s_buf + (threadIdx.x >> 6) * kWaveBuf;
+    uint32_t cnt = 0;  // wave-uniform
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t b0 = (uint64_t)blockIdx.x * kBlock; b0 < n; b0 += stride) {  // uniform per workgroup
-        const uint64_t i = b0 + threadIdx.x;
+    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < n; wb += stride) {  // per wave
+        const uint64_t i = wb + lane;
+        bool r0 = false, r1 = false;
+        uint32_t h0 = 0, h1 = 0;
         if (i < n) {
-            const uint32_t h0 = (uint32_t)(2 * i), h1 = h0 + 1;
+            h0 = (uint32_t)(2 * i);
+            h1 = h0 + 1;
             if (!is_uu(g, i)) {
                 g.succ[h0] = g.succ[h1] = kNone;
                 g.pred[h0] = g.pred[h1] = kInactive;
@@ -309,13 +352,27 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
             } else {
                 const int cl = g.cl[i], cr = g.cr[i];
                 const u128 s = key_of(g, (uint32_t)i);
-                const uint32_t R = step(g, (uint32_t)i, s, cl, cr, 0);
-                const uint32_t Lf = step(g, (uint32_t)i, s, cl, cr, 1);
+                const Step sr = step_target(g, s, cl, cr, 0), sl = step_target(g, s, cl, cr, 1);
+                const Lookup lr = lookup_start(g, sr.key), ll = lookup_start(g, sl.key);
+                uint4 ar, br, al, bl;
+                load_slot(g, lr.s, ar, br);  // both first probes in flight together
+                load_slot(g, ll.s, al, bl);
+                // the right and left neighbours: record and classes
+                uint32_t jR = kNone, jL = kNone;
+                int r_cl = 0, r_cr = 0, l_cl = 0, l_cr = 0;
+                int m = slot_match(lr, ar, br, jR, r_cl, r_cr);
+                if (m < 0) jR = lookup_rest(g, lr, r_cl, r_cr);
+                else if (m == 0) jR = kNone;
+                m = slot_match(ll, al, bl, jL, l_cl, l_cr);
+                if (m < 0) jL = lookup_rest(g, ll, l_cl, l_cr);
+                else if (m == 0) jL = kNone;
+                const uint32_t R = step_link((uint32_t)i, sr, 0, jR, r_cl, r_cr);
+                const uint32_t Lf = step_link((uint32_t)i, sl, 1, jL, l_cl, l_cr);
                 g.succ[h0] = R;
                 g.pred[h0] = Lf;
                 st(g.S + h0, pack(0, kNone));
                 const bool samp = sampled(h0);
-                if (Lf == kNone || samp) s_buf[atomicAdd(&s_cnt, 1u)] = h0;
+                r0 = Lf == kNone || samp;
                 if (g.fwd) {
                     g.succ[h1] = kNone;
                     g.pred[h1] = kInactive;
@@ -326,20 +383,27 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
                     g.succ[h1] = Lf == kNone ? kNone : (Lf ^ 1u);
                     g.pred[h1] = p1;
                     st(g.S + h1, pack(0, kNone));
-                    if (p1 == kNone || samp) s_buf[atomicAdd(&s_cnt, 1u)] = h1;
+                    r1 = p1 == kNone || samp;
                 }
             }
         }
-        __syncthreads();
-        const unsigned int c = s_cnt;
-        if (c > kRulerBuf - 2 * kBlock || b0 + stride >= n) {  // at most 2 more per thread fit before the next flush
-            if (threadIdx.x == 0) s_base = c ? atomicAdd(&g.ctl->n_rulers, c) : 0u;
-            __syncthreads();
-            for (unsigned int x = threadIdx.x; x < c; x += kBlock) g.listA[s_base + x] = s_buf[x];
-            __syncthreads();
-            if (threadIdx.x == 0) s_cnt = 0;
+        const uint64_t m0 = __ballot(r0), m1 = __ballot(r1);
+        const uint64_t below = (1ull << lane) - 1;
+        if (r0) wbuf[cnt + __popcll(m0 & below)] = h0;
+        cnt += (uint32_t)__popcll(m0);
+        if (r1) wbuf[cnt + __popcll(m1 & below)] = h1;
+        cnt += (uint32_t)__popcll(m1);
+        if (cnt > kWaveBuf - 128 || wb + stride >= n) {  // at most 128 more per pass fit before a flush
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            uint32_t base = 0;
+            if (lane == 0 && cnt) base = atomicAdd(&g.ctl->n_rulers, cnt);
+            base = __shfl(base, 0);
+            for (uint32_t x = lane; x < cnt; x += 64) g.listA[base + x] = wbuf[x];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            cnt = 0;
         }
-        __syncthreads();
     }
 }
 
@@ -348,27 +412,46 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
 // Each ruler walks its segment: every half-node up to the next ruler (or the
 // chain's end) gets (offset, ruler); the next ruler gets (segment length,
 // this ruler) as its ruler-level predecessor.  A head is its own ruler-level
-// head at distance 0.
+// head at distance 0.  A workgroup owns a contiguous range of rulers and a
+// lane whose walk ends takes the next one, so no lane idles while the
+// longest segment of its wave is walked.
 __global__ __launch_bounds__(kBlock) void k_ctg_walk(Graph g) {
+    __shared__ unsigned int s_next;
     if (stopped(g)) return;
     const uint32_t n = g.ctl->n_rulers;
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    if (threadIdx.x == 0) s_next = lo + kBlock;
+    __syncthreads();
     const uint32_t bound = (uint32_t)(2 * g.cap);
-    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
-        const uint32_t R = g.listA[x];
+    uint32_t x = lo + threadIdx.x, R = 0, cur = 0, t = 0;
+    bool live = x < hi;
+    if (live) {
+        R = cur = g.listA[x];
         st(g.S + R, pack(0, R));
         if (g.pred[R] == kNone) st(g.RS + R, pack(0, R));
-        uint32_t cur = R, t = 0, nx;
-        for (;;) {
-            nx = g.succ[cur];
-            if (nx == kNone || sampled(nx)) break;
-            if (++t >= bound) {  // longer than the graph: cannot happen
-                atomicOr(g.status, HM_ST_TIMEOUT);
-                break;
-            }
+    }
+    while (live) {
+        const uint32_t nx = g.succ[cur];
+        bool end = nx == kNone || sampled(nx);
+        if (!end && ++t >= bound) {  // longer than the graph: cannot happen
+            atomicOr(g.status, HM_ST_TIMEOUT);
+            end = true;  // t == bound: no ruler-level link written
+        } else if (!end) {
             st(g.S + nx, pack(t, R));
             cur = nx;
         }
-        if (nx != kNone && t < bound) st(g.RS + nx, pack(t + 1, R));
+        if (end) {
+            if (nx != kNone && t < bound) st(g.RS + nx, pack(t + 1, R));
+            x = atomicAdd(&s_next, 1u);
+            live = x < hi;
+            if (live) {
+                R = cur = g.listA[x];
+                t = 0;
+                st(g.S + R, pack(0, R));
+                if (g.pred[R] == kNone) st(g.RS + R, pack(0, R));
+            }
+        }
     }
 }
 
