@@ -203,9 +203,11 @@ def run_serving(args, dev, log):
     return out
 
 
-def measure_contigs(kc, k, n_records, stream, log, reps=3):
+def measure_contigs(kc, k, n_records, stream, log, reps=3, rates=None):
     """Time contig generation (hm_contigs) over the UU records of the bench table, outside the timed
-    step, and check that the contigs hold every UU k-mer once."""
+    step, and check that the contigs hold every UU k-mer once.  With the measured random-access
+    rates (`rates`: ops/s of loads and atomics, copy bytes/s), price the call's accesses at them:
+    the random-access ceiling of this call, and the fraction of it reached."""
     import torch
     from paper_1705_11147_amd import abi, kmer
     uu = kmer.Records(n_records, device=kc.device)
@@ -234,6 +236,24 @@ def measure_contigs(kc, k, n_records, stream, log, reps=3):
     res = {"uu_kmers": n_uu, "contigs": nc, "bases": nb, "n50": n50, "longest": int(lens[0].item()) if nc else 0,
            "ms": round(t, 3), "uu_kmers_per_s": round(n_uu / (t / 1000), 1),
            "work_bytes": int(cs.work.numel() * 8)}
+    # accesses per call (line granular, first probes only), per UU k-mer u and per reading h = 2u:
+    #   index: a probe load and a claiming CAS per u;  link: two neighbour slot loads per u;
+    #   walk: a successor load and a rank store per h;  settle: a ruler-rank load per h;
+    #   spell: a head-offset load per h and a base store per contig base;
+    # plus the streamed bytes: the index and offset fills (32 + 8 bytes per slot and reading of the
+    # buffer's capacity) and per u about 188 bytes of keys, classes, links and ranks read and written
+    cap = uu.capacity
+    loads, stores, atomics = 9 * n_uu, 2 * n_uu + nb, n_uu
+    seq_bytes = 32 * 2 * cap + 8 * 2 * cap + 188 * n_uu
+    res["random_ops_per_uu_kmer"] = round((loads + stores + atomics) / max(n_uu, 1), 2)
+    res["achieved_random_Gops"] = round((loads + stores + atomics) / (t / 1000) / 1e9, 2)
+    if rates:
+        model_s = (loads + stores) / rates["load"] + atomics / rates["atomic_add"] + seq_bytes / rates["copy_Bps"]
+        res["roofline"] = {"bound": "random access (measured rates)", "ceiling_ms": round(model_s * 1000, 2),
+                           "frac_of_measured_ceiling": round(model_s * 1000 / t, 4),
+                           "load_Gops": round(rates["load"] / 1e9, 2),
+                           "atomic_Gops": round(rates["atomic_add"] / 1e9, 2),
+                           "seq_bytes_per_uu_kmer": round(seq_bytes / max(n_uu, 1), 1)}
     log("contig generation: %s" % res)
     del cs, uu
     return res
@@ -398,6 +418,7 @@ def main():
                 if args.scale == 1.0 and args.workload == "mid" else None,
                 "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
                 "events_per_position": {x: round(v / positions, 4) for x, v in st.items() }}
+    rates = None
     if not args.no_probe:
         from paper_1705_11147_amd import roofline as ra
         m = ra.measure(kc.capacity * 64, kinds=("load", "atomic_add", "atomic_or_ret", "probe_cas"), n_ops=1 << 28,
@@ -413,6 +434,7 @@ def main():
         # is a probe + CAS on its line, a Bloom test a probe that misses + an OR with return, every
         # further probed slot a load, an insertion two atomics (key claim, count)
         rate = {x: m[x]["ops_per_s"] for x in ("load", "atomic_add", "atomic_or_ret", "probe_cas")}
+        rates = dict(rate, copy_Bps=m["copy"]["GBps"] * 1e9)
         hits = st["hit_first_lookup"]
         inserts = max(occ - hits - deferred, 0)
         model_s = (hits / rate["probe_cas"] + bloom_tests / rate["load"] + bloom_tests / rate["atomic_or_ret"]
@@ -430,7 +452,7 @@ def main():
         sorted_export = measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log)
     contigs = None
     if not args.no_contigs:
-        contigs = measure_contigs(kc, k, n_records, stream, log)
+        contigs = measure_contigs(kc, k, n_records, stream, log, rates=rates)
 
     cpu = None
     if not args.no_cpu:
