@@ -126,3 +126,136 @@ def test_human_share_streamed_batches():
     assert_tables_equal(got, exp, "human share 1/200")
     assert out.digest_words() == table_digest(exp)
     assert (oracle.owner_of(got["key_hi"], got["key_lo"], 16) == 0).all()
+
+
+def _codes(t):
+    lut = torch.full((256,), 255, dtype=torch.uint8, device=t.device)
+    for i, b in enumerate(b"ACGT"):
+        lut[b] = i
+    return lut[t.long()]
+
+
+def _window_keys(c, k, valid):
+    """Canonical (hi, lo) words of every window start p with valid[p] (2-bit codes c, first base most
+    significant), computed with torch on the device: a checker, independent of the HIP path."""
+    n = c.numel() - k + 1
+    p = torch.nonzero(valid[:n]).flatten()
+    lo_bases = min(k, 32)
+    hi_bases = k - lo_bases
+
+    def words(base_at):
+        hi = torch.zeros(p.numel(), dtype=torch.int64, device=c.device)
+        lo = torch.zeros_like(hi)
+        for j in range(hi_bases):
+            hi = (hi << 2) | base_at(j)
+        for j in range(hi_bases, k):
+            lo = (lo << 2) | base_at(j)
+        return hi, lo
+
+    fh, fl = words(lambda j: c[p + j].long())
+    rh, rl = words(lambda j: 3 - c[p + k - 1 - j].long())
+    s = -2 ** 63  # flip the sign bit: signed order of the flipped words = unsigned order
+    rc_less = (rh < fh) | ((rh == fh) & ((rl ^ s) < (fl ^ s)))
+    return torch.where(rc_less, rh, fh), torch.where(rc_less, rl, fl)
+
+
+def test_mid_workload_contigs_full_size():
+    """Contig generation at full size (the mid workload's 1.0e8 UU k-mers, the configuration bench.py
+    times), checked by properties that hold at any size: the contigs' windows are exactly the UU
+    k-mers, each once (device-side, with torch); and on 300 sampled contigs, consecutive k-mers are
+    linked from both ends, the ends do not extend, and the spelling is canonical."""
+    w = synth.mid()
+    r = w.reads()
+    p = w.params
+    L, k = r.read_len, p.k
+    positions = r.n_reads * (L - k + 1)
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(r.ascii).to(dev)
+    q = torch.from_numpy(r.qual).to(dev)
+    packed = kmer.pack_reads(a, q, read_len=L, qcut=p.qcut)
+    del a, q
+    card = kmer.CardSketch(k, positions, device=dev).run([packed], min_depth=p.min_depth)
+    cap, bw, lcap = kmer.plan_sizes(card, n_hash=4, device=dev)
+    kc = kmer.KmerCounter(k, cap, bw, lcap, n_hash=4, min_depth=p.min_depth, heavy=card, device=dev)
+    uu = kmer.Records(int(cap * 0.5), device=dev)
+    kc.run([packed], uu, flags=abi.HM_EXPORT_UU_ONLY, fused=True)
+    assert kc.status() == abi.HM_OK
+    del kc, packed
+    torch.cuda.empty_cache()
+    n_uu = int(uu.n_out.item())
+    print("mid full size: %d UU k-mers" % n_uu, flush=True)
+    cs = kmer.ContigSet(uu.capacity, k, device=dev)
+    assert cs.run(uu) == 0
+    nc, nb = (int(x) for x in cs.counts.cpu().numpy())
+    assert nb - nc * (k - 1) == n_uu and nc > 100_000
+    off = cs.off[:nc + 1]
+    assert (off[1:] - off[:-1] >= k).all() and int(off[0].item()) == 0 and int(off[-1].item()) == nb
+    seq = cs.seq[:nb]
+    c = _codes(seq)
+    assert (c < 4).all()
+    # windows inside a contig: p + k <= end of p's contig
+    cid = torch.bucketize(torch.arange(nb, device=dev), off[1:], right=True)
+    valid = torch.arange(nb, device=dev) + k <= off[1:][cid]
+    wh, wl = _window_keys(c, k, valid)
+    assert wh.numel() == n_uu
+    got = torch.unique(torch.stack([wh, wl], 1), dim=0)
+    exp = torch.unique(torch.stack([uu.key_hi[:n_uu], uu.key_lo[:n_uu]], 1), dim=0)
+    assert got.shape == exp.shape and torch.equal(got, exp), "contig windows differ from the UU k-mers"
+    del got, exp, wh, wl, cid, valid, c
+    # sampled contigs, with Python strings, against the export's keys and classes
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(nc, 300, replace=False))
+    offs = off.cpu().numpy()
+    sb = seq.cpu().numpy().tobytes()
+    contigs = [sb[offs[i]:offs[i + 1]].decode() for i in pick]
+    his = uu.key_hi[:n_uu].cpu().numpy().view(np.uint64)
+    from tests import brute
+
+    def canon(x):
+        return min(x, brute.revcomp(x))
+
+    want = set()
+    for ctg in contigs:
+        for i in range(len(ctg) - k + 1):
+            want.add(brute.enc(canon(ctg[i:i + k])) >> 64)
+        for x in ("ACGT"):
+            want.add(brute.enc(canon(x + ctg[:k - 1])) >> 64)
+            want.add(brute.enc(canon(ctg[-(k - 1):] + x)) >> 64)
+    m = np.isin(his, np.array(sorted(want), dtype=np.uint64))
+    los = uu.key_lo[:n_uu].cpu().numpy().view(np.uint64)[m]
+    cls_l = uu.cls_l[:n_uu].cpu().numpy()[m]
+    cls_r = uu.cls_r[:n_uu].cpu().numpy()[m]
+    table = {(int(h) << 64) | int(l): (int(a_), int(b_)) for h, l, a_, b_ in zip(his[m], los, cls_l, cls_r)}
+    B = "ACGT"
+
+    def ext(s):  # (left, right) extension of the oriented k-mer s, or None if not a UU k-mer
+        cs_ = canon(s)
+        v = table.get(brute.enc(cs_))
+        if v is None:
+            return None
+        l_, r_ = B[v[0]], B[v[1]]
+        return (l_, r_) if cs_ == s else (brute.COMP[r_], brute.COMP[l_])
+
+    def linked_right(s):  # the k-mer s links to on its right (both ends agree, no hairpin), or None
+        e = ext(s)
+        t = s[1:] + e[1]
+        et = ext(t)
+        if et is None or et[0] != s[0] or (canon(t) == canon(s) and t != s):
+            return None
+        return t
+
+    cycles = 0
+    for ctg in contigs:
+        ks = [ctg[i:i + k] for i in range(len(ctg) - k + 1)]
+        for x, y in zip(ks, ks[1:]):
+            assert linked_right(x) == y, ctg[:60]
+        nxt = linked_right(ks[-1])
+        prv = linked_right(brute.revcomp(ks[0]))  # the left link of the first k-mer, read backwards
+        if nxt is not None:  # a cycle: it closes on its first k-mer and starts at its smallest key
+            cycles += 1
+            assert nxt == ks[0] and prv == brute.revcomp(ks[-1])
+            assert ks[0] == canon(ks[0]) and brute.enc(ks[0]) == min(brute.enc(canon(x)) for x in ks)
+        else:
+            assert prv is None
+            assert ctg <= brute.revcomp(ctg)
+    print("sampled 300 contigs (%d cycles): links, ends and orientation hold" % cycles)
