@@ -272,6 +272,9 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
     ap.add_argument("--no-contigs", action="store_true", help="skip the contig generation measurement")
+    ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device copy measurement")
+    ap.add_argument("--no-bypass-diag", action="store_true",
+                    help="skip the Bloom-bypass diagnostic (one pass into a table sized for every distinct k-mer)")
     ap.add_argument("--no-heavy", action="store_true",
                     help="count heavy hitters through the table instead of workgroup-local counters")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
@@ -394,6 +397,9 @@ def main():
 
     stage_ms = {name: float(np.mean([events[s][i].elapsed_time(events[s][i + 1]) for s in range(args.steps)]))
                 for i, name in enumerate(stages)}
+    step_ms = np.array([events[s][0].elapsed_time(events[s][len(stages)]) for s in range(args.steps)])
+    step_dist = {"median": round(float(np.median(step_ms)), 3), "p10": round(float(np.percentile(step_ms, 10)), 3),
+                 "p90": round(float(np.percentile(step_ms, 90)), 3), "n": int(args.steps)}
     ms_per_step = elapsed * 1000 / args.steps
     value = positions * args.steps / elapsed
     log("stage ms: " + ", ".join("%s %.2f" % kv for kv in stage_ms.items()))
@@ -454,6 +460,61 @@ def main():
     if not args.no_contigs:
         contigs = measure_contigs(kc, k, n_records, stream, log, rates=rates)
 
+    h2d = None
+    if not args.no_h2d:
+        # secondary figure: the same ASCII + Phred handed over from pinned host memory (the boundary
+        # takes device buffers, so this copy is never part of `value`)
+        pa = torch.empty(r.ascii.size, dtype=torch.uint8, pin_memory=True)
+        pq = torch.empty(r.qual.size, dtype=torch.uint8, pin_memory=True)
+        pa.numpy()[:] = r.ascii
+        pq.numpy()[:] = r.qual
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ascii.copy_(pa, non_blocking=True)
+        qual.copy_(pq, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        nbytes = r.ascii.size + r.qual.size
+        h2d = {"bytes": int(nbytes), "ms": round(ms, 3), "GBps": round(nbytes / (ms / 1000) / 1e9, 2),
+               "kmers_per_s_with_h2d": round(positions / ((step_dist["median"] + ms) / 1000), 1)}
+        log("h2d: %s" % h2d)
+        del pa, pq
+
+    bypass = None
+    if not args.no_bypass_diag:
+        # diagnostic: the paper's pre-Bloom scheme, every occurrence counted in one pass into a table sized
+        # for every distinct k-mer (about 4x the Bloom design's table); same digest required
+        bcap = kmer.next_pow2(int(card.estimate / 0.45))
+        kb = kmer.KmerCounter(k, bcap, 1, 0, min_depth=p.min_depth, flags=abi.HM_BLOOM_BYPASS, device=dev)
+        ob = kmer.Records(int(n_records * 1.05), device=dev)
+        kb.run([packed], ob, fused=True)  # warm-up
+        abi.check(kb.status(), "bypass diagnostic")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        kb.reset()
+        ev[1].record(stream)
+        kb.insert(packed)
+        ev[2].record(stream)
+        kb.count()
+        ev[3].record(stream)
+        kb.export(ob, abi.HM_EXPORT_CLASSIFY)
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        abi.check(kb.status(), "bypass diagnostic")
+        same = ob.digest_words() == ref_digest and int(ob.n_out.item()) == n_records
+        bst = kb.stats()
+        bms = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+        bypass = {"table_slots": kb.capacity, "table_GB": round(kb.capacity * 64 / 1e9, 1),
+                  "init_ms": round(bms[0], 3), "pass1_ms": round(bms[1], 3), "pass2_ms": round(bms[2], 3),
+                  "export_ms": round(bms[3], 3), "total_ms": round(sum(bms), 3), "same_digest": same,
+                  "events_per_position": {x: round(v / positions, 4) for x, v in bst.items()}}
+        log("bloom-bypass diagnostic: %s" % bypass)
+        assert same, "bypass diagnostic changed the table"
+        del kb, ob
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -493,11 +554,14 @@ def main():
                                    "sampled_kept": card.sampled_kept, "sample_log2": card.sample_log2,
                                    "kept_estimate": card.sampled_kept << card.sample_log2,
                                    "heavy_hitters": card.n_heavy},
-                   "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()}},
+                   "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
+                   "step_ms": step_dist},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sorted_export": sorted_export,
         "contigs": contigs,
+        "h2d": h2d,
+        "bloom_bypass_diagnostic": bypass,
         "batched": batched,
         "serving": serving,
     }
