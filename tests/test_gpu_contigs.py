@@ -225,3 +225,38 @@ def test_contigs_cover_every_uu_kmer_once():
             assert brute.enc(min(x, brute.revcomp(x))) in uu
         seen += len(c) - k + 1
     assert sum(len(c) - k + 1 for c in got) == len(uu)
+
+
+@pytest.mark.parametrize("k,fwd", [(1, False), (1, True), (3, False), (2, True)])
+def test_smallest_k(k, fwd):
+    """k = 1..3: a handful of keys, every link a candidate, self-loops and hairpins everywhere."""
+    ascii, qual, off = random_read_set(990 + k, 300, 5, 40, genome_len=60)
+    t = oracle.run(ascii, qual, off, k, min_depth=1, forward_only=fwd, n_threads=4)
+    exp = oracle.contigs(t, k, forward_only=fwd)
+    assert gpu_contigs_of_table(t, k, forward_only=fwd) == exp
+
+
+def test_single_kmer_contigs_and_no_uu():
+    """UU k-mers with no links are one-k-mer contigs (in canonical spelling); a table without UU
+    records gives no contigs."""
+    rng = np.random.default_rng(21)
+    reads = ["".join(rng.choice(list(BASES), 23)) for _ in range(200)]  # k=21: three k-mers per read, no overlaps
+    t, _ = table_of(reads * 2, 21)
+    exp = oracle.contigs(t, 21)
+    assert gpu_contigs_of_table(t, 21) == exp
+    assert any(len(c) == 21 for c in exp)
+    m = oracle.uu_mask(t)
+    nouu = {x: v[~m] for x, v in t.items() if isinstance(v, np.ndarray)}
+    assert len(nouu["key_hi"]) > 0
+    assert gpu_contigs_of_table(nouu, 21) == [] == oracle.contigs(nouu, 21)
+
+
+def test_record_count_above_capacity():
+    """An export that overflowed reports more records than its buffer holds: only the buffer's
+    records are read."""
+    rng = np.random.default_rng(22)
+    g, reads = genome_reads(rng, 800, 60)
+    t, _ = table_of(reads, 21)
+    r = kmer.Records.from_numpy(t)
+    r.n_out.fill_(r.capacity + 12345)
+    assert kmer.contigs(r, 21) == oracle.contigs(t, 21)
