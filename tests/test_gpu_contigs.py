@@ -260,3 +260,38 @@ def test_record_count_above_capacity():
     r = kmer.Records.from_numpy(t)
     r.n_out.fill_(r.capacity + 12345)
     assert kmer.contigs(r, 21) == oracle.contigs(t, 21)
+
+
+def test_graph_replays_match_eager():
+    """hm_contigs captured in a HIP graph (its clears are fill kernels): three replays, with eager
+    contig generation on another input and host synchronizations between them, each equal to the
+    eager result."""
+    rng = np.random.default_rng(31)
+    reads = []
+    for G in (60, 500, 2000):
+        reads += genome_reads(rng, G, 40, circular=True)[1] + genome_reads(rng, G + 50, 40)[1]
+    t, _ = table_of(reads, 21)
+    exp = oracle.contigs(t, 21)
+    rec = kmer.Records.from_numpy(t)
+    cs = kmer.ContigSet(rec.capacity, 21)
+    assert cs.run(rec) == 0 and cs.to_list() == exp  # eager; sizes the outputs
+    other_t, _ = table_of(genome_reads(rng, 900, 40)[1], 21)
+    other = kmer.Records.from_numpy(other_t)
+    other_exp = oracle.contigs(other_t, 21)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        cs.launch(rec)  # warm-up on a side stream before capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cs.launch(rec)
+    for rep in range(3):
+        cs.counts.zero_()
+        cs.seq.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(cs.status_buf.item()) == 0, rep
+        assert cs.to_list() == exp, rep
+        assert kmer.contigs(other, 21) == other_exp  # eager work between replays
