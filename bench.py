@@ -238,13 +238,14 @@ def measure_contigs(kc, k, n_records, stream, log, reps=3, rates=None):
            "work_bytes": int(cs.work.numel() * 8)}
     # accesses per call (line granular, first probes only), per UU k-mer u and per reading h = 2u:
     #   index: a probe load and a claiming CAS per u;  link: two neighbour slot loads per u;
-    #   walk: a successor load and a rank store per h;  settle: a ruler-rank load per h;
-    #   spell: a head-offset load per h and a base store per contig base;
-    # plus the streamed bytes: the index and offset fills (32 + 8 bytes per slot and reading of the
-    # buffer's capacity) and per u about 188 bytes of keys, classes, links and ranks read and written
+    #   walk 1 (lengths) and walk 2 (copy into runs): a successor load per h each;
+    #   rulers (1 in 32 k-mers and the chain heads): a few words each, not counted;
+    # plus the streamed bytes: the index fill (64 bytes per record of the buffer's capacity) and
+    # per u about 90 bytes: keys and classes read twice, links written, runs written and read, the
+    # contig bases
     cap = uu.capacity
-    loads, stores, atomics = 9 * n_uu, 2 * n_uu + nb, n_uu
-    seq_bytes = 32 * 2 * cap + 8 * 2 * cap + 188 * n_uu
+    loads, stores, atomics = 7 * n_uu, 0, n_uu
+    seq_bytes = 64 * cap + 90 * n_uu + nb
     res["random_ops_per_uu_kmer"] = round((loads + stores + atomics) / max(n_uu, 1), 2)
     res["achieved_random_Gops"] = round((loads + stores + atomics) / (t / 1000) / 1e9, 2)
     if rates:

@@ -364,10 +364,10 @@ typedef struct {
     uint64_t work_bytes;
 } hm_contigs_t;
 
-/* Scratch of hm_contigs for an input of up to `capacity` records: 136 bytes
+/* Scratch of hm_contigs for an input of up to `capacity` records: 186 bytes
  * per record (two 32-byte index slots, so the index is at most half full; and
- * for each of the k-mer's two readings its links, ranks and list entries),
- * plus 512 bytes; 0 if capacity is 2^29 or more. */
+ * for each of the k-mer's two readings its links, ranks, segment and list
+ * entries), plus 512 bytes; 0 if capacity is 2^29 or more. */
 size_t hm_contigs_work_bytes(uint64_t capacity);
 
 /* Contigs of the UU k-mers among the records of `uu` (an export: key_hi,

@@ -10,17 +10,17 @@
 //   2. link: every UU k-mer looks up its right and left neighbours and keeps
 //      a link only where it agrees from both ends and is not a hairpin.  A
 //      half-node is a k-mer read in one orientation (2i: key orientation,
-//      2i+1: reverse complement); each half-node gets its successor and
-//      predecessor, so each path or cycle of k-mers appears twice, once per
-//      reading direction (once with HM_FORWARD_ONLY);
-//   3. rank (sparse ruling set): chain heads and one k-mer in 32 (picked by a
-//      hash of its record number) are rulers; each ruler walks its segment up
-//      to the next ruler, giving every half-node its ruler and offset; pointer
-//      jumping over the rulers alone gives each ruler its head and rank, and
-//      then every half-node its head and rank.  A ruler whose distance passes
-//      the number of k-mers sits on a cycle, and so does a half-node no walker
-//      reached;
-//   4. cycles: pointer jumping over the cycle half-nodes gives each the
+//      2i+1: reverse complement); each half-node gets its successor (with the
+//      base the step adds) and predecessor, so each path or cycle of k-mers
+//      appears twice, once per reading direction (once with HM_FORWARD_ONLY);
+//   3. segments (sparse ruling set): chain heads and one k-mer in 32 (picked
+//      by a hash of its record number) are rulers; each ruler walks its
+//      segment up to the next ruler, once to count it and once to copy its
+//      half-nodes and bases into a run of their own; pointer jumping over the
+//      rulers alone gives each segment its chain head and rank.  A ruler whose
+//      distance passes the number of k-mers sits on a cycle, and so does a
+//      half-node that no segment holds;
+//   4. cycles (per half-node): pointer jumping gives each cycle half-node the
 //      cycle's smallest key; the cycle is cut before it (the reading that
 //      holds that k-mer in key orientation becomes a chain, the mirror one a
 //      chain that is dropped) and ranked again;
@@ -29,8 +29,8 @@
 //      other and their first k bases already differ, so this is the smaller
 //      string;
 //   6. spell: each kept chain takes its contig number and base offset from
-//      one packed counter (so offsets rise with the contig number), and every
-//      half-node writes its base at its rank.
+//      one packed counter (so offsets rise with the contig number); each
+//      segment copies its run of bases to its rank, in order.
 // Counters shared by the whole grid are updated once per workgroup, not per
 // wave, on the paths every k-mer takes.  The round kernels read their work
 // counts from device memory, so the whole call is a fixed sequence of
@@ -40,16 +40,18 @@
 namespace hm {
 namespace {
 
-constexpr uint32_t kNone = 0xFFFFFFFFu;       // no link / chain end / no ruler yet
+constexpr uint32_t kNone = 0xFFFFFFFFu;       // no link / chain end
 constexpr uint32_t kInactive = 0xFFFFFFFEu;   // pred of a half-node outside the graph
 constexpr uint32_t kCut = 0xFFFFFFFDu;        // pred of a cycle cut's head
+constexpr uint32_t kIdMask = 0x3FFFFFFFu;     // successor word: half-node id | added base << 30
 constexpr unsigned long long kEmpty = ~0ull;  // empty index slot
 constexpr uint64_t kNoOff = ~0ull;            // chain not written
 constexpr uint64_t kIndexSeed = 0x13198A2E03707344ull;
 constexpr int kRounds = 32;                   // bound on pointer-jumping rounds per phase
 constexpr uint32_t kDone = 0x80000000u;       // ruler distance word: rank final
 constexpr uint32_t kCycW = 0x7FFFFFFFu;       // ruler distance word: on a cycle
-constexpr uint32_t kListDone = 0x80000000u;   // ruler list entry: settled
+constexpr uint32_t kListDone = 0x80000000u;   // ruler list entry: ranked
+constexpr uint32_t kSegEnd = 0x80000000u;     // segment length word: the segment ends its chain
 constexpr int kRulerShift = 27;               // 1 ruler in 2^(32 - 27) = 32 k-mers
 constexpr int kCntBits = 29;                  // contig counter: number in the high 29 bits,
 constexpr int kOffBits = 35;                  // bases in the low 35
@@ -57,16 +59,19 @@ constexpr uint64_t kOffMask = (1ull << kOffBits) - 1;
 constexpr uint64_t kMaxRecords = 1ull << 29;
 // fewer than 2^29 contigs, and at most 2^29 k-mers plus 62 bases per contig
 static_assert(kCntBits + kOffBits == 64 && (1ull << kCntBits) >= kMaxRecords, "contig counter fields");
+// with fewer than kMaxRecords records a half-node id is at most 2 * kMaxRecords - 3, below kIdMask, so a
+// successor word never reads as kNone
+static_assert(2 * kMaxRecords - 3 < kIdMask, "half-node ids fit the successor word");
 constexpr uint32_t kStop = HM_ST_DUPLICATE | HM_ST_TABLE_FULL;
 constexpr int kRulerBuf = 4096;               // workgroup-local ruler buffer (entries)
-constexpr int kAllocPer = 16;                 // half-nodes per thread in the offset pass
+constexpr int kPer = 16;                      // consecutive entries per thread in the placement passes
 
 struct Ctl {
-    unsigned long long alloc;  // (contigs << 35) | bases
-    unsigned int n_uu;         // UU records
-    unsigned int n_cyc;        // half-nodes found on cycles
+    unsigned long long alloc;     // (contigs << 35) | bases
+    unsigned long long seg_total; // half-nodes placed in segments
+    unsigned long long n_cyc;     // half-nodes found on cycles
+    unsigned int n_uu;            // UU records
     unsigned int n_rulers;
-    unsigned int pad;
     unsigned int cnt_re[kRounds + 1];
 };
 constexpr size_t kCtlBytes = 512;
@@ -81,29 +86,35 @@ static_assert(sizeof(IndexSlot) == 32, "index slot");
 
 struct Layout {
     uint64_t slots, half;
-    size_t ctl, table, S, RS, succ, pred, hlen, listA, cyc, total;
+    size_t ctl, table, S, RS, hoff, succ, pred, hlen, listA, cyc, rlA, seg, seglen, segoff, visited, total;
 };
 
 size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// work buffer: control block, index, and per half-node arrays.  The ruler
-// ranks (RS) become the chain offsets once every half-node is ranked, and the
-// second list of the cycle re-ranking lives in hlen until the chains are
-// chosen.
+// Work buffer: control block, index, and arrays of one entry per reading of a
+// k-mer (a ruler list entry, a segment position and a cycle list entry also
+// number at most that).  The second list of the cycle re-ranking lives in
+// hlen until the chains are chosen.
 Layout layout(uint64_t cap) {
     Layout L;
     L.slots = 2 * cap < 64 ? 64 : 2 * cap;
     L.half = 2 * cap;
     size_t o = 0;
-    L.ctl = o;   o += up256(kCtlBytes);
-    L.table = o; o += up256(L.slots * sizeof(IndexSlot));
-    L.S = o;     o += up256(L.half * 8);
-    L.RS = o;    o += up256(L.half * 8);
-    L.succ = o;  o += up256(L.half * 4);
-    L.pred = o;  o += up256(L.half * 4);
-    L.hlen = o;  o += up256(L.half * 4);
-    L.listA = o; o += up256(L.half * 4);
-    L.cyc = o;   o += up256(L.half * 4);
+    L.ctl = o;     o += up256(kCtlBytes);
+    L.table = o;   o += up256(L.slots * sizeof(IndexSlot));
+    L.S = o;       o += up256(L.half * 8);
+    L.RS = o;      o += up256(L.half * 8);
+    L.hoff = o;    o += up256(L.half * 8);
+    L.succ = o;    o += up256(L.half * 4);
+    L.pred = o;    o += up256(L.half * 4);
+    L.hlen = o;    o += up256(L.half * 4);
+    L.listA = o;   o += up256(L.half * 4);
+    L.cyc = o;     o += up256(L.half * 4);
+    L.rlA = o;     o += up256(L.half * 4);
+    L.seg = o;     o += up256(L.half * 4);
+    L.seglen = o;  o += up256(L.half * 4);
+    L.segoff = o;  o += up256(L.half * 4);
+    L.visited = o; o += up256(L.half);
     L.total = o;
     return L;
 }
@@ -115,9 +126,14 @@ struct Graph {
     uint64_t cap;
     IndexSlot *table;
     uint64_t slots;
-    unsigned long long *S;   // per half-node (distance << 32) | ancestor; (min node << 32) | ancestor on cycles
-    unsigned long long *RS;  // per ruler (distance << 32) | ancestor ruler; later per head: chain offset
-    uint32_t *succ, *pred, *hlen, *listA, *listB, *cyc;
+    unsigned long long *S;   // cycle half-nodes: (min node << 32) | ancestor, then (distance << 32) | ancestor
+    unsigned long long *RS;  // per ruler: (distance << 32) | ancestor ruler
+    uint64_t *hoff;          // per chain head: output offset, or kNoOff
+    uint32_t *succ;          // successor id | base it adds << 30, or kNone
+    uint32_t *pred, *hlen, *listA, *listB, *cyc, *rlA;
+    uint32_t *seg;             // segment runs: half-node id | the base it adds << 30
+    uint32_t *seglen, *segoff; // per ruler entry: run length | kSegEnd, run start
+    uint8_t *visited;
     Ctl *ctl;
     uint32_t *status;
     int k;
@@ -236,6 +252,43 @@ __device__ __forceinline__ unsigned int block_sum(unsigned int v, unsigned int *
     return t;
 }
 
+// last base of a k-mer read in orientation o (the base a step onto it adds)
+__device__ __forceinline__ uint32_t last_base(uint64_t hi, uint64_t lo, int o, int k) {
+    if (!o) return (uint32_t)(lo & 3);
+    const u128 x = ((u128)hi << 64) | lo;
+    return 3u - (uint32_t)((x >> (2 * (k - 1))) & 3);  // the complement of the key's first base
+}
+
+// Workgroup placement: each thread brings `mine` (a count, or packed counts),
+// the workgroup takes its range of `counter` with one atomic, and each thread
+// gets the start of its own part, in thread order.  Every thread of the
+// workgroup calls it, the same number of times.
+__device__ __forceinline__ unsigned long long block_place(unsigned long long mine, unsigned long long *counter,
+                                                          unsigned long long *s_w, unsigned long long *s_base) {
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    unsigned long long x = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            const unsigned long long v = s_w[w];
+            s_w[w] = t;
+            t += v;
+        }
+        *s_base = t ? atomicAdd(counter, t) : 0ull;
+    }
+    __syncthreads();
+    const unsigned long long r = *s_base + s_w[wave] + x - mine;
+    __syncthreads();  // s_w and s_base are reused by the next call
+    return r;
+}
+
 // ------------------------------------------------------------------ 1. index
 
 __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
@@ -334,6 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
     if (stopped(g)) return;
     const uint64_t n = n_records(g);
     const int lane = __lane_id();
+    const int k = g.k;
     uint32_t *wbuf = s_buf + (threadIdx.x >> 6) * kWaveBuf;
     uint32_t cnt = 0;  // wave-uniform
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -347,8 +401,6 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
             if (!is_uu(g, i)) {
                 g.succ[h0] = g.succ[h1] = kNone;
                 g.pred[h0] = g.pred[h1] = kInactive;
-                st(g.S + h0, pack(0, h0));
-                st(g.S + h1, pack(0, h1));
             } else {
                 const int cl = g.cl[i], cr = g.cr[i];
                 const u128 s = key_of(g, (uint32_t)i);
@@ -368,21 +420,21 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
                 else if (m == 0) jL = kNone;
                 const uint32_t R = step_link((uint32_t)i, sr, 0, jR, r_cl, r_cr);
                 const uint32_t Lf = step_link((uint32_t)i, sl, 1, jL, l_cl, l_cr);
-                g.succ[h0] = R;
+                // a successor word carries the base the step adds: the last base of the
+                // neighbour read in its orientation (its key is the one just looked up)
+                g.succ[h0] = R == kNone ? kNone : (R | last_base(lr.khi, lr.klo, (int)(R & 1), k) << 30);
                 g.pred[h0] = Lf;
-                st(g.S + h0, pack(0, kNone));
                 const bool samp = sampled(h0);
                 r0 = Lf == kNone || samp;
                 if (g.fwd) {
                     g.succ[h1] = kNone;
                     g.pred[h1] = kInactive;
-                    st(g.S + h1, pack(0, h1));
                 } else {
                     // the reverse-complement reading runs the same links backwards
                     const uint32_t p1 = R == kNone ? kNone : (R ^ 1u);
-                    g.succ[h1] = Lf == kNone ? kNone : (Lf ^ 1u);
+                    const uint32_t s1 = Lf == kNone ? kNone : (Lf ^ 1u);
+                    g.succ[h1] = s1 == kNone ? kNone : (s1 | last_base(ll.khi, ll.klo, (int)(s1 & 1), k) << 30);
                     g.pred[h1] = p1;
-                    st(g.S + h1, pack(0, kNone));
                     r1 = p1 == kNone || samp;
                 }
             }
@@ -407,15 +459,16 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
     }
 }
 
-// ------------------------------------------------------------------ 3. rank
+// ------------------------------------------------------------------ 3. segments
 
-// Each ruler walks its segment: every half-node up to the next ruler (or the
-// chain's end) gets (offset, ruler); the next ruler gets (segment length,
-// this ruler) as its ruler-level predecessor.  A head is its own ruler-level
-// head at distance 0.  A workgroup owns a contiguous range of rulers and a
-// lane whose walk ends takes the next one, so no lane idles while the
-// longest segment of its wave is walked.
-__global__ __launch_bounds__(kBlock) void k_ctg_walk(Graph g) {
+// Walk 1: each ruler follows successors up to the next ruler (or its chain's
+// end) and records its segment's length (with kSegEnd when the chain ends
+// there); the next ruler gets (segment length, this ruler) as its
+// ruler-level predecessor, and a head is its own ruler-level head at
+// distance 0.  A workgroup owns a contiguous range of the ruler list and a
+// lane whose walk ends takes the next one, so no lane idles while the longest
+// segment of its wave is walked.
+__global__ __launch_bounds__(kBlock) void k_ctg_seglen(Graph g) {
     __shared__ unsigned int s_next;
     if (stopped(g)) return;
     const uint32_t n = g.ctl->n_rulers;
@@ -428,29 +481,95 @@ __global__ __launch_bounds__(kBlock) void k_ctg_walk(Graph g) {
     bool live = x < hi;
     if (live) {
         R = cur = g.listA[x];
-        st(g.S + R, pack(0, R));
         if (g.pred[R] == kNone) st(g.RS + R, pack(0, R));
     }
     while (live) {
-        const uint32_t nx = g.succ[cur];
-        bool end = nx == kNone || sampled(nx);
+        const uint32_t w = g.succ[cur];
+        const uint32_t nx = w & kIdMask;
+        bool end = w == kNone || sampled(nx);
         if (!end && ++t >= bound) {  // longer than the graph: cannot happen
             atomicOr(g.status, HM_ST_TIMEOUT);
-            end = true;  // t == bound: no ruler-level link written
+            end = true;
+            t = 0;
         } else if (!end) {
-            st(g.S + nx, pack(t, R));
             cur = nx;
         }
         if (end) {
-            if (nx != kNone && t < bound) st(g.RS + nx, pack(t + 1, R));
+            if (w != kNone) st(g.RS + nx, pack(t + 1, R));
+            g.seglen[x] = (t + 1) | (w == kNone ? kSegEnd : 0u);
             x = atomicAdd(&s_next, 1u);
             live = x < hi;
             if (live) {
                 R = cur = g.listA[x];
                 t = 0;
-                st(g.S + R, pack(0, R));
                 if (g.pred[R] == kNone) st(g.RS + R, pack(0, R));
             }
+        }
+    }
+}
+
+// Each ruler entry's run in the segment arrays, kPer consecutive entries per
+// thread, one atomic per workgroup.
+__global__ __launch_bounds__(kBlock) void k_ctg_segplace(Graph g) {
+    __shared__ unsigned long long s_w[kBlock / 64], s_base;
+    if (stopped(g)) return;
+    const uint32_t n = g.ctl->n_rulers;
+    const uint32_t chunk = kBlock * kPer;
+    for (uint32_t c0 = blockIdx.x * chunk; c0 < n; c0 += gridDim.x * chunk) {  // uniform per workgroup
+        const uint32_t x0 = c0 + threadIdx.x * kPer;
+        unsigned long long mine = 0;
+        for (int j = 0; j < kPer && x0 + j < n; ++j) mine += g.seglen[x0 + j] & ~kSegEnd;
+        unsigned long long at = block_place(mine, &g.ctl->seg_total, s_w, &s_base);
+        for (int j = 0; j < kPer && x0 + j < n; ++j) {
+            g.segoff[x0 + j] = (uint32_t)at;
+            at += g.seglen[x0 + j] & ~kSegEnd;
+        }
+    }
+}
+
+// Walk 2: each ruler copies its segment into its run: each half-node's id with
+// the base it adds, which is the successor word that reached it (the ruler's
+// own base: the last base of its k-mer).
+__global__ __launch_bounds__(kBlock) void k_ctg_segfill(Graph g) {
+    __shared__ unsigned int s_next;
+    if (stopped(g)) return;
+    const uint32_t n = g.ctl->n_rulers;
+    const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    if (threadIdx.x == 0) s_next = lo + kBlock;
+    __syncthreads();
+    const uint64_t room = 2 * g.cap;
+    uint32_t x = lo + threadIdx.x, cur = 0, t = 0, len = 0, o = 0;
+    bool live = x < hi;
+    auto start = [&](uint32_t e) {
+        const uint32_t R = g.listA[e] & ~kListDone;
+        len = g.seglen[e] & ~kSegEnd;
+        o = g.segoff[e];
+        t = 0;
+        cur = R;
+        if ((uint64_t)o + len > room) {  // more than the graph holds: cannot happen
+            atomicOr(g.status, HM_ST_TIMEOUT);
+            len = 0;
+            return;
+        }
+        g.seg[o] = R | last_base(g.hi[R >> 1], g.lo[R >> 1], (int)(R & 1), g.k) << 30;
+    };
+    if (live) start(x);
+    while (live) {
+        if (t + 1 < len) {
+            const uint32_t w = g.succ[cur];
+            if (w == kNone) {  // shorter than walk 1 found it: cannot happen
+                atomicOr(g.status, HM_ST_TIMEOUT);
+                len = 0;
+                continue;
+            }
+            cur = w & kIdMask;
+            ++t;
+            g.seg[o + t] = w;
+        } else {
+            x = atomicAdd(&s_next, 1u);
+            live = x < hi;
+            if (live) start(x);
         }
     }
 }
@@ -498,46 +617,81 @@ __global__ __launch_bounds__(kBlock) void k_ctg_rjump(Graph g, int r) {
     }
 }
 
-// Every half-node's head and rank from its ruler's; half-nodes on cycles
-// (their ruler's, or no ruler at all) go to the cycle list.
-__global__ __launch_bounds__(kBlock) void k_ctg_settle(Graph g) {
+// The half-nodes of cycle rulers' segments go to the cycle list (kPer ruler
+// entries per thread, one atomic per workgroup).
+__global__ __launch_bounds__(kBlock) void k_ctg_cycseg(Graph g) {
+    __shared__ unsigned long long s_w[kBlock / 64], s_base;
     if (stopped(g)) return;
-    const uint64_t nh = 2 * n_records(g);
-    const int lane = __lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t wb = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < nh; wb += stride) {
-        const uint64_t h = wb + lane;
-        bool cyc = false;
-        if (h < nh && g.pred[h] != kInactive) {
-            const unsigned long long v = ld(g.S + h);
-            const uint32_t R = (uint32_t)v, t = (uint32_t)(v >> 32);
-            if (R == kNone) {
-                cyc = true;  // no walker came by: a cycle without a ruler
-            } else if (R >= nh) {
-                atomicOr(g.status, HM_ST_TIMEOUT);  // cannot happen
-            } else {
-                const unsigned long long r = ld(g.RS + R);
-                const uint32_t W = (uint32_t)(r >> 32);
-                if (W == kCycW) cyc = true;
-                else if (!(W & kDone)) atomicOr(g.status, HM_ST_TIMEOUT);  // cannot happen
-                else st(g.S + h, pack((W & ~kDone) + t, (uint32_t)r));
-            }
+    const uint32_t n = g.ctl->n_rulers;
+    const uint32_t chunk = kBlock * kPer;
+    for (uint32_t c0 = blockIdx.x * chunk; c0 < n; c0 += gridDim.x * chunk) {  // uniform per workgroup
+        const uint32_t x0 = c0 + threadIdx.x * kPer;
+        unsigned long long mine = 0;
+        for (int j = 0; j < kPer && x0 + j < n; ++j) {
+            const uint32_t R = g.listA[x0 + j] & ~kListDone;
+            if ((uint32_t)(ld(g.RS + R) >> 32) == kCycW) mine += g.seglen[x0 + j] & ~kSegEnd;
         }
-        wave_append(cyc, (uint32_t)h, g.cyc, &g.ctl->n_cyc);
+        unsigned long long at = block_place(mine, &g.ctl->n_cyc, s_w, &s_base);
+        if (!mine) continue;
+        for (int j = 0; j < kPer && x0 + j < n; ++j) {
+            const uint32_t R = g.listA[x0 + j] & ~kListDone;
+            if ((uint32_t)(ld(g.RS + R) >> 32) != kCycW) continue;
+            const uint32_t len = g.seglen[x0 + j] & ~kSegEnd, o = g.segoff[x0 + j];
+            for (uint32_t t = 0; t < len; ++t) g.cyc[at + t] = g.seg[o + t] & kIdMask;
+            at += len;
+        }
     }
 }
 
-// One round of pointer jumping over the half-nodes of the cut cycles (listA
-// and listB alternate): a half-node whose ancestor is a head is done, the
-// others take their ancestor's ancestor.  Rounds past the last non-empty one
-// find a zero count and return.
+// Half-nodes that no segment holds sit on cycles without a ruler.  These
+// three kernels find them, and return at once when the segments hold every
+// half-node of the graph (the usual case).
+__device__ __forceinline__ bool all_placed(const Graph &g) {
+    const unsigned long long active = (unsigned long long)g.ctl->n_uu * (g.fwd ? 1u : 2u);
+    return g.ctl->seg_total >= active;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctg_visit_clear(Graph g) {
+    if (stopped(g) || all_placed(g)) return;
+    const uint64_t nh = 2 * n_records(g);
+    for (uint64_t h = (uint64_t)blockIdx.x * kBlock + threadIdx.x; h < nh; h += (uint64_t)gridDim.x * kBlock)
+        g.visited[h] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctg_visit_mark(Graph g) {
+    if (stopped(g) || all_placed(g)) return;
+    const uint64_t np = g.ctl->seg_total;
+    for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < np; p += (uint64_t)gridDim.x * kBlock)
+        g.visited[g.seg[p] & kIdMask] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctg_visit_scan(Graph g) {
+    __shared__ unsigned long long s_w[kBlock / 64], s_base;
+    if (stopped(g) || all_placed(g)) return;
+    const uint64_t nh = 2 * n_records(g);
+    const uint64_t chunk = (uint64_t)kBlock * kPer;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < nh; c0 += (uint64_t)gridDim.x * chunk) {  // uniform
+        const uint64_t h0 = c0 + (uint64_t)threadIdx.x * kPer;
+        uint32_t bits = 0;
+        for (int j = 0; j < kPer && h0 + j < nh; ++j)
+            if (g.pred[h0 + j] != kInactive && !g.visited[h0 + j]) bits |= 1u << j;
+        unsigned long long at = block_place((unsigned long long)__popc(bits), &g.ctl->n_cyc, s_w, &s_base);
+        for (int j = 0; j < kPer; ++j)
+            if ((bits >> j) & 1) g.cyc[at++] = (uint32_t)(h0 + j);
+    }
+}
+
+// One round of pointer jumping over the half-nodes of the cut cycles (rlA and
+// listB alternate): a half-node whose ancestor is a head is done, the others
+// take their ancestor's ancestor.  Rounds past the last non-empty one find a
+// zero count and return.
 __global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int r) {
     if (stopped(g)) return;
     unsigned int *cnt = g.ctl->cnt_re;
     const uint32_t n = __hip_atomic_load(cnt + r, RLX, AGT);
     if (n == 0) return;
-    const uint32_t *in = (r & 1) ? g.listB : g.listA;
-    uint32_t *out = (r & 1) ? g.listA : g.listB;
+    const uint32_t *in = (r & 1) ? g.listB : g.rlA;
+    uint32_t *out = (r & 1) ? g.rlA : g.listB;
     const uint32_t limit = g.ctl->n_uu + 1u;
     const int lane = __lane_id();
     const uint32_t stride = gridDim.x * kBlock;
@@ -566,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_jump(Graph g, int r) {
 
 __global__ __launch_bounds__(kBlock) void k_ctg_cyc_init(Graph g) {
     if (stopped(g)) return;
-    const uint32_t n = g.ctl->n_cyc;
+    const uint32_t n = (uint32_t)g.ctl->n_cyc;
     for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
         const uint32_t h = g.cyc[x];
         uint32_t p = g.pred[h];
@@ -583,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_cyc_init(Graph g) {
 // spans its whole cycle and holds the node of the cycle's smallest key.
 __global__ __launch_bounds__(kBlock) void k_ctg_cyc_jump(Graph g, int r) {
     if (stopped(g)) return;
-    const uint32_t n = g.ctl->n_cyc;
+    const uint32_t n = (uint32_t)g.ctl->n_cyc;
     if (n <= 1) return;
     const int rounds = 32 - __clz(n - 1);
     if (r >= rounds) return;
@@ -603,7 +757,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_cyc_jump(Graph g, int r) {
 // again from their predecessor.
 __global__ __launch_bounds__(kBlock) void k_ctg_cut(Graph g) {
     if (stopped(g)) return;
-    const uint32_t n = g.ctl->n_cyc;
+    const uint32_t n = (uint32_t)g.ctl->n_cyc;
     const int lane = __lane_id();
     const uint32_t stride = gridDim.x * kBlock;
     for (uint32_t wb = blockIdx.x * kBlock + (threadIdx.x & ~63u); wb < n; wb += stride) {
@@ -625,108 +779,133 @@ __global__ __launch_bounds__(kBlock) void k_ctg_cut(Graph g) {
                 more = true;
             }
         }
-        wave_append(more, h, g.listA, &g.ctl->cnt_re[0]);
+        wave_append(more, h, g.rlA, &g.ctl->cnt_re[0]);
     }
 }
 
 // ------------------------------------------------------------------ 5. choose
 
-// At every chain's tail: keep the chain or not, and give its head the length.
+// At every chain end: keep the chain or not, and give its head the chain's
+// length.  Entries x < n_rulers are ruler entries (a path segment that ends
+// its chain); the rest are cycle half-nodes (the tail left by a cut).
 __global__ __launch_bounds__(kBlock) void k_ctg_choose(Graph g) {
     if (stopped(g)) return;
-    const uint64_t nh = 2 * n_records(g);
-    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < nh; t += (uint64_t)gridDim.x * kBlock) {
-        if (g.pred[t] == kInactive || g.succ[t] != kNone) continue;
-        const unsigned long long v = ld(g.S + t);
-        const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
-        if (H >= nh) continue;  // not ranked (reported): cannot happen
-        bool keep;
-        if (g.pred[H] == kCut) keep = (H & 1) == 0;  // the cycle read from its smallest key, key orientation
-        else keep = g.fwd || seq_of(g, H) < seq_of(g, (uint32_t)t ^ 1u);
-        g.hlen[H] = keep ? W + 1 : 0;
+    const uint32_t nr = g.ctl->n_rulers, n = nr + (uint32_t)g.ctl->n_cyc;
+    const uint32_t half = (uint32_t)(2 * g.cap);
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+        if (x < nr) {
+            const uint32_t sl = g.seglen[x];
+            if (!(sl & kSegEnd)) continue;
+            const uint32_t R = g.listA[x] & ~kListDone;
+            const unsigned long long v = ld(g.RS + R);
+            const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+            if (W == kCycW || !(W & kDone) || H >= half) continue;  // a cycle's, or not ranked (reported)
+            const uint32_t len = sl & ~kSegEnd;
+            const uint32_t tail = g.seg[g.segoff[x] + len - 1] & kIdMask;
+            const uint32_t last = (W & ~kDone) + len - 1;  // the tail's rank
+            const bool keep = g.fwd || seq_of(g, H) < seq_of(g, tail ^ 1u);
+            g.hlen[H] = keep ? last + 1 : 0;
+        } else {
+            const uint32_t t = g.cyc[x - nr];
+            if (g.succ[t] != kNone) continue;
+            const unsigned long long v = ld(g.S + t);
+            const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+            if (H >= half || g.pred[H] != kCut) continue;  // not ranked (reported): cannot happen
+            g.hlen[H] = (H & 1) == 0 ? W + 1 : 0;  // the cycle read from its smallest key, key orientation
+        }
     }
 }
 
 // ------------------------------------------------------------------ 6. spell
 
-// Contig numbers and offsets: a workgroup sums its chains' (1, bases) pairs
-// (packed in one word) over kAllocPer consecutive half-nodes per thread,
-// takes its range with one atomic, and hands the range out in order.
+// The chain head of entry x (a path head among the rulers, a cut head among
+// the cycle half-nodes), or kNone.
+__device__ __forceinline__ uint32_t head_of_entry(const Graph &g, uint32_t x, uint32_t nr) {
+    if (x < nr) {
+        const uint32_t R = g.listA[x] & ~kListDone;
+        return g.pred[R] == kNone ? R : kNone;
+    }
+    const uint32_t h = g.cyc[x - nr];
+    return g.pred[h] == kCut ? h : kNone;
+}
+
+// Contig numbers and offsets: kPer entries per thread; a workgroup sums its
+// chains' (1, bases) pairs (packed in one word), takes its range with one
+// atomic, and hands the range out in order.
 __global__ __launch_bounds__(kBlock) void k_ctg_alloc(Graph g, uint64_t *off, uint64_t off_cap, uint64_t seq_cap) {
-    __shared__ unsigned long long s_w[kBlock / 64];
-    __shared__ unsigned long long s_base;
+    __shared__ unsigned long long s_w[kBlock / 64], s_base;
     if (stopped(g)) return;
-    const uint64_t nh = 2 * n_records(g);
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    const uint64_t chunk = (uint64_t)kBlock * kAllocPer;
-    for (uint64_t c0 = (uint64_t)blockIdx.x * chunk; c0 < nh; c0 += (uint64_t)gridDim.x * chunk) {  // uniform
-        const uint64_t h0 = c0 + (uint64_t)threadIdx.x * kAllocPer;
+    const uint32_t nr = g.ctl->n_rulers, n = nr + (uint32_t)g.ctl->n_cyc;
+    const uint32_t chunk = kBlock * kPer;
+    for (uint32_t c0 = blockIdx.x * chunk; c0 < n; c0 += gridDim.x * chunk) {  // uniform per workgroup
+        const uint32_t x0 = c0 + threadIdx.x * kPer;
         unsigned long long mine = 0;
-        for (int j = 0; j < kAllocPer; ++j) {
-            const uint64_t h = h0 + j;
-            if (h >= nh) break;
-            const uint32_t p = g.pred[h];
-            if (p == kNone || p == kCut) {
-                const uint32_t len = g.hlen[h];
-                if (len) mine += (1ull << kOffBits) | ((uint64_t)g.k + len - 1);
+        for (int j = 0; j < kPer && x0 + j < n; ++j) {
+            const uint32_t H = head_of_entry(g, x0 + j, nr);
+            if (H == kNone) continue;
+            const uint32_t len = g.hlen[H];
+            if (len) mine += (1ull << kOffBits) | ((uint64_t)g.k + len - 1);
+        }
+        unsigned long long at = block_place(mine, &g.ctl->alloc, s_w, &s_base);
+        for (int j = 0; j < kPer && x0 + j < n; ++j) {
+            const uint32_t H = head_of_entry(g, x0 + j, nr);
+            if (H == kNone) continue;
+            const uint32_t len = g.hlen[H];
+            uint64_t o = kNoOff;
+            if (len) {
+                const uint64_t bases = (uint64_t)g.k + len - 1;
+                const uint64_t c = at >> kOffBits, b = at & kOffMask;
+                if (c < off_cap) off[c] = b;
+                if (c < off_cap && b + bases <= seq_cap) o = b;
+                else atomicOr(g.status, HM_ST_OUTPUT_FULL);
+                at += (1ull << kOffBits) | bases;
             }
+            g.hoff[H] = o;
         }
-        unsigned long long x = mine;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const unsigned long long y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) s_w[wave] = x;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long t = 0;
-            for (int w = 0; w < kBlock / 64; ++w) {
-                const unsigned long long v = s_w[w];
-                s_w[w] = t;
-                t += v;
-            }
-            s_base = t ? atomicAdd(&g.ctl->alloc, t) : 0ull;
-        }
-        __syncthreads();
-        unsigned long long at = s_base + s_w[wave] + x - mine;
-        for (int j = 0; j < kAllocPer; ++j) {
-            const uint64_t h = h0 + j;
-            if (h >= nh) break;
-            const uint32_t p = g.pred[h];
-            if (p != kNone && p != kCut) continue;
-            const uint32_t len = g.hlen[h];
-            if (!len) continue;  // offsets stay kNoOff
-            const uint64_t bases = (uint64_t)g.k + len - 1;
-            const uint64_t c = at >> kOffBits, b = at & kOffMask;
-            if (c < off_cap) off[c] = b;
-            if (c < off_cap && b + bases <= seq_cap) g.RS[h] = b;
-            else atomicOr(g.status, HM_ST_OUTPUT_FULL);
-            at += (1ull << kOffBits) | bases;
-        }
-        __syncthreads();
     }
 }
 
+__device__ __forceinline__ void write_kmer(uint8_t *seq, uint64_t o, u128 s, int k) {
+    for (int b = k - 1; b >= 0; --b) {
+        seq[o + b] = (uint8_t)"ACGT"[(int)(s & 3)];
+        s >>= 2;
+    }
+}
+
+// Spell the kept chains: a path segment copies its run of bases to its rank
+// (the head writes its whole k-mer), in order; a cycle half-node writes its
+// base at its rank.
 __global__ __launch_bounds__(kBlock) void k_ctg_write(Graph g, uint8_t *seq, uint64_t seq_cap) {
     if (stopped(g)) return;
-    const uint64_t nh = 2 * n_records(g);
+    const uint32_t nr = g.ctl->n_rulers, n = nr + (uint32_t)g.ctl->n_cyc;
+    const uint32_t half = (uint32_t)(2 * g.cap);
     const int k = g.k;
-    for (uint64_t h = (uint64_t)blockIdx.x * kBlock + threadIdx.x; h < nh; h += (uint64_t)gridDim.x * kBlock) {
-        if (g.pred[h] == kInactive) continue;
-        const unsigned long long v = ld(g.S + h);
-        const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
-        if (H >= nh) continue;  // not ranked (reported): cannot happen
-        const uint64_t o = g.RS[H];  // offset of a kept head, kNoOff elsewhere
-        if (o == kNoOff || o + k + W > seq_cap) continue;
-        u128 s = seq_of(g, (uint32_t)h);
-        if (W == 0) {
-            for (int b = k - 1; b >= 0; --b) {
-                seq[o + b] = (uint8_t)"ACGT"[(int)(s & 3)];
-                s >>= 2;
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+        if (x < nr) {
+            const uint32_t R = g.listA[x] & ~kListDone;
+            const unsigned long long v = ld(g.RS + R);
+            const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+            if (W == kCycW || !(W & kDone) || H >= half) continue;
+            const uint64_t o = g.hoff[H];  // kNoOff for a dropped chain
+            const uint32_t rank = W & ~kDone, len = g.seglen[x] & ~kSegEnd, s0 = g.segoff[x];
+            if (o >= seq_cap || (uint64_t)k + rank + len - 1 > seq_cap - o) continue;  // past the room: cannot happen
+            uint32_t t = 0;
+            if (rank == 0) {  // the head's segment starts with the head's k-mer
+                write_kmer(seq, o, seq_of(g, H), k);
+                t = 1;
             }
+            uint8_t *dst = seq + o + k - 1 + rank;
+            for (; t < len; ++t) dst[t] = (uint8_t)"ACGT"[g.seg[s0 + t] >> 30];
         } else {
-            seq[o + k - 1 + W] = (uint8_t)"ACGT"[(int)(s & 3)];
+            const uint32_t h = g.cyc[x - nr];
+            const unsigned long long v = ld(g.S + h);
+            const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+            if (H >= half) continue;
+            const uint64_t o = g.hoff[H];
+            if (o >= seq_cap || (uint64_t)k + W > seq_cap - o) continue;  // kNoOff, or past the room
+            const u128 s = seq_of(g, h);
+            if (W == 0) write_kmer(seq, o, s, k);
+            else seq[o + k - 1 + W] = (uint8_t)"ACGT"[(int)(s & 3)];
         }
     }
 }
@@ -790,12 +969,18 @@ int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *o
     g.slots = L.slots;
     g.S = reinterpret_cast<unsigned long long *>(w + L.S);
     g.RS = reinterpret_cast<unsigned long long *>(w + L.RS);
+    g.hoff = reinterpret_cast<uint64_t *>(w + L.hoff);
     g.succ = reinterpret_cast<uint32_t *>(w + L.succ);
     g.pred = reinterpret_cast<uint32_t *>(w + L.pred);
     g.hlen = reinterpret_cast<uint32_t *>(w + L.hlen);
     g.listA = reinterpret_cast<uint32_t *>(w + L.listA);
     g.listB = g.hlen;  // second re-ranking list, free until the chains are chosen
     g.cyc = reinterpret_cast<uint32_t *>(w + L.cyc);
+    g.rlA = reinterpret_cast<uint32_t *>(w + L.rlA);
+    g.seg = reinterpret_cast<uint32_t *>(w + L.seg);
+    g.seglen = reinterpret_cast<uint32_t *>(w + L.seglen);
+    g.segoff = reinterpret_cast<uint32_t *>(w + L.segoff);
+    g.visited = reinterpret_cast<uint8_t *>(w + L.visited);
     g.ctl = reinterpret_cast<Ctl *>(w + L.ctl);
     g.status = out->status;
     g.k = k;
@@ -816,20 +1001,23 @@ int hm_contigs(const hm_export_t *uu, int32_t k, uint32_t flags, hm_contigs_t *o
     HM_LAUNCH_CHECK("hm_contigs (index)");
     hipLaunchKernelGGL(k_ctg_link, g_rec, blk, 0, s, g);
     HM_LAUNCH_CHECK("hm_contigs (link)");
-    hipLaunchKernelGGL(k_ctg_walk, g_rul, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_seglen, g_rul, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_segplace, g_rul, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_segfill, g_rul, blk, 0, s, g);
     for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_rjump, g_rul, blk, 0, s, g, r);
-    hipLaunchKernelGGL(k_ctg_settle, g_half, blk, 0, s, g);
-    HM_LAUNCH_CHECK("hm_contigs (rank)");
+    HM_LAUNCH_CHECK("hm_contigs (segments)");
+    hipLaunchKernelGGL(k_ctg_cycseg, g_rul, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_visit_clear, g_half, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_visit_mark, g_half, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_visit_scan, g_half, blk, 0, s, g);
     hipLaunchKernelGGL(k_ctg_cyc_init, g_half, blk, 0, s, g);
     for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_cyc_jump, g_half, blk, 0, s, g, r);
     hipLaunchKernelGGL(k_ctg_cut, g_half, blk, 0, s, g);
     for (int r = 0; r < kRounds; ++r) hipLaunchKernelGGL(k_ctg_jump, g_half, blk, 0, s, g, r);
     HM_LAUNCH_CHECK("hm_contigs (cycles)");
-    // the ruler ranks are spent: the same words now hold the chain offsets (kNoOff unless a kept head)
-    if ((rc = fill<uint64_t>(reinterpret_cast<uint64_t *>(g.RS), L.half, kNoOff, s))) return rc;
-    hipLaunchKernelGGL(k_ctg_choose, g_half, blk, 0, s, g);
-    hipLaunchKernelGGL(k_ctg_alloc, g_half, blk, 0, s, g, out->off, out->off_capacity, out->seq_capacity);
-    hipLaunchKernelGGL(k_ctg_write, g_half, blk, 0, s, g, out->seq, out->seq_capacity);
+    hipLaunchKernelGGL(k_ctg_choose, g_rul, blk, 0, s, g);
+    hipLaunchKernelGGL(k_ctg_alloc, g_rul, blk, 0, s, g, out->off, out->off_capacity, out->seq_capacity);
+    hipLaunchKernelGGL(k_ctg_write, g_rul, blk, 0, s, g, out->seq, out->seq_capacity);
     hipLaunchKernelGGL(k_ctg_final, dim3(1), dim3(64), 0, s, g, out->counts, out->off, out->off_capacity,
                        out->seq_capacity);
     HM_LAUNCH_CHECK("hm_contigs (spell)");

@@ -185,7 +185,7 @@ def test_contigs_scratch_and_rejections(L):
     """hm_contigs_work_bytes and the host-side checks of hm_contigs (no device call)."""
     assert L.hm_contigs_work_bytes(0) > 0
     w = L.hm_contigs_work_bytes(1 << 20)
-    assert w == 136 * (1 << 20) + 512  # 136 bytes per record and the control block
+    assert w == 186 * (1 << 20) + 512  # 186 bytes per record and the control block
     assert L.hm_contigs_work_bytes(1 << 29) == 0  # too many records
     e = abi.Export(8, 8, None, None, None, 8, 8, 1000, 8, None)
     c = abi.Contigs(8, 100, 8, 10, 8, 8, 256, w)
