@@ -295,3 +295,21 @@ def test_graph_replays_match_eager():
         assert int(cs.status_buf.item()) == 0, rep
         assert cs.to_list() == exp, rep
         assert kmer.contigs(other, 21) == other_exp  # eager work between replays
+
+
+def test_long_cycle_and_path():
+    """A 300 kbp circular genome (one cycle of 3.0e5 k-mers, about 9400 rulers on it, and 6e5
+    readings in the cycle jumping) beside a 300 kbp linear one, k = 31."""
+    rng = np.random.default_rng(41)
+    L, k = 100, 31
+    reads = []
+    for circ in (True, False):
+        g = "".join(rng.choice(list(BASES), 300_000))
+        src = g + g[:L] if circ else g
+        reads += [src[s:s + L] for s in range(0, (300_000 if circ else 300_000 - L + 1), 3)]
+    t, (a, q, off) = table_of(reads, k, n_threads=8)
+    exp = oracle.contigs(t, k)
+    lens = sorted(len(c) for c in exp)
+    assert len(exp) == 2 and lens[1] == 300_000 + k - 1 and lens[0] > 299_900  # the cycle, and the path
+    assert gpu_contigs_of_table(t, k, shuffle=5) == exp
+    assert gpu_contigs_of_reads(a, q, off, k) == exp
