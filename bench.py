@@ -274,8 +274,10 @@ def main():
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
     ap.add_argument("--no-contigs", action="store_true", help="skip the contig generation measurement")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device copy measurement")
-    ap.add_argument("--no-bypass-diag", action="store_true",
-                    help="skip the Bloom-bypass diagnostic (one pass into a table sized for every distinct k-mer)")
+    ap.add_argument("--bypass-diag", action="store_true",
+                    help="add the Bloom-bypass diagnostic (one pass into a table sized for every distinct k-mer); "
+                         "off by default: it launches the same pass-1 kernel, so a kernel trace of the default run "
+                         "holds only the measured step's pass 1")
     ap.add_argument("--no-heavy", action="store_true",
                     help="count heavy hitters through the table instead of workgroup-local counters")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
@@ -484,7 +486,7 @@ def main():
         del pa, pq
 
     bypass = None
-    if not args.no_bypass_diag:
+    if args.bypass_diag:
         # diagnostic: the paper's pre-Bloom scheme, every occurrence counted in one pass into a table sized
         # for every distinct k-mer (about 4x the Bloom design's table); same digest required
         bcap = kmer.next_pow2(int(card.estimate / 0.45))
