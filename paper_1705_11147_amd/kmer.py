@@ -11,6 +11,7 @@ allocate buffers, fill the ABI structs and call the entry points in order:
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -451,12 +452,11 @@ def bloom_fp_rate(bits_per_key: float, n_hash: int) -> float:
     """False-positive rate of the single-word blocked Bloom filter (every key's n_hash bits in one
     64-bit word) at its final load: keys per word ~ Poisson(64 / bits_per_key)."""
     lam = 64.0 / max(bits_per_key, 1e-9)
-    fp, pj = 0.0, np.exp(-lam)
-    for j in range(0, int(lam * 8 + 64)):
-        if j:
-            pj *= lam / j
-        fp += pj * (1.0 - (1.0 - 1.0 / 64) ** (n_hash * j)) ** n_hash
-    return fp
+    # Poisson weights in log space over the mass around the mode (no underflow at any load)
+    lo = max(0, int(lam - 12.0 * np.sqrt(lam)) - 8)
+    j = np.arange(lo, int(lam + 12.0 * np.sqrt(lam)) + 64, dtype=np.float64)
+    logp = j * np.log(lam) - lam - np.array([math.lgamma(x + 1.0) for x in j])
+    return min(1.0, float(np.sum(np.exp(logp) * (1.0 - (1.0 - 1.0 / 64) ** (n_hash * j)) ** n_hash)))
 
 
 def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, table_load: float = 0.5,
