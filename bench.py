@@ -272,6 +272,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
+    ap.add_argument("--bloom-bits", type=float, default=12.0,
+                    help="Bloom filter bits per distinct k-mer before rounding the filter to a power of two")
+    ap.add_argument("--n-hash", type=int, default=4, help="Bloom filter bits set per k-mer (in one 64-bit word)")
+    ap.add_argument("--table-load", type=float, default=0.5,
+                    help="design load of the count table (the planned capacity is rounded up to a power of two)")
     ap.add_argument("--no-contigs", action="store_true", help="skip the contig generation measurement")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device copy measurement")
     ap.add_argument("--bypass-diag", action="store_true",
@@ -324,13 +329,14 @@ def main():
     sketch = kmer.CardSketch(k, positions, device=dev)
     card = sketch.run([packed], min_depth=p.min_depth)
     abi.check(card.status, "cardinality pass")
-    cap, bloom_words, list_cap = kmer.plan_sizes(card, n_hash=4, device=dev)
+    cap, bloom_words, list_cap = kmer.plan_sizes(card, n_hash=args.n_hash, bloom_bits=args.bloom_bits,
+                                                 table_load=args.table_load, device=dev)
     log("cardinality pass: %.4g distinct (HLL), %d of %d sampled keys kept (1/2^%d), %d heavy hitters "
         "-> table 2^%d, bloom 2^%d words, list %d" % (card.estimate, card.sampled_kept, card.sampled_distinct,
                                                       card.sample_log2, card.n_heavy, cap.bit_length() - 1,
                                                       bloom_words.bit_length() - 1, list_cap))
     while True:
-        kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=4, min_depth=p.min_depth,
+        kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=args.n_hash, min_depth=p.min_depth,
                               heavy=None if args.no_heavy else card, device=dev)
         out = kmer.Records(int(cap * 0.6), device=dev)
         kc.run([packed], out, fused=True)
@@ -441,13 +447,14 @@ def main():
             "copy_GBps": round(m["copy"]["GBps"], 1)}
         # the same pass priced at the measured rates of its own access kinds, one after another: a hit
         # is a probe + CAS on its line, a Bloom test a probe that misses + an OR with return, every
-        # further probed slot a load, an insertion two atomics (key claim, count)
+        # further table line a probe reaches a load (the first two slots share the home line), an
+        # insertion two atomics (key claim, count)
         rate = {x: m[x]["ops_per_s"] for x in ("load", "atomic_add", "atomic_or_ret", "probe_cas")}
         rates = dict(rate, copy_Bps=m["copy"]["GBps"] * 1e9)
         hits = st["hit_first_lookup"]
         inserts = max(occ - hits - deferred, 0)
         model_s = (hits / rate["probe_cas"] + bloom_tests / rate["load"] + bloom_tests / rate["atomic_or_ret"]
-                   + max(st["probe_slots"] - occ, 0) / rate["load"] + 2 * inserts / rate["atomic_add"])
+                   + max(st["probe_lines"] - occ, 0) / rate["load"] + 2 * inserts / rate["atomic_add"])
         roofline["measured_ceiling_ms"] = round(model_s * 1000, 2)
         roofline["frac_of_measured_ceiling"] = round(model_s * 1000 / stage_ms["pass1"], 4)
         # random memory requests of pass 1 (from the counters): a 16-byte load per probed slot,
@@ -551,7 +558,7 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
                    "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
-                   "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": 4,
+                   "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": args.n_hash,
                    "step": "pack+cardinality+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
                    "cardinality": {"hll_estimate": round(card.estimate, 1), "hll_p": card.hll_p,
                                    "sampled_kept": card.sampled_kept, "sample_log2": card.sample_log2,

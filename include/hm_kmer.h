@@ -124,7 +124,8 @@ typedef struct {
 #define HM_STAT_CAS 7        /* pass 1: compare-and-swap attempts on packed counters */
 #define HM_STAT_WIDE 8       /* pass 1: occurrences counted in the wide counters */
 #define HM_STAT_HEAVY 9      /* pass 1: occurrences of heavy keys counted in workgroup-local memory */
-#define HM_N_STATS 10
+#define HM_STAT_LINES 10     /* pass 1: table lines inspected (128 bytes: the two slots a probe checks first) */
+#define HM_N_STATS 11
 
 #define HM_MAX_HEAVY 256     /* longest heavy-key list of a table */
 

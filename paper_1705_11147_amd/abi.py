@@ -61,7 +61,7 @@ class Table(ctypes.Structure):
 
 
 STAT_NAMES = ["occurrences", "hit_first_lookup", "bloom_tests", "deferred", "probe_slots", "p2_entries",
-              "p2_found", "cas_attempts", "wide_counts", "heavy_local"]
+              "p2_found", "cas_attempts", "wide_counts", "heavy_local", "probe_lines"]
 
 
 class Bloom(ctypes.Structure):

@@ -204,8 +204,18 @@ struct Probe {
     bool inserted;    // this call claimed the slot for the key
 };
 
-// Locate (A, B) by linear probing from `start` (the first `used0` slots of
-// the sequence were already probed by an earlier call).  With `insert`, an
+// Slot of step t of the probe sequence from home slot h: the home slot, the
+// other slot of its 128-byte line (which the first access already brought in),
+// then the following lines' slots in order.  Every slot appears once.
+__device__ __forceinline__ uint64_t probe_slot(uint64_t h, uint32_t t, uint64_t cmask) {
+    if (t == 0) return h;
+    if (t == 1) return (h ^ 1) & cmask;
+    return ((h & ~1ull) + t) & cmask;
+}
+
+// Locate (A, B) along the probe sequence from the home slot `start & cmask`
+// (the first `used0` slots of the sequence were already probed by an earlier
+// call).  With `insert`, an
 // absent key claims the first empty slot: CAS on word a, then store of word b;
 // a reader that sees a matching a and an unwritten b re-reads b with a
 // device-scope atomic load until it is published.  Key words are written once
@@ -224,9 +234,10 @@ struct Probe {
 template <int KW>
 __device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_t start, uint64_t A, uint64_t B,
                                             uint32_t max_probe, bool insert, uint32_t used0 = 0) {
-    uint64_t i = start & cmask;
+    const uint64_t home = start & cmask;
     uint32_t probes = used0, spins = 0;
     while (true) {
+        const uint64_t i = probe_slot(home, probes, cmask);
         Slot *s = slots + i;
         const uint4 v = *reinterpret_cast<const uint4 *>(s);  // a, narrow
         uint64_t a = (uint64_t)v.x | ((uint64_t)v.y << 32);
@@ -249,7 +260,6 @@ __device__ __forceinline__ Probe table_find(Slot *slots, uint64_t cmask, uint64_
             }
             if (b == B) return Probe{(int64_t)i, i, probes, nw, false};
         }
-        i = (i + 1) & cmask;
         if (++probes >= max_probe) return Probe{-2, i, probes, 0, false};
     }
 }
@@ -500,11 +510,12 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
             for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
             uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
             const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
-            if ((old & mask) == mask) pr = table_find<KW>(a.slots, a.cmask, pr.at, A, B, a.max_probe, true, pr.used);
+            if ((old & mask) == mask) pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, true, pr.used);
             else deferred = true;
         }
         st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;
         st.v[HM_STAT_PROBES] += pr.used + 1;
+        st.v[HM_STAT_LINES] += pr.used / 2 + 1;  // steps 0-1 share the home line, then two per line
         if (pr.inserted && a.present) {
             uint64_t pw, pm;
             present_bits(h, a.present_mask, a.present_hash, pw, pm);

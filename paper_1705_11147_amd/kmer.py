@@ -264,7 +264,7 @@ class KmerCounter:
         self.capacity = next_pow2(capacity)
         self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
         self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.stats_buf = torch.zeros(10, dtype=torch.int64, device=self.device)
+        self.stats_buf = torch.zeros(len(abi.STAT_NAMES), dtype=torch.int64, device=self.device)
         if isinstance(heavy, CardResult):  # any subset of the heavy hitters gives the same counts
             n = min(len(heavy.heavy_hi), abi.HM_MAX_HEAVY)
             heavy = np.stack([heavy.heavy_hi[:n], heavy.heavy_lo[:n]], axis=1) if n else None
