@@ -97,7 +97,7 @@ size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // hlen until the chains are chosen.
 Layout layout(uint64_t cap) {
     Layout L;
-    L.slots = 2 * cap < 64 ? 64 : 2 * cap;
+    L.slots = ((2 * cap < 64 ? 64 : 2 * cap) + 3) & ~3ull;  // whole 128-byte lines of four slots
     L.half = 2 * cap;
     size_t o = 0;
     L.ctl = o;     o += up256(kCtlBytes);
@@ -175,6 +175,15 @@ __device__ __forceinline__ bool sampled(uint32_t h) { return ((h >> 1) * 0x9E377
 
 __device__ __forceinline__ uint64_t home_slot(uint64_t h, uint64_t slots) { return __umul64hi(h, slots); }
 
+// Slot of step t of the index's probe sequence from home slot h: the four
+// slots of the home slot's 128-byte line (from h on, wrapping within the
+// line), then the following lines' slots in order (slots is a multiple of 4).
+__device__ __forceinline__ uint64_t index_slot(uint64_t h, uint64_t t, uint64_t slots) {
+    if (t < 4) return (h & ~3ull) | ((h + t) & 3);
+    const uint64_t w = (h & ~3ull) + t;
+    return w >= slots ? w - slots : w;
+}
+
 // wave-wide append for rare events: every lane of the wave calls it; lanes
 // with `take` get consecutive slots (one atomic per wave that has any)
 __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, unsigned int *cnt) {
@@ -191,7 +200,7 @@ __device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *lis
 // A key lookup in the index: the first slot is loaded by the caller (so two
 // lookups can be in flight at once), further slots here.
 struct Lookup {
-    uint64_t khi, klo, s;
+    uint64_t khi, klo, s, home;
     uint32_t tag;
 };
 
@@ -201,7 +210,7 @@ __device__ __forceinline__ Lookup lookup_start(const Graph &g, u128 key) {
     L.klo = (uint64_t)key;
     const uint64_t h = key_hash(L.khi, L.klo, kIndexSeed);
     L.tag = (uint32_t)(h >> 32);
-    L.s = home_slot(h, g.slots);
+    L.s = L.home = home_slot(h, g.slots);
     return L;
 }
 
@@ -229,7 +238,7 @@ __device__ __forceinline__ int slot_match(const Lookup &L, const uint4 &a, const
 // record of a key whose first slot (a, b) did not settle it, or kNone
 __device__ __forceinline__ uint32_t lookup_rest(const Graph &g, Lookup L, int &cl, int &cr) {
     for (uint64_t p = 1; p < g.slots; ++p) {
-        L.s = L.s + 1 == g.slots ? 0 : L.s + 1;
+        L.s = index_slot(L.home, p, g.slots);
         uint4 a, b;
         load_slot(g, L.s, a, b);
         uint32_t j;
@@ -302,9 +311,10 @@ __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
         const uint64_t h = key_hash(khi, klo, kIndexSeed);
         const uint32_t tag = (uint32_t)(h >> 32);
         const unsigned long long mine = ((unsigned long long)tag << 32) | (uint32_t)i;
-        uint64_t s = home_slot(h, g.slots);
+        const uint64_t home = home_slot(h, g.slots);
         bool placed = false;
         for (uint64_t p = 0; p < g.slots; ++p) {
+            const uint64_t s = index_slot(home, p, g.slots);
             unsigned long long e = g.table[s].tagj;  // a load first: a CAS on a taken slot costs more
             if (e == kEmpty) {
                 e = atomicCAS(&g.table[s].tagj, kEmpty, mine);
@@ -324,7 +334,6 @@ __global__ __launch_bounds__(kBlock) void k_ctg_index(Graph g) {
                     break;
                 }
             }
-            s = s + 1 == g.slots ? 0 : s + 1;
         }
         if (!placed) atomicOr(g.status, HM_ST_TABLE_FULL);
     }
