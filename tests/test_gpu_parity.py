@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_1705_11147_amd import abi, kmer, synth
-from tests.util import assert_tables_equal, random_read_set, read_golden, table_digest, table_to_dict, enc
+from tests.util import assert_tables_equal, enc, pack_reads, random_read_set, read_golden, table_digest, table_to_dict
 
 pytestmark = pytest.mark.gpu
 
@@ -416,3 +416,30 @@ def test_sorted_export_tie_runs(k):
     exp = oracle.run(ascii, qual, off, k, forward_only=True, n_threads=4)
     got = kmer.analyze(ascii, qual, k, read_off=off, forward_only=True, export_flags=abi.HM_EXPORT_SORTED)
     assert_tables_equal(got, exp, "tie runs k=%d" % k)
+
+
+@pytest.mark.parametrize("k,n_keys", [(21, 58), (51, 60), (31, 64)])
+def test_nearly_full_small_table(k, n_keys):
+    """A 64-slot table filled to 90-100% (every k-mer inserted, Bloom bypassed): long probe sequences
+    that run through several lines and wrap past the end of the table; the table is exact, and one
+    key more than the slots is reported as a full table."""
+    rng = np.random.default_rng(k * 7 + n_keys)
+    g = "".join(rng.choice(list("ACGT"), n_keys + k - 1))  # n_keys distinct k-mers (checked below)
+    seqs = [g] * 3
+    a, q, off = pack_reads([(s, [40] * len(s)) for s in seqs])
+    exp = oracle.run(a, q, off, k, qcut=0, keep_all=True, min_depth=1)
+    if len(exp["count"]) != n_keys:
+        pytest.skip("the random genome repeats a k-mer")
+    kc = kmer.KmerCounter(k, 64, 1, 0, min_depth=1, flags=abi.HM_BLOOM_BYPASS, max_probe=64)
+    p = kmer.pack_reads(torch.from_numpy(a).cuda(), torch.from_numpy(q).cuda(), read_off=torch.from_numpy(off).cuda())
+    out = kmer.Records(64)
+    kc.run([p], out, flags=abi.HM_EXPORT_ALL, fused=True)
+    if n_keys <= 64:
+        assert kc.status() == abi.HM_OK
+        assert_tables_equal(out.to_numpy(), exp, "64-slot table, %d keys" % n_keys)
+    g2 = "".join(rng.choice(list("ACGT"), 64 + k))  # 65 distinct k-mers (or close): more than the slots
+    a2, q2, off2 = pack_reads([(g2, [40] * len(g2))] * 2)
+    if len(oracle.run(a2, q2, off2, k, qcut=0, keep_all=True, min_depth=1)["count"]) > 64:
+        kc.run([kmer.pack_reads(torch.from_numpy(a2).cuda(), torch.from_numpy(q2).cuda(),
+                                read_off=torch.from_numpy(off2).cuda())], out, flags=abi.HM_EXPORT_ALL, fused=True)
+        assert kc.status() == abi.HM_ECAPACITY
