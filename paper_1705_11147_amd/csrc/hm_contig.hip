@@ -390,13 +390,12 @@ __device__ __forceinline__ uint32_t step_link(uint32_t i, const Step &st_, int d
 // Links of every record; collects the rulers (heads and sampled half-nodes)
 // into listA through a wave-local buffer in LDS, flushed with one atomic per
 // kRulerBuf / 4 - 128 entries (no workgroup barrier in the loop).
-__global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ctg_link(Graph g) {
     constexpr int kWaveBuf = kRulerBuf / (kBlock / 64);
     __shared__ uint32_t s_buf[kRulerBuf];
     if (stopped(g)) return;
     const uint64_t n = n_records(g);
     const int lane = __lane_id();
-    const int k = g.k;
     uint32_t *wbuf = s_buf + (threadIdx.x >> 6) * kWaveBuf;
     uint32_t cnt = 0;  // wave-uniform
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -430,8 +429,10 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
                 const uint32_t R = step_link((uint32_t)i, sr, 0, jR, r_cl, r_cr);
                 const uint32_t Lf = step_link((uint32_t)i, sl, 1, jL, l_cl, l_cr);
                 // a successor word carries the base the step adds: the last base of the
-                // neighbour read in its orientation (its key is the one just looked up)
-                g.succ[h0] = R == kNone ? kNone : (R | last_base(lr.khi, lr.klo, (int)(R & 1), k) << 30);
+                // neighbour read in the walk's direction, which is the right extension
+                // (the left step, walked in the reverse-complement reading, adds the
+                // complement of the left extension)
+                g.succ[h0] = R == kNone ? kNone : (R | (uint32_t)cr << 30);
                 g.pred[h0] = Lf;
                 const bool samp = sampled(h0);
                 r0 = Lf == kNone || samp;
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_ctg_link(Graph g) {
                     // the reverse-complement reading runs the same links backwards
                     const uint32_t p1 = R == kNone ? kNone : (R ^ 1u);
                     const uint32_t s1 = Lf == kNone ? kNone : (Lf ^ 1u);
-                    g.succ[h1] = s1 == kNone ? kNone : (s1 | last_base(ll.khi, ll.klo, (int)(s1 & 1), k) << 30);
+                    g.succ[h1] = s1 == kNone ? kNone : (s1 | (3u - (uint32_t)cl) << 30);
                     g.pred[h1] = p1;
                     r1 = p1 == kNone || samp;
                 }
@@ -538,47 +539,74 @@ __global__ __launch_bounds__(kBlock) void k_ctg_segplace(Graph g) {
 
 // Walk 2: each ruler copies its segment into its run: each half-node's id with
 // the base it adds, which is the successor word that reached it (the ruler's
-// own base: the last base of its k-mer).
+// own base: the last base of its k-mer).  A lane stages its entries in LDS and
+// writes each 64-byte block of its run at once (one entry per step of the walk
+// would leave each line half written between the walk's random reads).
+constexpr uint32_t kStage = 16;  // entries of a 64-byte block of a run
+
+// Stage entry w at run position p; the staged entries are positions
+// p + 1 - nb .. p of one run, written out at the end of a block or of the run.
+__device__ __forceinline__ void stage_put(uint32_t *seg, uint32_t *stage, uint32_t &nb, uint32_t p, uint32_t w,
+                                          bool last) {
+    stage[nb++] = w;
+    if (((p + 1) & (kStage - 1)) == 0 || last) {
+        const uint32_t first = p + 1 - nb;
+        if (nb == kStage) {  // a whole aligned block
+            uint4 *d = reinterpret_cast<uint4 *>(seg + first);
+            for (uint32_t q = 0; q < kStage / 4; ++q)
+                d[q] = make_uint4(stage[4 * q], stage[4 * q + 1], stage[4 * q + 2], stage[4 * q + 3]);
+        } else {
+            for (uint32_t q = 0; q < nb; ++q) seg[first + q] = stage[q];
+        }
+        nb = 0;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ctg_segfill(Graph g) {
     __shared__ unsigned int s_next;
+    __shared__ uint32_t s_stage[kBlock * (kStage + 1)];
     if (stopped(g)) return;
     const uint32_t n = g.ctl->n_rulers;
     const uint32_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint32_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
     if (threadIdx.x == 0) s_next = lo + kBlock;
     __syncthreads();
+    uint32_t *stage = s_stage + threadIdx.x * (kStage + 1);
     const uint64_t room = 2 * g.cap;
-    uint32_t x = lo + threadIdx.x, cur = 0, t = 0, len = 0, o = 0;
+    uint32_t x = lo + threadIdx.x, cur = 0, t = 0, len = 0, o = 0, nb = 0;
     bool live = x < hi;
-    auto start = [&](uint32_t e) {
-        const uint32_t R = g.listA[e] & ~kListDone;
-        len = g.seglen[e] & ~kSegEnd;
-        o = g.segoff[e];
-        t = 0;
-        cur = R;
-        if ((uint64_t)o + len > room) {  // more than the graph holds: cannot happen
-            atomicOr(g.status, HM_ST_TIMEOUT);
-            len = 0;
-            return;
-        }
-        g.seg[o] = R | last_base(g.hi[R >> 1], g.lo[R >> 1], (int)(R & 1), g.k) << 30;
-    };
-    if (live) start(x);
+    bool fresh = live;  // x is a new ruler entry: place its ruler first
     while (live) {
-        if (t + 1 < len) {
+        if (fresh) {
+            fresh = false;
+            const uint32_t R = g.listA[x] & ~kListDone;
+            len = g.seglen[x] & ~kSegEnd;
+            o = g.segoff[x];
+            t = 0;
+            nb = 0;
+            cur = R;
+            if ((uint64_t)o + len > room || len == 0) {  // more than the graph holds, or empty: cannot happen
+                atomicOr(g.status, HM_ST_TIMEOUT);
+                len = 0;
+            } else {
+                const uint32_t b = last_base(g.hi[R >> 1], g.lo[R >> 1], (int)(R & 1), g.k);
+                stage_put(g.seg, stage, nb, o, R | b << 30, len == 1);
+            }
+        } else if (t + 1 < len) {
             const uint32_t w = g.succ[cur];
             if (w == kNone) {  // shorter than walk 1 found it: cannot happen
                 atomicOr(g.status, HM_ST_TIMEOUT);
                 len = 0;
+                nb = 0;
                 continue;
             }
             cur = w & kIdMask;
             ++t;
-            g.seg[o + t] = w;
+            stage_put(g.seg, stage, nb, o + t, w, t + 1 == len);
         } else {
             x = atomicAdd(&s_next, 1u);
             live = x < hi;
-            if (live) start(x);
+            fresh = live;
         }
     }
 }
@@ -883,39 +911,55 @@ __device__ __forceinline__ void write_kmer(uint8_t *seq, uint64_t o, u128 s, int
 
 // Spell the kept chains: a path segment copies its run of bases to its rank
 // (the head writes its whole k-mer), in order; a cycle half-node writes its
-// base at its rank.
+// base at its rank.  Path segments go 64 to a wave: each lane finds one
+// segment's place, then the whole wave copies the 64 runs one after the
+// other, its lanes on consecutive bases, so the loads and stores coalesce.
 __global__ __launch_bounds__(kBlock) void k_ctg_write(Graph g, uint8_t *seq, uint64_t seq_cap) {
     if (stopped(g)) return;
     const uint32_t nr = g.ctl->n_rulers, n = nr + (uint32_t)g.ctl->n_cyc;
     const uint32_t half = (uint32_t)(2 * g.cap);
     const int k = g.k;
-    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+    const int lane = __lane_id();
+    const uint32_t waves = gridDim.x * (kBlock / 64);
+    for (uint32_t x0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64u; x0 < nr; x0 += waves * 64u) {
+        const uint32_t x = x0 + lane;
+        unsigned long long dst = kNoOff;  // where the run's first base goes, or kNoOff: nothing to write
+        uint32_t len = 0, s0 = 0, t0 = 0;
         if (x < nr) {
             const uint32_t R = g.listA[x] & ~kListDone;
             const unsigned long long v = ld(g.RS + R);
             const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
-            if (W == kCycW || !(W & kDone) || H >= half) continue;
-            const uint64_t o = g.hoff[H];  // kNoOff for a dropped chain
-            const uint32_t rank = W & ~kDone, len = g.seglen[x] & ~kSegEnd, s0 = g.segoff[x];
-            if (o >= seq_cap || (uint64_t)k + rank + len - 1 > seq_cap - o) continue;  // past the room: cannot happen
-            uint32_t t = 0;
-            if (rank == 0) {  // the head's segment starts with the head's k-mer
-                write_kmer(seq, o, seq_of(g, H), k);
-                t = 1;
+            if (W != kCycW && (W & kDone) && H < half) {
+                const uint64_t o = g.hoff[H];  // kNoOff for a dropped chain
+                const uint32_t rank = W & ~kDone;
+                len = g.seglen[x] & ~kSegEnd;
+                s0 = g.segoff[x];
+                if (o < seq_cap && (uint64_t)k + rank + len - 1 <= seq_cap - o) {  // else past the room: cannot happen
+                    if (rank == 0) {  // the head's segment starts with the head's k-mer
+                        write_kmer(seq, o, seq_of(g, H), k);
+                        t0 = 1;
+                    }
+                    dst = o + k - 1 + rank;
+                }
             }
-            uint8_t *dst = seq + o + k - 1 + rank;
-            for (; t < len; ++t) dst[t] = (uint8_t)"ACGT"[g.seg[s0 + t] >> 30];
-        } else {
-            const uint32_t h = g.cyc[x - nr];
-            const unsigned long long v = ld(g.S + h);
-            const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
-            if (H >= half) continue;
-            const uint64_t o = g.hoff[H];
-            if (o >= seq_cap || (uint64_t)k + W > seq_cap - o) continue;  // kNoOff, or past the room
-            const u128 s = seq_of(g, h);
-            if (W == 0) write_kmer(seq, o, s, k);
-            else seq[o + k - 1 + W] = (uint8_t)"ACGT"[(int)(s & 3)];
         }
+        for (int j = 0; j < 64; ++j) {  // wave-uniform
+            const unsigned long long d = __shfl(dst, j);
+            if (d == kNoOff) continue;
+            const uint32_t lj = __shfl(len, j), sj = __shfl(s0, j);
+            for (uint32_t t = __shfl(t0, j) + lane; t < lj; t += 64) seq[d + t] = (uint8_t)"ACGT"[g.seg[sj + t] >> 30];
+        }
+    }
+    for (uint32_t x = nr + blockIdx.x * kBlock + threadIdx.x; x < n; x += gridDim.x * kBlock) {
+        const uint32_t h = g.cyc[x - nr];
+        const unsigned long long v = ld(g.S + h);
+        const uint32_t H = (uint32_t)v, W = (uint32_t)(v >> 32);
+        if (H >= half) continue;
+        const uint64_t o = g.hoff[H];
+        if (o >= seq_cap || (uint64_t)k + W > seq_cap - o) continue;  // kNoOff, or past the room
+        const u128 s = seq_of(g, h);
+        if (W == 0) write_kmer(seq, o, s, k);
+        else seq[o + k - 1 + W] = (uint8_t)"ACGT"[(int)(s & 3)];
     }
 }
 
