@@ -274,9 +274,11 @@ def main():
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
     ap.add_argument("--bloom-bits", type=float, default=12.0,
                     help="Bloom filter bits per distinct k-mer before rounding the filter to a power of two")
-    ap.add_argument("--n-hash", type=int, default=4, help="Bloom filter bits set per k-mer (in one 64-bit word)")
+    ap.add_argument("--n-hash", type=int, default=4, help="Bloom filter bits set per k-mer (in one filter word)")
     ap.add_argument("--table-load", type=float, default=0.5,
                     help="design load of the count table (the planned capacity is rounded up to a power of two)")
+    ap.add_argument("--separate-bloom", action="store_true",
+                    help="a separate Bloom filter instead of the one in the table slots' classification words")
     ap.add_argument("--no-contigs", action="store_true", help="skip the contig generation measurement")
     ap.add_argument("--no-h2d", action="store_true", help="skip the host-to-device copy measurement")
     ap.add_argument("--bypass-diag", action="store_true",
@@ -329,14 +331,16 @@ def main():
     sketch = kmer.CardSketch(k, positions, device=dev)
     card = sketch.run([packed], min_depth=p.min_depth)
     abi.check(card.status, "cardinality pass")
+    in_table = not args.separate_bloom
     cap, bloom_words, list_cap = kmer.plan_sizes(card, n_hash=args.n_hash, bloom_bits=args.bloom_bits,
-                                                 table_load=args.table_load, device=dev)
+                                                 table_load=args.table_load, device=dev, bloom_in_table=in_table)
     log("cardinality pass: %.4g distinct (HLL), %d of %d sampled keys kept (1/2^%d), %d heavy hitters "
         "-> table 2^%d, bloom 2^%d words, list %d" % (card.estimate, card.sampled_kept, card.sampled_distinct,
                                                       card.sample_log2, card.n_heavy, cap.bit_length() - 1,
                                                       bloom_words.bit_length() - 1, list_cap))
     while True:
         kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_hash=args.n_hash, min_depth=p.min_depth,
+                              bloom_in_table=in_table,
                               heavy=None if args.no_heavy else card, device=dev)
         out = kmer.Records(int(cap * 0.6), device=dev)
         kc.run([packed], out, fused=True)
@@ -362,8 +366,9 @@ def main():
     n_records = int(out.n_out.item())
     n_first = int(kc.list_count.item())
     ref_digest = out.digest_words()
-    log("sizes: table 2^%d slots (%.1f GB), bloom %.2f GB, list %.2f GB; kept %d, first-occurrence %d" % (
-        kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, kc.bloom_words * 8 / 1e9, list_cap * 17 / 1e9,
+    log("sizes: table 2^%d slots (%.1f GB), bloom %s, list %.2f GB; kept %d, first-occurrence %d" % (
+        kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9,
+        "in the table" if kc.bloom_in_table else "%.2f GB" % (kc.bloom_words * 8 / 1e9), list_cap * 17 / 1e9,
         n_records, n_first))
 
     stages = ["pack", "card", "init", "pass1", "pass2", "classify_export"]
@@ -418,13 +423,15 @@ def main():
     #   every occurrence counted through the table reads its home slot line (64 B) (heavy
     #   hitters counted in workgroup-local memory touch no table line);
     #   an occurrence counted in pass 1 (hit or insert) writes that line back (64 B);
-    #   a Bloom test-and-set reads and writes one line (128 B);
+    #   a Bloom test-and-set with the filter in the table writes back the home line the probe
+    #   read (64 B; an inserted k-mer's count lands on that line too: counted once); a separate
+    #   filter's word is one more line, read and written (128 B);
     #   a deferred occurrence appends a 17-byte list entry;
     #   the packed reads stream in once (0.5 B per base).
     st = kc.stats()  # cleared by every step's table init: the last step's counts
     occ, bloom_tests, deferred = st["occurrences"] - st["heavy_local"], st["bloom_tests"], st["deferred"]
-    pass1_bytes = (occ * LINE + (occ - deferred) * LINE + bloom_tests * 2 * LINE + deferred * 17
-                   + 0.5 * r.n_bases)
+    bloom_bytes = deferred * LINE if kc.bloom_in_table else bloom_tests * 2 * LINE
+    pass1_bytes = occ * LINE + (occ - deferred) * LINE + bloom_bytes + deferred * 17 + 0.5 * r.n_bases
     achieved = pass1_bytes / (stage_ms["pass1"] / 1000) / 1e9
     roofline = {"kernel": "k_pass1_fixed (table probe, Bloom test-and-set, insert/count)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -446,15 +453,18 @@ def main():
             "probe_cas_Gops": round(m["probe_cas"]["ops_per_s"] / 1e9, 2),
             "copy_GBps": round(m["copy"]["GBps"], 1)}
         # the same pass priced at the measured rates of its own access kinds, one after another: a hit
-        # is a probe + CAS on its line, a Bloom test a probe that misses + an OR with return, every
-        # further table line a probe reaches a load (the first two slots share the home line), an
-        # insertion two atomics (key claim, count)
+        # is a probe + CAS on its line; a Bloom test with the filter in the table a probe + an OR on
+        # the probed line (priced as a probe + CAS), with a separate filter a probe that misses + an
+        # OR with return on another line; every further table line a probe reaches a load (the first
+        # two slots share the home line); an insertion two atomics (key claim, count)
         rate = {x: m[x]["ops_per_s"] for x in ("load", "atomic_add", "atomic_or_ret", "probe_cas")}
         rates = dict(rate, copy_Bps=m["copy"]["GBps"] * 1e9)
         hits = st["hit_first_lookup"]
         inserts = max(occ - hits - deferred, 0)
-        model_s = (hits / rate["probe_cas"] + bloom_tests / rate["load"] + bloom_tests / rate["atomic_or_ret"]
-                   + max(st["probe_lines"] - occ, 0) / rate["load"] + 2 * inserts / rate["atomic_add"])
+        bloom_s = (bloom_tests / rate["probe_cas"] if kc.bloom_in_table
+                   else bloom_tests / rate["load"] + bloom_tests / rate["atomic_or_ret"])
+        model_s = (hits / rate["probe_cas"] + bloom_s + max(st["probe_lines"] - occ, 0) / rate["load"]
+                   + 2 * inserts / rate["atomic_add"])
         roofline["measured_ceiling_ms"] = round(model_s * 1000, 2)
         roofline["frac_of_measured_ceiling"] = round(model_s * 1000 / stage_ms["pass1"], 4)
         # random memory requests of pass 1 (from the counters): a 16-byte load per probed slot,
@@ -540,6 +550,9 @@ def main():
                    n_cpu, n_cpu * W, threads, res["seconds"], platform.processor() or platform.machine())}
 
     table_slots, bloom_words = kc.capacity, kc.bloom_words
+    bloom = ({"layout": "in table: the home slot's 32-bit classification word", "bits": kc.capacity * 32}
+             if kc.bloom_in_table else {"layout": "separate: 64-bit words", "bits": kc.bloom_words * 64})
+    bloom.update(n_hash=args.n_hash, bits_per_distinct_kmer=round(bloom["bits"] / card.estimate, 2))
     del kc, out, packed, ascii, qual
     torch.cuda.empty_cache()
     batched = None
@@ -558,7 +571,7 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
                    "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
-                   "table_slots": table_slots, "bloom_words": bloom_words, "n_hash": args.n_hash,
+                   "table_slots": table_slots, "bloom": bloom,
                    "step": "pack+cardinality+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
                    "cardinality": {"hll_estimate": round(card.estimate, 1), "hll_p": card.hll_p,
                                    "sampled_kept": card.sampled_kept, "sample_log2": card.sample_log2,

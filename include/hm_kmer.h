@@ -65,11 +65,13 @@ extern "C" {
 #define HM_ST_OUTPUT_FULL 8u
 #define HM_ST_TIMEOUT 16u
 #define HM_ST_DUPLICATE 32u /* hm_contigs: a key appears twice in the input */
+#define HM_ST_CLASSIFIED 64u /* not an error: hm_classify_ext has written the table's classification words */
 
 /* hm_params_t.flags */
 #define HM_FORWARD_ONLY 1u /* key = forward encoding (no canonical form); allows even k */
 #define HM_BLOOM_BYPASS 2u /* count every occurrence directly, no Bloom test */
 #define HM_CHECKED 4u      /* detect counter overflow (needed only past 2^32 positions per table) */
+#define HM_BLOOM_IN_TABLE 8u /* the Bloom filter lives in the table (see hm_bloom_t) */
 
 /* hm_export_table flags */
 #define HM_EXPORT_UU_ONLY 1u  /* only kept k-mers unique on both sides */
@@ -150,7 +152,19 @@ typedef struct {
 } hm_table_t;
 
 /* Single-word blocked Bloom filter: n_words 64-bit words (power of two),
- * n_hash bits per key set in one word (1..8). */
+ * n_hash bits per key set in one word (1..8).
+ * With HM_BLOOM_IN_TABLE there is no separate filter (`words` and `n_words`
+ * are ignored): the filter word of a key is the 32-bit classification word of
+ * its home slot (the slot its probe sequence starts from), which pass 1 tests
+ * and sets with one atomic OR on the table line the probe has just read, so a
+ * Bloom test costs no random access of its own.  The filter then has 32 bits
+ * per table slot; hm_table_init clears it with the table.  The word is free
+ * while counting: hm_classify_ext overwrites it with the slot's classes (only
+ * hm_export_table without HM_EXPORT_CLASSIFY reads them) and sets
+ * HM_ST_CLASSIFIED; a later pass 1 into the same table, whose filter bits are
+ * then gone, inserts every absent k-mer instead of testing the filter (the
+ * counts stay exact, the table takes the singletons too).  Counts never
+ * depend on the filter. */
 typedef struct {
     uint64_t *words;
     uint64_t n_words;
@@ -236,6 +250,8 @@ int hm_pack_reads(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases, ui
  * on one word: if the filter had already seen it, the k-mer is inserted and
  * this occurrence counted; otherwise the occurrence is appended to the
  * first-occurrence list `l`.
+ * With HM_BLOOM_IN_TABLE the word is the home slot's (see hm_bloom_t) and
+ * `b` only supplies n_hash.
  * With HM_BLOOM_BYPASS (or min_depth == 1) every occurrence is counted and
  * `b`/`l` may be NULL.  `t` must be initialized; `l` must be initialized
  * before the first pass-1 call of a table (several read batches may be

@@ -25,10 +25,12 @@ HM_ST_OVERFLOW = 4
 HM_ST_OUTPUT_FULL = 8
 HM_ST_TIMEOUT = 16
 HM_ST_DUPLICATE = 32
+HM_ST_CLASSIFIED = 64
 
 HM_FORWARD_ONLY = 1
 HM_BLOOM_BYPASS = 2
 HM_CHECKED = 4
+HM_BLOOM_IN_TABLE = 8
 
 HM_EXPORT_UU_ONLY = 1
 HM_EXPORT_ALL = 2

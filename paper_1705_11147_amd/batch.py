@@ -72,7 +72,7 @@ class _SetBuffers:
             card = sk.run([self.packed()], min_depth=params.get("min_depth", 2))
             del sk
             distinct, kept = card.distinct_hi(), card.kept_hi()
-            fp = kmer.bloom_fp_rate(tuning.bloom_bits, tuning.n_hash)
+            fp = kmer.bloom_fp_rate(tuning.bloom_bits, tuning.n_hash, word_bits=32)  # the filter in the table
             kept = kept + fp * max(distinct - kept, 0.0)
         else:  # the caller's size hints
             distinct, kept = spec.distinct_est, spec.kept_est

@@ -389,6 +389,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     if (export_flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL)) return fail(HM_EINVAL, "batch: unknown export flags");
     if (tu.set_major < 0 || tu.set_major > 64) return fail(HM_EINVAL, "batch: set_major must be 0..64");
     const bool bypass = (p->flags & HM_BLOOM_BYPASS) || p->min_depth == 1;
+    const bool in_table = (p->flags & HM_BLOOM_IN_TABLE) != 0;
 
     std::vector<BatchDesc> descs(n_sets);
     std::vector<int32_t> order(n_sets);
@@ -407,8 +408,8 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
             return fail(HM_EINVAL, "batch set %d: bad table", i);
         if (t.k != p->k) return fail(HM_EINVAL, "batch set %d: table k %d != %d", i, t.k, p->k);
         if (!bypass) {
-            if (!x.bloom.words || !pow2(x.bloom.n_words) || x.bloom.n_hash < 1 || x.bloom.n_hash > 8 ||
-                x.bloom.n_words > (1ull << 40))
+            if (x.bloom.n_hash < 1 || x.bloom.n_hash > 8 ||
+                (!in_table && (!x.bloom.words || !pow2(x.bloom.n_words) || x.bloom.n_words > (1ull << 40))))
                 return fail(HM_EINVAL, "batch set %d: bad Bloom filter", i);
             if (!x.list.keys || !x.list.ext || !x.list.count) return fail(HM_EINVAL, "batch set %d: bad list", i);
         }
@@ -436,8 +437,8 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
         d.status = t.status;
         d.stats = reinterpret_cast<unsigned long long *>(t.stats);
         if (!bypass) {
-            d.bloom = x.bloom.words;
-            d.bloom_mask = x.bloom.n_words - 1;
+            d.bloom = in_table ? nullptr : x.bloom.words;  // no pointer: the bits live in the table
+            d.bloom_mask = in_table ? 0 : x.bloom.n_words - 1;
             d.n_hash = x.bloom.n_hash;
             d.lkeys = x.list.keys;
             d.lext = x.list.ext;
@@ -524,7 +525,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     for (int32_t i = 0; i < n_sets; ++i) {
         const BatchDesc &d = sorted[i];
         reg[nr++] = Region{d.slots, d.capacity * HM_SLOT_BYTES, 0u, 0u};
-        reg[nr++] = Region{d.bloom, bypass ? 0ull : (d.bloom_mask + 1) * 8, 0u, 0u};
+        reg[nr++] = Region{d.bloom, (bypass || !d.bloom) ? 0ull : (d.bloom_mask + 1) * 8, 0u, 0u};
         reg[nr++] = Region{d.lcount, bypass ? 0ull : 8ull, 0u, 0u};
         reg[nr++] = Region{d.lext, bypass ? 0ull : (d.lcap + 3) / 4 * 4, 0xFFFFFFFFu, 0u};  // all holes
         reg[nr++] = Region{d.present, (bypass || !d.present) ? 0ull : d.present_words * 8, 0u, 0u};

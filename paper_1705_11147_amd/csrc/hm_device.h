@@ -50,7 +50,8 @@ struct Slot {
     uint32_t nl;      // wide: occurrences with no left extension
     uint32_t tl[4];   // wide: left tallies
     uint32_t tr[4];   // wide: right tallies
-    uint32_t cls;     // classify: cls_l | cls_r << 8 | kept << 16 | count >= 2^32 << 17
+    uint32_t cls;     // classify: cls_l | cls_r << 8 | kept << 16 | count >= 2^32 << 17; while
+                      // counting with the filter in the table: Bloom bits of the keys homed here
 };
 static_assert(sizeof(Slot) == HM_SLOT_BYTES, "slot is one 64-byte line");
 
@@ -320,7 +321,7 @@ struct PassArgs {
     uint32_t forward_only;
     uint32_t n_owners, owner;
     uint64_t seed;
-    // bloom
+    // bloom (nullptr: the filter is in the table's classification words)
     uint64_t *bloom;
     uint64_t bloom_mask;  // n_words - 1
     uint32_t n_hash;
@@ -483,13 +484,23 @@ __device__ __forceinline__ void heavy_flush(const PassArgs &a, const HeavyLds &h
 // Per-occurrence body of pass 1.  `act` lanes carry an occurrence; every lane
 // of the wave must call it (list appends are aggregated per wave).  With
 // HEAVY, occurrences of the table's heavy keys are counted in `hv` instead.
+// True when the filter lives in the table and a classification has since
+// overwritten its words: pass 1 must then take every absent k-mer as seen (its
+// earlier occurrences may have set bits that are gone).  Read once per launch.
+__device__ __forceinline__ bool classified_in_table(const PassArgs &a) {
+    if (a.bloom || a.bypass) return false;
+    return (__builtin_amdgcn_readfirstlane(__hip_atomic_load(a.status, RLX, AGT)) & HM_ST_CLASSIFIED) != 0;
+}
+
 template <int KW, bool CHECKED, uint32_t CHUNK = kListChunk, bool HEAVY = false>
 __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ &o, ListCursor &cur, Stats &st,
-                                          const HeavyLds *hv = nullptr) {
+                                          const HeavyLds *hv = nullptr, bool seen_all = false) {
     // The table is probed first: an occurrence whose k-mer is already there is
     // counted without touching the Bloom filter.  Only absent k-mers test and
     // set their Bloom bits; a k-mer the filter has seen is inserted and this
     // occurrence counted, an unseen one goes to the first-occurrence list.
+    // The filter word is a word of the separate filter, or the home slot's
+    // classification word, on the line the probe has just read.
     bool deferred = false;
     const uint64_t h = act ? key_hash(o.hi, o.lo, a.seed) : 0;
     if (HEAVY && act && heavy_count(*hv, h, o)) {
@@ -506,11 +517,23 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
         if (pr.slot == -1) {
             st.v[HM_STAT_BLOOM] += 1;
             const uint64_t g = fmix64(h + 0x9E3779B97F4A7C15ull);
-            uint64_t mask = 0;
-            for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
-            uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
-            const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
-            if ((old & mask) == mask) pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, true, pr.used);
+            bool seen;
+            if (a.bloom) {
+                uint64_t mask = 0;
+                for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1ull << ((g >> (6 * j)) & 63);
+                uint64_t *w = a.bloom + ((h >> 24) & a.bloom_mask);
+                const uint64_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
+                seen = (old & mask) == mask;
+            } else if (seen_all) {
+                seen = true;
+            } else {  // the home slot's classification word, on the line the probe just read
+                uint32_t mask = 0;
+                for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1u << ((g >> (5 * j)) & 31);
+                uint32_t *w = &a.slots[h & a.cmask].cls;
+                const uint32_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
+                seen = (old & mask) == mask;
+            }
+            if (seen) pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, true, pr.used);
             else deferred = true;
         }
         st.v[HM_STAT_DEFER] += deferred ? 1u : 0u;

@@ -80,8 +80,9 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
     if (HEAVY) hv = heavy_setup(a, s_heavy);
     ListCursor cur{0, kListChunk};
     Stats st = {};
+    const bool seen_all = classified_in_table(a);
     fixed_windows<true>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
-        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv);
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv, seen_all);
     });
     list_close(a, cur);
     if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
@@ -98,8 +99,9 @@ __global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tile
     if (HEAVY) hv = heavy_setup(a, s_heavy);
     ListCursor cur{0, kListChunk};
     Stats st = {};
+    const bool seen_all = classified_in_table(a);
     var_windows<true>(a, n_tiles, s_off, s_pre, [&](bool act, const Occ &o, int64_t) {
-        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv);
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv, seen_all);
     });
     list_close(a, cur);
     if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
@@ -124,7 +126,9 @@ __global__ __launch_bounds__(kBlock) void k_pass2(PassArgs a) {
     stats_flush(a.stats, st);
 }
 
-__global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, uint32_t min_depth, uint32_t ext_min) {
+__global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, uint32_t min_depth, uint32_t ext_min,
+                                                     uint32_t *status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, HM_ST_CLASSIFIED);  // the filter words are gone
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < cap; i += (uint64_t)gridDim.x * kBlock) {
         Slot *s = slots + i;
         if (s->a == 0) continue;
@@ -243,7 +247,8 @@ int hm_check_params(const hm_params_t *p) {
     if (p->min_depth < 1) return fail(HM_EINVAL, "min_depth must be >= 1");
     if (p->ext_min < 1) return fail(HM_EINVAL, "ext_min must be >= 1");
     if (p->n_owners < 1 || p->owner >= p->n_owners) return fail(HM_EINVAL, "owner must be < n_owners");
-    if (p->flags & ~(HM_FORWARD_ONLY | HM_BLOOM_BYPASS | HM_CHECKED)) return fail(HM_EINVAL, "unknown flags");
+    if (p->flags & ~(HM_FORWARD_ONLY | HM_BLOOM_BYPASS | HM_CHECKED | HM_BLOOM_IN_TABLE))
+        return fail(HM_EINVAL, "unknown flags");
     return HM_OK;
 }
 
@@ -332,11 +337,18 @@ static int make_args(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, h
     a.seed = p->seed;
     a.bypass = bypass ? 1 : 0;
     if (!bypass && need_reads) {
-        if (!b || !b->words || !pow2(b->n_words) || b->n_hash < 1 || b->n_hash > 8)
-            return fail(HM_EINVAL, "a Bloom filter (power-of-two words, 1..8 hashes) is needed unless bypassed");
-        if (b->n_words > (1ull << 40)) return fail(HM_EINVAL, "bloom too large");
-        a.bloom = b->words;
-        a.bloom_mask = b->n_words - 1;
+        if (p->flags & HM_BLOOM_IN_TABLE) {
+            if (!b || b->n_hash < 1 || b->n_hash > 8)
+                return fail(HM_EINVAL, "a Bloom filter in the table needs 1..8 hashes (hm_bloom_t.n_hash)");
+            a.bloom = nullptr;
+            a.bloom_mask = 0;
+        } else {
+            if (!b || !b->words || !pow2(b->n_words) || b->n_hash < 1 || b->n_hash > 8)
+                return fail(HM_EINVAL, "a Bloom filter (power-of-two words, 1..8 hashes) is needed unless bypassed");
+            if (b->n_words > (1ull << 40)) return fail(HM_EINVAL, "bloom too large");
+            a.bloom = b->words;
+            a.bloom_mask = b->n_words - 1;
+        }
         a.n_hash = b->n_hash;
     }
     if (!bypass || !need_reads) {
@@ -430,7 +442,7 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t s) {
     rc = check_table(t);
     if (rc) return rc;
     hipLaunchKernelGGL(k_classify, dim3((unsigned)grid_for(t->capacity, 16)), dim3(kBlock), 0, s,
-                       reinterpret_cast<Slot *>(t->slots), t->capacity, p->min_depth, p->ext_min);
+                       reinterpret_cast<Slot *>(t->slots), t->capacity, p->min_depth, p->ext_min, t->status);
     HM_LAUNCH_CHECK("hm_classify_ext");
     return HM_OK;
 }

@@ -244,23 +244,31 @@ def contigs(records: Records, k: int, forward_only: bool = False, device=None) -
 class KmerCounter:
     """One count table with its Bloom filter and first-occurrence list.
 
-    capacity:      table slots (power of two, 64 bytes each)
-    bloom_words:   Bloom filter words (power of two, 8 bytes each); n_hash bits per key
-    list_capacity: first-occurrence list entries (17 bytes each): at most one per
-                   distinct k-mer, plus list_slack() per pass-1 launch
+    capacity:       table slots (power of two, 64 bytes each)
+    bloom_words:    Bloom filter size in 64-bit words (power of two); n_hash bits per key
+    list_capacity:  first-occurrence list entries (17 bytes each): at most one per
+                    distinct k-mer, plus list_slack() per pass-1 launch
+    bloom_in_table: keep the filter in the table (abi.HM_BLOOM_IN_TABLE: one 32-bit word per
+                    slot, tested on the line the probe has read); the table then gets at least
+                    2 * bloom_words slots, so the filter has the bits asked for.  Otherwise a
+                    separate filter of bloom_words words.
     """
 
     def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,
                  min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
                  seed: int = DEFAULT_SEED, max_probe: int = 0, present_filter: bool = True, heavy=None,
-                 device="cuda"):
+                 bloom_in_table: bool = True, device="cuda"):
         """heavy: optional heavy-hitter keys, an (n, 2) array of (key_hi, key_lo) or a CardResult;
         pass 1 counts them in workgroup-local memory (at most abi.HM_MAX_HEAVY)."""
         self.device = torch.device(device)
+        self.bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
+        self.bloom_in_table = (bloom_in_table or bool(flags & abi.HM_BLOOM_IN_TABLE)) and not self.bypass
+        flags = (flags | abi.HM_BLOOM_IN_TABLE) if self.bloom_in_table else (flags & ~abi.HM_BLOOM_IN_TABLE)
         self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner, flags,
                                  seed & (2 ** 64 - 1))
         abi.call("hm_check_params", ctypes.byref(self.params))
-        self.bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
+        if self.bloom_in_table:  # 32 filter bits per slot: at least the bits of bloom_words words
+            capacity = max(capacity, 2 * int(bloom_words))
         self.capacity = next_pow2(capacity)
         self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
         self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -275,7 +283,7 @@ class KmerCounter:
         self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr(),
                                self.stats_buf.data_ptr(),
                                self.heavy_keys.data_ptr() if self.heavy_keys is not None else None, len(hk), 0)
-        self.bloom_words = next_pow2(bloom_words) if not self.bypass else 1
+        self.bloom_words = next_pow2(bloom_words) if not (self.bypass or self.bloom_in_table) else 1
         self.bloom_buf = torch.empty(self.bloom_words, dtype=torch.int64, device=self.device)
         self.bloom = abi.Bloom(self.bloom_buf.data_ptr(), self.bloom_words, n_hash)
         self.list_capacity = int(list_capacity) if not self.bypass else 0
@@ -303,7 +311,8 @@ class KmerCounter:
         s = _stream(stream)
         abi.call("hm_table_init", ctypes.byref(self.table), s)
         if not self.bypass:
-            abi.call("hm_bloom_init", ctypes.byref(self.bloom), s)
+            if not self.bloom_in_table:  # else hm_table_init cleared it
+                abi.call("hm_bloom_init", ctypes.byref(self.bloom), s)
             abi.call("hm_list_init", ctypes.byref(self.list), s)
 
     def insert(self, packed: Packed, stream=None):
@@ -448,29 +457,54 @@ class CardSketch:
         return self.result(stream)
 
 
-def bloom_fp_rate(bits_per_key: float, n_hash: int) -> float:
+def bloom_fp_rate(bits_per_key: float, n_hash: int, word_bits: int = 64) -> float:
     """False-positive rate of the single-word blocked Bloom filter (every key's n_hash bits in one
-    64-bit word) at its final load: keys per word ~ Poisson(64 / bits_per_key)."""
-    lam = 64.0 / max(bits_per_key, 1e-9)
+    word of word_bits bits: 64 for the separate filter, 32 for the filter in the table) at its
+    final load: keys per word ~ Poisson(word_bits / bits_per_key)."""
+    lam = word_bits / max(bits_per_key, 1e-9)
     # Poisson weights in log space over the mass around the mode (no underflow at any load)
     lo = max(0, int(lam - 12.0 * np.sqrt(lam)) - 8)
     j = np.arange(lo, int(lam + 12.0 * np.sqrt(lam)) + 64, dtype=np.float64)
     logp = j * np.log(lam) - lam - np.array([math.lgamma(x + 1.0) for x in j])
-    return min(1.0, float(np.sum(np.exp(logp) * (1.0 - (1.0 - 1.0 / 64) ** (n_hash * j)) ** n_hash)))
+    # P(a new key's n_hash bits are all set | j keys in its word): the word has x bits set after
+    # the j keys' n_hash * j uniform draws (occupancy of word_bits bins, one more draw at a time:
+    # x stays with probability x / word_bits), and the n_hash test bits all fall among them with
+    # probability (x / word_bits)^n_hash
+    w = word_bits
+    x = np.arange(w + 1, dtype=np.float64)
+    hit = (x / w) ** n_hash
+    occ = np.zeros(w + 1)
+    occ[0] = 1.0
+    cond = np.ones(len(j))
+    for m in range(n_hash * (int(j[-1]) + 1)):
+        if m % n_hash == 0 and m // n_hash >= lo:
+            cond[m // n_hash - lo] = occ @ hit
+            if occ[w] > 1.0 - 1e-15:  # every bit set from here on
+                break
+        nxt = occ * (x / w)
+        nxt[1:] += occ[:-1] * ((w - x[:-1]) / w)
+        occ = nxt
+    return min(1.0, float(np.sum(np.exp(logp) * cond)))
 
 
 def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, table_load: float = 0.5,
-               pass1_launches: int = 1, device=None) -> tuple[int, int, int]:
+               pass1_launches: int = 1, device=None, bloom_in_table: bool = True) -> tuple[int, int, int]:
     """(table capacity, Bloom words, list capacity) from a cardinality pass, the way the paper
     sizes its Bloom filter from the HyperLogLog estimate: the filter gets `bloom_bits` bits per
-    distinct k-mer; the table holds the kept k-mers plus the singletons the filter lets through;
-    the first-occurrence list holds at most one entry per distinct k-mer plus the per-launch
-    chunk slack."""
+    distinct k-mer (Bloom words: its size in 64-bit words); the table holds the kept k-mers plus
+    the singletons the filter lets through, and with the filter in the table (32 bits per slot)
+    at least the filter's bits; the first-occurrence list holds at most one entry per distinct
+    k-mer plus the per-launch chunk slack."""
     d_hi = card.distinct_hi()
     kept_hi = card.kept_hi()
     bloom_words = next_pow2(max(64, int(d_hi * bloom_bits / 64)))
-    fp = bloom_fp_rate(bloom_words * 64 / max(d_hi, 1.0), n_hash)
-    capacity = next_pow2(max(1024, int((kept_hi + fp * max(d_hi - kept_hi, 0.0)) / table_load)))
+    if bloom_in_table:
+        floor = max(1024, 2 * bloom_words)
+        fp = bloom_fp_rate(floor * 32 / max(d_hi, 1.0), n_hash, word_bits=32)  # a bigger table only lowers it
+        capacity = next_pow2(max(floor, int((kept_hi + fp * max(d_hi - kept_hi, 0.0)) / table_load)))
+    else:
+        fp = bloom_fp_rate(bloom_words * 64 / max(d_hi, 1.0), n_hash)
+        capacity = next_pow2(max(1024, int((kept_hi + fp * max(d_hi - kept_hi, 0.0)) / table_load)))
     lcap = int(d_hi) + list_slack(pass1_launches, device)
     return capacity, bloom_words, lcap
 
@@ -481,7 +515,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             bypass: bool = False, checked: bool = False, export_flags: int = 0, capacity: int | None = None,
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
             seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
-            present_filter: bool = True, sizing: str = "card", heavy: bool = True) -> dict:
+            present_filter: bool = True, sizing: str = "card", heavy: bool = True,
+            bloom_in_table: bool = True) -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
     Sizes not given are planned from a cardinality pass over the reads
@@ -489,7 +524,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     set to worst-case bounds from the number of windows (sizing="bound").  On
     a capacity error the table (or list) is doubled and the run repeated from
     scratch, which keeps the result exact.  heavy: count the heavy hitters the
-    cardinality pass finds in workgroup-local memory (sizing="card" only)."""
+    cardinality pass finds in workgroup-local memory (sizing="card" only).  bloom_in_table: the
+    Bloom filter in the table's slots (KmerCounter) or a separate one."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
     q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
@@ -502,7 +538,7 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     if sizing == "card" and (heavy or not (capacity and bloom_words and list_capacity is not None)):
         sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
         card = sk.run([packed], min_depth=min_depth)
-        c_cap, c_bw, c_lcap = plan_sizes(card, n_hash=n_hash, device=dev)
+        c_cap, c_bw, c_lcap = plan_sizes(card, n_hash=n_hash, device=dev, bloom_in_table=bloom_in_table)
         del sk
         if bypass or min_depth == 1:  # every distinct k-mer goes into the table
             c_cap = next_pow2(max(1024, int(card.distinct_hi() / 0.5)))
@@ -516,7 +552,7 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     for _ in range(retries + 1):
         kc = KmerCounter(k, cap, bw, lcap, n_hash=n_hash, min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
                          owner=owner, flags=flags, seed=seed, max_probe=max_probe, present_filter=present_filter,
-                         heavy=card if heavy else None,
+                         heavy=card if heavy else None, bloom_in_table=bloom_in_table,
                          device=dev)
         out = Records(kc.capacity, device=dev)
         kc.run([packed], out, flags=export_flags, fused=fused)

@@ -237,8 +237,10 @@ class GpuBackend:
         return self._reads_bytes(j) + self._sketch_bytes(j)
 
     def footprint(self, j: Job) -> int:
+        from .kmer import next_pow2
         cap, bw, lcap, ocap = self.sizes(j)
-        return self._reads_bytes(j) + 64 * cap + cap // 2 + 8 * bw + 17 * lcap + 54 * ocap
+        cap = next_pow2(max(cap, 2 * bw))  # the Bloom filter lives in the table: 32 bits per slot
+        return self._reads_bytes(j) + 64 * cap + cap // 2 + 17 * lcap + 54 * ocap
 
     def _stream(self):
         return self._streams.pop() if self._streams else self.torch.cuda.Stream(device=self.device)

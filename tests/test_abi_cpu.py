@@ -64,7 +64,8 @@ def test_check_params_rejects(L, bad):
 
 
 @pytest.mark.parametrize("good", [dict(), dict(k=1), dict(k=63), dict(k=20, flags=abi.HM_FORWARD_ONLY),
-                                  dict(n_owners=16, owner=15), dict(flags=abi.HM_BLOOM_BYPASS | abi.HM_CHECKED)])
+                                  dict(n_owners=16, owner=15), dict(flags=abi.HM_BLOOM_BYPASS | abi.HM_CHECKED),
+                                  dict(flags=abi.HM_BLOOM_IN_TABLE | abi.HM_CHECKED)])
 def test_check_params_accepts(L, good):
     assert L.hm_check_params(ctypes.byref(P(**good))) == abi.HM_OK
 
@@ -94,6 +95,17 @@ def test_host_side_rejections_touch_no_device(L):
                              None) == abi.HM_EINVAL  # k mismatch with the table
     assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31)), None, ctypes.byref(t), None,
                              None) == abi.HM_EINVAL  # Bloom needed
+    # the filter in the table still needs n_hash from hm_bloom_t (its words are not used)
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_IN_TABLE)), None,
+                             ctypes.byref(t), None, None) == abi.HM_EINVAL
+    b = abi.Bloom(None, 0, 0)
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_IN_TABLE)), ctypes.byref(b),
+                             ctypes.byref(t), None, None) == abi.HM_EINVAL
+    assert "n_hash" in abi.last_error()
+    b = abi.Bloom(None, 0, 4)  # accepted: the next check is the list's
+    assert L.hm_bloom_insert(ctypes.byref(r), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_IN_TABLE)), ctypes.byref(b),
+                             ctypes.byref(t), None, None) == abi.HM_EINVAL
+    assert "list" in abi.last_error()
     e = abi.Export(None, None, None, None, None, None, None, 10, 64, None)
     assert L.hm_export_table(ctypes.byref(t), 0, ctypes.byref(e), None) == abi.HM_EINVAL
     assert L.hm_export_table(ctypes.byref(t), 99, ctypes.byref(e), None) == abi.HM_EINVAL

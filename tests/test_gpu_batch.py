@@ -82,19 +82,20 @@ def test_output_independent_of_tuning():
     ref = None
     for tu in (Tuning(), Tuning(blocks_per_cu=1, tile_bases=1024, list_per_item=256, slots_per_item=2048),
                Tuning(blocks_per_cu=16, table_load=0.6, bloom_bits=6, n_hash=1)):
-        b = Batch(specs, 31, tuning=tu)
-        b.launch()
-        st = b.status()
-        assert all(x == abi.HM_OK for x in st), (tu, st)
-        d = b.digests()
-        ref = ref or d
-        assert d == ref
-        del b
-        torch.cuda.empty_cache()
+        for in_table in (True, False):
+            b = Batch(specs, 31, tuning=tu, bloom_in_table=in_table)
+            b.launch()
+            st = b.status()
+            assert all(x == abi.HM_OK for x in st), (tu, in_table, st)
+            d = b.digests()
+            ref = ref or d
+            assert d == ref
+            del b
+            torch.cuda.empty_cache()
     # a filter far too small for the table size (sized from the hints, not planned, so the table
     # does not make room for the false positives): false-positive singletons fill the table,
     # which must be reported as a capacity error, never as a wrong table
-    b = Batch(specs, 31, tuning=Tuning(table_load=0.9, bloom_bits=1, n_hash=1), plan=False)
+    b = Batch(specs, 31, tuning=Tuning(table_load=0.9, bloom_bits=1, n_hash=1), plan=False, bloom_in_table=False)
     b.launch()
     st = b.status()
     assert abi.HM_ECAPACITY in st and all(x in (abi.HM_OK, abi.HM_ECAPACITY) for x in st)

@@ -127,12 +127,60 @@ def test_fixed_length_reads(k, L):
 
 @pytest.mark.parametrize("bloom_words,n_hash", [(1, 1), (1, 8), (64, 2), (1 << 22, 4)])
 def test_output_independent_of_bloom(bloom_words, n_hash):
-    """A 1-word filter makes nearly every first occurrence a false positive; a huge one almost
-    none.  The table must not change."""
+    """A 1-word separate filter makes nearly every first occurrence a false positive; a huge one
+    almost none.  The table must not change."""
     ascii, qual, off = random_read_set(77, 2000, 90, 150, genome_len=15000)
     exp = oracle.run(ascii, qual, off, 31, n_threads=4)
-    got = kmer.analyze(ascii, qual, 31, read_off=off, bloom_words=bloom_words, n_hash=n_hash)
+    got = kmer.analyze(ascii, qual, 31, read_off=off, bloom_words=bloom_words, n_hash=n_hash, bloom_in_table=False)
     assert_tables_equal(got, exp, "bloom %d/%d" % (bloom_words, n_hash))
+
+
+@pytest.mark.parametrize("capacity,n_hash", [(None, 1), (None, 8), (1024, 8), (1 << 20, 4)])
+def test_output_independent_of_bloom_in_table(capacity, n_hash):
+    """The filter in the table's classification words (32 bits per slot): planned sizes, a
+    1024-slot start that fills up and is doubled until every kept k-mer and false positive
+    fits, and a 2^20-slot table whose filter almost never errs.  The table must not change."""
+    ascii, qual, off = random_read_set(77, 2000, 90, 150, genome_len=15000)
+    exp = oracle.run(ascii, qual, off, 31, n_threads=4)
+    got = kmer.analyze(ascii, qual, 31, read_off=off, capacity=capacity, bloom_words=1, n_hash=n_hash,
+                       retries=8)
+    assert_tables_equal(got, exp, "bloom in table, capacity %s, %d hashes" % (capacity, n_hash))
+    st = got["stats"]
+    assert 0 < st["deferred"] <= st["bloom_tests"]
+
+
+@pytest.mark.parametrize("in_table", [True, False])
+def test_classify_between_pass1_batches(in_table):
+    """A classification between two pass-1 batches overwrites the classification words, which
+    hold the filter when it is in the table: the classification marks the table, and the second
+    batch then inserts every absent k-mer instead of testing the lost bits.  Either way the table
+    equals the oracle's over both batches."""
+    ascii, qual, off = random_read_set(15, 3000, 150, 150)
+    exp = oracle.run(ascii, qual, off, 31)
+    kc = kmer.KmerCounter(31, 1 << 17, 1 << 14, 1 << 19, bloom_in_table=in_table)
+    assert kc.bloom_in_table == in_table
+    packs = []
+    for b0, b1 in ((0, 1400), (1400, 3000)):
+        a0, a1 = off[b0], off[b1]
+        packs.append(kmer.pack_reads(torch.from_numpy(ascii[a0:a1]).cuda(), torch.from_numpy(qual[a0:a1]).cuda(),
+                                     read_len=150))
+    out = kmer.Records(1 << 17)
+    kc.reset()
+    kc.insert(packs[0])
+    deferred_1 = kc.stats()["deferred"]
+    kc.classify()
+    assert int(kc.status_buf.item()) == abi.HM_ST_CLASSIFIED
+    kc.insert(packs[1])
+    deferred_2 = kc.stats()["deferred"] - deferred_1
+    kc.count()
+    kc.export(out, abi.HM_EXPORT_CLASSIFY)
+    assert kc.status() == abi.HM_OK
+    assert_tables_equal(out.to_numpy(), exp, "classify between pass-1 batches")
+    assert deferred_1 > 0
+    if in_table:  # nothing of the second batch was deferred
+        assert deferred_2 == 0
+    else:
+        assert deferred_2 > 0
 
 
 def test_bypass_and_keep_all_sum():

@@ -49,8 +49,9 @@ def test_capacity_retry_in_serving():
     _, builders = synth.serving_jobs(n_jobs=2, scale=0.005)
     pool = [b() for b in builders]
     jobs, _ = make_jobs(pool, n_jobs=2, rate=100.0)
-    for j in jobs:
-        j.kept_est = 100.0  # far too small a table: the server must resize and rerun
+    for j in jobs:  # far too small a table and filter: the server must resize and rerun
+        j.kept_est = 100.0
+        j.distinct_est = 100.0  # (the filter in the table would otherwise size the table from it)
     # sized from the (wrong) hints instead of a cardinality pass
     recs = Scheduler(GpuBackend(51, plan=False), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
     assert all(r.status == 0 and r.retries > 0 for r in recs)
