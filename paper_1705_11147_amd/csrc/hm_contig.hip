@@ -390,7 +390,7 @@ __device__ __forceinline__ uint32_t step_link(uint32_t i, const Step &st_, int d
 // Links of every record; collects the rulers (heads and sampled half-nodes)
 // into listA through a wave-local buffer in LDS, flushed with one atomic per
 // kRulerBuf / 4 - 128 entries (no workgroup barrier in the loop).
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_ctg_link(Graph g) {
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_ctg_link(Graph g) {
     constexpr int kWaveBuf = kRulerBuf / (kBlock / 64);
     __shared__ uint32_t s_buf[kRulerBuf];
     if (stopped(g)) return;

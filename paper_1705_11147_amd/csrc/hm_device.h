@@ -56,6 +56,10 @@ struct Slot {
 static_assert(sizeof(Slot) == HM_SLOT_BYTES, "slot is one 64-byte line");
 
 #define RLX __ATOMIC_RELAXED
+// Eight waves per SIMD (at most 64 registers a lane).  The random-access
+// kernels are bound by the memory requests they keep in flight, so spilling a
+// few registers to scratch costs less than losing one wave in eight.
+#define HM_EIGHT_WAVES __attribute__((amdgpu_waves_per_eu(8, 8)))
 #define AGT __HIP_MEMORY_SCOPE_AGENT
 
 // ------------------------------------------------------------------ hashing

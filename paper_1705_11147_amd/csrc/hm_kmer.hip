@@ -71,7 +71,7 @@ using namespace hm;
 // Pass 1 over fixed-length reads: tiles of whole reads staged in LDS.  HEAVY:
 // the table's heavy keys are counted in dynamic LDS and flushed at the end.
 template <int KW, bool CHECKED, bool HEAVY>
-__global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t reads_per_tile, int64_t n_tiles) {
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_fixed(PassArgs a, int32_t reads_per_tile, int64_t n_tiles) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_pass1_fixed(PassArgs a, int32_t read
 
 // Pass 1 over variable-length reads (read_off given).
 template <int KW, bool CHECKED, bool HEAVY>
-__global__ __launch_bounds__(kBlock) void k_pass1_var(PassArgs a, int64_t n_tiles) {
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_var(PassArgs a, int64_t n_tiles) {
     __shared__ int64_t s_off[kVarReads + 1];
     __shared__ int64_t s_pre[kVarReads + 1];
     extern __shared__ uint64_t s_heavy[];
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, 
 }
 
 template <int KW>
-__global__ __launch_bounds__(kBlock) void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
                                                    uint32_t *status, uint4 *staged) {
     __shared__ uint16_t s_rank[kBlock / 64][kExportChunk];
     uint64_t dsum = 0, dxor = 0;
