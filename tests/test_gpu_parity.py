@@ -123,6 +123,21 @@ def test_fixed_length_reads(k, L):
     assert_tables_equal(got, exp, "fixed k=%d L=%d" % (k, L))
 
 
+@pytest.mark.parametrize("k", [5, 31, 51, 63])
+def test_separate_bloom_filter(k):
+    """The separate 64-bit-word filter (the table's classification words left out of pass 1):
+    ragged reads, fixed-length reads with heavy hitters, and forward-only keys."""
+    ascii, qual, off = random_read_set(100 + k, 3000, 0, 220, genome_len=30000, n_rate=0.002, lower_rate=0.01)
+    got, exp = both(ascii, qual, off, k, qcut=20, bloom_in_table=False)
+    assert_tables_equal(got, exp, "separate filter, var k=%d" % k)
+    ascii, qual, off = random_read_set(200 + k, 2000, 150, 150, genome_len=8000)
+    got, exp = both(ascii, qual, off, k, read_len=150, qcut=20, bloom_in_table=False)
+    assert_tables_equal(got, exp, "separate filter, fixed k=%d" % k)
+    assert got["n_heavy"] > 0 or k == 5  # the 8 kbp genome at 37x has k-mers frequent enough to be heavy
+    got, exp = both(ascii, qual, off, k, read_len=150, qcut=20, bloom_in_table=False, forward_only=True)
+    assert_tables_equal(got, exp, "separate filter, forward only k=%d" % k)
+
+
 # ------------------------------------------------------------------ Bloom independence
 
 @pytest.mark.parametrize("bloom_words,n_hash", [(1, 1), (1, 8), (64, 2), (1 << 22, 4)])
