@@ -276,8 +276,11 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 
 /* Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
  * HM_EXPORT_ALL, HM_EXPORT_CLASSIFY, HM_EXPORT_SORTED.  Zeroes out->n_out (and
- * out->digest) first.  Without HM_EXPORT_SORTED the records are in table-slot
- * (hash) order.  With it they are in ascending key order: a radix sort of
+ * out->digest) first.  Without HM_EXPORT_SORTED the records come in no fixed
+ * order: each run of 512 table slots takes its output range with one atomic,
+ * so runs land in the order they finish, each in slot (hash) order; the set of
+ * records and the digest do not depend on it.  With HM_EXPORT_SORTED they are
+ * in ascending key order: a radix sort of
  * the 2k key bits runs after the compaction on the same
  * stream and uses out->sort_work as scratch (HM_EINVAL if it is NULL,
  * misaligned, smaller than hm_export_sort_bytes(out->capacity), or if
