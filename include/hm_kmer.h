@@ -108,7 +108,14 @@ typedef struct {
     int32_t k;          /* 1..63; odd unless HM_FORWARD_ONLY */
     uint32_t min_depth; /* keep k-mers seen >= min_depth times (>= 1; 1 forces HM_BLOOM_BYPASS) */
     uint32_t ext_min;   /* a side's base is a high-quality extension when tallied >= ext_min times (>= 1) */
-    uint32_t n_owners;  /* owner-computes partition: keep keys with own(key) == owner (1 = keep all) */
+    /* Owner-computes partition (section "Parallel k-mer analysis"): keep the
+     * keys with own(key) == owner (n_owners = 1 keeps all), where
+     * own(key) = floor(H * n_owners / 2^64) and
+     * H = fmix64(fmix64(key_hi ^ 0x243F6A8885A308D3) ^ key_lo), fmix64 being
+     * the 64-bit finalizer of MurmurHash3.  For n_owners a power of two the
+     * owners nest: owner 0 of 2^b is the part of owner 0 of 2^a (a < b) whose
+     * H has its top b bits zero. */
+    uint32_t n_owners;
     uint32_t owner;
     uint32_t flags;
     uint64_t seed; /* seed of the table and Bloom hashes; the output does not depend on it */
