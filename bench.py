@@ -260,14 +260,163 @@ def measure_contigs(kc, k, n_records, stream, log, reps=3, rates=None):
     return res
 
 
+def owner_zero_mask(key_hi, key_lo, bits: int):
+    """Records of owner 0 of 2^bits under the owner map of hm_params_t (own = the top bits of
+    H = fmix64(fmix64(key_hi ^ 0x243F6A8885A308D3) ^ key_lo)), computed with torch on the
+    device: wrapping int64 products are the unsigned 64-bit ones, and shifts are made logical
+    by masking.  A checker for the sub-shard comparison, outside the library."""
+    import torch
+
+    def s64(c):
+        return c - (1 << 64) if c >= 1 << 63 else c
+
+    def srl(x, n):
+        return (x >> n) & ((1 << (64 - n)) - 1)
+
+    def fmix(x):
+        x = x ^ srl(x, 33)
+        x = x * s64(0xFF51AFD7ED558CCD)
+        x = x ^ srl(x, 33)
+        x = x * s64(0xC4CEB9FE1A85EC53)
+        return x ^ srl(x, 33)
+
+    h = fmix(fmix(key_hi ^ s64(0x243F6A8885A308D3)) ^ key_lo)
+    return srl(h, 64 - bits) == 0 if bits > 0 else torch.ones_like(h, dtype=torch.bool)
+
+
+def run_human_share(args, dev):
+    """One GPU's share of the human-scale run at its real shape (owner 0 of 16; reads in
+    64M-read batches kept packed on the device), timed from the cardinality pass to the
+    exported table.  Checked by a single-pass count without the Bloom filter of the 1/64
+    sub-shard owner 0 of 1024, which must equal the main table's records of that sub-shard."""
+    import torch
+    from paper_1705_11147_amd import abi, kmer, synth
+
+    t0 = time.time()
+    w = synth.human_share(scale=args.scale)
+    p = w.params
+    L, k = w.read_len, p.k
+    nb = w.meta["batch_reads"]
+    cuts = list(range(0, w.n_reads, nb)) + [w.n_reads]
+    log("workload %s: genome %.3g bp, %d reads in %d batches (genome built in %.1fs)" % (
+        w.name, w.meta["G"], w.n_reads, len(cuts) - 1, time.time() - t0))
+    packs, gen_s, up_ms, pack_ms = [], 0.0, 0.0, 0.0
+    for b in range(len(cuts) - 1):
+        t1 = time.time()
+        r = w.reads(r0=cuts[b], n=cuts[b + 1] - cuts[b])
+        gen_s += time.time() - t1
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        ascii = torch.from_numpy(r.ascii).to(dev)
+        qual = torch.from_numpy(r.qual).to(dev)
+        e[1].record()
+        packs.append(kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut))
+        e[2].record()
+        torch.cuda.synchronize()
+        up_ms += e[0].elapsed_time(e[1])
+        pack_ms += e[1].elapsed_time(e[2])
+        del ascii, qual, r
+        log("batch %d of %d: %d reads generated, uploaded and packed" % (b + 1, len(cuts) - 1, cuts[b + 1] - cuts[b]))
+    torch.cuda.empty_cache()
+    scanned = w.n_reads * (L - k + 1)
+    sketch = kmer.CardSketch(k, scanned, n_owners=p.n_owners, owner=p.owner, device=dev)
+    card = sketch.run(packs, min_depth=p.min_depth)
+    abi.check(card.status, "cardinality pass")
+    cap, bloom_words, list_cap = kmer.plan_sizes(card, pass1_launches=len(packs), device=dev)
+    kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_owners=p.n_owners, owner=p.owner, heavy=card, device=dev)
+    out = kmer.Records(int(min(kc.capacity, card.kept_hi() * 1.3 + 1024)), device=dev)
+    log("owned: %.4g windows, %.4g distinct (HLL) -> table 2^%d slots (%.1f GB), list %.3g entries" % (
+        card.positions, card.estimate, kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, list_cap))
+    stages = ["card", "init", "pass1", "pass2", "classify_export"]
+
+    def step(ev):
+        ev[0].record()
+        sketch.reset()
+        for pk in packs:
+            sketch.update(pk)
+        sketch.summarize(min_depth=p.min_depth)
+        ev[1].record()
+        kc.reset()
+        ev[2].record()
+        for pk in packs:
+            kc.insert(pk)
+        ev[3].record()
+        kc.count()
+        ev[4].record()
+        kc.export(out, abi.HM_EXPORT_CLASSIFY)
+        ev[5].record()
+
+    n_steps = max(1, min(args.steps, 3))
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(n_steps + 1)]
+    for s in range(n_steps + 1):  # the first is a warm-up
+        step(events[s])
+        torch.cuda.synchronize()
+        abi.check(kc.status(), "human share step")
+        log("step %d of %d done" % (s + 1, n_steps + 1))
+    timed = events[1:]
+    stage_ms = {x: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in timed])) for i, x in enumerate(stages)}
+    step_ms = float(np.mean([ev[0].elapsed_time(ev[len(stages)]) for ev in timed]))
+    n_rec = int(out.n_out.item())
+    st = kc.stats()
+    owned = st["occurrences"]
+
+    # the check: the sub-shard owner 0 of 1024 counted in one pass without the Bloom filter
+    sub_bits = 10
+    sk2 = kmer.CardSketch(k, scanned, n_owners=1 << sub_bits, owner=0, device=dev)
+    c2 = sk2.run(packs, min_depth=p.min_depth)
+    kb = kmer.KmerCounter(k, kmer.next_pow2(max(1024, int(c2.distinct_hi() / 0.5))), 1, 0, min_depth=p.min_depth,
+                          n_owners=1 << sub_bits, owner=0, flags=abi.HM_BLOOM_BYPASS, device=dev)
+    ob = kmer.Records(int(c2.distinct_hi() * 1.1 + 1024), device=dev)
+    kb.run(packs, ob, fused=True)
+    abi.check(kb.status(), "sub-shard check")
+    nb_rec = int(ob.n_out.item())
+    sel = owner_zero_mask(out.key_hi[:n_rec], out.key_lo[:n_rec], sub_bits).nonzero().squeeze(1)
+
+    def rows(rec, idx):
+        return np.concatenate([x.cpu().numpy().astype(np.int64).reshape(len(idx), -1) for x in (
+            rec.key_hi[idx], rec.key_lo[idx], rec.count[idx], rec.tl.view(-1, 4)[idx], rec.tr.view(-1, 4)[idx],
+            rec.cls_l[idx], rec.cls_r[idx])], axis=1)
+
+    a = rows(out, sel)
+    b = rows(ob, torch.arange(nb_rec, device=dev))
+    a = a[np.lexsort(a[:, 1::-1].T)]
+    b = b[np.lexsort(b[:, 1::-1].T)]
+    same = a.shape == b.shape and bool((a == b).all())
+    log("sub-shard owner 0 of %d: %d records in the main table, %d in the single-pass count, identical: %s" % (
+        1 << sub_bits, len(a), len(b), same))
+    assert same, "the human-share table disagrees with the single-pass count of its sub-shard"
+    line = {
+        "metric": "owned k-mers/s k-mer analysis, one GPU's share of the human-scale run (bit-exact)",
+        "value": round(owned / (step_ms / 1000), 1), "unit": "k-mers/s", "n_gpus": 1, "steps": n_steps,
+        "warmup": 1, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": w.n_reads, "read_len": L, "k": k,
+                   "n_owners": p.n_owners, "owner": p.owner, "batches": len(packs),
+                   "scanned_positions": scanned, "owned_positions": owned,
+                   "scanned_positions_per_s": round(scanned / (step_ms / 1000), 1),
+                   "kept_kmers": n_rec, "table_slots": kc.capacity, "list_capacity": list_cap,
+                   "hll_estimate": round(card.estimate, 1),
+                   "step": "cardinality + init + pass 1 over every batch + pass 2 + classify/export; "
+                           "packed reads resident in HBM",
+                   "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
+                   "outside_step": {"generate_s": round(gen_s, 1), "h2d_ms": round(up_ms, 1),
+                                    "pack_ms": round(pack_ms, 1)}},
+        "check": {"sub_shard": "owner 0 of %d" % (1 << sub_bits), "records": len(a), "identical": same},
+        "events_per_owned_position": {x: round(v / max(owned, 1), 4) for x, v in st.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = the full mid workload)")
-    ap.add_argument("--workload", choices=["mid", "mid-heavy"], default="mid",
-                    help="mid: the headline workload; mid-heavy: mid with 2%% satellite arrays (heavy hitters)")
+    ap.add_argument("--workload", choices=["mid", "mid-heavy", "human-share"], default="mid",
+                    help="mid: the headline workload; mid-heavy: mid with 2%% satellite arrays (heavy hitters); "
+                         "human-share: one GPU's share of the human-scale run (owner 0 of 16, streamed batches; "
+                         "its own JSON line)")
     ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
@@ -310,6 +459,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     abi.lib()
+    if args.workload == "human-share":
+        run_human_share(args, dev)
+        return
 
     t0 = time.time()
     w = synth.mid(scale=args.scale) if args.workload == "mid" else synth.mid_heavy(scale=args.scale)
