@@ -635,6 +635,104 @@ __device__ __forceinline__ void fixed_windows(const PassArgs &a, int32_t reads_p
     }
 }
 
+// Fixed-length reads with an owner filter.  Most windows belong to other
+// owners, so counting each owned occurrence where it is found would keep one
+// or two lanes of a wave busy with the table while the others wait.  Instead
+// the owned occurrences are queued in LDS (one LDS atomic per wave per round)
+// and handed to op a workgroup at a time, every lane holding one (act = false
+// only in the last, partial round).  A full table is noticed per tile, for the
+// whole workgroup, since the rounds meet at workgroup barriers.
+constexpr unsigned kQueue = 512;  // a round adds at most kBlock: drained once more than kQueue - kBlock wait
+
+struct OccQueue {
+    uint4 *key;    // kQueue entries: (lo, hi) words of the canonical key
+    uint8_t *ext;  // left | right << 4
+    unsigned *n;
+    int *stop;
+};
+
+template <bool ABORT, class Op>
+__device__ __forceinline__ void fixed_windows_queued(const PassArgs &a, int32_t reads_per_tile, int64_t n_tiles,
+                                                     uint64_t *s_b2, uint64_t *s_nm, uint64_t *s_hq,
+                                                     const OccQueue &q, Op &&op) {
+    const int L = a.read_len;
+    const int k = a.k;
+    const int W = L - k + 1;  // windows per read (> 0, checked by the host)
+    const uint32_t lane = lane_id();
+    auto drain = [&](unsigned n) {  // every thread calls it with the same n
+        for (unsigned q0 = 0; q0 < n; q0 += kBlock) {
+            const unsigned i = q0 + threadIdx.x;
+            Occ o{0, 0, 4, 4};
+            const bool act = i < n;
+            if (act) {
+                const uint4 kk = q.key[i];
+                o.lo = ((uint64_t)kk.y << 32) | kk.x;
+                o.hi = ((uint64_t)kk.w << 32) | kk.z;
+                const uint8_t e = q.ext[i];
+                o.left = e & 15;
+                o.right = e >> 4;
+            }
+            op(act, o, (int64_t)0);
+        }
+    };
+    if (threadIdx.x == 0) *q.n = 0;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * reads_per_tile;
+        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
+        const int64_t base0 = r0 * L, base1 = r1 * L;
+        const int64_t org = base0 & ~(int64_t)63;
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)(((base1 + 63) >> 6) - mw0) + 2;
+        __syncthreads();  // previous tile's readers are done
+        if (threadIdx.x == 0) *q.stop = ABORT && (__hip_atomic_load(a.status, RLX, AGT) & kAbortBits) != 0;
+        for (int i = threadIdx.x; i < nmw; i += kBlock) {
+            s_nm[i] = a.nm[mw0 + i];
+            s_hq[i] = a.hq[mw0 + i];
+        }
+        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        if (*q.stop) break;  // workgroup-uniform
+        const Words w{s_b2, s_nm, s_hq};
+        const int total = (int)(r1 - r0) * W;
+        for (int f0 = 0; f0 < total; f0 += kBlock) {  // workgroup-uniform trip count
+            const int f = f0 + threadIdx.x;
+            Occ o{0, 0, 4, 4};
+            bool act = false;
+            if (f < total) {
+                const int r = f / W;
+                const int pos = f - r * W;
+                const int64_t rb = (r0 + r) * L - org;
+                act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
+            }
+            const uint64_t m = __ballot(act);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                unsigned base = 0;
+                if ((int)lane == leader) base = atomicAdd(q.n, (unsigned)__popcll(m));
+                base = __shfl(base, leader);
+                if (act) {
+                    const unsigned i = base + (unsigned)__popcll(m & ((1ull << lane) - 1));
+                    q.key[i] = make_uint4((uint32_t)o.lo, (uint32_t)(o.lo >> 32), (uint32_t)o.hi,
+                                          (uint32_t)(o.hi >> 32));
+                    q.ext[i] = (uint8_t)(o.left | (o.right << 4));
+                }
+            }
+            __syncthreads();  // the round's appends are done
+            const unsigned n = *q.n;
+            __syncthreads();  // every thread has read n before the count changes again
+            if (n > kQueue - kBlock) {  // workgroup-uniform
+                drain(n);
+                __syncthreads();  // the entries are read before the next round overwrites them
+                if (threadIdx.x == 0) *q.n = 0;
+                __syncthreads();  // the cleared count is seen before the next round's appends
+            }
+        }
+    }
+    __syncthreads();
+    const unsigned n = *q.n;
+    drain(n);  // the rest (also after a stop: its occurrences were found before the table filled)
+}
+
 // Visit every window of variable-length reads (read_off given): packed words
 // are read from global memory; a per-tile prefix sum in LDS (the caller's
 // s_off / s_pre, kVarReads + 1 entries each) maps flat window indices to

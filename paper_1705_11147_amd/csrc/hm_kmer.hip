@@ -89,6 +89,33 @@ __global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_fixed(PassArgs 
     stats_flush(a.stats, st);
 }
 
+// Pass 1 over fixed-length reads with an owner filter: owned occurrences are
+// queued in LDS and counted with every lane of the workgroup busy.
+template <int KW, bool CHECKED, bool HEAVY>
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_owned(PassArgs a, int32_t reads_per_tile,
+                                                                       int64_t n_tiles) {
+    __shared__ uint64_t s_b2[kTileB2Words];
+    __shared__ uint64_t s_nm[kTileMaskWords];
+    __shared__ uint64_t s_hq[kTileMaskWords];
+    __shared__ uint4 s_qkey[kQueue];
+    __shared__ uint8_t s_qext[kQueue];
+    __shared__ unsigned s_qn;
+    __shared__ int s_stop;
+    extern __shared__ uint64_t s_heavy[];
+    HeavyLds hv{};
+    if (HEAVY) hv = heavy_setup(a, s_heavy);
+    ListCursor cur{0, kListChunk};
+    Stats st = {};
+    const bool seen_all = classified_in_table(a);
+    const OccQueue q{s_qkey, s_qext, &s_qn, &s_stop};
+    fixed_windows_queued<true>(a, reads_per_tile, n_tiles, s_b2, s_nm, s_hq, q, [&](bool act, const Occ &o, int64_t) {
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv, seen_all);
+    });
+    list_close(a, cur);
+    if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
+    stats_flush(a.stats, st);
+}
+
 // Pass 1 over variable-length reads (read_off given).
 template <int KW, bool CHECKED, bool HEAVY>
 __global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_var(PassArgs a, int64_t n_tiles) {
@@ -391,11 +418,15 @@ int hm_bloom_insert(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, hm
     const int grid_cap = device_cus() * 8;
     if (!r->read_off && r->read_len <= kTileBases - 64) {
         if (r->read_len < p->k) return HM_OK;  // no windows
+        const bool owned = p->n_owners > 1;     // most windows dropped: queue the owned ones
         const int32_t rpt = kTileBases / r->read_len;
         const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
         const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
-#define LAUNCH_FIXED(KW, CH, HV) \
-    hipLaunchKernelGGL((k_pass1_fixed<KW, CH, HV>), g, dim3(kBlock), lds, s, a, rpt, n_tiles)
+#define LAUNCH_FIXED(KW, CH, HV)                                                                        \
+    do {                                                                                                \
+        if (owned) hipLaunchKernelGGL((k_pass1_owned<KW, CH, HV>), g, dim3(kBlock), lds, s, a, rpt, n_tiles); \
+        else hipLaunchKernelGGL((k_pass1_fixed<KW, CH, HV>), g, dim3(kBlock), lds, s, a, rpt, n_tiles);  \
+    } while (0)
 #define LAUNCH_FIXED2(KW, CH) \
     do { if (heavy) LAUNCH_FIXED(KW, CH, true); else LAUNCH_FIXED(KW, CH, false); } while (0)
         if (two) { if (checked) LAUNCH_FIXED2(2, true); else LAUNCH_FIXED2(2, false); }

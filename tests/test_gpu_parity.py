@@ -123,6 +123,32 @@ def test_fixed_length_reads(k, L):
     assert_tables_equal(got, exp, "fixed k=%d L=%d" % (k, L))
 
 
+@pytest.mark.parametrize("k,L", [(1, 4), (5, 12), (21, 100), (31, 31), (33, 40), (51, 150), (63, 200),
+                                 (15, 16384 - 64)])
+def test_owner_filtered_fixed_reads(k, L):
+    """Fixed-length reads with an owner filter take the rolled window loop (a run of 8 windows per
+    lane, codes rolled one base at a time): every owner of 3 against the oracle, with N bases,
+    low-quality bases and runs cut short at read ends (L - k + 1 windows per read: below 8, exactly
+    8, one, and not a multiple of 8), 2k just above 64 bits, one read per tile; and forward-only keys."""
+    n = max(3, 300_000 // L)
+    rng = np.random.default_rng(1000 + k)
+    g = rng.choice(np.frombuffer(b"ACGT", np.uint8), 20000)
+    starts = rng.integers(0, g.size - L + 1, n)
+    ascii = np.concatenate([g[s:s + L] for s in starts])
+    flip = rng.random(ascii.size) < 0.01
+    ascii[flip] = rng.choice(np.frombuffer(b"ACGTN", np.uint8), int(flip.sum()))
+    qual = rng.integers(2, 42, ascii.size).astype(np.uint8)
+    off = np.arange(n + 1, dtype=np.int64) * L
+    total = 0
+    for owner in range(3):
+        got, exp = both(ascii, qual, off, k, read_len=L, qcut=25, n_owners=3, owner=owner)
+        assert_tables_equal(got, exp, "owner %d of 3, k=%d L=%d" % (owner, k, L))
+        total += len(got["count"])
+    assert total == len(oracle.run(ascii, qual, off, k, qcut=25, n_threads=4)["count"])
+    got, exp = both(ascii, qual, off, k, read_len=L, qcut=25, n_owners=2, owner=1, forward_only=True)
+    assert_tables_equal(got, exp, "forward only, owner 1 of 2, k=%d L=%d" % (k, L))
+
+
 @pytest.mark.parametrize("k", [5, 31, 51, 63])
 def test_separate_bloom_filter(k):
     """The separate 64-bit-word filter (the table's classification words left out of pass 1):
