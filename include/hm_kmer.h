@@ -284,7 +284,7 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 /* Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
  * HM_EXPORT_ALL, HM_EXPORT_CLASSIFY, HM_EXPORT_SORTED.  Zeroes out->n_out (and
  * out->digest) first.  Without HM_EXPORT_SORTED the records come in no fixed
- * order: each run of 512 table slots takes its output range with one atomic,
+ * order: each run of 2048 table slots takes its output range with one atomic,
  * so runs land in the order they finish, each in slot (hash) order; the set of
  * records and the digest do not depend on it.  With HM_EXPORT_SORTED they are
  * in ascending key order: a radix sort of

@@ -855,22 +855,25 @@ __device__ __forceinline__ void pack16(uint4 sa, uint4 sq, int nvalid, int qual_
 constexpr int kExportPerLane = 8;  // slots per lane per wave iteration: 512 per wave
 constexpr int kExportChunk = 64 * kExportPerLane;
 
-// Export one chunk of 512 consecutive slots [first, first+512) ∩ [0, cap) with
-// one wave: the slots are tested 8 per lane (coalesced), the taken ones
-// ranked with a wave prefix sum and their offsets staged in `rank_of` (LDS,
-// 512 entries per wave); one atomic add reserves the wave's output range and
+// Export one chunk of 64 * PER consecutive slots [first, first + 64 * PER) ∩
+// [0, cap) with one wave: the slots are tested PER per lane (coalesced), the
+// taken ones ranked with a wave prefix sum and their offsets staged in
+// `rank_of` (LDS, 64 * PER entries per wave); one atomic add reserves the
+// wave's output range and
 // lane r writes record base+r, so every record store is coalesced.  With
 // HM_EXPORT_CLASSIFY the depth filter and classes come from the counters
 // (out.min_depth, out.ext_min); otherwise from the table's classify word.
-template <int KW>
+// PER: slots per lane (the chunk is 64 * PER slots; the default 512).
+template <int KW, int PER = kExportPerLane>
 __device__ __forceinline__ void export_chunk(const Slot *slots, uint64_t first, uint64_t cap, uint32_t flags,
                                              const hm_export_t &out, uint32_t *status, uint16_t *rank_of,
                                              uint64_t &dsum, uint64_t &dxor, uint4 *staged = nullptr) {
+    static_assert(PER >= 1 && PER <= 32, "one take bit per slot of a lane");
     const uint32_t lane = lane_id();
     const bool inline_cls = (flags & HM_EXPORT_CLASSIFY) != 0;
     uint32_t take_bits = 0;
 #pragma unroll 1
-    for (int j = 0; j < kExportPerLane; ++j) {
+    for (int j = 0; j < PER; ++j) {
         const uint64_t i = first + (uint64_t)j * 64 + lane;
         if (i < cap) {
             const Slot *sl = slots + i;
@@ -906,7 +909,7 @@ __device__ __forceinline__ void export_chunk(const Slot *slots, uint64_t first, 
     const uint32_t total = __shfl(incl, 63);
     if (total == 0) return;
     uint32_t r = incl - cnt;
-    for (int j = 0; j < kExportPerLane; ++j)
+    for (int j = 0; j < PER; ++j)
         if ((take_bits >> j) & 1) rank_of[r++] = (uint16_t)(j * 64 + lane);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

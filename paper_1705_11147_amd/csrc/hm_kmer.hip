@@ -167,15 +167,20 @@ __global__ __launch_bounds__(kBlock) void k_classify(Slot *slots, uint64_t cap, 
     }
 }
 
-template <int KW>
+// PER slots per lane: a chunk of 64 * PER slots per wave and one output-counter
+// atomic per chunk.  The plain export takes 2048-slot chunks (a quarter of the
+// atomics on the one counter); the key-ordered one keeps 512, whose record runs
+// its sort's grouping passes were measured faster on.
+template <int KW, int PER>
 __global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_export(const Slot *slots, uint64_t cap, uint32_t flags, hm_export_t out,
                                                    uint32_t *status, uint4 *staged) {
-    __shared__ uint16_t s_rank[kBlock / 64][kExportChunk];
+    constexpr int kChunk = 64 * PER;
+    __shared__ uint16_t s_rank[kBlock / 64][kChunk];
     uint64_t dsum = 0, dxor = 0;
     const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * kBlock) >> 6;
-    for (uint64_t first = wave * kExportChunk; first < cap; first += n_waves * kExportChunk)
-        export_chunk<KW>(slots, first, cap, flags, out, status, s_rank[threadIdx.x >> 6], dsum, dxor, staged);
+    for (uint64_t first = wave * kChunk; first < cap; first += n_waves * kChunk)
+        export_chunk<KW, PER>(slots, first, cap, flags, out, status, s_rank[threadIdx.x >> 6], dsum, dxor, staged);
     digest_flush(out, dsum, dxor);
 }
 
@@ -509,12 +514,17 @@ int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipSt
     }
     const dim3 g((unsigned)grid_for(t->capacity, 16));
     uint4 *staged = (flags & HM_EXPORT_SORTED) && out->capacity ? sort_staging(*out) : nullptr;
-    if (t->k >= 32)
-        hipLaunchKernelGGL(k_export<2>, g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), t->capacity,
-                           flags, *out, t->status, staged);
-    else
-        hipLaunchKernelGGL(k_export<1>, g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), t->capacity,
-                           flags, *out, t->status, staged);
+#define LAUNCH_EXPORT(KW, PER)                                                                              \
+    hipLaunchKernelGGL((k_export<KW, PER>), g, dim3(kBlock), 0, s, reinterpret_cast<const Slot *>(t->slots), \
+                       t->capacity, flags, *out, t->status, staged)
+    if (t->k >= 32) {
+        if (staged) LAUNCH_EXPORT(2, kExportPerLane);
+        else LAUNCH_EXPORT(2, 32);
+    } else {
+        if (staged) LAUNCH_EXPORT(1, kExportPerLane);
+        else LAUNCH_EXPORT(1, 32);
+    }
+#undef LAUNCH_EXPORT
     HM_LAUNCH_CHECK("hm_export_table");
     if (flags & HM_EXPORT_SORTED) return sort_export(*out, 2 * t->k, s);
     return HM_OK;
