@@ -331,6 +331,29 @@ def test_capacity_errors_are_reported_not_wrong():
     assert_tables_equal(got, exp, "after retries")
 
 
+def test_owner_filtered_capacity_errors():
+    """A table that fills during owner-filtered pass 1 over fixed-length reads (the queued loop, whose
+    workgroups notice a full table at their next tile and stop together, then count what they had
+    queued) is reported as a capacity error; the retrying driver ends with the owner's exact table.
+    250k reads make about 2300 tiles, more than the workgroups of one launch, so workgroups reach a
+    later tile after the table has filled."""
+    ascii, qual, off = random_read_set(13, 250_000, 150, 150, genome_len=200_000)
+    exp = oracle.run(ascii, qual, off, 31, n_owners=2, owner=1, n_threads=8)
+    a = torch.from_numpy(ascii).cuda()
+    q = torch.from_numpy(qual).cuda()
+    p = kmer.pack_reads(a, q, read_len=150)
+    kc = kmer.KmerCounter(31, 256, 64, 1 << 24, n_owners=2, owner=1, max_probe=32)
+    out = kmer.Records(1 << 16)
+    kc.run([p], out)
+    assert kc.status() == abi.HM_ECAPACITY
+    assert int(kc.status_buf.item()) & abi.HM_ST_TABLE_FULL
+    # a 1024-slot start (bloom_words=1 keeps the table from growing to the planned filter's size)
+    got = kmer.analyze(ascii, qual, 31, read_len=150, n_owners=2, owner=1, capacity=1024, bloom_words=1,
+                       max_probe=64, retries=12)
+    assert_tables_equal(got, exp, "owner-filtered, after retries")
+    assert got["capacity"] > 1024
+
+
 def test_export_buffer_too_small():
     ascii, qual, off = random_read_set(13, 500, 150, 150)
     kc = kmer.KmerCounter(31, 1 << 16, 1 << 12, 1 << 18)
