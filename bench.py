@@ -188,10 +188,13 @@ def run_serving(args, dev, log):
     Scheduler(GpuBackend(51, device=dev), budget, 1).run([min(jobs, key=lambda j: j.n_bases)])
     for name, slots in (("continuous", args.serve_slots), ("fifo_one_at_a_time", 1)):
         torch.cuda.synchronize()
-        sch = Scheduler(GpuBackend(51, device=dev), budget, slots)
+        # continuous: the next jobs plan while others count; one at a time: nothing overlaps a job
+        sch = Scheduler(GpuBackend(51, device=dev), budget, slots,
+                        max_planning=args.serve_planners if slots > 1 else 1, plan_while_busy=slots > 1)
         recs = sch.run(jobs)
         res = summarize(recs, positions, sch.trace)
         res["slots"] = slots
+        res["planners"] = args.serve_planners if slots > 1 else 1
         out[name] = {x: (round(v, 3) if isinstance(v, float) else v) for x, v in res.items()}
         log("serving %s: p50 %.1f ms p99 %.1f ms, %.3g k-mers/s" % (name, res["p50_ms"], res["p99_ms"],
                                                                      res["kmers_per_s"]))
@@ -445,6 +448,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-planners", type=int, default=2, help="jobs planned at once in the continuous run")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

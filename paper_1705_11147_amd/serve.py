@@ -18,7 +18,8 @@ sizes each job the way the paper sizes its Bloom filter: before admission the
 job at the head of the queue is copied to the device, packed and run through
 the cardinality pass (HyperLogLog estimate and distinct sample) on its own
 stream, holding only those buffers; its exact footprint then decides when it
-is admitted.  One job plans at a time, and planned jobs keep FIFO order.
+is admitted.  Up to `max_planning` jobs plan at once, also while every slot
+is busy, and planned jobs keep FIFO order.
 
 The scheduler is independent of the device: `GpuBackend` runs jobs through
 the C ABI, and tests drive the same scheduler with a fake backend and a
@@ -74,11 +75,17 @@ class WallClock:
 class Scheduler:
     """FIFO admission by HBM footprint into at most `max_slots` concurrent jobs."""
 
-    def __init__(self, backend, budget_bytes: int, max_slots: int, poll_s: float = 0.0005):
+    def __init__(self, backend, budget_bytes: int, max_slots: int, poll_s: float = 0.0005, max_planning: int = 2,
+                 plan_while_busy: bool = True):
+        """max_planning: jobs planned at once (in arrival order).  plan_while_busy: plan also while
+        every slot is busy, so that the next job is ready when a slot frees (else a job is planned
+        only once a slot is free and no planned job waits: nothing overlaps a running job)."""
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.poll_s = poll_s
+        self.max_planning = max(1, int(max_planning))
+        self.plan_while_busy = bool(plan_while_busy)
         self.trace = []  # (time, queued, running, bytes in use)
 
     def run(self, jobs: list[Job], clock=None, max_retries: int = 3) -> list[Record]:
@@ -96,7 +103,7 @@ class Scheduler:
         queue: list[Job] = []
         running = {}                 # job id -> (handle, bytes)
         used = 0
-        planning = None              # (job, plan handle, bytes held) of the job being planned
+        planning = []                # [job, plan handle, bytes held] of the jobs being planned, oldest first
         ready = None                 # (job, plan handle, bytes held): planned, waiting for admission
         while nxt < len(order) or queue or running or planning or ready:
             now = clock.now()
@@ -120,24 +127,14 @@ class Scheduler:
                     r.done = clock.now()
                     r.status = 0 if status == "ok" else status
                     r.result = result
-            if planning is not None and be.planned(planning[1]):
-                j, h, pb = planning
+            # the oldest plan becomes ready when it is done (later ones wait their turn: FIFO)
+            if ready is None and planning and be.planned(planning[0][1]):
+                j, h, pb = planning.pop(0)
                 ready = (be.finish_plan(h), h, pb)
-                planning = None
             # admission: FIFO, head of line waits for memory
             while len(running) < self.max_slots:
                 if planner:
                     if ready is None:
-                        if planning is None and queue:  # plan the head of the queue
-                            j = queue[0]
-                            pb = be.plan_footprint(j)
-                            if used + pb > self.budget:
-                                break
-                            queue.pop(0)
-                            if np.isnan(recs[j.id].admitted):
-                                recs[j.id].admitted = clock.now()
-                            planning = (j, be.plan(j), pb)
-                            used += pb
                         break
                     j, h, pb = ready
                     b = be.footprint(j)
@@ -165,6 +162,29 @@ class Scheduler:
                     recs[j.id].admitted = clock.now()
                 running[j.id] = (be.start(j), b)
                 used += b
+            if planner and (self.plan_while_busy or (len(running) < self.max_slots and ready is None)):
+                # plan ahead, in arrival order, while the budget holds the plans' buffers and still
+                # leaves the ready job room to be admitted (a plan must never keep it waiting)
+                held = be.footprint(ready[0]) - ready[2] if ready is not None else 0
+                while len(planning) < self.max_planning and queue:
+                    j = queue[0]
+                    pb = be.plan_footprint(j)
+                    if used + max(held, 0) + pb > self.budget:
+                        break
+                    queue.pop(0)
+                    if np.isnan(recs[j.id].admitted):
+                        recs[j.id].admitted = clock.now()
+                    planning.append([j, be.plan(j), pb])
+                    used += pb
+                # nothing running and the ready job does not fit beside the later plans' buffers:
+                # give back the newest finished plan (its job goes back to the queue's front)
+                if ready is not None and not running and planning:
+                    rj, rh, rpb = ready
+                    if used - rpb + be.footprint(rj) > self.budget and be.planned(planning[-1][1]):
+                        j, h, pb = planning.pop()
+                        be.discard(h)
+                        used -= pb
+                        queue.insert(0, j)
             self.trace.append((now, len(queue), len(running), used))
             if running or queue or planning or ready:
                 clock.sleep(self.poll_s)

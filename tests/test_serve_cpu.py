@@ -140,11 +140,13 @@ class PlanningBackend(FakeBackend):
 
     def finish_plan(self, h):
         self.planning_now -= 1
+        h["finished"] = True
         j = h["job"]
         return Job(j.id, j.arrival, j.n_bases, j.read_len, 1, 1, None, dict(j.meta, planned=True))
 
     def discard(self, h):
-        pass
+        if not h.get("finished"):  # a plan given back before it became ready
+            self.planning_now -= 1
 
     def footprint(self, j):
         assert j.meta.get("planned"), "admitted before planning"
@@ -155,16 +157,17 @@ class PlanningBackend(FakeBackend):
         return super().start(j)
 
 
-def test_planning_before_admission():
+@pytest.mark.parametrize("max_planning", [1, 2])
+def test_planning_before_admission(max_planning):
     clock = VirtualClock()
     be = PlanningBackend(clock)
     jobs = [Job(i, 0.01 * i, 10 + (i % 3) * 5, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.005, "phase2": 3})
             for i in range(40)]
     jobs[7].meta["fail_once"] = True
-    sch = Scheduler(be, budget_bytes=120, max_slots=4, poll_s=1e-3)
+    sch = Scheduler(be, budget_bytes=120, max_slots=4, poll_s=1e-3, max_planning=max_planning)
     recs = sch.run(jobs, clock=clock)
     assert all(r.status == 0 for r in recs) and recs[7].retries == 1
-    assert be.max_planning == 1                      # one job plans at a time
+    assert be.max_planning == max_planning           # at most that many jobs plan at once (and it is reached)
     assert max(t[3] for t in sch.trace) <= 120        # planning buffers count against the budget
     first_start = {}
     for e in be.events:
@@ -175,6 +178,38 @@ def test_planning_before_admission():
     for e in be.events:                               # every start comes after that job's planning
         if e[0] == "start":
             assert any(p[0] == "plan" and p[1] == e[1] and p[2] <= e[2] for p in be.events)
+
+
+def test_plan_ahead_never_blocks_the_ready_job():
+    """Job 1 starts planning beside job 0; once planned, job 0 needs more than the budget leaves beside
+    job 1's planning buffers, and nothing runs that could free memory.  The scheduler gives job 1's
+    plan back (job 1 returns to the queue's front), admits job 0, and plans job 1 again once it fits."""
+    clock = VirtualClock()
+    be = PlanningBackend(clock)
+    jobs = [Job(0, 0.0, 40, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.01, "phase2": 2}),
+            Job(1, 0.0, 30, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.01, "phase2": 2}),
+            Job(2, 0.001, 10, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.01, "phase2": 2})]
+    sch = Scheduler(be, budget_bytes=100, max_slots=4, poll_s=1e-3, max_planning=2)
+    recs = sch.run(jobs, clock=clock)
+    assert all(r.status == 0 for r in recs)
+    assert max(t[3] for t in sch.trace) <= 100
+    starts = [e for e in be.events if e[0] == "start"]
+    assert [e[1] for e in starts] == [0, 1, 2]                   # admitted in arrival order
+    assert sum(1 for e in be.events if e[0] == "plan" and e[1] == 1) == 2  # job 1 was planned twice
+
+
+def test_one_at_a_time_overlaps_nothing():
+    """With one slot and plan_while_busy off, a job is planned only after the previous one has
+    finished: planning never overlaps a running job (the serial baseline)."""
+    clock = VirtualClock()
+    be = PlanningBackend(clock)
+    jobs = [Job(i, 0.0, 10, 150, 1, 1, None, {"dur": 0.02, "plan_dur": 0.005, "phase2": 2}) for i in range(6)]
+    sch = Scheduler(be, budget_bytes=1000, max_slots=1, poll_s=1e-3, max_planning=1, plan_while_busy=False)
+    recs = sch.run(jobs, clock=clock)
+    assert all(r.status == 0 for r in recs)
+    plans = {e[1]: e[2] for e in be.events if e[0] == "plan"}
+    for i in range(1, len(jobs)):
+        assert plans[i] >= recs[i - 1].done - 1e-9, (i, plans[i], recs[i - 1].done)
 
 
 def test_planned_job_too_large_is_rejected():
