@@ -181,7 +181,14 @@ __global__ __launch_bounds__(kBlock) void k_pack_batch(const BatchHeader *hdr, c
     }
 }
 
-__device__ __forceinline__ PassArgs pass_args(const BatchHeader *hdr, const BatchDesc &d) {
+// A set's descriptor is written by the host before the launch and never by a
+// kernel, so it is read through the constant address space: the compiler may
+// then load its fields again where needed instead of holding them in
+// registers (the persistent kernel fits eight waves per SIMD without spills).
+typedef const __attribute__((address_space(4))) BatchDesc ConstDesc;
+
+__device__ __forceinline__ PassArgs pass_args(const BatchHeader *hdr, const BatchDesc &dg) {
+    const ConstDesc &d = *(ConstDesc *)&dg;
     PassArgs a;
     a.b2 = d.b2;
     a.nm = d.nm;
@@ -300,10 +307,10 @@ __global__ __launch_bounds__(kBlock) void k_export_batch(const BatchHeader *hdr,
     }
 }
 
-// 6 waves per SIMD: the budget that holds every pass-1/pass-2 value in
-// registers without spilling (a 7-wave budget spills and measured the same).
+// Eight waves per SIMD, as the plain pass-1 kernel: both passes' values fit
+// the 64-register budget once the set descriptors are constant loads.
 template <int KW, bool CHECKED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_batch(BatchHeader *hdr, const BatchDesc *sets, const int64_t *item_start,
                                                   const int32_t *group, uint32_t *done) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
@@ -343,10 +350,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
                         break;
                     }
                 }
+                // one agent-scope acquire per block (on this GPU it invalidates the XCD's L2);
+                // the barrier below orders the other threads' reads after it
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 s_ok = ok;
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // acquire for every thread of the block
             if (s_ok) item_pass2<KW, CHECKED>(pass_args(hdr, d), j, hdr->list_per_item);
         } else {
             const PassArgs a = pass_args(hdr, d);
@@ -356,10 +365,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
             }
             item_pass1<KW, CHECKED>(a, d.rpt, j, s_b2, s_nm, s_hq, cur);
         }
-        // release: this item's writes before the completion count
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // release: the barrier orders every thread's writes of this item before
+        // thread 0's release add, so one agent-scope release (an L2 write-back
+        // on this GPU) per item publishes them, not one per wave
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(done + phase * S + s, 1u);
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(done + phase * S + s, 1u, __ATOMIC_RELEASE, AGT);
     }
 }
 
