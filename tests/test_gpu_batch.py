@@ -58,10 +58,12 @@ def test_batched_equals_plain_equals_oracle(k):
     assert len(batched[-1]["count"]) == 0 and len(batched[-2]["count"]) == 0
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("set_major", [2, 1])  # 1: pass-2 items wait on their own set's pass 1
+def test_graph_replays_match_eager(set_major):
     ws = synth.batched_sets(n_sets=8, scale=0.01)
     specs, host = make_specs(ws)
-    b = Batch(specs, 31, tuning=Tuning(blocks_per_cu=8, tile_bases=8192, list_per_item=2048, slots_per_item=4096))
+    b = Batch(specs, 31, tuning=Tuning(blocks_per_cu=8, tile_bases=8192, list_per_item=2048, slots_per_item=4096,
+                                       set_major=set_major))
     b.launch()
     eager = b.digests()
     b.capture()
@@ -81,7 +83,10 @@ def test_output_independent_of_tuning():
     specs, _ = make_specs(ws)
     ref = None
     for tu in (Tuning(), Tuning(blocks_per_cu=1, tile_bases=1024, list_per_item=256, slots_per_item=2048),
-               Tuning(blocks_per_cu=16, table_load=0.6, bloom_bits=6, n_hash=1)):
+               Tuning(blocks_per_cu=16, table_load=0.6, bloom_bits=6, n_hash=1),
+               # lag 0: each set's pass-2 items follow its own pass 1 and wait on its tail (the
+               # release/acquire path); phase-major: every pass 1 first
+               Tuning(set_major=1, tile_bases=4096, list_per_item=4096), Tuning(set_major=0)):
         for in_table in (True, False):
             b = Batch(specs, 31, tuning=tu, bloom_in_table=in_table)
             b.launch()
