@@ -436,7 +436,7 @@ typedef struct {
 /* Launch shape of the persistent kernel (chosen by an autotuner). */
 typedef struct {
     int32_t blocks_per_cu;  /* persistent grid = CUs x blocks_per_cu, 1..16 */
-    int32_t tile_bases;     /* bases of reads per pass-1 work item, 1024..16384 */
+    int32_t tile_bases;     /* bases of reads per pass-1 work item, 1024..262144 (staged 16384 at a time) */
     int32_t list_per_item;  /* first-occurrence entries per pass-2 work item, >= 256 */
     int32_t slots_per_item; /* table slots per classify+export work item, multiple of 2048 */
     int32_t set_major;      /* 0: all pass-1 items first, then all pass-2 items; n >= 1: set by set, each

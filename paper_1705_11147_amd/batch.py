@@ -20,7 +20,7 @@ from .kmer import KmerCounter, Records, next_pow2
 @dataclass
 class Tuning:
     blocks_per_cu: int = 8
-    tile_bases: int = 16384
+    tile_bases: int = 65536      # bases of reads per pass-1 item (staged in LDS 16384 at a time)
     list_per_item: int = 65536
     slots_per_item: int = 65536
     table_load: float = 0.45     # sizing: expected kept k-mers / capacity

@@ -231,31 +231,38 @@ __device__ void item_pass1(const PassArgs &a, int32_t rpt, int64_t j, uint64_t *
     const int L = a.read_len, k = a.k, W = L - k + 1;
     const int64_t r0 = j * rpt;
     const int64_t r1 = min(r0 + (int64_t)rpt, a.n_reads);
-    const int64_t base0 = r0 * L, base1 = r1 * L;
-    const int64_t org = base0 & ~(int64_t)63;
-    const int64_t mw0 = org >> 6;
-    const int nmw = (int)(((base1 + 63) >> 6) - mw0) + 2;
-    for (int i = threadIdx.x; i < nmw; i += kBlock) {
-        s_nm[i] = a.nm[mw0 + i];
-        s_hq[i] = a.hq[mw0 + i];
-    }
-    for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
-    __syncthreads();
-    const Words w{s_b2, s_nm, s_hq};
-    const int total = (int)(r1 - r0) * W;
+    // the item's reads are staged in LDS kTileBases bases at a time (read_len <= kTileBases - 64, checked
+    // by the host, so a staged run plus its 64-base alignment fits the tile arrays)
+    const int64_t sub = kTileBases / L;
     Stats st = {};
-    for (int f0 = 0; f0 < total; f0 += kBlock) {
-        if (aborted(a.status)) break;
-        const int f = f0 + threadIdx.x;
-        Occ o{0, 0, 4, 4};
-        bool act = false;
-        if (f < total) {
-            const int r = f / W;
-            const int pos = f - r * W;
-            const int64_t rb = (r0 + r) * L - org;
-            act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
+    for (int64_t s0 = r0; s0 < r1; s0 += sub) {
+        const int64_t s1 = min(s0 + sub, r1);
+        if (s0 != r0) __syncthreads();  // the previous run's readers are done
+        const int64_t base0 = s0 * L, base1 = s1 * L;
+        const int64_t org = base0 & ~(int64_t)63;
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)(((base1 + 63) >> 6) - mw0) + 2;
+        for (int i = threadIdx.x; i < nmw; i += kBlock) {
+            s_nm[i] = a.nm[mw0 + i];
+            s_hq[i] = a.hq[mw0 + i];
         }
-        pass1_occ<KW, CHECKED>(a, act, o, cur, st);
+        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        const Words w{s_b2, s_nm, s_hq};
+        const int total = (int)(s1 - s0) * W;
+        for (int f0 = 0; f0 < total; f0 += kBlock) {
+            if (aborted(a.status)) break;
+            const int f = f0 + threadIdx.x;
+            Occ o{0, 0, 4, 4};
+            bool act = false;
+            if (f < total) {
+                const int r = f / W;
+                const int pos = f - r * W;
+                const int64_t rb = (s0 + r) * L - org;
+                act = extract(w, rb + pos, rb, rb + L, k, a.forward_only, a.n_owners, a.owner, o);
+            }
+            pass1_occ<KW, CHECKED>(a, act, o, cur, st);
+        }
     }
     (void)st;  // per-item event counters are not collected in the batched form
 }
@@ -393,7 +400,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
     if ((uintptr_t)work & 255) return fail(HM_EINVAL, "batch: work must be 256-byte aligned");
     const hm_batch_tuning_t tu = *tuning;
     if (tu.blocks_per_cu < 1 || tu.blocks_per_cu > 16) return fail(HM_EINVAL, "batch: blocks_per_cu 1..16");
-    if (tu.tile_bases < 1024 || tu.tile_bases > kTileBases) return fail(HM_EINVAL, "batch: tile_bases 1024..16384");
+    if (tu.tile_bases < 1024 || tu.tile_bases > 16 * kTileBases) return fail(HM_EINVAL, "batch: tile_bases 1024..262144");
     if (tu.list_per_item < 256) return fail(HM_EINVAL, "batch: list_per_item >= 256");
     if (tu.slots_per_item < 2048 || tu.slots_per_item % 2048) return fail(HM_EINVAL, "batch: slots_per_item % 2048");
     if (export_flags & ~(HM_EXPORT_UU_ONLY | HM_EXPORT_ALL)) return fail(HM_EINVAL, "batch: unknown export flags");

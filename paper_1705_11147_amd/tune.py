@@ -24,7 +24,7 @@ from .batch import Batch, SetSpec, Tuning
 LAUNCH_SPACE = {
     "set_major": [2, 1, 3, 0],
     "blocks_per_cu": [4, 8, 12],
-    "tile_bases": [4096, 8192, 16384],
+    "tile_bases": [16384, 32768, 65536, 131072],
     "list_per_item": [16384, 65536],
     "slots_per_item": [32768, 131072],
 }

@@ -86,7 +86,8 @@ def test_output_independent_of_tuning():
                Tuning(blocks_per_cu=16, table_load=0.6, bloom_bits=6, n_hash=1),
                # lag 0: each set's pass-2 items follow its own pass 1 and wait on its tail (the
                # release/acquire path); phase-major: every pass 1 first
-               Tuning(set_major=1, tile_bases=4096, list_per_item=4096), Tuning(set_major=0)):
+               Tuning(set_major=1, tile_bases=4096, list_per_item=4096), Tuning(set_major=0),
+               Tuning(tile_bases=262144), Tuning(tile_bases=16384 + 150)):  # items of many staged runs, ragged
         for in_table in (True, False):
             b = Batch(specs, 31, tuning=tu, bloom_in_table=in_table)
             b.launch()
