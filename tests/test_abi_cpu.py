@@ -216,3 +216,30 @@ def test_contigs_scratch_and_rejections(L):
     c4 = abi.Contigs(None, 100, 8, 10, 8, 8, 256, w)
     assert L.hm_contigs(ctypes.byref(e), 21, 0, ctypes.byref(c4), None) == abi.HM_EINVAL  # no seq
     assert abi.last_error()
+
+
+@pytest.mark.parametrize("bad", [dict(blocks_per_cu=0), dict(blocks_per_cu=17), dict(tile_bases=1023),
+                                 dict(tile_bases=262145), dict(list_per_item=255), dict(slots_per_item=3000),
+                                 dict(set_major=65)])
+def test_batch_tuning_rejections(L, bad):
+    """hm_batch_prepare checks the tuning on the host before any device call."""
+    tu = dict(blocks_per_cu=8, tile_bases=65536, list_per_item=65536, slots_per_item=65536, set_major=2)
+    tu.update(bad)
+    sets = (abi.BatchSet * 1)()
+    plan = abi.BatchPlan()
+    work = 1 << 20  # never dereferenced: the call fails first
+    rc = L.hm_batch_prepare(sets, 1, ctypes.byref(P()), 0, 20, 0, ctypes.byref(abi.BatchTuning(**tu)), work,
+                            L.hm_batch_work_bytes(1), ctypes.byref(plan), None)
+    assert rc == abi.HM_EINVAL and abi.last_error()
+
+
+@pytest.mark.parametrize("read_len,tile_bases", [(2000, 1024), (16321, 262144)])
+def test_batch_read_length_rejections(L, read_len, tile_bases):
+    """A read longer than a pass-1 item, or than one LDS run of an item, is refused on the host."""
+    sets = (abi.BatchSet * 1)()
+    sets[0].n_reads, sets[0].read_len = 10, read_len
+    tu = abi.BatchTuning(8, tile_bases, 65536, 65536, 2)
+    plan = abi.BatchPlan()
+    rc = L.hm_batch_prepare(sets, 1, ctypes.byref(P()), 0, 20, 0, ctypes.byref(tu), 1 << 20,
+                            L.hm_batch_work_bytes(1), ctypes.byref(plan), None)
+    assert rc == abi.HM_EINVAL and "read_len" in abi.last_error()
