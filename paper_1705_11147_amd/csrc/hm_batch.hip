@@ -6,12 +6,16 @@
 //   1. k_fill_regions clears every set's table, filter, counters;
 //   2. k_pack_batch packs every set's reads;
 //   3. k_batch, a persistent kernel.  Its blocks take work items from one
-//      atomic ticket.  Items of a set are its pass-1 read tiles followed by
-//      its pass-2 first-occurrence list ranges; sets run larger first, either
-//      one after another (set-major: only one or two sets' tables are live
-//      at a time, so they stay in the memory-side cache) or phase by phase.  A pass-2 item of set s waits until every pass-1 item of s has
-//      finished: per-set counters, release (fence + atomic add) by the
-//      finisher, acquire (atomic load + fence) by the waiter.  A waiter only
+//      atomic ticket.  Items of a set are its pass-1 runs of reads (staged in
+//      LDS one tile at a time) followed by its pass-2 first-occurrence list
+//      ranges; sets run larger first, either one after another (set-major:
+//      only one or two sets' tables are live at a time, so they stay in the
+//      memory-side cache) or phase by phase.  A pass-2 item of set s waits
+//      until every pass-1 item of s has finished: per-set counters, one
+//      release atomic add per finished item (thread 0, after the workgroup
+//      barrier), one acquire by the waiting block's thread 0 (an agent-scope
+//      release or acquire is an L2 write-back or invalidate of the XCD on
+//      this GPU, so each is made once per item, not once per wave).  A waiter only
 //      ever waits on items with smaller tickets, which running blocks already
 //      hold, so the schedule cannot deadlock; the wait is still bounded in
 //      time and reports HM_ST_TIMEOUT instead of hanging;
