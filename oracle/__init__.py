@@ -23,6 +23,7 @@ _SO = os.path.join(_HERE, "libkmer_oracle.so")
 FORWARD_ONLY = 1
 KEEP_ALL = 2
 SPLIT_READS = 4
+SORT_COUNT = 8
 
 CLS_FORK = 4
 CLS_X = 5
@@ -70,6 +71,14 @@ def lib():
         L.orc_run.restype = ctypes.c_int64
         L.orc_fetch.argtypes = [ctypes.c_void_p, ctypes.c_uint32] + [ctypes.c_void_p] * 7
         L.orc_fetch.restype = None
+        L.orc_acc_new.argtypes = [ctypes.POINTER(OrcParams)]
+        L.orc_acc_new.restype = ctypes.c_void_p
+        L.orc_acc_add.argtypes = [ctypes.c_void_p, u8p, u8p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]
+        L.orc_acc_add.restype = ctypes.c_int
+        L.orc_acc_finish.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_acc_finish.restype = ctypes.c_int64
+        L.orc_acc_free.argtypes = [ctypes.c_void_p]
+        L.orc_acc_free.restype = None
         L.orc_positions.argtypes = [ctypes.c_void_p]
         L.orc_positions.restype = ctypes.c_int64
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -98,10 +107,81 @@ def lib():
     return _LIB
 
 
+def _params(k, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard, qual_offset, forward_only, keep_all,
+            n_threads, split_reads, sort_count=False):
+    ext_min = min_depth if ext_min is None else ext_min
+    p = OrcParams(k, qual_offset, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard,
+                  (FORWARD_ONLY if forward_only else 0) | (KEEP_ALL if keep_all else 0) |
+                  (SPLIT_READS if split_reads else 0) | (SORT_COUNT if sort_count else 0), n_threads)
+    return p, ext_min
+
+
+def _fetch(h, n, ext_min) -> dict:
+    L = lib()
+    out = {"key_hi": np.empty(n, np.uint64), "key_lo": np.empty(n, np.uint64), "count": np.empty(n, np.uint32),
+           "tl": np.empty((n, 4), np.uint32), "tr": np.empty((n, 4), np.uint32), "cls_l": np.empty(n, np.uint8),
+           "cls_r": np.empty(n, np.uint8)}
+    try:
+        L.orc_fetch(h, ext_min, *(out[x].ctypes.data for x in ("key_hi", "key_lo", "count", "tl", "tr", "cls_l",
+                                                             "cls_r")))
+        out["positions"] = int(L.orc_positions(h))
+    finally:
+        L.orc_free(h)
+    return out
+
+
+class Accumulator:
+    """The oracle over reads given in batches (e.g. a read set too large to hold on the host at
+    once): add() counts a batch into the same state, finish() filters and sorts.  By additivity
+    of unfiltered tables the result equals run() over the concatenated batches.  Same keyword
+    arguments as run(); 'seconds' adds up the time spent in add() and finish()."""
+
+    def __init__(self, k: int, qcut: int = 20, min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1,
+                 owner: int = 0, n_shards: int = 1, shard: int = 0, qual_offset: int = 0, forward_only: bool = False,
+                 keep_all: bool = False, n_threads: int = 1, split_reads: bool = False, sort_count: bool = False):
+        p, self.ext_min = _params(k, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard, qual_offset,
+                                  forward_only, keep_all, n_threads, split_reads, sort_count)
+        self._h = lib().orc_acc_new(ctypes.byref(p))
+        if not self._h:
+            raise ValueError("oracle: bad parameters")
+        self.seconds = 0.0
+
+    def add(self, ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray):
+        ascii = np.ascontiguousarray(ascii, dtype=np.uint8)
+        qual = np.ascontiguousarray(qual, dtype=np.uint8)
+        read_off = np.ascontiguousarray(read_off, dtype=np.int64)
+        if read_off[-1] > ascii.size or read_off[-1] > qual.size:
+            raise ValueError("read offsets exceed the base arrays")
+        t0 = time.perf_counter()
+        rc = lib().orc_acc_add(self._h, ascii.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               qual.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                               read_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), read_off.size - 1)
+        self.seconds += time.perf_counter() - t0
+        if rc != 0:
+            raise ValueError("oracle failed with code %d" % rc)
+
+    def finish(self) -> dict:
+        h = ctypes.c_void_p()
+        t0 = time.perf_counter()
+        n = lib().orc_acc_finish(self._h, ctypes.byref(h))
+        self._h = None
+        self.seconds += time.perf_counter() - t0
+        if n < 0:
+            raise ValueError("oracle failed with code %d" % n)
+        out = _fetch(h, n, self.ext_min)
+        out["seconds"] = self.seconds
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_acc_free(self._h)
+            self._h = None
+
+
 def run(ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray, k: int, qcut: int = 20, min_depth: int = 2,
         ext_min: int | None = None, n_owners: int = 1, owner: int = 0, n_shards: int = 1, shard: int = 0,
         qual_offset: int = 0, forward_only: bool = False, keep_all: bool = False, n_threads: int = 1,
-        split_reads: bool = False) -> dict:
+        split_reads: bool = False, sort_count: bool = False) -> dict:
     """Oracle table as a dict of numpy arrays sorted by (key_hi, key_lo):
     key_hi, key_lo (uint64), count (uint32), tl, tr (uint32, n x 4),
     cls_l, cls_r (uint8: 0..3 unique base, 4 fork, 5 none), plus
@@ -112,10 +192,8 @@ def run(ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray, k: int, qcut:
     n_reads = read_off.size - 1
     if read_off[-1] > ascii.size or read_off[-1] > qual.size:
         raise ValueError("read offsets exceed the base arrays")
-    ext_min = min_depth if ext_min is None else ext_min
-    p = OrcParams(k, qual_offset, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard,
-                  (FORWARD_ONLY if forward_only else 0) | (KEEP_ALL if keep_all else 0) |
-                  (SPLIT_READS if split_reads else 0), n_threads)
+    p, ext_min = _params(k, qcut, min_depth, ext_min, n_owners, owner, n_shards, shard, qual_offset, forward_only,
+                         keep_all, n_threads, split_reads, sort_count)
     h = ctypes.c_void_p()
     L = lib()
     t0 = time.perf_counter()
@@ -125,15 +203,7 @@ def run(ascii: np.ndarray, qual: np.ndarray, read_off: np.ndarray, k: int, qcut:
     secs = time.perf_counter() - t0
     if n < 0:
         raise ValueError("oracle failed with code %d" % n)
-    out = {"key_hi": np.empty(n, np.uint64), "key_lo": np.empty(n, np.uint64), "count": np.empty(n, np.uint32),
-           "tl": np.empty((n, 4), np.uint32), "tr": np.empty((n, 4), np.uint32), "cls_l": np.empty(n, np.uint8),
-           "cls_r": np.empty(n, np.uint8)}
-    try:
-        L.orc_fetch(h, ext_min, *(out[x].ctypes.data for x in ("key_hi", "key_lo", "count", "tl", "tr", "cls_l",
-                                                             "cls_r")))
-        out["positions"] = int(L.orc_positions(h))
-    finally:
-        L.orc_free(h)
+    out = _fetch(h, n, ext_min)
     out["seconds"] = secs
     return out
 

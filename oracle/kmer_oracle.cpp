@@ -41,14 +41,24 @@
  *     separately seeded partition hash is t and scans every read; the union
  *     over threads is the table by the owner-partition identity;
  *   - read-partitioned (ORC_SPLIT_READS): thread t counts reads
- *     [t*N/T, (t+1)*N/T) into its own map and the maps are summed key by key
- *     before the depth filter, by additivity of unfiltered tables.
+ *     [t*N/T, (t+1)*N/T) into its own maps, one per key partition, and the
+ *     maps are summed key by key before the depth filter, by additivity of
+ *     unfiltered tables (thread q sums partition q).
+ *   - sort-counted (ORC_SORT_COUNT): thread t writes one record (key, left,
+ *     right) per kept window of reads [t*N/T, (t+1)*N/T) into a list per key
+ *     partition; thread q then sorts partition q's records by key and reads
+ *     each run of equal keys as one k-mer: its count is the run's length and
+ *     its tallies count the run's left and right bases.  The same definition,
+ *     with a sort in place of the map (no random access per window).
+ * Reads may also come in batches (orc_acc_*): counting batch after batch
+ * into the same state is the table of their union, by the same additivity.
  * Output records are sorted by key.
  */
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -104,7 +114,7 @@ typedef std::unordered_map<u128, Tally, KeyHash> Map;
 
 extern "C" {
 
-enum { ORC_FORWARD_ONLY = 1, ORC_KEEP_ALL = 2, ORC_SPLIT_READS = 4 };
+enum { ORC_FORWARD_ONLY = 1, ORC_KEEP_ALL = 2, ORC_SPLIT_READS = 4, ORC_SORT_COUNT = 8 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EOVERFLOW = -2 };
 
 typedef struct {
@@ -150,8 +160,13 @@ static uint8_t classify(const uint32_t t[4], uint32_t ext_min) {
     return 4;
 }
 
+/* Count the windows of reads [0, n_reads) into `maps`.  n_parts > 1: keep
+ * only the keys of partition `part` (into maps[0]).  Otherwise, with several
+ * maps, file each key under its partition: maps[partition of the key]. */
 static int scan_reads(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
-                      const orc_params_t *p, uint32_t n_parts, uint32_t part, Map &m, int64_t *positions) {
+                      const orc_params_t *p, uint32_t n_parts, uint32_t part, std::vector<Map> &maps,
+                      int64_t *positions) {
+    const uint32_t n_file = (uint32_t)maps.size();
     const int k = p->k;
     const u128 mask = (k == 64) ? ~(u128)0 : (((u128)1 << (2 * k)) - 1);
     int64_t npos = 0;
@@ -185,7 +200,10 @@ static int scan_reads(const uint8_t *ascii, const uint8_t *qual, const int64_t *
             const uint64_t hi = (uint64_t)(key >> 64), lo = (uint64_t)key;
             if (p->n_owners > 1 && orc_owner(hi, lo, p->n_owners) != p->owner) continue;
             if (p->n_shards > 1 && orc_shard(hi, lo, p->n_shards) != p->shard) continue;
-            if (n_parts > 1 && part_of(key_hash(hi, lo, kThreadSeed), n_parts) != part) continue;
+            const uint32_t kpart = (n_parts > 1 || n_file > 1)
+                                       ? part_of(key_hash(hi, lo, kThreadSeed), n_parts > 1 ? n_parts : n_file) : 0;
+            if (n_parts > 1 && kpart != part) continue;
+            Map &m = maps[n_parts > 1 ? 0 : kpart];
             int left = -1, right = -1;
             if (is_fwd) {
                 if (hq(i - 1)) left = code_of(s[i - 1]);
@@ -205,67 +223,204 @@ static int scan_reads(const uint8_t *ascii, const uint8_t *qual, const int64_t *
     return ORC_OK;
 }
 
-/* Run the oracle.  read_off has n_reads + 1 entries (base offsets).  Returns
- * the number of output records (>= 0) or a negative error; *handle receives
- * the result for orc_fetch / orc_free. */
-int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
-                const orc_params_t *p, void **handle) {
-    *handle = nullptr;
-    if (!p || p->k < 1 || p->k > 63) return ORC_EINVAL;
-    if (!(p->flags & ORC_FORWARD_ONLY) && (p->k % 2) == 0) return ORC_EINVAL;
-    if (p->n_owners < 1 || p->owner >= p->n_owners) return ORC_EINVAL;
-    if (p->n_shards < 1 || p->shard >= p->n_shards) return ORC_EINVAL;
-    if (n_reads < 0) return ORC_EINVAL;
-    const uint32_t T = p->n_threads > 1 ? (uint32_t)p->n_threads : 1u;
-    const bool split_reads = (p->flags & ORC_SPLIT_READS) != 0;
-    std::vector<Map> maps(T);
-    std::vector<int> rcs(T, 0);
-    std::vector<int64_t> npos(T, 0);
-    auto work = [&](uint32_t t) {
-        if (split_reads) {  // reads [r0, r1) into this thread's own map, every key kept
-            const int64_t r0 = n_reads * t / T, r1 = n_reads * (t + 1) / T;
-            rcs[t] = scan_reads(ascii, qual, read_off + r0, r1 - r0, p, 1, 0, maps[t], &npos[t]);
-        } else {
-            rcs[t] = scan_reads(ascii, qual, read_off, n_reads, p, T, t, maps[t], &npos[t]);
+/* One kept window for the sort-counted scheme: its key and its extension
+ * bases (-1: none). */
+struct OccRec {
+    uint64_t hi, lo;
+    int8_t left, right;
+};
+
+/* The windows of reads [0, n_reads) as records, each filed under its key
+ * partition (recs.size() partitions), with the same filters and extension
+ * rule as scan_reads. */
+static void scan_records(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
+                         const orc_params_t *p, std::vector<std::vector<OccRec>> &recs, int64_t *positions) {
+    const uint32_t n_file = (uint32_t)recs.size();
+    const int k = p->k;
+    const u128 mask = (((u128)1 << (2 * k)) - 1);
+    int64_t npos = 0;
+    for (int64_t r = 0; r < n_reads; ++r) {
+        const int64_t b = read_off[r];
+        const int64_t L = read_off[r + 1] - b;
+        const uint8_t *s = ascii + b;
+        const uint8_t *q = qual + b;
+        auto hq = [&](int64_t j) -> bool {
+            return j >= 0 && j < L && code_of(s[j]) < 4 && ((int)q[j] - p->qual_offset) >= p->qcut;
+        };
+        u128 fwd = 0, rc = 0;
+        int64_t run = 0;
+        for (int64_t j = 0; j < L; ++j) {
+            const int c = code_of(s[j]);
+            if (c == 4) {
+                run = 0;
+                fwd = rc = 0;
+                continue;
+            }
+            fwd = ((fwd << 2) | (u128)c) & mask;
+            rc = (rc >> 2) | ((u128)(3 - c) << (2 * (k - 1)));
+            if (++run < k) continue;
+            ++npos;
+            const int64_t i = j - k + 1;
+            const bool is_fwd = (p->flags & ORC_FORWARD_ONLY) != 0 || fwd <= rc;
+            const u128 key = is_fwd ? fwd : rc;
+            const uint64_t hi = (uint64_t)(key >> 64), lo = (uint64_t)key;
+            if (p->n_owners > 1 && orc_owner(hi, lo, p->n_owners) != p->owner) continue;
+            if (p->n_shards > 1 && orc_shard(hi, lo, p->n_shards) != p->shard) continue;
+            OccRec o{hi, lo, -1, -1};
+            if (is_fwd) {
+                if (hq(i - 1)) o.left = (int8_t)code_of(s[i - 1]);
+                if (hq(i + k)) o.right = (int8_t)code_of(s[i + k]);
+            } else {
+                if (hq(i + k)) o.left = (int8_t)(3 - code_of(s[i + k]));
+                if (hq(i - 1)) o.right = (int8_t)(3 - code_of(s[i - 1]));
+            }
+            const uint32_t kpart = n_file > 1 ? part_of(key_hash(hi, lo, kThreadSeed), n_file) : 0;
+            recs[kpart].push_back(o);
         }
-    };
+    }
+    *positions = npos;
+}
+
+/* The counting state of a run, which may take several read batches (by
+ * additivity of unfiltered tables, counting batch after batch into the same
+ * maps gives the table of their union).  maps[t][q]: thread t's counts of the
+ * keys of partition q (q = 0 only in the key-partitioned scheme, where thread
+ * t keeps partition t itself; in the read-partitioned scheme thread t files
+ * each key of its reads under its partition, and at the end thread q sums
+ * partition q over all threads, so the merge runs in parallel). */
+struct orc_acc {
+    orc_params_t p;
+    uint32_t T;
+    bool split;
+    bool sorted; /* ORC_SORT_COUNT: recs[t][q] instead of maps */
+    std::vector<std::vector<Map>> maps;
+    std::vector<std::vector<std::vector<OccRec>>> recs;
+    int64_t positions = 0;
+};
+
+static void run_threads(uint32_t T, const std::function<void(uint32_t)> &work) {
     if (T == 1) {
         work(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (uint32_t t = 0; t < T; ++t) th.emplace_back(work, t);
+    for (auto &x : th) x.join();
+}
+
+/* Count reads [0, n_reads) of one batch into the state. */
+static int acc_add(orc_acc *a, const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads) {
+    const uint32_t T = a->T;
+    std::vector<int> rcs(T, 0);
+    std::vector<int64_t> npos(T, 0);
+    if (a->sorted) {
+        run_threads(T, [&](uint32_t t) {
+            const int64_t r0 = n_reads * t / T, r1 = n_reads * (t + 1) / T;
+            scan_records(ascii, qual, read_off + r0, r1 - r0, &a->p, a->recs[t], &npos[t]);
+        });
+        for (auto x : npos) a->positions += x;
+        return ORC_OK;
+    }
+    if (a->split) {
+        /* reads [t*N/T, (t+1)*N/T) into thread t's maps, one map per key partition */
+        run_threads(T, [&](uint32_t t) {
+            const int64_t r0 = n_reads * t / T, r1 = n_reads * (t + 1) / T;
+            rcs[t] = scan_reads(ascii, qual, read_off + r0, r1 - r0, &a->p, 1, 0, a->maps[t], &npos[t]);
+        });
     } else {
-        std::vector<std::thread> th;
-        for (uint32_t t = 0; t < T; ++t) th.emplace_back(work, t);
-        for (auto &x : th) x.join();
+        /* thread t scans every read and keeps the keys of partition t */
+        run_threads(T, [&](uint32_t t) {
+            rcs[t] = scan_reads(ascii, qual, read_off, n_reads, &a->p, T, t, a->maps[t], &npos[t]);
+        });
     }
     for (uint32_t t = 0; t < T; ++t)
         if (rcs[t] != ORC_OK) return rcs[t];
-    if (split_reads && T > 1) {  // sum the per-thread tables key by key
-        for (uint32_t t = 1; t < T; ++t) {
-            for (auto &kv : maps[t]) {
-                Tally &d = maps[0][kv.first];
-                if ((uint64_t)d.cnt + kv.second.cnt > UINT32_MAX) return ORC_EOVERFLOW;
-                d.cnt += kv.second.cnt;
-                for (int b = 0; b < 4; ++b) {
-                    d.tl[b] += kv.second.tl[b];
-                    d.tr[b] += kv.second.tr[b];
+    a->positions += a->split ? [&] { int64_t s = 0; for (auto x : npos) s += x; return s; }() : npos[0];
+    return ORC_OK;
+}
+
+/* Sum the partitions over threads (read-partitioned scheme), apply the depth
+ * filter and sort by key. */
+static int64_t acc_finish(orc_acc *a, void **handle) {
+    const uint32_t T = a->T;
+    std::vector<int> rcs(T, 0);
+    if (a->split && T > 1) {
+        run_threads(T, [&](uint32_t q) {
+            Map &dst = a->maps[0][q];
+            for (uint32_t t = 1; t < T; ++t) {
+                for (auto &kv : a->maps[t][q]) {
+                    Tally &d = dst[kv.first];
+                    if ((uint64_t)d.cnt + kv.second.cnt > UINT32_MAX) {
+                        rcs[q] = ORC_EOVERFLOW;
+                        return;
+                    }
+                    d.cnt += kv.second.cnt;
+                    for (int b = 0; b < 4; ++b) {
+                        d.tl[b] += kv.second.tl[b];
+                        d.tr[b] += kv.second.tr[b];
+                    }
                 }
+                Map().swap(a->maps[t][q]);
             }
-            Map().swap(maps[t]);
+        });
+        for (uint32_t q = 0; q < T; ++q)
+            if (rcs[q] != ORC_OK) return rcs[q];
+    }
+    const bool keep_all = (a->p.flags & ORC_KEEP_ALL) != 0;
+    std::vector<std::pair<u128, Tally>> recs;
+    if (a->sorted) {
+        /* thread q: partition q's records from every thread, sorted by key; a run of equal keys is one
+           k-mer, counted and tallied over the run */
+        std::vector<std::vector<std::pair<u128, Tally>>> out(T);
+        run_threads(T, [&](uint32_t q) {
+            std::vector<OccRec> v;
+            size_t n = 0;
+            for (uint32_t t = 0; t < T; ++t) n += a->recs[t][q].size();
+            v.reserve(n);
+            for (uint32_t t = 0; t < T; ++t) {
+                v.insert(v.end(), a->recs[t][q].begin(), a->recs[t][q].end());
+                std::vector<OccRec>().swap(a->recs[t][q]);
+            }
+            std::sort(v.begin(), v.end(), [](const OccRec &x, const OccRec &y) {
+                return x.hi < y.hi || (x.hi == y.hi && x.lo < y.lo);
+            });
+            for (size_t i = 0; i < v.size();) {
+                size_t j = i;
+                Tally t;
+                while (j < v.size() && v[j].hi == v[i].hi && v[j].lo == v[i].lo) {
+                    if (v[j].left >= 0) ++t.tl[v[j].left];
+                    if (v[j].right >= 0) ++t.tr[v[j].right];
+                    ++j;
+                }
+                if (j - i > UINT32_MAX) {
+                    rcs[q] = ORC_EOVERFLOW;
+                    return;
+                }
+                t.cnt = (uint32_t)(j - i);
+                if (keep_all || t.cnt >= a->p.min_depth) out[q].push_back({((u128)v[i].hi << 64) | v[i].lo, t});
+                i = j;
+            }
+        });
+        for (uint32_t q = 0; q < T; ++q)
+            if (rcs[q] != ORC_OK) return rcs[q];
+        size_t n = 0;
+        for (auto &o : out) n += o.size();
+        recs.reserve(n);
+        for (auto &o : out) {
+            recs.insert(recs.end(), o.begin(), o.end());
+            std::vector<std::pair<u128, Tally>>().swap(o);
         }
-        int64_t total = 0;
-        for (uint32_t t = 0; t < T; ++t) total += npos[t];
-        npos[0] = total;
     }
     orc_result *res = new orc_result();
-    res->positions = npos[0];
-    const bool keep_all = (p->flags & ORC_KEEP_ALL) != 0;
-    std::vector<std::pair<u128, Tally>> recs;
-    for (auto &m : maps) {
-        for (auto &kv : m)
-            if (keep_all || kv.second.cnt >= p->min_depth) recs.push_back(kv);
-        Map().swap(m);
-    }
-    std::sort(recs.begin(), recs.end(), [](const std::pair<u128, Tally> &a, const std::pair<u128, Tally> &b) {
-        return a.first < b.first;
+    res->positions = a->positions;
+    for (auto &row : a->maps)
+        for (auto &m : row) {
+            for (auto &kv : m)
+                if (keep_all || kv.second.cnt >= a->p.min_depth) recs.push_back(kv);
+            Map().swap(m);
+        }
+    std::sort(recs.begin(), recs.end(), [](const std::pair<u128, Tally> &x, const std::pair<u128, Tally> &y) {
+        return x.first < y.first;
     });
     res->key.reserve(recs.size());
     res->val.reserve(recs.size());
@@ -275,6 +430,61 @@ int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_o
     }
     *handle = res;
     return (int64_t)recs.size();
+}
+
+static int check_params(const orc_params_t *p) {
+    if (!p || p->k < 1 || p->k > 63) return ORC_EINVAL;
+    if (!(p->flags & ORC_FORWARD_ONLY) && (p->k % 2) == 0) return ORC_EINVAL;
+    if (p->n_owners < 1 || p->owner >= p->n_owners) return ORC_EINVAL;
+    if (p->n_shards < 1 || p->shard >= p->n_shards) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/* A counting state for reads given in several batches (orc_acc_add per
+ * batch, then orc_acc_finish); NULL on bad parameters. */
+void *orc_acc_new(const orc_params_t *p) {
+    if (check_params(p) != ORC_OK) return nullptr;
+    orc_acc *a = new orc_acc();
+    a->p = *p;
+    a->T = p->n_threads > 1 ? (uint32_t)p->n_threads : 1u;
+    a->split = (p->flags & ORC_SPLIT_READS) != 0;
+    a->sorted = (p->flags & ORC_SORT_COUNT) != 0;
+    if (a->sorted) a->recs.assign(a->T, std::vector<std::vector<OccRec>>(a->T));
+    else a->maps.assign(a->T, std::vector<Map>(a->split ? a->T : 1));
+    return a;
+}
+
+int orc_acc_add(void *acc, const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads) {
+    if (!acc || n_reads < 0) return ORC_EINVAL;
+    return acc_add((orc_acc *)acc, ascii, qual, read_off, n_reads);
+}
+
+/* Finish and free the state: records as for orc_run (count or error). */
+int64_t orc_acc_finish(void *acc, void **handle) {
+    *handle = nullptr;
+    if (!acc) return ORC_EINVAL;
+    orc_acc *a = (orc_acc *)acc;
+    const int64_t n = acc_finish(a, handle);
+    delete a;
+    return n;
+}
+
+void orc_acc_free(void *acc) { delete (orc_acc *)acc; }
+
+/* Run the oracle.  read_off has n_reads + 1 entries (base offsets).  Returns
+ * the number of output records (>= 0) or a negative error; *handle receives
+ * the result for orc_fetch / orc_free. */
+int64_t orc_run(const uint8_t *ascii, const uint8_t *qual, const int64_t *read_off, int64_t n_reads,
+                const orc_params_t *p, void **handle) {
+    *handle = nullptr;
+    if (check_params(p) != ORC_OK || n_reads < 0) return ORC_EINVAL;
+    void *a = orc_acc_new(p);
+    const int rc = orc_acc_add(a, ascii, qual, read_off, n_reads);
+    if (rc != ORC_OK) {
+        orc_acc_free(a);
+        return rc;
+    }
+    return orc_acc_finish(a, handle);
 }
 
 /* Copy the sorted records out.  tl/tr are n x 4 row-major; cls_* as

@@ -79,8 +79,13 @@ read_st = st.tuples(st.text(alphabet="ACGTNacgt", min_size=0, max_size=40), st.i
 @settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow])
 @given(reads=st.lists(read_st, min_size=0, max_size=8), k=st.sampled_from([1, 3, 5, 7]),
        qcut=st.integers(0, 42), min_depth=st.integers(1, 3), ext_min=st.integers(1, 3),
-       n_owners=st.sampled_from([1, 3]), fwd=st.booleans(), keep_all=st.booleans())
-def test_oracle_equals_brute_force(reads, k, qcut, min_depth, ext_min, n_owners, fwd, keep_all):
+       n_owners=st.sampled_from([1, 3]), fwd=st.booleans(), keep_all=st.booleans(),
+       mode=st.sampled_from(["map", "split", "sort", "sort_threads"]))
+def test_oracle_equals_brute_force(reads, k, qcut, min_depth, ext_min, n_owners, fwd, keep_all, mode):
+    """Every counting scheme of the oracle (one map; read-partitioned maps; sort-counted, on one and
+    on three threads) against the brute force."""
+    kw = {"map": {}, "split": dict(n_threads=3, split_reads=True), "sort": dict(sort_count=True),
+          "sort_threads": dict(sort_count=True, n_threads=3)}[mode]
     rs = []
     for s, seed in reads:
         rng = np.random.default_rng(seed)
@@ -91,7 +96,7 @@ def test_oracle_equals_brute_force(reads, k, qcut, min_depth, ext_min, n_owners,
         exp = brute.brute(rs, k, qcut=qcut, min_depth=min_depth, ext_min=ext_min, forward_only=fwd,
                           keep_all=keep_all, n_owners=n_owners, own=own)
         t = run_reads(rs, k, qcut=qcut, min_depth=min_depth, ext_min=ext_min, forward_only=fwd, keep_all=keep_all,
-                      n_owners=n_owners, owner=own)
+                      n_owners=n_owners, owner=own, **kw)
         assert table_to_dict(t) == exp
 
 
@@ -111,10 +116,57 @@ def test_brute_force_larger_k_and_threads():
         for T in (1, 3):
             assert table_to_dict(run_reads(reads, k, qcut=20, min_depth=2, n_threads=T)) == exp
             assert table_to_dict(run_reads(reads, k, qcut=20, min_depth=2, n_threads=T, split_reads=True)) == exp
+            assert table_to_dict(run_reads(reads, k, qcut=20, min_depth=2, n_threads=T, sort_count=True)) == exp
+        shard1 = {key: v for key, v in exp.items()
+                  if oracle.shard_of(np.array([key >> 64], np.uint64),
+                                     np.array([key & (2 ** 64 - 1)], np.uint64), 3)[0] == 1}
         got = run_reads(reads, k, qcut=20, min_depth=2, n_threads=4, split_reads=True, n_shards=3, shard=1)
-        assert table_to_dict(got) == {key: v for key, v in exp.items()
-                                      if oracle.shard_of(np.array([key >> 64], np.uint64),
-                                                         np.array([key & (2 ** 64 - 1)], np.uint64), 3)[0] == 1}
+        assert table_to_dict(got) == shard1
+        got = run_reads(reads, k, qcut=20, min_depth=2, n_threads=4, sort_count=True, n_shards=3, shard=1)
+        assert table_to_dict(got) == shard1
+
+
+@pytest.mark.parametrize("mode", [dict(), dict(n_threads=2, split_reads=True), dict(sort_count=True),
+                                  dict(n_threads=3, sort_count=True)])
+def test_keys_sharing_their_low_word(mode):
+    """Two-word keys (k = 33) that differ only in their first base share the low 64 key bits: keys
+    must be told apart by both words (every scheme, against the brute force).  The reads alternate
+    between the two k-mers so that no scheme sees them grouped by accident."""
+    x = "GATTACAGATTACAGATTACAGATTACAGATT"  # 32 bases: the low 64 bits of both keys
+    reads = []
+    for i in range(12):
+        reads.append((("A" if i % 2 else "C") + x + "G", [40] * 34))
+    exp = brute.brute(reads, 33, qcut=20, min_depth=2, forward_only=True)
+    got = run_reads(reads, 33, qcut=20, min_depth=2, forward_only=True, **mode)
+    assert table_to_dict(got) == exp
+    assert len(exp) == 3 and sorted(v[0] for v in exp.values()) == [6, 6, 12]
+
+
+@pytest.mark.parametrize("mode", [dict(), dict(n_threads=3), dict(n_threads=3, split_reads=True),
+                                  dict(sort_count=True), dict(n_threads=4, sort_count=True)])
+def test_batched_reads_equal_brute_force(mode):
+    """Reads given in batches (oracle.Accumulator) against the brute force over all of them: the
+    unfiltered tables of the batches add up to the table of their union, and the depth filter and
+    classes apply once at the end (a k-mer seen once in each of two batches is kept)."""
+    rng = np.random.default_rng(17)
+    g = "".join(rng.choice(list(BASES), 300))
+    reads = []
+    for _ in range(50):
+        s = int(rng.integers(0, 300 - 60))
+        r = g[s:s + 60]
+        if rng.random() < 0.5:
+            r = "".join(COMP[c] for c in reversed(r))
+        reads.append((r, [int(x) for x in rng.integers(10, 41, 60)]))
+    for k, owners in ((21, 1), (33, 2)):
+        for own in range(owners):
+            exp = brute.brute(reads, k, qcut=20, min_depth=2, n_owners=owners, own=own)
+            acc = oracle.Accumulator(k, qcut=20, min_depth=2, n_owners=owners, owner=own, **mode)
+            for lo, hi in ((0, 7), (7, 30), (30, 30), (30, 50)):
+                a, q, off = pack_reads(reads[lo:hi])
+                acc.add(a, q, off)
+            got = acc.finish()
+            assert table_to_dict(got) == exp
+            assert got["positions"] == sum(len(r) - k + 1 for r, _ in reads)
 
 
 def test_owner_map_matches_independent_python():
