@@ -323,8 +323,13 @@ def run_human_share(args, dev):
     torch.cuda.empty_cache()
     scanned = w.n_reads * (L - k + 1)
     sketch = kmer.CardSketch(k, scanned, n_owners=p.n_owners, owner=p.owner, device=dev)
-    card = sketch.run(packs, min_depth=p.min_depth)
+    use_occ = not args.no_occ_stream
+    occ = kmer.OccStream.for_windows(scanned, p.n_owners, len(packs), device=dev) if use_occ else None
+    card = sketch.run(packs, min_depth=p.min_depth, occ=occ)
     abi.check(card.status, "cardinality pass")
+    if occ is not None and occ.overflowed():  # the share was larger than planned: rerun with room for it
+        occ = kmer.OccStream(card.positions + kmer.OccStream.slack(len(packs), dev), device=dev)
+        card = sketch.run(packs, min_depth=p.min_depth, occ=occ)
     cap, bloom_words, list_cap = kmer.plan_sizes(card, pass1_launches=len(packs), device=dev)
     kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_owners=p.n_owners, owner=p.owner, heavy=card, device=dev)
     out = kmer.Records(int(min(kc.capacity, card.kept_hi() * 1.3 + 1024)), device=dev)
@@ -335,14 +340,19 @@ def run_human_share(args, dev):
     def step(ev):
         ev[0].record()
         sketch.reset()
+        if occ is not None:
+            occ.reset()
         for pk in packs:
-            sketch.update(pk)
+            sketch.update(pk, occ=occ)
         sketch.summarize(min_depth=p.min_depth)
         ev[1].record()
         kc.reset()
         ev[2].record()
-        for pk in packs:
-            kc.insert(pk)
+        if occ is not None:  # pass 1 reads the owned occurrences the cardinality pass wrote
+            kc.insert_occ(occ)
+        else:
+            for pk in packs:
+                kc.insert(pk)
         ev[3].record()
         kc.count()
         ev[4].record()
@@ -437,6 +447,9 @@ def main():
                     help="add the Bloom-bypass diagnostic (one pass into a table sized for every distinct k-mer); "
                          "off by default: it launches the same pass-1 kernel, so a kernel trace of the default run "
                          "holds only the measured step's pass 1")
+    ap.add_argument("--no-occ-stream", action="store_true",
+                    help="human-share: pass 1 scans the reads with the owner filter instead of reading the owned "
+                         "occurrences the cardinality pass wrote")
     ap.add_argument("--no-heavy", action="store_true",
                     help="count heavy hitters through the table instead of workgroup-local counters")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")

@@ -66,6 +66,7 @@ extern "C" {
 #define HM_ST_TIMEOUT 16u
 #define HM_ST_DUPLICATE 32u /* hm_contigs: a key appears twice in the input */
 #define HM_ST_CLASSIFIED 64u /* not an error: hm_classify_ext has written the table's classification words */
+#define HM_ST_STREAM_FULL 128u /* hm_bloom_insert_occ: the occurrence stream had overflowed (see hm_occ_t) */
 
 /* hm_params_t.flags */
 #define HM_FORWARD_ONLY 1u /* key = forward encoding (no canonical form); allows even k */
@@ -358,6 +359,58 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
  * heavy_cap is 0). */
 int hm_card_summary(const hm_card_t *c, uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,
                     uint64_t heavy_cap, hm_card_summary_t *out, hipStream_t stream);
+
+
+/* ---- owned-occurrence stream: the sharded shape --------------------------
+ *
+ * Section "Parallel k-mer analysis" (owner computes): a processor keeps only
+ * the k-mers it owns, a small share of all windows.  A pass 1 over the reads
+ * would scan every window again to find that share after the cardinality
+ * pass has already found it, so the cardinality pass can write the owned
+ * occurrences out as it meets them, and pass 1 then reads that stream
+ * instead of the reads.  The table, and so the output, are the same as with
+ * hm_bloom_insert over the same reads and owner filter.
+ *
+ * Entries come in no fixed order: each wave of the cardinality pass reserves
+ * chunks of 1024 entries with one atomic add on `count` and fills them in
+ * order, up to 64 entries per write; the unused tail of a wave's last chunk of
+ * a launch is marked as holes (ext byte 0xFF), which pass 1 skips.  So *count (entries reserved,
+ * holes included) exceeds the owned occurrences by at most 1023 per wave of
+ * each hm_cardinality_occ launch (4 waves per workgroup, 4 workgroups per CU).
+ * If *count passes `capacity`, the entries past it were dropped: the stream
+ * is void (hm_bloom_insert_occ then sets HM_ST_STREAM_FULL and counts
+ * nothing), and the caller reruns with a larger stream. */
+typedef struct {
+    uint64_t *keys;    /* 2 * capacity words, 16-byte aligned: entry i is (key_hi, key_lo) at keys[2i], keys[2i+1] */
+    uint8_t *ext;      /* capacity bytes: left | right << 4, 0..3 = base, 4 = no extension; 0xFF = hole */
+    uint64_t capacity; /* entries */
+    uint64_t *count;   /* device counter of entries reserved (zeroed by hm_occ_init) */
+} hm_occ_t;
+
+size_t hm_occ_bytes(uint64_t capacity); /* 17 bytes per entry */
+
+/* Zero the stream's entry counter. */
+int hm_occ_init(hm_occ_t *o, hipStream_t stream);
+
+/* hm_cardinality, and in the same scan append every valid window whose key
+ * is owned (hm_params_t owner filter) to `o` as (canonical key, extension
+ * byte), with the extensions as pass 1 takes them (HQ neighbours, swapped and
+ * complemented when the reverse complement is the key).  Call once per read
+ * batch after hm_card_init and hm_occ_init; the batches' entries accumulate
+ * in one stream.  HM_EINVAL for a NULL or misaligned stream. */
+int hm_cardinality_occ(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hm_occ_t *o, hipStream_t stream);
+
+/* Counting pass 1 (as hm_bloom_insert) over the occurrences of a stream
+ * written by hm_cardinality_occ instead of over reads: every entry
+ * [0, *o->count) that is not a hole is looked up, counted, inserted or
+ * deferred to `l` exactly as hm_bloom_insert does with the same occurrence.
+ * The owner filter was applied when the stream was written (p->n_owners and
+ * p->owner are not used again); k, flags, seed and min_depth are.  Then
+ * hm_kmer_count, hm_classify_ext and hm_export_table as usual.  If the stream
+ * overflowed (*count > capacity) the pass sets HM_ST_STREAM_FULL in the
+ * table's status and does nothing else; hm_status reports HM_ECAPACITY. */
+int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, hm_table_t *t, hm_list_t *l,
+                        hipStream_t stream);
 
 
 /* ---- contig generation (section "Parallel contig generation") ---------- */

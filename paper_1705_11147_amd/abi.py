@@ -26,6 +26,7 @@ HM_ST_OUTPUT_FULL = 8
 HM_ST_TIMEOUT = 16
 HM_ST_DUPLICATE = 32
 HM_ST_CLASSIFIED = 64
+HM_ST_STREAM_FULL = 128
 
 HM_FORWARD_ONLY = 1
 HM_BLOOM_BYPASS = 2
@@ -95,6 +96,11 @@ class CardSummary(ctypes.Structure):
                 ("sampled_kept", ctypes.c_uint64), ("n_heavy", ctypes.c_uint64), ("positions", ctypes.c_uint64)]
 
 
+class Occ(ctypes.Structure):
+    _fields_ = [("keys", ctypes.c_void_p), ("ext", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("count", ctypes.c_void_p)]
+
+
 class Contigs(ctypes.Structure):
     _fields_ = [("seq", ctypes.c_void_p), ("seq_capacity", ctypes.c_uint64), ("off", ctypes.c_void_p),
                 ("off_capacity", ctypes.c_uint64), ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p),
@@ -142,6 +148,10 @@ SIGNATURES = {
     "hm_card_init": ([P(Card), vp], ctypes.c_int),
     "hm_cardinality": ([P(Reads), P(Params), P(Card), vp], ctypes.c_int),
     "hm_card_summary": ([P(Card), ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),
+    "hm_occ_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
+    "hm_occ_init": ([P(Occ), vp], ctypes.c_int),
+    "hm_cardinality_occ": ([P(Reads), P(Params), P(Card), P(Occ), vp], ctypes.c_int),
+    "hm_bloom_insert_occ": ([P(Occ), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
     "hm_contigs_work_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "hm_contigs": ([P(Export), ctypes.c_int32, ctypes.c_uint32, P(Contigs), vp], ctypes.c_int),
     "hm_batch_work_bytes": ([ctypes.c_int32], ctypes.c_size_t),

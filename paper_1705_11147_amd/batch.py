@@ -17,6 +17,12 @@ from . import abi, kmer
 from .kmer import KmerCounter, Records, next_pow2
 
 
+# The first-occurrence list of every set keeps room for one partly used
+# 256-entry chunk per wave of up to this many workgroups per CU, so any launch
+# shape the autotuner tries (tune.LAUNCH_SPACE) fits the same buffers.
+MAX_BLOCKS_PER_CU = 12
+
+
 @dataclass
 class Tuning:
     blocks_per_cu: int = 8
@@ -80,8 +86,8 @@ class _SetBuffers:
         cap = next_pow2(max(1024, int(keys / tuning.table_load)))
         bw = next_pow2(max(64, int(distinct * tuning.bloom_bits / 64)))
         cus = torch.cuda.get_device_properties(device).multi_processor_count
-        # + one partly used 256-entry chunk per wave of either form
-        lcap = int(distinct * (1.0 if plan else 1.2)) + cus * max(8, tuning.blocks_per_cu) * 4 * 255
+        # + one partly used 256-entry chunk per wave of either form, for every launch shape
+        lcap = int(distinct * (1.0 if plan else 1.2)) + cus * max(8, MAX_BLOCKS_PER_CU, tuning.blocks_per_cu) * 4 * 255
         self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, device=device, **params)
         self.out = Records(int(min(cap, keys * 1.3 + 1024)), device=device)
 

@@ -65,9 +65,9 @@ struct BatchDesc {
 };
 
 struct Region {
-    void *p;
-    uint64_t bytes;    // multiple of 4
-    uint32_t pattern;  // 32-bit fill value
+    void *p;           // any alignment
+    uint64_t bytes;    // any count
+    uint32_t pattern;  // fill byte, replicated into all four bytes (0 or 0xFFFFFFFF here)
     uint32_t pad;
 };
 
@@ -109,23 +109,24 @@ Layout layout(int32_t S) {
 
 // ------------------------------------------------------------------ kernels
 
-// Fill region blockIdx.y with its pattern (16-byte stores for the aligned
-// body, 4-byte tail).
+// Fill exactly r.bytes bytes of region blockIdx.y with its pattern byte:
+// single bytes up to the first 16-byte boundary and after the last one,
+// 16-byte stores between them.
 __global__ __launch_bounds__(kBlock) void k_fill_regions(const Region *regions) {
     const Region r = regions[blockIdx.y];
     if (!r.p || r.bytes == 0) return;
     uint8_t *p = reinterpret_cast<uint8_t *>(r.p);
     const uint32_t v = r.pattern;
+    const uint8_t byte = (uint8_t)v;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if ((((uintptr_t)p) & 15) == 0) {
-        const uint64_t n16 = r.bytes / 16;
-        uint4 *q = reinterpret_cast<uint4 *>(p);
-        for (uint64_t i = tid; i < n16; i += stride) q[i] = make_uint4(v, v, v, v);
-        for (uint64_t i = n16 * 4 + tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = v;
-    } else {
-        for (uint64_t i = tid; i < r.bytes / 4; i += stride) reinterpret_cast<uint32_t *>(p)[i] = v;
-    }
+    uint64_t head = (16 - (((uintptr_t)p) & 15)) & 15;
+    if (head > r.bytes) head = r.bytes;
+    const uint64_t n16 = (r.bytes - head) / 16;
+    for (uint64_t i = tid; i < head; i += stride) p[i] = byte;
+    uint4 *q = reinterpret_cast<uint4 *>(p + head);
+    for (uint64_t i = tid; i < n16; i += stride) q[i] = make_uint4(v, v, v, v);
+    for (uint64_t i = head + 16 * n16 + tid; i < r.bytes; i += stride) p[i] = byte;
 }
 
 __device__ __forceinline__ int find_range(const int64_t *start, int n, int64_t t) {
@@ -548,7 +549,7 @@ int hm_batch_prepare(const hm_batch_set_t *sets, int32_t n_sets, const hm_params
         reg[nr++] = Region{d.slots, d.capacity * HM_SLOT_BYTES, 0u, 0u};
         reg[nr++] = Region{d.bloom, (bypass || !d.bloom) ? 0ull : (d.bloom_mask + 1) * 8, 0u, 0u};
         reg[nr++] = Region{d.lcount, bypass ? 0ull : 8ull, 0u, 0u};
-        reg[nr++] = Region{d.lext, bypass ? 0ull : (d.lcap + 3) / 4 * 4, 0xFFFFFFFFu, 0u};  // all holes
+        reg[nr++] = Region{d.lext, bypass ? 0ull : d.lcap, 0xFFFFFFFFu, 0u};  // all holes, exactly lcap bytes
         reg[nr++] = Region{d.present, (bypass || !d.present) ? 0ull : d.present_words * 8, 0u, 0u};
         reg[nr++] = Region{d.out.n_out, 8, 0u, 0u};
         reg[nr++] = Region{d.out.digest, d.out.digest ? 16ull : 0ull, 0u, 0u};

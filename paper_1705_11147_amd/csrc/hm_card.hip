@@ -169,6 +169,123 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
     card_end(c, s_reg, npos);
 }
 
+// The same pass over fixed-length reads, also writing every owned occurrence
+// to a stream (hm_cardinality_occ) with its extensions, for a pass 1 that
+// then reads the stream instead of rescanning every window.  With an owner
+// filter a wave holds an owned window in only a few lanes at a time, so the
+// owned-window work (HyperLogLog hash and register, samples, extensions,
+// stream store) is not done where the window is found: each lane only rolls
+// its windows, takes the canonical key and tests the owner, and the owned
+// ones are staged in the wave's ring in LDS with their position.  Every 64
+// staged windows, and at the end of each tile, the wave finishes them with
+// every lane busy.  The loops have wave-uniform trip counts for that (a lane
+// past the tile's runs, or past its read's last window, idles).
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs c, OccOut out, int32_t reads_per_tile,
+                                                           int64_t n_tiles) {
+    __shared__ uint64_t s_b2[kTileB2Words];
+    __shared__ uint64_t s_nm[kTileMaskWords];
+    __shared__ uint64_t s_hq[kTileMaskWords];
+    __shared__ uint4 s_rkey[kBlock / 64][kRing];
+    __shared__ uint32_t s_raux[kBlock / 64][kRing];
+    extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers
+    uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
+    card_begin(c, s_reg32);
+    const int wv = threadIdx.x >> 6;
+    OccRing ring{s_rkey[wv], s_raux[wv], 0u, 0u};
+    OccCursor cur{0ull, kOccChunk};
+    uint32_t npos = 0;
+    const int L = a.read_len, k = a.k;
+    const int W = L - k + 1;  // > 0, checked by the host
+    const int runs = (W + kCardRun - 1) / kCardRun;
+    const int kb = 2 * k;
+    const uint64_t mlo = kb >= 64 ? ~0ull : ((1ull << kb) - 1);
+    const uint64_t mhi = kb > 64 ? ((1ull << (kb - 64)) - 1) : 0ull;
+    const int top = kb - 2;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * reads_per_tile;
+        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
+        const int64_t org = (r0 * L) & ~(int64_t)63;
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)((((r1 * L) + 63) >> 6) - mw0) + 2;
+        __syncthreads();
+        for (int i = threadIdx.x; i < nmw; i += kBlock) {
+            s_nm[i] = a.nm[mw0 + i];
+            s_hq[i] = a.hq[mw0 + i];
+        }
+        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        const Words w{s_b2, s_nm, s_hq};
+        // finish the n oldest staged windows (wave-uniform n <= 64), one per lane; aux packs the
+        // window's start (tile-relative, 15 bits), its offset in its read (15 bits) and orientation
+        auto finish = [&](uint32_t n) {
+            uint4 kk = make_uint4(0, 0, 0, 0);
+            uint32_t m = 0;
+            uint8_t e = 0;
+            if (ring_take(ring, n, kk, m)) {
+                const int64_t j = m & 0x7FFF;
+                const int pos = (int)((m >> 15) & 0x7FFF);
+                const bool fwd = (m >> 31) != 0;
+                Occ o{((uint64_t)kk.y << 32) | kk.x, ((uint64_t)kk.w << 32) | kk.z, 4, 4};
+                card_window<KW>(c, s_reg, true, o, org + j, npos);
+                // HQ neighbours inside the read, as pass 1 takes them
+                const int lb = (pos > 0 && w.hqbit(j - 1)) ? (int)w.code(j - 1) : 4;
+                const int rr = (pos + k < L && w.hqbit(j + k)) ? (int)w.code(j + k) : 4;
+                const int left = fwd ? lb : (rr < 4 ? 3 - rr : 4);
+                const int right = fwd ? rr : (lb < 4 ? 3 - lb : 4);
+                e = (uint8_t)(left | (right << 4));
+            }
+            occ_emit(out, cur, n, kk, e);
+        };
+        const int total = (int)(r1 - r0) * runs;
+        for (int g0 = 0; g0 < total; g0 += kBlock) {  // workgroup-uniform trip count
+            const int gi = g0 + threadIdx.x;
+            int cnt = 0, p0 = 0;
+            int64_t j0 = 0;
+            U128 f{0, 0}, rc{0, 0};
+            if (gi < total) {
+                const int r = gi / runs;
+                p0 = (gi - r * runs) * kCardRun;
+                cnt = min(kCardRun, W - p0);
+                j0 = (r0 + r) * L - org + p0;  // first window of the run, relative to the tile origin
+                f = w.window(j0, k);
+                rc = revcomp(f, k);
+            }
+            for (int i = 0; i < kCardRun; ++i) {
+                bool act = false;
+                bool fwd = true;
+                if (i < cnt) {
+                    if (i > 0) {
+                        const uint64_t b = w.code(j0 + i + k - 1);
+                        if (KW == 1) {
+                            f.lo = ((f.lo << 2) | b) & mlo;
+                            rc.lo = (rc.lo >> 2) | ((3 - b) << top);
+                        } else {
+                            f.hi = ((f.hi << 2) | (f.lo >> 62)) & mhi;
+                            f.lo = ((f.lo << 2) | b) & mlo;
+                            rc.lo = (rc.lo >> 2) | (rc.hi << 62);
+                            rc.hi >>= 2;
+                            if (top >= 64) rc.hi |= (3 - b) << (top - 64);
+                            else rc.lo |= (3 - b) << top;
+                        }
+                    }
+                    if (w.window_valid(j0 + i, k)) {
+                        fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
+                        act = a.n_owners <= 1 ||
+                              owner_of(fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, a.n_owners) == a.owner;
+                    }
+                }
+                const uint32_t aux = (uint32_t)(j0 + i) | ((uint32_t)(p0 + i) << 15) | (fwd ? 1u << 31 : 0u);
+                ring_push(ring, act, fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, aux);
+                if (ring.tail - ring.head >= 64) finish(64);
+            }
+        }
+        if (ring.tail != ring.head) finish(ring.tail - ring.head);  // before the next tile replaces the LDS words
+    }
+    card_end(c, s_reg, npos);
+    occ_close(out, cur);
+}
+
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_card_var(PassArgs a, CardArgs c, int64_t n_tiles) {
     __shared__ int64_t s_off[kVarReads + 1];
@@ -180,6 +297,39 @@ __global__ __launch_bounds__(kBlock) void k_card_var(PassArgs a, CardArgs c, int
     var_windows<false>(a, n_tiles, s_off, s_pre,
                        [&](bool act, const Occ &o, int64_t j) { card_window<KW>(c, s_reg, act, o, j, npos); });
     card_end(c, s_reg, npos);
+}
+
+// Variable-length reads, writing the owned occurrences too (extract() gives
+// them with their extensions; var_windows' trip counts are workgroup-uniform).
+// The sketch is updated where a window is found; the stream entries are
+// staged in the wave's ring and written 64 at a time.
+template <int KW>
+__global__ __launch_bounds__(kBlock) void k_card_var_occ(PassArgs a, CardArgs c, OccOut out, int64_t n_tiles) {
+    __shared__ int64_t s_off[kVarReads + 1];
+    __shared__ int64_t s_pre[kVarReads + 1];
+    __shared__ uint4 s_rkey[kBlock / 64][kRing];
+    __shared__ uint32_t s_raux[kBlock / 64][kRing];
+    extern __shared__ uint32_t s_reg32[];
+    uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
+    card_begin(c, s_reg32);
+    const int wv = threadIdx.x >> 6;
+    OccRing ring{s_rkey[wv], s_raux[wv], 0u, 0u};
+    OccCursor cur{0ull, kOccChunk};
+    uint32_t npos = 0;
+    auto flush = [&](uint32_t n) {
+        uint4 kk = make_uint4(0, 0, 0, 0);
+        uint32_t e = 0;
+        ring_take(ring, n, kk, e);
+        occ_emit(out, cur, n, kk, (uint8_t)e);
+    };
+    var_windows<false>(a, n_tiles, s_off, s_pre, [&](bool act, const Occ &o, int64_t j) {
+        card_window<KW>(c, s_reg, act, o, j, npos);
+        ring_push(ring, act, o.hi, o.lo, (uint32_t)(o.left | (o.right << 4)));
+        if (ring.tail - ring.head >= 64) flush(64);
+    });
+    if (ring.tail != ring.head) flush(ring.tail - ring.head);
+    card_end(c, s_reg, npos);
+    occ_close(out, cur);
 }
 
 // Distinct-sample size and kept count; heavy hitters of the window sample.
@@ -283,7 +433,8 @@ int hm_card_init(hm_card_t *c, hipStream_t s) {
     return hm_table_init(&c->heavy, s);
 }
 
-int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipStream_t s) {
+// Checks and kernel arguments shared by hm_cardinality and hm_cardinality_occ.
+static int card_setup(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, PassArgs &a, CardArgs &ca) {
     int rc = hm_check_params(p);
     if (rc) return rc;
     rc = check_card(c);
@@ -293,8 +444,6 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
                     c->heavy.k, p->k);
     rc = check_reads(r, p->k);
     if (rc) return rc;
-    if (r->n_reads == 0) return HM_OK;
-    PassArgs a;
     memset(&a, 0, sizeof a);
     a.b2 = r->bases2;
     a.nm = r->nmask;
@@ -308,7 +457,6 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
     a.n_owners = p->n_owners;
     a.owner = p->owner;
     a.status = c->sample.status;
-    CardArgs ca;
     ca.regs = c->registers;
     ca.p = c->hll_p;
     ca.smask = c->sample_log2 ? (~0ull >> (64 - c->sample_log2)) : 0ull;
@@ -323,6 +471,12 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
     ca.h_status = c->heavy.status;
     ca.positions = reinterpret_cast<unsigned long long *>(c->positions);
     ca.seed = p->seed;
+    return HM_OK;
+}
+
+// Launch the pass over the reads; `out` NULL: no occurrence stream.
+static int card_launch(const hm_reads_t *r, const hm_params_t *p, const hm_card_t *c, const PassArgs &a,
+                       const CardArgs &ca, const OccOut *out, hipStream_t s) {
     const bool two = p->k >= 32;
     const size_t lds = (size_t)1 << c->hll_p;
     const int grid_cap = device_cus() * kCardBlocksPerCu;
@@ -331,17 +485,48 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
         const int32_t rpt = kTileBases / r->read_len;
         const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
         const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
-        if (two) hipLaunchKernelGGL(k_card_fixed<2>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
-        else hipLaunchKernelGGL(k_card_fixed<1>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+        if (out) {
+            if (two) hipLaunchKernelGGL(k_card_fixed_occ<2>, g, dim3(kBlock), lds, s, a, ca, *out, rpt, n_tiles);
+            else hipLaunchKernelGGL(k_card_fixed_occ<1>, g, dim3(kBlock), lds, s, a, ca, *out, rpt, n_tiles);
+        } else {
+            if (two) hipLaunchKernelGGL(k_card_fixed<2>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+            else hipLaunchKernelGGL(k_card_fixed<1>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+        }
     } else {
         if (!r->read_off) return fail(HM_EINVAL, "reads longer than %d bases need read_off", kTileBases - 64);
         const int64_t n_tiles = (r->n_reads + kVarReads - 1) / kVarReads;
         const dim3 g((unsigned)(n_tiles < grid_cap ? n_tiles : grid_cap));
-        if (two) hipLaunchKernelGGL(k_card_var<2>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
-        else hipLaunchKernelGGL(k_card_var<1>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
+        if (out) {
+            if (two) hipLaunchKernelGGL(k_card_var_occ<2>, g, dim3(kBlock), lds, s, a, ca, *out, n_tiles);
+            else hipLaunchKernelGGL(k_card_var_occ<1>, g, dim3(kBlock), lds, s, a, ca, *out, n_tiles);
+        } else {
+            if (two) hipLaunchKernelGGL(k_card_var<2>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
+            else hipLaunchKernelGGL(k_card_var<1>, g, dim3(kBlock), lds, s, a, ca, n_tiles);
+        }
     }
-    HM_LAUNCH_CHECK("hm_cardinality");
+    HM_LAUNCH_CHECK(out ? "hm_cardinality_occ" : "hm_cardinality");
     return HM_OK;
+}
+
+int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipStream_t s) {
+    PassArgs a;
+    CardArgs ca;
+    int rc = card_setup(r, p, c, a, ca);
+    if (rc) return rc;
+    if (r->n_reads == 0) return HM_OK;
+    return card_launch(r, p, c, a, ca, nullptr, s);
+}
+
+int hm_cardinality_occ(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hm_occ_t *o, hipStream_t s) {
+    PassArgs a;
+    CardArgs ca;
+    int rc = card_setup(r, p, c, a, ca);
+    if (rc) return rc;
+    rc = check_occ(o);
+    if (rc) return rc;
+    if (r->n_reads == 0) return HM_OK;
+    const OccOut out{o->keys, o->ext, o->capacity, reinterpret_cast<unsigned long long *>(o->count)};
+    return card_launch(r, p, c, a, ca, &out, s);
 }
 
 int hm_card_summary(const hm_card_t *c, uint32_t min_depth, uint32_t heavy_min, uint64_t *heavy_keys,

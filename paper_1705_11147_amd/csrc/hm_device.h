@@ -27,7 +27,7 @@ constexpr int kTileB2Words = 2 * kTileMaskWords;
 constexpr int kVarReads = 256;              // reads per tile on the variable-length path
 constexpr uint32_t kMaxSpin = 1u << 22;     // bound on re-reads of a half-published slot
 constexpr uint32_t kDefaultMaxProbe = 4096; // default linear-probe bound
-constexpr uint32_t kAbortBits = HM_ST_TABLE_FULL | HM_ST_LIST_FULL;
+constexpr uint32_t kAbortBits = HM_ST_TABLE_FULL | HM_ST_LIST_FULL | HM_ST_STREAM_FULL;
 
 // True once a pass has failed (table or list full): the table will be rebuilt
 // by the caller, so the remaining work is skipped.  Wave-uniform.
@@ -733,7 +733,106 @@ __device__ __forceinline__ void fixed_windows_queued(const PassArgs &a, int32_t 
     drain(n);  // the rest (also after a stop: its occurrences were found before the table filled)
 }
 
-// Visit every window of variable-length reads (read_off given): packed words
+// ------------------------------------------------------------------ owned-occurrence stream writer
+
+// A wave's stream space comes in chunks of kOccChunk entries, one atomic add
+// each.  A write of n <= 64 entries (lane l the l-th) fills the current chunk
+// and, when it runs out, continues in a fresh one, so entries are contiguous
+// and the only holes are the tail of a wave's last chunk of a launch.
+constexpr uint32_t kOccChunk = 1024;
+
+struct OccOut {
+    uint64_t *keys;  // 2 words per entry (hi, lo); 16-byte aligned
+    uint8_t *ext;    // left | right << 4; kHole marks an unused entry
+    uint64_t cap;
+    unsigned long long *count;
+};
+
+struct OccCursor {  // wave-uniform
+    uint64_t base;  // current chunk's first entry
+    uint32_t used;  // entries of the chunk written (kOccChunk: no chunk yet)
+};
+
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Write n (<= 64, wave-uniform) entries: lane l < n holds entry l (key words
+// (hi lo32, hi hi32, lo lo32, lo hi32) and its extension byte).  Called by
+// every lane of the wave.
+__device__ __forceinline__ void occ_emit(const OccOut &out, OccCursor &cur, uint32_t n, uint4 key, uint8_t e) {
+    const uint32_t l = lane_id();
+    const uint32_t rem = kOccChunk - cur.used;
+    uint64_t fresh = 0;
+    if (n > rem) {
+        unsigned long long b = 0;
+        if (l == 0) b = atomicAdd(out.count, (unsigned long long)kOccChunk);
+        fresh = __shfl(b, 0);
+    }
+    if (l < n) {
+        const uint64_t idx = l < rem ? cur.base + cur.used + l : fresh + (l - rem);
+        if (idx < out.cap) {
+            *reinterpret_cast<uint4 *>(out.keys + 2 * idx) = key;
+            out.ext[idx] = e;
+        }
+    }
+    if (n > rem) {
+        cur.base = fresh;
+        cur.used = n - rem;
+    } else {
+        cur.used += n;
+    }
+}
+
+// End of a wave's work: mark the rest of its chunk as holes.
+__device__ __forceinline__ void occ_close(const OccOut &out, const OccCursor &cur) {
+    if (cur.used >= kOccChunk) return;
+    for (uint32_t i = cur.used + lane_id(); i < kOccChunk; i += 64) {
+        const uint64_t idx = cur.base + i;
+        if (idx < out.cap) out.ext[idx] = kHole;
+    }
+}
+
+// A wave's staging ring in LDS (kRing entries): occurrences are appended by
+// the lanes that hold one, and written 64 at a time with every lane busy.
+constexpr uint32_t kRing = 128;  // a push adds <= 64 to fewer than 64 staged
+
+struct OccRing {
+    uint4 *key;
+    uint32_t *aux;  // the ext byte, or what the caller needs to finish the entry
+    uint32_t head, tail;  // wave-uniform: staged entries are [head, tail) mod kRing
+};
+
+// Stage the (key, aux) of every `act` lane (called by every lane of the wave).
+__device__ __forceinline__ void ring_push(OccRing &g, bool act, uint64_t hi, uint64_t lo, uint32_t aux) {
+    const uint64_t m = __ballot(act);
+    if (act) {
+        const uint32_t r = (g.tail + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))) & (kRing - 1);
+        g.key[r] = make_uint4((uint32_t)hi, (uint32_t)(hi >> 32), (uint32_t)lo, (uint32_t)(lo >> 32));
+        g.aux[r] = aux;
+    }
+    g.tail += (uint32_t)__popcll(m);
+}
+
+// Take the n (<= 64) oldest staged entries, lane l the l-th: returns whether
+// the lane holds one (then `key` and `aux` are set).
+__device__ __forceinline__ bool ring_take(OccRing &g, uint32_t n, uint4 &key, uint32_t &aux) {
+    lds_wave_sync();  // every lane's staged entries are visible
+    const uint32_t l = lane_id();
+    const bool mine = l < n;
+    if (mine) {
+        const uint32_t r = (g.head + l) & (kRing - 1);
+        key = g.key[r];
+        aux = g.aux[r];
+    }
+    g.head += n;
+    lds_wave_sync();  // the slots are read before later pushes reuse them
+    return mine;
+}
+
+// Visit every window of variable-length reads (read_off given): packed words// Visit every window of variable-length reads (read_off given): packed words
 // are read from global memory; a per-tile prefix sum in LDS (the caller's
 // s_off / s_pre, kVarReads + 1 entries each) maps flat window indices to
 // reads.  op as for fixed_windows.
@@ -988,6 +1087,7 @@ uint64_t grid_for(uint64_t items, int per_cu = 8);
 // argument checks shared by the entry points (defined in hm_kmer.hip)
 int check_reads(const hm_reads_t *r, int k);
 int check_table(const hm_table_t *t);
+int check_occ(const hm_occ_t *o);
 // key-order sort of an export (defined in hm_sort.hip); key_bits = 2k.  The
 // export writes each record's counters and classes into sort_staging(out)
 // (one 64-byte line per record), from where the sort gathers them.

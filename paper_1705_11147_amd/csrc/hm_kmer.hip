@@ -21,12 +21,19 @@
 //   * Pass 2 walks that list and counts the entries whose k-mer made it into
 //     the table.  Every occurrence is therefore counted exactly once, so the
 //     final table equals the plain definition whatever the false positives.
-//   * Slots are 64 bytes (one per cache line): two key words, each carrying a
-//     "written" bit so a reader can tell a half-published two-word key from a
-//     complete one without fences, then u32 counters: tl[4], tr[4] and nl
-//     (occurrences without a left extension); count = nl + sum(tl).
-//     A hit therefore costs one atomic add on the left counter and one on the
-//     right counter, both on the line the probe already touched.
+//   * Slots are 64 bytes (two per 128-byte cache line): two key words, each
+//     carrying a "written" bit so a reader can tell a half-published two-word
+//     key from a complete one without fences; a word of nine 7-bit narrow
+//     counters (no left extension, left A..T, right A..T); u32 wide counters
+//     nl, tl[4], tr[4]; and a 32-bit word that is the Bloom filter word of the
+//     keys homed at the slot until classification.  A hit costs one 64-bit CAS
+//     on the narrow word, which the probe's 16-byte load returned together
+//     with the first key word; a lane about to pass 127, or a CAS that keeps
+//     losing to others (a hot key), moves the slot to the wide counters (two
+//     atomic adds per later occurrence).  count = nl + sum(tl), narrow + wide.
+//   * With an owner filter (one share of a sharded run) the cardinality pass
+//     can write the owned occurrences to a stream, and pass 1 then reads that
+//     stream (k_pass1_stream) instead of scanning every window again.
 #include "hm_device.h"
 
 namespace hm {
@@ -130,6 +137,48 @@ __global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_var(PassArgs a,
     var_windows<true>(a, n_tiles, s_off, s_pre, [&](bool act, const Occ &o, int64_t) {
         pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv, seen_all);
     });
+    list_close(a, cur);
+    if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
+    stats_flush(a.stats, st);
+}
+
+// Pass 1 over an owned-occurrence stream (hm_bloom_insert_occ): one entry per
+// lane, grid-stride with a wave-uniform trip count (pass1_occ appends to the
+// first-occurrence list a wave at a time); holes are skipped.
+template <int KW, bool CHECKED, bool HEAVY>
+__global__ __launch_bounds__(kBlock) HM_EIGHT_WAVES void k_pass1_stream(PassArgs a, const uint64_t *keys,
+                                                                        const uint8_t *ext,
+                                                                        const unsigned long long *count, uint64_t cap) {
+    extern __shared__ uint64_t s_heavy[];
+    const uint64_t n = *count;  // written by earlier kernels on the stream
+    if (n > cap) {  // entries were dropped: the stream is void
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(a.status, HM_ST_STREAM_FULL);
+        return;
+    }
+    HeavyLds hv{};
+    if (HEAVY) hv = heavy_setup(a, s_heavy);
+    ListCursor cur{0, kListChunk};
+    Stats st = {};
+    const bool seen_all = classified_in_table(a);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock; i0 < n; i0 += stride) {
+        if (aborted(a.status)) break;  // wave-uniform
+        const uint64_t i = i0 + threadIdx.x;
+        Occ o{0, 0, 4, 4};
+        bool act = false;
+        if (i < n) {
+            const uint8_t e = ext[i];
+            if (e != kHole) {
+                const uint4 kk = *reinterpret_cast<const uint4 *>(keys + 2 * i);
+                o.hi = ((uint64_t)kk.y << 32) | kk.x;
+                o.lo = ((uint64_t)kk.w << 32) | kk.z;
+                o.left = e & 15;
+                o.right = e >> 4;
+                act = true;
+            }
+        }
+        pass1_occ<KW, CHECKED, kListChunk, HEAVY>(a, act, o, cur, st, &hv, seen_all);
+    }
     list_close(a, cur);
     if (HEAVY) heavy_flush<KW, CHECKED>(a, hv);
     stats_flush(a.stats, st);
@@ -244,6 +293,13 @@ int check_reads(const hm_reads_t *r, int k) {
     return HM_OK;
 }
 
+int check_occ(const hm_occ_t *o) {
+    if (!o || !o->count) return fail(HM_EINVAL, "occurrence stream or its counter is NULL");
+    if (o->capacity > 0 && (!o->keys || !o->ext)) return fail(HM_EINVAL, "occurrence stream arrays are NULL");
+    if (((uintptr_t)o->keys) & 15) return fail(HM_EINVAL, "occurrence stream keys must be 16-byte aligned");
+    return HM_OK;
+}
+
 int check_table(const hm_table_t *t) {
     if (!t || !t->slots || !t->status) return fail(HM_EINVAL, "table or its buffers are NULL");
     if (!pow2(t->capacity)) return fail(HM_EINVAL, "table capacity must be a power of two");
@@ -270,6 +326,8 @@ size_t hm_table_bytes(uint64_t capacity) { return (size_t)capacity * HM_SLOT_BYT
 size_t hm_bloom_bytes(uint64_t n_words) { return (size_t)n_words * 8; }
 
 size_t hm_list_bytes(uint64_t capacity) { return (size_t)capacity * 17; }
+
+size_t hm_occ_bytes(uint64_t capacity) { return (size_t)capacity * 17; }
 
 int hm_check_params(const hm_params_t *p) {
     if (!p) return fail(HM_EINVAL, "params is NULL");
@@ -312,6 +370,12 @@ int hm_list_init(hm_list_t *l, hipStream_t s) {
     return fill<uint64_t>(l->count, 1, 0ull, s);
 }
 
+int hm_occ_init(hm_occ_t *o, hipStream_t s) {
+    int rc = check_occ(o);
+    if (rc) return rc;
+    return fill<uint64_t>(o->count, 1, 0ull, s);
+}
+
 int hm_status(const hm_table_t *t, hipStream_t s) {
     if (!t || !t->status) return fail(HM_EINVAL, "table status is NULL");
     hipError_t e = hipStreamSynchronize(s);
@@ -321,6 +385,8 @@ int hm_status(const hm_table_t *t, hipStream_t s) {
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
     if (st & HM_ST_TIMEOUT) return fail(HM_ETIMEOUT, "a batched-phase wait passed its bound (status 0x%x)", st);
     if (st & HM_ST_OVERFLOW) return fail(HM_EOVERFLOW, "a k-mer counter passed 2^32 - 1 (status 0x%x)", st);
+    if (st & HM_ST_STREAM_FULL)
+        return fail(HM_ECAPACITY, "occurrence stream overflowed before pass 1 (status 0x%x)", st);
     if (st & (HM_ST_TABLE_FULL | HM_ST_LIST_FULL))
         return fail(HM_ECAPACITY, "%s full (status 0x%x)", (st & HM_ST_TABLE_FULL) ? "count table" : "first-occurrence list",
                     st);
@@ -450,6 +516,32 @@ int hm_bloom_insert(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, hm
 #undef LAUNCH_VAR
     }
     HM_LAUNCH_CHECK("hm_bloom_insert");
+    return HM_OK;
+}
+
+int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, hm_table_t *t, hm_list_t *l,
+                        hipStream_t s) {
+    int rc = check_occ(o);
+    if (rc) return rc;
+    // the Bloom filter and list are set up as for pass 1 over reads; the reads are the stream
+    const hm_reads_t none = {nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
+    PassArgs a;
+    rc = make_args(&none, p, b, t, l, a, true);
+    if (rc) return rc;
+    const bool two = p->k >= 32;
+    const bool checked = (p->flags & HM_CHECKED) != 0;
+    const bool heavy = a.n_heavy > 0;
+    const size_t lds = heavy_lds_bytes(a.n_heavy);
+    const dim3 g((unsigned)(device_cus() * 8));
+    const unsigned long long *cnt = reinterpret_cast<const unsigned long long *>(o->count);
+#define LAUNCH_S(KW, CH, HV) \
+    hipLaunchKernelGGL((k_pass1_stream<KW, CH, HV>), g, dim3(kBlock), lds, s, a, o->keys, o->ext, cnt, o->capacity)
+#define LAUNCH_S2(KW, CH) do { if (heavy) LAUNCH_S(KW, CH, true); else LAUNCH_S(KW, CH, false); } while (0)
+    if (two) { if (checked) LAUNCH_S2(2, true); else LAUNCH_S2(2, false); }
+    else { if (checked) LAUNCH_S2(1, true); else LAUNCH_S2(1, false); }
+#undef LAUNCH_S2
+#undef LAUNCH_S
+    HM_LAUNCH_CHECK("hm_bloom_insert_occ");
     return HM_OK;
 }
 

@@ -98,6 +98,46 @@ def pack_reads(ascii: torch.Tensor, qual: torch.Tensor, read_len: int | None = N
     return out
 
 
+class OccStream:
+    """Owned-occurrence stream (hm_occ_t, 17 bytes per entry): written by the
+    cardinality pass (CardSketch.update(..., occ=stream)), read by pass 1
+    (KmerCounter.insert_occ) in place of the reads, for the sharded shape
+    where an owner keeps a small share of all windows."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.capacity = int(capacity)
+        self.device = torch.device(device)
+        n = max(self.capacity, 1)
+        self.keys = torch.empty(2 * n, dtype=torch.int64, device=self.device)
+        self.ext = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.occ = abi.Occ(self.keys.data_ptr(), self.ext.data_ptr(), self.capacity, self.count.data_ptr())
+
+    @staticmethod
+    def slack(launches: int = 1, device=None) -> int:
+        """Entries a cardinality launch can leave as holes: every wave (4 per workgroup, 4 workgroups
+        per CU) may leave up to 1023 of its last 1024-entry chunk unused."""
+        cus = torch.cuda.get_device_properties(device or torch.cuda.current_device()).multi_processor_count
+        return int(launches) * cus * 16 * 1023
+
+    @classmethod
+    def for_windows(cls, windows: int, n_owners: int, launches: int, device="cuda") -> "OccStream":
+        """A stream for the owned share of `windows` windows: the expected share plus 2% and the
+        hole slack (an overflow is reported and the pass rerun with a larger stream)."""
+        share = int(windows / max(n_owners, 1) * 1.02) + 4096
+        return cls(min(share, windows) + cls.slack(launches, device), device=device)
+
+    def reset(self, stream=None):
+        abi.call("hm_occ_init", ctypes.byref(self.occ), _stream(stream))
+
+    def entries(self) -> int:
+        """Entries reserved so far, holes included (synchronizes)."""
+        return int(self.count.item())
+
+    def overflowed(self) -> bool:
+        return self.entries() > self.capacity
+
+
 class Records:
     """Device export buffer (structure of arrays)."""
 
@@ -321,6 +361,12 @@ class KmerCounter:
                  None if self.bypass else ctypes.byref(self.bloom), ctypes.byref(self.table),
                  None if self.bypass else ctypes.byref(self.list), _stream(stream))
 
+    def insert_occ(self, occ: "OccStream", stream=None):
+        """Pass 1 over an owned-occurrence stream written by the cardinality pass."""
+        abi.call("hm_bloom_insert_occ", ctypes.byref(occ.occ), ctypes.byref(self.params),
+                 None if self.bypass else ctypes.byref(self.bloom), ctypes.byref(self.table),
+                 None if self.bypass else ctypes.byref(self.list), _stream(stream))
+
     def count(self, stream=None):
         abi.call("hm_kmer_count", None, ctypes.byref(self.params), ctypes.byref(self.table),
                  None if self.bypass else ctypes.byref(self.list), _stream(stream))
@@ -348,6 +394,16 @@ class KmerCounter:
         self.reset(stream)
         for p in batches:
             self.insert(p, stream)
+        self._finish(out, flags, stream, digest, fused)
+
+    def run_occ(self, occ: OccStream, out: Records, flags: int = 0, stream=None, digest: bool = True,
+                fused: bool = False):
+        """As run(), with pass 1 over an owned-occurrence stream instead of the reads."""
+        self.reset(stream)
+        self.insert_occ(occ, stream)
+        self._finish(out, flags, stream, digest, fused)
+
+    def _finish(self, out: Records, flags: int, stream, digest: bool, fused: bool):
         self.count(stream)
         if fused:
             self.export(out, flags | abi.HM_EXPORT_CLASSIFY, stream, digest)
@@ -419,10 +475,15 @@ class CardSketch:
     def reset(self, stream=None):
         abi.call("hm_card_init", ctypes.byref(self.card), _stream(stream))
 
-    def update(self, packed: Packed, stream=None):
+    def update(self, packed: Packed, stream=None, occ: OccStream | None = None):
+        """Add a batch of reads; with `occ`, also append its owned occurrences to that stream."""
         r = packed.struct()
-        abi.call("hm_cardinality", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
-                 _stream(stream))
+        if occ is None:
+            abi.call("hm_cardinality", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
+                     _stream(stream))
+        else:
+            abi.call("hm_cardinality_occ", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
+                     ctypes.byref(occ.occ), _stream(stream))
 
     def summarize(self, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int | None = None, stream=None):
         """Launch hm_card_summary (asynchronous); result() reads it.  Up to heavy_cap heavy keys
@@ -449,10 +510,13 @@ class CardSketch:
                           self.heavy_log2, hk[order, 0].copy(), hk[order, 1].copy(), rc)
 
     def run(self, batches, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int | None = None,
-            stream=None) -> CardResult:
+            stream=None, occ: OccStream | None = None) -> CardResult:
+        """The whole pass over `batches`; with `occ` (reset here) their owned occurrences are written to it."""
         self.reset(stream)
+        if occ is not None:
+            occ.reset(stream)
         for p in batches:
-            self.update(p, stream)
+            self.update(p, stream, occ)
         self.summarize(min_depth, heavy_min, heavy_cap, stream)
         return self.result(stream)
 
@@ -516,7 +580,7 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
             seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
             present_filter: bool = True, sizing: str = "card", heavy: bool = True,
-            bloom_in_table: bool = True) -> dict:
+            bloom_in_table: bool = True, occ_stream: bool = False, occ_capacity: int | None = None) -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
     Sizes not given are planned from a cardinality pass over the reads
@@ -525,7 +589,10 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     a capacity error the table (or list) is doubled and the run repeated from
     scratch, which keeps the result exact.  heavy: count the heavy hitters the
     cardinality pass finds in workgroup-local memory (sizing="card" only).  bloom_in_table: the
-    Bloom filter in the table's slots (KmerCounter) or a separate one."""
+    Bloom filter in the table's slots (KmerCounter) or a separate one.  occ_stream: the
+    cardinality pass writes the owned occurrences to a stream (occ_capacity entries, default
+    OccStream.for_windows; doubled and rerun on overflow) and pass 1 reads it instead of the
+    reads (sizing="card" only)."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
     q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
@@ -535,9 +602,21 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
         (abi.HM_CHECKED if checked else 0)
     card = None
-    if sizing == "card" and (heavy or not (capacity and bloom_words and list_capacity is not None)):
+    occ = None
+    if occ_stream and sizing != "card":
+        raise ValueError("occ_stream needs sizing='card' (the cardinality pass writes the stream)")
+    if sizing == "card" and (heavy or occ_stream or not (capacity and bloom_words and list_capacity is not None)):
         sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
-        card = sk.run([packed], min_depth=min_depth)
+        if occ_stream:
+            occ = OccStream(occ_capacity, device=dev) if occ_capacity is not None else \
+                OccStream.for_windows(P, n_owners, 1, device=dev)
+            while True:
+                card = sk.run([packed], min_depth=min_depth, occ=occ)
+                if not occ.overflowed():
+                    break
+                occ = OccStream(2 * max(occ.capacity, occ.entries()), device=dev)
+        else:
+            card = sk.run([packed], min_depth=min_depth)
         c_cap, c_bw, c_lcap = plan_sizes(card, n_hash=n_hash, device=dev, bloom_in_table=bloom_in_table)
         del sk
         if bypass or min_depth == 1:  # every distinct k-mer goes into the table
@@ -555,7 +634,10 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
                          heavy=card if heavy else None, bloom_in_table=bloom_in_table,
                          device=dev)
         out = Records(kc.capacity, device=dev)
-        kc.run([packed], out, flags=export_flags, fused=fused)
+        if occ is not None:
+            kc.run_occ(occ, out, flags=export_flags, fused=fused)
+        else:
+            kc.run([packed], out, flags=export_flags, fused=fused)
         rc = kc.status()
         if rc == abi.HM_OK:
             res = out.to_numpy(sort=not (export_flags & abi.HM_EXPORT_SORTED))
@@ -564,6 +646,9 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             res["capacity"] = kc.capacity
             res["stats"] = kc.stats()
             res["n_heavy"] = kc.table.n_heavy
+            if occ is not None:
+                res["occ_entries"] = occ.entries()
+                res["card_positions"] = card.positions
             return res
         if rc == abi.HM_ECAPACITY:
             st = int(kc.status_buf.item())

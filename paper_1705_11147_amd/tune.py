@@ -19,11 +19,11 @@ import os
 
 import torch
 
-from .batch import Batch, SetSpec, Tuning
+from .batch import MAX_BLOCKS_PER_CU, Batch, SetSpec, Tuning
 
 LAUNCH_SPACE = {
     "set_major": [2, 1, 3, 0],
-    "blocks_per_cu": [4, 8, 12],
+    "blocks_per_cu": [4, 8, MAX_BLOCKS_PER_CU],  # the sets' list slack covers every value here
     "tile_bases": [16384, 32768, 65536, 131072],
     "list_per_item": [16384, 65536],
     "slots_per_item": [32768, 131072],
@@ -71,6 +71,7 @@ def autotune(specs: list[SetSpec], k: int, sample: int = 16, reps: int = 2, cach
     sub = [specs[i] for i in order[::step]][:sample]
     best = Tuning()
     trials = []
+    rejected = []
     reference = None
 
     def run(tu: Tuning, batch: Batch | None = None):
@@ -81,7 +82,10 @@ def autotune(specs: list[SetSpec], k: int, sample: int = 16, reps: int = 2, cach
             b._prepare()
         ms = _time(b, reps)
         st = b.status()
-        if any(x != 0 for x in st):
+        if any(x != 0 for x in st):  # reported, never timed as a valid candidate
+            rejected.append({"tuning": dataclasses.asdict(tu), "status": st})
+            if log:
+                log("tune %s: rejected, set statuses %s" % (tu.key(), sorted(set(st))))
             return None, b
         dig = b.digests()
         if reference is None:
@@ -116,7 +120,7 @@ def autotune(specs: list[SetSpec], k: int, sample: int = 16, reps: int = 2, cach
             if ms is not None and ms < best_ms:
                 best, best_ms = tu, ms
     report = {"key": key, "tuning": dataclasses.asdict(best), "ms": best_ms, "sample_sets": len(sub),
-              "trials": trials}
+              "trials": trials, "rejected": rejected}
     if cache_path:
         try:
             cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}

@@ -111,6 +111,41 @@ def test_host_side_rejections_touch_no_device(L):
     assert L.hm_export_table(ctypes.byref(t), 99, ctypes.byref(e), None) == abi.HM_EINVAL
 
 
+def test_occ_stream_rejections(L):
+    """The owned-occurrence stream's entry points reject bad arguments on the host."""
+    assert L.hm_occ_bytes(10) == 170
+    assert L.hm_occ_init(None, None) == abi.HM_EINVAL
+    o = abi.Occ(64, 64, 10, None)  # no counter
+    assert L.hm_occ_init(ctypes.byref(o), None) == abi.HM_EINVAL
+    o = abi.Occ(None, None, 10, 64)  # arrays missing for a non-empty stream
+    assert L.hm_occ_init(ctypes.byref(o), None) == abi.HM_EINVAL
+    o = abi.Occ(72, 64, 10, 64)  # keys not 16-byte aligned
+    assert L.hm_occ_init(ctypes.byref(o), None) == abi.HM_EINVAL
+    assert "aligned" in abi.last_error()
+    t = abi.Table(64, 1024, 0, 31, 64, None)
+    good = abi.Occ(64, 64, 10, 64)
+    # pass 1 over a stream: the same parameter, table, filter and list checks as over reads
+    assert L.hm_bloom_insert_occ(ctypes.byref(o), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_BYPASS)), None,
+                                 ctypes.byref(t), None, None) == abi.HM_EINVAL
+    assert L.hm_bloom_insert_occ(ctypes.byref(good), ctypes.byref(P(k=21, flags=abi.HM_BLOOM_BYPASS)), None,
+                                 ctypes.byref(t), None, None) == abi.HM_EINVAL  # k mismatch with the table
+    assert L.hm_bloom_insert_occ(ctypes.byref(good), ctypes.byref(P(k=31)), None, ctypes.byref(t), None,
+                                 None) == abi.HM_EINVAL  # Bloom needed
+    b = abi.Bloom(None, 0, 4)
+    assert L.hm_bloom_insert_occ(ctypes.byref(good), ctypes.byref(P(k=31, flags=abi.HM_BLOOM_IN_TABLE)),
+                                 ctypes.byref(b), ctypes.byref(t), None, None) == abi.HM_EINVAL
+    assert "list" in abi.last_error()
+    # the card pass with a stream: a bad stream is rejected after the sketch's own checks
+    tab = abi.Table(64, 1024, 0, 31, 64, None)
+    c = abi.Card(64, 14, 10, 8, 0, 64, tab, tab)
+    r = abi.Reads(8, 8, 8, None, 1, 100, 100)
+    assert L.hm_cardinality_occ(ctypes.byref(r), ctypes.byref(P(k=31)), ctypes.byref(c), ctypes.byref(o),
+                                None) == abi.HM_EINVAL
+    assert "aligned" in abi.last_error()
+    assert L.hm_cardinality_occ(ctypes.byref(r), ctypes.byref(P(k=31)), ctypes.byref(c), None,
+                                None) == abi.HM_EINVAL
+
+
 def test_random_access_rejects(L):
     assert L.hm_random_access(None, 1024, 0, 10, 1, 8, None) == abi.HM_EINVAL
     assert L.hm_random_access(8, 1000, 0, 10, 1, 8, None) == abi.HM_EINVAL
@@ -132,7 +167,7 @@ def test_package_import_is_lazy_and_loud():
 
 C_NAMES = {"Reads": "hm_reads_t", "Params": "hm_params_t", "Table": "hm_table_t", "Bloom": "hm_bloom_t",
            "List": "hm_list_t", "Export": "hm_export_t", "Card": "hm_card_t", "CardSummary": "hm_card_summary_t",
-           "Contigs": "hm_contigs_t", "BatchSet": "hm_batch_set_t",
+           "Contigs": "hm_contigs_t", "Occ": "hm_occ_t", "BatchSet": "hm_batch_set_t",
            "BatchTuning": "hm_batch_tuning_t", "BatchPlan": "hm_batch_plan_t"}
 
 

@@ -126,10 +126,11 @@ def test_fixed_length_reads(k, L):
 @pytest.mark.parametrize("k,L", [(1, 4), (5, 12), (21, 100), (31, 31), (33, 40), (51, 150), (63, 200),
                                  (15, 16384 - 64)])
 def test_owner_filtered_fixed_reads(k, L):
-    """Fixed-length reads with an owner filter take the rolled window loop (a run of 8 windows per
-    lane, codes rolled one base at a time): every owner of 3 against the oracle, with N bases,
-    low-quality bases and runs cut short at read ends (L - k + 1 windows per read: below 8, exactly
-    8, one, and not a multiple of 8), 2k just above 64 bits, one read per tile; and forward-only keys."""
+    """Fixed-length reads with an owner filter take the queued pass 1 (k_pass1_owned: each
+    workgroup queues its owned occurrences in LDS and counts them 256 at a time with every lane
+    busy): every owner of 3 against the oracle, with N bases, low-quality bases, few windows per
+    read (L - k + 1 below 8, exactly 8, one, not a multiple of 8), 2k just above 64 bits, one read
+    per tile; and forward-only keys."""
     n = max(3, 300_000 // L)
     rng = np.random.default_rng(1000 + k)
     g = rng.choice(np.frombuffer(b"ACGT", np.uint8), 20000)
