@@ -299,6 +299,24 @@ int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
  * more), or takes a counting pass per 8 key bits (shorter keys). */
 int hm_export_table(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * hm_export_table whose key-ordered export (HM_EXPORT_SORTED) takes its
+ * scratch from an array the library holds on each GPU instead of
+ * out->sort_work (out->sort_work and out->sort_work_bytes are ignored).
+ * Limit: out->capacity <= HM_EXPORT_STATIC_MAX_RECORDS (2^18 records; the
+ * array is 24 MiB per GPU, held from the library's load on that GPU until the
+ * process ends); a larger capacity returns HM_EINVAL before any device work.
+ * Nothing is allocated.  The first call on a device looks up the array's
+ * address there (make one call before capturing a graph).  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents (each
+ * call writes what it reads, so nothing needs clearing): calls that overlap
+ * on one GPU (two streams, two host threads) race and give wrong records.
+ * Without HM_EXPORT_SORTED it is hm_export_table.  Output equals
+ * hm_export_table's with a caller scratch. */
+#define HM_EXPORT_STATIC_MAX_RECORDS (1u << 18)
+int hm_export_table_static(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t stream);
+
 
 /* ---- cardinality pass: sizing and heavy hitters, before pass 1 -------- */
 

@@ -38,6 +38,7 @@ HM_EXPORT_ALL = 2
 HM_EXPORT_CLASSIFY = 4
 HM_EXPORT_SORTED = 8
 HM_MAX_HEAVY = 256
+HM_EXPORT_STATIC_MAX_RECORDS = 1 << 18
 
 HM_CLS_FORK = 4
 HM_CLS_X = 5
@@ -145,6 +146,7 @@ SIGNATURES = {
     "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),
     "hm_classify_ext": ([P(Params), P(Table), vp], ctypes.c_int),
     "hm_export_table": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
+    "hm_export_table_static": ([P(Table), ctypes.c_uint32, P(Export), vp], ctypes.c_int),
     "hm_card_init": ([P(Card), vp], ctypes.c_int),
     "hm_cardinality": ([P(Reads), P(Params), P(Card), vp], ctypes.c_int),
     "hm_card_summary": ([P(Card), ctypes.c_uint32, ctypes.c_uint32, vp, ctypes.c_uint64, vp, vp], ctypes.c_int),

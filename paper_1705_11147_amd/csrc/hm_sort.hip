@@ -37,6 +37,8 @@
 // Keys in a table are distinct, so the final order is unique.
 #include "hm_device.h"
 
+#include <mutex>
+
 namespace hm {
 namespace {
 
@@ -603,6 +605,62 @@ int sort_export(const hm_export_t &out, int key_bits, hipStream_t s) {
     return key_bits > 64 ? sort_keys<2>(out, L, key_bits, s) : sort_keys<1>(out, L, key_bits, s);
 }
 
+// ------------------------------------------------------------------ scratch held by the library
+
+// The key-ordered export's scratch for callers that cannot allocate
+// (hm_export_table_static): a device array of the library's code object,
+// allocated on each GPU when the library is loaded there and held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is only a stand-in): the array's device address is looked up
+// once per device and kept in g_scratch.
+constexpr uint64_t kStaticRecords = HM_EXPORT_STATIC_MAX_RECORDS;
+constexpr uint64_t kStaticBytes = 24ull << 20;  // >= sort_work_bytes(kStaticRecords), checked at first use
+
+static __device__ __align__(256) uint8_t scratch[kStaticBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch[64];
+
+// Device address of this device's scratch array (looked up on the first call
+// on each device, with that device current).
+static int static_scratch(void **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(HM_EINVAL, "device %d out of range for the static scratch", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || (((uintptr_t)p) & 255)) return fail(HM_EHIP, "static scratch: bad device address %p", p);
+        g_scratch[dev] = p;
+    }
+    *ptr = g_scratch[dev];
+    return HM_OK;
+}
+
 }  // namespace hm
 
 extern "C" size_t hm_export_sort_bytes(uint64_t capacity) { return (size_t)hm::sort_work_bytes(capacity); }
+
+extern "C" int hm_export_table_static(const hm_table_t *t, uint32_t flags, hm_export_t *out, hipStream_t s) {
+    using namespace hm;
+    if (!(flags & HM_EXPORT_SORTED)) return hm_export_table(t, flags, out, s);  // no scratch needed
+    if (!out) return fail(HM_EINVAL, "export: out is NULL");
+    if (out->capacity > kStaticRecords)
+        return fail(HM_EINVAL, "hm_export_table_static: export capacity %llu exceeds the static scratch's %llu records",
+                    (unsigned long long)out->capacity, (unsigned long long)kStaticRecords);
+    static_assert(kStaticRecords < (1ull << 32), "record indices are 32-bit");
+    if (sort_work_bytes(kStaticRecords) > kStaticBytes)
+        return fail(HM_EINVAL, "static scratch of %llu bytes is smaller than the %llu a sort of %llu records needs",
+                    (unsigned long long)kStaticBytes, (unsigned long long)sort_work_bytes(kStaticRecords),
+                    (unsigned long long)kStaticRecords);
+    void *p = nullptr;
+    const int rc = static_scratch(&p);
+    if (rc) return rc;
+    hm_export_t o = *out;  // the same outputs; only the scratch differs
+    o.sort_work = p;
+    o.sort_work_bytes = kStaticBytes;
+    return hm_export_table(t, flags, &o, s);
+}

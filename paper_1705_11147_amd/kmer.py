@@ -374,11 +374,15 @@ class KmerCounter:
     def classify(self, stream=None):
         abi.call("hm_classify_ext", ctypes.byref(self.params), ctypes.byref(self.table), _stream(stream))
 
-    def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
+    def export(self, out: Records, flags: int = 0, stream=None, digest: bool = True, static: bool = False):
         """hm_export_table; with abi.HM_EXPORT_CLASSIFY in flags the export
-        classifies from the counters (no hm_classify_ext needed before)."""
-        e = out.struct(digest, self.params.min_depth, self.params.ext_min, sort=bool(flags & abi.HM_EXPORT_SORTED))
-        abi.call("hm_export_table", ctypes.byref(self.table), flags, ctypes.byref(e), _stream(stream))
+        classifies from the counters (no hm_classify_ext needed before).  static: the
+        no-allocation variant hm_export_table_static (a key-ordered export's scratch is the
+        library's own array; out.capacity <= abi.HM_EXPORT_STATIC_MAX_RECORDS)."""
+        sort = bool(flags & abi.HM_EXPORT_SORTED) and not static
+        e = out.struct(digest, self.params.min_depth, self.params.ext_min, sort=sort)
+        abi.call("hm_export_table_static" if static else "hm_export_table", ctypes.byref(self.table), flags,
+                 ctypes.byref(e), _stream(stream))
 
     def stats(self) -> dict:
         """Event counters of the counting passes (synchronizes)."""
