@@ -2,14 +2,19 @@
 """Benchmark: k-mer analysis throughput (k-mers/s) on one MI355X.
 
 One step = the whole path over one read set already resident in HBM (ASCII
-bases + Phred bytes): pack -> table/Bloom/list init -> pass 1 (Bloom test +
-insert/count) -> pass 2 (first occurrences) -> classify -> export.  The
-workload is the mid-size read set: 100 Mbp synthetic genome with 5%
-segmental repeats, 20M reads of 150 bp (30x), 0.5% end-biased substitution
-errors, Phred ~ clamp(N(32,6),2,41), k=51, Q20, min depth 2.
+bases + Phred bytes): pack -> cardinality pass -> table/Bloom/list init ->
+pass 1 (Bloom test + insert/count) -> pass 2 (first occurrences) -> classify
++ export.  The headline workload is the mid-size read set: 100 Mbp synthetic
+genome with 5% segmental repeats, 20M reads of 150 bp (30x), 0.5% end-biased
+substitution errors, Phred ~ clamp(N(32,6),2,41), k=51, Q20, min depth 2.
 
-Prints ONE JSON line with the throughput, the dominant kernel's place on the
-HBM random-access roofline and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line: the throughput; the dominant kernel's place on the HBM
+roofline; one key shard of the timed export checked against the CPU oracle;
+the oracle timed on a bounded sample (whose table the GPU must reproduce);
+and, as sub-records, the batched form (64 read sets) against the plain form,
+the serving loop, and one GPU's share of the human-scale run (owner 0 of 16,
+ten 64M-read batches) with a sub-shard of its table checked against the
+oracle.
 """
 from __future__ import annotations
 
@@ -32,6 +37,41 @@ LINE = 64  # bytes moved by one random access (HBM/L2 line granularity)
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_threads() -> int:
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+RECORD_FIELDS = ("key_hi", "key_lo", "count", "tl", "tr", "cls_l", "cls_r")
+
+
+def device_rows(rec, idx) -> dict:
+    """Host copies of the records `idx` (a device index tensor) of an export buffer, in key order."""
+    n = int(idx.numel())
+    t = {"key_hi": rec.key_hi[idx].cpu().numpy().view(np.uint64),
+         "key_lo": rec.key_lo[idx].cpu().numpy().view(np.uint64),
+         "count": rec.count[idx].cpu().numpy().view(np.uint32),
+         "tl": rec.tl.view(-1, 4)[idx].cpu().numpy().view(np.uint32).reshape(n, 4),
+         "tr": rec.tr.view(-1, 4)[idx].cpu().numpy().view(np.uint32).reshape(n, 4),
+         "cls_l": rec.cls_l[idx].cpu().numpy(), "cls_r": rec.cls_r[idx].cpu().numpy()}
+    order = np.lexsort((t["key_lo"], t["key_hi"]))
+    return {x: v[order] for x, v in t.items()}
+
+
+def same_records(a: dict, b: dict) -> bool:
+    """Field-by-field equality of two key-ordered record sets."""
+    return len(a["count"]) == len(b["count"]) and all(np.array_equal(a[f], b[f]) for f in RECORD_FIELDS)
 
 
 def source_digest(paths) -> str:
@@ -156,6 +196,7 @@ def run_batched(args, dev, log):
     ms_p = timed(b.run_plain, args.steps)
     st = b.status()
     same = st == [abi.HM_OK] * len(st) and b.digests() == ref
+    assert same, "batched and plain forms disagree (statuses %s)" % sorted(set(st))
     return {"workload": "batched-64-sets-0.5to8Mbp-10to60x-150bp-k31", "sets": len(ws), "positions": positions,
             "batched_kmers_per_s": round(positions / (ms_b / 1000), 1), "batched_ms": round(ms_b, 3),
             "plain_kmers_per_s": round(positions / (ms_p / 1000), 1), "plain_ms": round(ms_p, 3),
@@ -192,6 +233,8 @@ def run_serving(args, dev, log):
         sch = Scheduler(GpuBackend(51, device=dev), budget, slots,
                         max_planning=args.serve_planners if slots > 1 else 1, plan_while_busy=slots > 1)
         recs = sch.run(jobs)
+        bad = [r.job for r in recs if r.status != 0 or r.result is None]
+        assert not bad, "serving (%s): jobs %s failed" % (name, bad[:10])
         res = summarize(recs, positions, sch.trace)
         res["slots"] = slots
         res["planners"] = args.serve_planners if slots > 1 else 1
@@ -202,6 +245,7 @@ def run_serving(args, dev, log):
             results = {r.job: r.result for r in recs}
         else:
             same = all(results[r.job] == r.result for r in recs)
+            assert same, "a job's output differs between the continuous mix and one-at-a-time serving"
             out["identical_alone_vs_mix"] = bool(same)
     return out
 
@@ -287,22 +331,32 @@ def owner_zero_mask(key_hi, key_lo, bits: int):
     return srl(h, 64 - bits) == 0 if bits > 0 else torch.ones_like(h, dtype=torch.bool)
 
 
-def run_human_share(args, dev):
+def run_human_share(args, dev) -> dict:
     """One GPU's share of the human-scale run at its real shape (owner 0 of 16; reads in
-    64M-read batches kept packed on the device), timed from the cardinality pass to the
-    exported table.  Checked by a single-pass count without the Bloom filter of the 1/64
-    sub-shard owner 0 of 1024, which must equal the main table's records of that sub-shard."""
+    64M-read batches kept packed on the device), timed from the cardinality pass to the exported
+    table.  The cardinality pass writes the owned occurrences to a stream that pass 1 reads.
+    Checked against the CPU oracle on the 1/64 sub-shard owner 0 of 1024 (the owners nest): the
+    oracle counts every batch's windows as the batch is generated (oracle.Accumulator, the
+    sort-counted scheme on every host core), and the sub-shard's records of the GPU table must
+    equal its records field by field."""
     import torch
+    import oracle
     from paper_1705_11147_amd import abi, kmer, synth
 
     t0 = time.time()
-    w = synth.human_share(scale=args.scale)
+    w = synth.human_share(scale=args.human_scale)
     p = w.params
     L, k = w.read_len, p.k
     nb = w.meta["batch_reads"]
     cuts = list(range(0, w.n_reads, nb)) + [w.n_reads]
     log("workload %s: genome %.3g bp, %d reads in %d batches (genome built in %.1fs)" % (
         w.name, w.meta["G"], w.n_reads, len(cuts) - 1, time.time() - t0))
+    sub_bits = 10  # the checked sub-shard: owner 0 of 2^10, inside owner 0 of 16
+    threads = host_threads()
+    # every key of the sub-shard (keep_all), so that the counts also give its exact occurrence total
+    acc = None if args.no_human_oracle else oracle.Accumulator(
+        k, qcut=p.qcut, min_depth=p.min_depth, n_owners=1 << sub_bits, owner=0, sort_count=True, n_threads=threads,
+        keep_all=True)
     packs, gen_s, up_ms, pack_ms = [], 0.0, 0.0, 0.0
     for b in range(len(cuts) - 1):
         t1 = time.time()
@@ -315,11 +369,14 @@ def run_human_share(args, dev):
         e[1].record()
         packs.append(kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut))
         e[2].record()
+        if acc is not None:  # the oracle counts this batch on the host while the device packs it
+            acc.add(r.ascii, r.qual, r.offsets())
         torch.cuda.synchronize()
         up_ms += e[0].elapsed_time(e[1])
         pack_ms += e[1].elapsed_time(e[2])
         del ascii, qual, r
-        log("batch %d of %d: %d reads generated, uploaded and packed" % (b + 1, len(cuts) - 1, cuts[b + 1] - cuts[b]))
+        log("batch %d of %d: %d reads generated, uploaded and packed%s" % (
+            b + 1, len(cuts) - 1, cuts[b + 1] - cuts[b], "; oracle %.1fs so far" % acc.seconds if acc else ""))
     torch.cuda.empty_cache()
     scanned = w.n_reads * (L - k + 1)
     sketch = kmer.CardSketch(k, scanned, n_owners=p.n_owners, owner=p.owner, device=dev)
@@ -330,11 +387,12 @@ def run_human_share(args, dev):
     if occ is not None and occ.overflowed():  # the share was larger than planned: rerun with room for it
         occ = kmer.OccStream(card.positions + kmer.OccStream.slack(len(packs), dev), device=dev)
         card = sketch.run(packs, min_depth=p.min_depth, occ=occ)
-    cap, bloom_words, list_cap = kmer.plan_sizes(card, pass1_launches=len(packs), device=dev)
+    cap, bloom_words, list_cap = kmer.plan_sizes(card, pass1_launches=1 if use_occ else len(packs), device=dev)
     kc = kmer.KmerCounter(k, cap, bloom_words, list_cap, n_owners=p.n_owners, owner=p.owner, heavy=card, device=dev)
     out = kmer.Records(int(min(kc.capacity, card.kept_hi() * 1.3 + 1024)), device=dev)
-    log("owned: %.4g windows, %.4g distinct (HLL) -> table 2^%d slots (%.1f GB), list %.3g entries" % (
-        card.positions, card.estimate, kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, list_cap))
+    log("owned: %.4g windows, %.4g distinct (HLL) -> table 2^%d slots (%.1f GB), list %.3g entries%s" % (
+        card.positions, card.estimate, kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9, list_cap,
+        ", stream %.3g entries (%.1f GB)" % (occ.capacity, occ.capacity * 17 / 1e9) if occ else ""))
     stages = ["card", "init", "pass1", "pass2", "classify_export"]
 
     def step(ev):
@@ -361,11 +419,14 @@ def run_human_share(args, dev):
 
     n_steps = max(1, min(args.steps, 3))
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(n_steps + 1)]
+    digests = []
     for s in range(n_steps + 1):  # the first is a warm-up
         step(events[s])
         torch.cuda.synchronize()
         abi.check(kc.status(), "human share step")
+        digests.append(out.digest_words())
         log("step %d of %d done" % (s + 1, n_steps + 1))
+    assert len(set(digests)) == 1, "the human-share table changed between steps"
     timed = events[1:]
     stage_ms = {x: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in timed])) for i, x in enumerate(stages)}
     step_ms = float(np.mean([ev[0].elapsed_time(ev[len(stages)]) for ev in timed]))
@@ -373,51 +434,57 @@ def run_human_share(args, dev):
     st = kc.stats()
     owned = st["occurrences"]
 
-    # the check: the sub-shard owner 0 of 1024 counted in one pass without the Bloom filter
-    sub_bits = 10
-    sk2 = kmer.CardSketch(k, scanned, n_owners=1 << sub_bits, owner=0, device=dev)
-    c2 = sk2.run(packs, min_depth=p.min_depth)
-    kb = kmer.KmerCounter(k, kmer.next_pow2(max(1024, int(c2.distinct_hi() / 0.5))), 1, 0, min_depth=p.min_depth,
-                          n_owners=1 << sub_bits, owner=0, flags=abi.HM_BLOOM_BYPASS, device=dev)
-    ob = kmer.Records(int(c2.distinct_hi() * 1.1 + 1024), device=dev)
-    kb.run(packs, ob, fused=True)
-    abi.check(kb.status(), "sub-shard check")
-    nb_rec = int(ob.n_out.item())
-    sel = owner_zero_mask(out.key_hi[:n_rec], out.key_lo[:n_rec], sub_bits).nonzero().squeeze(1)
-
-    def rows(rec, idx):
-        return np.concatenate([x.cpu().numpy().astype(np.int64).reshape(len(idx), -1) for x in (
-            rec.key_hi[idx], rec.key_lo[idx], rec.count[idx], rec.tl.view(-1, 4)[idx], rec.tr.view(-1, 4)[idx],
-            rec.cls_l[idx], rec.cls_r[idx])], axis=1)
-
-    a = rows(out, sel)
-    b = rows(ob, torch.arange(nb_rec, device=dev))
-    a = a[np.lexsort(a[:, 1::-1].T)]
-    b = b[np.lexsort(b[:, 1::-1].T)]
-    same = a.shape == b.shape and bool((a == b).all())
-    log("sub-shard owner 0 of %d: %d records in the main table, %d in the single-pass count, identical: %s" % (
-        1 << sub_bits, len(a), len(b), same))
-    assert same, "the human-share table disagrees with the single-pass count of its sub-shard"
-    line = {
+    check, cpu = None, None
+    if acc is not None:
+        t2 = time.perf_counter()
+        every = acc.finish()
+        sub_owned = int(every["count"].sum(dtype=np.uint64))  # owned occurrences of the sub-shard
+        kept = every["count"] >= p.min_depth
+        exp = {f: every[f][kept] for f in RECORD_FIELDS}
+        exp["positions"] = every["positions"]
+        del every
+        sel = owner_zero_mask(out.key_hi[:n_rec], out.key_lo[:n_rec], sub_bits).nonzero().squeeze(1)
+        got = device_rows(out, sel)
+        same = same_records(got, exp)
+        log("sub-shard owner 0 of %d: %d records in the GPU table, %d from the oracle, identical: %s (oracle %.1fs)" % (
+            1 << sub_bits, len(got["count"]), len(exp["count"]), same, acc.seconds))
+        assert same, "the human-share table disagrees with the oracle on its sub-shard"
+        assert exp["positions"] == scanned
+        check = {"sub_shard": "owner 0 of %d (1/%d of the share's keys)" % (1 << sub_bits, (1 << sub_bits) // 16),
+                 "records": len(got["count"]), "oracle_identical": same, "compare_s": round(time.perf_counter() - t2, 1)}
+        cpu = {"value": round(sub_owned / acc.seconds, 1), "unit": "k-mers/s", "cores": threads, "kind": "oracle",
+               "sample": "the sub-shard owner 0 of %d: all %.3g windows of the ten batches scanned, its %d owned "
+                         "occurrences counted (sort-counted, %d threads, %.1fs); %s" % (
+                             1 << sub_bits, scanned, sub_owned, threads, acc.seconds, cpu_model()),
+               "scanned_windows_per_s": round(scanned / acc.seconds, 1)}
+    g = LINE
+    s_seen = 1.0 - st["deferred"] / max(owned, 1)
+    bpp = (1.0 + s_seen) * 2 * g + g
+    return {
         "metric": "owned k-mers/s k-mer analysis, one GPU's share of the human-scale run (bit-exact)",
-        "value": round(owned / (step_ms / 1000), 1), "unit": "k-mers/s", "n_gpus": 1, "steps": n_steps,
-        "warmup": 1, "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "value": round(owned / (step_ms / 1000), 1), "unit": "k-mers/s", "steps": n_steps, "warmup": 1,
+        "ms_per_step": round(step_ms, 3),
         "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": w.n_reads, "read_len": L, "k": k,
                    "n_owners": p.n_owners, "owner": p.owner, "batches": len(packs),
                    "scanned_positions": scanned, "owned_positions": owned,
                    "scanned_positions_per_s": round(scanned / (step_ms / 1000), 1),
                    "kept_kmers": n_rec, "table_slots": kc.capacity, "list_capacity": list_cap,
-                   "hll_estimate": round(card.estimate, 1),
-                   "step": "cardinality + init + pass 1 over every batch + pass 2 + classify/export; "
-                           "packed reads resident in HBM",
+                   "occ_stream_entries": occ.capacity if occ else 0, "hll_estimate": round(card.estimate, 1),
+                   "step": "cardinality pass writing the owned occurrences + init + pass 1 over them + pass 2 + "
+                           "classify/export; packed reads resident in HBM" if occ else
+                           "cardinality + init + pass 1 over every batch + pass 2 + classify/export; packed reads "
+                           "resident in HBM",
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
                    "outside_step": {"generate_s": round(gen_s, 1), "h2d_ms": round(up_ms, 1),
                                     "pack_ms": round(pack_ms, 1)}},
-        "check": {"sub_shard": "owner 0 of %d" % (1 << sub_bits), "records": len(a), "identical": same},
+        "roofline": {"kernel": "k_pass1_stream" if occ else "k_pass1_owned", "bound": "hbm",
+                     "bytes_per_position": round(bpp, 1), "s": round(s_seen, 4),
+                     "frac": round(bpp * owned / (stage_ms["pass1"] / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_step": round(bpp * owned / (step_ms / 1000) / 1e9 / HBM_PEAK_GBS, 4)},
+        "oracle_check": check,
+        "cpu_baseline": cpu,
         "events_per_owned_position": {x: round(v / max(owned, 1), 4) for x, v in st.items()},
     }
-    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -430,8 +497,11 @@ def main():
                     help="mid: the headline workload; mid-heavy: mid with 2%% satellite arrays (heavy hitters); "
                          "human-share: one GPU's share of the human-scale run (owner 0 of 16, streamed batches; "
                          "its own JSON line)")
-    ap.add_argument("--cpu-sample-reads", type=int, default=300_000)
+    ap.add_argument("--cpu-sample-reads", type=int, default=2_000_000,
+                    help="reads of the headline workload the CPU oracle is timed on (default 10%%)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle comparison of one key shard of the timed export")
     ap.add_argument("--no-probe", action="store_true", help="skip the random-access ceiling probe")
     ap.add_argument("--no-sort", action="store_true", help="skip the key-ordered export measurement")
     ap.add_argument("--bloom-bits", type=float, default=12.0,
@@ -456,13 +526,18 @@ def main():
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
-    ap.add_argument("--serve-jobs", type=int, default=60)
+    ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=12)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-scale", type=float, default=1.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-planners", type=int, default=2, help="jobs planned at once in the continuous run")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--no-human-share", action="store_true",
+                    help="skip one GPU's share of the human-scale run (the human_share sub-record)")
+    ap.add_argument("--no-human-oracle", action="store_true",
+                    help="human share: skip the oracle check of its sub-shard (about a minute of host work)")
+    ap.add_argument("--human-scale", type=float, default=1.0, help="human share: workload scale")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this k-mer analysis build runs on a single MI355X "
@@ -476,8 +551,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     abi.lib()
-    if args.workload == "human-share":
-        run_human_share(args, dev)
+    if args.workload == "human-share":  # its own JSON line
+        hs = run_human_share(args, dev)
+        print(json.dumps(dict(hs, n_gpus=1, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="u64",
+                              data="synthetic")), flush=True)
         return
 
     t0 = time.time()
@@ -535,6 +612,10 @@ def main():
     n_records = int(out.n_out.item())
     n_first = int(kc.list_count.item())
     ref_digest = out.digest_words()
+    table_slots = kc.capacity
+    bloom = ({"layout": "in table: the home slot's 32-bit classification word", "bits": kc.capacity * 32}
+             if kc.bloom_in_table else {"layout": "separate: 64-bit words", "bits": kc.bloom_words * 64})
+    bloom.update(n_hash=args.n_hash, bits_per_distinct_kmer=round(bloom["bits"] / card.estimate, 2))
     log("sizes: table 2^%d slots (%.1f GB), bloom %s, list %.2f GB; kept %d, first-occurrence %d" % (
         kc.capacity.bit_length() - 1, kc.capacity * 64 / 1e9,
         "in the table" if kc.bloom_in_table else "%.2f GB" % (kc.bloom_words * 8 / 1e9), list_cap * 17 / 1e9,
@@ -587,28 +668,41 @@ def main():
     value = positions * args.steps / elapsed
     log("stage ms: " + ", ".join("%s %.2f" % kv for kv in stage_ms.items()))
 
-    # roofline of the dominant kernel (pass 1).  Algorithmic bytes, line granular
-    # (one 64-byte line per random access), from the pass's own event counters:
-    #   every occurrence counted through the table reads its home slot line (64 B) (heavy
-    #   hitters counted in workgroup-local memory touch no table line);
-    #   an occurrence counted in pass 1 (hit or insert) writes that line back (64 B);
-    #   a Bloom test-and-set with the filter in the table writes back the home line the probe
-    #   read (64 B; an inserted k-mer's count lands on that line too: counted once); a separate
-    #   filter's word is one more line, read and written (128 B);
-    #   a deferred occurrence appends a 17-byte list entry;
-    #   the packed reads stream in once (0.5 B per base).
+    # roofline of the dominant kernel (pass 1).  Algorithmic bytes per k-mer position of the method
+    # (line granular, g = one 64-byte line per random access): (1 + s) random read-modify-writes of
+    # a line (a Bloom update for every position, a counter update for the fraction s of positions
+    # the filter has seen) and one read-only table probe, (1 + s) * 2g + g, with s = 1 - deferred /
+    # positions (the positions counted in pass 1) from the pass's own counters.  Pass 1 does most
+    # of this work and pass 2 the rest, so `frac` (over the pass-1 kernel's time) is an upper
+    # bound; `frac_counting` prices the same bytes over both passes and `frac_step` over the step.
     st = kc.stats()  # cleared by every step's table init: the last step's counts
     occ, bloom_tests, deferred = st["occurrences"] - st["heavy_local"], st["bloom_tests"], st["deferred"]
+    s_seen = 1.0 - deferred / max(st["occurrences"], 1)
+    bpp = (1.0 + s_seen) * 2 * LINE + LINE
+    alg_bytes = bpp * positions
+    achieved = alg_bytes / (stage_ms["pass1"] / 1000) / 1e9
+    # the pass's own, smaller model from its event counters: a home line read per occurrence
+    # counted through the table, written back when counted in pass 1 (or by the Bloom OR of a
+    # deferred occurrence, the filter being in the table; a separate filter's word is one more
+    # line read and written), 17 bytes per list entry, the packed reads once
     bloom_bytes = deferred * LINE if kc.bloom_in_table else bloom_tests * 2 * LINE
-    pass1_bytes = occ * LINE + (occ - deferred) * LINE + bloom_bytes + deferred * 17 + 0.5 * r.n_bases
-    achieved = pass1_bytes / (stage_ms["pass1"] / 1000) / 1e9
+    own_bytes = occ * LINE + (occ - deferred) * LINE + bloom_bytes + deferred * 17 + 0.5 * r.n_bases
+    own_achieved = own_bytes / (stage_ms["pass1"] / 1000) / 1e9
     roofline = {"kernel": "k_pass1_fixed (table probe, Bloom test-and-set, insert/count)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_pass1_fixed_mid_k51_traffic.md"))
                 if args.scale == 1.0 and args.workload == "mid" else None,
-                "bytes_per_position": round(pass1_bytes / positions, 2), "kernel_ms": round(stage_ms["pass1"], 3),
-                "events_per_position": {x: round(v / positions, 4) for x, v in st.items() }}
+                "bytes_per_position": round(bpp, 2), "s": round(s_seen, 4),
+                "model": "(1 + s) * 2g + g bytes per position, g = 64 B, s = 1 - deferred / positions",
+                "kernel_ms": round(stage_ms["pass1"], 3),
+                "frac_counting": round(alg_bytes / ((stage_ms["pass1"] + stage_ms["pass2"]) / 1000) / 1e9
+                                       / HBM_PEAK_GBS, 4),
+                "frac_step": round(alg_bytes / (step_dist["median"] / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+                "own_model": {"bytes_per_position": round(own_bytes / positions, 2),
+                              "achieved_GBps": round(own_achieved, 1),
+                              "frac": round(own_achieved / HBM_PEAK_GBS, 4)},
+                "events_per_position": {x: round(v / positions, 4) for x, v in st.items()}}
     rates = None
     if not args.no_probe:
         from paper_1705_11147_amd import roofline as ra
@@ -704,24 +798,56 @@ def main():
         del kb, ob
         torch.cuda.empty_cache()
 
+    # the timed export against the oracle: every record of one key shard (1/64 of the keys, by a
+    # hash independent of the table layout), field by field
+    oracle_check = None
+    threads = host_threads()
+    if not args.no_oracle_check:
+        import oracle
+        n_shards, shard = 64, 5
+        t1 = time.perf_counter()
+        hk = out.key_hi[:n_records].cpu().numpy().view(np.uint64)
+        lk = out.key_lo[:n_records].cpu().numpy().view(np.uint64)
+        idx = np.nonzero(oracle.shard_of(hk, lk, n_shards) == shard)[0]
+        del hk, lk
+        got = device_rows(out, torch.from_numpy(idx).to(dev))
+        exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_shards=n_shards,
+                         shard=shard, n_threads=threads, sort_count=True)
+        same = same_records(got, exp)
+        oracle_check = {"shard": "%d of %d" % (shard, n_shards), "records": len(got["count"]),
+                        "oracle_records": len(exp["count"]), "oracle_identical": same,
+                        "oracle_positions": exp["positions"], "s": round(time.perf_counter() - t1, 1)}
+        log("oracle check of the timed export: %s" % oracle_check)
+        assert same and exp["positions"] == positions, "the timed export disagrees with the oracle on its shard"
+        del got, exp
+
     cpu = None
     if not args.no_cpu:
         import oracle
+        # the oracle timed on the first cpu_sample_reads reads (sort-counted, every host core), and the
+        # GPU path on the same sample, which must give the same table record by record
         n_cpu = min(args.cpu_sample_reads, r.n_reads)
-        threads = min(16, len(os.sched_getaffinity(0)))
         sub_a = r.ascii[: n_cpu * L]
         sub_q = r.qual[: n_cpu * L]
         off = np.arange(n_cpu + 1, dtype=np.int64) * L
-        res = oracle.run(sub_a, sub_q, off, k, qcut=p.qcut, min_depth=p.min_depth, n_threads=threads)
+        res = oracle.run(sub_a, sub_q, off, k, qcut=p.qcut, min_depth=p.min_depth, n_threads=threads,
+                         sort_count=True)
+        del kc, out
+        torch.cuda.empty_cache()
+        g = kmer.analyze(sub_a, sub_q, k, read_len=L, qcut=p.qcut, min_depth=p.min_depth,
+                         export_flags=abi.HM_EXPORT_SORTED, fused=True, device=dev)
+        same = same_records(g, res)
+        assert same, "the GPU table of the CPU-baseline sample disagrees with the oracle"
         cpu = {"value": round(n_cpu * W / res["seconds"], 1), "unit": "k-mers/s", "cores": threads,
                "kind": "oracle",
-               "sample": "first %d reads (%d positions) of the same workload, %d threads, %.1fs; %s" % (
-                   n_cpu, n_cpu * W, threads, res["seconds"], platform.processor() or platform.machine())}
+               "sample": "first %d reads (%d positions, %.0f%% of the workload), sort-counted on %d threads, %.1fs; "
+                         "the GPU's table of the same sample is identical (%d records); %s" % (
+                             n_cpu, n_cpu * W, 100.0 * n_cpu / r.n_reads, threads, res["seconds"],
+                             len(res["count"]), cpu_model())}
+        log("cpu baseline: %s" % cpu)
+        del g, res
+        kc = out = None
 
-    table_slots, bloom_words = kc.capacity, kc.bloom_words
-    bloom = ({"layout": "in table: the home slot's 32-bit classification word", "bits": kc.capacity * 32}
-             if kc.bloom_in_table else {"layout": "separate: 64-bit words", "bits": kc.bloom_words * 64})
-    bloom.update(n_hash=args.n_hash, bits_per_distinct_kmer=round(bloom["bits"] / card.estimate, 2))
     del kc, out, packed, ascii, qual
     torch.cuda.empty_cache()
     batched = None
@@ -733,6 +859,12 @@ def main():
         gc.collect()
         torch.cuda.empty_cache()
         serving = run_serving(args, dev, log)
+    human = None
+    if not args.no_human_share:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        human = run_human_share(args, dev)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
@@ -749,6 +881,7 @@ def main():
                    "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
                    "step_ms": step_dist},
         "roofline": roofline,
+        "oracle_check": oracle_check,
         "cpu_baseline": cpu,
         "sorted_export": sorted_export,
         "contigs": contigs,
@@ -756,6 +889,7 @@ def main():
         "bloom_bypass_diagnostic": bypass,
         "batched": batched,
         "serving": serving,
+        "human_share": human,
     }
     print(json.dumps(line), flush=True)
 

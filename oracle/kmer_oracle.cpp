@@ -59,6 +59,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <queue>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -403,13 +404,27 @@ static int64_t acc_finish(orc_acc *a, void **handle) {
         });
         for (uint32_t q = 0; q < T; ++q)
             if (rcs[q] != ORC_OK) return rcs[q];
+        /* every partition is in key order: merge them (a heap of the partitions' next records) */
         size_t n = 0;
         for (auto &o : out) n += o.size();
-        recs.reserve(n);
-        for (auto &o : out) {
-            recs.insert(recs.end(), o.begin(), o.end());
-            std::vector<std::pair<u128, Tally>>().swap(o);
+        orc_result *res = new orc_result();
+        res->positions = a->positions;
+        res->key.reserve(n);
+        res->val.reserve(n);
+        typedef std::pair<u128, uint32_t> Head; /* next key of a partition, the partition */
+        std::priority_queue<Head, std::vector<Head>, std::greater<Head>> heap;
+        std::vector<size_t> at(T, 0);
+        for (uint32_t q = 0; q < T; ++q)
+            if (!out[q].empty()) heap.push({out[q][0].first, q});
+        while (!heap.empty()) {
+            const uint32_t q = heap.top().second;
+            heap.pop();
+            res->key.push_back(out[q][at[q]].first);
+            res->val.push_back(out[q][at[q]].second);
+            if (++at[q] < out[q].size()) heap.push({out[q][at[q]].first, q});
         }
+        *handle = res;
+        return (int64_t)n;
     }
     orc_result *res = new orc_result();
     res->positions = a->positions;

@@ -222,9 +222,13 @@ class GpuBackend:
     plan=False by the job's own size hints (distinct_est, kept_est)."""
 
     def __init__(self, k: int, qcut: int = 20, min_depth: int = 2, table_load: float = 0.45, bloom_bits: float = 12.0,
-                 n_hash: int = 4, device="cuda", plan: bool = True):
+                 n_hash: int = 4, device="cuda", plan: bool = True, keep_records: bool = False):
+        """keep_records: copy every finished job's records to the host, sorted by key
+        (`records[job id]`), besides the count and digest each result holds."""
         import torch
         self.torch = torch
+        self.keep_records = keep_records
+        self.records = {}
         self.device = torch.device(device)
         self.k, self.qcut, self.min_depth = k, qcut, min_depth
         self.table_load, self.bloom_bits, self.n_hash = table_load, bloom_bits, n_hash
@@ -343,6 +347,8 @@ class GpuBackend:
         status = "ok"
         if rc == abi.HM_OK:
             result = {"n_out": int(out.n_out.item()), "digest": out.digest_words()}
+            if self.keep_records:  # the job's stream is done (hm_status synchronized it)
+                self.records[j.id] = out.to_numpy()
         elif rc in (abi.HM_ECAPACITY, abi.HM_EOUTPUT):
             # too small for this job: rerun from scratch with the structure that overflowed doubled
             s = int(kc.status_buf.item())

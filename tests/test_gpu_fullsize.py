@@ -1,11 +1,11 @@
 """Parity at full workload size, in the launch configuration bench.py times.
 
-The whole table of the mid workload (2e9 positions) is too large for the CPU
-oracle to rebuild within a test, so the oracle computes one key shard
-(1/64 of the keys, selected by a hash independent of the table layout) from
-all reads, and the GPU's full export is cut to the same shard and compared
-record by record.  Properties that hold at any size (position count, event
-balance, determinism) are checked on the full table."""
+The mid workload's whole table (2e9 positions, 1.0e8 kept k-mers) is compared
+with the oracle's record by record (the sort-counted oracle on every host
+core); so are all 64 read sets of the batched workload, and one GPU's share of
+the human-scale recipe at 1/10 of its reads in ten streamed batches.
+Properties that hold at any size (position count, event balance,
+determinism) are checked on the full tables too."""
 import os
 
 import numpy as np
@@ -18,7 +18,7 @@ from tests.util import assert_tables_equal, table_digest
 
 pytestmark = pytest.mark.gpu
 
-THREADS = min(16, len(os.sched_getaffinity(0)))
+THREADS = len(os.sched_getaffinity(0))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -29,12 +29,7 @@ def gpu():
     torch.cuda.set_device(0)
 
 
-def shard(t, n, s):
-    m = oracle.shard_of(t["key_hi"], t["key_lo"], n) == s
-    return {x: v[m] for x, v in t.items() if isinstance(v, np.ndarray)}
-
-
-def test_mid_workload_full_size_sampled():
+def test_mid_workload_full_size():
     w = synth.mid()
     r = w.reads()
     p = w.params
@@ -71,13 +66,12 @@ def test_mid_workload_full_size_sampled():
     assert ((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all()
     assert (got["count"] >= 2).all()
     assert (got["tl"].sum(1) <= got["count"]).all() and (got["tr"].sum(1) <= got["count"]).all()
-    n_shards, s = 64, 5
-    g = shard(got, n_shards, s)  # a filter keeps the key order
-    exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_shards=n_shards,
-                     shard=s, n_threads=THREADS, split_reads=True)
+    exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_threads=THREADS,
+                     sort_count=True)
     assert exp["positions"] == positions
-    assert len(exp["count"]) > 1_000_000
-    assert_tables_equal(g, exp, "mid full size, shard %d/%d" % (s, n_shards))
+    assert len(exp["count"]) > 90_000_000
+    assert_tables_equal(got, exp, "mid full size, every record")
+    del exp
     # the cardinality pass at full size, bit for bit
     ec = oracle.card(r.ascii, r.offsets(), k, hll_p=card.hll_p, sample_log2=card.sample_log2,
                      heavy_log2=card.heavy_log2, min_depth=p.min_depth, heavy_min=16, n_threads=THREADS)
@@ -85,6 +79,70 @@ def test_mid_workload_full_size_sampled():
     assert (card.positions, card.sampled_distinct, card.sampled_kept, card.n_heavy) == (
         ec["positions"], ec["sampled_distinct"], ec["sampled_kept"], ec["n_heavy"])
     assert abs(card.estimate - ec["estimate"]) <= 1e-12 * ec["estimate"]
+
+
+def test_batched_workload_every_set_full_size():
+    """The batched workload at full size (64 read sets, 0.5-8 Mbp genomes at 10-60x, k=31), one
+    persistent launch: every set's table equals the oracle's record by record."""
+    from paper_1705_11147_amd.batch import Batch, SetSpec
+    dev = torch.device("cuda:0")
+    ws = synth.batched_sets(n_sets=64, scale=1.0)
+    specs, host = [], []
+    for w in ws:
+        r = w.reads()
+        d, kept = w.size_estimates()
+        specs.append(SetSpec(torch.from_numpy(r.ascii).to(dev), torch.from_numpy(r.qual).to(dev), r.read_len, d,
+                             kept))
+        host.append(r)
+    k = ws[0].params.k
+    b = Batch(specs, k, device=dev)
+    b.launch()
+    assert b.status() == [abi.HM_OK] * len(ws)
+    print("batched: %d sets, %.3g positions launched" % (len(ws), b.positions()), flush=True)
+    total = 0
+    for i, r in enumerate(host):
+        exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=20, min_depth=2, n_threads=THREADS, sort_count=True)
+        got = b.table(i)
+        assert_tables_equal(got, exp, "batched set %d of %d" % (i, len(host)))
+        total += len(exp["count"])
+    assert total > 64 * 100_000
+
+
+def test_human_share_ten_batches_stream():
+    """One GPU's share of the human-scale recipe (interspersed repeats, owner 0 of 16) at 1/10 of its
+    reads in ten batches, in bench.py's form: the cardinality pass writes the owned occurrences of
+    every batch to one stream, and one pass-1 launch reads it.  The whole table equals the
+    oracle's, which counts the ten batches one after another (oracle.Accumulator)."""
+    w = synth.human_share(scale=1 / 10)
+    p = w.params
+    dev = torch.device("cuda:0")
+    nb = w.meta["batch_reads"]
+    cuts = list(range(0, w.n_reads, nb)) + [w.n_reads]
+    assert len(cuts) - 1 == 10
+    acc = oracle.Accumulator(p.k, qcut=p.qcut, min_depth=p.min_depth, n_owners=p.n_owners, owner=p.owner,
+                             sort_count=True, n_threads=THREADS)
+    packs = []
+    for i in range(10):
+        r = w.reads(r0=cuts[i], n=cuts[i + 1] - cuts[i])
+        packs.append(kmer.pack_reads(torch.from_numpy(r.ascii).to(dev), torch.from_numpy(r.qual).to(dev),
+                                     read_len=r.read_len, qcut=p.qcut))
+        acc.add(r.ascii, r.qual, r.offsets())
+        del r
+    sk = kmer.CardSketch(p.k, w.positions, n_owners=p.n_owners, owner=p.owner, device=dev)
+    occ = kmer.OccStream.for_windows(w.positions, p.n_owners, len(packs), device=dev)
+    card = sk.run(packs, min_depth=p.min_depth, occ=occ)
+    assert card.status == abi.HM_OK and not occ.overflowed()
+    cap, bw, lcap = kmer.plan_sizes(card, device=dev)
+    kc = kmer.KmerCounter(p.k, cap, bw, lcap, n_owners=p.n_owners, owner=p.owner, heavy=card, device=dev)
+    out = kmer.Records(int(min(kc.capacity, card.kept_hi() * 1.3 + 1024)), device=dev)
+    kc.run_occ(occ, out, flags=abi.HM_EXPORT_SORTED, fused=True)
+    assert kc.status() == abi.HM_OK
+    assert kc.stats()["occurrences"] == card.positions
+    got = out.to_numpy(sort=False)  # key order
+    exp = acc.finish()
+    assert exp["positions"] == w.positions
+    assert len(exp["count"]) > 5_000_000
+    assert_tables_equal(got, exp, "human share 1/10, ten batches through the stream")
 
 
 def test_human_share_streamed_batches():

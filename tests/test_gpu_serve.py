@@ -7,7 +7,7 @@ import torch
 import oracle
 from paper_1705_11147_amd import abi, synth
 from paper_1705_11147_amd.serve import GpuBackend, Scheduler, make_jobs, summarize
-from tests.util import table_digest
+from tests.util import assert_tables_equal, table_digest
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,30 @@ def test_alone_equals_in_mix_equals_oracle():
         exp = oracle.run(rd.ascii, rd.qual, rd.offsets(), 51, n_threads=4)
         assert mix[p].result["n_out"] == len(exp["count"])
         assert mix[p].result["digest"] == table_digest(exp)
+
+
+def test_sixteen_jobs_record_by_record():
+    """16 seeded jobs of the serving recipe (hexaploid-like genomes, distinct sizes) served together
+    with continuous batching: every job's records equal the oracle's field by field, and equal the
+    records of the same job served alone."""
+    n = 16
+    _, builders = synth.serving_jobs(n_jobs=n, scale=0.004)
+    pool = [b() for b in builders]
+    jobs, positions = make_jobs(pool, n_jobs=n, rate=400.0)
+    mix_be = GpuBackend(51, keep_records=True)
+    mix = Scheduler(mix_be, budget_bytes=8 << 30, max_slots=4).run(jobs)
+    assert all(r.status == 0 for r in mix) and len(mix_be.records) == n
+    s = summarize(mix, positions)
+    assert s["jobs"] == n and s["failed"] == 0
+    alone_be = GpuBackend(51, keep_records=True)
+    for j in jobs:
+        Scheduler(alone_be, budget_bytes=8 << 30, max_slots=1).run([j])
+    for j, w in zip(jobs, pool):
+        rd = w.reads()
+        exp = oracle.run(rd.ascii, rd.qual, rd.offsets(), 51, n_threads=8, sort_count=True)
+        assert len(exp["count"]) > 100
+        assert_tables_equal(mix_be.records[j.id], exp, "job %d in the mix vs the oracle" % j.id)
+        assert_tables_equal(alone_be.records[j.id], mix_be.records[j.id], "job %d alone vs in the mix" % j.id)
 
 
 def test_capacity_retry_in_serving():
