@@ -17,9 +17,17 @@ BASES = "ACGT"
 COMP = {"A": "T", "C": "G", "G": "C", "T": "A"}
 
 
+def ascending(t) -> bool:
+    """Records in strictly ascending key order (the oracle's output contract)."""
+    hi, lo = t["key_hi"], t["key_lo"]
+    return bool(((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all())
+
+
 def run_reads(reads, k, **kw):
     a, q, off = pack_reads(reads)
-    return oracle.run(a, q, off, k, **kw)
+    t = oracle.run(a, q, off, k, **kw)
+    assert ascending(t), "oracle output not in ascending key order"
+    return t
 
 
 def hq_reads(seqs, q=40):
@@ -165,6 +173,7 @@ def test_batched_reads_equal_brute_force(mode):
                 a, q, off = pack_reads(reads[lo:hi])
                 acc.add(a, q, off)
             got = acc.finish()
+            assert ascending(got)
             assert table_to_dict(got) == exp
             assert got["positions"] == sum(len(r) - k + 1 for r, _ in reads)
 
