@@ -267,7 +267,10 @@ int hm_pack_reads(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases, ui
 int hm_bloom_insert(const hm_reads_t *r, const hm_params_t *p, hm_bloom_t *b, hm_table_t *t, hm_list_t *l,
                     hipStream_t stream);
 
-/* Counting pass 2: each first-occurrence entry of `l` whose k-mer is in the
+/* Counting pass 2 (section "Parallel k-mer analysis": the Bloom filter
+ * paragraph, where a k-mer the filter has seen is inserted so that the count
+ * table then counts it; read here so that every occurrence is counted
+ * exactly once): each first-occurrence entry of `l` whose k-mer is in the
  * table (i.e. was seen at least twice, or is a Bloom false positive) is
  * counted with its extensions.  After it the table holds, for every k-mer
  * with count >= 2, exactly its count and extension tallies over all
@@ -282,7 +285,11 @@ int hm_kmer_count(const hm_reads_t *r, const hm_params_t *p, hm_table_t *t, hm_l
  * its class byte.  Results stay in the table for hm_export_table. */
 int hm_classify_ext(const hm_params_t *p, hm_table_t *t, hipStream_t stream);
 
-/* Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
+/* Export (section "Parallel contig generation": only the UU k-mers, those
+ * with a unique high-quality extension on both sides, go on to build the de
+ * Bruijn graph; section "The Meraculous Assembly Pipeline", step 1: the
+ * k-mers that survive the depth filter, with their extensions).
+ * Stream-compact the classified table into `out`.  flags: HM_EXPORT_UU_ONLY,
  * HM_EXPORT_ALL, HM_EXPORT_CLASSIFY, HM_EXPORT_SORTED.  Zeroes out->n_out (and
  * out->digest) first.  Without HM_EXPORT_SORTED the records come in no fixed
  * order: each run of 2048 table slots takes its output range with one atomic,

@@ -107,6 +107,36 @@ __device__ __forceinline__ void card_end(const CardArgs &c, const uint8_t *s_reg
 // complemented base on top).  The extensions are not needed here.
 constexpr int kCardRun = 8;
 
+// What a run of kCardRun windows starting at base j0 (relative to the tile
+// origin) reads besides its first window, in registers: the invalid-base bits
+// from j0 on (128 bits, first base most significant), which cover every
+// window of the run since kCardRun - 1 + k <= 70, and the 7 bases the run
+// rolls in (j0 + k .. j0 + k + 6).  Two loads of mask words and two of base
+// words per run instead of an LDS round trip per window.
+struct RunBits {
+    uint64_t m0, m1;  // invalid-base bits of bases j0 .. j0 + 127
+    uint64_t in;      // bases j0 + k .. j0 + k + 31, first base most significant
+    __device__ __forceinline__ void load(const Words &w, int64_t j0, int k) {
+        const int64_t i = j0 >> 6;
+        const int s = (int)(j0 & 63);
+        const uint64_t a = w.nm[i], b = w.nm[i + 1], c = w.nm[i + 2];
+        m0 = s ? (a << s) | (b >> (64 - s)) : a;
+        m1 = s ? (b << s) | (c >> (64 - s)) : b;
+        const int64_t p = 2 * (j0 + k);
+        const int64_t q = p >> 6;
+        const int t = (int)(p & 63);
+        const uint64_t x = w.b2[q], y = w.b2[q + 1];
+        in = t ? (x << t) | (y >> (64 - t)) : x;
+    }
+    // window j0 + i (0 <= i < kCardRun) holds no invalid base
+    __device__ __forceinline__ bool valid(int i, int k) const {
+        const uint64_t m = i ? (m0 << i) | (m1 >> (64 - i)) : m0;
+        return (m >> (64 - k)) == 0;
+    }
+    // the base window j0 + i (1 <= i < kCardRun) rolls in: base j0 + i + k - 1
+    __device__ __forceinline__ uint64_t base(int i) const { return (in >> (64 - 2 * i)) & 3; }
+};
+
 template <int KW>
 __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile,
                                                        int64_t n_tiles) {
@@ -141,11 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
             const int cnt = min(kCardRun, W - p0);
             const int64_t j0 = (r0 + r) * L - org + p0;  // first window, relative to the tile origin
             const int64_t jg = (r0 + r) * L + p0;        // and in the read set
+            RunBits rb;
+            rb.load(w, j0, k);
             U128 f = w.window(j0, k);
             U128 rc = revcomp(f, k);
             for (int i = 0; i < cnt; ++i) {
                 if (i > 0) {
-                    const uint64_t b = w.code(j0 + i + k - 1);
+                    const uint64_t b = rb.base(i);
                     if (KW == 1) {
                         f.lo = ((f.lo << 2) | b) & mlo;
                         rc.lo = (rc.lo >> 2) | ((3 - b) << top);
@@ -158,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
                         else rc.lo |= (3 - b) << top;
                     }
                 }
-                if (!w.window_valid(j0 + i, k)) continue;
+                if (!rb.valid(i, k)) continue;
                 const bool fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
                 Occ o{fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, 4, 4};
                 if (a.n_owners > 1 && owner_of(o.hi, o.lo, a.n_owners) != a.owner) continue;
@@ -243,11 +275,13 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
             int cnt = 0, p0 = 0;
             int64_t j0 = 0;
             U128 f{0, 0}, rc{0, 0};
+            RunBits rb{0, 0, 0};
             if (gi < total) {
                 const int r = gi / runs;
                 p0 = (gi - r * runs) * kCardRun;
                 cnt = min(kCardRun, W - p0);
                 j0 = (r0 + r) * L - org + p0;  // first window of the run, relative to the tile origin
+                rb.load(w, j0, k);
                 f = w.window(j0, k);
                 rc = revcomp(f, k);
             }
@@ -256,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
                 bool fwd = true;
                 if (i < cnt) {
                     if (i > 0) {
-                        const uint64_t b = w.code(j0 + i + k - 1);
+                        const uint64_t b = rb.base(i);
                         if (KW == 1) {
                             f.lo = ((f.lo << 2) | b) & mlo;
                             rc.lo = (rc.lo >> 2) | ((3 - b) << top);
@@ -269,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
                             else rc.lo |= (3 - b) << top;
                         }
                     }
-                    if (w.window_valid(j0 + i, k)) {
+                    if (rb.valid(i, k)) {
                         fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
                         act = a.n_owners <= 1 ||
                               owner_of(fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, a.n_owners) == a.owner;

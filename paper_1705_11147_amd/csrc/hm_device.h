@@ -79,9 +79,12 @@ __device__ __forceinline__ uint64_t key_hash(uint64_t hi, uint64_t lo, uint64_t 
     return fmix64(lo ^ fmix64(hi ^ seed));
 }
 
-// owner-computes map: floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo)
+// owner-computes map: floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo);
+// for n = 2^b that is the top b bits of H (no 64-bit product)
 __device__ __forceinline__ uint32_t owner_of(uint64_t hi, uint64_t lo, uint32_t n) {
     uint64_t h = fmix64(fmix64(hi ^ kOwnerSeed) ^ lo);
+    if (n <= 1) return 0;
+    if ((n & (n - 1)) == 0) return (uint32_t)(h >> (64 - (31 - __clz((int)n))));
     return (uint32_t)__umul64hi(h, (uint64_t)n);
 }
 
