@@ -225,19 +225,35 @@ def run_serving(args, dev, log):
     budget = int(args.serve_budget_gb * 2 ** 30)
     out = {"workload": "serving-hexaploid-1to50Mbp-x3-30x-150bp-k51-poisson%gps" % args.serve_rate,
            "scale": args.serve_scale, "pool_jobs": args.serve_pool, "budget_GiB": args.serve_budget_gb}
-    # warm-up: one small job through the backend (stream, allocator, kernels)
-    Scheduler(GpuBackend(51, device=dev), budget, 1).run([min(jobs, key=lambda j: j.n_bases)])
+    # the backend reserves the whole budget once (its arena), outside the timed runs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    be = GpuBackend(51, device=dev, memory_bytes=budget)
+    # warm-up: one small job through the backend (stream, kernels)
+    Scheduler(be, budget, 1).run([min(jobs, key=lambda j: j.n_bases)])
     for name, slots in (("continuous", args.serve_slots), ("fifo_one_at_a_time", 1)):
         torch.cuda.synchronize()
+        be.arena.peak = be.arena.used
+        spills = be.arena.spills
         # continuous: the next jobs plan while others count; one at a time: nothing overlaps a job
-        sch = Scheduler(GpuBackend(51, device=dev), budget, slots,
+        sch = Scheduler(be, budget, slots,
                         max_planning=args.serve_planners if slots > 1 else 1, plan_while_busy=slots > 1)
+        m0 = torch.cuda.memory_stats(dev)
         recs = sch.run(jobs)
+        m1 = torch.cuda.memory_stats(dev)
         bad = [r.job for r in recs if r.status != 0 or r.result is None]
         assert not bad, "serving (%s): jobs %s failed" % (name, bad[:10])
         res = summarize(recs, positions, sch.trace)
         res["slots"] = slots
         res["planners"] = args.serve_planners if slots > 1 else 1
+        # caching allocator during the run: device allocations, and retries (a retry frees the
+        # cached blocks and synchronizes the device)
+        for key, name_ in (("num_device_alloc", "device_allocs"), ("num_alloc_retries", "alloc_retries"),
+                           ("num_sync_all_streams", "allocator_syncs")):
+            if key in m1:
+                res[name_] = int(m1[key] - m0.get(key, 0))
+        res["arena_peak_GiB"] = be.arena.peak / 2 ** 30
+        res["arena_spills"] = be.arena.spills - spills
         out[name] = {x: (round(v, 3) if isinstance(v, float) else v) for x, v in res.items()}
         log("serving %s: p50 %.1f ms p99 %.1f ms, %.3g k-mers/s" % (name, res["p50_ms"], res["p99_ms"],
                                                                      res["kmers_per_s"]))

@@ -239,6 +239,11 @@ int hm_bloom_init(hm_bloom_t *b, hipStream_t stream);
 int hm_list_init(hm_list_t *l, hipStream_t stream);
 /* Synchronize `stream`, read the status word and map it to a return code. */
 int hm_status(const hm_table_t *t, hipStream_t stream);
+/* Map a status word the caller has already copied to the host (for instance
+ * with an asynchronous copy into pinned memory, so that a host thread serving
+ * many streams never blocks on one) to the code hm_status would return, with
+ * the same error message.  Touches no device; never fails itself. */
+int hm_status_code(uint32_t status);
 
 /* ---- the k-mer analysis path ------------------------------------------ */
 

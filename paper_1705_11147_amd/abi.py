@@ -141,6 +141,7 @@ SIGNATURES = {
     "hm_bloom_init": ([P(Bloom), vp], ctypes.c_int),
     "hm_list_init": ([P(List), vp], ctypes.c_int),
     "hm_status": ([P(Table), vp], ctypes.c_int),
+    "hm_status_code": ([ctypes.c_uint32], ctypes.c_int),
     "hm_pack_reads": ([vp, vp, ctypes.c_int64, ctypes.c_uint8, ctypes.c_uint8, vp, vp, vp, vp], ctypes.c_int),
     "hm_bloom_insert": ([P(Reads), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
     "hm_kmer_count": ([P(Reads), P(Params), P(Table), P(List), vp], ctypes.c_int),

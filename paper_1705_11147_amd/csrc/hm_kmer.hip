@@ -376,13 +376,7 @@ int hm_occ_init(hm_occ_t *o, hipStream_t s) {
     return fill<uint64_t>(o->count, 1, 0ull, s);
 }
 
-int hm_status(const hm_table_t *t, hipStream_t s) {
-    if (!t || !t->status) return fail(HM_EINVAL, "table status is NULL");
-    hipError_t e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    uint32_t st = 0;
-    e = hipMemcpy(&st, t->status, sizeof st, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
+int hm_status_code(uint32_t st) {
     if (st & HM_ST_TIMEOUT) return fail(HM_ETIMEOUT, "a batched-phase wait passed its bound (status 0x%x)", st);
     if (st & HM_ST_OVERFLOW) return fail(HM_EOVERFLOW, "a k-mer counter passed 2^32 - 1 (status 0x%x)", st);
     if (st & HM_ST_STREAM_FULL)
@@ -392,6 +386,16 @@ int hm_status(const hm_table_t *t, hipStream_t s) {
                     st);
     if (st & HM_ST_OUTPUT_FULL) return fail(HM_EOUTPUT, "export buffer too small (status 0x%x)", st);
     return HM_OK;
+}
+
+int hm_status(const hm_table_t *t, hipStream_t s) {
+    if (!t || !t->status) return fail(HM_EINVAL, "table status is NULL");
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t st = 0;
+    e = hipMemcpy(&st, t->status, sizeof st, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(status)");
+    return hm_status_code(st);
 }
 
 int hm_pack_reads(const uint8_t *ascii, const uint8_t *qual, int64_t n_bases, uint8_t qual_offset, uint8_t qcut,

@@ -44,6 +44,61 @@ def _empty_u64(n: int, device) -> torch.Tensor:
     return torch.empty(max(int(n), 1), dtype=torch.int64, device=device)
 
 
+def _new(n: int, dtype, device, alloc=None, zero: bool = False) -> torch.Tensor:
+    """A 1-D tensor of max(n, 1) elements: from `alloc` (an object with empty(n, dtype), such as
+    arena.Slab) when given, else from PyTorch's allocator on `device`.  zero: cleared on the
+    current stream."""
+    n = max(int(n), 1)
+    t = torch.empty(n, dtype=dtype, device=device) if alloc is None else alloc.empty(n, dtype)
+    return t.zero_() if zero else t
+
+
+def _to_device(a: np.ndarray, device, alloc=None) -> torch.Tensor:
+    """Copy a host array to a new device tensor: through pinned memory, asynchronously on the
+    current stream, for a device; a plain copy for the CPU."""
+    src = torch.from_numpy(np.ascontiguousarray(a))
+    t = _new(src.numel(), src.dtype, device, alloc)[:src.numel()]
+    if t.is_cuda:
+        t.copy_(src.pin_memory(), non_blocking=True)
+    else:
+        t.copy_(src)
+    return t
+
+
+def tensor_bytes(n: int, itemsize: int) -> int:
+    """Bytes a tensor of max(n, 1) elements takes in an arena slab (256-byte aligned)."""
+    return (max(int(n), 1) * itemsize + 255) // 256 * 256
+
+
+def packed_bytes(n_bases: int) -> int:
+    """Bytes of the packed form of n_bases bases (hm_pack_reads' outputs) in an arena slab."""
+    L = abi.lib()
+    return tensor_bytes(L.hm_bases2_words(n_bases), 8) + 2 * tensor_bytes(L.hm_mask_words(n_bases), 8)
+
+
+def new_packed(n_bases: int, device, alloc=None) -> "Packed":
+    """Output buffers for pack_reads(out=...) of n_bases bases."""
+    L = abi.lib()
+    n_b2, n_m = int(L.hm_bases2_words(n_bases)), int(L.hm_mask_words(n_bases))
+    return Packed(_new(n_b2, torch.int64, device, alloc), _new(n_m, torch.int64, device, alloc),
+                  _new(n_m, torch.int64, device, alloc), None, 0, n_bases, 0)
+
+
+def fetch_async(tensors, stream=None) -> list:
+    """Queue copies of small device tensors into pinned host tensors on `stream` and return
+    the host tensors.  They hold the values once the stream has passed this point (for
+    instance once an event recorded after this call has completed): a host thread that
+    serves many streams reads results without blocking on any of them."""
+    st = stream if stream is not None else torch.cuda.current_stream()
+    out = []
+    with torch.cuda.stream(st):
+        for t in tensors:
+            h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+            h.copy_(t, non_blocking=True)
+            out.append(h)
+    return out
+
+
 @dataclass
 class Packed:
     """Packed reads resident on the device (layout: include/hm_kmer.h, hm_reads_t)."""
@@ -141,20 +196,28 @@ class OccStream:
 class Records:
     """Device export buffer (structure of arrays)."""
 
-    def __init__(self, capacity: int, device="cuda"):
+    def __init__(self, capacity: int, device="cuda", alloc=None):
+        """alloc: take the buffers from this allocator (see _new) instead of PyTorch's."""
         self.capacity = int(capacity)
         n = max(self.capacity, 1)
-        self.key_hi = torch.empty(n, dtype=torch.int64, device=device)
-        self.key_lo = torch.empty(n, dtype=torch.int64, device=device)
-        self.count = torch.empty(n, dtype=torch.int32, device=device)
-        self.tl = torch.empty(n * 4, dtype=torch.int32, device=device)
-        self.tr = torch.empty(n * 4, dtype=torch.int32, device=device)
-        self.cls_l = torch.empty(n, dtype=torch.uint8, device=device)
-        self.cls_r = torch.empty(n, dtype=torch.uint8, device=device)
-        self.n_out = torch.zeros(1, dtype=torch.int64, device=device)
-        self.digest = torch.zeros(2, dtype=torch.int64, device=device)
+        self.key_hi = _new(n, torch.int64, device, alloc)
+        self.key_lo = _new(n, torch.int64, device, alloc)
+        self.count = _new(n, torch.int32, device, alloc)
+        self.tl = _new(n * 4, torch.int32, device, alloc)
+        self.tr = _new(n * 4, torch.int32, device, alloc)
+        self.cls_l = _new(n, torch.uint8, device, alloc)
+        self.cls_r = _new(n, torch.uint8, device, alloc)
+        self.n_out = _new(1, torch.int64, device, alloc, zero=True)
+        self.digest = _new(2, torch.int64, device, alloc, zero=True)
         self.device = device
         self.sort_work = None
+
+    @staticmethod
+    def bytes_for(capacity: int) -> int:
+        """Bytes the buffers of Records(capacity, alloc=slab) take in an arena slab."""
+        n = max(int(capacity), 1)
+        return (2 * tensor_bytes(n, 8) + tensor_bytes(n, 4) + 2 * tensor_bytes(4 * n, 4) + 2 * tensor_bytes(n, 1)
+                + tensor_bytes(1, 8) + tensor_bytes(2, 8))
 
     def sort_scratch(self) -> tuple[int, int]:
         """(pointer, bytes) of the scratch a key-ordered export needs, allocated on first use."""
@@ -190,9 +253,15 @@ class Records:
             out = {key: v[order] for key, v in out.items()}
         return out
 
-    def digest_words(self) -> tuple[int, int]:
-        d = self.digest.cpu().numpy().view(np.uint64)
+    def digest_words(self, fetched: tuple | None = None) -> tuple[int, int]:
+        """The order-free digest; from the host copies fetch_summary() queued, if given."""
+        d = (fetched[1] if fetched is not None else self.digest.cpu()).numpy().view(np.uint64)
         return int(d[0]), int(d[1])
+
+    def fetch_summary(self, stream=None) -> tuple:
+        """Queue copies of the record count and the digest into pinned host memory (see
+        fetch_async): (n_out, digest) host tensors."""
+        return tuple(fetch_async([self.n_out, self.digest], stream))
 
     @classmethod
     def from_numpy(cls, t: dict, device="cuda") -> "Records":
@@ -297,9 +366,11 @@ class KmerCounter:
     def __init__(self, k: int, capacity: int, bloom_words: int, list_capacity: int, n_hash: int = 4,
                  min_depth: int = 2, ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
                  seed: int = DEFAULT_SEED, max_probe: int = 0, present_filter: bool = True, heavy=None,
-                 bloom_in_table: bool = True, device="cuda"):
+                 bloom_in_table: bool = True, device="cuda", alloc=None):
         """heavy: optional heavy-hitter keys, an (n, 2) array of (key_hi, key_lo) or a CardResult;
-        pass 1 counts them in workgroup-local memory (at most abi.HM_MAX_HEAVY)."""
+        pass 1 counts them in workgroup-local memory (at most abi.HM_MAX_HEAVY).  alloc: take the
+        buffers from this allocator (see _new) instead of PyTorch's.  The constructor's clears and
+        the copy of the heavy keys are queued on the current stream."""
         self.device = torch.device(device)
         self.bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
         self.bloom_in_table = (bloom_in_table or bool(flags & abi.HM_BLOOM_IN_TABLE)) and not self.bypass
@@ -310,33 +381,51 @@ class KmerCounter:
         if self.bloom_in_table:  # 32 filter bits per slot: at least the bits of bloom_words words
             capacity = max(capacity, 2 * int(bloom_words))
         self.capacity = next_pow2(capacity)
-        self.slots = torch.empty(self.capacity * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
-        self.status_buf = torch.zeros(1, dtype=torch.int32, device=self.device)
-        self.stats_buf = torch.zeros(len(abi.STAT_NAMES), dtype=torch.int64, device=self.device)
+        self.slots = _new(self.capacity * abi.HM_SLOT_BYTES // 8, torch.int64, self.device, alloc)
+        self.status_buf = _new(1, torch.int32, self.device, alloc, zero=True)
+        self.stats_buf = _new(len(abi.STAT_NAMES), torch.int64, self.device, alloc, zero=True)
         if isinstance(heavy, CardResult):  # any subset of the heavy hitters gives the same counts
             n = min(len(heavy.heavy_hi), abi.HM_MAX_HEAVY)
             heavy = np.stack([heavy.heavy_hi[:n], heavy.heavy_lo[:n]], axis=1) if n else None
         hk = np.zeros((0, 2), np.uint64) if heavy is None else np.asarray(heavy, dtype=np.uint64).reshape(-1, 2)
         if len(hk) > abi.HM_MAX_HEAVY:
             raise ValueError("at most %d heavy keys" % abi.HM_MAX_HEAVY)
-        self.heavy_keys = torch.from_numpy(hk.view(np.int64).reshape(-1).copy()).to(self.device) if len(hk) else None
+        self.heavy_keys = _to_device(hk.view(np.int64).reshape(-1), self.device, alloc) if len(hk) else None
         self.table = abi.Table(self.slots.data_ptr(), self.capacity, max_probe, k, self.status_buf.data_ptr(),
                                self.stats_buf.data_ptr(),
                                self.heavy_keys.data_ptr() if self.heavy_keys is not None else None, len(hk), 0)
         self.bloom_words = next_pow2(bloom_words) if not (self.bypass or self.bloom_in_table) else 1
-        self.bloom_buf = torch.empty(self.bloom_words, dtype=torch.int64, device=self.device)
+        self.bloom_buf = _new(self.bloom_words, torch.int64, self.device, alloc)
         self.bloom = abi.Bloom(self.bloom_buf.data_ptr(), self.bloom_words, n_hash)
         self.list_capacity = int(list_capacity) if not self.bypass else 0
         lc = max(self.list_capacity, 1)
-        self.list_keys = torch.empty(2 * lc, dtype=torch.int64, device=self.device)
-        self.list_ext = torch.empty(lc, dtype=torch.uint8, device=self.device)
-        self.list_count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.list_keys = _new(2 * lc, torch.int64, self.device, alloc)
+        self.list_ext = _new(lc, torch.uint8, self.device, alloc)
+        self.list_count = _new(1, torch.int64, self.device, alloc, zero=True)
         # presence filter of inserted keys: about 8 bits per key at the table's design load
         self.present_words = 0 if (self.bypass or not present_filter) else next_pow2(max(64, self.capacity // 16))
-        self.present_buf = torch.empty(max(self.present_words, 1), dtype=torch.int64, device=self.device)
+        self.present_buf = _new(self.present_words, torch.int64, self.device, alloc)
         self.list = abi.List(self.list_keys.data_ptr(), self.list_ext.data_ptr(), self.list_capacity,
                              self.list_count.data_ptr(), self.present_buf.data_ptr() if self.present_words else None,
                              self.present_words, 3)
+
+    @staticmethod
+    def bytes_for(capacity: int, bloom_words: int, list_capacity: int, n_heavy: int = 0, min_depth: int = 2,
+                  flags: int = 0, present_filter: bool = True, bloom_in_table: bool = True) -> int:
+        """Bytes the buffers of KmerCounter(..., alloc=slab) take in an arena slab (the same
+        sizing rules as the constructor)."""
+        bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
+        in_table = (bloom_in_table or bool(flags & abi.HM_BLOOM_IN_TABLE)) and not bypass
+        if in_table:
+            capacity = max(capacity, 2 * int(bloom_words))
+        cap = next_pow2(capacity)
+        words = next_pow2(bloom_words) if not (bypass or in_table) else 1
+        lc = max(int(list_capacity) if not bypass else 0, 1)
+        pw = 0 if (bypass or not present_filter) else next_pow2(max(64, cap // 16))
+        return (tensor_bytes(cap * abi.HM_SLOT_BYTES // 8, 8) + tensor_bytes(1, 4)
+                + tensor_bytes(len(abi.STAT_NAMES), 8) + (tensor_bytes(2 * n_heavy, 8) if n_heavy else 0)
+                + tensor_bytes(words, 8) + tensor_bytes(2 * lc, 8) + tensor_bytes(lc, 1) + tensor_bytes(1, 8)
+                + tensor_bytes(pw, 8))
 
     @property
     def k(self) -> int:
@@ -391,6 +480,15 @@ class KmerCounter:
     def status(self, stream=None) -> int:
         """Synchronize and return the table's status code (HM_OK or a negative code)."""
         return abi.lib().hm_status(ctypes.byref(self.table), _stream(stream))
+
+    def fetch_status(self, stream=None) -> torch.Tensor:
+        """Queue a copy of the status word into pinned host memory (see fetch_async);
+        status_code() of it, once the stream has passed, is what status() returns."""
+        return fetch_async([self.status_buf], stream)[0]
+
+    @staticmethod
+    def status_code(word: torch.Tensor) -> int:
+        return abi.lib().hm_status_code(int(word[0]) & 0xFFFFFFFF)
 
     def run(self, batches, out: Records, flags: int = 0, stream=None, digest: bool = True, fused: bool = False):
         """reset -> pass 1 over every packed batch -> pass 2 -> classify -> export
@@ -450,7 +548,8 @@ class CardSketch:
 
     def __init__(self, k: int, positions_hint: int, hll_p: int = 14, sample_log2: int | None = None,
                  heavy_log2: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
-                 seed: int = DEFAULT_SEED, device="cuda"):
+                 seed: int = DEFAULT_SEED, device="cuda", alloc=None):
+        """alloc: take the buffers from this allocator (see _new) instead of PyTorch's."""
         self.device = torch.device(device)
         self.params = abi.Params(k, 2, 2, n_owners, owner, abi.HM_FORWARD_ONLY if forward_only else 0,
                                  seed & (2 ** 64 - 1))
@@ -460,21 +559,33 @@ class CardSketch:
         self.hll_p = hll_p
         self.sample_log2 = auto if sample_log2 is None else sample_log2
         self.heavy_log2 = auto if heavy_log2 is None else heavy_log2
-        self.registers = torch.zeros(1 << hll_p, dtype=torch.int32, device=self.device)
-        self.positions = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.registers = _new(1 << hll_p, torch.int32, self.device, alloc, zero=True)
+        self.positions = _new(1, torch.int64, self.device, alloc, zero=True)
         self._tabs = []
         tables = []
         for log2 in (self.sample_log2, self.heavy_log2):
             cap = next_pow2(max(1024, 2 * (hint >> log2) + 256))
-            slots = torch.empty(cap * abi.HM_SLOT_BYTES // 8, dtype=torch.int64, device=self.device)
-            status = torch.zeros(1, dtype=torch.int32, device=self.device)
+            slots = _new(cap * abi.HM_SLOT_BYTES // 8, torch.int64, self.device, alloc)
+            status = _new(1, torch.int32, self.device, alloc, zero=True)
             self._tabs.append((slots, status))
             tables.append(abi.Table(slots.data_ptr(), cap, 0, k, status.data_ptr(), None))
         self.card = abi.Card(self.registers.data_ptr(), hll_p, self.sample_log2, self.heavy_log2, 0,
                              self.positions.data_ptr(), tables[0], tables[1])
-        self.summary_buf = torch.zeros(5, dtype=torch.int64, device=self.device)
+        self.summary_buf = _new(5, torch.int64, self.device, alloc, zero=True)
         self.heavy_cap = 4096
-        self.heavy_keys = torch.zeros(2 * self.heavy_cap, dtype=torch.int64, device=self.device)
+        self.heavy_keys = _new(2 * self.heavy_cap, torch.int64, self.device, alloc, zero=True)
+
+    @staticmethod
+    def bytes_for(positions_hint: int, hll_p: int = 14, sample_log2: int | None = None,
+                  heavy_log2: int | None = None) -> int:
+        """Bytes the buffers of CardSketch(..., alloc=slab) take in an arena slab (default heavy_cap)."""
+        hint = max(int(positions_hint), 1)
+        auto = max(0, hint.bit_length() - 18)
+        total = tensor_bytes(1 << hll_p, 4) + tensor_bytes(1, 8) + tensor_bytes(5, 8) + tensor_bytes(2 * 4096, 8)
+        for log2 in (auto if sample_log2 is None else sample_log2, auto if heavy_log2 is None else heavy_log2):
+            cap = next_pow2(max(1024, 2 * (hint >> log2) + 256))
+            total += tensor_bytes(cap * abi.HM_SLOT_BYTES // 8, 8) + tensor_bytes(1, 4)
+        return total
 
     def reset(self, stream=None):
         abi.call("hm_card_init", ctypes.byref(self.card), _stream(stream))
@@ -498,20 +609,31 @@ class CardSketch:
         abi.call("hm_card_summary", ctypes.byref(self.card), min_depth, heavy_min, self.heavy_keys.data_ptr(),
                  self.heavy_cap, self.summary_buf.data_ptr(), _stream(stream))
 
-    def result(self, stream=None) -> CardResult:
-        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
-        raw = self.summary_buf.cpu().numpy()
+    def fetch(self, stream=None) -> list:
+        """Queue copies of the summary hm_card_summary wrote (and of the sample tables' status
+        words) into pinned host memory on the stream (see fetch_async); decode() them once the
+        stream has passed."""
+        return fetch_async([self.summary_buf, self.heavy_keys] + [status for _, status in self._tabs], stream)
+
+    def decode(self, fetched: list) -> CardResult:
+        raw = fetched[0].numpy()
         est = float(raw[:1].view(np.float64)[0])
         u = raw.view(np.uint64)
         n_heavy = int(u[3])
-        hk = self.heavy_keys[: 2 * min(n_heavy, self.heavy_cap)].cpu().numpy().view(np.uint64).reshape(-1, 2)
+        hk = fetched[1].numpy()[: 2 * min(n_heavy, self.heavy_cap)].view(np.uint64).reshape(-1, 2)
         order = np.lexsort((hk[:, 1], hk[:, 0])) if len(hk) else np.zeros(0, np.int64)
         rc = abi.HM_OK
-        for _, status in self._tabs:
-            if int(status.item()) & abi.HM_ST_TABLE_FULL:
+        for status in fetched[2:]:
+            if int(status[0]) & abi.HM_ST_TABLE_FULL:
                 rc = abi.HM_ECAPACITY
         return CardResult(est, int(u[1]), int(u[2]), n_heavy, int(u[4]), self.hll_p, self.sample_log2,
                           self.heavy_log2, hk[order, 0].copy(), hk[order, 1].copy(), rc)
+
+    def result(self, stream=None) -> CardResult:
+        """Synchronize the stream and return the summary."""
+        fetched = self.fetch(stream)
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        return self.decode(fetched)
 
     def run(self, batches, min_depth: int = 2, heavy_min: int = 16, heavy_cap: int | None = None,
             stream=None, occ: OccStream | None = None) -> CardResult:

@@ -7,10 +7,15 @@ while others are on the GPU starts as soon as a slot and memory free up, and
 its work overlaps theirs on the device.  Each admitted job runs the whole
 path on its own HIP stream:
 
-    pinned host -> HBM copy -> pack -> init -> pass 1 -> pass 2 -> classify -> export
+    pinned host -> HBM copy -> pack -> init -> pass 1 -> pass 2 -> export (classifying inline)
 
 Its table and export stay device-resident until the job completes.  Latency
-is completion time minus arrival time.
+is completion time minus arrival time.  The scheduler's thread never waits
+on a stream: a job's status word, record count and digest (and a plan's
+summary) are copied into pinned host memory on the job's own stream ahead
+of the event it polls.  A blocking read would wait behind the other jobs'
+kernels, which hold every compute unit while they run, and the scheduler
+could neither admit jobs nor start their copies meanwhile.
 
 A backend with `plans` set (and `plan`, `planned`, `finish_plan`, `discard`,
 `plan_footprint`)
@@ -81,7 +86,8 @@ class Scheduler:
         every slot is busy, so that the next job is ready when a slot frees (else a job is planned
         only once a slot is free and no planned job waits: nothing overlaps a running job)."""
         self.backend = backend
-        self.budget = int(budget_bytes)
+        # never more than the backend's own memory, if it states it
+        self.budget = min(int(budget_bytes), int(getattr(backend, "capacity_bytes", budget_bytes)))
         self.max_slots = int(max_slots)
         self.poll_s = poll_s
         self.max_planning = max(1, int(max_planning))
@@ -93,6 +99,9 @@ class Scheduler:
         be = self.backend
         planner = bool(getattr(be, "plans", False))
         first_need = be.plan_footprint if planner else be.footprint
+        # placement hooks of a backend whose memory can fragment (else the byte budget decides alone)
+        can_plan = getattr(be, "can_plan", lambda j, then=None: True)
+        can_start = getattr(be, "can_start", lambda j, h=None: True)
         order = sorted(range(len(jobs)), key=lambda i: jobs[i].arrival)
         recs = {j.id: Record(j.id, j.arrival) for j in jobs}
         for j in jobs:
@@ -105,6 +114,7 @@ class Scheduler:
         used = 0
         planning = []                # [job, plan handle, bytes held] of the jobs being planned, oldest first
         ready = None                 # (job, plan handle, bytes held): planned, waiting for admission
+        replanned = {}               # job id -> plans given back because the job could not be placed
         while nxt < len(order) or queue or running or planning or ready:
             now = clock.now()
             while nxt < len(order) and jobs[order[nxt]].arrival <= now:
@@ -145,7 +155,7 @@ class Scheduler:
                         recs[j.id].done = clock.now()
                         recs[j.id].status = "capacity"
                         continue
-                    if used - pb + b > self.budget:
+                    if used - pb + b > self.budget or not can_start(j, h):
                         break
                     ready = None
                     running[j.id] = (be.start(j, h), b)
@@ -155,7 +165,7 @@ class Scheduler:
                     break
                 j = queue[0]
                 b = be.footprint(j)
-                if used + b > self.budget:
+                if used + b > self.budget or not can_start(j):
                     break
                 queue.pop(0)
                 if np.isnan(recs[j.id].admitted):
@@ -169,7 +179,7 @@ class Scheduler:
                 while len(planning) < self.max_planning and queue:
                     j = queue[0]
                     pb = be.plan_footprint(j)
-                    if used + max(held, 0) + pb > self.budget:
+                    if used + max(held, 0) + pb > self.budget or not can_plan(j, ready[0] if ready else None):
                         break
                     queue.pop(0)
                     if np.isnan(recs[j.id].admitted):
@@ -177,14 +187,29 @@ class Scheduler:
                     planning.append([j, be.plan(j), pb])
                     used += pb
                 # nothing running and the ready job does not fit beside the later plans' buffers:
-                # give back the newest finished plan (its job goes back to the queue's front)
-                if ready is not None and not running and planning:
+                # give back the newest finished plan (its job goes back to the queue's front); with
+                # no later plan, a ready job that cannot be placed alone gives back its own plan and
+                # is planned again into memory that is then free
+                if ready is not None and not running:
                     rj, rh, rpb = ready
-                    if used - rpb + be.footprint(rj) > self.budget and be.planned(planning[-1][1]):
+                    blocked = used - rpb + be.footprint(rj) > self.budget or not can_start(rj, rh)
+                    if blocked and planning and be.planned(planning[-1][1]):
                         j, h, pb = planning.pop()
                         be.discard(h)
                         used -= pb
                         queue.insert(0, j)
+                    elif blocked and not planning:
+                        be.discard(rh)
+                        used -= rpb
+                        ready = None
+                        replanned[rj.id] = replanned.get(rj.id, 0) + 1
+                        if replanned[rj.id] > 1:  # blocked alone in empty memory: it cannot fit
+                            recs[rj.id].done = clock.now()
+                            recs[rj.id].status = "capacity"
+                        else:
+                            meta = {x: v for x, v in rj.meta.items() if x not in ("plan", "card")}
+                            queue.insert(0, Job(rj.id, rj.arrival, rj.n_bases, rj.read_len, rj.distinct_est,
+                                                rj.kept_est, rj.payload, meta))
             self.trace.append((now, len(queue), len(running), used))
             if running or queue or planning or ready:
                 clock.sleep(self.poll_s)
@@ -219,13 +244,24 @@ def summarize(recs: list[Record], positions: dict, trace=None) -> dict:
 class GpuBackend:
     """Runs each job through the C ABI on its own HIP stream.  With plan=True
     (default) each job is sized by a cardinality pass before admission; with
-    plan=False by the job's own size hints (distinct_est, kept_est)."""
+    plan=False by the job's own size hints (distinct_est, kept_est).
+
+    Device memory: one arena of `memory_bytes`, reserved at construction
+    (give the scheduler the same budget).  A job holds three slabs of it:
+    its ASCII and quality bytes with the cardinality pass's state (from the
+    plan until the plan has finished: the packed reads replace them), its
+    packed reads (until the job completes) and its table, list and output
+    (from admission until the job completes).  The scheduler asks
+    can_plan / can_start whether the slabs can be placed, besides its byte
+    budget."""
 
     def __init__(self, k: int, qcut: int = 20, min_depth: int = 2, table_load: float = 0.45, bloom_bits: float = 12.0,
-                 n_hash: int = 4, device="cuda", plan: bool = True, keep_records: bool = False):
+                 n_hash: int = 4, device="cuda", plan: bool = True, keep_records: bool = False,
+                 memory_bytes: int = 8 << 30):
         """keep_records: copy every finished job's records to the host, sorted by key
         (`records[job id]`), besides the count and digest each result holds."""
         import torch
+        from .arena import DeviceArena
         self.torch = torch
         self.keep_records = keep_records
         self.records = {}
@@ -234,6 +270,8 @@ class GpuBackend:
         self.table_load, self.bloom_bits, self.n_hash = table_load, bloom_bits, n_hash
         self._streams = []
         self.plans = plan  # the scheduler plans jobs (cardinality pass) before admission
+        self.arena = DeviceArena(memory_bytes, self.device)
+        self.capacity_bytes = self.arena.size
 
     # ---- sizes
     def _hint_sizes(self, j: Job):
@@ -247,64 +285,107 @@ class GpuBackend:
     def sizes(self, j: Job):
         return j.meta["plan"] if "plan" in j.meta else self._hint_sizes(j)
 
-    @staticmethod
-    def _reads_bytes(j: Job) -> int:
-        return 2 * j.n_bases + j.n_bases // 2 + 64  # ASCII + Phred, packed reads
+    def _slab_bytes(self, j: Job) -> tuple[int, int]:
+        """(bytes of the slab with ASCII, quality and the cardinality state, bytes of the packed reads)."""
+        from .kmer import CardSketch, packed_bytes, tensor_bytes
+        reads = 2 * tensor_bytes(j.n_bases, 1)
+        if self.plans:
+            reads += CardSketch.bytes_for(j.n_bases)
+        return reads, packed_bytes(j.n_bases)
 
-    def _sketch_bytes(self, j: Job) -> int:
-        from .kmer import next_pow2
-        hint = max(j.n_bases, 1)
-        cap = next_pow2(max(1024, 2 * (hint >> max(0, hint.bit_length() - 18)) + 256))
-        return 2 * 64 * cap + 4 * (1 << 14)
+    def _count_bytes(self, j: Job) -> int:
+        from .kmer import KmerCounter, Records
+        cap, bw, lcap, ocap = self.sizes(j)
+        card = j.meta.get("card")
+        n_heavy = 0 if card is None else min(len(card.heavy_hi), self._max_heavy())
+        return (KmerCounter.bytes_for(cap, bw, lcap, n_heavy, min_depth=self.min_depth)
+                + Records.bytes_for(ocap))
+
+    @staticmethod
+    def _max_heavy() -> int:
+        from . import abi
+        return abi.HM_MAX_HEAVY
 
     def plan_footprint(self, j: Job) -> int:
-        return self._reads_bytes(j) + self._sketch_bytes(j)
+        return sum(self._slab_bytes(j))
 
     def footprint(self, j: Job) -> int:
-        from .kmer import next_pow2
-        cap, bw, lcap, ocap = self.sizes(j)
-        cap = next_pow2(max(cap, 2 * bw))  # the Bloom filter lives in the table: 32 bits per slot
-        return self._reads_bytes(j) + 64 * cap + cap // 2 + 17 * lcap + 54 * ocap
+        """Bytes the job holds while it counts (a planned job no longer holds its ASCII and quality)."""
+        reads, packed = self._slab_bytes(j)
+        return (packed if "plan" in j.meta else reads + packed) + self._count_bytes(j)
+
+    def can_plan(self, j: Job, then: Job | None = None) -> bool:
+        """Whether j's plan slabs can be placed now, and still leave room for the counting slab
+        of `then` (the planned job waiting for admission)."""
+        need = list(self._slab_bytes(j))
+        if then is not None:
+            need.append(self._count_bytes(then))
+        return self.arena.fits(need)
+
+    def can_start(self, j: Job, plan_handle=None) -> bool:
+        need = [self._count_bytes(j)]
+        if plan_handle is None:
+            need = list(self._slab_bytes(j)) + need
+        return self.arena.fits(need)
 
     def _stream(self):
         return self._streams.pop() if self._streams else self.torch.cuda.Stream(device=self.device)
 
     # ---- planning: reads to the device, pack, cardinality pass
-    def _upload(self, j: Job, st):
+    def _upload(self, j: Job, st, slabs):
+        """Copy the job's reads in and pack them, on stream st, into the two slabs (reads, packed)."""
         from . import kmer
         torch = self.torch
         ascii_h, qual_h = j.payload
+        reads, packed_slab = slabs
         with torch.cuda.stream(st):
-            a = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
-            q = torch.empty(j.n_bases, dtype=torch.uint8, device=self.device)
+            a = reads.empty(j.n_bases, torch.uint8)[:j.n_bases]
+            q = reads.empty(j.n_bases, torch.uint8)[:j.n_bases]
             a.copy_(ascii_h, non_blocking=True)
             q.copy_(qual_h, non_blocking=True)
-            packed = kmer.pack_reads(a, q, read_len=j.read_len, qcut=self.qcut, stream=st)
-        return a, q, packed
+            packed = kmer.pack_reads(a, q, read_len=j.read_len, qcut=self.qcut, stream=st,
+                                     out=kmer.new_packed(j.n_bases, self.device, packed_slab))
+        return packed
+
+    def _slabs(self, j: Job):
+        from .arena import Slab
+        reads_b, packed_b = self._slab_bytes(j)
+        packed = Slab(self.arena, packed_b)
+        try:
+            reads = Slab(self.arena, reads_b, high=True)  # short-lived: the high end
+        except MemoryError:
+            packed.release()
+            raise
+        return reads, packed
 
     def plan(self, j: Job):
         from . import kmer
         torch = self.torch
         st = self._stream()
-        bufs = self._upload(j, st)
+        slabs = self._slabs(j)
+        packed = self._upload(j, st, slabs)
         with torch.cuda.stream(st):
-            sk = kmer.CardSketch(self.k, j.n_bases, device=self.device)
+            sk = kmer.CardSketch(self.k, j.n_bases, device=self.device, alloc=slabs[0])
             sk.reset(st)
-            sk.update(bufs[2], st)
+            sk.update(packed, st)
             sk.summarize(min_depth=self.min_depth, stream=st)
+            fetched = sk.fetch(st)  # read after the event: the scheduler never blocks on a stream
             ev = torch.cuda.Event()
             ev.record(st)
-        return {"job": j, "stream": st, "event": ev, "sketch": sk, "bufs": bufs}
+        return {"job": j, "stream": st, "event": ev, "sketch": sk, "fetched": fetched, "packed": packed,
+                "slabs": list(slabs)}
 
     def planned(self, h) -> bool:
         return h["event"].query()
 
     def finish_plan(self, h) -> Job:
         """The planned job, with table / filter / list / output sizes from its cardinality pass
-        (doubled per earlier capacity retry)."""
+        (doubled per earlier capacity retry).  The plan's event has completed, so the slab of
+        ASCII, quality and cardinality state is released here."""
         from . import kmer
         j = h["job"]
-        card = h.pop("sketch").result(h["stream"])
+        card = h.pop("sketch").decode(h.pop("fetched"))
+        h["slabs"][0].release()
         cap, bw, lcap = kmer.plan_sizes(card, n_hash=self.n_hash, bloom_bits=self.bloom_bits,
                                         table_load=self.table_load, device=self.device)
         cap *= j.meta.get("grow_table", 1)
@@ -314,27 +395,38 @@ class GpuBackend:
         return Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est, j.payload, meta)
 
     def discard(self, h):
-        self._streams.append(h["stream"])
+        """Give back a plan (finished, or not yet started counting)."""
+        if "event" in h:
+            h["event"].synchronize()
+        for sl in h.get("slabs", ()):
+            sl.release()
+        if "stream" in h:
+            self._streams.append(h["stream"])
         h.clear()
 
     # ---- the counting passes
     def start(self, j: Job, plan_handle=None):
         from . import kmer
+        from .arena import Slab
         torch = self.torch
         cap, bw, lcap, ocap = self.sizes(j)
         if plan_handle is not None:
-            st, (a, q, packed) = plan_handle["stream"], plan_handle["bufs"]
+            st, packed, slabs = plan_handle["stream"], plan_handle["packed"], plan_handle["slabs"]
         else:
             st = self._stream()
-            a, q, packed = self._upload(j, st)
+            slabs = list(self._slabs(j))
+            packed = self._upload(j, st, slabs)
+        count = Slab(self.arena, self._count_bytes(j))
+        slabs.append(count)
         with torch.cuda.stream(st):
             kc = kmer.KmerCounter(self.k, cap, bw, lcap, n_hash=self.n_hash, min_depth=self.min_depth,
-                                  heavy=j.meta.get("card"), device=self.device)
-            out = kmer.Records(ocap, device=self.device)
-            kc.run([packed], out, stream=st)
+                                  heavy=j.meta.get("card"), device=self.device, alloc=count)
+            out = kmer.Records(ocap, device=self.device, alloc=count)
+            kc.run([packed], out, stream=st, fused=True)
+            fetched = (kc.fetch_status(st),) + out.fetch_summary(st)
             ev = torch.cuda.Event()
             ev.record(st)
-        return {"job": j, "stream": st, "event": ev, "kc": kc, "out": out, "bufs": (a, q, packed)}
+        return {"job": j, "stream": st, "event": ev, "kc": kc, "out": out, "fetched": fetched, "slabs": slabs}
 
     def poll(self, h) -> bool:
         return h["event"].query()
@@ -342,16 +434,17 @@ class GpuBackend:
     def finish(self, h):
         from . import abi
         kc, out, st, j = h["kc"], h["out"], h["stream"], h["job"]
-        rc = kc.status(stream=st)
+        word, n_out, digest = h["fetched"]  # pinned host copies: the job's event has completed
+        rc = kc.status_code(word)
         result = None
         status = "ok"
         if rc == abi.HM_OK:
-            result = {"n_out": int(out.n_out.item()), "digest": out.digest_words()}
-            if self.keep_records:  # the job's stream is done (hm_status synchronized it)
-                self.records[j.id] = out.to_numpy()
+            result = {"n_out": int(n_out[0]), "digest": out.digest_words((n_out, digest))}
+            if self.keep_records:
+                self.records[j.id] = out.to_numpy(int(n_out[0]))
         elif rc in (abi.HM_ECAPACITY, abi.HM_EOUTPUT):
             # too small for this job: rerun from scratch with the structure that overflowed doubled
-            s = int(kc.status_buf.item())
+            s = int(word[0]) & 0xFFFFFFFF
             meta = {x: v for x, v in j.meta.items() if x not in ("plan", "card")}
             if s & abi.HM_ST_TABLE_FULL:
                 meta["kept"] = 2 * meta.get("kept", j.kept_est)
@@ -360,13 +453,15 @@ class GpuBackend:
                 meta["list"] = 2 * meta.get("list", j.distinct_est * 1.2)
                 meta["grow_list"] = 2 * meta.get("grow_list", 1)
             if rc == abi.HM_EOUTPUT:
-                meta["out"] = int(out.n_out.item() * 1.1) + 1024
+                meta["out"] = int(int(n_out[0]) * 1.1) + 1024
                 meta["grow_out"] = 2 * meta.get("grow_out", 1)
             status, result = "retry", Job(j.id, j.arrival, j.n_bases, j.read_len, j.distinct_est, j.kept_est,
                                           j.payload, meta)
         else:
             status = rc
-        h.clear()  # drop device buffers: the caching allocator reuses them once the stream is done
+        for sl in h["slabs"]:  # the job's work on the device has completed
+            sl.release()
+        h.clear()
         self._streams.append(st)
         return status, result
 

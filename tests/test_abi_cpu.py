@@ -146,6 +146,24 @@ def test_occ_stream_rejections(L):
                                 None) == abi.HM_EINVAL
 
 
+def test_status_code_maps_words_on_the_host(L):
+    """hm_status_code maps a status word already on the host to the code hm_status returns:
+    errors by severity (timeout, overflow, capacity, output), the classification bit alone is
+    no error."""
+    assert L.hm_status_code(0) == abi.HM_OK
+    assert L.hm_status_code(abi.HM_ST_CLASSIFIED) == abi.HM_OK
+    assert L.hm_status_code(abi.HM_ST_TABLE_FULL) == abi.HM_ECAPACITY
+    assert "count table" in abi.last_error()
+    assert L.hm_status_code(abi.HM_ST_LIST_FULL | abi.HM_ST_CLASSIFIED) == abi.HM_ECAPACITY
+    assert "first-occurrence list" in abi.last_error()
+    assert L.hm_status_code(abi.HM_ST_STREAM_FULL) == abi.HM_ECAPACITY
+    assert "occurrence stream" in abi.last_error()
+    assert L.hm_status_code(abi.HM_ST_OUTPUT_FULL) == abi.HM_EOUTPUT
+    assert L.hm_status_code(abi.HM_ST_OUTPUT_FULL | abi.HM_ST_TABLE_FULL) == abi.HM_ECAPACITY
+    assert L.hm_status_code(abi.HM_ST_OVERFLOW | abi.HM_ST_TABLE_FULL) == abi.HM_EOVERFLOW
+    assert L.hm_status_code(abi.HM_ST_TIMEOUT | abi.HM_ST_OVERFLOW) == abi.HM_ETIMEOUT
+
+
 def test_random_access_rejects(L):
     assert L.hm_random_access(None, 1024, 0, 10, 1, 8, None) == abi.HM_EINVAL
     assert L.hm_random_access(8, 1000, 0, 10, 1, 8, None) == abi.HM_EINVAL

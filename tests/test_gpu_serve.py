@@ -94,3 +94,23 @@ def test_planned_and_hinted_sizing_agree():
     hinted = Scheduler(GpuBackend(51, plan=False), budget_bytes=8 << 30, max_slots=2).run(jobs, max_retries=20)
     assert [r.result for r in planned] == [r.result for r in hinted]
     assert all(r.status == 0 for r in planned)
+
+
+def test_tight_arena_waits_and_agrees():
+    """The same job stream through an arena barely larger than what one job at a time needs:
+    jobs wait for room (and may be planned again when their slabs cannot be placed), every
+    result equals the one from a roomy arena, nothing spills, and the arena is empty at the end."""
+    _, builders = synth.serving_jobs(n_jobs=6, scale=0.005)
+    pool = [b() for b in builders]
+    jobs, _ = make_jobs(pool, n_jobs=12, rate=400.0)
+    roomy = GpuBackend(51)
+    ref = Scheduler(roomy, budget_bytes=8 << 30, max_slots=1, max_planning=1, plan_while_busy=False).run(jobs)
+    assert all(r.status == 0 for r in ref)
+    one_at_a_time = roomy.arena.peak
+    tight = GpuBackend(51, memory_bytes=int(one_at_a_time * 1.3))
+    sch = Scheduler(tight, budget_bytes=8 << 30, max_slots=4, max_planning=2)
+    assert sch.budget == tight.arena.size
+    got = sch.run(jobs)
+    assert [r.result for r in got] == [r.result for r in ref]
+    assert tight.arena.used == 0 and tight.arena.spills == 0 and roomy.arena.spills == 0
+    assert tight.arena.peak <= tight.arena.size

@@ -219,3 +219,99 @@ def test_planned_job_too_large_is_rejected():
             Job(1, 0.0, 10, 150, 1, 1, None, {"dur": 0.05, "phase2": 2})]
     recs = Scheduler(be, budget_bytes=100, max_slots=2, poll_s=1e-3).run(jobs, clock=clock)
     assert recs[0].status == "capacity" and recs[1].status == 0
+
+
+class ArenaBackend(PlanningBackend):
+    """PlanningBackend whose memory is a DeviceArena over a host tensor, laid out as the GPU
+    backend lays out its slabs: a plan holds a short-lived slab of meta['A'] units (the high end of
+    its hole) and the packed slab of meta['P'] units until the job ends; admission adds the
+    counting slab of meta['C'] units.  Placement can fail where the byte budget would not."""
+    UNIT = 256
+
+    def __init__(self, clock, units):
+        super().__init__(clock)
+        from paper_1705_11147_amd.arena import DeviceArena
+        self.arena = DeviceArena(units * self.UNIT, device="cpu")
+        self.capacity_bytes = self.arena.size
+
+    def _b(self, j, key):
+        return j.meta[key] * self.UNIT
+
+    def plan_footprint(self, j):
+        return self._b(j, "A") + self._b(j, "P")
+
+    def footprint(self, j):
+        assert j.meta.get("planned"), "admitted before planning"
+        return self._b(j, "P") + self._b(j, "C")
+
+    def can_plan(self, j, then=None):
+        need = [self._b(j, "A"), self._b(j, "P")] + ([self._b(then, "C")] if then is not None else [])
+        return self.arena.fits(need)
+
+    def can_start(self, j, h=None):
+        return self.arena.fits([self._b(j, "C")])
+
+    def plan(self, j):
+        from paper_1705_11147_amd.arena import Slab
+        h = super().plan(j)
+        h["P"] = Slab(self.arena, self._b(j, "P"))
+        h["A"] = Slab(self.arena, self._b(j, "A"), high=True)
+        return h
+
+    def finish_plan(self, h):
+        h["A"].release()
+        return super().finish_plan(h)
+
+    def discard(self, h):
+        super().discard(h)
+        h["A"].release()
+        h["P"].release()
+
+    def start(self, j, h=None):
+        from paper_1705_11147_amd.arena import Slab
+        r = super().start(j, h)
+        r["slabs"] = [h["P"], Slab(self.arena, self._b(j, "C"))]
+        return r
+
+    def finish(self, h):
+        for s in h["slabs"]:
+            s.release()
+        return super().finish(h)
+
+
+def test_arena_placement_replans_a_job_stranded_by_fragmentation():
+    """Job 0 (P 30 at the bottom, C 10 above it) runs while job 1 plans: job 1's packed slab
+    (20) lands above job 0's.  When job 0 ends, job 1 fits the byte budget (20 + 50 of 100) but
+    no hole holds its 50-unit counting slab (holes of 40 and 40), and nothing runs that could
+    free one.  The scheduler gives job 1's plan back and plans it again into empty memory."""
+    clock = VirtualClock()
+    be = ArenaBackend(clock, 100)
+    jobs = [Job(0, 0.0, 1, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.001, "A": 5, "P": 30, "C": 10}),
+            Job(1, 0.01, 1, 150, 1, 1, None, {"dur": 0.05, "plan_dur": 0.001, "A": 5, "P": 20, "C": 50})]
+    sch = Scheduler(be, budget_bytes=10 ** 9, max_slots=4, poll_s=1e-3, max_planning=2)
+    assert sch.budget == 100 * ArenaBackend.UNIT  # never more than the backend's memory
+    recs = sch.run(jobs, clock=clock)
+    assert [r.status for r in recs] == [0, 0]
+    assert sum(1 for e in be.events if e[0] == "plan" and e[1] == 1) == 2
+    assert be.arena.used == 0 and be.arena.spills == 0
+
+
+def test_arena_placement_under_load():
+    """A Poisson stream of jobs of mixed sizes through an arena of the budget's size: every job
+    completes, the arena never overflows or spills, and it is empty at the end."""
+    rng = np.random.default_rng(11)
+    clock = VirtualClock()
+    be = ArenaBackend(clock, 1000)
+    t = np.cumsum(rng.exponential(1 / 200.0, 300))
+    jobs = []
+    for i in range(300):
+        size = int(np.exp(rng.uniform(np.log(5), np.log(150))))
+        jobs.append(Job(i, float(t[i]), 1, 150, 1, 1, None,
+                        {"dur": 0.002 * size ** 0.5, "plan_dur": 0.0005 * size ** 0.5,
+                         "A": 2 * size, "P": size // 2 + 1, "C": int(size * rng.uniform(1, 3)) + 1}))
+    sch = Scheduler(be, budget_bytes=1000 * ArenaBackend.UNIT, max_slots=4, poll_s=1e-3, max_planning=2)
+    recs = sch.run(jobs, clock=clock)
+    assert all(r.status == 0 for r in recs)
+    assert max(x[3] for x in sch.trace) <= 1000 * ArenaBackend.UNIT
+    assert be.arena.used == 0 and be.arena.spills == 0
+    assert be.arena.peak <= be.arena.size
