@@ -537,8 +537,11 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
                 uint32_t mask = 0;
                 for (uint32_t j = 0; j < a.n_hash; ++j) mask |= 1u << ((g >> (5 * j)) & 31);
                 uint32_t *w = &a.slots[h & a.cmask].cls;
-                const uint32_t old = __hip_atomic_fetch_or(w, mask, RLX, AGT);
-                seen = (old & mask) == mask;
+                // Filter bits are only ever set while counting, so bits a plain (possibly stale) load
+                // shows are set for good: a k-mer whose bits all show needs no atomic to know it was
+                // seen.  Otherwise the atomic OR sets them and decides.
+                seen = (*w & mask) == mask;
+                if (!seen) seen = (__hip_atomic_fetch_or(w, mask, RLX, AGT) & mask) == mask;
             }
             if (seen) pr = table_find<KW>(a.slots, a.cmask, h, A, B, a.max_probe, true, pr.used);
             else deferred = true;
