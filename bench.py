@@ -325,9 +325,9 @@ def measure_contigs(kc, k, n_records, stream, log, reps=3, rates=None):
 
 def owner_zero_mask(key_hi, key_lo, bits: int):
     """Records of owner 0 of 2^bits under the owner map of hm_params_t (own = the top bits of
-    H = fmix64(fmix64(key_hi ^ 0x243F6A8885A308D3) ^ key_lo)), computed with torch on the
-    device: wrapping int64 products are the unsigned 64-bit ones, and shifts are made logical
-    by masking.  A checker for the sub-shard comparison, outside the library."""
+    H = (key_lo ^ key_hi * 0x9E3779B97F4A7C15) * 0xD1B54A32D192ED03 mod 2^64), computed with
+    torch on the device: wrapping int64 products are the unsigned 64-bit ones, and the shift is
+    made logical by masking.  A checker for the sub-shard comparison, outside the library."""
     import torch
 
     def s64(c):
@@ -336,14 +336,7 @@ def owner_zero_mask(key_hi, key_lo, bits: int):
     def srl(x, n):
         return (x >> n) & ((1 << (64 - n)) - 1)
 
-    def fmix(x):
-        x = x ^ srl(x, 33)
-        x = x * s64(0xFF51AFD7ED558CCD)
-        x = x ^ srl(x, 33)
-        x = x * s64(0xC4CEB9FE1A85EC53)
-        return x ^ srl(x, 33)
-
-    h = fmix(fmix(key_hi ^ s64(0x243F6A8885A308D3)) ^ key_lo)
+    h = (key_lo ^ key_hi * s64(0x9E3779B97F4A7C15)) * s64(0xD1B54A32D192ED03)
     return srl(h, 64 - bits) == 0 if bits > 0 else torch.ones_like(h, dtype=torch.bool)
 
 

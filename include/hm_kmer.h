@@ -112,8 +112,8 @@ typedef struct {
     /* Owner-computes partition (section "Parallel k-mer analysis"): keep the
      * keys with own(key) == owner (n_owners = 1 keeps all), where
      * own(key) = floor(H * n_owners / 2^64) and
-     * H = fmix64(fmix64(key_hi ^ 0x243F6A8885A308D3) ^ key_lo), fmix64 being
-     * the 64-bit finalizer of MurmurHash3.  For n_owners a power of two the
+     * H = (key_lo ^ key_hi * 0x9E3779B97F4A7C15) * 0xD1B54A32D192ED03 mod 2^64
+     * (multiply-shift hashing).  For n_owners a power of two the
      * owners nest: owner 0 of 2^b is the part of owner 0 of 2^a (a < b) whose
      * H has its top b bits zero. */
     uint32_t n_owners;

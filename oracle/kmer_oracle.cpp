@@ -31,10 +31,11 @@
  *     qualities of the bases inside the k-mer are not used;
  *   - a window containing a non-ACGT byte yields no k-mer; a neighbour that
  *     is non-ACGT or beyond the read end yields no tally;
- *   - owner map (owner-computes, section "Parallel k-mer analysis"):
+ *   - owner map (owner-computes, section "Parallel k-mer analysis", which
+ *     hashes each k-mer to its owner without fixing the function):
  *     own(key) = floor(H(key) * n_owners / 2^64) with
- *     H = fmix64(fmix64(hi ^ 0x243F6A8885A308D3) ^ lo), fmix64 being the
- *     64-bit finalizer of Austin Appleby's MurmurHash3 (public domain).
+ *     H = (lo ^ hi * 0x9E3779B97F4A7C15) * 0xD1B54A32D192ED03 mod 2^64, the
+ *     multiply-shift scheme (the high bits of a product by an odd constant).
  *
  * Threads, two plain schemes (both exact, each pinned by a test):
  *   - key-partitioned (default): thread t of T keeps the keys whose
@@ -69,7 +70,8 @@ typedef unsigned __int128 u128;
 
 namespace {
 
-constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ULL;  /* method-defined owner map */
+constexpr uint64_t kOwnerMul1 = 0x9E3779B97F4A7C15ULL;  /* method-defined owner map */
+constexpr uint64_t kOwnerMul2 = 0xD1B54A32D192ED03ULL;
 constexpr uint64_t kShardSeed = 0x13198A2E03707344ULL;  /* test sampling shards */
 constexpr uint64_t kThreadSeed = 0xA4093822299F31D0ULL; /* oracle thread partition */
 constexpr uint64_t kCardSeed = 0xB7E151628AED2A6AULL;   /* method-defined cardinality hash */
@@ -138,13 +140,14 @@ struct orc_result {
     int64_t positions = 0; /* valid k-mer windows scanned (before owner/shard filters) */
 };
 
-uint32_t orc_owner(uint64_t hi, uint64_t lo, uint32_t n_owners) { return part_of(key_hash(hi, lo, kOwnerSeed), n_owners); }
+inline uint64_t owner_hash(uint64_t hi, uint64_t lo) { return (lo ^ hi * kOwnerMul1) * kOwnerMul2; }
+uint32_t orc_owner(uint64_t hi, uint64_t lo, uint32_t n_owners) { return part_of(owner_hash(hi, lo), n_owners); }
 uint32_t orc_shard(uint64_t hi, uint64_t lo, uint32_t n_shards) { return part_of(key_hash(hi, lo, kShardSeed), n_shards); }
 
 /* vector forms for filtering exported records: which = 0 owner map, 1 shard */
 void orc_part_many(const uint64_t *hi, const uint64_t *lo, int64_t n, uint32_t n_parts, int32_t which, uint32_t *out) {
-    const uint64_t seed = which == 0 ? kOwnerSeed : kShardSeed;
-    for (int64_t i = 0; i < n; ++i) out[i] = part_of(key_hash(hi[i], lo[i], seed), n_parts);
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = which == 0 ? orc_owner(hi[i], lo[i], n_parts) : orc_shard(hi[i], lo[i], n_parts);
 }
 
 /* class of one side: the base if exactly one base reaches ext_min, 4 (fork)

@@ -19,7 +19,8 @@ constexpr uint64_t kWritten = 1ull << 63;   // set in every written key word
 constexpr uint64_t kLow63 = kWritten - 1;
 constexpr uint64_t kWideBit = 1ull << 63;   // narrow counters frozen, counting goes wide
 constexpr int kCasTries = 3;                // narrow CAS attempts before going wide
-constexpr uint64_t kOwnerSeed = 0x243F6A8885A308D3ull;  // owner map (definition constant)
+constexpr uint64_t kOwnerMul1 = 0x9E3779B97F4A7C15ull;  // owner map (definition constants)
+constexpr uint64_t kOwnerMul2 = 0xD1B54A32D192ED03ull;
 constexpr int kBlock = 256;
 constexpr int kTileBases = 16384;           // bases staged in LDS per tile
 constexpr int kTileMaskWords = kTileBases / 64 + 4;
@@ -79,10 +80,12 @@ __device__ __forceinline__ uint64_t key_hash(uint64_t hi, uint64_t lo, uint64_t 
     return fmix64(lo ^ fmix64(hi ^ seed));
 }
 
-// owner-computes map: floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo);
-// for n = 2^b that is the top b bits of H (no 64-bit product)
+// owner-computes map: floor(H * n / 2^64), H = (lo ^ hi * m1) * m2 mod 2^64 (multiply-shift:
+// the top bits of the product depend on every bit of its operand); for n = 2^b that is the top b
+// bits of H (no 64-bit product).  Every window of every read is tested, so the map is kept to two
+// 64-bit products.
 __device__ __forceinline__ uint32_t owner_of(uint64_t hi, uint64_t lo, uint32_t n) {
-    uint64_t h = fmix64(fmix64(hi ^ kOwnerSeed) ^ lo);
+    const uint64_t h = (lo ^ hi * kOwnerMul1) * kOwnerMul2;
     if (n <= 1) return 0;
     if ((n & (n - 1)) == 0) return (uint32_t)(h >> (64 - (31 - __clz((int)n))));
     return (uint32_t)__umul64hi(h, (uint64_t)n);

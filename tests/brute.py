@@ -38,9 +38,9 @@ def fmix64(x: int) -> int:
 
 
 def owner(key: int, n_owners: int) -> int:
-    """own(key) = floor(H * n / 2^64), H = fmix64(fmix64(hi ^ s) ^ lo)."""
+    """own(key) = floor(H * n / 2^64), H = (lo xor hi * m1) * m2 mod 2^64 (multiply-shift)."""
     hi, lo = key >> 64, key & MASK64
-    h = fmix64(fmix64(hi ^ 0x243F6A8885A308D3) ^ lo)
+    h = ((lo ^ ((hi * 0x9E3779B97F4A7C15) & MASK64)) * 0xD1B54A32D192ED03) & MASK64
     return (h * n_owners) >> 64
 
 

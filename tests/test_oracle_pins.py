@@ -188,6 +188,28 @@ def test_owner_map_matches_independent_python():
         assert brute.owner((int(h) << 64) | int(l), 16) == int(x)
 
 
+@pytest.mark.parametrize("k,n", [(31, 16), (51, 16), (51, 5), (51, 1024)])
+def test_owner_map_balances_a_genomes_kmers(k, n):
+    """The owner map spreads the distinct canonical k-mers of a random 300 kbp genome (chains of
+    keys that are shifts of one another, as every genome's are) evenly: the owner counts pass a
+    chi-square test (n - 1 degrees of freedom, bound 6 standard deviations above the mean).  A map
+    that used only part of the key, or left its top bits poorly mixed, fails it."""
+    rng = np.random.default_rng(17 + k + n)
+    g = "".join(rng.choice(list(BASES), 300_000))
+    reads = [g[i:i + 150] for i in range(0, len(g) - 150 + 1, 100)]
+    t = run_reads(hq_reads(reads), k, min_depth=1)
+    N = len(t["count"])
+    assert N > 290_000
+    c = np.bincount(oracle.owner_of(t["key_hi"], t["key_lo"], n), minlength=n)
+    assert len(c) == n
+    e = N / n
+    chi2 = float(((c - e) ** 2 / e).sum())
+    assert chi2 < (n - 1) + 6 * (2 * (n - 1)) ** 0.5, chi2
+    if n == 1024:  # owners nest for powers of two: owner j of 1024 lies inside owner j // 64 of 16
+        o16 = oracle.owner_of(t["key_hi"], t["key_lo"], 16)
+        assert (oracle.owner_of(t["key_hi"], t["key_lo"], 1024) // 64 == o16).all()
+
+
 def test_invalid_arguments():
     a, q, off = pack_reads(hq_reads(["ACGT"]))
     with pytest.raises(ValueError):
