@@ -133,8 +133,73 @@ struct RunBits {
         const uint64_t m = i ? (m0 << i) | (m1 >> (64 - i)) : m0;
         return (m >> (64 - k)) == 0;
     }
+    // bit i (i < cnt) set: window j0 + i holds no invalid base.  One test covers the run's
+    // k + kCardRun - 1 bases; only a run that holds an invalid base tests its windows one by one.
+    __device__ __forceinline__ uint32_t valid_mask(int k, int cnt) const {
+        const uint32_t live = (1u << cnt) - 1u;
+        const int span = k + kCardRun - 1;  // <= 70
+        const bool clean = span <= 64 ? (m0 >> (64 - span)) == 0 : (m0 == 0 && (m1 >> (128 - span)) == 0);
+        if (clean) return live;
+        uint32_t v = 0;
+        for (int i = 0; i < kCardRun; ++i) v |= valid(i, k) ? 1u << i : 0u;
+        return v & live;
+    }
     // the base window j0 + i (1 <= i < kCardRun) rolls in: base j0 + i + k - 1
     __device__ __forceinline__ uint64_t base(int i) const { return (in >> (64 - 2 * i)) & 3; }
+};
+
+// The forward code and the reverse complement of a window in 2 * KW words of 32 bits (word 0
+// least significant), moved on by one base with funnel shifts: the forward code shifts left and
+// takes the base at the bottom, the reverse complement shifts right and takes the complemented
+// base at bit 2k - 2.  The masks and the word and shift of bit 2k - 2 are the same for every
+// lane (set once per launch).
+template <int KW>
+struct Roll {
+    static constexpr int N = 2 * KW;
+    uint32_t f[N], r[N];
+    struct Shape {
+        uint32_t m_top, m_next;  // masks of the two top words of the forward code
+        int ts;                  // bit 2k - 2 within the two top words (it always lies there)
+    };
+    __device__ static Shape shape(int k) {
+        const int kb = 2 * k;
+        Shape s;
+        const int lo_bits = kb - 32 * (N - 2);  // bits in the two top words (KW = 1: the only two)
+        s.m_next = lo_bits >= 32 ? ~0u : (1u << lo_bits) - 1u;
+        s.m_top = lo_bits > 32 ? (lo_bits >= 64 ? ~0u : (1u << (lo_bits - 32)) - 1u) : 0u;
+        s.ts = kb - 2 - 32 * (N - 2);
+        return s;
+    }
+    __device__ __forceinline__ void set(U128 x, U128 y) {
+        f[0] = (uint32_t)x.lo, f[1] = (uint32_t)(x.lo >> 32);
+        r[0] = (uint32_t)y.lo, r[1] = (uint32_t)(y.lo >> 32);
+        if (KW == 2) {
+            f[2] = (uint32_t)x.hi, f[3] = (uint32_t)(x.hi >> 32);
+            r[2] = (uint32_t)y.hi, r[3] = (uint32_t)(y.hi >> 32);
+        }
+    }
+    __device__ __forceinline__ void step(uint32_t b, const Shape &s) {
+#pragma unroll
+        for (int i = N - 1; i > 0; --i) f[i] = __builtin_amdgcn_alignbit(f[i], f[i - 1], 30);
+        f[0] = (f[0] << 2) | b;
+        f[N - 1] &= s.m_top;
+        f[N - 2] &= s.m_next;
+#pragma unroll
+        for (int i = 0; i < N - 1; ++i) r[i] = __builtin_amdgcn_alignbit(r[i + 1], r[i], 2);
+        r[N - 1] >>= 2;
+        const uint64_t c = (uint64_t)(b ^ 3u) << s.ts;
+        r[N - 2] |= (uint32_t)c;
+        r[N - 1] |= (uint32_t)(c >> 32);
+    }
+    __device__ __forceinline__ uint64_t fhi() const { return KW == 2 ? ((uint64_t)f[3] << 32) | f[2] : 0; }
+    __device__ __forceinline__ uint64_t flo() const { return ((uint64_t)f[1] << 32) | f[0]; }
+    __device__ __forceinline__ uint64_t rhi() const { return KW == 2 ? ((uint64_t)r[3] << 32) | r[2] : 0; }
+    __device__ __forceinline__ uint64_t rlo() const { return ((uint64_t)r[1] << 32) | r[0]; }
+    // the forward code is the canonical key (it is not larger than the reverse complement)
+    __device__ __forceinline__ bool forward() const {
+        const uint64_t a = fhi(), c = rhi();
+        return a < c || (a == c && flo() <= rlo());
+    }
 };
 
 template <int KW>
@@ -149,10 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
     const int L = a.read_len, k = a.k;
     const int W = L - k + 1;  // > 0, checked by the host
     const int runs = (W + kCardRun - 1) / kCardRun;
-    const int kb = 2 * k;
-    const uint64_t mlo = kb >= 64 ? ~0ull : ((1ull << kb) - 1);
-    const uint64_t mhi = kb > 64 ? ((1ull << (kb - 64)) - 1) : 0ull;
-    const int top = kb - 2;  // bit of the newest base in the reverse-complement code
+    const typename Roll<KW>::Shape sh = Roll<KW>::shape(k);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * reads_per_tile;
         const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
@@ -173,26 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
             const int64_t jg = (r0 + r) * L + p0;        // and in the read set
             RunBits rb;
             rb.load(w, j0, k);
-            U128 f = w.window(j0, k);
-            U128 rc = revcomp(f, k);
+            const uint32_t vm = rb.valid_mask(k, cnt);
+            Roll<KW> x;
+            {
+                const U128 f = w.window(j0, k);
+                x.set(f, revcomp(f, k));
+            }
             for (int i = 0; i < cnt; ++i) {
-                if (i > 0) {
-                    const uint64_t b = rb.base(i);
-                    if (KW == 1) {
-                        f.lo = ((f.lo << 2) | b) & mlo;
-                        rc.lo = (rc.lo >> 2) | ((3 - b) << top);
-                    } else {
-                        f.hi = ((f.hi << 2) | (f.lo >> 62)) & mhi;
-                        f.lo = ((f.lo << 2) | b) & mlo;
-                        rc.lo = (rc.lo >> 2) | (rc.hi << 62);
-                        rc.hi >>= 2;
-                        if (top >= 64) rc.hi |= (3 - b) << (top - 64);
-                        else rc.lo |= (3 - b) << top;
-                    }
-                }
-                if (!rb.valid(i, k)) continue;
-                const bool fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
-                Occ o{fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, 4, 4};
+                if (i > 0) x.step((uint32_t)rb.base(i), sh);
+                if (!((vm >> i) & 1u)) continue;
+                const bool fwd = a.forward_only || x.forward();
+                Occ o{fwd ? x.fhi() : x.rhi(), fwd ? x.flo() : x.rlo(), 4, 4};
                 if (a.n_owners > 1 && owner_of(o.hi, o.lo, a.n_owners) != a.owner) continue;
                 card_window<KW>(c, s_reg, true, o, jg + i, npos);
             }
@@ -230,10 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
     const int L = a.read_len, k = a.k;
     const int W = L - k + 1;  // > 0, checked by the host
     const int runs = (W + kCardRun - 1) / kCardRun;
-    const int kb = 2 * k;
-    const uint64_t mlo = kb >= 64 ? ~0ull : ((1ull << kb) - 1);
-    const uint64_t mhi = kb > 64 ? ((1ull << (kb - 64)) - 1) : 0ull;
-    const int top = kb - 2;
+    const typename Roll<KW>::Shape sh = Roll<KW>::shape(k);
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * reads_per_tile;
         const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
@@ -272,45 +322,29 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
         const int total = (int)(r1 - r0) * runs;
         for (int g0 = 0; g0 < total; g0 += kBlock) {  // workgroup-uniform trip count
             const int gi = g0 + threadIdx.x;
-            int cnt = 0, p0 = 0;
+            int p0 = 0;
             int64_t j0 = 0;
-            U128 f{0, 0}, rc{0, 0};
+            uint32_t vm = 0;  // windows of the lane's run that hold no invalid base (none past its read)
+            Roll<KW> x;
+            x.set(U128{0, 0}, U128{0, 0});
             RunBits rb{0, 0, 0};
             if (gi < total) {
                 const int r = gi / runs;
                 p0 = (gi - r * runs) * kCardRun;
-                cnt = min(kCardRun, W - p0);
                 j0 = (r0 + r) * L - org + p0;  // first window of the run, relative to the tile origin
                 rb.load(w, j0, k);
-                f = w.window(j0, k);
-                rc = revcomp(f, k);
+                vm = rb.valid_mask(k, min(kCardRun, W - p0));
+                const U128 f = w.window(j0, k);
+                x.set(f, revcomp(f, k));
             }
             for (int i = 0; i < kCardRun; ++i) {
-                bool act = false;
-                bool fwd = true;
-                if (i < cnt) {
-                    if (i > 0) {
-                        const uint64_t b = rb.base(i);
-                        if (KW == 1) {
-                            f.lo = ((f.lo << 2) | b) & mlo;
-                            rc.lo = (rc.lo >> 2) | ((3 - b) << top);
-                        } else {
-                            f.hi = ((f.hi << 2) | (f.lo >> 62)) & mhi;
-                            f.lo = ((f.lo << 2) | b) & mlo;
-                            rc.lo = (rc.lo >> 2) | (rc.hi << 62);
-                            rc.hi >>= 2;
-                            if (top >= 64) rc.hi |= (3 - b) << (top - 64);
-                            else rc.lo |= (3 - b) << top;
-                        }
-                    }
-                    if (rb.valid(i, k)) {
-                        fwd = a.forward_only || f.hi < rc.hi || (f.hi == rc.hi && f.lo <= rc.lo);
-                        act = a.n_owners <= 1 ||
-                              owner_of(fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, a.n_owners) == a.owner;
-                    }
-                }
+                // every lane rolls (an idle lane's code is never used): no divergent branch
+                if (i > 0) x.step((uint32_t)rb.base(i), sh);
+                const bool fwd = a.forward_only || x.forward();
+                const uint64_t khi = fwd ? x.fhi() : x.rhi(), klo = fwd ? x.flo() : x.rlo();
+                const bool act = ((vm >> i) & 1u) && (a.n_owners <= 1 || owner_of(khi, klo, a.n_owners) == a.owner);
                 const uint32_t aux = (uint32_t)(j0 + i) | ((uint32_t)(p0 + i) << 15) | (fwd ? 1u << 31 : 0u);
-                ring_push(ring, act, fwd ? f.hi : rc.hi, fwd ? f.lo : rc.lo, aux);
+                ring_push(ring, act, khi, klo, aux);
                 if (ring.tail - ring.head >= 64) finish(64);
             }
         }

@@ -319,6 +319,11 @@ __device__ __forceinline__ uint64_t slot_counts(const Slot *s, uint32_t tl[4], u
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// set bits of the 64-lane mask m below the calling lane
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // ------------------------------------------------------------------ kernels
 
 struct PassArgs {
@@ -570,7 +575,7 @@ __device__ __forceinline__ void pass1_occ(const PassArgs &a, bool act, const Occ
         const uint64_t m = __ballot(need);
         if (m) {
             const uint32_t n = (uint32_t)__popcll(m);
-            const uint32_t pos = cur.used + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1));
+            const uint32_t pos = cur.used + lanes_below(m);
             uint64_t fresh = 0;
             if (cur.used + n > CHUNK) {  // wave-uniform: take a new chunk
                 const int leader = __ffsll((long long)m) - 1;
@@ -818,7 +823,7 @@ struct OccRing {
 __device__ __forceinline__ void ring_push(OccRing &g, bool act, uint64_t hi, uint64_t lo, uint32_t aux) {
     const uint64_t m = __ballot(act);
     if (act) {
-        const uint32_t r = (g.tail + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))) & (kRing - 1);
+        const uint32_t r = (g.tail + lanes_below(m)) & (kRing - 1);
         g.key[r] = make_uint4((uint32_t)hi, (uint32_t)(hi >> 32), (uint32_t)lo, (uint32_t)(lo >> 32));
         g.aux[r] = aux;
     }
