@@ -166,7 +166,8 @@ def run_batched(args, dev, log):
     k = ws[0].params.k
     log("batched: %d sets generated in %.1fs" % (len(ws), time.time() - t0))
     t1 = time.time()
-    best, report = tune.autotune(specs, k, sample=16, reps=2, log=None)
+    # tuned on the whole batch (a sample of sets timed with few launches chose differently from run to run)
+    best, report = tune.autotune(specs, k, sample=len(specs), reps=3, log=log)
     tune_s = time.time() - t1
     log("batched: tuned in %.1fs -> %s" % (tune_s, best.key()))
     torch.cuda.empty_cache()
@@ -202,8 +203,11 @@ def run_batched(args, dev, log):
             "plain_kmers_per_s": round(positions / (ms_p / 1000), 1), "plain_ms": round(ms_p, 3),
             "speedup": round(ms_p / ms_b, 3), "outputs_identical": bool(same),
             "tuning": dict(zip(["blocks_per_cu", "tile_bases", "list_per_item", "slots_per_item", "table_load",
-                                "bloom_bits", "n_hash", "set_major"], best.key())),
+                                "bloom_bits", "n_hash", "set_major", "bloom_in_table"], best.key())),
             "tune_s": round(tune_s, 1), "tune_trials": len(report.get("trials", [])),
+            "tune_ms": {"best": round(report["ms"], 3),
+                        "bloom_in_table_false": min([t["ms"] for t in report.get("trials", [])
+                                                     if not t["tuning"]["bloom_in_table"]] or [None])},
             "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 5 plain calls"}
 
 

@@ -33,6 +33,7 @@ class Tuning:
     bloom_bits: float = 12.0     # sizing: Bloom bits per expected distinct k-mer
     n_hash: int = 4
     set_major: int = 2           # set by set, pass 2 lagging one set (cache-resident tables, few waits)
+    bloom_in_table: bool = True  # sizing: the filter in the table's slots (32 bits each) or a separate one
 
     def struct(self) -> abi.BatchTuning:
         return abi.BatchTuning(self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item,
@@ -40,7 +41,7 @@ class Tuning:
 
     def key(self) -> tuple:
         return (self.blocks_per_cu, self.tile_bases, self.list_per_item, self.slots_per_item, self.table_load,
-                self.bloom_bits, self.n_hash, self.set_major)
+                self.bloom_bits, self.n_hash, self.set_major, self.bloom_in_table)
 
 
 @dataclass
@@ -68,6 +69,8 @@ class _SetBuffers:
         self.nm = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
         self.hq = torch.empty(int(L.hm_mask_words(n_bases)), dtype=torch.int64, device=device)
         bypass = params.get("min_depth", 2) == 1 or bool(params.get("flags", 0) & abi.HM_BLOOM_BYPASS)
+        params = dict(params)
+        in_table = bool(params.pop("bloom_in_table", tuning.bloom_in_table))  # an explicit choice wins
         if plan:  # sizes from a cardinality pass over the set's own reads
             kmer.pack_reads(spec.ascii, spec.qual, read_len=spec.read_len, qcut=qcut, qual_offset=qual_offset,
                             out=self.packed())
@@ -78,7 +81,7 @@ class _SetBuffers:
             card = sk.run([self.packed()], min_depth=params.get("min_depth", 2))
             del sk
             distinct, kept = card.distinct_hi(), card.kept_hi()
-            fp = kmer.bloom_fp_rate(tuning.bloom_bits, tuning.n_hash, word_bits=32)  # the filter in the table
+            fp = kmer.bloom_fp_rate(tuning.bloom_bits, tuning.n_hash, word_bits=32 if in_table else 64)
             kept = kept + fp * max(distinct - kept, 0.0)
         else:  # the caller's size hints
             distinct, kept = spec.distinct_est, spec.kept_est
@@ -88,7 +91,8 @@ class _SetBuffers:
         cus = torch.cuda.get_device_properties(device).multi_processor_count
         # + one partly used 256-entry chunk per wave of either form, for every launch shape
         lcap = int(distinct * (1.0 if plan else 1.2)) + cus * max(8, MAX_BLOCKS_PER_CU, tuning.blocks_per_cu) * 4 * 255
-        self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, device=device, **params)
+        self.kc = KmerCounter(k, cap, bw, lcap, n_hash=tuning.n_hash, bloom_in_table=in_table, device=device,
+                              **params)
         self.out = Records(int(min(cap, keys * 1.3 + 1024)), device=device)
 
     def packed(self) -> kmer.Packed:

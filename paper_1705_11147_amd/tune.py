@@ -31,6 +31,9 @@ LAUNCH_SPACE = {
 SIZING_SPACE = {
     "table_load": [0.3, 0.45, 0.6],
     "bloom_bits": [8.0, 12.0, 16.0],
+    # with many more distinct than kept k-mers, the filter in the table (32 bits per 64-byte slot) makes
+    # the table larger than its keys need, and the clear and the export sweep every slot
+    "bloom_in_table": [True, False],
 }
 
 
