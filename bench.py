@@ -211,6 +211,65 @@ def run_batched(args, dev, log):
             "form": "hipGraph replay of clear + pack + persistent counting kernel + export, vs 64 x 5 plain calls"}
 
 
+def run_heavy(args, dev, log):
+    """Heavy hitters (the mid workload with 2% of the genome in tandem satellite arrays, so that a
+    few k-mers hold millions of windows each): pass 1 with the cardinality pass's heavy list counted
+    in workgroup-local memory, against the same pass with every occurrence going through the table;
+    both tables must be identical."""
+    import torch
+    from paper_1705_11147_amd import abi, kmer, synth
+
+    t0 = time.time()
+    w = synth.mid_heavy()
+    r = w.reads()
+    p = w.params
+    L, k = r.read_len, p.k
+    positions = r.n_reads * (L - k + 1)
+    ascii = torch.from_numpy(r.ascii).to(dev)
+    qual = torch.from_numpy(r.qual).to(dev)
+    del r
+    packed = kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut)
+    del ascii, qual
+    card = kmer.CardSketch(k, positions, device=dev).run([packed], min_depth=p.min_depth)
+    abi.check(card.status, "cardinality pass (heavy workload)")
+    cap, bw, lcap = kmer.plan_sizes(card, device=dev)
+    log("heavy: %s generated and sized in %.1fs, %d heavy hitters" % (w.name, time.time() - t0, card.n_heavy))
+    out = {"workload": w.name, "positions": positions, "heavy_hitters": card.n_heavy}
+    digests = {}
+    for name, heavy in (("heavy_in_lds", card), ("through_table", None)):
+        kc = kmer.KmerCounter(k, cap, bw, lcap, min_depth=p.min_depth, heavy=heavy, device=dev)
+        rec = kmer.Records(int(cap * 0.6), device=dev)
+        ms = []
+        for i in range(1 + args.steps):  # one untimed
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            kc.reset()
+            ev[0].record()
+            kc.insert(packed)
+            ev[1].record()
+            kc.count()
+            kc.export(rec, abi.HM_EXPORT_CLASSIFY)
+            ev[2].record()
+            torch.cuda.synchronize()
+            if i:
+                ms.append((ev[0].elapsed_time(ev[1]), ev[0].elapsed_time(ev[2])))
+        abi.check(kc.status(), "heavy workload (%s)" % name)
+        st = kc.stats()
+        digests[name] = (rec.digest_words(), int(rec.n_out.item()))
+        out[name] = {"pass1_ms": round(float(np.mean([x[0] for x in ms])), 3),
+                     "pass1_to_export_ms": round(float(np.mean([x[1] for x in ms])), 3),
+                     "wide_counts_per_position": round(st["wide_counts"] / positions, 5),
+                     "heavy_local_per_position": round(st["heavy_local"] / positions, 5)}
+        del kc, rec
+        torch.cuda.empty_cache()
+    same = digests["heavy_in_lds"] == digests["through_table"]
+    assert same, "the heavy-hitter treatment changed the table"
+    out["outputs_identical"] = bool(same)
+    out["pass1_gain"] = round(out["through_table"]["pass1_ms"] / out["heavy_in_lds"]["pass1_ms"], 3)
+    log("heavy: pass 1 %.1f ms with the heavy list in LDS, %.1f ms through the table" % (
+        out["heavy_in_lds"]["pass1_ms"], out["through_table"]["pass1_ms"]))
+    return out
+
+
 def run_serving(args, dev, log):
     """Poisson arrivals (20 jobs/s) of hexaploid-like k-mer analysis jobs
     (ancestor log-U[1,50] Mbp + 3 homeologs at 1.5%, 30x of 150 bp, 0.5%
@@ -539,6 +598,8 @@ def main():
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-heavy-workload", action="store_true",
+                    help="skip the heavy-hitter comparison on the satellite-rich mid workload")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=12)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -866,6 +927,12 @@ def main():
     batched = None
     if not args.no_batched:
         batched = run_batched(args, dev, log)
+    heavy = None
+    if not args.no_heavy_workload:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        heavy = run_heavy(args, dev, log)
     serving = None
     if not args.no_serving:
         import gc
@@ -901,6 +968,7 @@ def main():
         "h2d": h2d,
         "bloom_bypass_diagnostic": bypass,
         "batched": batched,
+        "heavy_hitters": heavy,
         "serving": serving,
         "human_share": human,
     }
