@@ -114,3 +114,32 @@ def test_tight_arena_waits_and_agrees():
     assert [r.result for r in got] == [r.result for r in ref]
     assert tight.arena.used == 0 and tight.arena.spills == 0 and roomy.arena.spills == 0
     assert tight.arena.peak <= tight.arena.size
+
+
+def test_degenerate_jobs_in_the_mix():
+    """A job with no reads and a job whose reads are shorter than k, served among ordinary jobs:
+    both complete with the oracle's empty table, and the ordinary jobs' results are the ones they
+    get without them."""
+    from paper_1705_11147_amd.serve import Job
+    _, builders = synth.serving_jobs(n_jobs=3, scale=0.003)
+    pool = [b() for b in builders]
+    jobs, _ = make_jobs(pool, n_jobs=3, rate=400.0)
+    ref = Scheduler(GpuBackend(51), budget_bytes=8 << 30, max_slots=4).run(jobs)
+    assert all(r.status == 0 for r in ref)
+    rng = np.random.default_rng(3)
+    short_a = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, 40 * 10)]
+    short_q = np.full(40 * 10, 40, np.uint8)
+    pin = lambda x: torch.from_numpy(np.ascontiguousarray(x)).pin_memory()
+    empty = Job(100, 0.001, 0, 150, 1.0, 1.0, (pin(np.zeros(0, np.uint8)), pin(np.zeros(0, np.uint8))), {})
+    short = Job(101, 0.002, 400, 40, 1.0, 1.0, (pin(short_a), pin(short_q)), {})
+    be = GpuBackend(51, keep_records=True)
+    got = Scheduler(be, budget_bytes=8 << 30, max_slots=4).run(jobs + [empty, short])
+    assert [r.status for r in got] == [0] * 5
+    assert [r.result for r in got[:3]] == [r.result for r in ref]
+    off = np.arange(0, 401, 40, dtype=np.int64)
+    exp = oracle.run(short_a, short_q, off, 51)
+    assert len(exp["count"]) == 0
+    for r in got[3:]:
+        assert r.result["n_out"] == 0
+        assert len(be.records[r.job]["count"]) == 0
+    assert be.arena.used == 0 and be.arena.spills == 0
