@@ -11,7 +11,8 @@ substitution errors, Phred ~ clamp(N(32,6),2,41), k=51, Q20, min depth 2.
 Prints ONE JSON line: the throughput; the dominant kernel's place on the HBM
 roofline; one key shard of the timed export checked against the CPU oracle;
 the oracle timed on a bounded sample (whose table the GPU must reproduce);
-and, as sub-records, the batched form (64 read sets) against the plain form,
+and, as sub-records, the tiny read set (checked against the oracle in full, the oracle timed on
+one host thread and on all of them), the batched form (64 read sets) against the plain form,
 the serving loop, and one GPU's share of the human-scale run (owner 0 of 16,
 ten 64M-read batches) with a sub-shard of its table checked against the
 oracle.
@@ -268,6 +269,93 @@ def run_heavy(args, dev, log):
     log("heavy: pass 1 %.1f ms with the heavy list in LDS, %.1f ms through the table" % (
         out["heavy_in_lds"]["pass1_ms"], out["through_table"]["pass1_ms"]))
     return out
+
+
+def run_tiny(args, dev, log, steps=50):
+    """The tiny read set (1 Mbp genome, 200k reads of 100 bp, k=21): the whole step on the GPU,
+    its table against the oracle's in full, and the oracle timed on one host thread and on all of
+    them.  The step is bound by kernel latency, not by HBM, so no roofline fraction is claimed."""
+    import torch
+    import oracle
+    from paper_1705_11147_amd import abi, kmer, synth
+
+    w = synth.tiny()
+    r = w.reads()
+    p = w.params
+    L, k = r.read_len, p.k
+    positions = r.n_reads * (L - k + 1)
+    stream = torch.cuda.current_stream()
+    ascii = torch.from_numpy(r.ascii).to(dev)
+    qual = torch.from_numpy(r.qual).to(dev)
+    packed = kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut)
+    sketch = kmer.CardSketch(k, positions, device=dev)
+    card = sketch.run([packed], min_depth=p.min_depth)
+    abi.check(card.status, "cardinality pass (tiny)")
+    cap, bw, lcap = kmer.plan_sizes(card, device=dev)
+    kc = kmer.KmerCounter(k, cap, bw, lcap, min_depth=p.min_depth, heavy=card, device=dev)
+    out = kmer.Records(int(cap * 0.6), device=dev)
+
+    stages = ["pack", "card", "init", "pass1", "pass2", "classify_export"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut, out=packed)
+        mark(1)
+        sketch.reset()
+        sketch.update(packed)
+        sketch.summarize(min_depth=p.min_depth)
+        mark(2)
+        kc.reset()
+        mark(3)
+        kc.insert(packed)
+        mark(4)
+        kc.count()
+        mark(5)
+        kc.export(out, abi.HM_EXPORT_CLASSIFY)
+        mark(6)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    # whole steps back to back, then the same steps with an event between stages
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for i in range(steps):
+        step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    sev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(10)]
+    for e in sev:
+        step(e)
+    torch.cuda.synchronize()
+    abi.check(kc.status(), "k-mer analysis (tiny)")
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    stage_ms = {x: round(float(np.median([e[i].elapsed_time(e[i + 1]) for e in sev])), 4)
+                for i, x in enumerate(stages)}
+    got = out.to_numpy()
+    threads = host_threads()
+    runs = {}
+    for name, th, sort_count in (("sort_counted_1_thread", 1, True), ("sort_counted_all_threads", threads, True),
+                                 ("hash_map_1_thread", 1, False)):
+        res = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_threads=th,
+                         sort_count=sort_count)
+        assert same_records(got, res) and res["positions"] == positions, \
+            "the tiny workload's GPU table disagrees with the oracle (%s)" % name
+        runs[name] = {"threads": th, "s": round(res["seconds"], 3),
+                      "kmers_per_s": round(positions / res["seconds"], 1)}
+    med = float(np.median(step_ms))
+    res = {"workload": w.name, "positions": positions, "kept_kmers": len(got["count"]), "table_slots": kc.capacity,
+           "steps": steps, "ms_per_step": {"median": round(med, 4), "p10": round(float(np.percentile(step_ms, 10)), 4),
+                                           "p90": round(float(np.percentile(step_ms, 90)), 4)},
+           "kmers_per_s": round(positions / (med / 1000), 1), "stage_ms": stage_ms,
+           "bound": "kernel latency (the tables fit in cache); no roofline fraction claimed",
+           "oracle_identical": True, "oracle": runs, "host_cpu": cpu_model()}
+    log("tiny: %.3f ms/step (%.3g k-mers/s), stages %s; oracle %s" % (med, positions / (med / 1000), stage_ms, runs))
+    del kc, out, packed, ascii, qual
+    return res
 
 
 def run_serving(args, dev, log):
@@ -598,6 +686,8 @@ def main():
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-tiny", action="store_true",
+                    help="skip the tiny read set (GPU step, full oracle comparison, oracle on 1 and all threads)")
     ap.add_argument("--no-heavy-workload", action="store_true",
                     help="skip the heavy-hitter comparison on the satellite-rich mid workload")
     ap.add_argument("--serve-jobs", type=int, default=200)
@@ -924,6 +1014,10 @@ def main():
 
     del kc, out, packed, ascii, qual
     torch.cuda.empty_cache()
+    tiny = None
+    if not args.no_tiny:
+        tiny = run_tiny(args, dev, log)
+        torch.cuda.empty_cache()
     batched = None
     if not args.no_batched:
         batched = run_batched(args, dev, log)
@@ -967,6 +1061,7 @@ def main():
         "contigs": contigs,
         "h2d": h2d,
         "bloom_bypass_diagnostic": bypass,
+        "tiny": tiny,
         "batched": batched,
         "heavy_hitters": heavy,
         "serving": serving,
