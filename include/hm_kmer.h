@@ -443,6 +443,91 @@ int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, 
                         hipStream_t stream);
 
 
+/* ---- binned counting: owner computes inside one GPU -------------------
+ *
+ * Section "Parallel k-mer analysis" gives every k-mer an owner by a hash of
+ * the k-mer; each occurrence travels to its owner, which filters its share
+ * with a Bloom filter and counts it in a hash table of its own.  The binned
+ * path makes the owners bins small enough for one workgroup's local memory:
+ *   hm_bin_kmers   partitions the occurrences of a read set by a hash of the
+ *                  canonical key into 2^(group_bits + bin_bits) bins of
+ *                  16-byte records (two counting-sort passes with exact
+ *                  offsets from histograms);
+ *   hm_count_bins  runs, per bin and in local memory, the two-pass method of
+ *                  hm_bloom_insert / hm_kmer_count (an occurrence of a k-mer in
+ *                  the bin's table is counted; an absent k-mer tests and sets
+ *                  its bits in the bin's Bloom filter, and is inserted and
+ *                  counted if the filter had seen it, else deferred and
+ *                  counted after the bin's last occurrence if its k-mer is in
+ *                  the table by then), then the depth filter, classification
+ *                  and export of hm_export_table with HM_EXPORT_CLASSIFY.
+ * A bin whose keys would fill its local table past three quarters (more
+ * than 384 k-mers inserted) or whose deferred occurrences pass 2048 is not
+ * counted there: its records go whole to an occurrence stream, which the
+ * global-table path counts (hm_bloom_insert_occ, hm_kmer_count,
+ * hm_export_table into a second buffer), and hm_export_merge appends that
+ * export to the binned one.  The records and the digest are those of the
+ * global-table path over the same reads; the order differs.
+ *
+ * Limits: fixed-length reads (read_off NULL) of at most 16320 bases, k <= 61
+ * (the key and its two extension codes share a 16-byte record), fewer than
+ * 2^32 windows per call. */
+
+/* Event counters of hm_count_bins (hm_bins_t.stats, HM_N_BIN_STATS 64-bit words). */
+#define HM_BIN_STAT_RECORDS 0     /* records (valid, owned windows) in the bins */
+#define HM_BIN_STAT_SPILLED_BINS 1 /* bins sent to the occurrence stream */
+#define HM_BIN_STAT_SPILLED 2     /* records sent to the occurrence stream */
+#define HM_BIN_STAT_DEFERRED 3    /* occurrences deferred by the bins' Bloom filters (bins counted locally) */
+#define HM_BIN_STAT_KEYS 4        /* k-mers inserted into the bins' local tables */
+#define HM_BIN_STAT_KEPT 5        /* records exported from the local tables */
+#define HM_N_BIN_STATS 6
+
+typedef struct {
+    uint64_t *recs;      /* 2 * capacity words, 16-byte aligned: the records, bin after bin */
+    uint64_t *tmp;       /* 2 * capacity words, 16-byte aligned: records grouped by their top group_bits
+                            (scratch of hm_bin_kmers; free afterwards, e.g. as the keys of the spill stream) */
+    uint64_t capacity;   /* records: at least n_reads * (read_len - k + 1) */
+    uint32_t group_bits; /* 0..12 */
+    uint32_t bin_bits;   /* 0..12: bins = 2^(group_bits + bin_bits) */
+    uint64_t *scratch;   /* hm_bins_scratch_bytes(group_bits, bin_bits) bytes, 8-byte aligned */
+    uint64_t *bin_start; /* 2^(group_bits + bin_bits) + 1 words: bin i holds records [bin_start[i], bin_start[i+1]) */
+    uint32_t *status;    /* device status word (cleared by hm_bin_kmers) */
+    uint64_t *stats;     /* optional (may be NULL): HM_N_BIN_STATS counters (cleared by hm_bin_kmers) */
+} hm_bins_t;
+
+/* Scratch bytes of hm_bin_kmers: for 2^g groups and 2^(g+b) bins,
+ * 8 * (2 * 2^g + 1) + 4096 * 2^g + 32 * 2^(g+b) bytes; 0 if g or b is above 12. */
+size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits);
+
+/* Partition every valid window of `r` whose key is owned (hm_params_t
+ * owner filter) into the bins of `b`: record = (key_lo, key_hi | ext << 58),
+ * ext = left | right << 3 with the extensions as pass 1 takes them.  The bin
+ * of a key is the top group_bits + bin_bits bits of
+ * (key_lo ^ key_hi * 0xC2B2AE3D27D4EB4F) * 0x165667B19E3779F9 mod 2^64
+ * (multiply-shift hashing).  HM_EINVAL (nothing launched) for variable-length
+ * reads, k > 61, more windows than b->capacity or 2^32 or more windows. */
+int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStream_t stream);
+
+/* Count the bins of `b` (after hm_bin_kmers with the same params) and export
+ * every k-mer with count >= p->min_depth, classified with p->ext_min, into
+ * `out` (only the UU k-mers with flags = HM_EXPORT_UU_ONLY; no other flag).
+ * Zeroes out->n_out, out->digest and spill->count first.  The records of bins
+ * that do not fit in local memory go to `spill` (no holes; spill->keys may be
+ * b->tmp, whose capacity suffices); count them with the global-table path
+ * and hm_export_merge.  Device errors in b->status: HM_ST_OUTPUT_FULL (out
+ * too small: *out->n_out holds the number needed), HM_ST_STREAM_FULL (spill
+ * too small).  Bloom bypass (HM_BLOOM_BYPASS or min_depth == 1) inserts every
+ * k-mer, so bins then take fewer distinct k-mers before spilling. */
+int hm_count_bins(const hm_bins_t *b, const hm_params_t *p, uint32_t flags, hm_export_t *out, hm_occ_t *spill,
+                  hipStream_t stream);
+
+/* Append src's records [0, *src->n_out) to dst after its *dst->n_out
+ * records, add the record counts and combine the digests (sum added, xor
+ * xor-ed).  Both run on `stream`; a dst too small sets HM_ST_OUTPUT_FULL in
+ * *status (dst's count then holds the number needed). */
+int hm_export_merge(const hm_export_t *src, hm_export_t *dst, uint32_t *status, hipStream_t stream);
+
+
 /* ---- contig generation (section "Parallel contig generation") ---------- */
 
 /* The UU k-mers form the de Bruijn graph: a k-mer's two-letter value names

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(PKG, "libhm_kmer.so")
-SOURCES = ["hm_kmer.hip", "hm_batch.hip", "hm_sort.hip", "hm_card.hip", "hm_contig.hip", "hm_roofline.hip"]
+SOURCES = ["hm_kmer.hip", "hm_batch.hip", "hm_sort.hip", "hm_card.hip", "hm_contig.hip", "hm_roofline.hip", "hm_bins.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -40,6 +40,9 @@ HM_EXPORT_SORTED = 8
 HM_MAX_HEAVY = 256
 HM_EXPORT_STATIC_MAX_RECORDS = 1 << 18
 
+HM_N_BIN_STATS = 6
+BIN_STAT_NAMES = ("records", "spilled_bins", "spilled", "deferred", "keys", "kept")
+
 HM_CLS_FORK = 4
 HM_CLS_X = 5
 HM_SLOT_BYTES = 64
@@ -102,6 +105,12 @@ class Occ(ctypes.Structure):
                 ("count", ctypes.c_void_p)]
 
 
+class Bins(ctypes.Structure):
+    _fields_ = [("recs", ctypes.c_void_p), ("tmp", ctypes.c_void_p), ("capacity", ctypes.c_uint64),
+                ("group_bits", ctypes.c_uint32), ("bin_bits", ctypes.c_uint32), ("scratch", ctypes.c_void_p),
+                ("bin_start", ctypes.c_void_p), ("status", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
 class Contigs(ctypes.Structure):
     _fields_ = [("seq", ctypes.c_void_p), ("seq_capacity", ctypes.c_uint64), ("off", ctypes.c_void_p),
                 ("off_capacity", ctypes.c_uint64), ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p),
@@ -155,6 +164,10 @@ SIGNATURES = {
     "hm_occ_init": ([P(Occ), vp], ctypes.c_int),
     "hm_cardinality_occ": ([P(Reads), P(Params), P(Card), P(Occ), vp], ctypes.c_int),
     "hm_bloom_insert_occ": ([P(Occ), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
+    "hm_bins_scratch_bytes": ([ctypes.c_uint32, ctypes.c_uint32], ctypes.c_size_t),
+    "hm_bin_kmers": ([P(Reads), P(Params), P(Bins), vp], ctypes.c_int),
+    "hm_count_bins": ([P(Bins), P(Params), ctypes.c_uint32, P(Export), P(Occ), vp], ctypes.c_int),
+    "hm_export_merge": ([P(Export), P(Export), vp, vp], ctypes.c_int),
     "hm_contigs_work_bytes": ([ctypes.c_uint64], ctypes.c_size_t),
     "hm_contigs": ([P(Export), ctypes.c_int32, ctypes.c_uint32, P(Contigs), vp], ctypes.c_int),
     "hm_batch_work_bytes": ([ctypes.c_int32], ctypes.c_size_t),

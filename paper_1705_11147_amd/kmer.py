@@ -182,6 +182,16 @@ class OccStream:
         share = int(windows / max(n_owners, 1) * 1.02) + 4096
         return cls(min(share, windows) + cls.slack(launches, device), device=device)
 
+    @classmethod
+    def view(cls, keys: torch.Tensor, ext: torch.Tensor, capacity: int, count: torch.Tensor) -> "OccStream":
+        """A stream over existing buffers (2 * capacity int64 key words, capacity ext bytes, one
+        int64 counter), e.g. the spill stream of BinnedCounter."""
+        o = cls.__new__(cls)
+        o.capacity, o.device = int(capacity), keys.device
+        o.keys, o.ext, o.count = keys, ext, count
+        o.occ = abi.Occ(keys.data_ptr(), ext.data_ptr(), o.capacity, count.data_ptr())
+        return o
+
     def reset(self, stream=None):
         abi.call("hm_occ_init", ctypes.byref(self.occ), _stream(stream))
 
@@ -699,6 +709,132 @@ def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, tabl
     return capacity, bloom_words, lcap
 
 
+BIN_SLOTS = 512       # local table of a bin (hm_count_bins spills a bin past 384 keys)
+BIN_DEFER_CAP = 2048  # deferred occurrences a bin holds
+MAX_BIN_BITS = 12     # group_bits and bin_bits each
+
+
+def plan_bins(distinct_hi: float, seen2_hi: float, bypass: bool = False) -> tuple[int, int]:
+    """(group_bits, bin_bits) for the binned path: enough bins that a bin's distinct k-mers (its
+    deferred occurrences, about one per distinct k-mer) stay near 900 of the 2048 its list holds,
+    and the k-mers it inserts (those seen at least twice, or with the Bloom filter bypassed every
+    distinct k-mer) near 192 of the 384 its table takes before the bin spills."""
+    need = seen2_hi / 192.0 if not bypass else distinct_hi / 192.0
+    need = max(1.0, need, distinct_hi / 900.0)
+    total = min(2 * MAX_BIN_BITS, max(0, int(math.ceil(math.log2(need)))))
+    g = min(MAX_BIN_BITS, (total + 1) // 2)
+    return g, total - g
+
+
+class BinnedCounter:
+    """The binned path (hm_bin_kmers, hm_count_bins): the occurrences partitioned by key hash into
+    bins small enough for a workgroup's local memory, each bin counted there with its own Bloom
+    filter and table.  Bins that do not fit go to a spill stream (in the buffer the partition
+    used as scratch) and are counted by the global-table path (KmerCounter.insert_occ), whose
+    export is merged into the binned one.
+
+    capacity: records (at least the windows of the read set, n_reads * (read_len - k + 1))."""
+
+    def __init__(self, k: int, capacity: int, group_bits: int, bin_bits: int, min_depth: int = 2,
+                 ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
+                 seed: int = DEFAULT_SEED, device="cuda", alloc=None):
+        self.device = torch.device(device)
+        self.bypass = bool(flags & abi.HM_BLOOM_BYPASS) or min_depth == 1
+        self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner,
+                                 flags & ~abi.HM_BLOOM_IN_TABLE, seed & (2 ** 64 - 1))
+        abi.call("hm_check_params", ctypes.byref(self.params))
+        self.capacity = int(capacity)
+        self.group_bits, self.bin_bits = int(group_bits), int(bin_bits)
+        self.n_bins = 1 << (self.group_bits + self.bin_bits)
+        n = max(self.capacity, 1)
+        self.recs = _new(2 * n, torch.int64, self.device, alloc)
+        self.tmp = _new(2 * n, torch.int64, self.device, alloc)
+        self.spill_ext = _new(n, torch.uint8, self.device, alloc)
+        sb = abi.lib().hm_bins_scratch_bytes(self.group_bits, self.bin_bits)
+        if sb == 0:
+            raise ValueError("group_bits and bin_bits must each be at most %d" % MAX_BIN_BITS)
+        self.scratch = _new((sb + 7) // 8, torch.int64, self.device, alloc)
+        self.bin_start = _new(self.n_bins + 1, torch.int64, self.device, alloc)
+        self.status_buf = _new(1, torch.int32, self.device, alloc, zero=True)
+        self.stats_buf = _new(abi.HM_N_BIN_STATS, torch.int64, self.device, alloc, zero=True)
+        self.spill_count = _new(1, torch.int64, self.device, alloc, zero=True)
+        self.bins = abi.Bins(self.recs.data_ptr(), self.tmp.data_ptr(), self.capacity, self.group_bits,
+                             self.bin_bits, self.scratch.data_ptr(), self.bin_start.data_ptr(),
+                             self.status_buf.data_ptr(), self.stats_buf.data_ptr())
+        self.spill = OccStream.view(self.tmp, self.spill_ext, self.capacity, self.spill_count)
+        self.fallback = None  # the KmerCounter of the last spilled run
+
+    @property
+    def k(self) -> int:
+        return self.params.k
+
+    def bin(self, packed: Packed, stream=None):
+        r = packed.struct()
+        abi.call("hm_bin_kmers", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.bins), _stream(stream))
+
+    def count(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
+        """hm_count_bins into `out` (flags: 0 or abi.HM_EXPORT_UU_ONLY); spilled bins are left in the
+        spill stream (see finish)."""
+        ex = out.struct(digest=digest)
+        abi.call("hm_count_bins", ctypes.byref(self.bins), ctypes.byref(self.params), flags, ctypes.byref(ex),
+                 ctypes.byref(self.spill.occ), _stream(stream))
+
+    def spilled(self) -> int:
+        """Records sent to the spill stream (synchronizes)."""
+        return int(self.spill_count.item())
+
+    def finish(self, out: Records, flags: int = 0, stream=None, digest: bool = True, distinct_per_record: float = 1.0,
+               retries: int = 4) -> int:
+        """Count the spill stream with the global-table path and merge its export into `out`
+        (nothing to do when no bin spilled).  distinct_per_record bounds the distinct k-mers per
+        spilled record for sizing the table (doubled and rerun on a capacity error).  Returns the
+        spilled records."""
+        n = self.spilled()
+        if n == 0:
+            return 0
+        est = max(1024, int(n * min(1.0, distinct_per_record)) + 1)
+        cap = next_pow2(2 * est)
+        for _ in range(retries + 1):
+            kc = KmerCounter(self.k, cap, 64, n + list_slack(1, self.device), min_depth=self.params.min_depth,
+                             ext_min=self.params.ext_min, flags=self.params.flags, seed=self.params.seed,
+                             device=self.device)
+            out2 = Records(max(1, cap // 2), device=self.device)
+            kc.reset(stream)
+            kc.insert_occ(self.spill, stream)
+            kc.count(stream)
+            kc.export(out2, flags | abi.HM_EXPORT_CLASSIFY, stream, digest=digest)
+            rc = kc.status(stream)
+            if rc == abi.HM_ECAPACITY:
+                cap *= 2
+                continue
+            abi.check(rc, "binned path: the spilled bins")
+            ex2, ex = out2.struct(digest=digest), out.struct(digest=digest)
+            abi.call("hm_export_merge", ctypes.byref(ex2), ctypes.byref(ex), self.status_buf.data_ptr(),
+                     _stream(stream))
+            self.fallback = kc
+            return n
+        raise abi.HmError(abi.HM_ECAPACITY, "binned path: the spilled bins", "still full after %d retries" % retries)
+
+    def run(self, packed: Packed, out: Records, flags: int = 0, stream=None, digest: bool = True,
+            distinct_per_record: float = 1.0) -> int:
+        """The whole binned path over one read set; returns the spilled records."""
+        self.bin(packed, stream)
+        self.count(out, flags, stream, digest)
+        return self.finish(out, flags, stream, digest, distinct_per_record)
+
+    def stats(self) -> dict:
+        v = self.stats_buf.cpu().numpy()
+        return {name: int(x) for name, x in zip(abi.BIN_STAT_NAMES, v)}
+
+    def status(self, stream=None) -> int:
+        """Code of the bins' status word (synchronizes)."""
+        (torch.cuda.current_stream(self.device) if stream is None else stream).synchronize()
+        return abi.lib().hm_status_code(int(self.status_buf.item()) & 0xFFFFFFFF)
+
+    def bin_sizes(self) -> np.ndarray:
+        return np.diff(self.bin_start.cpu().numpy())
+
+
 def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = None,
             read_off: np.ndarray | None = None, qcut: int = 20, qual_offset: int = 0, min_depth: int = 2,
             ext_min: int | None = None, n_owners: int = 1, owner: int = 0, forward_only: bool = False,
@@ -706,7 +842,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
             bloom_words: int | None = None, n_hash: int = 4, list_capacity: int | None = None,
             seed: int = DEFAULT_SEED, max_probe: int = 0, device="cuda", retries: int = 4, fused: bool = False,
             present_filter: bool = True, sizing: str = "card", heavy: bool = True,
-            bloom_in_table: bool = True, occ_stream: bool = False, occ_capacity: int | None = None) -> dict:
+            bloom_in_table: bool = True, occ_stream: bool = False, occ_capacity: int | None = None,
+            binned: bool = False, bin_bits: tuple[int, int] | None = None) -> dict:
     """Host arrays in, sorted host table out (the whole path on the GPU).
 
     Sizes not given are planned from a cardinality pass over the reads
@@ -718,7 +855,9 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     Bloom filter in the table's slots (KmerCounter) or a separate one.  occ_stream: the
     cardinality pass writes the owned occurrences to a stream (occ_capacity entries, default
     OccStream.for_windows; doubled and rerun on overflow) and pass 1 reads it instead of the
-    reads (sizing="card" only)."""
+    reads (sizing="card" only).  binned: the binned path (BinnedCounter: fixed-length reads,
+    k <= 61), with (group_bits, bin_bits) from plan_bins over a cardinality pass unless bin_bits
+    is given; its records are those of the table path."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
     q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
@@ -727,6 +866,24 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     P = packed.positions(k)
     flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
         (abi.HM_CHECKED if checked else 0)
+    if binned:
+        if bin_bits is None:
+            sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
+            c2 = sk.run([packed], min_depth=2)
+            bin_bits = plan_bins(c2.distinct_hi(), c2.kept_hi(), bypass or min_depth == 1)
+            del sk
+        bc = BinnedCounter(k, P, bin_bits[0], bin_bits[1], min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
+                           owner=owner, flags=flags, seed=seed, device=dev)
+        out = Records(max(1024, P), device=dev)
+        spilled = bc.run(packed, out, export_flags & abi.HM_EXPORT_UU_ONLY)
+        abi.check(bc.status(), "binned k-mer analysis")
+        res = out.to_numpy(sort=True)
+        res["digest"] = out.digest_words()
+        res["positions"] = P
+        res["bin_stats"] = bc.stats()
+        res["spilled"] = spilled
+        res["bin_bits"] = tuple(bin_bits)
+        return res
     card = None
     occ = None
     if occ_stream and sizing != "card":

@@ -146,6 +146,60 @@ def test_occ_stream_rejections(L):
                                 None) == abi.HM_EINVAL
 
 
+def test_binned_path_rejections(L):
+    """The binned path's entry points check their arguments on the host: scratch sizes follow the
+    formula in the header, and bad bins, reads, k or flags return HM_EINVAL before any launch."""
+    assert L.hm_bins_scratch_bytes(0, 0) == 8 * 3 + 4096 + 32
+    assert L.hm_bins_scratch_bytes(9, 10) == 8 * (2 * 512 + 1) + 4096 * 512 + 32 * (1 << 19)
+    assert L.hm_bins_scratch_bytes(13, 0) == 0 and L.hm_bins_scratch_bytes(0, 13) == 0
+    good = dict(recs=256, tmp=512, capacity=1000, group_bits=2, bin_bits=3, scratch=1024, bin_start=2048,
+                status=4096, stats=None)
+    r = abi.Reads(8, 8, 8, None, 10, 1000, 100)
+    for bad, msg in ((dict(recs=None), "NULL"), (dict(status=None), "NULL"), (dict(recs=264), "aligned"),
+                     (dict(group_bits=13), "at most"), (dict(bin_bits=13), "at most"),
+                     (dict(capacity=100), "windows")):
+        b = abi.Bins(**dict(good, **bad))
+        assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(b), None) == abi.HM_EINVAL
+        assert msg in abi.last_error(), (bad, abi.last_error())
+    b = abi.Bins(**good)
+    assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=63)), ctypes.byref(b), None) == abi.HM_EINVAL
+    assert "k <= 61" in abi.last_error()
+    rv = abi.Reads(8, 8, 8, 8, 10, 1000, 0)  # read offsets: variable-length reads
+    assert L.hm_bin_kmers(ctypes.byref(rv), ctypes.byref(P(k=21)), ctypes.byref(b), None) == abi.HM_EINVAL
+    assert "fixed-length" in abi.last_error()
+    big = abi.Bins(**dict(good, capacity=1 << 40))
+    rb = abi.Reads(8, 8, 8, None, 1 << 26, 150 << 26, 150)  # 2^26 reads x 130 windows >= 2^32
+    assert L.hm_bin_kmers(ctypes.byref(rb), ctypes.byref(P(k=21)), ctypes.byref(big), None) == abi.HM_EINVAL
+    assert "2^32" in abi.last_error()
+    e = abi.Export(64, 64, 64, 64, 64, 64, 64, 10, 64, None, 2, 2, None, 0)
+    o = abi.Occ(64, 64, 10, 64)
+    assert L.hm_count_bins(ctypes.byref(b), ctypes.byref(P(k=21)), abi.HM_EXPORT_SORTED, ctypes.byref(e),
+                           ctypes.byref(o), None) == abi.HM_EINVAL
+    assert L.hm_count_bins(ctypes.byref(b), ctypes.byref(P(k=21)), 0, ctypes.byref(e), None, None) == abi.HM_EINVAL
+    assert L.hm_count_bins(ctypes.byref(b), ctypes.byref(P(k=63)), 0, ctypes.byref(e), ctypes.byref(o),
+                           None) == abi.HM_EINVAL
+    assert L.hm_export_merge(None, ctypes.byref(e), 64, None) == abi.HM_EINVAL
+    assert L.hm_export_merge(ctypes.byref(e), ctypes.byref(e), None, None) == abi.HM_EINVAL
+
+
+def test_bin_plan_keeps_bins_within_their_local_limits():
+    """plan_bins: enough bins that a bin's expected distinct k-mers and inserted k-mers stay well
+    inside the deferred list (2048) and the table's spill limit (384), and the two levels split
+    the bits as evenly as their 12-bit limits allow."""
+    from paper_1705_11147_amd.kmer import plan_bins
+    for distinct, seen2, bypass in ((4.76e8, 1.03e8, False), (4.4e6, 1.1e6, False), (1e3, 500, False),
+                                    (4.76e8, 1.03e8, True), (1.2e9, 2.5e8, False), (10, 2, False)):
+        g, b = plan_bins(distinct, seen2, bypass)
+        assert 0 <= g <= 12 and 0 <= b <= 12 and abs(g - b) <= 1 or g == 12 or b == 0
+        bins = 1 << (g + b)
+        inserted = (distinct if bypass else seen2) / bins
+        assert distinct / bins <= 900 and inserted <= 192 or g + b == 24
+        if g + b > 0:  # not more bins than needed: half as many would break a limit
+            half = bins / 2
+            assert distinct / half > 900 or (distinct if bypass else seen2) / half > 192
+    assert plan_bins(4.76e8, 1.03e8) == (10, 10)
+
+
 def test_status_code_maps_words_on_the_host(L):
     """hm_status_code maps a status word already on the host to the code hm_status returns:
     errors by severity (timeout, overflow, capacity, output), the classification bit alone is
@@ -185,7 +239,7 @@ def test_package_import_is_lazy_and_loud():
 
 C_NAMES = {"Reads": "hm_reads_t", "Params": "hm_params_t", "Table": "hm_table_t", "Bloom": "hm_bloom_t",
            "List": "hm_list_t", "Export": "hm_export_t", "Card": "hm_card_t", "CardSummary": "hm_card_summary_t",
-           "Contigs": "hm_contigs_t", "Occ": "hm_occ_t", "BatchSet": "hm_batch_set_t",
+           "Contigs": "hm_contigs_t", "Occ": "hm_occ_t", "Bins": "hm_bins_t", "BatchSet": "hm_batch_set_t",
            "BatchTuning": "hm_batch_tuning_t", "BatchPlan": "hm_batch_plan_t"}
 
 

@@ -1,0 +1,156 @@
+"""The binned path (hm_bin_kmers, hm_count_bins; spilled bins through the global-table path and
+hm_export_merge) against the CPU oracle, record by record.
+
+Integer output: the bar is bit-exact equality of the sorted tables (keys, counts, both tally
+arrays, both class bytes) and of the order-free digest."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1705_11147_amd import abi, kmer, synth
+from tests.util import assert_tables_equal, random_read_set, table_digest
+
+pytestmark = pytest.mark.gpu
+
+OKW = ("qcut", "min_depth", "ext_min", "n_owners", "owner", "qual_offset", "forward_only")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.lib()
+    torch.cuda.set_device(0)
+
+
+def fixed_reads(seed, n_reads, L, genome_len, err=0.01, n_rate=0.0, lower_rate=0.0):
+    ascii, qual, _ = random_read_set(seed, n_reads, L, L, genome_len, err, n_rate, lower_rate)
+    return ascii, qual
+
+
+def run_both(ascii, qual, L, k, bin_bits=None, **kw):
+    n = ascii.size // L if L else 0
+    off = np.arange(n + 1, dtype=np.int64) * L
+    got = kmer.analyze(ascii, qual, k, read_len=L, binned=True, bin_bits=bin_bits, **kw)
+    exp = oracle.run(ascii, qual, off, k, n_threads=8, sort_count=True, **{x: kw[x] for x in OKW if x in kw})
+    return got, exp
+
+
+def valid_windows(ascii, L, k):
+    """Windows of the fixed-length reads that hold only A/C/G/T (either case)."""
+    if ascii.size == 0 or L < k:
+        return 0
+    bad = ~np.isin(ascii | 0x20, np.frombuffer(b"acgt", np.uint8)).reshape(-1, L)
+    c = np.concatenate([np.zeros((bad.shape[0], 1), np.int64), np.cumsum(bad, axis=1)], axis=1)
+    return int(((c[:, k:] - c[:, :-k]) == 0).sum())
+
+
+def check(got, exp, what, ascii=None, L=None, k=None):
+    assert_tables_equal(got, exp, what)
+    assert got["digest"] == table_digest(exp), what
+    if ascii is not None:  # every valid window went into a bin once
+        assert got["bin_stats"]["records"] == valid_windows(ascii, L, k), what
+
+
+@pytest.mark.parametrize("k,L,n_reads,G,err,n_rate,lower", [
+    (21, 100, 20000, 50000, 0.01, 0.0, 0.0),
+    (51, 150, 10000, 100000, 0.005, 0.0, 0.0),
+    (31, 150, 10000, 60000, 0.01, 0.0, 0.0),
+    (61, 150, 5000, 40000, 0.01, 0.0, 0.0),   # the largest k of the binned path
+    (33, 100, 4000, 20000, 0.01, 0.0, 0.0),   # keys just past one 64-bit word
+    (25, 120, 5000, 30000, 0.01, 0.01, 0.1),  # N bases and lowercase
+    (3, 40, 2000, 500, 0.02, 0.0, 0.0),       # 32 canonical 3-mers, huge counts
+    (1, 50, 500, 1000, 0.0, 0.0, 0.0),        # two canonical 1-mers
+])
+def test_binned_matches_oracle(k, L, n_reads, G, err, n_rate, lower):
+    print("binned k=%d L=%d reads=%d G=%d" % (k, L, n_reads, G), flush=True)
+    ascii, qual = fixed_reads(1000 + k, n_reads, L, G, err, n_rate, lower)
+    got, exp = run_both(ascii, qual, L, k)
+    check(got, exp, "k=%d" % k, ascii, L, k)
+
+
+@pytest.mark.parametrize("kw", [dict(forward_only=True), dict(min_depth=3, ext_min=1), dict(min_depth=2, ext_min=3),
+                                dict(n_owners=4, owner=1), dict(qcut=30), dict(seed=12345)])
+def test_binned_params(kw):
+    print("binned params %r" % kw, flush=True)
+    ascii, qual = fixed_reads(77, 8000, 100, 40000, 0.01)
+    got, exp = run_both(ascii, qual, 100, 21, **kw)
+    check(got, exp, repr(kw), None if "n_owners" in kw else ascii, 100, 21)
+
+
+def test_binned_uu_only():
+    ascii, qual = fixed_reads(78, 8000, 100, 40000, 0.01)
+    got, exp = run_both(ascii, qual, 100, 21, export_flags=abi.HM_EXPORT_UU_ONLY)
+    uu = (exp["cls_l"] < 4) & (exp["cls_r"] < 4)
+    exp = {f: (v[uu] if isinstance(v, np.ndarray) and len(v) == len(uu) else v) for f, v in exp.items()}
+    assert_tables_equal(got, exp, "UU only")
+    assert got["digest"] == table_digest(exp)
+
+
+def test_every_bin_spills():
+    """One bin holding every record, with far more repeated k-mers than its local table takes:
+    the bin goes whole to the spill stream and the global-table path counts it."""
+    ascii, qual = fixed_reads(79, 6000, 100, 20000, 0.01)
+    got, exp = run_both(ascii, qual, 100, 21, bin_bits=(0, 0))
+    check(got, exp, "one bin", ascii, 100, 21)
+    assert got["bin_stats"]["spilled_bins"] == 1 and got["spilled"] == valid_windows(ascii, 100, 21)
+
+
+def test_some_bins_spill():
+    """Eight bins for about 2900 repeated k-mers (320 to 390 a bin, around the spill limit of 384): some
+    bins are counted locally, the others through the global path, and the merged export is exact."""
+    ascii, qual = fixed_reads(80, 4000, 100, 2600, 0.002)
+    got, exp = run_both(ascii, qual, 100, 21, bin_bits=(1, 2))
+    check(got, exp, "mixed")
+    st = got["bin_stats"]
+    print("spilled bins %d of 8, %d records" % (st["spilled_bins"], st["spilled"]), flush=True)
+    assert 0 < st["spilled_bins"] < 8
+
+
+def test_deferred_list_spills():
+    """A bin whose distinct k-mers pass its deferred list (2048): error-rich reads, one bin."""
+    ascii, qual = fixed_reads(81, 800, 100, 200000, 0.05)
+    got, exp = run_both(ascii, qual, 100, 21, bin_bits=(0, 0))
+    check(got, exp, "deferred overflow")
+    assert got["bin_stats"]["spilled_bins"] == 1
+
+
+@pytest.mark.parametrize("bin_bits", [None, (0, 1)])
+def test_bypass(bin_bits):
+    """min_depth = 1: no Bloom filter, every k-mer inserted (with (0, 1) both bins spill)."""
+    ascii, qual = fixed_reads(82, 3000, 100, 20000, 0.01)
+    got, exp = run_both(ascii, qual, 100, 21, bin_bits=bin_bits, min_depth=1)
+    check(got, exp, "bypass %r" % (bin_bits,))
+
+
+def test_heavy_hitter_bin():
+    """A k-mer in 20% of the windows: its bin takes a third of all records and one slot's counters
+    take every one of its occurrences."""
+    ascii, qual = fixed_reads(83, 10000, 100, 40000, 0.01)
+    ascii = ascii.reshape(10000, 100)
+    ascii[::5] = ord("A")  # 2000 poly-A reads: 80 windows each of the key A...A
+    got, exp = run_both(ascii.reshape(-1).copy(), qual, 100, 21)
+    check(got, exp, "heavy")
+    assert int(exp["count"].max()) >= 160000
+
+
+@pytest.mark.parametrize("n_reads,L,k", [(0, 100, 21), (50, 20, 21), (1, 21, 21)])
+def test_degenerate(n_reads, L, k):
+    """No reads, reads shorter than k, one read of exactly k bases."""
+    ascii, qual = fixed_reads(84, n_reads, L, 1000, 0.0) if n_reads else (np.zeros(0, np.uint8), np.zeros(0, np.uint8))
+    got, exp = run_both(ascii, qual, L, k, min_depth=1)
+    check(got, exp, "degenerate", ascii, L, k)
+
+
+def test_binned_equals_table_path_mid_scale():
+    """The mid workload at 1/100 scale (2*10^7 windows, about 2^14 bins): the binned export equals
+    the oracle's table and the global-table path's, record by record."""
+    w = synth.mid(scale=0.01)
+    r = w.reads()
+    p = w.params
+    got, exp = run_both(r.ascii, r.qual, r.read_len, p.k, qcut=p.qcut, min_depth=p.min_depth)
+    check(got, exp, "mid 0.01")
+    tab = kmer.analyze(r.ascii, r.qual, p.k, read_len=r.read_len, qcut=p.qcut, min_depth=p.min_depth)
+    assert_tables_equal(got, tab, "binned vs table path")
+    assert got["spilled"] == 0
