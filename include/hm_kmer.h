@@ -470,8 +470,8 @@ int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, 
  * global-table path over the same reads; the order differs.
  *
  * Limits: fixed-length reads (read_off NULL) of at most 16320 bases, k <= 61
- * (the key and its two extension codes share a 16-byte record), fewer than
- * 2^32 windows per call. */
+ * (the key and its two extension codes share a 16-byte record), at most 2^20
+ * bins, fewer than 2^32 records (windows and padding) per call. */
 
 /* Event counters of hm_count_bins (hm_bins_t.stats, HM_N_BIN_STATS 64-bit words). */
 #define HM_BIN_STAT_RECORDS 0     /* records (valid, owned windows) in the bins */
@@ -483,21 +483,31 @@ int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, 
 #define HM_N_BIN_STATS 6
 
 typedef struct {
-    uint64_t *recs;      /* 2 * capacity words, 16-byte aligned: the records, bin after bin */
-    uint64_t *tmp;       /* 2 * capacity words, 16-byte aligned: records grouped by their top group_bits
+    uint64_t *recs;      /* 2 * capacity words, 128-byte aligned: the records, bin after bin */
+    uint64_t *tmp;       /* 2 * capacity words, 128-byte aligned: records grouped by their top group_bits
                             (scratch of hm_bin_kmers; free afterwards, e.g. as the keys of the spill stream) */
-    uint64_t capacity;   /* records: at least n_reads * (read_len - k + 1) */
-    uint32_t group_bits; /* 0..12 */
-    uint32_t bin_bits;   /* 0..12: bins = 2^(group_bits + bin_bits) */
-    uint64_t *scratch;   /* hm_bins_scratch_bytes(group_bits, bin_bits) bytes, 8-byte aligned */
+    uint64_t capacity;   /* records: at least hm_bins_capacity(windows, group_bits, bin_bits) */
+    uint32_t group_bits; /* 0..10 */
+    uint32_t bin_bits;   /* 0..10: bins = 2^(group_bits + bin_bits) */
+    uint64_t *scratch;   /* hm_bins_scratch_bytes(group_bits, bin_bits) bytes, 16-byte aligned */
     uint64_t *bin_start; /* 2^(group_bits + bin_bits) + 1 words: bin i holds records [bin_start[i], bin_start[i+1]) */
     uint32_t *status;    /* device status word (cleared by hm_bin_kmers) */
     uint64_t *stats;     /* optional (may be NULL): HM_N_BIN_STATS counters (cleared by hm_bin_kmers) */
 } hm_bins_t;
 
-/* Scratch bytes of hm_bin_kmers: for 2^g groups and 2^(g+b) bins,
- * 8 * (2 * 2^g + 1) + 4096 * 2^g + 32 * 2^(g+b) bytes; 0 if g or b is above 12. */
+/* Scratch bytes of hm_bin_kmers and hm_count_bins: for 2^g groups and 2^(g+b) bins,
+ * 2^27 + 8 * (4 * 2^g + 2) + 4096 * 2^g + 32 * 2^(g+b) bytes (the 128 MiB are where
+ * hm_count_bins stages each workgroup's records before it takes their output
+ * range with one atomic add); 0 if g or b is above 10. */
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits);
+
+/* Records the bins need room for (hm_bins_t.capacity) for a read set of `windows`
+ * windows: the windows plus the padding that makes every destination range a
+ * whole number of the blocks each partition level writes whole (2 records at
+ * the first level, 4 at the second), windows + max(1024 * 2^g, 24 * 2^(g+b));
+ * 0 if g or b is above 10.  Padding records ("holes": extension field 63) sit
+ * at the ends of ranges and are skipped. */
+uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits);
 
 /* Partition every valid window of `r` whose key is owned (hm_params_t
  * owner filter) into the bins of `b`: record = (key_lo, key_hi | ext << 58),
@@ -505,7 +515,7 @@ size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits);
  * of a key is the top group_bits + bin_bits bits of
  * (key_lo ^ key_hi * 0xC2B2AE3D27D4EB4F) * 0x165667B19E3779F9 mod 2^64
  * (multiply-shift hashing).  HM_EINVAL (nothing launched) for variable-length
- * reads, k > 61, more windows than b->capacity or 2^32 or more windows. */
+ * reads, k > 61, b->capacity below hm_bins_capacity, or 2^32 or more records. */
 int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStream_t stream);
 
 /* Count the bins of `b` (after hm_bin_kmers with the same params) and export

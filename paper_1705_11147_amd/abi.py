@@ -165,6 +165,7 @@ SIGNATURES = {
     "hm_cardinality_occ": ([P(Reads), P(Params), P(Card), P(Occ), vp], ctypes.c_int),
     "hm_bloom_insert_occ": ([P(Occ), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
     "hm_bins_scratch_bytes": ([ctypes.c_uint32, ctypes.c_uint32], ctypes.c_size_t),
+    "hm_bins_capacity": ([ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
     "hm_bin_kmers": ([P(Reads), P(Params), P(Bins), vp], ctypes.c_int),
     "hm_count_bins": ([P(Bins), P(Params), ctypes.c_uint32, P(Export), P(Occ), vp], ctypes.c_int),
     "hm_export_merge": ([P(Export), P(Export), vp, vp], ctypes.c_int),

@@ -33,17 +33,26 @@ constexpr uint64_t kBinMul1 = 0xC2B2AE3D27D4EB4Full;
 constexpr uint64_t kBinMul2 = 0x165667B19E3779F9ull;
 constexpr int kGrid1 = 1024;       // most workgroups of the two passes over the reads
 constexpr int kSlices = 8;         // workgroups per group in the second partition level
-constexpr int kMaxBits = 12;       // group_bits and bin_bits are each at most this
+constexpr int kMaxBits = 10;       // group_bits and bin_bits are each at most this (LDS of the scatters)
+#ifndef HM_BIN_BLK1
+#define HM_BIN_BLK1 2
+#endif
+#ifndef HM_BIN_BLK2
+#define HM_BIN_BLK2 4
+#endif
+constexpr int kBlk1 = HM_BIN_BLK1;  // records per written block, first level
+constexpr int kBlk2 = HM_BIN_BLK2;  // records per written block, second level
+constexpr int kT2 = 512;            // threads of a second-level workgroup
 constexpr int kBinSlots = 512;     // LDS table of one bin
 constexpr int kBloomWords = 512;   // 32-bit filter words: 16384 bits per bin
 constexpr int kDeferCap = 2048;    // deferred occurrences of one bin
 constexpr int kPer = 4;            // records per thread per round
 constexpr int kChunk = kPer * kBlock;
 constexpr uint32_t kMaxKeys = kBinSlots * 3 / 4;
-constexpr uint64_t kTaken = 1ull << 63;  // marks an occupied LDS slot (key_hi < 2^58)
 constexpr int kExtShift = 58;
 constexpr int kMaxBinK = 61;       // 2k + 6 extension bits fit in 128
 constexpr int kCountBlocksPerCu = 4;
+static_assert(kBinSlots == 2 * kBlock, "the export takes two slots a thread");
 
 __device__ __forceinline__ uint64_t bin_hash(uint64_t hi, uint64_t lo) { return (lo ^ hi * kBinMul1) * kBinMul2; }
 
@@ -76,6 +85,91 @@ __device__ __forceinline__ Rec rec_unpack(uint4 r) {
 
 // ------------------------------------------------------------------ partition
 
+// A hole: padding that keeps every destination range a whole number of blocks (word 3 has the
+// extension field 63, which no record has); readers skip it.
+__device__ __forceinline__ bool is_hole(uint4 r) { return (r.w >> (kExtShift - 32)) == 63u; }
+__device__ __forceinline__ uint4 hole_rec() { return make_uint4(0u, 0u, 0u, 0xFFFFFFFFu); }
+
+// Write-combining of 16-byte records into F destinations, each a range of a global array that
+// starts at a multiple of BLK records and is padded with holes to a multiple of BLK.  Each
+// destination keeps a ring of BLK records in LDS; a round of put() calls is followed (after a
+// barrier) by flush(), which writes every completed block with BLK consecutive stores, so HBM
+// sees whole blocks instead of one partial line per record.  A record whose block is not the
+// ring's current one (its destination took more than a block in one round) is stored at once.
+template <int BLK>
+struct Combiner {
+    uint4 *ring;        // F * BLK
+    uint32_t *fill;     // records placed, relative to the destination's start
+    uint32_t *done;     // records written out in whole blocks (a multiple of BLK)
+    uint8_t *bits;      // ring entries that hold a record
+    uint16_t *ready;    // destinations whose block filled up this round
+    uint32_t *n_ready;  // two counters: rounds alternate between them
+    // LDS bytes for F destinations
+    static constexpr size_t bytes(size_t F) {
+        return F * (BLK * 16 + 8) + 2 * ((F + 1) & ~(size_t)1) + ((F + 3) & ~(size_t)3) + 8;
+    }
+    // carve the arrays from `lds` (16-byte aligned) for F destinations; returns the first free byte
+    __device__ uint8_t *carve(void *lds, int F) {
+        ring = reinterpret_cast<uint4 *>(lds);
+        fill = reinterpret_cast<uint32_t *>(ring + (size_t)F * BLK);
+        done = fill + F;
+        ready = reinterpret_cast<uint16_t *>(done + F);
+        bits = reinterpret_cast<uint8_t *>(ready + ((F + 1) & ~1));
+        n_ready = reinterpret_cast<uint32_t *>(bits + ((F + 3) & ~3));
+        return reinterpret_cast<uint8_t *>(n_ready + 2);
+    }
+    // round `par` (0 or 1, alternating)
+    __device__ void put(uint32_t d, uint4 r, uint4 *at, uint32_t par) {  // at: the destination's first record
+        const uint32_t p = atomicAdd(&fill[d], 1u);
+        const uint32_t q = p - done[d];
+        if (q < (uint32_t)BLK) {
+            ring[d * BLK + q] = r;
+            atomicOr(reinterpret_cast<uint32_t *>(bits + (d & ~3u)), 1u << (8 * (d & 3) + q));
+            if (q == BLK - 1) ready[atomicAdd(&n_ready[par], 1u)] = (uint16_t)d;  // the block is complete
+        } else {
+            at[p] = r;
+        }
+    }
+    // after a barrier: write out the completed blocks of the round's ready destinations and clear
+    // the other round's counter (then a barrier before the next round)
+    template <class At>
+    __device__ void flush_ready(uint32_t tid, uint32_t nthreads, At at, uint32_t par) {
+        if (tid == 0) n_ready[par ^ 1] = 0;
+        const uint32_t n = n_ready[par];
+        for (uint32_t i = tid; i < n; i += nthreads) {
+            const uint32_t d = ready[i];
+            uint4 *o = at(d);
+            const uint32_t f = fill[d];
+            uint32_t dn = done[d], b = bits[d];
+            const uint4 *src = ring + d * BLK;
+            while (f - dn >= (uint32_t)BLK) {
+                if (b == (1u << BLK) - 1) {
+#pragma unroll
+                    for (int q = 0; q < BLK; ++q) o[dn + q] = src[q];
+                } else {
+                    for (int q = 0; q < BLK; ++q)
+                        if ((b >> q) & 1) o[dn + q] = src[q];
+                }
+                b = 0;
+                dn += BLK;
+            }
+            done[d] = dn;
+            bits[d] = (uint8_t)b;
+        }
+    }
+    __device__ void flush_tail(uint32_t d, uint4 *at) {  // the last block, padded with holes
+        const uint32_t f = fill[d], dn = done[d], b = bits[d];
+        if (f == dn) return;
+        const uint4 *src = ring + d * BLK;
+#pragma unroll
+        for (int q = 0; q < BLK; ++q) {
+            const uint32_t p = dn + q;
+            if (p >= f) at[p] = hole_rec();
+            else if ((b >> q) & 1) at[p] = src[q];
+        }
+    }
+};
+
 // Level-1 histogram: counts of each group's windows in this workgroup's tiles (the tiles
 // fixed_windows hands a workgroup depend only on the grid, which the scatter pass repeats).
 __global__ __launch_bounds__(kBlock) void k_hist1(PassArgs a, int32_t rpt, int64_t n_tiles, uint32_t *hist1,
@@ -93,15 +187,16 @@ __global__ __launch_bounds__(kBlock) void k_hist1(PassArgs a, int32_t rpt, int64
     for (int i = threadIdx.x; i < ng; i += kBlock) hist1[(size_t)i * gridDim.x + blockIdx.x] = s_h[i];
 }
 
-// Exclusive prefix sum of each row of x (rows x cols, one workgroup per row) in place; the row
-// total to tot[row] when tot is not NULL.  Every row total is below 2^32 (checked by the host).
-__global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t *x, int cols, uint64_t *tot) {
+// Exclusive prefix sum, in place, of each row of x (rows x cols, one workgroup per row) over
+// the counts rounded up to a multiple of `pad`; the row total to tot[row].  Every row total is
+// below 2^32 (checked by the host).
+__global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t *x, int cols, uint32_t pad, uint64_t *tot) {
     __shared__ uint32_t s_part[kBlock];
     uint32_t *row = x + (size_t)blockIdx.x * cols;
     const int per = (cols + kBlock - 1) / kBlock;
     const int b = min((int)threadIdx.x * per, cols), e = min(b + per, cols);
     uint32_t sum = 0;
-    for (int i = b; i < e; ++i) sum += row[i];
+    for (int i = b; i < e; ++i) sum += (row[i] + pad - 1) / pad * pad;
     s_part[threadIdx.x] = sum;
     __syncthreads();
     for (int d = 1; d < kBlock; d <<= 1) {  // inclusive scan of the thread sums
@@ -112,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t *x, int cols, uin
     }
     uint32_t run = s_part[threadIdx.x] - sum;
     for (int i = b; i < e; ++i) {
-        const uint32_t v = row[i];
+        const uint32_t v = (row[i] + pad - 1) / pad * pad;
         row[i] = run;
         run += v;
     }
@@ -142,24 +237,38 @@ __global__ __launch_bounds__(kBlock) void k_scan_totals(const uint64_t *tot, int
     if (threadIdx.x == kBlock - 1) start[n] = s_part[kBlock - 1];
 }
 
-// Level-1 scatter: the same windows as k_hist1, each written to its group's range at the
-// workgroup's offset (an LDS cursor per group).
+// Level-1 scatter: the same windows as k_hist1, each placed in its group's range at this
+// workgroup's offset, through a combiner per group.
 __global__ __launch_bounds__(kBlock) void k_scatter1(PassArgs a, int32_t rpt, int64_t n_tiles, const uint32_t *rel1,
                                                      const uint64_t *gstart, uint4 *tmp, int total_bits,
                                                      int bin_bits) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
-    extern __shared__ uint32_t s_cur[];
+    extern __shared__ uint4 s_dyn[];
     const int ng = 1 << (total_bits - bin_bits);
-    for (int i = threadIdx.x; i < ng; i += kBlock) s_cur[i] = rel1[(size_t)i * gridDim.x + blockIdx.x];
+    Combiner<kBlk1> cb;
+    uint32_t *s_rel = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ng));
+    for (int i = threadIdx.x; i < ng; i += kBlock) {
+        s_rel[i] = rel1[(size_t)i * gridDim.x + blockIdx.x];
+        cb.fill[i] = cb.done[i] = 0;
+        cb.bits[i] = 0;
+    }
+    if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
+    auto at = [&](uint32_t g) { return tmp + gstart[g] + s_rel[g]; };
+    uint32_t par = 0;
     fixed_windows<false>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
         if (act) {
             const uint32_t g = bin_of(o.hi, o.lo, total_bits) >> bin_bits;
-            const uint32_t pos = atomicAdd(&s_cur[g], 1u);
-            tmp[gstart[g] + pos] = rec_pack(o);
+            cb.put(g, rec_pack(o), at(g), par);
         }
+        __syncthreads();
+        cb.flush_ready(threadIdx.x, kBlock, at, par);
+        __syncthreads();
+        par ^= 1;
     });
+    __syncthreads();
+    for (int g = threadIdx.x; g < ng; g += kBlock) cb.flush_tail(g, at(g));
 }
 
 // Level-2 histogram: workgroup (g, slice) counts the bins of its slice of group g's records.
@@ -178,64 +287,82 @@ __global__ __launch_bounds__(kBlock) void k_hist2(const uint4 *tmp, const uint64
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const uint64_t i = i0 + j * kBlock + threadIdx.x;
-            r[j] = i < e ? tmp[i] : make_uint4(0, 0, 0, 0);
+            r[j] = i < e ? tmp[i] : hole_rec();
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const uint64_t i = i0 + j * kBlock + threadIdx.x;
-            if (i < e) {
-                const Rec x = rec_unpack(r[j]);
-                atomicAdd(&s_h[bin_of(x.hi, x.lo, total_bits) & mask], 1u);
-            }
+            if (is_hole(r[j])) continue;
+            const Rec x = rec_unpack(r[j]);
+            atomicAdd(&s_h[bin_of(x.hi, x.lo, total_bits) & mask], 1u);
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < ns; i += kBlock) hist2[((size_t)g * ns + i) * kSlices + sl] = s_h[i];
 }
 
-// bin_start[g * ns + s] = group start + offset of (s, slice 0) within the group; the last entry
-// closes the final bin.
-__global__ __launch_bounds__(kBlock) void k_bin_starts(const uint32_t *rel2, const uint64_t *gstart, uint64_t *bin_start,
-                                                       int total_bits, int bin_bits) {
+// bin_start[g * ns + s] = group start (in recs) + offset of (s, slice 0) within the group; the
+// last entry closes the final bin.
+__global__ __launch_bounds__(kBlock) void k_bin_starts(const uint32_t *rel2, const uint64_t *gstart2,
+                                                       uint64_t *bin_start, int total_bits, int bin_bits) {
     const uint64_t n_bins = 1ull << total_bits;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= n_bins; i += (uint64_t)gridDim.x * kBlock) {
-        if (i == n_bins) bin_start[i] = gstart[n_bins >> bin_bits];
-        else bin_start[i] = gstart[i >> bin_bits] + rel2[i * kSlices];
+        if (i == n_bins) bin_start[i] = gstart2[n_bins >> bin_bits];
+        else bin_start[i] = gstart2[i >> bin_bits] + rel2[i * kSlices];
     }
 }
 
-// Level-2 scatter: workgroup (g, slice) rereads its slice and writes each record to its bin's
-// range at the slice's offset.
-__global__ __launch_bounds__(kBlock) void k_scatter2(const uint4 *tmp, const uint64_t *gstart, const uint32_t *rel2,
-                                                     uint4 *recs, int total_bits, int bin_bits) {
-    extern __shared__ uint32_t s_cur[];
+// Level-2 scatter: workgroup (g, slice) rereads its slice and places each record in its bin's
+// range at the slice's offset, through a combiner per bin.
+__global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint64_t *gstart, const uint64_t *gstart2,
+                                                  const uint32_t *rel2, uint4 *recs, int total_bits, int bin_bits) {
+    extern __shared__ uint4 s_dyn[];
     const int ns = 1 << bin_bits;
     const uint32_t g = blockIdx.x / kSlices, sl = blockIdx.x % kSlices;
-    for (int i = threadIdx.x; i < ns; i += kBlock) s_cur[i] = rel2[((size_t)g * ns + i) * kSlices + sl];
+    Combiner<kBlk2> cb;
+    uint32_t *s_rel = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ns));
+    for (int i = threadIdx.x; i < ns; i += kT2) {
+        s_rel[i] = rel2[((size_t)g * ns + i) * kSlices + sl];
+        cb.fill[i] = cb.done[i] = 0;
+        cb.bits[i] = 0;
+    }
+    if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
     __syncthreads();
+    uint32_t par = 0;
+    uint4 *base = recs + gstart2[g];
+    auto at = [&](uint32_t d) { return base + s_rel[d]; };
     const uint64_t g0 = gstart[g], len = gstart[g + 1] - g0;
     const uint64_t b = g0 + len * sl / kSlices, e = g0 + len * (sl + 1) / kSlices;
     const uint32_t mask = (uint32_t)ns - 1;
-    for (uint64_t i0 = b; i0 < e; i0 += kChunk) {
-        uint4 r[kPer];
+    for (uint64_t i0 = b; i0 < e; i0 += 2 * kT2) {
+        uint4 r[2];
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const uint64_t i = i0 + j * kBlock + threadIdx.x;
-            r[j] = i < e ? tmp[i] : make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+            const uint64_t i = i0 + j * kT2 + threadIdx.x;
+            r[j] = i < e ? tmp[i] : hole_rec();
         }
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const uint64_t i = i0 + j * kBlock + threadIdx.x;
-            if (i < e) {
-                const Rec x = rec_unpack(r[j]);
-                const uint32_t pos = atomicAdd(&s_cur[bin_of(x.hi, x.lo, total_bits) & mask], 1u);
-                recs[g0 + pos] = r[j];
-            }
+        for (int j = 0; j < 2; ++j) {
+            if (is_hole(r[j])) continue;
+            const Rec x = rec_unpack(r[j]);
+            const uint32_t d = bin_of(x.hi, x.lo, total_bits) & mask;
+            cb.put(d, r[j], at(d), par);
         }
+        __syncthreads();
+        cb.flush_ready(threadIdx.x, kT2, at, par);
+        __syncthreads();
+        par ^= 1;
     }
+    __syncthreads();
+    for (int d = threadIdx.x; d < ns; d += kT2) cb.flush_tail(d, at(d));
 }
 
 // ------------------------------------------------------------------ counting in LDS
+
+constexpr int kStage = 2048;               // records a workgroup stages before it takes an output range
+constexpr int kCountGrid = 1024;           // most workgroups of hm_count_bins (one staging area each)
+constexpr uint64_t kClaimed = 1ull << 62;  // LDS key word: key_hi | kClaimed, then | kReady (key_hi < 2^58)
+constexpr uint64_t kReady = 1ull << 63;
+constexpr uint32_t kLdsSpin = 1u << 20;    // bound on waiting for another wave's claim to be published
 
 struct CountArgs {
     const uint4 *recs;
@@ -247,28 +374,103 @@ struct CountArgs {
     uint32_t uu_only;
     uint32_t *status;
     unsigned long long *stats;
+    uint4 *stage;  // kCountGrid areas of kStage records, 4 x 16 bytes each
 };
 
 struct BinLds {
-    uint64_t hi[kBinSlots];         // key_hi | kTaken (0 = empty)
+    uint64_t hi[kBinSlots];      // 0 = empty; key_hi | kClaimed while the second word is written; | kReady after
     uint64_t lo[kBinSlots];
-    uint32_t cnt[9][kBinSlots];     // no left extension, left A..T, right A..T
+    uint32_t cnt[9][kBinSlots];  // no left extension, left A..T, right A..T
     uint32_t bloom[kBloomWords];
-    uint32_t defer[kDeferCap];      // bin-relative record index of each deferred occurrence
-    uint16_t pend[kChunk];          // index within the round of each occurrence to insert
-    uint32_t n_pend, n_defer, n_keys, spill;
+    uint32_t defer[kDeferCap];   // bin-relative record index of each deferred occurrence
+    uint32_t n_defer, n_keys, spill, staged;
+    uint32_t wsum[kBlock / 64];
     unsigned long long base;
 };
 
-__device__ __forceinline__ int lds_find(const BinLds &t, uint64_t th, uint64_t lo, uint64_t h) {
+__device__ __forceinline__ uint64_t lds_word(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Wait until a claimed slot's key is published (x: its first word as read); false past the bound.
+__device__ __forceinline__ bool lds_published(const BinLds &t, uint32_t s, uint64_t &x) {
+    for (uint32_t spins = 0; !(x & kReady); ++spins) {
+        if (spins > kLdsSpin) return false;
+        x = lds_word(&t.hi[s]);
+    }
+    return true;
+}
+
+// Slot of the key in the bin's table: -1 absent, -2 a claim stayed unpublished past the bound.
+// Only another wave can hold a claim unpublished here (a wave publishes its own claims before
+// it looks up its next occurrences).
+__device__ __forceinline__ int lds_find(const BinLds &t, uint64_t hi, uint64_t lo, uint64_t h) {
+    const uint64_t want = hi | kClaimed;
     uint32_t s = (uint32_t)h & (kBinSlots - 1);
-    for (int p = 0; p < kBinSlots; ++p) {  // the table is never full, so an empty slot ends the probe
-        const uint64_t x = t.hi[s];
+    for (int p = 0; p < kBinSlots; ++p) {
+        uint64_t x = lds_word(&t.hi[s]);
         if (x == 0) return -1;
-        if (x == th && t.lo[s] == lo) return (int)s;
+        if ((x & ~kReady) == want) {
+            if (!lds_published(t, s, x)) return -2;
+            if (t.lo[s] == lo) return (int)s;
+        }
         s = (s + 1) & (kBinSlots - 1);
     }
     return -1;
+}
+
+// Insert the key of every lane with `act` (or find it, if another lane got there first) and
+// return its slot; -2 when the probe met no free slot or a claim stayed unpublished.  Called by
+// every lane of the wave.  A lane claims an empty slot with a compare-and-swap of the first
+// word to key_hi | kClaimed, stores the second word and sets kReady; the claims of one step are
+// published before any lane of the wave compares a claimed slot's key, so a wave never waits
+// for itself, and lanes of other waves wait for kReady.
+__device__ __forceinline__ int lds_insert(BinLds &t, bool act, uint64_t hi, uint64_t lo, uint64_t h, bool &added) {
+    const uint64_t want = hi | kClaimed;
+    uint32_t s = (uint32_t)h & (kBinSlots - 1), probes = 0;
+    int res = -2;
+    bool active = act;
+    added = false;
+    while (__ballot(active)) {
+        bool won = false;
+        uint64_t x = 0;
+        if (active) {
+            x = lds_word(&t.hi[s]);
+            if (x == 0) {
+                unsigned long long e = 0;
+                won = __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(&t.hi[s]), &e,
+                                                           (unsigned long long)want, __ATOMIC_ACQ_REL,
+                                                           __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                x = won ? want : e;
+            }
+        }
+        if (won) {
+            t.lo[s] = lo;
+            __hip_atomic_fetch_or(reinterpret_cast<unsigned long long *>(&t.hi[s]), (unsigned long long)kReady,
+                                  __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (active) {
+            if (won) {
+                res = (int)s;
+                added = true;
+                active = false;
+            } else {
+                if ((x & ~kReady) == want) {
+                    if (!lds_published(t, s, x)) {
+                        active = false;
+                    } else if (t.lo[s] == lo) {
+                        res = (int)s;
+                        active = false;
+                    }
+                }
+                if (active) {
+                    s = (s + 1) & (kBinSlots - 1);
+                    if (++probes >= (uint32_t)kBinSlots) active = false;
+                }
+            }
+        }
+    }
+    return res;
 }
 
 __device__ __forceinline__ void lds_count(BinLds &t, int s, int left, int right) {
@@ -283,70 +485,52 @@ __device__ __forceinline__ void lds_bloom_bits(uint64_t h, uint32_t &w, uint32_t
     m = (1u << ((h >> 32) & 31)) | (1u << ((h >> 37) & 31)) | (1u << ((h >> 42) & 31)) | (1u << ((h >> 47) & 31));
 }
 
-// Insert (or find) and count the round's pending occurrences: wave 0 alone, while the other
-// waves wait at a barrier, so a slot's key words are only written here.  A lane claims an empty
-// slot with a compare-and-swap of the first key word and then stores the second; lanes of the
-// wave that lost the same slot read both words only after a wave barrier, so they see the
-// whole key and either count there (the same key) or probe on.
-__device__ __forceinline__ void lds_insert_pending(BinLds &t, const uint4 *R, uint64_t seed, uint32_t &keys_added) {
-    // R: the round's first record
-    const uint32_t lane = lane_id();
-    const uint32_t np = t.n_pend;
-    for (uint32_t p0 = 0; p0 < np; p0 += 64) {
-        const uint32_t p = p0 + lane;
-        bool active = p < np;
-        Rec x{0, 0, 4, 4};
-        uint32_t s = 0, probes = 0;
-        if (active) {
-            x = rec_unpack(R[t.pend[p]]);
-            s = (uint32_t)key_hash(x.hi, x.lo, seed) & (kBinSlots - 1);
-        }
-        const uint64_t th = x.hi | kTaken;
-        while (__ballot(active)) {
-            bool won = false;
-            if (active && t.hi[s] == 0) {
-                unsigned long long expected = 0;
-                won = __hip_atomic_compare_exchange_strong(reinterpret_cast<unsigned long long *>(&t.hi[s]), &expected,
-                                                           (unsigned long long)th, __ATOMIC_RELAXED,
-                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            if (won) t.lo[s] = x.lo;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (active) {
-                if (won) {
-                    lds_count(t, (int)s, x.left, x.right);
-                    ++keys_added;
-                    active = false;
-                } else if (t.hi[s] == th && t.lo[s] == x.lo) {
-                    lds_count(t, (int)s, x.left, x.right);
-                    active = false;
-                } else {
-                    s = (s + 1) & (kBinSlots - 1);
-                    if (++probes >= (uint32_t)kBinSlots) {  // not reached: the key limit keeps a slot free
-                        t.spill = 1;
-                        active = false;
-                    }
-                }
-            }
+// Move the workgroup's staged records to the export (one atomic add takes their range).  Called
+// by every thread of the workgroup.
+__device__ __forceinline__ void stage_flush(BinLds &t, const uint4 *area, const hm_export_t &out, uint32_t *status) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the staged stores are in L2
+    __syncthreads();
+    const uint32_t n = t.staged;
+    if (threadIdx.x == 0 && n)
+        t.base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out), (unsigned long long)n);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // read them from L2, not a stale L1 line
+    const uint64_t base = t.base;
+    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+        const uint4 q0 = area[4 * i], q1 = area[4 * i + 1], q2 = area[4 * i + 2], q3 = area[4 * i + 3];
+        const uint64_t idx = base + i;
+        if (idx < out.capacity) {
+            out.key_lo[idx] = ((uint64_t)q0.y << 32) | q0.x;
+            out.key_hi[idx] = ((uint64_t)q0.w << 32) | q0.z;
+            *reinterpret_cast<uint4 *>(out.tl + 4 * idx) = q1;
+            *reinterpret_cast<uint4 *>(out.tr + 4 * idx) = q2;
+            out.count[idx] = q3.x;
+            out.cls_l[idx] = (uint8_t)q3.y;
+            out.cls_r[idx] = (uint8_t)(q3.y >> 8);
+        } else {
+            atomicOr(status, HM_ST_OUTPUT_FULL);
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) t.staged = 0;
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t out, hm_occ_t spill) {
     __shared__ BinLds t;
     const uint32_t lane = lane_id();
     const int wave = threadIdx.x >> 6;
+    uint4 *area = c.stage + (size_t)blockIdx.x * kStage * 4;
     auto clear = [&]() {
         for (int i = threadIdx.x; i < kBinSlots; i += kBlock) t.hi[i] = 0;
         uint4 *cz = reinterpret_cast<uint4 *>(&t.cnt[0][0]);
         for (int i = threadIdx.x; i < 9 * kBinSlots / 4; i += kBlock) cz[i] = make_uint4(0, 0, 0, 0);
         uint4 *bz = reinterpret_cast<uint4 *>(t.bloom);
         for (int i = threadIdx.x; i < kBloomWords / 4; i += kBlock) bz[i] = make_uint4(0, 0, 0, 0);
-        if (threadIdx.x == 0) t.n_pend = t.n_defer = t.n_keys = t.spill = 0;
+        if (threadIdx.x == 0) t.n_defer = t.n_keys = t.spill = 0;
     };
     clear();
+    if (threadIdx.x == 0) t.staged = 0;
     __syncthreads();
     uint64_t dsum = 0, dxor = 0;
     uint64_t st_recs = 0, st_spilled_bins = 0, st_spilled = 0, st_defer = 0, st_keys = 0, st_kept = 0;
@@ -355,9 +539,10 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
         const uint64_t n = c.bin_start[bin + 1] - b0;  // workgroup-uniform
         if (n == 0) continue;
         const uint4 *R = c.recs + b0;
-        st_recs += threadIdx.x == 0 ? n : 0;
-        // first pass over the bin, a round of kChunk records at a time
+        uint64_t bin_recs = 0;  // this thread's records of the bin (holes aside)
+        // one pass over the bin's occurrences: count, or test the filter and insert, or defer
         for (uint64_t c0 = 0; c0 < n; c0 += kChunk) {
+            if (t.spill) break;  // set by any wave; the other waves may finish their round
             uint4 r[kPer];
 #pragma unroll
             for (int j = 0; j < kPer; ++j) {
@@ -367,122 +552,126 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
 #pragma unroll
             for (int j = 0; j < kPer; ++j) {
                 const uint64_t i = c0 + j * kBlock + threadIdx.x;
-                if (i >= n) continue;
+                const bool valid = i < n && !is_hole(r[j]);
+                bin_recs += valid ? 1 : 0;
                 const Rec x = rec_unpack(r[j]);
-                const uint64_t h = key_hash(x.hi, x.lo, c.seed);
-                const int s = lds_find(t, x.hi | kTaken, x.lo, h);
+                const uint64_t h = valid ? key_hash(x.hi, x.lo, c.seed) : 0;
+                const int s = valid ? lds_find(t, x.hi, x.lo, h) : -1;
+                bool ins = false;
                 if (s >= 0) {
                     lds_count(t, s, x.left, x.right);
-                    continue;
-                }
-                bool seen = c.bypass != 0;
-                if (!seen) {
-                    uint32_t w, m;
-                    lds_bloom_bits(h, w, m);
-                    seen = (atomicOr(&t.bloom[w], m) & m) == m;
-                }
-                if (seen) {
-                    t.pend[atomicAdd(&t.n_pend, 1u)] = (uint16_t)(i - c0);
-                } else {
-                    const uint32_t d = atomicAdd(&t.n_defer, 1u);
-                    if (d < (uint32_t)kDeferCap) t.defer[d] = (uint32_t)i;
-                    else t.spill = 1;
-                }
-            }
-            __syncthreads();
-            if (wave == 0) {
-                if (!t.spill) {
-                    uint32_t added = 0;
-                    lds_insert_pending(t, R + c0, c.seed, added);
-                    for (int off = 32; off > 0; off >>= 1) added += __shfl_xor(added, off);
-                    if (lane == 0) {
-                        t.n_keys += added;
-                        if (t.n_keys > kMaxKeys) t.spill = 1;
+                } else if (s == -2) {
+                    t.spill = 1;
+                } else if (valid) {
+                    ins = c.bypass != 0;
+                    if (!ins) {
+                        uint32_t w, m;
+                        lds_bloom_bits(h, w, m);
+                        ins = (atomicOr(&t.bloom[w], m) & m) == m;
+                    }
+                    if (!ins) {
+                        const uint32_t d = atomicAdd(&t.n_defer, 1u);
+                        if (d < (uint32_t)kDeferCap) t.defer[d] = (uint32_t)i;
+                        else t.spill = 1;
                     }
                 }
-                if (lane == 0) t.n_pend = 0;
+                bool added;
+                const int si = lds_insert(t, ins, x.hi, x.lo, h, added);
+                if (ins) {
+                    if (si >= 0) lds_count(t, si, x.left, x.right);
+                    else t.spill = 1;
+                }
+                if (added && atomicAdd(&t.n_keys, 1u) >= kMaxKeys) t.spill = 1;
             }
-            __syncthreads();
-            if (t.spill) break;
         }
+        __syncthreads();
         if (!t.spill) {
+            st_recs += bin_recs;
             // deferred occurrences: counted when their k-mer is in the table
             const uint32_t nd = t.n_defer;
             for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
                 const Rec x = rec_unpack(R[t.defer[d]]);
-                const int s = lds_find(t, x.hi | kTaken, x.lo, key_hash(x.hi, x.lo, c.seed));
+                const int s = lds_find(t, x.hi, x.lo, key_hash(x.hi, x.lo, c.seed));
                 if (s >= 0) lds_count(t, s, x.left, x.right);
             }
-            __syncthreads();
             if (threadIdx.x == 0) {
                 st_defer += nd;
                 st_keys += t.n_keys;
             }
-            // depth filter, classification and export of the bin's table
-            for (int s0 = 0; s0 < kBinSlots; s0 += kBlock) {
-                const int s = s0 + threadIdx.x;
+            __syncthreads();
+            // depth filter, classification and export of the bin's table (two slots a thread),
+            // staged in the workgroup's area
+            bool take[2];
+            uint32_t tl[2][4], tr[2][4], count[2], cl[2], cr[2];
+            uint64_t khi[2], klo[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int s = j * kBlock + threadIdx.x;
                 const uint64_t th = t.hi[s];
-                bool take = false;
-                uint32_t tl[4], tr[4], count = 0, cl = 0, cr = 0;
+                take[j] = false;
+                count[j] = cl[j] = cr[j] = 0;
+                khi[j] = th & ((1ull << kExtShift) - 1);
+                klo[j] = 0;
                 if (th) {
                     uint64_t cnt = t.cnt[0][s];
                     for (int q = 0; q < 4; ++q) {
-                        tl[q] = t.cnt[1 + q][s];
-                        tr[q] = t.cnt[5 + q][s];
-                        cnt += tl[q];
+                        tl[j][q] = t.cnt[1 + q][s];
+                        tr[j][q] = t.cnt[5 + q][s];
+                        cnt += tl[j][q];
                     }
-                    count = (uint32_t)cnt;
-                    cl = side_class(tl, c.ext_min);
-                    cr = side_class(tr, c.ext_min);
-                    take = cnt >= c.min_depth && (!c.uu_only || (cl < 4 && cr < 4));
-                }
-                const uint64_t m = __ballot(take);
-                if (m) {
-                    const int leader = __ffsll((long long)m) - 1;
-                    unsigned long long base = 0;
-                    if ((int)lane == leader)
-                        base = atomicAdd(reinterpret_cast<unsigned long long *>(out.n_out),
-                                         (unsigned long long)__popcll(m));
-                    base = __shfl(base, leader);
-                    if (take) {
-                        const uint64_t idx = base + lanes_below(m);
-                        const uint64_t hi = th & ~kTaken, lo = t.lo[s];
-                        if (idx < out.capacity) {
-                            out.key_hi[idx] = hi;
-                            out.key_lo[idx] = lo;
-                            out.count[idx] = count;
-                            *reinterpret_cast<uint4 *>(out.tl + 4 * idx) = make_uint4(tl[0], tl[1], tl[2], tl[3]);
-                            *reinterpret_cast<uint4 *>(out.tr + 4 * idx) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
-                            out.cls_l[idx] = (uint8_t)cl;
-                            out.cls_r[idx] = (uint8_t)cr;
-                        } else {
-                            atomicOr(c.status, HM_ST_OUTPUT_FULL);
-                        }
-                        if (out.digest) {
-                            const uint64_t y = record_hash(hi, lo, count, tl, tr, cl, cr);
-                            dsum += y;
-                            dxor ^= y;
-                        }
-                        ++st_kept;
-                    }
+                    count[j] = (uint32_t)cnt;
+                    cl[j] = side_class(tl[j], c.ext_min);
+                    cr[j] = side_class(tr[j], c.ext_min);
+                    take[j] = cnt >= c.min_depth && (!c.uu_only || (cl[j] < 4 && cr[j] < 4));
+                    klo[j] = t.lo[s];
                 }
             }
+            const uint64_t m0 = __ballot(take[0]), m1 = __ballot(take[1]);
+            if (lane == 0) t.wsum[wave] = (uint32_t)(__popcll(m0) + __popcll(m1));
+            __syncthreads();
+            uint32_t tot = 0, before = 0;
+            for (int q = 0; q < kBlock / 64; ++q) {
+                before += q < wave ? t.wsum[q] : 0u;
+                tot += t.wsum[q];
+            }
+            if (t.staged + tot > (uint32_t)kStage) stage_flush(t, area, out, c.status);  // uniform
+            const uint32_t at = t.staged + before;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (!take[j]) continue;
+                const uint32_t i = at + (j == 0 ? lanes_below(m0) : (uint32_t)__popcll(m0) + lanes_below(m1));
+                area[4 * i] = make_uint4((uint32_t)klo[j], (uint32_t)(klo[j] >> 32), (uint32_t)khi[j],
+                                         (uint32_t)(khi[j] >> 32));
+                area[4 * i + 1] = make_uint4(tl[j][0], tl[j][1], tl[j][2], tl[j][3]);
+                area[4 * i + 2] = make_uint4(tr[j][0], tr[j][1], tr[j][2], tr[j][3]);
+                area[4 * i + 3] = make_uint4(count[j], cl[j] | (cr[j] << 8), 0u, 0u);
+                if (out.digest) {
+                    const uint64_t y = record_hash(khi[j], klo[j], count[j], tl[j], tr[j], cl[j], cr[j]);
+                    dsum += y;
+                    dxor ^= y;
+                }
+                ++st_kept;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) t.staged += tot;
         } else {
             // the bin goes to the global-table path whole
             if (threadIdx.x == 0) {
                 t.base = atomicAdd(reinterpret_cast<unsigned long long *>(spill.count), (unsigned long long)n);
                 st_spilled_bins += 1;
-                st_spilled += n;
             }
             __syncthreads();
             const uint64_t base = t.base;
             for (uint64_t i = threadIdx.x; i < n; i += kBlock) {
-                const Rec x = rec_unpack(R[i]);
+                const uint4 rr = R[i];
+                const Rec x = rec_unpack(rr);
                 const uint64_t idx = base + i;
                 if (idx < spill.capacity) {
                     *reinterpret_cast<uint4 *>(spill.keys + 2 * idx) =
                         make_uint4((uint32_t)x.hi, (uint32_t)(x.hi >> 32), (uint32_t)x.lo, (uint32_t)(x.lo >> 32));
-                    spill.ext[idx] = (uint8_t)(x.left | (x.right << 4));
+                    spill.ext[idx] = is_hole(rr) ? kHole : (uint8_t)(x.left | (x.right << 4));
+                    st_spilled += is_hole(rr) ? 0 : 1;
+                    st_recs += is_hole(rr) ? 0 : 1;
                 } else {
                     atomicOr(c.status, HM_ST_STREAM_FULL);
                 }
@@ -492,6 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
         clear();
         __syncthreads();
     }
+    stage_flush(t, area, out, c.status);
     digest_flush(out, dsum, dxor);
     if (c.stats) {
         const uint64_t v[6] = {st_recs, st_spilled_bins, st_spilled, st_defer, st_keys, st_kept};
@@ -538,28 +728,42 @@ __global__ void k_merge_counts(hm_export_t src, hm_export_t dst, uint32_t *statu
 int check_bins(const hm_bins_t *b) {
     if (!b || !b->recs || !b->tmp || !b->scratch || !b->bin_start || !b->status)
         return fail(HM_EINVAL, "bins: a buffer is NULL");
-    if (((uintptr_t)b->recs) & 15 || ((uintptr_t)b->tmp) & 15 || ((uintptr_t)b->scratch) & 7)
-        return fail(HM_EINVAL, "bins: recs and tmp must be 16-byte aligned, scratch 8-byte aligned");
+    if (((uintptr_t)b->recs) & 127 || ((uintptr_t)b->tmp) & 127 || ((uintptr_t)b->scratch) & 15)
+        return fail(HM_EINVAL, "bins: recs and tmp must be 128-byte aligned, scratch 16-byte aligned");
     if (b->group_bits > (uint32_t)kMaxBits || b->bin_bits > (uint32_t)kMaxBits)
         return fail(HM_EINVAL, "bins: group_bits and bin_bits must be at most %d", kMaxBits);
     return HM_OK;
 }
 
-// scratch layout (64-bit words): group starts (ng + 1), group totals (ng), then the two
-// histograms (32-bit counters)
+// scratch layout: the staging areas of hm_count_bins (kCountGrid x kStage records of 64 bytes),
+// then the group starts in tmp and in recs (ng + 1 words each), the group totals (ng words
+// each) and the two histograms (32-bit counters)
+constexpr uint64_t kStageBytes = (uint64_t)kCountGrid * kStage * 64;
+
 struct Scratch {
-    uint64_t *gstart, *gtot;
+    uint4 *stage;
+    uint64_t *gstart, *gtot, *gstart2, *gtot2;
     uint32_t *hist1, *hist2;
 };
 
 Scratch scratch_of(const hm_bins_t *b) {
     const uint64_t ng = 1ull << b->group_bits;
     Scratch s;
-    s.gstart = b->scratch;
+    s.stage = reinterpret_cast<uint4 *>(b->scratch);
+    s.gstart = b->scratch + kStageBytes / 8;
     s.gtot = s.gstart + ng + 1;
-    s.hist1 = reinterpret_cast<uint32_t *>(s.gtot + ng);
+    s.gstart2 = s.gtot + ng;
+    s.gtot2 = s.gstart2 + ng + 1;
+    s.hist1 = reinterpret_cast<uint32_t *>(s.gtot2 + ng);
     s.hist2 = s.hist1 + ng * kGrid1;
     return s;
+}
+
+// records hm_bin_kmers needs room for: the windows plus the padding of both levels' ranges
+uint64_t bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits, uint64_t g1) {
+    const uint64_t ng = 1ull << group_bits, nb = 1ull << (group_bits + bin_bits);
+    const uint64_t pad1 = (uint64_t)(kBlk1 - 1) * g1 * ng, pad2 = (uint64_t)(kBlk2 - 1) * nb * kSlices;
+    return windows + (pad1 > pad2 ? pad1 : pad2);
 }
 
 }  // namespace
@@ -572,7 +776,12 @@ extern "C" {
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits) {
     if (group_bits > (uint32_t)kMaxBits || bin_bits > (uint32_t)kMaxBits) return 0;
     const uint64_t ng = 1ull << group_bits, nb = 1ull << (group_bits + bin_bits);
-    return (size_t)(8 * (2 * ng + 1) + 4 * ng * kGrid1 + 4 * nb * kSlices);
+    return (size_t)(kStageBytes + 8 * (4 * ng + 2) + 4 * ng * kGrid1 + 4 * nb * kSlices);
+}
+
+uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits) {
+    if (group_bits > (uint32_t)kMaxBits || bin_bits > (uint32_t)kMaxBits) return 0;
+    return bins_capacity(windows, group_bits, bin_bits, kGrid1);
 }
 
 int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStream_t s) {
@@ -590,9 +799,15 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStr
     const uint64_t ng = 1ull << b->group_bits, ns = 1ull << b->bin_bits, n_bins = 1ull << total_bits;
     const int64_t W = r->n_reads > 0 ? (int64_t)r->read_len - p->k + 1 : 0;
     const uint64_t windows = W > 0 ? (uint64_t)r->n_reads * (uint64_t)W : 0;
-    if (windows > b->capacity) return fail(HM_EINVAL, "bins hold %llu records, the reads have %llu windows",
-                                           (unsigned long long)b->capacity, (unsigned long long)windows);
-    if (windows >= (1ull << 32)) return fail(HM_EINVAL, "binned counting takes fewer than 2^32 windows per call");
+    if (bins_capacity(windows, b->group_bits, b->bin_bits, kGrid1) >= (1ull << 32))
+        return fail(HM_EINVAL, "binned counting takes fewer than 2^32 records (windows and padding) per call");
+    const int32_t rpt = windows ? kTileBases / r->read_len : 1;
+    const int64_t n_tiles = windows ? (r->n_reads + rpt - 1) / rpt : 0;
+    const int g1 = (int)(n_tiles < kGrid1 ? n_tiles : kGrid1);
+    if (bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1) > b->capacity)
+        return fail(HM_EINVAL, "bins hold %llu records, the reads need %llu (windows and padding; see hm_bins_capacity)",
+                    (unsigned long long)b->capacity,
+                    (unsigned long long)bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1));
     rc = fill<uint32_t>(b->status, 1, 0u, s);
     if (rc) return rc;
     if (b->stats) {
@@ -615,23 +830,24 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStr
     a.owner = p->owner;
     a.seed = p->seed;
     a.status = b->status;
-    const int32_t rpt = kTileBases / r->read_len;
-    const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
-    const int g1 = (int)(n_tiles < kGrid1 ? n_tiles : kGrid1);
     uint4 *tmp = reinterpret_cast<uint4 *>(b->tmp);
     uint4 *recs = reinterpret_cast<uint4 *>(b->recs);
+    // the combiner's arrays and the range starts (4 bytes per destination)
+    const size_t lds1 = Combiner<kBlk1>::bytes(ng) + 4 * ng, lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;
     hipLaunchKernelGGL(k_hist1, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles, sc.hist1, total_bits, bin_bits);
-    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist1, g1, sc.gtot);
+    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist1, g1, (uint32_t)kBlk1, sc.gtot);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot, (int)ng, sc.gstart);
-    hipLaunchKernelGGL(k_scatter1, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles, sc.hist1, sc.gstart, tmp,
+    hipLaunchKernelGGL(k_scatter1, dim3(g1), dim3(kBlock), lds1, s, a, rpt, n_tiles, sc.hist1, sc.gstart, tmp,
                        total_bits, bin_bits);
     const dim3 g2((unsigned)(ng * kSlices));
     hipLaunchKernelGGL(k_hist2, g2, dim3(kBlock), ns * 4, s, tmp, sc.gstart, sc.hist2, total_bits, bin_bits);
     hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist2, (int)(ns * kSlices),
-                       (uint64_t *)nullptr);
-    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)grid_for(n_bins + 1, 16)), dim3(kBlock), 0, s, sc.hist2, sc.gstart,
-                       b->bin_start, total_bits, bin_bits);
-    hipLaunchKernelGGL(k_scatter2, g2, dim3(kBlock), ns * 4, s, tmp, sc.gstart, sc.hist2, recs, total_bits, bin_bits);
+                       (uint32_t)kBlk2, sc.gtot2);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot2, (int)ng, sc.gstart2);
+    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)grid_for(n_bins + 1, 16)), dim3(kBlock), 0, s, sc.hist2,
+                       sc.gstart2, b->bin_start, total_bits, bin_bits);
+    hipLaunchKernelGGL(k_scatter2, g2, dim3(kT2), lds2, s, tmp, sc.gstart, sc.gstart2, sc.hist2, recs, total_bits,
+                       bin_bits);
     HM_LAUNCH_CHECK("hm_bin_kmers");
     return HM_OK;
 }
@@ -666,7 +882,9 @@ int hm_count_bins(const hm_bins_t *b, const hm_params_t *p, uint32_t flags, hm_e
     c.uu_only = (flags & HM_EXPORT_UU_ONLY) ? 1 : 0;
     c.status = b->status;
     c.stats = reinterpret_cast<unsigned long long *>(b->stats);
-    const uint64_t cap = (uint64_t)device_cus() * kCountBlocksPerCu;
+    c.stage = scratch_of(b).stage;
+    uint64_t cap = (uint64_t)device_cus() * kCountBlocksPerCu;
+    if (cap > (uint64_t)kCountGrid) cap = kCountGrid;
     const dim3 g((unsigned)(c.n_bins < cap ? c.n_bins : cap));
     hipLaunchKernelGGL(k_count_bins, g, dim3(kBlock), 0, s, c, *out, *spill);
     HM_LAUNCH_CHECK("hm_count_bins");

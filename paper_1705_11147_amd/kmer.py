@@ -711,7 +711,7 @@ def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, tabl
 
 BIN_SLOTS = 512       # local table of a bin (hm_count_bins spills a bin past 384 keys)
 BIN_DEFER_CAP = 2048  # deferred occurrences a bin holds
-MAX_BIN_BITS = 12     # group_bits and bin_bits each
+MAX_BIN_BITS = 10     # group_bits and bin_bits each
 
 
 def plan_bins(distinct_hi: float, seen2_hi: float, bypass: bool = False) -> tuple[int, int]:
@@ -733,9 +733,10 @@ class BinnedCounter:
     used as scratch) and are counted by the global-table path (KmerCounter.insert_occ), whose
     export is merged into the binned one.
 
-    capacity: records (at least the windows of the read set, n_reads * (read_len - k + 1))."""
+    windows: the read set's windows, n_reads * (read_len - k + 1) (the buffers hold those plus the
+    padding of the partition's ranges, abi hm_bins_capacity)."""
 
-    def __init__(self, k: int, capacity: int, group_bits: int, bin_bits: int, min_depth: int = 2,
+    def __init__(self, k: int, windows: int, group_bits: int, bin_bits: int, min_depth: int = 2,
                  ext_min: int | None = None, n_owners: int = 1, owner: int = 0, flags: int = 0,
                  seed: int = DEFAULT_SEED, device="cuda", alloc=None):
         self.device = torch.device(device)
@@ -743,8 +744,10 @@ class BinnedCounter:
         self.params = abi.Params(k, min_depth, min_depth if ext_min is None else ext_min, n_owners, owner,
                                  flags & ~abi.HM_BLOOM_IN_TABLE, seed & (2 ** 64 - 1))
         abi.call("hm_check_params", ctypes.byref(self.params))
-        self.capacity = int(capacity)
         self.group_bits, self.bin_bits = int(group_bits), int(bin_bits)
+        self.capacity = int(abi.lib().hm_bins_capacity(int(windows), self.group_bits, self.bin_bits))
+        if self.capacity == 0:
+            raise ValueError("group_bits and bin_bits must each be at most %d" % MAX_BIN_BITS)
         self.n_bins = 1 << (self.group_bits + self.bin_bits)
         n = max(self.capacity, 1)
         self.recs = _new(2 * n, torch.int64, self.device, alloc)
