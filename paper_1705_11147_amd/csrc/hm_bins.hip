@@ -46,8 +46,13 @@ constexpr int kT2 = 512;            // threads of a second-level workgroup
 constexpr int kBinSlots = 512;     // LDS table of one bin
 constexpr int kBloomWords = 512;   // 32-bit filter words: 16384 bits per bin
 constexpr int kDeferCap = 2048;    // deferred occurrences of one bin
-constexpr int kPer = 4;            // records per thread per round
+constexpr int kPer = 4;            // records per thread per round (second-level histogram)
 constexpr int kChunk = kPer * kBlock;
+#ifndef HM_BIN_COUNT_PER
+#define HM_BIN_COUNT_PER 2
+#endif
+constexpr int kCPer = HM_BIN_COUNT_PER;  // records per thread per round of the counting pass
+constexpr int kCChunk = kCPer * kBlock;
 constexpr uint32_t kMaxKeys = kBinSlots * 3 / 4;
 constexpr int kExtShift = 58;
 constexpr int kMaxBinK = 61;       // 2k + 6 extension bits fit in 128
@@ -388,6 +393,19 @@ struct BinLds {
     unsigned long long base;
 };
 
+// Hash of a key inside its bin (home slot in the low 9 bits, filter word in the next 9, filter
+// bits in the top 20): a multilinear sum of the key's four 32-bit words mod 2^32, then a
+// xorshift-multiply mix.  The bin itself was chosen by another hash, so any good mix of the
+// key works here; the output does not depend on it.
+__device__ __forceinline__ uint32_t bin_local_hash(uint64_t hi, uint64_t lo, uint32_t seed) {
+    uint32_t x = seed + (uint32_t)lo * 0x9E3779B1u + (uint32_t)(lo >> 32) * 0x85EBCA77u + (uint32_t)hi * 0xC2B2AE3Du +
+                 (uint32_t)(hi >> 32) * 0x27D4EB2Fu;
+    x ^= x >> 15;
+    x *= 0x2C1B3C6Du;
+    x ^= x >> 13;
+    return x;
+}
+
 __device__ __forceinline__ uint64_t lds_word(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -404,9 +422,9 @@ __device__ __forceinline__ bool lds_published(const BinLds &t, uint32_t s, uint6
 // Slot of the key in the bin's table: -1 absent, -2 a claim stayed unpublished past the bound.
 // Only another wave can hold a claim unpublished here (a wave publishes its own claims before
 // it looks up its next occurrences).
-__device__ __forceinline__ int lds_find(const BinLds &t, uint64_t hi, uint64_t lo, uint64_t h) {
+__device__ __forceinline__ int lds_find(const BinLds &t, uint64_t hi, uint64_t lo, uint32_t h) {
     const uint64_t want = hi | kClaimed;
-    uint32_t s = (uint32_t)h & (kBinSlots - 1);
+    uint32_t s = h & (kBinSlots - 1);
     for (int p = 0; p < kBinSlots; ++p) {
         uint64_t x = lds_word(&t.hi[s]);
         if (x == 0) return -1;
@@ -425,9 +443,9 @@ __device__ __forceinline__ int lds_find(const BinLds &t, uint64_t hi, uint64_t l
 // word to key_hi | kClaimed, stores the second word and sets kReady; the claims of one step are
 // published before any lane of the wave compares a claimed slot's key, so a wave never waits
 // for itself, and lanes of other waves wait for kReady.
-__device__ __forceinline__ int lds_insert(BinLds &t, bool act, uint64_t hi, uint64_t lo, uint64_t h, bool &added) {
+__device__ __forceinline__ int lds_insert(BinLds &t, bool act, uint64_t hi, uint64_t lo, uint32_t h, bool &added) {
     const uint64_t want = hi | kClaimed;
-    uint32_t s = (uint32_t)h & (kBinSlots - 1), probes = 0;
+    uint32_t s = h & (kBinSlots - 1), probes = 0;
     int res = -2;
     bool active = act;
     added = false;
@@ -478,11 +496,11 @@ __device__ __forceinline__ void lds_count(BinLds &t, int s, int left, int right)
     if (right < 4) atomicAdd(&t.cnt[5 + right][s], 1u);
 }
 
-// Filter word and bits of a key in its bin's Bloom filter (4 bits of one 32-bit word; bits of the
-// hash other than those of the home slot).
-__device__ __forceinline__ void lds_bloom_bits(uint64_t h, uint32_t &w, uint32_t &m) {
-    w = (uint32_t)(h >> 9) & (kBloomWords - 1);
-    m = (1u << ((h >> 32) & 31)) | (1u << ((h >> 37) & 31)) | (1u << ((h >> 42) & 31)) | (1u << ((h >> 47) & 31));
+// Filter word and bits of a key in its bin's Bloom filter: 4 bits of one 32-bit word, from bits
+// of the in-bin hash other than those of the home slot.
+__device__ __forceinline__ void lds_bloom_bits(uint32_t h, uint32_t &w, uint32_t &m) {
+    w = (h >> 9) & (kBloomWords - 1);
+    m = (1u << ((h >> 12) & 31)) | (1u << ((h >> 17) & 31)) | (1u << ((h >> 22) & 31)) | (1u << (h >> 27));
 }
 
 // Move the workgroup's staged records to the export (one atomic add takes their range).  Called
@@ -541,21 +559,29 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
         const uint4 *R = c.recs + b0;
         uint64_t bin_recs = 0;  // this thread's records of the bin (holes aside)
         // one pass over the bin's occurrences: count, or test the filter and insert, or defer
-        for (uint64_t c0 = 0; c0 < n; c0 += kChunk) {
-            if (t.spill) break;  // set by any wave; the other waves may finish their round
-            uint4 r[kPer];
+        // the next round's records are loaded while this round's are counted
+        uint4 nxt[kCPer];
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const uint64_t i = c0 + j * kBlock + threadIdx.x;
-                r[j] = i < n ? R[i] : make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < kCPer; ++j) {
+            const uint64_t i = (uint64_t)j * kBlock + threadIdx.x;
+            nxt[j] = i < n ? R[i] : make_uint4(0, 0, 0, 0);
+        }
+        for (uint64_t c0 = 0; c0 < n; c0 += kCChunk) {
+            if (t.spill) break;  // set by any wave; the other waves may finish their round
+            uint4 r[kCPer];
+#pragma unroll
+            for (int j = 0; j < kCPer; ++j) {
+                r[j] = nxt[j];
+                const uint64_t i = c0 + kCChunk + j * kBlock + threadIdx.x;
+                nxt[j] = i < n ? R[i] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) {
+            for (int j = 0; j < kCPer; ++j) {
                 const uint64_t i = c0 + j * kBlock + threadIdx.x;
                 const bool valid = i < n && !is_hole(r[j]);
                 bin_recs += valid ? 1 : 0;
                 const Rec x = rec_unpack(r[j]);
-                const uint64_t h = valid ? key_hash(x.hi, x.lo, c.seed) : 0;
+                const uint32_t h = valid ? bin_local_hash(x.hi, x.lo, (uint32_t)c.seed) : 0u;
                 const int s = valid ? lds_find(t, x.hi, x.lo, h) : -1;
                 bool ins = false;
                 if (s >= 0) {
@@ -569,8 +595,17 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
                         lds_bloom_bits(h, w, m);
                         ins = (atomicOr(&t.bloom[w], m) & m) == m;
                     }
-                    if (!ins) {
-                        const uint32_t d = atomicAdd(&t.n_defer, 1u);
+                }
+                // deferred: one LDS atomic per wave reserves the wave's entries
+                const bool dfr = valid && s == -1 && !ins;
+                const uint64_t dm = __ballot(dfr);
+                if (dm) {
+                    const int leader = __ffsll((long long)dm) - 1;
+                    uint32_t d0 = 0;
+                    if ((int)lane == leader) d0 = atomicAdd(&t.n_defer, (uint32_t)__popcll(dm));
+                    d0 = __shfl(d0, leader);
+                    if (dfr) {
+                        const uint32_t d = d0 + lanes_below(dm);
                         if (d < (uint32_t)kDeferCap) t.defer[d] = (uint32_t)i;
                         else t.spill = 1;
                     }
@@ -591,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_count_bins(CountArgs c, hm_export_t 
             const uint32_t nd = t.n_defer;
             for (uint32_t d = threadIdx.x; d < nd; d += kBlock) {
                 const Rec x = rec_unpack(R[t.defer[d]]);
-                const int s = lds_find(t, x.hi, x.lo, key_hash(x.hi, x.lo, c.seed));
+                const int s = lds_find(t, x.hi, x.lo, bin_local_hash(x.hi, x.lo, (uint32_t)c.seed));
                 if (s >= 0) lds_count(t, s, x.left, x.right);
             }
             if (threadIdx.x == 0) {
