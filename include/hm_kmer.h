@@ -470,7 +470,7 @@ int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, 
  * global-table path over the same reads; the order differs.
  *
  * Limits: fixed-length reads (read_off NULL) of at most 16320 bases, k <= 61
- * (the key and its two extension codes share a 16-byte record), at most 2^20
+ * (the key and its two extension codes share a 16-byte record), at most 2^21
  * bins, fewer than 2^32 records (windows and padding) per call. */
 
 /* Event counters of hm_count_bins (hm_bins_t.stats, HM_N_BIN_STATS 64-bit words). */
@@ -488,7 +488,7 @@ typedef struct {
                             (scratch of hm_bin_kmers; free afterwards, e.g. as the keys of the spill stream) */
     uint64_t capacity;   /* records: at least hm_bins_capacity(windows, group_bits, bin_bits) */
     uint32_t group_bits; /* 0..10 */
-    uint32_t bin_bits;   /* 0..10: bins = 2^(group_bits + bin_bits) */
+    uint32_t bin_bits;   /* 0..11: bins = 2^(group_bits + bin_bits) */
     uint64_t *scratch;   /* hm_bins_scratch_bytes(group_bits, bin_bits) bytes, 16-byte aligned */
     uint64_t *bin_start; /* 2^(group_bits + bin_bits) + 1 words: bin i holds records [bin_start[i], bin_start[i+1]) */
     uint32_t *status;    /* device status word (cleared by hm_bin_kmers) */
@@ -498,15 +498,15 @@ typedef struct {
 /* Scratch bytes of hm_bin_kmers and hm_count_bins: for 2^g groups and 2^(g+b) bins,
  * 2^27 + 8 * (4 * 2^g + 2) + 4096 * 2^g + 32 * 2^(g+b) bytes (the 128 MiB are where
  * hm_count_bins stages each workgroup's records before it takes their output
- * range with one atomic add); 0 if g or b is above 10. */
+ * range with one atomic add); 0 if g is above 10 or b above 11. */
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits);
 
 /* Records the bins need room for (hm_bins_t.capacity) for a read set of `windows`
  * windows: the windows plus the padding that makes every destination range a
- * whole number of the blocks each partition level writes whole (2 records at
- * the first level, 4 at the second), windows + max(1024 * 2^g, 24 * 2^(g+b));
- * 0 if g or b is above 10.  Padding records ("holes": extension field 63) sit
- * at the ends of ranges and are skipped. */
+ * whole number of the 4-record (64-byte) blocks both partition levels write
+ * whole, windows + 3 * max(1024 * 2^g, 8 * 2^(g+b)); 0 if g is above 10 or b
+ * above 11.  Padding records ("holes": extension field 63) sit at the ends of
+ * ranges and are skipped. */
 uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits);
 
 /* Partition every valid window of `r` whose key is owned (hm_params_t

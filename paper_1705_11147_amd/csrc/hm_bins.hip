@@ -31,18 +31,26 @@ namespace {
 // bin map: multiply-shift hashing (any odd constants; the output does not depend on them)
 constexpr uint64_t kBinMul1 = 0xC2B2AE3D27D4EB4Full;
 constexpr uint64_t kBinMul2 = 0x165667B19E3779F9ull;
-constexpr int kGrid1 = 1024;       // most workgroups of the two passes over the reads
+#ifndef HM_BIN_GRID1
+#define HM_BIN_GRID1 1024
+#endif
+constexpr int kGrid1 = HM_BIN_GRID1;  // most workgroups of the two passes over the reads
 constexpr int kSlices = 8;         // workgroups per group in the second partition level
-constexpr int kMaxBits = 10;       // group_bits and bin_bits are each at most this (LDS of the scatters)
+constexpr int kMaxGroupBits = 10;  // LDS of the first-level scatter's combiner
+constexpr int kMaxBinBits = 11;    // LDS of the second-level scatter's combiner
 #ifndef HM_BIN_BLK1
-#define HM_BIN_BLK1 2
+#define HM_BIN_BLK1 4
 #endif
 #ifndef HM_BIN_BLK2
 #define HM_BIN_BLK2 4
 #endif
 constexpr int kBlk1 = HM_BIN_BLK1;  // records per written block, first level
 constexpr int kBlk2 = HM_BIN_BLK2;  // records per written block, second level
-constexpr int kT2 = 512;            // threads of a second-level workgroup
+constexpr int kT2 = 1024;           // threads of a second-level workgroup
+#ifndef HM_BIN_FLUSH1
+#define HM_BIN_FLUSH1 4
+#endif
+constexpr int kFlush1 = HM_BIN_FLUSH1;  // first level: rounds of windows between flushes
 constexpr int kBinSlots = 512;     // LDS table of one bin
 constexpr int kBloomWords = 512;   // 32-bit filter words: 16384 bits per bin
 constexpr int kDeferCap = 2048;    // deferred occurrences of one bin
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t *x, int cols, uin
     if (tot && threadIdx.x == kBlock - 1) tot[blockIdx.x] = s_part[kBlock - 1];
 }
 
-// start[g] = sum of tot[0..g), g = 0..n (one workgroup, n <= 2^kMaxBits)
+// start[g] = sum of tot[0..g), g = 0..n (one workgroup, n <= 2^kMaxGroupBits)
 __global__ __launch_bounds__(kBlock) void k_scan_totals(const uint64_t *tot, int n, uint64_t *start) {
     __shared__ uint64_t s_part[kBlock];
     const int per = (n + kBlock - 1) / kBlock;
@@ -261,17 +269,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter1(PassArgs a, int32_t rpt, in
     }
     if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
     auto at = [&](uint32_t g) { return tmp + gstart[g] + s_rel[g]; };
-    uint32_t par = 0;
+    uint32_t par = 0, round = 0;
     fixed_windows<false>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
         if (act) {
             const uint32_t g = bin_of(o.hi, o.lo, total_bits) >> bin_bits;
             cb.put(g, rec_pack(o), at(g), par);
         }
-        __syncthreads();
-        cb.flush_ready(threadIdx.x, kBlock, at, par);
-        __syncthreads();
-        par ^= 1;
+        if (++round == (uint32_t)kFlush1) {  // workgroup-uniform
+            round = 0;
+            __syncthreads();
+            cb.flush_ready(threadIdx.x, kBlock, at, par);
+            __syncthreads();
+            par ^= 1;
+        }
     });
+    __syncthreads();
+    cb.flush_ready(threadIdx.x, kBlock, at, par);  // blocks completed since the last flush
     __syncthreads();
     for (int g = threadIdx.x; g < ng; g += kBlock) cb.flush_tail(g, at(g));
 }
@@ -765,8 +778,9 @@ int check_bins(const hm_bins_t *b) {
         return fail(HM_EINVAL, "bins: a buffer is NULL");
     if (((uintptr_t)b->recs) & 127 || ((uintptr_t)b->tmp) & 127 || ((uintptr_t)b->scratch) & 15)
         return fail(HM_EINVAL, "bins: recs and tmp must be 128-byte aligned, scratch 16-byte aligned");
-    if (b->group_bits > (uint32_t)kMaxBits || b->bin_bits > (uint32_t)kMaxBits)
-        return fail(HM_EINVAL, "bins: group_bits and bin_bits must be at most %d", kMaxBits);
+    if (b->group_bits > (uint32_t)kMaxGroupBits || b->bin_bits > (uint32_t)kMaxBinBits)
+        return fail(HM_EINVAL, "bins: group_bits must be at most %d and bin_bits at most %d", kMaxGroupBits,
+                    kMaxBinBits);
     return HM_OK;
 }
 
@@ -809,13 +823,13 @@ using namespace hm;
 extern "C" {
 
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits) {
-    if (group_bits > (uint32_t)kMaxBits || bin_bits > (uint32_t)kMaxBits) return 0;
+    if (group_bits > (uint32_t)kMaxGroupBits || bin_bits > (uint32_t)kMaxBinBits) return 0;
     const uint64_t ng = 1ull << group_bits, nb = 1ull << (group_bits + bin_bits);
     return (size_t)(kStageBytes + 8 * (4 * ng + 2) + 4 * ng * kGrid1 + 4 * nb * kSlices);
 }
 
 uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits) {
-    if (group_bits > (uint32_t)kMaxBits || bin_bits > (uint32_t)kMaxBits) return 0;
+    if (group_bits > (uint32_t)kMaxGroupBits || bin_bits > (uint32_t)kMaxBinBits) return 0;
     return bins_capacity(windows, group_bits, bin_bits, kGrid1);
 }
 
@@ -838,7 +852,10 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStr
         return fail(HM_EINVAL, "binned counting takes fewer than 2^32 records (windows and padding) per call");
     const int32_t rpt = windows ? kTileBases / r->read_len : 1;
     const int64_t n_tiles = windows ? (r->n_reads + rpt - 1) / rpt : 0;
-    const int g1 = (int)(n_tiles < kGrid1 ? n_tiles : kGrid1);
+    // the first level's workgroups: three per CU (what the scatter's LDS allows at once), at most kGrid1
+    int64_t g1_cap = 3 * (int64_t)device_cus();
+    if (g1_cap > kGrid1) g1_cap = kGrid1;
+    const int g1 = (int)(n_tiles < g1_cap ? n_tiles : g1_cap);
     if (bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1) > b->capacity)
         return fail(HM_EINVAL, "bins hold %llu records, the reads need %llu (windows and padding; see hm_bins_capacity)",
                     (unsigned long long)b->capacity,

@@ -711,19 +711,22 @@ def plan_sizes(card: CardResult, n_hash: int = 4, bloom_bits: float = 12.0, tabl
 
 BIN_SLOTS = 512       # local table of a bin (hm_count_bins spills a bin past 384 keys)
 BIN_DEFER_CAP = 2048  # deferred occurrences a bin holds
-MAX_BIN_BITS = 10     # group_bits and bin_bits each
+MAX_GROUP_BITS = 10   # first partition level
+MAX_BIN_BITS = 11     # second partition level (bins per group)
 
 
 def plan_bins(distinct_hi: float, seen2_hi: float, bypass: bool = False) -> tuple[int, int]:
     """(group_bits, bin_bits) for the binned path: enough bins that a bin's distinct k-mers (its
     deferred occurrences, about one per distinct k-mer) stay near 900 of the 2048 its list holds,
     and the k-mers it inserts (those seen at least twice, or with the Bloom filter bypassed every
-    distinct k-mer) near 192 of the 384 its table takes before the bin spills."""
+    distinct k-mer) near 192 of the 384 its table takes before the bin spills; at most 2^21 bins.
+    The second level takes up to 11 bits and at least half, so that small inputs still spread
+    over many first-level groups."""
     need = seen2_hi / 192.0 if not bypass else distinct_hi / 192.0
     need = max(1.0, need, distinct_hi / 900.0)
-    total = min(2 * MAX_BIN_BITS, max(0, int(math.ceil(math.log2(need)))))
-    g = min(MAX_BIN_BITS, (total + 1) // 2)
-    return g, total - g
+    total = min(MAX_GROUP_BITS + MAX_BIN_BITS, max(0, int(math.ceil(math.log2(need)))))
+    b = min(MAX_BIN_BITS, total, max(total - MAX_GROUP_BITS, (total + 3) // 2))
+    return total - b, b
 
 
 class BinnedCounter:
@@ -747,15 +750,13 @@ class BinnedCounter:
         self.group_bits, self.bin_bits = int(group_bits), int(bin_bits)
         self.capacity = int(abi.lib().hm_bins_capacity(int(windows), self.group_bits, self.bin_bits))
         if self.capacity == 0:
-            raise ValueError("group_bits and bin_bits must each be at most %d" % MAX_BIN_BITS)
+            raise ValueError("group_bits must be at most %d and bin_bits at most %d" % (MAX_GROUP_BITS, MAX_BIN_BITS))
         self.n_bins = 1 << (self.group_bits + self.bin_bits)
         n = max(self.capacity, 1)
         self.recs = _new(2 * n, torch.int64, self.device, alloc)
         self.tmp = _new(2 * n, torch.int64, self.device, alloc)
         self.spill_ext = _new(n, torch.uint8, self.device, alloc)
         sb = abi.lib().hm_bins_scratch_bytes(self.group_bits, self.bin_bits)
-        if sb == 0:
-            raise ValueError("group_bits and bin_bits must each be at most %d" % MAX_BIN_BITS)
         self.scratch = _new((sb + 7) // 8, torch.int64, self.device, alloc)
         self.bin_start = _new(self.n_bins + 1, torch.int64, self.device, alloc)
         self.status_buf = _new(1, torch.int32, self.device, alloc, zero=True)

@@ -151,17 +151,17 @@ def test_binned_path_rejections(L):
     formula in the header, and bad bins, reads, k or flags return HM_EINVAL before any launch."""
     assert L.hm_bins_scratch_bytes(0, 0) == (1 << 27) + 8 * 6 + 4096 + 32
     assert L.hm_bins_scratch_bytes(9, 10) == (1 << 27) + 8 * (4 * 512 + 2) + 4096 * 512 + 32 * (1 << 19)
-    assert L.hm_bins_scratch_bytes(11, 0) == 0 and L.hm_bins_scratch_bytes(0, 11) == 0
-    # capacity: the windows plus the padding of either level's ranges (blocks of 2 and 4 records),
-    # whichever is more
-    assert L.hm_bins_capacity(1000, 2, 3) == 1000 + max(1024 * 4, 24 * 32)
-    assert L.hm_bins_capacity(10 ** 9, 10, 10) == 10 ** 9 + 24 * (1 << 20)
-    assert L.hm_bins_capacity(5, 11, 0) == 0
-    good = dict(recs=256, tmp=512, capacity=1000 + 4096, group_bits=2, bin_bits=3, scratch=1024, bin_start=2048,
+    assert L.hm_bins_scratch_bytes(11, 0) == 0 and L.hm_bins_scratch_bytes(0, 12) == 0
+    assert L.hm_bins_scratch_bytes(0, 11) > 0
+    # capacity: the windows plus 3 padding records per range of either level, whichever is more
+    assert L.hm_bins_capacity(1000, 2, 3) == 1000 + 3 * max(1024 * 4, 8 * 32)
+    assert L.hm_bins_capacity(10 ** 9, 9, 11) == 10 ** 9 + 3 * 8 * (1 << 20)
+    assert L.hm_bins_capacity(5, 11, 0) == 0 and L.hm_bins_capacity(5, 0, 12) == 0
+    good = dict(recs=256, tmp=512, capacity=1000 + 3 * 4096, group_bits=2, bin_bits=3, scratch=1024, bin_start=2048,
                 status=4096, stats=None)
     r = abi.Reads(8, 8, 8, None, 10, 1000, 100)
     for bad, msg in ((dict(recs=None), "NULL"), (dict(status=None), "NULL"), (dict(recs=264), "aligned"), (dict(scratch=1032), "aligned"),
-                     (dict(group_bits=11), "at most"), (dict(bin_bits=11), "at most"),
+                     (dict(group_bits=11), "at most"), (dict(bin_bits=12), "at most"),
                      (dict(capacity=1000), "padding"), (dict(tmp=576), "aligned")):
         b = abi.Bins(**dict(good, **bad))
         assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(b), None) == abi.HM_EINVAL
@@ -189,20 +189,20 @@ def test_binned_path_rejections(L):
 
 def test_bin_plan_keeps_bins_within_their_local_limits():
     """plan_bins: enough bins that a bin's expected distinct k-mers and inserted k-mers stay well
-    inside the deferred list (2048) and the table's spill limit (384), up to 2^20 bins, and the
-    two levels split the bits evenly."""
+    inside the deferred list (2048) and the table's spill limit (384), up to 2^21 bins, with the
+    second level taking at least half of the bits (at most 11)."""
     from paper_1705_11147_amd.kmer import plan_bins
     for distinct, seen2, bypass in ((4.76e8, 1.03e8, False), (4.4e6, 1.1e6, False), (1e3, 500, False),
                                     (4.76e8, 1.03e8, True), (1.2e9, 2.5e8, False), (10, 2, False), (3e9, 9e8, True)):
         g, b = plan_bins(distinct, seen2, bypass)
-        assert 0 <= g <= 10 and 0 <= b <= 10 and abs(g - b) <= 1
+        assert 0 <= g <= 10 and 0 <= b <= 11 and (b >= g or b == 11)
         bins = 1 << (g + b)
         inserted = (distinct if bypass else seen2) / bins
-        assert distinct / bins <= 900 and inserted <= 192 or g + b == 20
+        assert distinct / bins <= 900 and inserted <= 192 or g + b == 21
         if g + b > 0:  # not more bins than needed: half as many would break a limit
             half = bins / 2
             assert distinct / half > 900 or (distinct if bypass else seen2) / half > 192
-    assert plan_bins(4.76e8, 1.03e8) == (10, 10)
+    assert plan_bins(4.76e8, 1.03e8) == (9, 11)
 
 
 def test_status_code_maps_words_on_the_host(L):
