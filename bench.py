@@ -358,6 +358,91 @@ def run_tiny(args, dev, log, steps=50):
     return res
 
 
+RECORD_OUT_BYTES = 54  # an exported record: key 16 + count 4 + two tally arrays 32 + two class bytes
+BIN_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_bins.hip")]
+
+
+def run_binned_step(args, dev, log, ascii, qual, packed, sketch, card, positions, L, p, stream, ref_digest,
+                    n_records, method_bpp):
+    """The binned path as the step: pack, cardinality pass, partition into LDS-sized bins
+    (hm_bin_kmers), per-bin Bloom filter + table + classification + export in workgroup memory
+    (hm_count_bins), and, when a bin did not fit, its records through the table path (checked
+    every step: the spill count is read back).  Returns the figures and the export buffer."""
+    import torch
+    from paper_1705_11147_amd import abi, kmer
+
+    g, b = kmer.plan_bins(card.distinct_hi(), card.kept_hi(), p.min_depth == 1)
+    bc = kmer.BinnedCounter(p.k, positions, g, b, min_depth=p.min_depth, device=dev)
+    out = kmer.Records(int(n_records * 1.2) + 4096, device=dev)
+    stages = ["pack", "card", "partition", "count"]
+    spilled = [0]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut, out=packed)
+        mark(1)
+        sketch.reset()
+        sketch.update(packed)
+        sketch.summarize(min_depth=p.min_depth)
+        mark(2)
+        bc.bin(packed)
+        mark(3)
+        bc.count(out)
+        mark(4)
+        n_sp = bc.spilled()  # synchronizes; a spilled bin is counted by the table path
+        if n_sp:
+            spilled[0] += n_sp
+            bc.finish(out)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(args.steps)]
+    spilled[0] = 0
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    abi.check(bc.status(), "binned k-mer analysis (timed steps)")
+    same = out.digest_words() == ref_digest and int(out.n_out.item()) == n_records
+    assert same, "the binned export differs from the table path's"
+    stage_ms = {x: float(np.mean([events[s][i].elapsed_time(events[s][i + 1]) for s in range(args.steps)]))
+                for i, x in enumerate(stages)}
+    step_ms = np.array([events[s][0].elapsed_time(events[s][len(stages)]) for s in range(args.steps)])
+    st = bc.stats()
+    # the longest kernel: k_count_bins (one launch of hm_count_bins, timed by the events around it).
+    # Algorithmic bytes: every record read once, every kept record written
+    cnt_ms = stage_ms["count"]
+    alg = RECORD_OUT_BYTES * n_records + 16 * positions
+    achieved = alg / (cnt_ms / 1000) / 1e9
+    med = float(np.median(step_ms))
+    roofline = {"kernel": "k_count_bins (per-bin Bloom filter, table, classification and export in LDS)",
+                "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(os.path.join(ROOT, "profiles", "k_count_bins_mid_k51_traffic.md"),
+                                            BIN_SOURCES) if args.scale == 1.0 and args.workload == "mid" else None,
+                "bytes_per_position": round(alg / positions, 2),
+                "model": "16 B read per record + %d B written per kept k-mer" % RECORD_OUT_BYTES,
+                "kernel_ms": round(cnt_ms, 3),
+                "frac_step_method_model": round(method_bpp * positions / (med / 1000) / 1e9 / HBM_PEAK_GBS, 4),
+                "method_model": "(1 + s) * 2g + g bytes per position (g = 64 B) over the whole step: the random "
+                                "line accesses the table design makes, which the binned design replaces"}
+    res = {"value": round(positions * args.steps / elapsed, 1), "ms_per_step": round(elapsed * 1000 / args.steps, 3),
+           "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
+           "step_ms": {"median": round(med, 3), "p10": round(float(np.percentile(step_ms, 10)), 3),
+                       "p90": round(float(np.percentile(step_ms, 90)), 3), "n": int(args.steps)},
+           "bins": {"group_bits": g, "bin_bits": b, "n_bins": 1 << (g + b), "records_padded": bc.capacity,
+                    "spilled_records_per_step": spilled[0] // max(args.steps, 1), **st},
+           "roofline": roofline, "same_as_table_path": bool(same)}
+    log("binned step: %.2f ms (%s), count kernel %.2f ms" % (med, ", ".join("%s %.2f" % kv for kv in stage_ms.items()),
+                                                           cnt_ms))
+    return res, bc, out
+
+
 def run_serving(args, dev, log):
     """Poisson arrivals (20 jobs/s) of hexaploid-like k-mer analysis jobs
     (ancestor log-U[1,50] Mbp + 3 homeologs at 1.5%, 30x of 150 bp, 0.5%
@@ -686,6 +771,11 @@ def main():
     ap.add_argument("--batch-sets", type=int, default=64)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--path", choices=["binned", "table"], default="binned",
+                    help="the timed step: the binned path (LDS-sized bins) or the table path (one count table in "
+                         "HBM); the other is measured as a sub-record")
+    ap.add_argument("--no-binned-sub", action="store_true",
+                    help="with --path table: skip the binned path's sub-record")
     ap.add_argument("--no-tiny", action="store_true",
                     help="skip the tiny read set (GPU step, full oracle comparison, oracle on 1 and all threads)")
     ap.add_argument("--no-heavy-workload", action="store_true",
@@ -900,6 +990,11 @@ def main():
         reqs = st["probe_slots"] + (occ - deferred) + bloom_tests + st["cas_attempts"] + 2 * st["wide_counts"]
         roofline["pass1_random_requests_Gps"] = round(reqs / (stage_ms["pass1"] / 1000) / 1e9, 2)
 
+    binned, bc, out_b = None, None, None
+    if args.path == "binned" or not args.no_binned_sub:
+        binned, bc, out_b = run_binned_step(args, dev, log, ascii, qual, packed, sketch, card, positions, L, p, stream,
+                                            ref_digest, n_records, bpp)
+
     sorted_export = None
     if not args.no_sort:
         sorted_export = measure_sorted_export(kc, out, k, n_records, ref_digest, stream, log)
@@ -925,7 +1020,8 @@ def main():
         ms = e0.elapsed_time(e1)
         nbytes = r.ascii.size + r.qual.size
         h2d = {"bytes": int(nbytes), "ms": round(ms, 3), "GBps": round(nbytes / (ms / 1000) / 1e9, 2),
-               "kmers_per_s_with_h2d": round(positions / ((step_dist["median"] + ms) / 1000), 1)}
+               "kmers_per_s_with_h2d": round(positions / (((binned["step_ms"]["median"] if args.path == "binned"
+                                                            else step_dist["median"]) + ms) / 1000), 1)}
         log("h2d: %s" % h2d)
         del pa, pq
 
@@ -970,11 +1066,12 @@ def main():
         import oracle
         n_shards, shard = 64, 5
         t1 = time.perf_counter()
-        hk = out.key_hi[:n_records].cpu().numpy().view(np.uint64)
-        lk = out.key_lo[:n_records].cpu().numpy().view(np.uint64)
+        timed = out_b if args.path == "binned" else out  # the export of the timed steps
+        hk = timed.key_hi[:n_records].cpu().numpy().view(np.uint64)
+        lk = timed.key_lo[:n_records].cpu().numpy().view(np.uint64)
         idx = np.nonzero(oracle.shard_of(hk, lk, n_shards) == shard)[0]
         del hk, lk
-        got = device_rows(out, torch.from_numpy(idx).to(dev))
+        got = device_rows(timed, torch.from_numpy(idx).to(dev))
         exp = oracle.run(r.ascii, r.qual, r.offsets(), k, qcut=p.qcut, min_depth=p.min_depth, n_shards=n_shards,
                          shard=shard, n_threads=threads, sort_count=True)
         same = same_records(got, exp)
@@ -996,23 +1093,23 @@ def main():
         off = np.arange(n_cpu + 1, dtype=np.int64) * L
         res = oracle.run(sub_a, sub_q, off, k, qcut=p.qcut, min_depth=p.min_depth, n_threads=threads,
                          sort_count=True)
-        del kc, out
+        del kc, out, bc, out_b
         torch.cuda.empty_cache()
         g = kmer.analyze(sub_a, sub_q, k, read_len=L, qcut=p.qcut, min_depth=p.min_depth,
-                         export_flags=abi.HM_EXPORT_SORTED, fused=True, device=dev)
+                         export_flags=abi.HM_EXPORT_SORTED, fused=True, binned=args.path == "binned", device=dev)
         same = same_records(g, res)
         assert same, "the GPU table of the CPU-baseline sample disagrees with the oracle"
         cpu = {"value": round(n_cpu * W / res["seconds"], 1), "unit": "k-mers/s", "cores": threads,
                "kind": "oracle",
                "sample": "first %d reads (%d positions, %.0f%% of the workload), sort-counted on %d threads, %.1fs; "
-                         "the GPU's table of the same sample is identical (%d records); %s" % (
-                             n_cpu, n_cpu * W, 100.0 * n_cpu / r.n_reads, threads, res["seconds"],
+                         "the GPU's table of the same sample (%s path) is identical (%d records); %s" % (
+                             n_cpu, n_cpu * W, 100.0 * n_cpu / r.n_reads, threads, res["seconds"], args.path,
                              len(res["count"]), cpu_model())}
         log("cpu baseline: %s" % cpu)
         del g, res
-        kc = out = None
+        kc = out = bc = out_b = None
 
-    del kc, out, packed, ascii, qual
+    del kc, out, bc, out_b, packed, ascii, qual
     torch.cuda.empty_cache()
     tiny = None
     if not args.no_tiny:
@@ -1040,21 +1137,36 @@ def main():
         torch.cuda.empty_cache()
         human = run_human_share(args, dev)
 
+    cardinality = {"hll_estimate": round(card.estimate, 1), "hll_p": card.hll_p, "sampled_kept": card.sampled_kept,
+                   "sample_log2": card.sample_log2, "kept_estimate": card.sampled_kept << card.sample_log2,
+                   "heavy_hitters": card.n_heavy}
+    table_step = "pack+cardinality+init+pass1+pass2+(classify fused into export), inputs resident in HBM"
+    table_path = {"value": round(value, 1), "ms_per_step": round(ms_per_step, 3), "table_slots": table_slots,
+                  "bloom": bloom, "step": table_step, "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
+                  "step_ms": step_dist, "roofline": roofline}
+    config = {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
+              "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
+              "cardinality": cardinality}
+    if args.path == "binned":
+        head = binned
+        config.update(path="binned", step="pack+cardinality+partition into LDS-sized bins+per-bin Bloom filter, "
+                                           "table, classification and export in workgroup memory (spilled bins "
+                                           "through the table path), inputs resident in HBM",
+                      bins=binned["bins"], stage_ms=binned["stage_ms"], step_ms=binned["step_ms"])
+        sub = {"table_path": table_path}
+    else:
+        head = dict(table_path, value=value, ms_per_step=ms_per_step)
+        config.update(path="table", table_slots=table_slots, bloom=bloom, step=table_step,
+                      stage_ms=table_path["stage_ms"], step_ms=step_dist)
+        sub = {"binned_path": {x: binned[x] for x in ("value", "ms_per_step", "stage_ms", "step_ms", "bins",
+                                                      "roofline")} if binned else None}
     line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": w.name, "genome_bp": int(w.meta["G"]), "reads": r.n_reads, "read_len": L, "k": k,
-                   "qcut": p.qcut, "min_depth": p.min_depth, "positions": positions, "kept_kmers": n_records,
-                   "table_slots": table_slots, "bloom": bloom,
-                   "step": "pack+cardinality+init+pass1+pass2+(classify fused into export), inputs resident in HBM",
-                   "cardinality": {"hll_estimate": round(card.estimate, 1), "hll_p": card.hll_p,
-                                   "sampled_kept": card.sampled_kept, "sample_log2": card.sample_log2,
-                                   "kept_estimate": card.sampled_kept << card.sample_log2,
-                                   "heavy_hitters": card.n_heavy},
-                   "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
-                   "step_ms": step_dist},
-        "roofline": roofline,
+        "metric": METRIC, "value": round(head["value"], 1), "unit": "k-mers/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": config,
+        "roofline": head["roofline"],
+        **sub,
         "oracle_check": oracle_check,
         "cpu_baseline": cpu,
         "sorted_export": sorted_export,
