@@ -1,8 +1,8 @@
 """Parity at full workload size, in the launch configuration bench.py times.
 
-The mid workload's whole table (2e9 positions, 1.0e8 kept k-mers) is compared
-with the oracle's record by record (the sort-counted oracle on every host
-core); so are all 64 read sets of the batched workload, and one GPU's share of
+The mid workload's whole table (2e9 positions, 1.0e8 kept k-mers), from the
+table path and from the binned path, is compared with the oracle's record by
+record (the sort-counted oracle on every host core); so are all 64 read sets of the batched workload, and one GPU's share of
 the human-scale recipe at 1/10 of its reads in ten streamed batches.
 Properties that hold at any size (position count, event balance,
 determinism) are checked on the full tables too."""
@@ -60,7 +60,19 @@ def test_mid_workload_full_size():
     assert st["hit_first_lookup"] + st["bloom_tests"] + st["heavy_local"] == positions
     assert st["p2_entries"] == st["deferred"]
     got = out.to_numpy(sort=False)  # in key order: HM_EXPORT_SORTED
-    del a, q, packed, kc, out
+    del kc, out
+    torch.cuda.empty_cache()
+    # the binned path (the bench's timed step) on the same reads, with the bench's partition
+    g, b = kmer.plan_bins(card.distinct_hi(), card.kept_hi())
+    bc = kmer.BinnedCounter(k, positions, g, b, min_depth=p.min_depth, device=dev)
+    bout = kmer.Records(int(len(got["count"]) * 1.2) + 4096, device=dev)
+    assert bc.run(packed, bout) == 0  # no bin spills at this workload
+    assert bc.status() == abi.HM_OK
+    bst = bc.stats()
+    assert bst["records"] == positions and bst["kept"] == len(got["count"])
+    assert bout.digest_words() == digests[0]
+    binned = bout.to_numpy(sort=True)
+    del a, q, packed, bc, bout
     torch.cuda.empty_cache()
     hi, lo = got["key_hi"], got["key_lo"]
     assert ((hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] > lo[:-1]))).all()
@@ -71,7 +83,8 @@ def test_mid_workload_full_size():
     assert exp["positions"] == positions
     assert len(exp["count"]) > 90_000_000
     assert_tables_equal(got, exp, "mid full size, every record")
-    del exp
+    assert_tables_equal(binned, exp, "mid full size, binned path, every record")
+    del exp, binned
     # the cardinality pass at full size, bit for bit
     ec = oracle.card(r.ascii, r.offsets(), k, hll_p=card.hll_p, sample_log2=card.sample_log2,
                      heavy_log2=card.heavy_log2, min_depth=p.min_depth, heavy_min=16, n_threads=THREADS)
