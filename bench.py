@@ -359,7 +359,7 @@ def run_tiny(args, dev, log, steps=50):
 
 
 RECORD_OUT_BYTES = 54  # an exported record: key 16 + count 4 + two tally arrays 32 + two class bytes
-BIN_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_bins.hip")]
+BIN_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_bins.h", "hm_bins.hip")]
 
 
 def run_binned_step(args, dev, log, ascii, qual, packed, sketch, card, positions, L, p, stream, ref_digest,
@@ -385,10 +385,10 @@ def run_binned_step(args, dev, log, ascii, qual, packed, sketch, card, positions
         kmer.pack_reads(ascii, qual, read_len=L, qcut=p.qcut, out=packed)
         mark(1)
         sketch.reset()
-        sketch.update(packed)
+        sketch.update(packed, bins=bc)  # also counts the partition's first-level histogram
         sketch.summarize(min_depth=p.min_depth)
         mark(2)
-        bc.bin(packed)
+        bc.bin(packed, counted=True)
         mark(3)
         bc.count(out)
         mark(4)

@@ -514,9 +514,28 @@ uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bi
  * ext = left | right << 3 with the extensions as pass 1 takes them.  The bin
  * of a key is the top group_bits + bin_bits bits of
  * (key_lo ^ key_hi * 0xC2B2AE3D27D4EB4F) * 0x165667B19E3779F9 mod 2^64
- * (multiply-shift hashing).  HM_EINVAL (nothing launched) for variable-length
- * reads, k > 61, b->capacity below hm_bins_capacity, or 2^32 or more records. */
-int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStream_t stream);
+ * (multiply-shift hashing).  flags: 0, or HM_BINS_COUNTED when
+ * hm_cardinality_bins has counted the first level's histogram for these
+ * reads, params and bins, on the same stream, with no hm_bin_kmers on these
+ * bins' scratch since (the partition then starts from it; the library notes
+ * each hm_cardinality_bins on the host and checks the note).  HM_EINVAL
+ * (nothing launched) for unknown flags, HM_BINS_COUNTED without such a
+ * note, variable-length reads, k > 61, b->capacity below hm_bins_capacity,
+ * or 2^32 or more records. */
+#define HM_BINS_COUNTED 1u
+int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32_t flags, hipStream_t stream);
+
+/* hm_cardinality (section "Parallel k-mer analysis": the HyperLogLog pass that
+ * sizes the filters), also counting, for each workgroup of hm_bin_kmers' first
+ * level, how many owned windows of each group its tiles hold: the histogram
+ * hm_bin_kmers would otherwise count in a pass of its own.  Call it with the
+ * same reads, params and bins (group_bits, bin_bits) right before
+ * hm_bin_kmers(..., HM_BINS_COUNTED, ...), which then skips that pass; the
+ * histogram lives in the bins' scratch until that hm_bin_kmers consumes it.
+ * The sketch it leaves is the same as hm_cardinality's.  HM_EINVAL: reads of
+ * variable length, or 2^hll_p + 4 * 2^group_bits above 65536 (the pass keeps
+ * the registers and the group counters in one workgroup's memory). */
+int hm_cardinality_bins(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hm_bins_t *b, hipStream_t stream);
 
 /* Count the bins of `b` (after hm_bin_kmers with the same params) and export
  * every k-mer with count >= p->min_depth, classified with p->ext_min, into

@@ -41,6 +41,7 @@ HM_MAX_HEAVY = 256
 HM_EXPORT_STATIC_MAX_RECORDS = 1 << 18
 
 HM_N_BIN_STATS = 6
+HM_BINS_COUNTED = 1
 BIN_STAT_NAMES = ("records", "spilled_bins", "spilled", "deferred", "keys", "kept")
 
 HM_CLS_FORK = 4
@@ -166,7 +167,8 @@ SIGNATURES = {
     "hm_bloom_insert_occ": ([P(Occ), P(Params), P(Bloom), P(Table), P(List), vp], ctypes.c_int),
     "hm_bins_scratch_bytes": ([ctypes.c_uint32, ctypes.c_uint32], ctypes.c_size_t),
     "hm_bins_capacity": ([ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
-    "hm_bin_kmers": ([P(Reads), P(Params), P(Bins), vp], ctypes.c_int),
+    "hm_bin_kmers": ([P(Reads), P(Params), P(Bins), ctypes.c_uint32, vp], ctypes.c_int),
+    "hm_cardinality_bins": ([P(Reads), P(Params), P(Card), P(Bins), vp], ctypes.c_int),
     "hm_count_bins": ([P(Bins), P(Params), ctypes.c_uint32, P(Export), P(Occ), vp], ctypes.c_int),
     "hm_export_merge": ([P(Export), P(Export), vp, vp], ctypes.c_int),
     "hm_contigs_work_bytes": ([ctypes.c_uint64], ctypes.c_size_t),

@@ -23,14 +23,14 @@
 // (hm_bloom_insert_occ, hm_kmer_count, hm_export_table), whose export
 // hm_export_merge appends to this one.  Either way every occurrence is counted
 // exactly once, whatever the Bloom false positives.
-#include "hm_device.h"
+#include <mutex>
+#include <unordered_map>
+
+#include "hm_bins.h"
 
 namespace hm {
 namespace {
 
-// bin map: multiply-shift hashing (any odd constants; the output does not depend on them)
-constexpr uint64_t kBinMul1 = 0xC2B2AE3D27D4EB4Full;
-constexpr uint64_t kBinMul2 = 0x165667B19E3779F9ull;
 #ifndef HM_BIN_GRID1
 #define HM_BIN_GRID1 1024
 #endif
@@ -67,12 +67,6 @@ constexpr int kMaxBinK = 61;       // 2k + 6 extension bits fit in 128
 constexpr int kCountBlocksPerCu = 4;
 static_assert(kBinSlots == 2 * kBlock, "the export takes two slots a thread");
 
-__device__ __forceinline__ uint64_t bin_hash(uint64_t hi, uint64_t lo) { return (lo ^ hi * kBinMul1) * kBinMul2; }
-
-// bin of a key: the top `bits` bits of its bin hash (0 when bits == 0)
-__device__ __forceinline__ uint32_t bin_of(uint64_t hi, uint64_t lo, int bits) {
-    return bits ? (uint32_t)(bin_hash(hi, lo) >> (64 - bits)) : 0u;
-}
 
 // record: word 0 = key_lo, word 1 = key_hi | ext << 58, ext = left | right << 3 (0..3 base, 4 none)
 __device__ __forceinline__ uint4 rec_pack(const Occ &o) {
@@ -773,16 +767,6 @@ __global__ void k_merge_counts(hm_export_t src, hm_export_t dst, uint32_t *statu
     }
 }
 
-int check_bins(const hm_bins_t *b) {
-    if (!b || !b->recs || !b->tmp || !b->scratch || !b->bin_start || !b->status)
-        return fail(HM_EINVAL, "bins: a buffer is NULL");
-    if (((uintptr_t)b->recs) & 127 || ((uintptr_t)b->tmp) & 127 || ((uintptr_t)b->scratch) & 15)
-        return fail(HM_EINVAL, "bins: recs and tmp must be 128-byte aligned, scratch 16-byte aligned");
-    if (b->group_bits > (uint32_t)kMaxGroupBits || b->bin_bits > (uint32_t)kMaxBinBits)
-        return fail(HM_EINVAL, "bins: group_bits must be at most %d and bin_bits at most %d", kMaxGroupBits,
-                    kMaxBinBits);
-    return HM_OK;
-}
 
 // scratch layout: the staging areas of hm_count_bins (kCountGrid x kStage records of 64 bytes),
 // then the group starts in tmp and in recs (ng + 1 words each), the group totals (ng words
@@ -816,6 +800,71 @@ uint64_t bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits,
 }
 
 }  // namespace
+
+int check_bins(const hm_bins_t *b) {
+    if (!b || !b->recs || !b->tmp || !b->scratch || !b->bin_start || !b->status)
+        return fail(HM_EINVAL, "bins: a buffer is NULL");
+    if (((uintptr_t)b->recs) & 127 || ((uintptr_t)b->tmp) & 127 || ((uintptr_t)b->scratch) & 15)
+        return fail(HM_EINVAL, "bins: recs and tmp must be 128-byte aligned, scratch 16-byte aligned");
+    if (b->group_bits > (uint32_t)kMaxGroupBits || b->bin_bits > (uint32_t)kMaxBinBits)
+        return fail(HM_EINVAL, "bins: group_bits must be at most %d and bin_bits at most %d", kMaxGroupBits,
+                    kMaxBinBits);
+    return HM_OK;
+}
+
+int bins_grid1(int64_t n_tiles) {
+    // three workgroups per CU: what the first-level scatter's LDS allows at once
+    int64_t cap = 3 * (int64_t)device_cus();
+    if (cap > kGrid1) cap = kGrid1;
+    return (int)(n_tiles < cap ? n_tiles : cap);
+}
+
+uint32_t *bins_hist1(const hm_bins_t *b) { return scratch_of(b).hist1; }
+
+namespace {
+// What a first-level histogram in a bins scratch was counted for, noted by hm_cardinality_bins
+// and taken (whatever the flags) by the next hm_bin_kmers on that scratch: a histogram of other
+// reads, parameters or bin counts would send the scatter's records outside their ranges.
+struct Counted {
+    const void *bases2;
+    int64_t n_reads;
+    int32_t read_len, k, forward_only;
+    uint32_t n_owners, owner, group_bits, bin_bits;
+    int device;
+    bool operator==(const Counted &o) const {
+        return bases2 == o.bases2 && n_reads == o.n_reads && read_len == o.read_len && k == o.k &&
+               forward_only == o.forward_only && n_owners == o.n_owners && owner == o.owner &&
+               group_bits == o.group_bits && bin_bits == o.bin_bits && device == o.device;
+    }
+};
+
+Counted counted_key(const hm_bins_t *b, const hm_reads_t *r, const hm_params_t *p) {
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    return Counted{r->bases2, r->n_reads, r->read_len, p->k, (p->flags & HM_FORWARD_ONLY) ? 1 : 0,
+                   p->n_owners, p->owner, b->group_bits, b->bin_bits, dev};
+}
+
+std::mutex g_counted_mu;
+std::unordered_map<const void *, Counted> g_counted;  // by scratch address
+}  // namespace
+
+void bins_note_counted(const hm_bins_t *b, const hm_reads_t *r, const hm_params_t *p) {
+    const Counted c = counted_key(b, r, p);
+    std::lock_guard<std::mutex> g(g_counted_mu);
+    g_counted[b->scratch] = c;
+}
+
+bool bins_take_counted(const hm_bins_t *b, const hm_reads_t *r, const hm_params_t *p) {
+    const Counted c = counted_key(b, r, p);
+    std::lock_guard<std::mutex> g(g_counted_mu);
+    auto it = g_counted.find(b->scratch);
+    if (it == g_counted.end()) return false;
+    const bool same = it->second == c;
+    g_counted.erase(it);
+    return same;
+}
+
 }  // namespace hm
 
 using namespace hm;
@@ -833,7 +882,8 @@ uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bi
     return bins_capacity(windows, group_bits, bin_bits, kGrid1);
 }
 
-int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStream_t s) {
+int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32_t flags, hipStream_t s) {
+    if (flags & ~HM_BINS_COUNTED) return fail(HM_EINVAL, "hm_bin_kmers: unknown flags 0x%x", flags);
     int rc = hm_check_params(p);
     if (rc) return rc;
     rc = check_reads(r, p->k);
@@ -852,14 +902,14 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStr
         return fail(HM_EINVAL, "binned counting takes fewer than 2^32 records (windows and padding) per call");
     const int32_t rpt = windows ? kTileBases / r->read_len : 1;
     const int64_t n_tiles = windows ? (r->n_reads + rpt - 1) / rpt : 0;
-    // the first level's workgroups: three per CU (what the scatter's LDS allows at once), at most kGrid1
-    int64_t g1_cap = 3 * (int64_t)device_cus();
-    if (g1_cap > kGrid1) g1_cap = kGrid1;
-    const int g1 = (int)(n_tiles < g1_cap ? n_tiles : g1_cap);
+    const int g1 = bins_grid1(n_tiles);
     if (bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1) > b->capacity)
         return fail(HM_EINVAL, "bins hold %llu records, the reads need %llu (windows and padding; see hm_bins_capacity)",
                     (unsigned long long)b->capacity,
                     (unsigned long long)bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1));
+    if (!bins_take_counted(b, r, p) && (flags & HM_BINS_COUNTED))
+        return fail(HM_EINVAL, "hm_bin_kmers: HM_BINS_COUNTED, but the last hm_cardinality_bins on these bins' scratch "
+                    "was not over the same reads, params and bin counts (or a partition has used its histogram)");
     rc = fill<uint32_t>(b->status, 1, 0u, s);
     if (rc) return rc;
     if (b->stats) {
@@ -886,7 +936,9 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, hipStr
     uint4 *recs = reinterpret_cast<uint4 *>(b->recs);
     // the combiner's arrays and the range starts (4 bytes per destination)
     const size_t lds1 = Combiner<kBlk1>::bytes(ng) + 4 * ng, lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;
-    hipLaunchKernelGGL(k_hist1, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles, sc.hist1, total_bits, bin_bits);
+    if (!(flags & HM_BINS_COUNTED))  // else hm_cardinality_bins counted the histogram on its way
+        hipLaunchKernelGGL(k_hist1, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles, sc.hist1, total_bits,
+                           bin_bits);
     hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist1, g1, (uint32_t)kBlk1, sc.gtot);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot, (int)ng, sc.gstart);
     hipLaunchKernelGGL(k_scatter1, dim3(g1), dim3(kBlock), lds1, s, a, rpt, n_tiles, sc.hist1, sc.gstart, tmp,

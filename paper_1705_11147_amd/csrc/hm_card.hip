@@ -16,7 +16,7 @@
 // samples are rare events (1 in 2^sample_log2 keys, 1 in 2^heavy_log2
 // windows) counted in small open-addressing tables with the pass-1 probe and
 // counter code.
-#include "hm_device.h"
+#include "hm_bins.h"
 
 namespace hm {
 namespace {
@@ -202,13 +202,24 @@ struct Roll {
     }
 };
 
-template <int KW>
+// The first partition level's histogram of the binned path, counted on the way (HIST): the
+// number of owned windows of each group in this workgroup's tiles, into
+// hist1[group * gridDim.x + blockIdx.x] (the layout hm_bin_kmers reads).
+struct BinHist {
+    uint32_t *hist1;
+    int total_bits, bin_bits;
+};
+
+template <int KW, bool HIST = false>
 __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile,
-                                                       int64_t n_tiles) {
+                                                       int64_t n_tiles, BinHist bh) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
-    extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers
+    extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers (then, with HIST, the group counters)
     uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
+    uint32_t *s_g = s_reg32 + ((1 << c.p) >> 2);
+    const int ng = HIST ? 1 << (bh.total_bits - bh.bin_bits) : 0;
+    for (int i = threadIdx.x; i < ng; i += kBlock) s_g[i] = 0;
     card_begin(c, s_reg32);
     uint32_t npos = 0;
     const int L = a.read_len, k = a.k;
@@ -248,10 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
                 Occ o{fwd ? x.fhi() : x.rhi(), fwd ? x.flo() : x.rlo(), 4, 4};
                 if (a.n_owners > 1 && owner_of(o.hi, o.lo, a.n_owners) != a.owner) continue;
                 card_window<KW>(c, s_reg, true, o, jg + i, npos);
+                if (HIST) atomicAdd(&s_g[bin_of(o.hi, o.lo, bh.total_bits) >> bh.bin_bits], 1u);
             }
         }
     }
-    card_end(c, s_reg, npos);
+    card_end(c, s_reg, npos);  // starts with a barrier: the group counters are complete
+    if (HIST)
+        for (int i = threadIdx.x; i < ng; i += kBlock) bh.hist1[(size_t)i * gridDim.x + blockIdx.x] = s_g[i];
 }
 
 // The same pass over fixed-length reads, also writing every owned occurrence
@@ -557,8 +571,9 @@ static int card_launch(const hm_reads_t *r, const hm_params_t *p, const hm_card_
             if (two) hipLaunchKernelGGL(k_card_fixed_occ<2>, g, dim3(kBlock), lds, s, a, ca, *out, rpt, n_tiles);
             else hipLaunchKernelGGL(k_card_fixed_occ<1>, g, dim3(kBlock), lds, s, a, ca, *out, rpt, n_tiles);
         } else {
-            if (two) hipLaunchKernelGGL(k_card_fixed<2>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
-            else hipLaunchKernelGGL(k_card_fixed<1>, g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles);
+            const BinHist none{nullptr, 0, 0};
+            if (two) hipLaunchKernelGGL((k_card_fixed<2, false>), g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles, none);
+            else hipLaunchKernelGGL((k_card_fixed<1, false>), g, dim3(kBlock), lds, s, a, ca, rpt, n_tiles, none);
         }
     } else {
         if (!r->read_off) return fail(HM_EINVAL, "reads longer than %d bases need read_off", kTileBases - 64);
@@ -583,6 +598,35 @@ int hm_cardinality(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hipS
     if (rc) return rc;
     if (r->n_reads == 0) return HM_OK;
     return card_launch(r, p, c, a, ca, nullptr, s);
+}
+
+int hm_cardinality_bins(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hm_bins_t *b, hipStream_t s) {
+    PassArgs a;
+    CardArgs ca;
+    int rc = card_setup(r, p, c, a, ca);
+    if (rc) return rc;
+    rc = check_bins(b);
+    if (rc) return rc;
+    if (r->read_off || r->read_len > kTileBases - 64)
+        return fail(HM_EINVAL, "hm_cardinality_bins needs fixed-length reads of at most %d bases", kTileBases - 64);
+    const int32_t rpt = r->read_len > 0 ? kTileBases / r->read_len : 1;
+    const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
+    const int g1 = bins_grid1(n_tiles);  // the tiles of each workgroup are those hm_bin_kmers scatters
+    const int ng = 1 << b->group_bits;
+    const size_t lds = ((size_t)1 << c->hll_p) + 4 * (size_t)ng;
+    if (lds > 65536)
+        return fail(HM_EINVAL, "hm_cardinality_bins: 2^hll_p register bytes and 4 bytes per group exceed 64 KiB "
+                    "(hll_p %d, %d groups)", c->hll_p, ng);
+    if (r->n_reads == 0 || r->read_len < p->k) {  // no windows: the partition needs no histogram
+        bins_note_counted(b, r, p);
+        return HM_OK;
+    }
+    const BinHist bh{bins_hist1(b), (int)(b->group_bits + b->bin_bits), (int)b->bin_bits};
+    if (p->k >= 32) hipLaunchKernelGGL((k_card_fixed<2, true>), dim3(g1), dim3(kBlock), lds, s, a, ca, rpt, n_tiles, bh);
+    else hipLaunchKernelGGL((k_card_fixed<1, true>), dim3(g1), dim3(kBlock), lds, s, a, ca, rpt, n_tiles, bh);
+    HM_LAUNCH_CHECK("hm_cardinality_bins");
+    bins_note_counted(b, r, p);
+    return HM_OK;
 }
 
 int hm_cardinality_occ(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c, hm_occ_t *o, hipStream_t s) {

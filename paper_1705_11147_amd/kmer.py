@@ -600,10 +600,17 @@ class CardSketch:
     def reset(self, stream=None):
         abi.call("hm_card_init", ctypes.byref(self.card), _stream(stream))
 
-    def update(self, packed: Packed, stream=None, occ: OccStream | None = None):
-        """Add a batch of reads; with `occ`, also append its owned occurrences to that stream."""
+    def update(self, packed: Packed, stream=None, occ: OccStream | None = None, bins: "BinnedCounter | None" = None):
+        """Add a batch of reads; with `occ`, also append its owned occurrences to that stream; with
+        `bins`, also count the first partition level's histogram of those bins (then call
+        bins.bin(packed, counted=True) next, with the same reads)."""
         r = packed.struct()
-        if occ is None:
+        if bins is not None:
+            if occ is not None:
+                raise ValueError("update: occ and bins are exclusive")
+            abi.call("hm_cardinality_bins", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
+                     ctypes.byref(bins.bins), _stream(stream))
+        elif occ is None:
             abi.call("hm_cardinality", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.card),
                      _stream(stream))
         else:
@@ -772,9 +779,12 @@ class BinnedCounter:
     def k(self) -> int:
         return self.params.k
 
-    def bin(self, packed: Packed, stream=None):
+    def bin(self, packed: Packed, stream=None, counted: bool = False):
+        """Partition the reads' windows into the bins; counted: CardSketch.update(packed, bins=self)
+        has just counted the first level's histogram."""
         r = packed.struct()
-        abi.call("hm_bin_kmers", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.bins), _stream(stream))
+        abi.call("hm_bin_kmers", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.bins),
+                 abi.HM_BINS_COUNTED if counted else 0, _stream(stream))
 
     def count(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
         """hm_count_bins into `out` (flags: 0 or abi.HM_EXPORT_UU_ONLY); spilled bins are left in the

@@ -79,9 +79,9 @@ def test_host_side_rejections_touch_no_device(L):
     t = abi.Table(65, 1024, 0, 21, 64, None)  # misaligned slots
     assert L.hm_table_init(ctypes.byref(t), None) == abi.HM_EINVAL
     b = abi.Bloom(64, 1000, 4)
-    assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
+    assert L.hm_bloom_init(ctypes.byref(b), 0, None) == abi.HM_EINVAL
     b = abi.Bloom(64, 1024, 9)
-    assert L.hm_bloom_init(ctypes.byref(b), None) == abi.HM_EINVAL
+    assert L.hm_bloom_init(ctypes.byref(b), 0, None) == abi.HM_EINVAL
     assert L.hm_list_init(None, None) == abi.HM_EINVAL
     t = abi.Table(64, 1024, 0, 31, 64, None)
     r = abi.Reads(8, 8, 8, None, 10, 100, 0)  # read_len 0 without offsets
@@ -164,18 +164,46 @@ def test_binned_path_rejections(L):
                      (dict(group_bits=11), "at most"), (dict(bin_bits=12), "at most"),
                      (dict(capacity=1000), "padding"), (dict(tmp=576), "aligned")):
         b = abi.Bins(**dict(good, **bad))
-        assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(b), None) == abi.HM_EINVAL
+        assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(b), 0, None) == abi.HM_EINVAL
         assert msg in abi.last_error(), (bad, abi.last_error())
     b = abi.Bins(**good)
-    assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=63)), ctypes.byref(b), None) == abi.HM_EINVAL
+    assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=63)), ctypes.byref(b), 0, None) == abi.HM_EINVAL
     assert "k <= 61" in abi.last_error()
     rv = abi.Reads(8, 8, 8, 8, 10, 1000, 0)  # read offsets: variable-length reads
-    assert L.hm_bin_kmers(ctypes.byref(rv), ctypes.byref(P(k=21)), ctypes.byref(b), None) == abi.HM_EINVAL
+    assert L.hm_bin_kmers(ctypes.byref(rv), ctypes.byref(P(k=21)), ctypes.byref(b), 0, None) == abi.HM_EINVAL
     assert "fixed-length" in abi.last_error()
     big = abi.Bins(**dict(good, capacity=1 << 40))
     rb = abi.Reads(8, 8, 8, None, 1 << 26, 150 << 26, 150)  # 2^26 reads x 130 windows >= 2^32
-    assert L.hm_bin_kmers(ctypes.byref(rb), ctypes.byref(P(k=21)), ctypes.byref(big), None) == abi.HM_EINVAL
+    assert L.hm_bin_kmers(ctypes.byref(rb), ctypes.byref(P(k=21)), ctypes.byref(big), 0, None) == abi.HM_EINVAL
     assert "2^32" in abi.last_error()
+    assert L.hm_bin_kmers(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(b), 2, None) == abi.HM_EINVAL
+    assert "flags" in abi.last_error()
+    # the card pass that counts the first level's histogram: the sketch's checks, then the bins'
+    tab = abi.Table(64, 1024, 0, 21, 64, None)
+    c = abi.Card(64, 14, 10, 8, 0, 64, tab, tab)
+    cb = abi.Bins(**dict(good, recs=None))
+    assert L.hm_cardinality_bins(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(c), ctypes.byref(cb),
+                                 None) == abi.HM_EINVAL
+    assert "NULL" in abi.last_error()
+    assert L.hm_cardinality_bins(ctypes.byref(rv), ctypes.byref(P(k=21)), ctypes.byref(c), ctypes.byref(b),
+                                 None) == abi.HM_EINVAL
+    assert "fixed-length" in abi.last_error()
+    c16 = abi.Card(64, 16, 10, 8, 0, 64, tab, tab)  # 64 KiB of registers leave no room for the groups
+    assert L.hm_cardinality_bins(ctypes.byref(r), ctypes.byref(P(k=21)), ctypes.byref(c16), ctypes.byref(b),
+                                 None) == abi.HM_EINVAL
+    assert "64 KiB" in abi.last_error()
+    # HM_BINS_COUNTED is taken only after a matching hm_cardinality_bins (noted on the host); with no
+    # reads hm_cardinality_bins launches nothing (its acceptance is a GPU test: it clears device words)
+    r0 = abi.Reads(8, 8, 8, None, 0, 0, 100)
+    assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(b), abi.HM_BINS_COUNTED,
+                          None) == abi.HM_EINVAL
+    assert "HM_BINS_COUNTED" in abi.last_error()
+    assert L.hm_cardinality_bins(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(c), ctypes.byref(b), None) == 0
+    other = abi.Bins(**dict(good, bin_bits=4, capacity=1000 + 3 * 4096))
+    assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(other), abi.HM_BINS_COUNTED,
+                          None) == abi.HM_EINVAL  # same scratch, other bin count: the note is taken and refused
+    assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(b), abi.HM_BINS_COUNTED,
+                          None) == abi.HM_EINVAL  # ... and gone
     e = abi.Export(64, 64, 64, 64, 64, 64, 64, 10, 64, None, 2, 2, None, 0)
     o = abi.Occ(64, 64, 10, 64)
     assert L.hm_count_bins(ctypes.byref(b), ctypes.byref(P(k=21)), abi.HM_EXPORT_SORTED, ctypes.byref(e),

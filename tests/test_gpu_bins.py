@@ -154,3 +154,63 @@ def test_binned_equals_table_path_mid_scale():
     tab = kmer.analyze(r.ascii, r.qual, p.k, read_len=r.read_len, qcut=p.qcut, min_depth=p.min_depth)
     assert_tables_equal(got, tab, "binned vs table path")
     assert got["spilled"] == 0
+
+
+def _bins_by_bin(bc):
+    """(bin, key_lo, key_hi | ext << 58) of every record that is not padding, sorted.  The order
+    inside a bin, and so the padding, follow the partition's schedule; which records a bin holds
+    does not."""
+    start = bc.bin_start.cpu().numpy()
+    n = int(start[-1])
+    recs = bc.recs[: 2 * n].cpu().numpy().view(np.uint64).reshape(-1, 2)
+    bin_id = np.repeat(np.arange(len(start) - 1, dtype=np.uint64), np.diff(start))
+    keep = (recs[:, 1] >> np.uint64(58)) != 63  # holes: extension field 63
+    t = np.stack([bin_id[keep], recs[keep, 0], recs[keep, 1]], axis=1)
+    return t[np.lexsort((t[:, 2], t[:, 1], t[:, 0]))]
+
+
+@pytest.mark.parametrize("k,L,kw", [(21, 100, {}), (51, 150, dict(n_owners=4, owner=1)), (31, 150, dict(forward_only=True))])
+def test_histogram_counted_by_the_cardinality_pass(k, L, kw):
+    """hm_cardinality_bins + hm_bin_kmers(HM_BINS_COUNTED) against hm_cardinality + hm_bin_kmers: every
+    bin holds the same records, the HyperLogLog registers and the sample summary are the same, and
+    the counted export equals the oracle's."""
+    print("fused histogram k=%d L=%d %r" % (k, L, kw), flush=True)
+    ascii, qual = fixed_reads(90 + k, 12000, L, 60000, 0.01)
+    dev = torch.device("cuda")
+    packed = kmer.pack_reads(torch.from_numpy(ascii).to(dev), torch.from_numpy(qual).to(dev), read_len=L)
+    P = packed.positions(k)
+    n_owners, owner = kw.get("n_owners", 1), kw.get("owner", 0)
+    fwd = kw.get("forward_only", False)
+    flags = abi.HM_FORWARD_ONLY if fwd else 0
+    got = []
+    for fused in (False, True):
+        sk = kmer.CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=fwd, device=dev)
+        bc = kmer.BinnedCounter(k, P, 3, 6, n_owners=n_owners, owner=owner, flags=flags, device=dev)
+        sk.reset()
+        sk.update(packed, bins=bc if fused else None)
+        bc.bin(packed, counted=fused)
+        sk.summarize(min_depth=2)
+        fetched = sk.fetch()
+        torch.cuda.synchronize()
+        res = sk.decode(fetched)
+        out = kmer.Records(max(1024, P), device=dev)
+        bc.count(out)
+        assert bc.finish(out) == 0
+        abi.check(bc.status(), "binned")
+        tab = out.to_numpy(sort=True)
+        got.append((_bins_by_bin(bc), sk.registers.cpu().numpy().copy(), res, tab, bc.stats()))
+    b0, reg0, c0, t0, st0 = got[0]
+    b1, reg1, c1, t1, st1 = got[1]
+    assert np.array_equal(b0, b1)
+    assert np.array_equal(reg0, reg1)
+    assert (c0.estimate, c0.sampled_distinct, c0.sampled_kept, c0.positions) == \
+        (c1.estimate, c1.sampled_distinct, c1.sampled_kept, c1.positions)
+    # keys inserted and occurrences deferred follow the order inside a bin (a Bloom false positive
+    # lets a k-mer in early); the rest does not
+    fixed = ("records", "spilled_bins", "spilled", "kept")
+    assert {x: st0[x] for x in fixed} == {x: st1[x] for x in fixed}
+    off = np.arange(ascii.size // L + 1, dtype=np.int64) * L
+    exp = oracle.run(ascii, qual, off, k, n_threads=8, sort_count=True, **kw)
+    assert_tables_equal(t1, exp, "fused histogram")
+    if n_owners == 1:
+        assert st1["records"] == valid_windows(ascii, L, k)
