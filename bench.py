@@ -359,7 +359,7 @@ def run_tiny(args, dev, log, steps=50):
 
 
 RECORD_OUT_BYTES = 54  # an exported record: key 16 + count 4 + two tally arrays 32 + two class bytes
-BIN_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_bins.h", "hm_bins.hip")]
+BIN_SOURCES = [os.path.join(ROOT, "paper_1705_11147_amd", "csrc", f) for f in ("hm_device.h", "hm_bins.h", "hm_roll.h", "hm_bins.hip")]
 
 
 def run_binned_step(args, dev, log, ascii, qual, packed, sketch, card, positions, L, p, stream, ref_digest,

@@ -496,15 +496,16 @@ typedef struct {
 } hm_bins_t;
 
 /* Scratch bytes of hm_bin_kmers and hm_count_bins: for 2^g groups and 2^(g+b) bins,
- * 2^27 + 8 * (4 * 2^g + 2) + 4096 * 2^g + 32 * 2^(g+b) bytes (the 128 MiB are where
+ * 2^27 + 8 * (2050 + 2 * 2^g) + 4096 * 2^g + 32 * 2^(g+b) bytes (the 128 MiB are where
  * hm_count_bins stages each workgroup's records before it takes their output
  * range with one atomic add); 0 if g is above 10 or b above 11. */
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits);
 
 /* Records the bins need room for (hm_bins_t.capacity) for a read set of `windows`
  * windows: the windows plus the padding that makes every destination range a
- * whole number of the 4-record (64-byte) blocks both partition levels write
- * whole, windows + 3 * max(1024 * 2^g, 8 * 2^(g+b)); 0 if g is above 10 or b
+ * whole number of the blocks the partition writes whole (8 records, 128 bytes,
+ * in the first level; 4 records, 64 bytes, in the second),
+ * windows + max(7 * 1024 * 2^g, 3 * 8 * 2^(g+b)); 0 if g is above 10 or b
  * above 11.  Padding records ("holes": extension field 63) sit at the ends of
  * ranges and are skipped. */
 uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits);

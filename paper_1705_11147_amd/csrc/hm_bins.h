@@ -22,7 +22,7 @@ __device__ __forceinline__ uint32_t bin_of(uint64_t hi, uint64_t lo, int bits) {
 // read set of n_tiles tiles (the pass that counts its histogram and the pass that scatters must
 // both use it, as they must use the same tiles), and where that histogram lives in the scratch
 int check_bins(const hm_bins_t *b);
-int bins_grid1(int64_t n_tiles);
+int bins_grid1(int64_t n_tiles, uint32_t group_bits);
 uint32_t *bins_hist1(const hm_bins_t *b);
 // hm_cardinality_bins notes what it counted the histogram for; every hm_bin_kmers takes the note
 // and, with HM_BINS_COUNTED, accepts only a note of the same reads, params and bin counts

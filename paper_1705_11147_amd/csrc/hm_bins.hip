@@ -27,6 +27,7 @@
 #include <unordered_map>
 
 #include "hm_bins.h"
+#include "hm_roll.h"
 
 namespace hm {
 namespace {
@@ -39,7 +40,7 @@ constexpr int kSlices = 8;         // workgroups per group in the second partiti
 constexpr int kMaxGroupBits = 10;  // LDS of the first-level scatter's combiner
 constexpr int kMaxBinBits = 11;    // LDS of the second-level scatter's combiner
 #ifndef HM_BIN_BLK1
-#define HM_BIN_BLK1 4
+#define HM_BIN_BLK1 8
 #endif
 #ifndef HM_BIN_BLK2
 #define HM_BIN_BLK2 4
@@ -48,9 +49,14 @@ constexpr int kBlk1 = HM_BIN_BLK1;  // records per written block, first level
 constexpr int kBlk2 = HM_BIN_BLK2;  // records per written block, second level
 constexpr int kT2 = 1024;           // threads of a second-level workgroup
 #ifndef HM_BIN_FLUSH1
-#define HM_BIN_FLUSH1 4
+#define HM_BIN_FLUSH1 1024
 #endif
-constexpr int kFlush1 = HM_BIN_FLUSH1;  // first level: rounds of windows between flushes
+#ifndef HM_BIN_T1
+#define HM_BIN_T1 512
+#endif
+constexpr int kT1 = HM_BIN_T1;               // threads of a first-level scatter workgroup
+constexpr int kFlush1 = HM_BIN_FLUSH1 / kT1;  // first level: rounds between flushes (HM_BIN_FLUSH1 windows)
+static_assert(kFlush1 >= 1, "flush at most once a round");
 constexpr int kBinSlots = 512;     // LDS table of one bin
 constexpr int kBloomWords = 512;   // 32-bit filter words: 16384 bits per bin
 constexpr int kDeferCap = 2048;    // deferred occurrences of one bin
@@ -177,8 +183,79 @@ struct Combiner {
     }
 };
 
-// Level-1 histogram: counts of each group's windows in this workgroup's tiles (the tiles
-// fixed_windows hands a workgroup depend only on the grid, which the scatter pass repeats).
+// Every window of the fixed-length reads of this workgroup's tiles (tile = blockIdx.x, then
+// every gridDim.x-th: they depend only on the grid), a run of kCardRun windows per lane, handed
+// to op(act, occurrence) in rounds the whole workgroup takes together: round i gives every lane
+// its run's window i, act false where the window holds an invalid base, is past the read's last
+// window or has another owner.  The key is the canonical one, with the extensions pass 1 takes.
+template <int KW, int NT, class Op>
+__device__ __forceinline__ void fixed_runs(const PassArgs &a, int32_t reads_per_tile, int64_t n_tiles, uint64_t *s_b2,
+                                           uint64_t *s_nm, uint64_t *s_hq, Op &&op) {
+    const int L = a.read_len, k = a.k;
+    const int W = L - k + 1;  // > 0, checked by the host
+    const int runs = (W + kCardRun - 1) / kCardRun;
+    const typename Roll<KW>::Shape sh = Roll<KW>::shape(k);
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t r0 = tile * reads_per_tile;
+        const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
+        const int64_t org = (r0 * L) & ~(int64_t)63;
+        const int64_t mw0 = org >> 6;
+        const int nmw = (int)((((r1 * L) + 63) >> 6) - mw0) + 2;  // incl. 2 guard words
+        __syncthreads();  // the previous tile's readers are done
+        for (int i = threadIdx.x; i < nmw; i += NT) {
+            s_nm[i] = a.nm[mw0 + i];
+            s_hq[i] = a.hq[mw0 + i];
+        }
+        for (int i = threadIdx.x; i < 2 * nmw; i += NT) s_b2[i] = a.b2[2 * mw0 + i];
+        __syncthreads();
+        const Words w{s_b2, s_nm, s_hq};
+        const int total = (int)(r1 - r0) * runs;
+        for (int g0 = 0; g0 < total; g0 += NT) {  // workgroup-uniform
+            const int g = g0 + (int)threadIdx.x;
+            int cnt = 0;
+            int64_t j0 = 0, rb = 0;
+            uint32_t vm = 0;
+            RunBits bits;
+            RunExt ext;
+            Roll<KW> x;
+            if (g < total) {
+                const int r = g / runs;
+                const int p0 = (g - r * runs) * kCardRun;
+                cnt = min(kCardRun, W - p0);
+                rb = (r0 + r) * L - org;
+                j0 = rb + p0;
+                bits.load(w, j0, k);
+                vm = bits.valid_mask(k, cnt);
+                ext.load(w, j0, k);
+                const U128 f = w.window(j0, k);
+                x.set(f, revcomp(f, k));
+            }
+#pragma unroll 1
+            for (int i = 0; i < kCardRun; ++i) {  // round i
+                Occ o{0, 0, 4, 4};
+                bool act = false;
+                if (i < cnt) {
+                    if (i > 0) x.step((uint32_t)bits.base(i), sh);
+                    if ((vm >> i) & 1u) {
+                        const bool fwd = a.forward_only || x.forward();
+                        int left, right;
+                        ext.fwd_ext(bits, i, j0, rb, rb + L, k, left, right);
+                        o.hi = fwd ? x.fhi() : x.rhi();
+                        o.lo = fwd ? x.flo() : x.rlo();
+                        o.left = fwd ? left : (right < 4 ? 3 - right : 4);
+                        o.right = fwd ? right : (left < 4 ? 3 - left : 4);
+                        act = a.n_owners <= 1 || owner_of(o.hi, o.lo, a.n_owners) == a.owner;
+                    }
+                }
+                op(act, o);
+            }
+        }
+    }
+}
+
+// Level-1 histogram: counts of each group's windows in this workgroup's tiles (the same tiles
+// and windows as the scatter pass with the same grid), into hist1[blockIdx.x * groups + group].
+template <int KW>
 __global__ __launch_bounds__(kBlock) void k_hist1(PassArgs a, int32_t rpt, int64_t n_tiles, uint32_t *hist1,
                                                   int total_bits, int bin_bits) {
     __shared__ uint64_t s_b2[kTileB2Words];
@@ -187,11 +264,11 @@ __global__ __launch_bounds__(kBlock) void k_hist1(PassArgs a, int32_t rpt, int64
     extern __shared__ uint32_t s_h[];
     const int ng = 1 << (total_bits - bin_bits);
     for (int i = threadIdx.x; i < ng; i += kBlock) s_h[i] = 0;
-    fixed_windows<false>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
+    fixed_runs<KW, kBlock>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o) {
         if (act) atomicAdd(&s_h[bin_of(o.hi, o.lo, total_bits) >> bin_bits], 1u);
     });
     __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += kBlock) hist1[(size_t)i * gridDim.x + blockIdx.x] = s_h[i];
+    for (int i = threadIdx.x; i < ng; i += kBlock) hist1[(size_t)blockIdx.x * ng + i] = s_h[i];
 }
 
 // Exclusive prefix sum, in place, of each row of x (rows x cols, one workgroup per row) over
@@ -221,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t *x, int cols, uin
     if (tot && threadIdx.x == kBlock - 1) tot[blockIdx.x] = s_part[kBlock - 1];
 }
 
-// start[g] = sum of tot[0..g), g = 0..n (one workgroup, n <= 2^kMaxGroupBits)
+// start[i] = sum of tot[0..i), i = 0..n (one workgroup; n: groups or first-level workgroups)
 __global__ __launch_bounds__(kBlock) void k_scan_totals(const uint64_t *tot, int n, uint64_t *start) {
     __shared__ uint64_t s_part[kBlock];
     const int per = (n + kBlock - 1) / kBlock;
@@ -244,27 +321,33 @@ __global__ __launch_bounds__(kBlock) void k_scan_totals(const uint64_t *tot, int
     if (threadIdx.x == kBlock - 1) start[n] = s_part[kBlock - 1];
 }
 
-// Level-1 scatter: the same windows as k_hist1, each placed in its group's range at this
-// workgroup's offset, through a combiner per group.
-__global__ __launch_bounds__(kBlock) void k_scatter1(PassArgs a, int32_t rpt, int64_t n_tiles, const uint32_t *rel1,
-                                                     const uint64_t *gstart, uint4 *tmp, int total_bits,
-                                                     int bin_bits) {
+// Level-1 scatter: the same windows as k_hist1, through a combiner per group, into this
+// workgroup's own region of tmp (from wstart[blockIdx.x]), where each group has a piece at the
+// offset rel1[blockIdx.x * groups + group].  One region a workgroup keeps the pages its stores
+// touch few: with a range per group spread over the whole buffer, nearly every store missed the
+// address translation cache.
+template <int KW>
+__global__ __launch_bounds__(kT1) void k_scatter1(PassArgs a, int32_t rpt, int64_t n_tiles, const uint32_t *rel1,
+                                                  const uint64_t *wstart, uint4 *tmp, int total_bits, int bin_bits) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     __shared__ uint64_t s_hq[kTileMaskWords];
     extern __shared__ uint4 s_dyn[];
     const int ng = 1 << (total_bits - bin_bits);
     Combiner<kBlk1> cb;
-    uint32_t *s_rel = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ng));
-    for (int i = threadIdx.x; i < ng; i += kBlock) {
-        s_rel[i] = rel1[(size_t)i * gridDim.x + blockIdx.x];
+    // each group's piece (below 2^32 records, checked by the host), in LDS so that the put path
+    // makes no global load
+    uint32_t *s_at = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ng));
+    const uint64_t region = wstart[blockIdx.x];
+    for (int i = threadIdx.x; i < ng; i += kT1) {
+        s_at[i] = (uint32_t)(region + rel1[(size_t)blockIdx.x * ng + i]);
         cb.fill[i] = cb.done[i] = 0;
         cb.bits[i] = 0;
     }
     if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
-    auto at = [&](uint32_t g) { return tmp + gstart[g] + s_rel[g]; };
+    auto at = [&](uint32_t g) { return tmp + s_at[g]; };
     uint32_t par = 0, round = 0;
-    fixed_windows<false>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o, int64_t) {
+    fixed_runs<KW, kT1>(a, rpt, n_tiles, s_b2, s_nm, s_hq, [&](bool act, const Occ &o) {
         if (act) {
             const uint32_t g = bin_of(o.hi, o.lo, total_bits) >> bin_bits;
             cb.put(g, rec_pack(o), at(g), par);
@@ -272,34 +355,78 @@ __global__ __launch_bounds__(kBlock) void k_scatter1(PassArgs a, int32_t rpt, in
         if (++round == (uint32_t)kFlush1) {  // workgroup-uniform
             round = 0;
             __syncthreads();
-            cb.flush_ready(threadIdx.x, kBlock, at, par);
+            cb.flush_ready(threadIdx.x, kT1, at, par);
             __syncthreads();
             par ^= 1;
         }
     });
     __syncthreads();
-    cb.flush_ready(threadIdx.x, kBlock, at, par);  // blocks completed since the last flush
+    cb.flush_ready(threadIdx.x, kT1, at, par);  // blocks completed since the last flush
     __syncthreads();
-    for (int g = threadIdx.x; g < ng; g += kBlock) cb.flush_tail(g, at(g));
+    for (int g = threadIdx.x; g < ng; g += kT1) cb.flush_tail(g, at(g));
+}
+
+// The second level's input: group g's records lie in pieces, one per first-level workgroup w,
+// from wstart[w] + rel1[w * ng + g] to the next group's piece (the workgroup's region's end for
+// the last group).  Second-level workgroup (g, slice) takes the pieces of first-level workgroups
+// [slice * g1 / kSlices, (slice + 1) * g1 / kSlices) as one run of positions: vs[j] is where piece
+// j starts in the run (vs[n] its length), ad[j] where it starts in tmp.  Returns the length.
+constexpr int kMaxPieces = (kGrid1 + kSlices - 1) / kSlices;
+
+__device__ uint32_t load_pieces(const uint32_t *rel1, const uint64_t *wstart, int ng, int g1, uint32_t g,
+                                uint32_t sl, uint32_t *vs, uint32_t *ad, int &n) {
+    const int w0 = (int)(sl * (uint32_t)g1 / kSlices), w1 = (int)((sl + 1) * (uint32_t)g1 / kSlices);
+    n = w1 - w0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int w = w0 + j;
+        const uint64_t b = wstart[w] + rel1[(size_t)w * ng + g];
+        const uint64_t e = g + 1 < (uint32_t)ng ? wstart[w] + rel1[(size_t)w * ng + g + 1] : wstart[w + 1];
+        ad[j] = (uint32_t)b;  // below 2^32 records (checked by the host)
+        vs[j] = (uint32_t)(e - b);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // at most kMaxPieces lengths
+        uint32_t run = 0;
+        for (int j = 0; j < n; ++j) {
+            const uint32_t len = vs[j];
+            vs[j] = run;
+            run += len;
+        }
+        vs[n] = run;
+    }
+    __syncthreads();
+    return vs[n];
+}
+
+// tmp index of position v (< the run's length) of the run of pieces: the last piece starting at
+// or before v (a non-empty one)
+__device__ __forceinline__ uint32_t piece_at(const uint32_t *vs, const uint32_t *ad, int n, uint32_t v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vs[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return ad[lo] + (v - vs[lo]);
 }
 
 // Level-2 histogram: workgroup (g, slice) counts the bins of its slice of group g's records.
-__global__ __launch_bounds__(kBlock) void k_hist2(const uint4 *tmp, const uint64_t *gstart, uint32_t *hist2,
-                                                  int total_bits, int bin_bits) {
+__global__ __launch_bounds__(kBlock) void k_hist2(const uint4 *tmp, const uint32_t *rel1, const uint64_t *wstart,
+                                                  int g1, uint32_t *hist2, int total_bits, int bin_bits) {
     extern __shared__ uint32_t s_h[];
-    const int ns = 1 << bin_bits;
+    __shared__ uint32_t s_vs[kMaxPieces + 1], s_ad[kMaxPieces];
+    const int ns = 1 << bin_bits, ng = 1 << (total_bits - bin_bits);
     const uint32_t g = blockIdx.x / kSlices, sl = blockIdx.x % kSlices;
     for (int i = threadIdx.x; i < ns; i += kBlock) s_h[i] = 0;
-    __syncthreads();
-    const uint64_t g0 = gstart[g], len = gstart[g + 1] - g0;
-    const uint64_t b = g0 + len * sl / kSlices, e = g0 + len * (sl + 1) / kSlices;
+    int n;
+    const uint32_t len = load_pieces(rel1, wstart, ng, g1, g, sl, s_vs, s_ad, n);  // starts with a barrier
     const uint32_t mask = (uint32_t)ns - 1;
-    for (uint64_t i0 = b; i0 < e; i0 += kChunk) {
+    for (uint32_t v0 = 0; v0 < len; v0 += kChunk) {
         uint4 r[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            const uint64_t i = i0 + j * kBlock + threadIdx.x;
-            r[j] = i < e ? tmp[i] : hole_rec();
+            const uint32_t v = v0 + j * kBlock + threadIdx.x;
+            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v)] : hole_rec();
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
@@ -325,10 +452,12 @@ __global__ __launch_bounds__(kBlock) void k_bin_starts(const uint32_t *rel2, con
 
 // Level-2 scatter: workgroup (g, slice) rereads its slice and places each record in its bin's
 // range at the slice's offset, through a combiner per bin.
-__global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint64_t *gstart, const uint64_t *gstart2,
-                                                  const uint32_t *rel2, uint4 *recs, int total_bits, int bin_bits) {
+__global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint32_t *rel1, const uint64_t *wstart, int g1,
+                                                  const uint64_t *gstart2, const uint32_t *rel2, uint4 *recs,
+                                                  int total_bits, int bin_bits) {
     extern __shared__ uint4 s_dyn[];
-    const int ns = 1 << bin_bits;
+    __shared__ uint32_t s_vs[kMaxPieces + 1], s_ad[kMaxPieces];
+    const int ns = 1 << bin_bits, ng = 1 << (total_bits - bin_bits);
     const uint32_t g = blockIdx.x / kSlices, sl = blockIdx.x % kSlices;
     Combiner<kBlk2> cb;
     uint32_t *s_rel = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ns));
@@ -338,19 +467,18 @@ __global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint64
         cb.bits[i] = 0;
     }
     if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
-    __syncthreads();
+    int n;
+    const uint32_t len = load_pieces(rel1, wstart, ng, g1, g, sl, s_vs, s_ad, n);  // starts with a barrier
     uint32_t par = 0;
     uint4 *base = recs + gstart2[g];
     auto at = [&](uint32_t d) { return base + s_rel[d]; };
-    const uint64_t g0 = gstart[g], len = gstart[g + 1] - g0;
-    const uint64_t b = g0 + len * sl / kSlices, e = g0 + len * (sl + 1) / kSlices;
     const uint32_t mask = (uint32_t)ns - 1;
-    for (uint64_t i0 = b; i0 < e; i0 += 2 * kT2) {
+    for (uint32_t v0 = 0; v0 < len; v0 += 2 * kT2) {
         uint4 r[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const uint64_t i = i0 + j * kT2 + threadIdx.x;
-            r[j] = i < e ? tmp[i] : hole_rec();
+            const uint32_t v = v0 + j * kT2 + threadIdx.x;
+            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v)] : hole_rec();
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -775,7 +903,7 @@ constexpr uint64_t kStageBytes = (uint64_t)kCountGrid * kStage * 64;
 
 struct Scratch {
     uint4 *stage;
-    uint64_t *gstart, *gtot, *gstart2, *gtot2;
+    uint64_t *wstart, *wtot, *gstart2, *gtot2;
     uint32_t *hist1, *hist2;
 };
 
@@ -783,9 +911,9 @@ Scratch scratch_of(const hm_bins_t *b) {
     const uint64_t ng = 1ull << b->group_bits;
     Scratch s;
     s.stage = reinterpret_cast<uint4 *>(b->scratch);
-    s.gstart = b->scratch + kStageBytes / 8;
-    s.gtot = s.gstart + ng + 1;
-    s.gstart2 = s.gtot + ng;
+    s.wstart = b->scratch + kStageBytes / 8;
+    s.wtot = s.wstart + kGrid1 + 1;
+    s.gstart2 = s.wtot + kGrid1;
     s.gtot2 = s.gstart2 + ng + 1;
     s.hist1 = reinterpret_cast<uint32_t *>(s.gtot2 + ng);
     s.hist2 = s.hist1 + ng * kGrid1;
@@ -793,6 +921,11 @@ Scratch scratch_of(const hm_bins_t *b) {
 }
 
 // records hm_bin_kmers needs room for: the windows plus the padding of both levels' ranges
+// dynamic LDS of the first-level scatter for ng groups: the combiner and the range starts
+size_t scatter1_lds(size_t ng) { return Combiner<kBlk1>::bytes(ng) + 4 * ng; }
+constexpr size_t kScatter1StaticLds = 8 * (kTileB2Words + 2 * kTileMaskWords);  // the staged tile
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 uint64_t bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits, uint64_t g1) {
     const uint64_t ng = 1ull << group_bits, nb = 1ull << (group_bits + bin_bits);
     const uint64_t pad1 = (uint64_t)(kBlk1 - 1) * g1 * ng, pad2 = (uint64_t)(kBlk2 - 1) * nb * kSlices;
@@ -812,9 +945,11 @@ int check_bins(const hm_bins_t *b) {
     return HM_OK;
 }
 
-int bins_grid1(int64_t n_tiles) {
-    // three workgroups per CU: what the first-level scatter's LDS allows at once
-    int64_t cap = 3 * (int64_t)device_cus();
+int bins_grid1(int64_t n_tiles, uint32_t group_bits) {
+    // as many workgroups as the first-level scatter's LDS lets a CU hold at once
+    const size_t per_wg = scatter1_lds((size_t)1 << group_bits) + kScatter1StaticLds;
+    const int64_t per_cu = (int64_t)(kLdsPerCu / per_wg);
+    int64_t cap = (per_cu > 0 ? per_cu : 1) * (int64_t)device_cus();
     if (cap > kGrid1) cap = kGrid1;
     return (int)(n_tiles < cap ? n_tiles : cap);
 }
@@ -874,7 +1009,7 @@ extern "C" {
 size_t hm_bins_scratch_bytes(uint32_t group_bits, uint32_t bin_bits) {
     if (group_bits > (uint32_t)kMaxGroupBits || bin_bits > (uint32_t)kMaxBinBits) return 0;
     const uint64_t ng = 1ull << group_bits, nb = 1ull << (group_bits + bin_bits);
-    return (size_t)(kStageBytes + 8 * (4 * ng + 2) + 4 * ng * kGrid1 + 4 * nb * kSlices);
+    return (size_t)(kStageBytes + 8 * (2 * kGrid1 + 2 * ng + 2) + 4 * ng * kGrid1 + 4 * nb * kSlices);
 }
 
 uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bits) {
@@ -902,7 +1037,7 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32
         return fail(HM_EINVAL, "binned counting takes fewer than 2^32 records (windows and padding) per call");
     const int32_t rpt = windows ? kTileBases / r->read_len : 1;
     const int64_t n_tiles = windows ? (r->n_reads + rpt - 1) / rpt : 0;
-    const int g1 = bins_grid1(n_tiles);
+    const int g1 = bins_grid1(n_tiles, b->group_bits);
     if (bins_capacity(windows, b->group_bits, b->bin_bits, (uint64_t)g1) > b->capacity)
         return fail(HM_EINVAL, "bins hold %llu records, the reads need %llu (windows and padding; see hm_bins_capacity)",
                     (unsigned long long)b->capacity,
@@ -934,24 +1069,28 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32
     a.status = b->status;
     uint4 *tmp = reinterpret_cast<uint4 *>(b->tmp);
     uint4 *recs = reinterpret_cast<uint4 *>(b->recs);
-    // the combiner's arrays and the range starts (4 bytes per destination)
-    const size_t lds1 = Combiner<kBlk1>::bytes(ng) + 4 * ng, lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;
+    // the combiner's arrays and the range starts (4 bytes a destination)
+    const size_t lds1 = scatter1_lds(ng), lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;
+    const bool two = p->k >= 32;  // keys of two 64-bit words
     if (!(flags & HM_BINS_COUNTED))  // else hm_cardinality_bins counted the histogram on its way
-        hipLaunchKernelGGL(k_hist1, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles, sc.hist1, total_bits,
-                           bin_bits);
-    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist1, g1, (uint32_t)kBlk1, sc.gtot);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot, (int)ng, sc.gstart);
-    hipLaunchKernelGGL(k_scatter1, dim3(g1), dim3(kBlock), lds1, s, a, rpt, n_tiles, sc.hist1, sc.gstart, tmp,
-                       total_bits, bin_bits);
+        hipLaunchKernelGGL(two ? k_hist1<2> : k_hist1<1>, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles,
+                           sc.hist1, total_bits, bin_bits);
+    // the first level's regions: each workgroup's pieces (a row of hist1), then the regions
+    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)g1), dim3(kBlock), 0, s, sc.hist1, (int)ng, (uint32_t)kBlk1,
+                       sc.wtot);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.wtot, g1, sc.wstart);
+    hipLaunchKernelGGL(two ? k_scatter1<2> : k_scatter1<1>, dim3(g1), dim3(kT1), lds1, s, a, rpt, n_tiles,
+                       sc.hist1, sc.wstart, tmp, total_bits, bin_bits);
     const dim3 g2((unsigned)(ng * kSlices));
-    hipLaunchKernelGGL(k_hist2, g2, dim3(kBlock), ns * 4, s, tmp, sc.gstart, sc.hist2, total_bits, bin_bits);
+    hipLaunchKernelGGL(k_hist2, g2, dim3(kBlock), ns * 4, s, tmp, sc.hist1, sc.wstart, g1, sc.hist2, total_bits,
+                       bin_bits);
     hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist2, (int)(ns * kSlices),
                        (uint32_t)kBlk2, sc.gtot2);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot2, (int)ng, sc.gstart2);
     hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)grid_for(n_bins + 1, 16)), dim3(kBlock), 0, s, sc.hist2,
                        sc.gstart2, b->bin_start, total_bits, bin_bits);
-    hipLaunchKernelGGL(k_scatter2, g2, dim3(kT2), lds2, s, tmp, sc.gstart, sc.gstart2, sc.hist2, recs, total_bits,
-                       bin_bits);
+    hipLaunchKernelGGL(k_scatter2, g2, dim3(kT2), lds2, s, tmp, sc.hist1, sc.wstart, g1, sc.gstart2, sc.hist2, recs,
+                       total_bits, bin_bits);
     HM_LAUNCH_CHECK("hm_bin_kmers");
     return HM_OK;
 }

@@ -17,6 +17,7 @@
 // windows) counted in small open-addressing tables with the pass-1 probe and
 // counter code.
 #include "hm_bins.h"
+#include "hm_roll.h"
 
 namespace hm {
 namespace {
@@ -99,112 +100,13 @@ __device__ __forceinline__ void card_end(const CardArgs &c, const uint8_t *s_reg
     if (lane_id() == 0 && x) atomicAdd(c.positions, (unsigned long long)x);
 }
 
-// Fixed-length reads, tiles staged in LDS as in pass 1, but each lane takes a
-// run of kCardRun consecutive windows of one read: the first window's code
-// and reverse complement are extracted from the packed words, and each next
-// window is rolled in from one more base (shift the forward code left and
-// append the base, shift the reverse complement right and insert the
-// complemented base on top).  The extensions are not needed here.
-constexpr int kCardRun = 8;
-
-// What a run of kCardRun windows starting at base j0 (relative to the tile
-// origin) reads besides its first window, in registers: the invalid-base bits
-// from j0 on (128 bits, first base most significant), which cover every
-// window of the run since kCardRun - 1 + k <= 70, and the 7 bases the run
-// rolls in (j0 + k .. j0 + k + 6).  Two loads of mask words and two of base
-// words per run instead of an LDS round trip per window.
-struct RunBits {
-    uint64_t m0, m1;  // invalid-base bits of bases j0 .. j0 + 127
-    uint64_t in;      // bases j0 + k .. j0 + k + 31, first base most significant
-    __device__ __forceinline__ void load(const Words &w, int64_t j0, int k) {
-        const int64_t i = j0 >> 6;
-        const int s = (int)(j0 & 63);
-        const uint64_t a = w.nm[i], b = w.nm[i + 1], c = w.nm[i + 2];
-        m0 = s ? (a << s) | (b >> (64 - s)) : a;
-        m1 = s ? (b << s) | (c >> (64 - s)) : b;
-        const int64_t p = 2 * (j0 + k);
-        const int64_t q = p >> 6;
-        const int t = (int)(p & 63);
-        const uint64_t x = w.b2[q], y = w.b2[q + 1];
-        in = t ? (x << t) | (y >> (64 - t)) : x;
-    }
-    // window j0 + i (0 <= i < kCardRun) holds no invalid base
-    __device__ __forceinline__ bool valid(int i, int k) const {
-        const uint64_t m = i ? (m0 << i) | (m1 >> (64 - i)) : m0;
-        return (m >> (64 - k)) == 0;
-    }
-    // bit i (i < cnt) set: window j0 + i holds no invalid base.  One test covers the run's
-    // k + kCardRun - 1 bases; only a run that holds an invalid base tests its windows one by one.
-    __device__ __forceinline__ uint32_t valid_mask(int k, int cnt) const {
-        const uint32_t live = (1u << cnt) - 1u;
-        const int span = k + kCardRun - 1;  // <= 70
-        const bool clean = span <= 64 ? (m0 >> (64 - span)) == 0 : (m0 == 0 && (m1 >> (128 - span)) == 0);
-        if (clean) return live;
-        uint32_t v = 0;
-        for (int i = 0; i < kCardRun; ++i) v |= valid(i, k) ? 1u << i : 0u;
-        return v & live;
-    }
-    // the base window j0 + i (1 <= i < kCardRun) rolls in: base j0 + i + k - 1
-    __device__ __forceinline__ uint64_t base(int i) const { return (in >> (64 - 2 * i)) & 3; }
-};
-
-// The forward code and the reverse complement of a window in 2 * KW words of 32 bits (word 0
-// least significant), moved on by one base with funnel shifts: the forward code shifts left and
-// takes the base at the bottom, the reverse complement shifts right and takes the complemented
-// base at bit 2k - 2.  The masks and the word and shift of bit 2k - 2 are the same for every
-// lane (set once per launch).
-template <int KW>
-struct Roll {
-    static constexpr int N = 2 * KW;
-    uint32_t f[N], r[N];
-    struct Shape {
-        uint32_t m_top, m_next;  // masks of the two top words of the forward code
-        int ts;                  // bit 2k - 2 within the two top words (it always lies there)
-    };
-    __device__ static Shape shape(int k) {
-        const int kb = 2 * k;
-        Shape s;
-        const int lo_bits = kb - 32 * (N - 2);  // bits in the two top words (KW = 1: the only two)
-        s.m_next = lo_bits >= 32 ? ~0u : (1u << lo_bits) - 1u;
-        s.m_top = lo_bits > 32 ? (lo_bits >= 64 ? ~0u : (1u << (lo_bits - 32)) - 1u) : 0u;
-        s.ts = kb - 2 - 32 * (N - 2);
-        return s;
-    }
-    __device__ __forceinline__ void set(U128 x, U128 y) {
-        f[0] = (uint32_t)x.lo, f[1] = (uint32_t)(x.lo >> 32);
-        r[0] = (uint32_t)y.lo, r[1] = (uint32_t)(y.lo >> 32);
-        if (KW == 2) {
-            f[2] = (uint32_t)x.hi, f[3] = (uint32_t)(x.hi >> 32);
-            r[2] = (uint32_t)y.hi, r[3] = (uint32_t)(y.hi >> 32);
-        }
-    }
-    __device__ __forceinline__ void step(uint32_t b, const Shape &s) {
-#pragma unroll
-        for (int i = N - 1; i > 0; --i) f[i] = __builtin_amdgcn_alignbit(f[i], f[i - 1], 30);
-        f[0] = (f[0] << 2) | b;
-        f[N - 1] &= s.m_top;
-        f[N - 2] &= s.m_next;
-#pragma unroll
-        for (int i = 0; i < N - 1; ++i) r[i] = __builtin_amdgcn_alignbit(r[i + 1], r[i], 2);
-        r[N - 1] >>= 2;
-        const uint64_t c = (uint64_t)(b ^ 3u) << s.ts;
-        r[N - 2] |= (uint32_t)c;
-        r[N - 1] |= (uint32_t)(c >> 32);
-    }
-    __device__ __forceinline__ uint64_t fhi() const { return KW == 2 ? ((uint64_t)f[3] << 32) | f[2] : 0; }
-    __device__ __forceinline__ uint64_t flo() const { return ((uint64_t)f[1] << 32) | f[0]; }
-    __device__ __forceinline__ uint64_t rhi() const { return KW == 2 ? ((uint64_t)r[3] << 32) | r[2] : 0; }
-    __device__ __forceinline__ uint64_t rlo() const { return ((uint64_t)r[1] << 32) | r[0]; }
-    // the forward code is the canonical key (it is not larger than the reverse complement)
-    __device__ __forceinline__ bool forward() const {
-        const uint64_t a = fhi(), c = rhi();
-        return a < c || (a == c && flo() <= rlo());
-    }
-};
+// Fixed-length reads, tiles staged in LDS as in pass 1, but each lane takes a run of kCardRun
+// consecutive windows of one read, rolled from one window to the next (Roll, RunBits); the
+// extensions are not needed here.
 
 // The first partition level's histogram of the binned path, counted on the way (HIST): the
 // number of owned windows of each group in this workgroup's tiles, into
-// hist1[group * gridDim.x + blockIdx.x] (the layout hm_bin_kmers reads).
+// hist1[blockIdx.x * groups + group] (the layout hm_bin_kmers reads).
 struct BinHist {
     uint32_t *hist1;
     int total_bits, bin_bits;
@@ -265,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
     }
     card_end(c, s_reg, npos);  // starts with a barrier: the group counters are complete
     if (HIST)
-        for (int i = threadIdx.x; i < ng; i += kBlock) bh.hist1[(size_t)i * gridDim.x + blockIdx.x] = s_g[i];
+        for (int i = threadIdx.x; i < ng; i += kBlock) bh.hist1[(size_t)blockIdx.x * ng + i] = s_g[i];
 }
 
 // The same pass over fixed-length reads, also writing every owned occurrence
@@ -611,7 +513,7 @@ int hm_cardinality_bins(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c,
         return fail(HM_EINVAL, "hm_cardinality_bins needs fixed-length reads of at most %d bases", kTileBases - 64);
     const int32_t rpt = r->read_len > 0 ? kTileBases / r->read_len : 1;
     const int64_t n_tiles = (r->n_reads + rpt - 1) / rpt;
-    const int g1 = bins_grid1(n_tiles);  // the tiles of each workgroup are those hm_bin_kmers scatters
+    const int g1 = bins_grid1(n_tiles, b->group_bits);  // the tiles of each workgroup are those hm_bin_kmers scatters
     const int ng = 1 << b->group_bits;
     const size_t lds = ((size_t)1 << c->hll_p) + 4 * (size_t)ng;
     if (lds > 65536)

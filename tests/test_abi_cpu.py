@@ -149,15 +149,16 @@ def test_occ_stream_rejections(L):
 def test_binned_path_rejections(L):
     """The binned path's entry points check their arguments on the host: scratch sizes follow the
     formula in the header, and bad bins, reads, k or flags return HM_EINVAL before any launch."""
-    assert L.hm_bins_scratch_bytes(0, 0) == (1 << 27) + 8 * 6 + 4096 + 32
-    assert L.hm_bins_scratch_bytes(9, 10) == (1 << 27) + 8 * (4 * 512 + 2) + 4096 * 512 + 32 * (1 << 19)
+    assert L.hm_bins_scratch_bytes(0, 0) == (1 << 27) + 8 * (2050 + 2) + 4096 + 32
+    assert L.hm_bins_scratch_bytes(9, 10) == (1 << 27) + 8 * (2050 + 2 * 512) + 4096 * 512 + 32 * (1 << 19)
     assert L.hm_bins_scratch_bytes(11, 0) == 0 and L.hm_bins_scratch_bytes(0, 12) == 0
     assert L.hm_bins_scratch_bytes(0, 11) > 0
-    # capacity: the windows plus 3 padding records per range of either level, whichever is more
-    assert L.hm_bins_capacity(1000, 2, 3) == 1000 + 3 * max(1024 * 4, 8 * 32)
+    # capacity: the windows plus the padding of every range of either level (7 records a range in the
+    # first, 3 in the second), whichever is more
+    assert L.hm_bins_capacity(1000, 2, 3) == 1000 + max(7 * 1024 * 4, 3 * 8 * 32)
     assert L.hm_bins_capacity(10 ** 9, 9, 11) == 10 ** 9 + 3 * 8 * (1 << 20)
     assert L.hm_bins_capacity(5, 11, 0) == 0 and L.hm_bins_capacity(5, 0, 12) == 0
-    good = dict(recs=256, tmp=512, capacity=1000 + 3 * 4096, group_bits=2, bin_bits=3, scratch=1024, bin_start=2048,
+    good = dict(recs=256, tmp=512, capacity=1000 + 7 * 4096, group_bits=2, bin_bits=3, scratch=1024, bin_start=2048,
                 status=4096, stats=None)
     r = abi.Reads(8, 8, 8, None, 10, 1000, 100)
     for bad, msg in ((dict(recs=None), "NULL"), (dict(status=None), "NULL"), (dict(recs=264), "aligned"), (dict(scratch=1032), "aligned"),
@@ -199,7 +200,7 @@ def test_binned_path_rejections(L):
                           None) == abi.HM_EINVAL
     assert "HM_BINS_COUNTED" in abi.last_error()
     assert L.hm_cardinality_bins(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(c), ctypes.byref(b), None) == 0
-    other = abi.Bins(**dict(good, bin_bits=4, capacity=1000 + 3 * 4096))
+    other = abi.Bins(**dict(good, bin_bits=4))
     assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(other), abi.HM_BINS_COUNTED,
                           None) == abi.HM_EINVAL  # same scratch, other bin count: the note is taken and refused
     assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(b), abi.HM_BINS_COUNTED,
