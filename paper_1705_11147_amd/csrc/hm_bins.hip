@@ -58,8 +58,14 @@ constexpr int kT1 = HM_BIN_T1;               // threads of a first-level scatter
 constexpr int kFlush1 = HM_BIN_FLUSH1 / kT1;  // first level: rounds between flushes (HM_BIN_FLUSH1 windows)
 static_assert(kFlush1 >= 1, "flush at most once a round");
 constexpr int kBinSlots = 512;     // LDS table of one bin
-constexpr int kBloomWords = 512;   // 32-bit filter words: 16384 bits per bin
-constexpr int kDeferCap = 2048;    // deferred occurrences of one bin
+#ifndef HM_BIN_BLOOM_WORDS
+#define HM_BIN_BLOOM_WORDS 512
+#endif
+#ifndef HM_BIN_DEFER_CAP
+#define HM_BIN_DEFER_CAP 2048
+#endif
+constexpr int kBloomWords = HM_BIN_BLOOM_WORDS;  // 32-bit filter words: 16384 bits per bin
+constexpr int kDeferCap = HM_BIN_DEFER_CAP;  // deferred occurrences of one bin
 constexpr int kPer = 4;            // records per thread per round (second-level histogram)
 constexpr int kChunk = kPer * kBlock;
 #ifndef HM_BIN_COUNT_PER
@@ -70,7 +76,10 @@ constexpr int kCChunk = kCPer * kBlock;
 constexpr uint32_t kMaxKeys = kBinSlots * 3 / 4;
 constexpr int kExtShift = 58;
 constexpr int kMaxBinK = 61;       // 2k + 6 extension bits fit in 128
-constexpr int kCountBlocksPerCu = 4;
+#ifndef HM_BIN_COUNT_PER_CU
+#define HM_BIN_COUNT_PER_CU 4
+#endif
+constexpr int kCountBlocksPerCu = HM_BIN_COUNT_PER_CU;
 static_assert(kBinSlots == 2 * kBlock, "the export takes two slots a thread");
 
 
@@ -499,7 +508,10 @@ __global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint32
 // ------------------------------------------------------------------ counting in LDS
 
 constexpr int kStage = 2048;               // records a workgroup stages before it takes an output range
-constexpr int kCountGrid = 1024;           // most workgroups of hm_count_bins (one staging area each)
+#ifndef HM_BIN_COUNT_GRID
+#define HM_BIN_COUNT_GRID 1024
+#endif
+constexpr int kCountGrid = HM_BIN_COUNT_GRID;  // most workgroups of hm_count_bins (one staging area each)
 constexpr uint64_t kClaimed = 1ull << 62;  // LDS key word: key_hi | kClaimed, then | kReady (key_hi < 2^58)
 constexpr uint64_t kReady = 1ull << 63;
 constexpr uint32_t kLdsSpin = 1u << 20;    // bound on waiting for another wave's claim to be published

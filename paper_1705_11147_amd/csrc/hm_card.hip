@@ -26,6 +26,7 @@ constexpr uint64_t kCardSeed = 0xB7E151628AED2A6Aull;  // cardinality hash (defi
 constexpr uint64_t kPosSeed = 0x452821E638D01377ull;   // window sampling hash (definition constant)
 constexpr int kCardBlocksPerCu = 4;
 constexpr int kCardMaxP = 16;
+constexpr int kCardHistBlock = 512;  // threads of the pass that also counts the partition's histogram
 
 struct CardArgs {
     uint32_t *regs;
@@ -85,13 +86,13 @@ __device__ __forceinline__ void card_window(const CardArgs &c, uint8_t *s_reg, b
 }
 
 __device__ __forceinline__ void card_begin(const CardArgs &c, uint32_t *s_reg32) {
-    for (int i = threadIdx.x; i < (1 << c.p) / 4; i += kBlock) s_reg32[i] = 0;
+    for (int i = threadIdx.x; i < (1 << c.p) / 4; i += blockDim.x) s_reg32[i] = 0;
     __syncthreads();
 }
 
 __device__ __forceinline__ void card_end(const CardArgs &c, const uint8_t *s_reg, uint32_t npos) {
     __syncthreads();
-    for (int i = threadIdx.x; i < (1 << c.p); i += kBlock) {
+    for (int i = threadIdx.x; i < (1 << c.p); i += blockDim.x) {
         const uint32_t v = s_reg[i];
         if (v > c.regs[i]) atomicMax(c.regs + i, v);  // the plain read only skips needless atomics
     }
@@ -112,16 +113,16 @@ struct BinHist {
     int total_bits, bin_bits;
 };
 
-template <int KW, bool HIST = false>
-__global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile,
-                                                       int64_t n_tiles, BinHist bh) {
+template <int KW, bool HIST = false, int NT = kBlock>
+__global__ __launch_bounds__(NT) void k_card_fixed(PassArgs a, CardArgs c, int32_t reads_per_tile, int64_t n_tiles,
+                                                   BinHist bh) {
     __shared__ uint64_t s_b2[kTileB2Words];
     __shared__ uint64_t s_nm[kTileMaskWords];
     extern __shared__ uint32_t s_reg32[];  // 2^p bytes of registers (then, with HIST, the group counters)
     uint8_t *s_reg = reinterpret_cast<uint8_t *>(s_reg32);
     uint32_t *s_g = s_reg32 + ((1 << c.p) >> 2);
     const int ng = HIST ? 1 << (bh.total_bits - bh.bin_bits) : 0;
-    for (int i = threadIdx.x; i < ng; i += kBlock) s_g[i] = 0;
+    for (int i = threadIdx.x; i < ng; i += NT) s_g[i] = 0;
     card_begin(c, s_reg32);
     uint32_t npos = 0;
     const int L = a.read_len, k = a.k;
@@ -135,12 +136,12 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
         const int64_t mw0 = org >> 6;
         const int nmw = (int)((((r1 * L) + 63) >> 6) - mw0) + 2;
         __syncthreads();
-        for (int i = threadIdx.x; i < nmw; i += kBlock) s_nm[i] = a.nm[mw0 + i];
-        for (int i = threadIdx.x; i < 2 * nmw; i += kBlock) s_b2[i] = a.b2[2 * mw0 + i];
+        for (int i = threadIdx.x; i < nmw; i += NT) s_nm[i] = a.nm[mw0 + i];
+        for (int i = threadIdx.x; i < 2 * nmw; i += NT) s_b2[i] = a.b2[2 * mw0 + i];
         __syncthreads();
         const Words w{s_b2, s_nm, nullptr};
         const int total = (int)(r1 - r0) * runs;
-        for (int g = threadIdx.x; g < total; g += kBlock) {
+        for (int g = threadIdx.x; g < total; g += NT) {
             const int r = g / runs;
             const int p0 = (g - r * runs) * kCardRun;
             const int cnt = min(kCardRun, W - p0);
@@ -167,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed(PassArgs a, CardArgs c, i
     }
     card_end(c, s_reg, npos);  // starts with a barrier: the group counters are complete
     if (HIST)
-        for (int i = threadIdx.x; i < ng; i += kBlock) bh.hist1[(size_t)blockIdx.x * ng + i] = s_g[i];
+        for (int i = threadIdx.x; i < ng; i += NT) bh.hist1[(size_t)blockIdx.x * ng + i] = s_g[i];
 }
 
 // The same pass over fixed-length reads, also writing every owned occurrence
@@ -524,8 +525,13 @@ int hm_cardinality_bins(const hm_reads_t *r, const hm_params_t *p, hm_card_t *c,
         return HM_OK;
     }
     const BinHist bh{bins_hist1(b), (int)(b->group_bits + b->bin_bits), (int)b->bin_bits};
-    if (p->k >= 32) hipLaunchKernelGGL((k_card_fixed<2, true>), dim3(g1), dim3(kBlock), lds, s, a, ca, rpt, n_tiles, bh);
-    else hipLaunchKernelGGL((k_card_fixed<1, true>), dim3(g1), dim3(kBlock), lds, s, a, ca, rpt, n_tiles, bh);
+    // the partition's grid is small (a few workgroups a CU): larger workgroups keep the CUs busy
+    if (p->k >= 32)
+        hipLaunchKernelGGL((k_card_fixed<2, true, kCardHistBlock>), dim3(g1), dim3(kCardHistBlock), lds, s, a, ca, rpt,
+                           n_tiles, bh);
+    else
+        hipLaunchKernelGGL((k_card_fixed<1, true, kCardHistBlock>), dim3(g1), dim3(kCardHistBlock), lds, s, a, ca, rpt,
+                           n_tiles, bh);
     HM_LAUNCH_CHECK("hm_cardinality_bins");
     bins_note_counted(b, r, p);
     return HM_OK;
