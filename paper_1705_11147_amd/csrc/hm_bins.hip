@@ -407,16 +407,12 @@ __device__ uint32_t load_pieces(const uint32_t *rel1, const uint64_t *wstart, in
     return vs[n];
 }
 
-// tmp index of position v (< the run's length) of the run of pieces: the last piece starting at
-// or before v (a non-empty one)
-__device__ __forceinline__ uint32_t piece_at(const uint32_t *vs, const uint32_t *ad, int n, uint32_t v) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (vs[mid] <= v) lo = mid;
-        else hi = mid - 1;
-    }
-    return ad[lo] + (v - vs[lo]);
+// tmp index of position v (< the run's length) of the run of pieces, in the last piece starting at
+// or before v (a non-empty one).  A thread asks for increasing positions, so its piece index p
+// (start it at 0) only moves forward, past empty pieces too.
+__device__ __forceinline__ uint32_t piece_at(const uint32_t *vs, const uint32_t *ad, int n, uint32_t v, int &p) {
+    while (p + 1 < n && vs[p + 1] <= v) ++p;
+    return ad[p] + (v - vs[p]);
 }
 
 // Level-2 histogram: workgroup (g, slice) counts the bins of its slice of group g's records.
@@ -430,12 +426,13 @@ __global__ __launch_bounds__(kBlock) void k_hist2(const uint4 *tmp, const uint32
     int n;
     const uint32_t len = load_pieces(rel1, wstart, ng, g1, g, sl, s_vs, s_ad, n);  // starts with a barrier
     const uint32_t mask = (uint32_t)ns - 1;
+    int pc = 0;  // this thread's piece
     for (uint32_t v0 = 0; v0 < len; v0 += kChunk) {
         uint4 r[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const uint32_t v = v0 + j * kBlock + threadIdx.x;
-            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v)] : hole_rec();
+            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v, pc)] : hole_rec();
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
@@ -482,12 +479,13 @@ __global__ __launch_bounds__(kT2) void k_scatter2(const uint4 *tmp, const uint32
     uint4 *base = recs + gstart2[g];
     auto at = [&](uint32_t d) { return base + s_rel[d]; };
     const uint32_t mask = (uint32_t)ns - 1;
+    int pc = 0;  // this thread's piece
     for (uint32_t v0 = 0; v0 < len; v0 += 2 * kT2) {
         uint4 r[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const uint32_t v = v0 + j * kT2 + threadIdx.x;
-            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v)] : hole_rec();
+            r[j] = v < len ? tmp[piece_at(s_vs, s_ad, n, v, pc)] : hole_rec();
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
