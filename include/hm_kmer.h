@@ -526,6 +526,17 @@ uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bi
 #define HM_BINS_COUNTED 1u
 int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32_t flags, hipStream_t stream);
 
+/* hm_bin_kmers over an owned-occurrence stream (hm_cardinality_occ's output:
+ * one owner's share of a sharded run, section "Parallel k-mer analysis")
+ * instead of over the reads: every entry of `o` but its holes becomes a
+ * record in its bin, as hm_bin_kmers would place it; hm_count_bins and
+ * hm_export_merge follow as after hm_bin_kmers.  The stream must be whole (its
+ * count not past its capacity; an overflowed stream's dropped entries are not
+ * there).  b->capacity: at least hm_bins_capacity(o->capacity, ...).
+ * HM_EINVAL (nothing launched) for k > 61, bins too small for the stream's
+ * capacity, or a capacity of 2^32 or more records with the padding. */
+int hm_bin_occ(const hm_occ_t *o, const hm_params_t *p, hm_bins_t *b, hipStream_t stream);
+
 /* hm_cardinality (section "Parallel k-mer analysis": the HyperLogLog pass that
  * sizes the filters), also counting, for each workgroup of hm_bin_kmers' first
  * level, how many owned windows of each group its tiles hold: the histogram

@@ -169,6 +169,7 @@ SIGNATURES = {
     "hm_bins_capacity": ([ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32], ctypes.c_uint64),
     "hm_bin_kmers": ([P(Reads), P(Params), P(Bins), ctypes.c_uint32, vp], ctypes.c_int),
     "hm_cardinality_bins": ([P(Reads), P(Params), P(Card), P(Bins), vp], ctypes.c_int),
+    "hm_bin_occ": ([P(Occ), P(Params), P(Bins), vp], ctypes.c_int),
     "hm_count_bins": ([P(Bins), P(Params), ctypes.c_uint32, P(Export), P(Occ), vp], ctypes.c_int),
     "hm_export_merge": ([P(Export), P(Export), vp, vp], ctypes.c_int),
     "hm_contigs_work_bytes": ([ctypes.c_uint64], ctypes.c_size_t),

@@ -28,5 +28,6 @@ uint32_t *bins_hist1(const hm_bins_t *b);
 // and, with HM_BINS_COUNTED, accepts only a note of the same reads, params and bin counts
 void bins_note_counted(const hm_bins_t *b, const hm_reads_t *r, const hm_params_t *p);
 bool bins_take_counted(const hm_bins_t *b, const hm_reads_t *r, const hm_params_t *p);
+void bins_drop_counted(const hm_bins_t *b);  // a partition that does not use the note drops it
 
 }  // namespace hm

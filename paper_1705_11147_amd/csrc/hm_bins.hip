@@ -375,6 +375,89 @@ __global__ __launch_bounds__(kT1) void k_scatter1(PassArgs a, int32_t rpt, int64
     for (int g = threadIdx.x; g < ng; g += kT1) cb.flush_tail(g, at(g));
 }
 
+// The first level over an occurrence stream (hm_occ_t: the owned occurrences a cardinality pass
+// wrote) instead of over the reads: workgroup w takes the entries [w * per, (w + 1) * per) of the
+// n = min(count, capacity) reserved ones, per = ceil(n / gridDim.x), NT a round, and hands each
+// to op(act, record); holes (ext 0xFF) and positions past the chunk come with act false.  The
+// histogram pass and the scatter pass use the same grid, so they see the same chunks.
+template <int NT, class Op>
+__device__ __forceinline__ void occ_rounds(const hm_occ_t &o, Op &&op) {
+    const uint64_t n = min(*o.count, o.capacity);
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b = min(n, (uint64_t)blockIdx.x * per), e = min(n, b + per);
+    const uint4 *keys = reinterpret_cast<const uint4 *>(o.keys);
+    for (uint64_t i0 = b; i0 < e; i0 += NT) {  // workgroup-uniform
+        const uint64_t i = i0 + threadIdx.x;
+        uint4 rec = make_uint4(0, 0, 0, 0);
+        bool act = false;
+        if (i < e) {
+            const uint32_t x = o.ext[i];
+            if (x != kHole) {
+                const uint4 kk = keys[i];  // key_hi, key_lo as four 32-bit words
+                const uint32_t ext = (x & 15u) | ((x >> 4) << 3);
+                rec = make_uint4(kk.z, kk.w, kk.x, kk.y | (ext << (kExtShift - 32)));
+                act = true;
+            }
+        }
+        op(act, rec);
+    }
+}
+
+__device__ __forceinline__ uint32_t rec_bin(uint4 r, int total_bits) {
+    const uint64_t lo = ((uint64_t)r.y << 32) | r.x;
+    const uint64_t hi = (((uint64_t)r.w << 32) | r.z) & ((1ull << kExtShift) - 1);
+    return bin_of(hi, lo, total_bits);
+}
+
+// Level-1 histogram over a stream: hist1[blockIdx.x * groups + group].
+__global__ __launch_bounds__(kBlock) void k_hist1_occ(hm_occ_t o, uint32_t *hist1, int total_bits, int bin_bits) {
+    extern __shared__ uint32_t s_h[];
+    const int ng = 1 << (total_bits - bin_bits);
+    for (int i = threadIdx.x; i < ng; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+    occ_rounds<kBlock>(o, [&](bool act, uint4 r) {
+        if (act) atomicAdd(&s_h[rec_bin(r, total_bits) >> bin_bits], 1u);
+    });
+    __syncthreads();
+    for (int i = threadIdx.x; i < ng; i += kBlock) hist1[(size_t)blockIdx.x * ng + i] = s_h[i];
+}
+
+// Level-1 scatter over a stream: as k_scatter1, from the workgroup's chunk of entries.
+__global__ __launch_bounds__(kT1) void k_scatter1_occ(hm_occ_t o, const uint32_t *rel1, const uint64_t *wstart,
+                                                      uint4 *tmp, int total_bits, int bin_bits) {
+    extern __shared__ uint4 s_dyn[];
+    const int ng = 1 << (total_bits - bin_bits);
+    Combiner<kBlk1> cb;
+    uint32_t *s_at = reinterpret_cast<uint32_t *>(cb.carve(s_dyn, ng));
+    const uint64_t region = wstart[blockIdx.x];
+    for (int i = threadIdx.x; i < ng; i += kT1) {
+        s_at[i] = (uint32_t)(region + rel1[(size_t)blockIdx.x * ng + i]);
+        cb.fill[i] = cb.done[i] = 0;
+        cb.bits[i] = 0;
+    }
+    if (threadIdx.x < 2) cb.n_ready[threadIdx.x] = 0;
+    __syncthreads();
+    auto at = [&](uint32_t g) { return tmp + s_at[g]; };
+    uint32_t par = 0, round = 0;
+    occ_rounds<kT1>(o, [&](bool act, uint4 r) {
+        if (act) {
+            const uint32_t g = rec_bin(r, total_bits) >> bin_bits;
+            cb.put(g, r, at(g), par);
+        }
+        if (++round == (uint32_t)kFlush1) {  // workgroup-uniform
+            round = 0;
+            __syncthreads();
+            cb.flush_ready(threadIdx.x, kT1, at, par);
+            __syncthreads();
+            par ^= 1;
+        }
+    });
+    __syncthreads();
+    cb.flush_ready(threadIdx.x, kT1, at, par);
+    __syncthreads();
+    for (int g = threadIdx.x; g < ng; g += kT1) cb.flush_tail(g, at(g));
+}
+
 // The second level's input: group g's records lie in pieces, one per first-level workgroup w,
 // from wstart[w] + rel1[w * ng + g] to the next group's piece (the workgroup's region's end for
 // the last group).  Second-level workgroup (g, slice) takes the pieces of first-level workgroups
@@ -1010,6 +1093,11 @@ bool bins_take_counted(const hm_bins_t *b, const hm_reads_t *r, const hm_params_
     return same;
 }
 
+void bins_drop_counted(const hm_bins_t *b) {
+    std::lock_guard<std::mutex> g(g_counted_mu);
+    g_counted.erase(b->scratch);
+}
+
 }  // namespace hm
 
 using namespace hm;
@@ -1027,6 +1115,33 @@ uint64_t hm_bins_capacity(uint64_t windows, uint32_t group_bits, uint32_t bin_bi
     return bins_capacity(windows, group_bits, bin_bits, kGrid1);
 }
 
+namespace {
+// the first level's regions: each workgroup's pieces (a row of hist1, rounded up to blocks), then
+// the regions one after the other
+void level1_regions(const Scratch &sc, int g1, int ng, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)g1), dim3(kBlock), 0, s, sc.hist1, ng, (uint32_t)kBlk1, sc.wtot);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.wtot, g1, sc.wstart);
+}
+
+// the second level, from the first level's pieces in b->tmp to the bins in b->recs
+void level2(const hm_bins_t *b, const Scratch &sc, int g1, int total_bits, int bin_bits, hipStream_t s) {
+    const uint64_t ng = 1ull << (total_bits - bin_bits), ns = 1ull << bin_bits, n_bins = 1ull << total_bits;
+    const uint4 *tmp = reinterpret_cast<const uint4 *>(b->tmp);
+    uint4 *recs = reinterpret_cast<uint4 *>(b->recs);
+    const size_t lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;  // the combiner and the range starts
+    const dim3 g2((unsigned)(ng * kSlices));
+    hipLaunchKernelGGL(k_hist2, g2, dim3(kBlock), ns * 4, s, tmp, sc.hist1, sc.wstart, g1, sc.hist2, total_bits,
+                       bin_bits);
+    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist2, (int)(ns * kSlices),
+                       (uint32_t)kBlk2, sc.gtot2);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot2, (int)ng, sc.gstart2);
+    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)grid_for(n_bins + 1, 16)), dim3(kBlock), 0, s, sc.hist2,
+                       sc.gstart2, b->bin_start, total_bits, bin_bits);
+    hipLaunchKernelGGL(k_scatter2, g2, dim3(kT2), lds2, s, tmp, sc.hist1, sc.wstart, g1, sc.gstart2, sc.hist2, recs,
+                       total_bits, bin_bits);
+}
+}  // namespace
+
 int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32_t flags, hipStream_t s) {
     if (flags & ~HM_BINS_COUNTED) return fail(HM_EINVAL, "hm_bin_kmers: unknown flags 0x%x", flags);
     int rc = hm_check_params(p);
@@ -1040,7 +1155,7 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32
     if (r->n_reads > 0 && r->read_len > kTileBases - 64)
         return fail(HM_EINVAL, "binned counting needs reads of at most %d bases", kTileBases - 64);
     const int total_bits = (int)(b->group_bits + b->bin_bits), bin_bits = (int)b->bin_bits;
-    const uint64_t ng = 1ull << b->group_bits, ns = 1ull << b->bin_bits, n_bins = 1ull << total_bits;
+    const uint64_t ng = 1ull << b->group_bits, n_bins = 1ull << total_bits;
     const int64_t W = r->n_reads > 0 ? (int64_t)r->read_len - p->k + 1 : 0;
     const uint64_t windows = W > 0 ? (uint64_t)r->n_reads * (uint64_t)W : 0;
     if (bins_capacity(windows, b->group_bits, b->bin_bits, kGrid1) >= (1ull << 32))
@@ -1078,30 +1193,53 @@ int hm_bin_kmers(const hm_reads_t *r, const hm_params_t *p, hm_bins_t *b, uint32
     a.seed = p->seed;
     a.status = b->status;
     uint4 *tmp = reinterpret_cast<uint4 *>(b->tmp);
-    uint4 *recs = reinterpret_cast<uint4 *>(b->recs);
-    // the combiner's arrays and the range starts (4 bytes a destination)
-    const size_t lds1 = scatter1_lds(ng), lds2 = Combiner<kBlk2>::bytes(ns) + 4 * ns;
-    const bool two = p->k >= 32;  // keys of two 64-bit words
+    const size_t lds1 = scatter1_lds(ng);  // the combiner's arrays and the range starts
+    const bool two = p->k >= 32;           // keys of two 64-bit words
     if (!(flags & HM_BINS_COUNTED))  // else hm_cardinality_bins counted the histogram on its way
         hipLaunchKernelGGL(two ? k_hist1<2> : k_hist1<1>, dim3(g1), dim3(kBlock), ng * 4, s, a, rpt, n_tiles,
                            sc.hist1, total_bits, bin_bits);
-    // the first level's regions: each workgroup's pieces (a row of hist1), then the regions
-    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)g1), dim3(kBlock), 0, s, sc.hist1, (int)ng, (uint32_t)kBlk1,
-                       sc.wtot);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.wtot, g1, sc.wstart);
+    level1_regions(sc, g1, (int)ng, s);
     hipLaunchKernelGGL(two ? k_scatter1<2> : k_scatter1<1>, dim3(g1), dim3(kT1), lds1, s, a, rpt, n_tiles,
                        sc.hist1, sc.wstart, tmp, total_bits, bin_bits);
-    const dim3 g2((unsigned)(ng * kSlices));
-    hipLaunchKernelGGL(k_hist2, g2, dim3(kBlock), ns * 4, s, tmp, sc.hist1, sc.wstart, g1, sc.hist2, total_bits,
-                       bin_bits);
-    hipLaunchKernelGGL(k_scan_rows, dim3((unsigned)ng), dim3(kBlock), 0, s, sc.hist2, (int)(ns * kSlices),
-                       (uint32_t)kBlk2, sc.gtot2);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, s, sc.gtot2, (int)ng, sc.gstart2);
-    hipLaunchKernelGGL(k_bin_starts, dim3((unsigned)grid_for(n_bins + 1, 16)), dim3(kBlock), 0, s, sc.hist2,
-                       sc.gstart2, b->bin_start, total_bits, bin_bits);
-    hipLaunchKernelGGL(k_scatter2, g2, dim3(kT2), lds2, s, tmp, sc.hist1, sc.wstart, g1, sc.gstart2, sc.hist2, recs,
-                       total_bits, bin_bits);
+    level2(b, sc, g1, total_bits, bin_bits, s);
     HM_LAUNCH_CHECK("hm_bin_kmers");
+    return HM_OK;
+}
+
+int hm_bin_occ(const hm_occ_t *o, const hm_params_t *p, hm_bins_t *b, hipStream_t s) {
+    int rc = hm_check_params(p);
+    if (rc) return rc;
+    rc = check_occ(o);
+    if (rc) return rc;
+    rc = check_bins(b);
+    if (rc) return rc;
+    if (p->k > kMaxBinK) return fail(HM_EINVAL, "binned counting needs k <= %d (k=%d)", kMaxBinK, p->k);
+    const int total_bits = (int)(b->group_bits + b->bin_bits), bin_bits = (int)b->bin_bits;
+    const uint64_t ng = 1ull << b->group_bits, n_bins = 1ull << total_bits;
+    // the stream's entries are at most its capacity; the grid is the one the first level's LDS allows
+    if (bins_capacity(o->capacity, b->group_bits, b->bin_bits, kGrid1) >= (1ull << 32))
+        return fail(HM_EINVAL, "binned counting takes fewer than 2^32 records (stream capacity and padding) per call");
+    const int g1 = bins_grid1(kGrid1, b->group_bits);
+    if (bins_capacity(o->capacity, b->group_bits, b->bin_bits, (uint64_t)g1) > b->capacity)
+        return fail(HM_EINVAL, "bins hold %llu records, a stream of %llu entries needs %llu (see hm_bins_capacity)",
+                    (unsigned long long)b->capacity, (unsigned long long)o->capacity,
+                    (unsigned long long)bins_capacity(o->capacity, b->group_bits, b->bin_bits, (uint64_t)g1));
+    bins_drop_counted(b);  // a histogram noted for these bins is not this partition's
+    rc = fill<uint32_t>(b->status, 1, 0u, s);
+    if (rc) return rc;
+    if (b->stats) {
+        rc = fill<uint64_t>(b->stats, HM_N_BIN_STATS, 0ull, s);
+        if (rc) return rc;
+    }
+    if (o->capacity == 0) return fill<uint64_t>(b->bin_start, n_bins + 1, 0ull, s);
+    const Scratch sc = scratch_of(b);
+    uint4 *tmp = reinterpret_cast<uint4 *>(b->tmp);
+    hipLaunchKernelGGL(k_hist1_occ, dim3(g1), dim3(kBlock), ng * 4, s, *o, sc.hist1, total_bits, bin_bits);
+    level1_regions(sc, g1, (int)ng, s);
+    hipLaunchKernelGGL(k_scatter1_occ, dim3(g1), dim3(kT1), scatter1_lds(ng), s, *o, sc.hist1, sc.wstart, tmp,
+                       total_bits, bin_bits);
+    level2(b, sc, g1, total_bits, bin_bits, s);
+    HM_LAUNCH_CHECK("hm_bin_occ");
     return HM_OK;
 }
 

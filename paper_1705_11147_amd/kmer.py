@@ -786,6 +786,12 @@ class BinnedCounter:
         abi.call("hm_bin_kmers", ctypes.byref(r), ctypes.byref(self.params), ctypes.byref(self.bins),
                  abi.HM_BINS_COUNTED if counted else 0, _stream(stream))
 
+    def bin_occ(self, occ: OccStream, stream=None):
+        """Partition an owned-occurrence stream (CardSketch.update(..., occ=stream)) into the bins,
+        in place of the reads: build the counter with windows = occ.capacity."""
+        abi.call("hm_bin_occ", ctypes.byref(occ.occ), ctypes.byref(self.params), ctypes.byref(self.bins),
+                 _stream(stream))
+
     def count(self, out: Records, flags: int = 0, stream=None, digest: bool = True):
         """hm_count_bins into `out` (flags: 0 or abi.HM_EXPORT_UU_ONLY); spilled bins are left in the
         spill stream (see finish)."""

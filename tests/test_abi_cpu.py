@@ -205,6 +205,18 @@ def test_binned_path_rejections(L):
                           None) == abi.HM_EINVAL  # same scratch, other bin count: the note is taken and refused
     assert L.hm_bin_kmers(ctypes.byref(r0), ctypes.byref(P(k=21)), ctypes.byref(b), abi.HM_BINS_COUNTED,
                           None) == abi.HM_EINVAL  # ... and gone
+    # partition of a stream: the stream's checks, k, and room for the stream's capacity, before any launch
+    so = abi.Occ(64, 64, 1000, 64)
+    assert L.hm_bin_occ(ctypes.byref(abi.Occ(64, 64, 10, None)), ctypes.byref(P(k=21)), ctypes.byref(b),
+                        None) == abi.HM_EINVAL
+    assert L.hm_bin_occ(ctypes.byref(so), ctypes.byref(P(k=63)), ctypes.byref(b), None) == abi.HM_EINVAL
+    assert "k <= 61" in abi.last_error()
+    assert L.hm_bin_occ(ctypes.byref(abi.Occ(64, 64, 5000, 64)), ctypes.byref(P(k=21)), ctypes.byref(b),
+                        None) == abi.HM_EINVAL  # 5000 entries and their padding do not fit 1000 + 7 * 4096
+    assert "stream" in abi.last_error()
+    assert L.hm_bin_occ(ctypes.byref(abi.Occ(64, 64, 1 << 32, 64)), ctypes.byref(P(k=21)), ctypes.byref(big),
+                        None) == abi.HM_EINVAL
+    assert "2^32" in abi.last_error()
     e = abi.Export(64, 64, 64, 64, 64, 64, 64, 10, 64, None, 2, 2, None, 0)
     o = abi.Occ(64, 64, 10, 64)
     assert L.hm_count_bins(ctypes.byref(b), ctypes.byref(P(k=21)), abi.HM_EXPORT_SORTED, ctypes.byref(e),

@@ -214,3 +214,54 @@ def test_histogram_counted_by_the_cardinality_pass(k, L, kw):
     assert_tables_equal(t1, exp, "fused histogram")
     if n_owners == 1:
         assert st1["records"] == valid_windows(ascii, L, k)
+
+
+def _stream_run(ascii, qual, L, k, batches, n_owners, owner, bin_bits=None):
+    """The owner's occurrences written to a stream by the cardinality pass (one launch a batch, so
+    the stream has holes), partitioned from the stream and counted in bins."""
+    dev = torch.device("cuda")
+    n = ascii.size // L
+    cuts = np.linspace(0, n, batches + 1).astype(np.int64)
+    packs = [kmer.pack_reads(torch.from_numpy(ascii[a * L:b * L].copy()).to(dev),
+                             torch.from_numpy(qual[a * L:b * L].copy()).to(dev), read_len=L)
+             for a, b in zip(cuts[:-1], cuts[1:])]
+    P = n * (L - k + 1)
+    sk = kmer.CardSketch(k, P, n_owners=n_owners, owner=owner, device=dev)
+    occ = kmer.OccStream.for_windows(P, n_owners, batches, device=dev)
+    card = sk.run(packs, min_depth=2, occ=occ)
+    assert not occ.overflowed()
+    g, b = bin_bits if bin_bits is not None else kmer.plan_bins(card.distinct_hi(), card.kept_hi(), False)
+    bc = kmer.BinnedCounter(k, occ.capacity, g, b, n_owners=n_owners, owner=owner, device=dev)
+    out = kmer.Records(max(1024, P // max(n_owners, 1)), device=dev)
+    bc.bin_occ(occ)
+    bc.count(out)
+    spilled = bc.finish(out)
+    abi.check(bc.status(), "binned from a stream")
+    res = out.to_numpy(sort=True)
+    res["digest"] = out.digest_words()
+    return res, spilled, bc.stats(), card
+
+
+@pytest.mark.parametrize("k,L,batches,n_owners,owner", [(21, 100, 2, 4, 1), (51, 150, 3, 3, 2), (31, 150, 1, 1, 0)])
+def test_binned_from_occurrence_stream(k, L, batches, n_owners, owner):
+    """hm_cardinality_occ writes one owner's occurrences, hm_bin_occ partitions the stream and
+    hm_count_bins counts it: the oracle's table of that owner, record by record."""
+    print("stream k=%d L=%d batches=%d owner %d of %d" % (k, L, batches, owner, n_owners), flush=True)
+    ascii, qual = fixed_reads(95 + k, 12000, L, 60000, 0.01)
+    got, spilled, st, card = _stream_run(ascii, qual, L, k, batches, n_owners, owner)
+    off = np.arange(ascii.size // L + 1, dtype=np.int64) * L
+    exp = oracle.run(ascii, qual, off, k, n_threads=8, sort_count=True, n_owners=n_owners, owner=owner)
+    assert_tables_equal(got, exp, "stream k=%d" % k)
+    assert got["digest"] == table_digest(exp)
+    assert st["records"] == card.positions  # every owned occurrence, none of the holes
+
+
+def test_binned_from_stream_spills():
+    """One bin for the whole stream: it spills and the table path counts it from the spill stream."""
+    ascii, qual = fixed_reads(97, 4000, 100, 20000, 0.01)
+    got, spilled, st, card = _stream_run(ascii, qual, 100, 21, 2, 2, 1, bin_bits=(0, 0))
+    off = np.arange(ascii.size // 100 + 1, dtype=np.int64) * 100
+    exp = oracle.run(ascii, qual, off, 21, n_threads=8, sort_count=True, n_owners=2, owner=1)
+    assert_tables_equal(got, exp, "stream spill")
+    # the spill stream holds the bin's range, padding included; its records are the owned occurrences
+    assert st["spilled_bins"] == 1 and st["spilled"] == card.positions and spilled >= card.positions
