@@ -702,10 +702,20 @@ def run_human_share(args, dev) -> dict:
                          "occurrences counted (sort-counted, %d threads, %.1fs); %s" % (
                              1 << sub_bits, scanned, sub_owned, threads, acc.seconds, cpu_model()),
                "scanned_windows_per_s": round(scanned / acc.seconds, 1)}
+    table_slots = kc.capacity
+    binned = None
+    if occ is not None and not args.no_binned_share and k <= 61:
+        del kc, out  # the binned structures take the table's place in HBM
+        torch.cuda.empty_cache()
+        try:
+            binned = run_binned_share(args, dev, packs, sketch, occ, card, p, k, digests[0], n_rec, owned)
+        except torch.cuda.OutOfMemoryError as e:  # reported, not fatal: the table path's figures stand
+            binned = {"error": "out of device memory: %s" % str(e).splitlines()[0]}
+        torch.cuda.empty_cache()
     g = LINE
     s_seen = 1.0 - st["deferred"] / max(owned, 1)
     bpp = (1.0 + s_seen) * 2 * g + g
-    return {
+    rec = {
         "metric": "owned k-mers/s k-mer analysis, one GPU's share of the human-scale run (bit-exact)",
         "value": round(owned / (step_ms / 1000), 1), "unit": "k-mers/s", "steps": n_steps, "warmup": 1,
         "ms_per_step": round(step_ms, 3),
@@ -713,7 +723,7 @@ def run_human_share(args, dev) -> dict:
                    "n_owners": p.n_owners, "owner": p.owner, "batches": len(packs),
                    "scanned_positions": scanned, "owned_positions": owned,
                    "scanned_positions_per_s": round(scanned / (step_ms / 1000), 1),
-                   "kept_kmers": n_rec, "table_slots": kc.capacity, "list_capacity": list_cap,
+                   "kept_kmers": n_rec, "table_slots": table_slots, "list_capacity": list_cap,
                    "occ_stream_entries": occ.capacity if occ else 0, "hll_estimate": round(card.estimate, 1),
                    "step": "cardinality pass writing the owned occurrences + init + pass 1 over them + pass 2 + "
                            "classify/export; packed reads resident in HBM" if occ else
@@ -730,6 +740,85 @@ def run_human_share(args, dev) -> dict:
         "cpu_baseline": cpu,
         "events_per_owned_position": {x: round(v / max(owned, 1), 4) for x, v in st.items()},
     }
+    if binned is None or "error" in binned:
+        rec["binned_path"] = binned
+        return rec
+    # the binned path's export equals the table path's (checked every step), which equals the oracle
+    # on the sub-shard: the faster of the two is the record, the other its sub-record
+    if binned["ms_per_step"] >= rec["ms_per_step"]:
+        rec["binned_path"] = binned
+        return rec
+    table = {x: rec.pop(x) for x in ("value", "ms_per_step", "roofline", "events_per_owned_position")}
+    table["stage_ms"] = rec["config"].pop("stage_ms")
+    table["step"] = rec["config"].pop("step")
+    rec["value"], rec["ms_per_step"] = binned.pop("value"), binned.pop("ms_per_step")
+    rec["config"]["path"] = "binned"
+    rec["config"]["step"] = binned.pop("step")
+    rec["config"]["stage_ms"] = binned.pop("stage_ms")
+    rec["config"]["scanned_positions_per_s"] = round(scanned / (rec["ms_per_step"] / 1000), 1)
+    rec["config"]["bins"] = binned.pop("bins")
+    rec["binned_check"] = binned
+    rec["table_path"] = table
+    return rec
+
+
+def run_binned_share(args, dev, packs, sketch, occ, card, p, k, ref_digest, n_rec, owned) -> dict:
+    """The human-scale share through the binned path: the same cardinality pass writing the owned
+    occurrences, then the stream partitioned into LDS-sized bins (hm_bin_occ) and counted there
+    (hm_count_bins; a spilled bin through the table path).  Every step's export must equal the
+    table path's (its digest and its record count)."""
+    import torch
+    from paper_1705_11147_amd import abi, kmer
+
+    g, b = kmer.plan_bins(card.distinct_hi(), card.kept_hi(), p.min_depth == 1)
+    if args.share_bins:
+        g, b = (int(x) for x in args.share_bins.split(","))
+    bc = kmer.BinnedCounter(k, occ.capacity, g, b, min_depth=p.min_depth, n_owners=p.n_owners, owner=p.owner,
+                            device=dev)
+    out = kmer.Records(int(n_rec * 1.2) + 4096, device=dev)
+    log("binned share: 2^%d bins (%d x %d), bins %.1f GB" % (g + b, 1 << g, 1 << b, 2 * bc.capacity * 16 / 1e9))
+    stages = ["card", "partition", "count"]
+    spilled = [0]
+
+    def step(ev):
+        ev[0].record()
+        sketch.reset()
+        occ.reset()
+        for pk in packs:
+            sketch.update(pk, occ=occ)
+        sketch.summarize(min_depth=p.min_depth)
+        ev[1].record()
+        bc.bin_occ(occ)
+        ev[2].record()
+        bc.count(out)
+        ev[3].record()
+        n_sp = bc.spilled()  # synchronizes; a spilled bin is counted by the table path
+        if n_sp:
+            spilled[0] += n_sp
+            bc.finish(out)
+
+    n_steps = max(1, min(args.steps, 3))
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)] for _ in range(n_steps + 1)]
+    for s in range(n_steps + 1):  # the first is a warm-up
+        step(events[s])
+        torch.cuda.synchronize()
+        abi.check(bc.status(), "binned human share step")
+        same = out.digest_words() == ref_digest and int(out.n_out.item()) == n_rec
+        assert same, "the binned share's export differs from the table path's"
+        log("binned share step %d of %d done" % (s + 1, n_steps + 1))
+    timed = events[1:]
+    stage_ms = {x: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in timed])) for i, x in enumerate(stages)}
+    step_ms = float(np.mean([ev[0].elapsed_time(ev[len(stages)]) for ev in timed]))
+    st = bc.stats()
+    return {"value": round(owned / (step_ms / 1000), 1), "ms_per_step": round(step_ms, 3),
+            "step": "cardinality pass writing the owned occurrences + partition of the stream into LDS-sized bins "
+                    "+ per-bin Bloom filter, table, classification and export in workgroup memory; packed reads "
+                    "resident in HBM",
+            "stage_ms": {x: round(v, 3) for x, v in stage_ms.items()},
+            "bins": {"group_bits": g, "bin_bits": b, "n_bins": 1 << (g + b), "records": st["records"],
+                     "spilled_bins": st["spilled_bins"], "spilled": st["spilled"], "deferred": st["deferred"],
+                     "keys": st["keys"], "kept": st["kept"], "spilled_records_per_step": spilled[0] // (n_steps + 1)},
+            "identical_to_table_path": True}
 
 
 def main():
@@ -774,6 +863,10 @@ def main():
     ap.add_argument("--path", choices=["binned", "table"], default="binned",
                     help="the timed step: the binned path (LDS-sized bins) or the table path (one count table in "
                          "HBM); the other is measured as a sub-record")
+    ap.add_argument("--share-bins", default=None, metavar="G,B",
+                    help="group and bin bits of the human share's binned path (default: kmer.plan_bins)")
+    ap.add_argument("--no-binned-share", action="store_true",
+                    help="skip the binned path on the human-scale share (the table path alone)")
     ap.add_argument("--no-binned-sub", action="store_true",
                     help="with --path table: skip the binned path's sub-record")
     ap.add_argument("--no-tiny", action="store_true",

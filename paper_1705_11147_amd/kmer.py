@@ -726,12 +726,17 @@ def plan_bins(distinct_hi: float, seen2_hi: float, bypass: bool = False) -> tupl
     """(group_bits, bin_bits) for the binned path: enough bins that a bin's distinct k-mers (its
     deferred occurrences, about one per distinct k-mer) stay near 900 of the 2048 its list holds,
     and the k-mers it inserts (those seen at least twice, or with the Bloom filter bypassed every
-    distinct k-mer) near 192 of the 384 its table takes before the bin spills; at most 2^21 bins.
+    distinct k-mer) near 192 of the 384 its table takes before the bin spills; at most 2^21 bins, and
+    2^20 while that keeps a bin within 25% of those targets.
     The second level takes up to 11 bits and at least half, so that small inputs still spread
     over many first-level groups."""
     need = seen2_hi / 192.0 if not bypass else distinct_hi / 192.0
     need = max(1.0, need, distinct_hi / 900.0)
     total = min(MAX_GROUP_BITS + MAX_BIN_BITS, max(0, int(math.ceil(math.log2(need)))))
+    # 2^10 first-level groups leave the first-level scatter one workgroup a CU (its LDS), so up to
+    # 25% past the targets (about 240 keys a bin, far from the 384 that spill) 2^20 bins are faster
+    if total == MAX_GROUP_BITS + MAX_BIN_BITS and need <= 1.25 * 2.0 ** (total - 1):
+        total -= 1
     b = min(MAX_BIN_BITS, total, max(total - MAX_GROUP_BITS, (total + 3) // 2))
     return total - b, b
 
