@@ -377,29 +377,32 @@ __global__ __launch_bounds__(kT1) void k_scatter1(PassArgs a, int32_t rpt, int64
 
 // The first level over an occurrence stream (hm_occ_t: the owned occurrences a cardinality pass
 // wrote) instead of over the reads: workgroup w takes the entries [w * per, (w + 1) * per) of the
-// n = min(count, capacity) reserved ones, per = ceil(n / gridDim.x), NT a round, and hands each
-// to op(act, record); holes (ext 0xFF) and positions past the chunk come with act false.  The
-// histogram pass and the scatter pass use the same grid, so they see the same chunks.
+// n = min(count, capacity) reserved ones, per = ceil(n / gridDim.x), NT a round (the entries of
+// four rounds loaded together), and hands each to op(act, record); holes (ext 0xFF) and positions
+// past the chunk come with act false.  The histogram pass and the scatter pass use the same grid,
+// so they see the same chunks.
 template <int NT, class Op>
 __device__ __forceinline__ void occ_rounds(const hm_occ_t &o, Op &&op) {
+    constexpr int kAhead = 4;  // rounds whose entries are loaded together
     const uint64_t n = min(*o.count, o.capacity);
     const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
     const uint64_t b = min(n, (uint64_t)blockIdx.x * per), e = min(n, b + per);
     const uint4 *keys = reinterpret_cast<const uint4 *>(o.keys);
-    for (uint64_t i0 = b; i0 < e; i0 += NT) {  // workgroup-uniform
-        const uint64_t i = i0 + threadIdx.x;
-        uint4 rec = make_uint4(0, 0, 0, 0);
-        bool act = false;
-        if (i < e) {
-            const uint32_t x = o.ext[i];
-            if (x != kHole) {
-                const uint4 kk = keys[i];  // key_hi, key_lo as four 32-bit words
-                const uint32_t ext = (x & 15u) | ((x >> 4) << 3);
-                rec = make_uint4(kk.z, kk.w, kk.x, kk.y | (ext << (kExtShift - 32)));
-                act = true;
-            }
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kAhead) {  // workgroup-uniform
+        uint4 kk[kAhead];
+        uint32_t x[kAhead];
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) {
+            const uint64_t i = i0 + (uint64_t)j * NT + threadIdx.x;
+            x[j] = i < e ? o.ext[i] : kHole;
+            kk[j] = i < e ? keys[i] : make_uint4(0, 0, 0, 0);  // key_hi, key_lo as four 32-bit words
         }
-        op(act, rec);
+#pragma unroll
+        for (int j = 0; j < kAhead; ++j) {
+            if (i0 + (uint64_t)j * NT >= e) break;  // workgroup-uniform: no round past the chunk
+            const uint32_t ext = (x[j] & 15u) | ((x[j] >> 4) << 3);
+            op(x[j] != kHole, make_uint4(kk[j].z, kk[j].w, kk[j].x, kk[j].y | (ext << (kExtShift - 32))));
+        }
     }
 }
 
@@ -409,17 +412,38 @@ __device__ __forceinline__ uint32_t rec_bin(uint4 r, int total_bits) {
     return bin_of(hi, lo, total_bits);
 }
 
-// Level-1 histogram over a stream: hist1[blockIdx.x * groups + group].
-__global__ __launch_bounds__(kBlock) void k_hist1_occ(hm_occ_t o, uint32_t *hist1, int total_bits, int bin_bits) {
+// Level-1 histogram over a stream: hist1[blockIdx.x * groups + group].  The chunks are those of
+// occ_rounds (they depend on the grid alone); a pure stream, so 1024 threads a workgroup and
+// kHistPer entries a thread in flight.
+constexpr int kHistT = 1024, kHistPer = 4;
+
+__global__ __launch_bounds__(kHistT) void k_hist1_occ(hm_occ_t o, uint32_t *hist1, int total_bits, int bin_bits) {
     extern __shared__ uint32_t s_h[];
     const int ng = 1 << (total_bits - bin_bits);
-    for (int i = threadIdx.x; i < ng; i += kBlock) s_h[i] = 0;
+    for (int i = threadIdx.x; i < ng; i += kHistT) s_h[i] = 0;
     __syncthreads();
-    occ_rounds<kBlock>(o, [&](bool act, uint4 r) {
-        if (act) atomicAdd(&s_h[rec_bin(r, total_bits) >> bin_bits], 1u);
-    });
+    const uint64_t n = min(*o.count, o.capacity);
+    const uint64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const uint64_t b = min(n, (uint64_t)blockIdx.x * per), e = min(n, b + per);
+    const uint4 *keys = reinterpret_cast<const uint4 *>(o.keys);
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)kHistT * kHistPer) {
+        uint4 kk[kHistPer];
+        uint32_t x[kHistPer];
+#pragma unroll
+        for (int j = 0; j < kHistPer; ++j) {
+            const uint64_t i = i0 + (uint64_t)j * kHistT + threadIdx.x;
+            x[j] = i < e ? o.ext[i] : kHole;
+            kk[j] = i < e ? keys[i] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < kHistPer; ++j) {
+            if (x[j] == kHole) continue;
+            const uint64_t hi = ((uint64_t)kk[j].y << 32) | kk[j].x, lo = ((uint64_t)kk[j].w << 32) | kk[j].z;
+            atomicAdd(&s_h[bin_of(hi, lo, total_bits) >> bin_bits], 1u);
+        }
+    }
     __syncthreads();
-    for (int i = threadIdx.x; i < ng; i += kBlock) hist1[(size_t)blockIdx.x * ng + i] = s_h[i];
+    for (int i = threadIdx.x; i < ng; i += kHistT) hist1[(size_t)blockIdx.x * ng + i] = s_h[i];
 }
 
 // Level-1 scatter over a stream: as k_scatter1, from the workgroup's chunk of entries.
@@ -1234,7 +1258,7 @@ int hm_bin_occ(const hm_occ_t *o, const hm_params_t *p, hm_bins_t *b, hipStream_
     if (o->capacity == 0) return fill<uint64_t>(b->bin_start, n_bins + 1, 0ull, s);
     const Scratch sc = scratch_of(b);
     uint4 *tmp = reinterpret_cast<uint4 *>(b->tmp);
-    hipLaunchKernelGGL(k_hist1_occ, dim3(g1), dim3(kBlock), ng * 4, s, *o, sc.hist1, total_bits, bin_bits);
+    hipLaunchKernelGGL(k_hist1_occ, dim3(g1), dim3(kHistT), ng * 4, s, *o, sc.hist1, total_bits, bin_bits);
     level1_regions(sc, g1, (int)ng, s);
     hipLaunchKernelGGL(k_scatter1_occ, dim3(g1), dim3(kT1), scatter1_lds(ng), s, *o, sc.hist1, sc.wstart, tmp,
                        total_bits, bin_bits);
