@@ -125,7 +125,8 @@ def test_human_share_ten_batches_stream():
     """One GPU's share of the human-scale recipe (interspersed repeats, owner 0 of 16) at 1/10 of its
     reads in ten batches, in bench.py's form: the cardinality pass writes the owned occurrences of
     every batch to one stream, and one pass-1 launch reads it.  The whole table equals the
-    oracle's, which counts the ten batches one after another (oracle.Accumulator)."""
+    oracle's, which counts the ten batches one after another (oracle.Accumulator), and so does
+    the binned path's from the same stream (hm_bin_occ, hm_count_bins)."""
     w = synth.human_share(scale=1 / 10)
     p = w.params
     dev = torch.device("cuda:0")
@@ -156,6 +157,22 @@ def test_human_share_ten_batches_stream():
     assert exp["positions"] == w.positions
     assert len(exp["count"]) > 5_000_000
     assert_tables_equal(got, exp, "human share 1/10, ten batches through the stream")
+    # the same stream through the binned path (hm_bin_occ, hm_count_bins), as bench.py times it
+    n_tab = len(got["count"])
+    del kc, out, got
+    torch.cuda.empty_cache()
+    g, b = kmer.plan_bins(card.distinct_hi(), card.kept_hi(), False)
+    bc = kmer.BinnedCounter(p.k, occ.capacity, g, b, min_depth=p.min_depth, n_owners=p.n_owners, owner=p.owner,
+                            device=dev)
+    bout = kmer.Records(int(n_tab * 1.2) + 4096, device=dev)
+    bc.bin_occ(occ)
+    bc.count(bout)
+    bc.finish(bout)
+    abi.check(bc.status(), "binned share 1/10")
+    st = bc.stats()
+    assert st["records"] == card.positions
+    print("binned: 2^%d bins, %d spilled bins" % (g + b, st["spilled_bins"]), flush=True)
+    assert_tables_equal(bout.to_numpy(sort=True), exp, "human share 1/10, the stream through the binned path")
 
 
 def test_human_share_streamed_batches():
