@@ -201,6 +201,10 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
     const int W = L - k + 1;  // > 0, checked by the host
     const int runs = (W + kCardRun - 1) / kCardRun;
     const typename Roll<KW>::Shape sh = Roll<KW>::shape(k);
+    // the owner filter's operands, held in a vector register: read from the kernel arguments in
+    // the per-window loop they cost a scalar load and a wait on every outstanding LDS store
+    uint32_t n_own = a.n_owners, me = a.owner;
+    asm volatile("" : "+v"(n_own), "+v"(me));
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t r0 = tile * reads_per_tile;
         const int64_t r1 = min(r0 + (int64_t)reads_per_tile, a.n_reads);
@@ -254,12 +258,13 @@ __global__ __launch_bounds__(kBlock) void k_card_fixed_occ(PassArgs a, CardArgs 
                 const U128 f = w.window(j0, k);
                 x.set(f, revcomp(f, k));
             }
+#pragma unroll
             for (int i = 0; i < kCardRun; ++i) {
                 // every lane rolls (an idle lane's code is never used): no divergent branch
                 if (i > 0) x.step((uint32_t)rb.base(i), sh);
                 const bool fwd = a.forward_only || x.forward();
                 const uint64_t khi = fwd ? x.fhi() : x.rhi(), klo = fwd ? x.flo() : x.rlo();
-                const bool act = ((vm >> i) & 1u) && (a.n_owners <= 1 || owner_of(khi, klo, a.n_owners) == a.owner);
+                const bool act = ((vm >> i) & 1u) && (n_own <= 1 || owner_of(khi, klo, n_own) == me);
                 const uint32_t aux = (uint32_t)(j0 + i) | ((uint32_t)(p0 + i) << 15) | (fwd ? 1u << 31 : 0u);
                 ring_push(ring, act, khi, klo, aux);
                 if (ring.tail - ring.head >= 64) finish(64);
