@@ -484,8 +484,10 @@ int hm_bloom_insert_occ(const hm_occ_t *o, const hm_params_t *p, hm_bloom_t *b, 
 
 typedef struct {
     uint64_t *recs;      /* 2 * capacity words, 128-byte aligned: the records, bin after bin */
-    uint64_t *tmp;       /* 2 * capacity words, 128-byte aligned: records grouped by their top group_bits
-                            (scratch of hm_bin_kmers; free afterwards, e.g. as the keys of the spill stream) */
+    uint64_t *tmp;       /* 2 * capacity words, 128-byte aligned: the first partition level's output, a region
+                            per first-level workgroup holding a piece per group (the top group_bits of the bin)
+                            (scratch of hm_bin_kmers / hm_bin_occ; free afterwards, e.g. as the keys of the
+                            spill stream) */
     uint64_t capacity;   /* records: at least hm_bins_capacity(windows, group_bits, bin_bits) */
     uint32_t group_bits; /* 0..10 */
     uint32_t bin_bits;   /* 0..11: bins = 2^(group_bits + bin_bits) */
