@@ -882,7 +882,8 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     OccStream.for_windows; doubled and rerun on overflow) and pass 1 reads it instead of the
     reads (sizing="card" only).  binned: the binned path (BinnedCounter: fixed-length reads,
     k <= 61), with (group_bits, bin_bits) from plan_bins over a cardinality pass unless bin_bits
-    is given; its records are those of the table path."""
+    is given; with occ_stream too, the bins are filled from the stream the cardinality pass writes
+    (hm_bin_occ) instead of from the reads; its records are those of the table path."""
     dev = torch.device(device)
     a = torch.from_numpy(np.ascontiguousarray(ascii, dtype=np.uint8)).to(dev)
     q = torch.from_numpy(np.ascontiguousarray(qual, dtype=np.uint8)).to(dev)
@@ -892,15 +893,31 @@ def analyze(ascii: np.ndarray, qual: np.ndarray, k: int, read_len: int | None = 
     flags = (abi.HM_FORWARD_ONLY if forward_only else 0) | (abi.HM_BLOOM_BYPASS if bypass else 0) | \
         (abi.HM_CHECKED if checked else 0)
     if binned:
-        if bin_bits is None:
+        occ = None
+        if bin_bits is None or occ_stream:
             sk = CardSketch(k, P, n_owners=n_owners, owner=owner, forward_only=forward_only, seed=seed, device=dev)
-            c2 = sk.run([packed], min_depth=2)
-            bin_bits = plan_bins(c2.distinct_hi(), c2.kept_hi(), bypass or min_depth == 1)
+            if occ_stream:  # the owned occurrences written by the cardinality pass, partitioned from there
+                occ = OccStream(occ_capacity, device=dev) if occ_capacity is not None else \
+                    OccStream.for_windows(P, n_owners, 1, device=dev)
+                while True:
+                    c2 = sk.run([packed], min_depth=2, occ=occ)
+                    if not occ.overflowed():
+                        break
+                    occ = OccStream(2 * max(occ.capacity, occ.entries()), device=dev)
+            else:
+                c2 = sk.run([packed], min_depth=2)
+            if bin_bits is None:
+                bin_bits = plan_bins(c2.distinct_hi(), c2.kept_hi(), bypass or min_depth == 1)
             del sk
-        bc = BinnedCounter(k, P, bin_bits[0], bin_bits[1], min_depth=min_depth, ext_min=ext_min, n_owners=n_owners,
-                           owner=owner, flags=flags, seed=seed, device=dev)
+        bc = BinnedCounter(k, occ.capacity if occ is not None else P, bin_bits[0], bin_bits[1], min_depth=min_depth,
+                           ext_min=ext_min, n_owners=n_owners, owner=owner, flags=flags, seed=seed, device=dev)
         out = Records(max(1024, P), device=dev)
-        spilled = bc.run(packed, out, export_flags & abi.HM_EXPORT_UU_ONLY)
+        if occ is not None:
+            bc.bin_occ(occ)
+            bc.count(out, export_flags & abi.HM_EXPORT_UU_ONLY)
+            spilled = bc.finish(out, export_flags & abi.HM_EXPORT_UU_ONLY)
+        else:
+            spilled = bc.run(packed, out, export_flags & abi.HM_EXPORT_UU_ONLY)
         abi.check(bc.status(), "binned k-mer analysis")
         res = out.to_numpy(sort=True)
         res["digest"] = out.digest_words()

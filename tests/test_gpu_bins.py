@@ -265,3 +265,12 @@ def test_binned_from_stream_spills():
     assert_tables_equal(got, exp, "stream spill")
     # the spill stream holds the bin's range, padding included; its records are the owned occurrences
     assert st["spilled_bins"] == 1 and st["spilled"] == card.positions and spilled >= card.positions
+
+
+@pytest.mark.parametrize("n_owners,owner", [(3, 1), (1, 0)])
+def test_analyze_binned_from_stream(n_owners, owner):
+    """kmer.analyze(binned=True, occ_stream=True): the cardinality pass writes the owned occurrences
+    and the bins are filled from that stream; the table equals the oracle's for that owner."""
+    ascii, qual = fixed_reads(98, 8000, 120, 40000, 0.01)
+    got, exp = run_both(ascii, qual, 120, 31, n_owners=n_owners, owner=owner, occ_stream=True)
+    check(got, exp, "analyze stream %d of %d" % (owner, n_owners))
