@@ -2,9 +2,13 @@
 """Benchmark: k-mer analysis throughput (k-mers/s) on one MI355X.
 
 One step = the whole path over one read set already resident in HBM (ASCII
-bases + Phred bytes): pack -> cardinality pass -> table/Bloom/list init ->
-pass 1 (Bloom test + insert/count) -> pass 2 (first occurrences) -> classify
-+ export.  The headline workload is the mid-size read set: 100 Mbp synthetic
+bases + Phred bytes): pack -> cardinality pass (which also counts the
+partition's first-level histogram) -> partition of the windows into LDS-sized
+bins -> per bin, in workgroup memory: Bloom filter test + insert/count, the
+deferred first occurrences, classify + export (the binned path).  The table
+path's step (pack -> cardinality -> table/Bloom/list init -> pass 1 -> pass 2
+-> classify + export) is timed beside it as a sub-record, and both must give
+the same export.  The headline workload is the mid-size read set: 100 Mbp synthetic
 genome with 5% segmental repeats, 20M reads of 150 bp (30x), 0.5% end-biased
 substitution errors, Phred ~ clamp(N(32,6),2,41), k=51, Q20, min depth 2.
 
@@ -14,7 +18,8 @@ the oracle timed on a bounded sample (whose table the GPU must reproduce);
 and, as sub-records, the tiny read set (checked against the oracle in full, the oracle timed on
 one host thread and on all of them), the batched form (64 read sets) against the plain form,
 the serving loop, and one GPU's share of the human-scale run (owner 0 of 16,
-ten 64M-read batches) with a sub-shard of its table checked against the
+ten 64M-read batches; the binned path from the owned-occurrence stream, the
+table path beside it) with a sub-shard of its table checked against the
 oracle.
 """
 from __future__ import annotations
